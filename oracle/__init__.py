@@ -1,0 +1,12 @@
+"""CPU oracle for the volume-potential hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only tests/, the smoke check (__graft_entry__.smoke) and bench.py's
+cpu_baseline leg may import, call, link or execute anything in this package.
+The GPU library never does, and the two share no code: the only inputs they
+share come from the seeded generators in vp_workloads.
+
+  direct.c / direct.py : float64 direct sums (smooth part, correction part,
+                         adjoint, target gradient), OpenMP over targets
+  tree.py              : plain quadtree and U/V/W/X lists by definition
+  expansions.py        : multipole/local coefficients by definition
+"""
