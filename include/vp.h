@@ -1,0 +1,184 @@
+/*
+ * vp.h -- C ABI of the MI355X volume-potential evaluation library (libvp.so).
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the
+ * target-independent smooth quadrature of the volume potential
+ *
+ *     u_b(t_i) = sum_j G(r_j, t_i) w_j f_b(r_j)  +  sum_k C[i,k] f_b(r_k)
+ *
+ * with the 2D Laplace Green's function G(r, r0) = -(1/(2 pi)) log|r - r0|
+ * (Section 2.1 of Anderson, Zhu and Veerapaneni, arXiv 2203.05933).  The first
+ * sum is the smooth rule of Section 3.2 (eq. Tk_smooth_quad) whose "modified
+ * weights" w_j = J^k(xi_j) w_j make it a plain point sum (Section 4.2 gives
+ * the same rule for boxes), evaluated by a fast multipole method over an
+ * adaptive quadtree.  The second is the sparse local correction matrix the
+ * paper assembles from its per-cell maps Pi_k (Section 4, next to eqs.
+ * ndofs/nsrcs).  A source/target pair at exactly zero distance (the self
+ * pair when the targets are the nodes) contributes nothing to the first sum.
+ *
+ * Conventions
+ *   * All floating-point arrays are float64, C-contiguous.  Batched arrays are
+ *     [nbatch][len] (density b is the contiguous row b).
+ *   * vp_plan takes HOST pointers and copies everything it needs into
+ *     plan-owned device memory; the caller may free its arrays on return.
+ *   * vp_eval* take DEVICE pointers owned by the caller (e.g. torch tensor
+ *     data), in the caller's (user) order, never in the library's sorted
+ *     order.  Outputs are overwritten, not accumulated.
+ *   * Evaluations are asynchronous on the plan's stream; they do not
+ *     allocate and do not synchronise the host.  Inputs must stay valid and
+ *     unmodified until the stream reaches the evaluation.
+ *   * A plan must not be used from two host threads at once.
+ *   * No function throws or aborts: every error is a status code, with a
+ *     message from vp_last_error.  VP_EINVAL leaves the plan usable.
+ *     VP_EDEVICE (a HIP runtime error) poisons the plan: later calls on it
+ *     return VP_EDEVICE.
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vp_plan_s *vp_plan_t; /* opaque, library-owned */
+
+typedef enum {
+    VP_OK = 0,
+    VP_EINVAL = 1,       /* invalid argument; nothing was done */
+    VP_ENOMEM = 2,       /* device allocation failed */
+    VP_EDEVICE = 3,      /* HIP runtime error; the plan is poisoned */
+    VP_EUNSUPPORTED = 4, /* valid but outside what this build supports */
+    VP_EINTERNAL = 5     /* internal limit exceeded (e.g. list traversal depth) */
+} vp_status;
+
+enum { VP_FP64 = 0, VP_FP32_BULK = 1 };
+enum { VP_M2L_AUTO = 0, VP_M2L_FP64_MFMA = 1, VP_M2L_FP32_MFMA = 2, VP_M2L_FP32_SPLIT = 3 };
+enum { VP_P2P_AUTO = 0, VP_P2P_PAIRWISE = 1, VP_P2P_TABLES = 2 };
+
+typedef struct {
+    int32_t order;     /* p: highest power kept in the expansions (p+1 complex
+                          coefficients including the log term); 1..60; default 30 */
+    int32_t max_leaf;  /* a box is split while it holds more than max_leaf
+                          sources or targets; 1..256; default 64 */
+    int32_t nbatch;    /* densities per evaluation; 1..64; default 1 */
+    int32_t precision; /* VP_FP64: every stage in float64.  VP_FP32_BULK: the
+                          expansion stages (P2M, M2M, M2L, L2L, L2P, M2P, P2L)
+                          in float32; charges, near field, translation
+                          operator set-up and final accumulation in float64 */
+    int32_t m2l_mode;  /* VP_M2L_*; AUTO = FP64 MFMA for VP_FP64, FP32 MFMA
+                          for VP_FP32_BULK.  FP32_SPLIT forms T_hi M_hi +
+                          T_hi M_lo + T_lo M_hi with FP32 MFMA (VP_FP32_BULK only) */
+    int32_t p2p_mode;  /* VP_P2P_*; AUTO uses precomputed near-field tables on
+                          leaves whose nodes are congruent copies of one
+                          pattern (uniform box grids) and the pairwise kernel
+                          elsewhere */
+    int32_t max_level; /* deepest tree level; 1..30; 0 = 30 */
+    int32_t flags;     /* reserved, must be 0 */
+    double root[3];    /* x0, y0, side of the root square; side <= 0 selects
+                          the bounding square of sources and targets */
+    void *stream;      /* hipStream_t for plan-time copies and evaluations;
+                          NULL = the null stream */
+} vp_options;
+
+/* Fill *opt with the defaults listed above. */
+void vp_default_options(vp_options *opt);
+
+/*
+ * vp_plan -- build the static-geometry plan (the paper excludes this set-up
+ * from its timings, Section 5 / Table 3).
+ *   x, y, w [n]      : node coordinates and smooth-rule weights (host)
+ *   tx, ty  [m]      : target coordinates (host), or both NULL: the targets
+ *                      are the nodes (m must then equal n)
+ *   rowptr [m+1], col [nnz], val [nnz] : correction matrix C in CSR form,
+ *                      rows = targets, columns = nodes (host); rowptr NULL
+ *                      means no correction.  rowptr[0] must be 0, rowptr
+ *                      non-decreasing, 0 <= col < n.
+ *   opt              : options (NULL = defaults)
+ *   out              : receives the plan; NULL on failure
+ * Errors: VP_EINVAL (n < 1, m < 1, non-finite coordinates or weights, bad
+ * CSR, options out of range, out == NULL), VP_ENOMEM, VP_EDEVICE,
+ * VP_EINTERNAL.  The tree is built on the device with this library's kernels.
+ */
+vp_status vp_plan(const double *x, const double *y, const double *w, int64_t n,
+                  const double *tx, const double *ty, int64_t m,
+                  const int64_t *rowptr, const int32_t *col, const double *val,
+                  const vp_options *opt, vp_plan_t *out);
+
+/*
+ * vp_eval -- u[b][i] = sum_j G(r_j, t_i) w_j f[b][j] + sum_k C[i,k] f[b][k].
+ *   f [nbatch][n] device, u [nbatch][m] device; f and u must not overlap.
+ */
+vp_status vp_eval(vp_plan_t plan, const double *f, double *u);
+
+/*
+ * vp_eval_adjoint -- the exact transpose of vp_eval (used for dL/df):
+ *   df[b][j] = w_j sum_i G(r_j, t_i) g[b][i] + sum_i C[i,j] g[b][i].
+ *   g [nbatch][m] device, df [nbatch][n] device; no overlap.
+ */
+vp_status vp_eval_adjoint(vp_plan_t plan, const double *g, double *df);
+
+/*
+ * vp_eval_grad_targets -- gradient of the smooth sum with respect to the
+ * target positions (the correction matrix is a fixed input and has none):
+ *   grad[b][0][i] = d/dtx_i, grad[b][1][i] = d/dty_i of
+ *   sum_j G(r_j, t_i) w_j f[b][j].
+ *   f [nbatch][n] device, grad [nbatch][2][m] device; no overlap.
+ */
+vp_status vp_eval_grad_targets(vp_plan_t plan, const double *f, double *grad);
+
+/* Change the stream later evaluations run on (hipStream_t; NULL = null stream). */
+vp_status vp_set_stream(vp_plan_t plan, void *stream);
+
+/* Release the plan's device memory (synchronises its stream).  NULL is a no-op. */
+vp_status vp_destroy(vp_plan_t plan);
+
+/* Message of the last error on this plan, or of the calling thread's last
+ * vp_plan failure when plan is NULL.  Never NULL; valid until the next call. */
+const char *vp_last_error(vp_plan_t plan);
+
+/* Sizes of a built plan, for callers and tests. */
+typedef struct {
+    int64_t n, m, nnz;
+    int32_t nbatch, order, precision, m2l_mode, p2p_mode_used, max_leaf;
+    int32_t nbox, nleaf, nlevels, self_targets;
+    int64_t list_len[4];       /* total entries of the U, V, W, X lists */
+    int64_t table_leaves;      /* leaves served by near-field tables */
+    int64_t near_pairs;        /* pairwise near-field interactions per density */
+    int64_t workspace_bytes;   /* device memory held by the plan */
+    double root[3];
+} vp_plan_info_t;
+
+vp_status vp_get_info(vp_plan_t plan, vp_plan_info_t *info);
+
+/*
+ * Introspection for tests: copy one plan array to host memory (synchronous).
+ *   which: VP_ARR_* below; out must hold the advertised count of elements of
+ *   the stated type (query with out == NULL: *count receives the length).
+ */
+enum {
+    VP_ARR_SRC_PERM = 0,   /* int32 [n]      sorted position -> node index    */
+    VP_ARR_TGT_PERM = 1,   /* int32 [m]      sorted position -> target index  */
+    VP_ARR_BOX = 2,        /* int32 [nbox][10]: level, ix, iy, parent,
+                              child_begin (-1 leaf), nchild, src_begin,
+                              src_end, tgt_begin, tgt_end                     */
+    VP_ARR_LEVEL_BEGIN = 3,/* int32 [nlevels+1]                               */
+    VP_ARR_U_PTR = 4, VP_ARR_U_IDX = 5,  /* int32 CSR over boxes (sorted)     */
+    VP_ARR_V_PTR = 6, VP_ARR_V_IDX = 7,
+    VP_ARR_W_PTR = 8, VP_ARR_W_IDX = 9,
+    VP_ARR_X_PTR = 10, VP_ARR_X_IDX = 11,
+    VP_ARR_MULTIPOLE = 12, /* float64 [nbox][nbatch][2][p+1] (re, im) after the
+                              last vp_eval (float32 forms are widened)        */
+    VP_ARR_LOCAL = 13,     /* same layout: local expansions after the last
+                              vp_eval's downward pass                         */
+    VP_ARR_SRC_KEYS = 14,  /* int64 [n] sorted Morton keys                    */
+    VP_ARR_TGT_KEYS = 15   /* int64 [m]                                       */
+};
+vp_status vp_get_array(vp_plan_t plan, int32_t which, void *out, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VP_H */

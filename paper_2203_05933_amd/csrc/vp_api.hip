@@ -1,0 +1,370 @@
+// C ABI of libvp (declared in include/vp.h): argument validation, plan
+// construction and the evaluation entry points.  Internal errors are C++
+// exceptions, caught here and turned into vp_status codes.
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "vp_internal.hpp"
+
+namespace vp {
+
+[[noreturn]] void throw_hip(hipError_t e, const char *expr, const char *file, int line) {
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), expr,
+                  file, line);
+    throw Error(VP_EDEVICE, buf);
+}
+
+}  // namespace vp
+
+using vp::Error;
+
+static thread_local std::string g_last_error;
+
+static vp_status set_err(vp_plan_s *P, vp_status st, const std::string &msg) {
+    if (P) {
+        P->err = msg;
+        if (st == VP_EDEVICE) P->poisoned = true;
+    } else {
+        g_last_error = msg;
+    }
+    return st;
+}
+
+template <class F>
+static vp_status guarded(vp_plan_s *P, F &&fn) {
+    try {
+        fn();
+        return VP_OK;
+    } catch (const Error &e) {
+        return set_err(P, e.status, e.what());
+    } catch (const std::bad_alloc &) {
+        return set_err(P, VP_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return set_err(P, VP_EINTERNAL, e.what());
+    } catch (...) {
+        return set_err(P, VP_EINTERNAL, "unknown internal error");
+    }
+}
+
+extern "C" void vp_default_options(vp_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->order = 30;
+    opt->max_leaf = 64;
+    opt->nbatch = 1;
+    opt->precision = VP_FP64;
+    opt->m2l_mode = VP_M2L_AUTO;
+    opt->p2p_mode = VP_P2P_AUTO;
+    opt->max_level = 0;
+    opt->flags = 0;
+    opt->root[0] = opt->root[1] = opt->root[2] = 0.0;
+    opt->stream = nullptr;
+}
+
+static void validate_plan_args(const double *x, const double *y, const double *w, int64_t n,
+                               const double *tx, const double *ty, int64_t m, const int64_t *rowptr,
+                               const int32_t *col, const double *val, const vp_options &o,
+                               vp_plan_t *out) {
+    auto bad = [](const std::string &s) { throw Error(VP_EINVAL, s); };
+    if (!out) bad("out is NULL");
+    if (!x || !y || !w) bad("x, y and w must not be NULL");
+    if (n < 1) bad("n must be >= 1");
+    if (n > 0x3FFFFFFF) bad("n too large (must fit 30-bit indices)");
+    if ((tx == nullptr) != (ty == nullptr)) bad("tx and ty must both be NULL or both non-NULL");
+    if (!tx && m != n) bad("targets are the nodes (tx == ty == NULL) but m != n");
+    if (m < 1) bad("m must be >= 1");
+    if (m > 0x3FFFFFFF) bad("m too large");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || !std::isfinite(w[i]))
+            bad("non-finite node coordinate or weight at index " + std::to_string(i));
+    if (tx)
+        for (int64_t i = 0; i < m; ++i)
+            if (!std::isfinite(tx[i]) || !std::isfinite(ty[i]))
+                bad("non-finite target coordinate at index " + std::to_string(i));
+    if (rowptr) {
+        if (!col && rowptr[m] > 0) bad("col is NULL");
+        if (!val && rowptr[m] > 0) bad("val is NULL");
+        if (rowptr[0] != 0) bad("rowptr[0] must be 0");
+        for (int64_t i = 0; i < m; ++i)
+            if (rowptr[i + 1] < rowptr[i]) bad("rowptr must be non-decreasing (row " + std::to_string(i) + ")");
+        int64_t nnz = rowptr[m];
+        if (nnz > 0x7FFFFFFF) throw Error(VP_EUNSUPPORTED, "more than 2^31-1 correction non-zeros");
+        for (int64_t q = 0; q < nnz; ++q)
+            if (col[q] < 0 || col[q] >= n) bad("col out of range at non-zero " + std::to_string(q));
+        for (int64_t q = 0; q < nnz; ++q)
+            if (!std::isfinite(val[q])) bad("non-finite correction value at non-zero " + std::to_string(q));
+    }
+    if (o.order < 1 || o.order > 60) bad("order must be in 1..60");
+    if (o.max_leaf < 1 || o.max_leaf > 256) bad("max_leaf must be in 1..256");
+    if (o.nbatch < 1 || o.nbatch > vp::MAX_BATCH) bad("nbatch must be in 1..64");
+    if (o.precision != VP_FP64 && o.precision != VP_FP32_BULK) bad("unknown precision");
+    if (o.m2l_mode < 0 || o.m2l_mode > 3) bad("unknown m2l_mode");
+    if (o.precision == VP_FP64 && (o.m2l_mode == VP_M2L_FP32_MFMA || o.m2l_mode == VP_M2L_FP32_SPLIT))
+        bad("FP32 M2L modes need precision VP_FP32_BULK");
+    if (o.p2p_mode < 0 || o.p2p_mode > 2) bad("unknown p2p_mode");
+    if (o.max_level < 0 || o.max_level > vp::LBITS) bad("max_level must be in 0..30");
+    if (o.flags != 0) bad("flags must be 0");
+    if (o.root[2] > 0 && (!std::isfinite(o.root[0]) || !std::isfinite(o.root[1]) || !std::isfinite(o.root[2])))
+        bad("non-finite root square");
+}
+
+static void free_plan(vp_plan_s *P) {
+    if (!P) return;
+    if (P->stream) (void)hipStreamSynchronize(P->stream);
+    else (void)hipDeviceSynchronize();
+    P->mem.free_all();
+    delete P;
+}
+
+extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, int64_t n, const double *tx,
+                             const double *ty, int64_t m, const int64_t *rowptr, const int32_t *col,
+                             const double *val, const vp_options *opt, vp_plan_t *out) {
+    if (out) *out = nullptr;
+    vp_options o;
+    if (opt) o = *opt;
+    else vp_default_options(&o);
+    vp_plan_s *P = nullptr;
+    vp_status st = guarded(nullptr, [&] {
+        validate_plan_args(x, y, w, n, tx, ty, m, rowptr, col, val, o, out);
+        P = new vp_plan_s();
+        P->opt = o;
+        P->n = n;
+        P->m = m;
+        P->self = (tx == nullptr);
+        P->nbatch = o.nbatch;
+        P->p = o.order;
+        P->P = o.order + 1;
+        P->PD = ((2 * P->P + 1 + 15) / 16) * 16;
+        if (P->PD > 128) throw Error(VP_EUNSUPPORTED, "order too large (2(p+1)+1 must be <= 128)");
+        P->fp32 = (o.precision == VP_FP32_BULK);
+        P->m2l_mode = o.m2l_mode == VP_M2L_AUTO ? (P->fp32 ? VP_M2L_FP32_MFMA : VP_M2L_FP64_MFMA) : o.m2l_mode;
+        P->stream = static_cast<hipStream_t>(o.stream);
+        VP_HIP(hipGetDevice(&P->device));
+        P->err_flag = P->mem.alloc<int32_t>(1);
+        P->w_user = P->mem.alloc<double>(n);
+        VP_HIP(hipMemcpyAsync(P->w_user, w, sizeof(double) * n, hipMemcpyHostToDevice, P->stream));
+        vp::build_tree(P, x, y, tx, ty);
+        vp::build_operators(P);
+        // correction matrix
+        P->nnz = rowptr ? rowptr[m] : 0;
+        P->rowptr = P->mem.alloc<int64_t>(m + 1);
+        if (rowptr) {
+            VP_HIP(hipMemcpyAsync(P->rowptr, rowptr, sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, P->stream));
+        } else {
+            std::vector<int64_t> z(m + 1, 0);
+            VP_HIP(hipMemcpyAsync(P->rowptr, z.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, P->stream));
+            VP_HIP(hipStreamSynchronize(P->stream));
+        }
+        P->col = P->mem.alloc<int32_t>(P->nnz);
+        P->val = P->mem.alloc<double>(P->nnz);
+        if (P->nnz > 0) {
+            VP_HIP(hipMemcpyAsync(P->col, col, sizeof(int32_t) * P->nnz, hipMemcpyHostToDevice, P->stream));
+            VP_HIP(hipMemcpyAsync(P->val, val, sizeof(double) * P->nnz, hipMemcpyHostToDevice, P->stream));
+        }
+        vp::build_csr_transpose(P);
+        vp::build_schedules(P);
+        // workspace
+        const int64_t len = std::max(n, m);
+        P->q = P->mem.alloc<double>((size_t)P->nbatch * len);
+        P->acc = P->mem.alloc<double>((size_t)P->nbatch * 2 * len);
+        const size_t esz = P->fp32 ? 4 : 8;
+        const size_t ecount = (size_t)P->tree.nbox * P->nbatch * P->PD;
+        P->Mexp = P->mem.alloc<unsigned char>(ecount * esz);
+        P->Lexp = P->mem.alloc<unsigned char>(ecount * esz);
+        if (P->fp32) {
+            vp::fill_f32((float *)P->Mexp, 0.f, (int64_t)ecount, P->stream);
+            vp::fill_f32((float *)P->Lexp, 0.f, (int64_t)ecount, P->stream);
+        } else {
+            vp::fill_f64((double *)P->Mexp, 0.0, (int64_t)ecount, P->stream);
+            vp::fill_f64((double *)P->Lexp, 0.0, (int64_t)ecount, P->stream);
+        }
+        VP_HIP(hipStreamSynchronize(P->stream));
+        // near-field pair count (host estimate from the U lists)
+        {
+            vp::Tree &T = P->tree;
+            std::vector<int32_t> up(T.nbox + 1), ui(T.llen[0]), sb(T.nbox), se(T.nbox), tb(T.nbox), te(T.nbox);
+            VP_HIP(hipMemcpy(up.data(), T.lptr[0], 4 * (T.nbox + 1), hipMemcpyDeviceToHost));
+            if (T.llen[0]) VP_HIP(hipMemcpy(ui.data(), T.lidx[0], 4 * T.llen[0], hipMemcpyDeviceToHost));
+            VP_HIP(hipMemcpy(sb.data(), T.sb, 4 * T.nbox, hipMemcpyDeviceToHost));
+            VP_HIP(hipMemcpy(se.data(), T.se, 4 * T.nbox, hipMemcpyDeviceToHost));
+            VP_HIP(hipMemcpy(tb.data(), T.tb, 4 * T.nbox, hipMemcpyDeviceToHost));
+            VP_HIP(hipMemcpy(te.data(), T.te, 4 * T.nbox, hipMemcpyDeviceToHost));
+            int64_t pairs = 0;
+            for (int b = 0; b < T.nbox; ++b)
+                for (int e = up[b]; e < up[b + 1]; ++e) pairs += (int64_t)(te[b] - tb[b]) * (se[ui[e]] - sb[ui[e]]);
+            P->near_pairs = pairs;
+        }
+    });
+    if (st != VP_OK) {
+        if (P) {
+            g_last_error = P->err;
+            free_plan(P);
+        }
+        return st;
+    }
+    *out = P;
+    return VP_OK;
+}
+
+static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
+    auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+extern "C" vp_status vp_eval(vp_plan_t P, const double *f, double *u) {
+    if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
+    if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned by an earlier device error: " + P->err);
+    if (!f || !u) return set_err(P, VP_EINVAL, "f and u must not be NULL");
+    if (overlaps(f, 8 * (size_t)P->nbatch * P->n, u, 8 * (size_t)P->nbatch * P->m))
+        return set_err(P, VP_EINVAL, "f and u overlap");
+    return guarded(P, [&] {
+        vp::prepare_charges(P, f, false);
+        vp::run_fmm(P, false, false);
+        vp::finish_output(P, f, u, false);
+    });
+}
+
+extern "C" vp_status vp_eval_adjoint(vp_plan_t P, const double *g, double *df) {
+    if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
+    if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned by an earlier device error: " + P->err);
+    if (!g || !df) return set_err(P, VP_EINVAL, "g and df must not be NULL");
+    if (overlaps(g, 8 * (size_t)P->nbatch * P->m, df, 8 * (size_t)P->nbatch * P->n))
+        return set_err(P, VP_EINVAL, "g and df overlap");
+    return guarded(P, [&] {
+        vp::prepare_charges(P, g, true);
+        vp::run_fmm(P, true, false);
+        vp::finish_output(P, g, df, true);
+    });
+}
+
+extern "C" vp_status vp_eval_grad_targets(vp_plan_t P, const double *f, double *grad) {
+    if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
+    if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned by an earlier device error: " + P->err);
+    if (!f || !grad) return set_err(P, VP_EINVAL, "f and grad must not be NULL");
+    if (overlaps(f, 8 * (size_t)P->nbatch * P->n, grad, 16 * (size_t)P->nbatch * P->m))
+        return set_err(P, VP_EINVAL, "f and grad overlap");
+    return guarded(P, [&] {
+        vp::prepare_charges(P, f, false);
+        vp::run_fmm(P, false, true);
+        vp::finish_grad(P, grad);
+    });
+}
+
+extern "C" vp_status vp_set_stream(vp_plan_t P, void *stream) {
+    if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
+    P->stream = static_cast<hipStream_t>(stream);
+    P->opt.stream = stream;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_destroy(vp_plan_t P) {
+    if (!P) return VP_OK;
+    free_plan(P);
+    return VP_OK;
+}
+
+extern "C" const char *vp_last_error(vp_plan_t P) {
+    if (P) return P->err.c_str();
+    return g_last_error.c_str();
+}
+
+extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
+    if (!P || !info) return set_err(P, VP_EINVAL, "plan and info must not be NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->n = P->n;
+    info->m = P->m;
+    info->nnz = P->nnz;
+    info->nbatch = P->nbatch;
+    info->order = P->p;
+    info->precision = P->opt.precision;
+    info->m2l_mode = P->m2l_mode;
+    info->p2p_mode_used = P->near.active ? VP_P2P_TABLES : VP_P2P_PAIRWISE;
+    info->max_leaf = P->opt.max_leaf;
+    info->nbox = P->tree.nbox;
+    info->nleaf = P->tree.nleaf;
+    info->nlevels = P->tree.nlevels;
+    info->self_targets = P->self ? 1 : 0;
+    for (int k = 0; k < 4; ++k) info->list_len[k] = P->tree.llen[k];
+    info->table_leaves = P->near.nleaf_tab;
+    info->near_pairs = P->near_pairs;
+    info->workspace_bytes = (int64_t)P->mem.bytes;
+    for (int k = 0; k < 3; ++k) info->root[k] = P->opt.root[k];
+    return VP_OK;
+}
+
+template <class T>
+static void d2h(void *out, const T *d, int64_t count) {
+    if (count > 0) VP_HIP(hipMemcpy(out, d, sizeof(T) * count, hipMemcpyDeviceToHost));
+}
+
+extern "C" vp_status vp_get_array(vp_plan_t P, int32_t which, void *out, int64_t *count) {
+    if (!P || !count) return set_err(P, VP_EINVAL, "plan and count must not be NULL");
+    if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned: " + P->err);
+    vp::Tree &T = P->tree;
+    return guarded(P, [&] {
+        VP_HIP(P->stream ? hipStreamSynchronize(P->stream) : hipDeviceSynchronize());
+        int64_t c = 0;
+        switch (which) {
+            case VP_ARR_SRC_PERM: c = P->n; if (out) d2h(out, P->sperm, c); break;
+            case VP_ARR_TGT_PERM: c = P->m; if (out) d2h(out, P->tperm, c); break;
+            case VP_ARR_SRC_KEYS: c = P->n; if (out) d2h(out, P->skeys, c); break;
+            case VP_ARR_TGT_KEYS: c = P->m; if (out) d2h(out, P->tkeys, c); break;
+            case VP_ARR_LEVEL_BEGIN:
+                c = T.nlevels + 1;
+                if (out) std::memcpy(out, T.level_begin.data(), 4 * c);
+                break;
+            case VP_ARR_BOX: {
+                c = (int64_t)T.nbox * 10;
+                if (out) {
+                    const int32_t *cols[10] = {T.level, T.ix, T.iy, T.parent, T.child, T.nchild, T.sb, T.se, T.tb, T.te};
+                    std::vector<int32_t> tmp(T.nbox);
+                    int32_t *o = static_cast<int32_t *>(out);
+                    for (int k = 0; k < 10; ++k) {
+                        d2h(tmp.data(), cols[k], T.nbox);
+                        for (int b = 0; b < T.nbox; ++b) o[(int64_t)b * 10 + k] = tmp[b];
+                    }
+                }
+                break;
+            }
+            case VP_ARR_U_PTR: case VP_ARR_V_PTR: case VP_ARR_W_PTR: case VP_ARR_X_PTR: {
+                int k = (which - VP_ARR_U_PTR) / 2;
+                c = T.nbox + 1;
+                if (out) d2h(out, T.lptr[k], c);
+                break;
+            }
+            case VP_ARR_U_IDX: case VP_ARR_V_IDX: case VP_ARR_W_IDX: case VP_ARR_X_IDX: {
+                int k = (which - VP_ARR_U_IDX) / 2;
+                c = T.llen[k];
+                if (out) d2h(out, T.lidx[k], c);
+                break;
+            }
+            case VP_ARR_MULTIPOLE:
+            case VP_ARR_LOCAL: {
+                c = (int64_t)T.nbox * P->nbatch * 2 * P->P;
+                if (out) {
+                    const size_t cnt = (size_t)T.nbox * P->nbatch * P->PD;
+                    std::vector<double> h(cnt);
+                    const void *src = which == VP_ARR_MULTIPOLE ? P->Mexp : P->Lexp;
+                    if (P->fp32) {
+                        std::vector<float> hf(cnt);
+                        d2h(hf.data(), static_cast<const float *>(src), (int64_t)cnt);
+                        for (size_t i = 0; i < cnt; ++i) h[i] = hf[i];
+                    } else {
+                        d2h(h.data(), static_cast<const double *>(src), (int64_t)cnt);
+                    }
+                    double *o = static_cast<double *>(out);
+                    for (size_t col = 0; col < (size_t)T.nbox * P->nbatch; ++col)
+                        for (int r = 0; r < 2 * P->P; ++r) o[col * 2 * P->P + r] = h[col * P->PD + r];
+                }
+                break;
+            }
+            default:
+                throw Error(VP_EINVAL, "unknown array id");
+        }
+        *count = c;
+    });
+}

@@ -1,0 +1,873 @@
+// Evaluation kernels of the volume-potential hot path.
+//
+// One evaluation of u_b(t_i) = sum_j G(r_j, t_i) w_j f_b(r_j) + (C f_b)(t_i)
+// (smooth rule of Section 3.2, eq. Tk_smooth_quad; box rule of Section 4.2;
+// Green's function of Section 2.1; correction matrix of Section 4) runs as:
+//   charge     q_b[j] = w_j f_b[perm[j]]                (sorted source order)
+//   P2M        leaf multipoles                         (VALU, LDS reduction)
+//   M2M        upward pass, level by level             (VALU)
+//   M2L        V lists, one launch for all levels      (MFMA, operators in FP64)
+//   P2L        X lists                                 (VALU)
+//   L2L        downward pass, level by level           (VALU)
+//   P2P        U lists, LDS-staged source tiles        (FP64 VALU)
+//   L2P + M2P  local expansion and W lists at targets  (VALU)
+//   finish     u = acc[inverse perm] + C f             (HBM bound)
+// The adjoint runs the same passes with the point roles swapped (charges
+// g at the targets, evaluated at the nodes, times w) plus C^T g.
+// Expansions are [box][batch][PD] columns: rows 0..P-1 real parts,
+// P..2P-1 imaginary parts, zero padding; float64, or float32 in the
+// FP32-bulk form.  Every reduction has a fixed order: no atomics.
+
+#include "vp_internal.hpp"
+
+namespace vp {
+
+struct Cplx {
+    double re, im;
+};
+
+template <class E>
+struct C2 {
+    E re, im;
+};
+
+template <class E>
+__device__ inline C2<E> cmul(C2<E> a, C2<E> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// Point-set view: which points act as sources and which as targets.
+struct PointRoles {
+    const double *sx, *sy;         // source coordinates (sorted)
+    const int32_t *sb, *se;        // per box source range
+    const double *tx, *ty;         // target coordinates (sorted)
+    const int32_t *tb, *te;        // per box target range
+    int64_t nsrc, ntgt;
+};
+
+struct BoxGeo {
+    const int32_t *level, *ix, *iy, *parent, *child, *nchild;
+    const double *cx, *cy, *side, *logside;
+};
+
+// ----------------------------------------------------------------------------
+// charges
+// ----------------------------------------------------------------------------
+__global__ void k_charge(const double *__restrict__ f, const int32_t *__restrict__ perm,
+                         const double *__restrict__ w, double *__restrict__ q, int64_t len,
+                         int nbatch) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    int32_t j = perm[i];
+    double wi = w ? w[i] : 1.0;
+    for (int b = 0; b < nbatch; ++b) q[(int64_t)b * len + i] = wi * f[(int64_t)b * len + j];
+}
+
+// ----------------------------------------------------------------------------
+// P2M: one wave per leaf.  Lane j of a chunk builds the row
+// W[j][k] = -(1/k) ((z_j - c)/s)^k (W[j][0] = 1) in LDS; lane r then forms
+// A_r = sum_j q_j W[j][r] for each density, in source order.
+// ----------------------------------------------------------------------------
+template <class E>
+__global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_t *__restrict__ boxes,
+                                            int nboxes, const double *__restrict__ q, int nbatch,
+                                            int P, int PD, const E *__restrict__ invk,
+                                            E *__restrict__ Mexp) {
+    extern __shared__ unsigned char smem[];
+    E *Wre = reinterpret_cast<E *>(smem);   // [64][P]
+    E *Wim = Wre + 64 * P;                  // [64][P]
+    const int lane = threadIdx.x;
+    const int b = boxes[blockIdx.x];
+    const int s0 = R.sb[b], s1 = R.se[b];
+    const double cx = G.cx[b], cy = G.cy[b];
+    const double inv_s = 1.0 / G.side[G.level[b]];
+    E *out = Mexp + (int64_t)b * nbatch * PD;
+    for (int base = s0; base < s1 || base == s0; base += 64) {
+        int cnt = min(64, s1 - base);
+        if (lane < cnt) {
+            int j = base + lane;
+            C2<E> w = {(E)((R.sx[j] - cx) * inv_s), (E)((R.sy[j] - cy) * inv_s)};
+            C2<E> pw = {(E)1, (E)0};
+            Wre[lane * P] = (E)1;
+            Wim[lane * P] = (E)0;
+            for (int k = 1; k < P; ++k) {
+                pw = cmul(pw, w);
+                Wre[lane * P + k] = -pw.re * invk[k];
+                Wim[lane * P + k] = -pw.im * invk[k];
+            }
+        }
+        __syncthreads();
+        for (int r = lane; r < PD; r += 64) {
+            if (r < 2 * P) {
+                const int k = r < P ? r : r - P;
+                const E *Wc = r < P ? Wre : Wim;
+                for (int bt = 0; bt < nbatch; ++bt) {
+                    const double *qb = q + (int64_t)bt * R.nsrc + base;
+                    E acc = (E)0;
+                    for (int j = 0; j < cnt; ++j) acc += (E)qb[j] * Wc[j * P + k];
+                    if (base == s0) out[bt * PD + r] = acc;
+                    else out[bt * PD + r] += acc;
+                }
+            } else if (base == s0) {
+                for (int bt = 0; bt < nbatch; ++bt) out[bt * PD + r] = (E)0;
+            }
+        }
+        __syncthreads();
+        if (cnt <= 0) break;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// M2M: one wave per parent box of a level; lane r forms row r of
+// sum over children of R_q M_child (R_q row-major PD x PD).
+// ----------------------------------------------------------------------------
+template <class E>
+__global__ void __launch_bounds__(64) k_m2m(BoxGeo G, const int32_t *__restrict__ boxes, int nboxes,
+                                            int nbatch, int P, int PD, const E *__restrict__ Rm2m,
+                                            E *__restrict__ Mexp) {
+    const int lane = threadIdx.x;
+    const int b = boxes[blockIdx.x];
+    const int c0 = G.child[b], nc = G.nchild[b];
+    for (int bt = 0; bt < nbatch; ++bt) {
+        for (int r = lane; r < PD; r += 64) {
+            E acc = (E)0;
+            if (r < 2 * P) {
+                for (int c = c0; c < c0 + nc; ++c) {
+                    int qd = (G.ix[c] & 1) | ((G.iy[c] & 1) << 1);
+                    const E *Rr = Rm2m + ((int64_t)qd * PD + r) * PD;
+                    const E *Mc = Mexp + ((int64_t)c * nbatch + bt) * PD;
+                    for (int k = 0; k < 2 * P; ++k) acc += Rr[k] * Mc[k];
+                }
+            }
+            Mexp[((int64_t)b * nbatch + bt) * PD + r] = acc;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// M2L with matrix cores.  One wave computes a 16-column tile of
+//   L[:, col] = sum_o R_o M[:, src(col, o)]   (+ A_0 log s on row 0)
+// where a column is a (box, density) pair and o runs over the 40 outer
+// offsets.  R_o are stored in A-fragment order, so each MFMA reads one
+// contiguous 512-byte (f64) fragment.  Both 16x16x4 instructions take
+// A[l%16][l/16] and B[l/16][l%16] from lane l; the 16x16 result sits in
+// element i of lane l as D[4i + l/16][l%16] for v_mfma_f64_16x16x4 and as
+// D[4(l/16) + i][l%16] for v_mfma_f32_16x16x4 (both measured on gfx950).
+// ----------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int RB>
+__global__ void __launch_bounds__(64) k_m2l_f64(const int32_t *__restrict__ cols_box, int ncols,
+                                                int nbatch, int P, const int32_t *__restrict__ vslot,
+                                                const int32_t *__restrict__ level,
+                                                const double *__restrict__ logside,
+                                                const double *__restrict__ Afrag,
+                                                const double *__restrict__ Mexp,
+                                                double *__restrict__ Lexp) {
+    constexpr int PD = RB * 16;
+    constexpr int S = PD / 4;
+    const int lane = threadIdx.x;
+    const int cl = lane & 15, g = lane >> 4;
+    const int col = blockIdx.x * 16 + cl;
+    const bool valid = col < ncols;
+    const int box = valid ? cols_box[col / nbatch] : 0;
+    const int bt = valid ? col % nbatch : 0;
+    v4d acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int o = 0; o < NOFF; ++o) {
+        int src = valid ? vslot[(int64_t)box * NOFF + o] : -1;
+        if (__ballot(src >= 0) == 0ull) continue;
+        double bv[S];
+        const double *Ms = Mexp + ((int64_t)(src >= 0 ? src : 0) * nbatch + bt) * PD + g;
+#pragma unroll
+        for (int s = 0; s < S; ++s) bv[s] = (src >= 0) ? Ms[4 * s] : 0.0;
+        const double *Ao = Afrag + (int64_t)o * PD * PD + lane;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                double a = Ao[((r * S) + s) * 64];
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[s], acc[r], 0, 0, 0);
+            }
+        }
+    }
+    // row 2P holds sum Re A_0: add A_0 log s to row 0
+    const int r2 = 2 * P;
+    const int rb2 = r2 >> 4, g2 = r2 & 3, i2 = (r2 & 15) >> 2;
+    double sumA0 = 0.0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (r == rb2) sumA0 = acc[r][i2];
+    sumA0 = __shfl(sumA0, g2 * 16 + cl, 64);
+    if (g == 0 && valid) acc[0][0] += sumA0 * logside[level[box]];
+    if (valid) {
+        double *Lo = Lexp + ((int64_t)box * nbatch + bt) * PD;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int row = r * 16 + 4 * i + g;
+                Lo[row] = (row < 2 * P) ? acc[r][i] : 0.0;
+            }
+    }
+}
+
+// FP32-bulk form: mode 0 = one FP32 product, 1 = T_hi M + T_lo M (split
+// operator), 2 = widen to FP64 and use the FP64 operators.
+template <int RB, int MODE>
+__global__ void __launch_bounds__(64) k_m2l_f32(const int32_t *__restrict__ cols_box, int ncols,
+                                                int nbatch, int P, const int32_t *__restrict__ vslot,
+                                                const int32_t *__restrict__ level,
+                                                const double *__restrict__ logside,
+                                                const float *__restrict__ Ahi,
+                                                const float *__restrict__ Alo,
+                                                const double *__restrict__ A64,
+                                                const float *__restrict__ Mexp,
+                                                float *__restrict__ Lexp) {
+    constexpr int PD = RB * 16;
+    constexpr int S = PD / 4;
+    const int lane = threadIdx.x;
+    const int cl = lane & 15, g = lane >> 4;
+    const int col = blockIdx.x * 16 + cl;
+    const bool valid = col < ncols;
+    const int box = valid ? cols_box[col / nbatch] : 0;
+    const int bt = valid ? col % nbatch : 0;
+    v4f acc[RB];
+    v4d acc64[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        acc[r] = (v4f){0.f, 0.f, 0.f, 0.f};
+        acc64[r] = (v4d){0.0, 0.0, 0.0, 0.0};
+    }
+    for (int o = 0; o < NOFF; ++o) {
+        int src = valid ? vslot[(int64_t)box * NOFF + o] : -1;
+        if (__ballot(src >= 0) == 0ull) continue;
+        float bv[S];
+        const float *Ms = Mexp + ((int64_t)(src >= 0 ? src : 0) * nbatch + bt) * PD + g;
+#pragma unroll
+        for (int s = 0; s < S; ++s) bv[s] = (src >= 0) ? Ms[4 * s] : 0.f;
+        const int64_t ob = (int64_t)o * PD * PD + lane;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int64_t ai = ob + ((r * S) + s) * 64;
+                if (MODE == 2) {
+                    acc64[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(A64[ai], (double)bv[s], acc64[r], 0, 0, 0);
+                } else {
+                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ahi[ai], bv[s], acc[r], 0, 0, 0);
+                    if (MODE == 1) acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(Alo[ai], bv[s], acc[r], 0, 0, 0);
+                }
+            }
+        }
+    }
+    const int r2 = 2 * P;
+    const int rb2 = r2 >> 4;
+    const int g2 = (MODE == 2) ? (r2 & 3) : ((r2 & 15) >> 2);
+    const int i2 = (MODE == 2) ? ((r2 & 15) >> 2) : (r2 & 3);
+    double vals[RB][4];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vals[r][i] = (MODE == 2) ? acc64[r][i] : (double)acc[r][i];
+    double sumA0 = 0.0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (r == rb2) sumA0 = vals[r][i2];
+    sumA0 = __shfl(sumA0, g2 * 16 + cl, 64);
+    if (g == 0 && valid) vals[0][0] += sumA0 * logside[level[box]];
+    if (valid) {
+        float *Lo = Lexp + ((int64_t)box * nbatch + bt) * PD;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int row = (MODE == 2) ? (r * 16 + 4 * i + g) : (r * 16 + 4 * g + i);
+                Lo[row] = (row < 2 * P) ? (float)vals[r][i] : 0.f;
+            }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// P2L (X lists): sources of a coarser leaf straight into the local expansion
+// of box b: B_0 += sum q log|c - z|, B_l += -(1/l) sum q (s/(z - c))^l.
+// ----------------------------------------------------------------------------
+template <class E>
+__global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_t *__restrict__ boxes,
+                                            const int32_t *__restrict__ xptr,
+                                            const int32_t *__restrict__ xidx,
+                                            const double *__restrict__ q, int nbatch, int P, int PD,
+                                            const E *__restrict__ invk, E *__restrict__ Lexp) {
+    extern __shared__ unsigned char smem[];
+    E *Wre = reinterpret_cast<E *>(smem);
+    E *Wim = Wre + 64 * P;
+    const int lane = threadIdx.x;
+    const int b = boxes[blockIdx.x];
+    const double cx = G.cx[b], cy = G.cy[b];
+    const double s = G.side[G.level[b]];
+    E *Lo = Lexp + (int64_t)b * nbatch * PD;
+    E acc[2][16];  // rows lane and lane + 64 (2P <= 128), 16 densities at a time
+    for (int bt0 = 0; bt0 < nbatch; bt0 += 16) {
+        const int nb = min(16, nbatch - bt0);
+        for (int k = 0; k < 16; ++k) acc[0][k] = acc[1][k] = (E)0;
+        for (int e = xptr[b]; e < xptr[b + 1]; ++e) {
+            const int a = xidx[e];
+            const int s0 = R.sb[a], s1 = R.se[a];
+            for (int base = s0; base < s1; base += 64) {
+                const int cnt = min(64, s1 - base);
+                if (lane < cnt) {
+                    int j = base + lane;
+                    double dx = R.sx[j] - cx, dy = R.sy[j] - cy;
+                    double d2 = dx * dx + dy * dy;
+                    // s / (z - c) = s (dx - i dy) / d2
+                    C2<E> iw = {(E)(s * dx / d2), (E)(-s * dy / d2)};
+                    C2<E> pw = {(E)1, (E)0};
+                    Wre[lane * P] = (E)(0.5 * log(d2));
+                    Wim[lane * P] = (E)0;
+                    for (int k = 1; k < P; ++k) {
+                        pw = cmul(pw, iw);
+                        Wre[lane * P + k] = -pw.re * invk[k];
+                        Wim[lane * P + k] = -pw.im * invk[k];
+                    }
+                }
+                __syncthreads();
+                for (int r = lane, ri = 0; r < 2 * P; r += 64, ++ri) {
+                    const int k = r < P ? r : r - P;
+                    const E *Wc = r < P ? Wre : Wim;
+                    for (int bb = 0; bb < nb; ++bb) {
+                        const double *qb = q + (int64_t)(bt0 + bb) * R.nsrc + base;
+                        E t = (E)0;
+                        for (int j = 0; j < cnt; ++j) t += (E)qb[j] * Wc[j * P + k];
+                        acc[ri][bb] += t;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int r = lane, ri = 0; r < 2 * P; r += 64, ++ri)
+            for (int bb = 0; bb < nb; ++bb) Lo[(bt0 + bb) * PD + r] += acc[ri][bb];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// L2L: one wave per child box of a level; lane r adds row r of R_q L_parent.
+// ----------------------------------------------------------------------------
+template <class E>
+__global__ void __launch_bounds__(64) k_l2l(BoxGeo G, const int32_t *__restrict__ boxes, int nboxes,
+                                            int nbatch, int P, int PD, const E *__restrict__ Rl2l,
+                                            E *__restrict__ Lexp) {
+    const int lane = threadIdx.x;
+    const int b = boxes[blockIdx.x];
+    const int par = G.parent[b];
+    const int qd = (G.ix[b] & 1) | ((G.iy[b] & 1) << 1);
+    for (int r = lane; r < 2 * P; r += 64) {
+        const E *Rr = Rl2l + ((int64_t)qd * PD + r) * PD;
+        for (int bt = 0; bt < nbatch; ++bt) {
+            const E *Lp = Lexp + ((int64_t)par * nbatch + bt) * PD;
+            E acc = (E)0;
+            for (int k = 0; k < 2 * P; ++k) acc += Rr[k] * Lp[k];
+            Lexp[((int64_t)b * nbatch + bt) * PD + r] += acc;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// L2P + M2P at the targets of one leaf (one wave, lane = target):
+//   u += -(1/2pi) Re[ sum_l B_l w^l + sum_{a in W} (A_0 log(z - c_a) +
+//                    sum_k A_k (s_a/(z - c_a))^k) ]
+// and, with grad, the gradient -(1/2pi) (Re phi', -Im phi').
+// ----------------------------------------------------------------------------
+template <class E, bool GRAD>
+__global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_t *__restrict__ leaves,
+                                            const int32_t *__restrict__ wptr,
+                                            const int32_t *__restrict__ widx, int nbatch, int P,
+                                            int PD, const E *__restrict__ Mexp,
+                                            const E *__restrict__ Lexp, double *__restrict__ acc) {
+    const int lane = threadIdx.x;
+    const int b = leaves[blockIdx.x];
+    const int t0 = R.tb[b], t1 = R.te[b];
+    if (t1 <= t0) return;
+    const double cx = G.cx[b], cy = G.cy[b];
+    const int lb = G.level[b];
+    const double s = G.side[lb];
+    const bool has_local = lb >= 2;
+    for (int base = t0; base < t1; base += 64) {
+        const int t = base + lane;
+        const bool act = t < t1;
+        const double px = act ? R.tx[t] : cx, py = act ? R.ty[t] : cy;
+        const C2<E> w = {(E)((px - cx) / s), (E)((py - cy) / s)};
+        for (int bt = 0; bt < nbatch; ++bt) {
+            C2<E> phi = {(E)0, (E)0}, dphi = {(E)0, (E)0};
+            if (has_local) {
+                const E *Lb = Lexp + ((int64_t)b * nbatch + bt) * PD;
+                for (int l = P - 1; l >= 0; --l) {
+                    if (GRAD && l >= 1) {
+                        dphi = cmul(dphi, w);
+                        dphi.re += (E)l * Lb[l];
+                        dphi.im += (E)l * Lb[P + l];
+                    }
+                    phi = cmul(phi, w);
+                    phi.re += Lb[l];
+                    phi.im += Lb[P + l];
+                }
+                if (GRAD) {
+                    dphi.re /= (E)s;
+                    dphi.im /= (E)s;
+                }
+            }
+            double u = (double)phi.re;
+            double gx = (double)dphi.re, gy = -(double)dphi.im;
+            for (int e = wptr[b]; e < wptr[b + 1]; ++e) {
+                const int a = widx[e];
+                const double ax = G.cx[a], ay = G.cy[a], sa = G.side[G.level[a]];
+                const double dx = px - ax, dy = py - ay, d2 = dx * dx + dy * dy;
+                const E *Ma = Mexp + ((int64_t)a * nbatch + bt) * PD;
+                // iw = s_a / (z - c_a)
+                const C2<E> iw = {(E)(sa * dx / d2), (E)(-sa * dy / d2)};
+                C2<E> ser = {(E)0, (E)0}, dser = {(E)0, (E)0};
+                for (int k = P - 1; k >= 1; --k) {
+                    ser = cmul(ser, iw);
+                    ser.re += Ma[k];
+                    ser.im += Ma[P + k];
+                    if (GRAD) {
+                        dser = cmul(dser, iw);
+                        dser.re += (E)k * Ma[k];
+                        dser.im += (E)k * Ma[P + k];
+                    }
+                }
+                ser = cmul(ser, iw);
+                u += (double)ser.re + (double)Ma[0] * 0.5 * log(d2);
+                if (GRAD) {
+                    // phi' = (A_0 - sum_k k A_k iw^k) / (z - c)
+                    dser = cmul(dser, iw);
+                    double nre = (double)Ma[0] - (double)dser.re, nim = -(double)dser.im;
+                    // 1/(z - c) = (dx - i dy)/d2
+                    double ire = dx / d2, iim = -dy / d2;
+                    gx += nre * ire - nim * iim;
+                    gy -= nre * iim + nim * ire;
+                }
+            }
+            if (act) {
+                if (GRAD) {
+                    acc[((int64_t)bt * 2 + 0) * R.ntgt + t] += -INV_2PI * gx;
+                    acc[((int64_t)bt * 2 + 1) * R.ntgt + t] += -INV_2PI * gy;
+                } else {
+                    acc[(int64_t)bt * R.ntgt + t] += -INV_2PI * u;
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// P2P (U lists), FP64: one wave per target leaf.  Source tiles of up to
+// P2P_TILE points are staged in LDS as SoA (x, y, q per density).  When a
+// leaf has few targets the lanes also split the source loop (K lane
+// groups) and the partial sums are combined in a fixed order.
+// Pairs at zero distance (the self pair) contribute nothing.
+// Writes acc = near-field value (the first writer of acc).
+// ----------------------------------------------------------------------------
+constexpr int P2P_TILE = 256;
+
+template <int NB, bool GRAD>
+__global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restrict__ leaves,
+                                            const int32_t *__restrict__ uptr,
+                                            const int32_t *__restrict__ uidx,
+                                            const double *__restrict__ q, int nbatch, int bt0,
+                                            double *__restrict__ acc) {
+    __shared__ double xs[P2P_TILE], ys[P2P_TILE];
+    __shared__ double qs[NB][P2P_TILE];
+    __shared__ double red[GRAD ? 2 * NB : NB][64];
+    const int lane = threadIdx.x;
+    const int b = leaves[blockIdx.x];
+    const int t0 = R.tb[b], t1 = R.te[b];
+    if (t1 <= t0) return;
+    const int nt = t1 - t0;
+    int T2 = 1;
+    while (T2 < nt && T2 < 64) T2 <<= 1;
+    const int K = 64 / T2;
+    const int tl = lane % T2, kg = lane / T2;
+    const int nbh = min(NB, nbatch - bt0);
+    for (int base = t0; base < t1; base += 64) {
+        const int t = base + tl;
+        const bool act = t < t1 && (T2 < 64 || true);
+        const double px = act ? R.tx[t] : 0.0, py = act ? R.ty[t] : 0.0;
+        double a[NB], gxa[NB], gya[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) a[k] = gxa[k] = gya[k] = 0.0;
+        for (int e = uptr[b]; e < uptr[b + 1]; ++e) {
+            const int src = uidx[e];
+            const int s0 = R.sb[src], s1 = R.se[src];
+            for (int sbase = s0; sbase < s1; sbase += P2P_TILE) {
+                const int cnt = min(P2P_TILE, s1 - sbase);
+                __syncthreads();
+                for (int j = lane; j < cnt; j += 64) {
+                    xs[j] = R.sx[sbase + j];
+                    ys[j] = R.sy[sbase + j];
+#pragma unroll
+                    for (int k = 0; k < NB; ++k)
+                        qs[k][j] = (k < nbh) ? q[(int64_t)(bt0 + k) * R.nsrc + sbase + j] : 0.0;
+                }
+                __syncthreads();
+                if (act) {
+                    for (int j = kg; j < cnt; j += K) {
+                        const double dx = xs[j] - px, dy = ys[j] - py;
+                        const double r2 = dx * dx + dy * dy;
+                        if (r2 == 0.0) continue;
+                        if (GRAD) {
+                            const double ir2 = 1.0 / r2;
+#pragma unroll
+                            for (int k = 0; k < NB; ++k) {
+                                const double c = qs[k][j] * ir2;
+                                gxa[k] += c * dx;
+                                gya[k] += c * dy;
+                            }
+                        } else {
+                            const double lg = log(r2);
+#pragma unroll
+                            for (int k = 0; k < NB; ++k) a[k] += qs[k][j] * lg;
+                        }
+                    }
+                }
+            }
+        }
+        // combine the K lane groups in a fixed order
+        if (K > 1) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                if (GRAD) {
+                    red[2 * k][lane] = gxa[k];
+                    red[2 * k + 1][lane] = gya[k];
+                } else {
+                    red[k][lane] = a[k];
+                }
+            }
+            __syncthreads();
+            if (kg == 0) {
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    double s0 = 0.0, s1 = 0.0;
+                    for (int g2 = 0; g2 < K; ++g2) {
+                        if (GRAD) {
+                            s0 += red[2 * k][g2 * T2 + tl];
+                            s1 += red[2 * k + 1][g2 * T2 + tl];
+                        } else {
+                            s0 += red[k][g2 * T2 + tl];
+                        }
+                    }
+                    if (GRAD) {
+                        gxa[k] = s0;
+                        gya[k] = s1;
+                    } else {
+                        a[k] = s0;
+                    }
+                }
+            }
+        }
+        if (act && kg == 0) {
+            for (int k = 0; k < nbh; ++k) {
+                if (GRAD) {
+                    acc[((int64_t)(bt0 + k) * 2 + 0) * R.ntgt + t] = INV_2PI * gxa[k];
+                    acc[((int64_t)(bt0 + k) * 2 + 1) * R.ntgt + t] = INV_2PI * gya[k];
+                } else {
+                    acc[(int64_t)(bt0 + k) * R.ntgt + t] = -INV_4PI * a[k];
+                }
+            }
+        }
+        if (T2 < 64) break;  // all targets of the leaf handled in one pass
+    }
+}
+
+// ----------------------------------------------------------------------------
+// finish: out[b][i] = scale_i * acc[b][inv[i]] + sum_{q in row i} val[q] f[b][col[q]]
+// one wave per row, lanes over the row's non-zeros, fixed-order reduction.
+// ----------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, const int32_t *__restrict__ inv,
+                                                const double *__restrict__ scale,
+                                                const double *__restrict__ acc, int64_t acc_len,
+                                                const int64_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ colv,
+                                                const double *__restrict__ valv,
+                                                const double *__restrict__ f, int64_t flen,
+                                                double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = wave; i < nrows; i += nwaves) {
+        const int64_t p0 = rowptr ? rowptr[i] : 0, p1 = rowptr ? rowptr[i + 1] : 0;
+        const int32_t si = inv[i];
+        const double sc = scale ? scale[i] : 1.0;
+        for (int bt = 0; bt < nbatch; ++bt) {
+            double part = 0.0;
+            for (int64_t pq = p0 + lane; pq < p1; pq += 64)
+                part += valv[pq] * f[(int64_t)bt * flen + colv[pq]];
+            part = wave_sum(part);
+            if (lane == 0) out[(int64_t)bt * nrows + i] = sc * acc[(int64_t)bt * acc_len + si] + part;
+        }
+    }
+}
+
+__global__ void k_unpermute_grad(int64_t m, int nbatch, const int32_t *__restrict__ inv,
+                                 const double *__restrict__ acc, double *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int32_t si = inv[i];
+    for (int bt = 0; bt < nbatch; ++bt)
+        for (int d = 0; d < 2; ++d)
+            out[((int64_t)bt * 2 + d) * m + i] = acc[((int64_t)bt * 2 + d) * m + si];
+}
+
+// ----------------------------------------------------------------------------
+// Schedules (plan time): box groups for each pass.
+// ----------------------------------------------------------------------------
+void build_schedules(vp_plan_s *P) {
+    Tree &T = P->tree;
+    hipStream_t s = P->stream;
+    const int nbox = T.nbox;
+    std::vector<int32_t> lev(nbox), ix(nbox), iy(nbox), nch(nbox), xp(nbox + 1), wp(nbox + 1);
+    VP_HIP(hipMemcpyAsync(lev.data(), T.level, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(ix.data(), T.ix, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(iy.data(), T.iy, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(nch.data(), T.nchild, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(xp.data(), T.lptr[3], 4 * (nbox + 1), hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(wp.data(), T.lptr[2], 4 * (nbox + 1), hipMemcpyDeviceToHost, s));
+    VP_HIP(hipStreamSynchronize(s));
+    auto up = [&](const std::vector<int32_t> &h) {
+        int32_t *d = P->mem.alloc<int32_t>(h.size());
+        if (!h.empty()) VP_HIP(hipMemcpyAsync(d, h.data(), 4 * h.size(), hipMemcpyHostToDevice, s));
+        return d;
+    };
+    // M2L columns and L2L boxes: levels >= 2 grouped by child class, level order kept
+    std::vector<int32_t> m2l;
+    for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < nbox; ++b)
+            if (lev[b] >= 2 && ((ix[b] & 1) | ((iy[b] & 1) << 1)) == c) m2l.push_back(b);
+    P->n_m2l_boxes = (int)m2l.size();
+    P->m2l_cols = up(m2l);
+    std::vector<int32_t> lb, par;
+    P->lvl_box_begin.assign(T.nlevels + 1, 0);
+    P->m2m_begin.assign(T.nlevels + 1, 0);
+    for (int l = 0; l < T.nlevels; ++l) {
+        P->lvl_box_begin[l] = (int)lb.size();
+        P->m2m_begin[l] = (int)par.size();
+        for (int b = T.level_begin[l]; b < T.level_begin[l + 1]; ++b) {
+            lb.push_back(b);
+            if (nch[b] > 0) par.push_back(b);
+        }
+    }
+    P->lvl_box_begin[T.nlevels] = (int)lb.size();
+    P->m2m_begin[T.nlevels] = (int)par.size();
+    P->lvl_boxes = up(lb);
+    P->m2m_parents = up(par);
+    std::vector<int32_t> p2m, xb, wl;
+    for (int b = 0; b < nbox; ++b) {
+        if (nch[b] == 0 && lev[b] >= 2) p2m.push_back(b);
+        if (xp[b + 1] > xp[b]) xb.push_back(b);
+        if (nch[b] == 0 && wp[b + 1] > wp[b]) wl.push_back(b);
+    }
+    P->n_p2m = (int)p2m.size();
+    P->p2m_leaves = up(p2m);
+    P->n_x_boxes = (int)xb.size();
+    P->x_boxes = up(xb);
+    P->n_w_leaves = (int)wl.size();
+    P->w_leaves = up(wl);
+    VP_HIP(hipStreamSynchronize(s));
+}
+
+// ----------------------------------------------------------------------------
+// Host orchestration of one evaluation
+// ----------------------------------------------------------------------------
+static PointRoles roles(vp_plan_s *P, bool adjoint) {
+    Tree &T = P->tree;
+    PointRoles R;
+    if (!adjoint) {
+        R = {P->sx, P->sy, T.sb, T.se, P->tx, P->ty, T.tb, T.te, P->n, P->m};
+    } else {
+        R = {P->tx, P->ty, T.tb, T.te, P->sx, P->sy, T.sb, T.se, P->m, P->n};
+    }
+    return R;
+}
+
+static BoxGeo geo(vp_plan_s *P) {
+    Tree &T = P->tree;
+    return BoxGeo{T.level, T.ix, T.iy, T.parent, T.child, T.nchild, T.cx, T.cy, T.d_side, T.d_logside};
+}
+
+void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
+    int64_t len = adjoint ? P->m : P->n;
+    const int32_t *perm = adjoint ? P->tperm : P->sperm;
+    const double *w = adjoint ? nullptr : P->sw;
+    hipLaunchKernelGGL(k_charge, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, P->stream, f, perm, w,
+                       P->q, len, P->nbatch);
+    VP_LAUNCH_CHECK();
+}
+
+template <class E>
+static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
+    Tree &T = P->tree;
+    hipStream_t s = P->stream;
+    const int nb = P->nbatch, Pn = P->P, PD = P->PD;
+    E *M = static_cast<E *>(P->Mexp);
+    E *L = static_cast<E *>(P->Lexp);
+    const bool f32 = sizeof(E) == 4;
+    const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
+    const E *Rm2m = f32 ? (const E *)P->ops.m2m_f32 : (const E *)P->ops.m2m_f64;
+    const E *Rl2l = f32 ? (const E *)P->ops.l2l_f32 : (const E *)P->ops.l2l_f64;
+    const size_t lds = sizeof(E) * 2 * 64 * Pn;
+    if (T.nlevels < 3) return;  // no box is well separated from another
+    if (P->n_p2m > 0) {
+        hipLaunchKernelGGL(k_p2m<E>, dim3(P->n_p2m), dim3(64), lds, s, R, G, P->p2m_leaves, P->n_p2m,
+                           P->q, nb, Pn, PD, invk, M);
+        VP_LAUNCH_CHECK();
+    }
+    for (int l = T.nlevels - 2; l >= 2; --l) {
+        int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
+        if (c1 > c0) {
+            hipLaunchKernelGGL(k_m2m<E>, dim3(c1 - c0), dim3(64), 0, s, G, P->m2m_parents + c0, c1 - c0, nb,
+                               Pn, PD, Rm2m, M);
+            VP_LAUNCH_CHECK();
+        }
+    }
+    const int ncols = P->n_m2l_boxes * nb;
+    const unsigned ntiles = (unsigned)((ncols + 15) / 16);
+    if (ncols > 0) {
+        if (!f32) {
+            switch (PD) {
+#define VP_M2L64(RBV)                                                                                   \
+    case RBV * 16:                                                                                      \
+        hipLaunchKernelGGL(k_m2l_f64<RBV>, dim3(ntiles), dim3(64), 0, s, P->m2l_cols, ncols, nb, Pn,     \
+                           T.v_slot, T.level, T.d_logside, P->ops.m2l_f64, (const double *)M, (double *)L); \
+        break;
+                VP_M2L64(1) VP_M2L64(2) VP_M2L64(3) VP_M2L64(4) VP_M2L64(5) VP_M2L64(6) VP_M2L64(7)
+                VP_M2L64(8)
+#undef VP_M2L64
+                default:
+                    throw Error(VP_EUNSUPPORTED, "order too large for the M2L kernel");
+            }
+        } else {
+            int mode = P->m2l_mode == VP_M2L_FP32_SPLIT ? 1 : (P->m2l_mode == VP_M2L_FP64_MFMA ? 2 : 0);
+            switch (PD * 4 + mode) {
+#define VP_M2L32(RBV, MD)                                                                              \
+    case RBV * 64 + MD:                                                                                \
+        hipLaunchKernelGGL((k_m2l_f32<RBV, MD>), dim3(ntiles), dim3(64), 0, s, P->m2l_cols, ncols, nb,  \
+                           Pn, T.v_slot, T.level, T.d_logside, P->ops.m2l_f32, P->ops.m2l_f32_lo,       \
+                           P->ops.m2l_f64, (const float *)M, (float *)L);                              \
+        break;
+                VP_M2L32(1, 0) VP_M2L32(1, 1) VP_M2L32(1, 2) VP_M2L32(2, 0) VP_M2L32(2, 1) VP_M2L32(2, 2)
+                VP_M2L32(3, 0) VP_M2L32(3, 1) VP_M2L32(3, 2) VP_M2L32(4, 0) VP_M2L32(4, 1) VP_M2L32(4, 2)
+                VP_M2L32(5, 0) VP_M2L32(5, 1) VP_M2L32(5, 2) VP_M2L32(6, 0) VP_M2L32(6, 1) VP_M2L32(6, 2)
+                VP_M2L32(7, 0) VP_M2L32(7, 1) VP_M2L32(7, 2) VP_M2L32(8, 0) VP_M2L32(8, 1) VP_M2L32(8, 2)
+#undef VP_M2L32
+                default:
+                    throw Error(VP_EUNSUPPORTED, "order too large for the M2L kernel");
+            }
+        }
+        VP_LAUNCH_CHECK();
+    }
+    if (P->n_x_boxes > 0) {
+        hipLaunchKernelGGL(k_p2l<E>, dim3(P->n_x_boxes), dim3(64), lds, s, R, G, P->x_boxes, T.lptr[3],
+                           T.lidx[3], P->q, nb, Pn, PD, invk, L);
+        VP_LAUNCH_CHECK();
+    }
+    for (int l = 3; l < T.nlevels; ++l) {
+        int c0 = P->lvl_box_begin[l], c1 = P->lvl_box_begin[l + 1];
+        if (c1 > c0) {
+            hipLaunchKernelGGL(k_l2l<E>, dim3(c1 - c0), dim3(64), 0, s, G, P->lvl_boxes + c0, c1 - c0, nb, Pn,
+                               PD, Rl2l, L);
+            VP_LAUNCH_CHECK();
+        }
+    }
+}
+
+template <int NB, bool GRAD>
+static void launch_p2p(vp_plan_s *P, const PointRoles &R, int bt0, double *acc) {
+    Tree &T = P->tree;
+    hipLaunchKernelGGL((k_p2p<NB, GRAD>), dim3(T.nleaf), dim3(64), 0, P->stream, R, T.leaves, T.lptr[0],
+                       T.lidx[0], P->q, P->nbatch, bt0, acc);
+    VP_LAUNCH_CHECK();
+}
+
+template <bool GRAD>
+static void run_p2p(vp_plan_s *P, const PointRoles &R, double *acc) {
+    int nb = P->nbatch;
+    for (int bt0 = 0; bt0 < nb;) {
+        int left = nb - bt0;
+        if (left >= 16) {
+            launch_p2p<16, GRAD>(P, R, bt0, acc);
+            bt0 += 16;
+        } else if (left >= 8) {
+            launch_p2p<8, GRAD>(P, R, bt0, acc);
+            bt0 += 8;
+        } else if (left >= 4) {
+            launch_p2p<4, GRAD>(P, R, bt0, acc);
+            bt0 += 4;
+        } else if (left >= 2) {
+            launch_p2p<2, GRAD>(P, R, bt0, acc);
+            bt0 += 2;
+        } else {
+            launch_p2p<1, GRAD>(P, R, bt0, acc);
+            bt0 += 1;
+        }
+    }
+}
+
+template <class E, bool GRAD>
+static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *acc) {
+    Tree &T = P->tree;
+    hipLaunchKernelGGL((k_far<E, GRAD>), dim3(T.nleaf), dim3(64), 0, P->stream, R, G, T.leaves, T.lptr[2],
+                       T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp, (const E *)P->Lexp, acc);
+    VP_LAUNCH_CHECK();
+}
+
+void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
+    PointRoles R = roles(P, adjoint);
+    BoxGeo G = geo(P);
+    if (P->fp32) run_expansions<float>(P, R, G);
+    else run_expansions<double>(P, R, G);
+    if (grad) {
+        run_p2p<true>(P, R, P->acc);
+        if (P->tree.nlevels >= 3) {
+            if (P->fp32) run_far<float, true>(P, R, G, P->acc);
+            else run_far<double, true>(P, R, G, P->acc);
+        }
+    } else {
+        run_p2p<false>(P, R, P->acc);
+        if (P->tree.nlevels >= 3) {
+            if (P->fp32) run_far<float, false>(P, R, G, P->acc);
+            else run_far<double, false>(P, R, G, P->acc);
+        }
+    }
+}
+
+void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint) {
+    const int64_t nrows = adjoint ? P->n : P->m;
+    const int32_t *inv = adjoint ? P->sinv : P->tinv;
+    const double *scale = adjoint ? P->w_user : nullptr;
+    const int64_t *rp = adjoint ? P->rowptrT : P->rowptr;
+    const int32_t *cv = adjoint ? P->colT : P->col;
+    const double *vv = adjoint ? P->valT : P->val;
+    const int64_t flen = adjoint ? P->m : P->n;
+    int64_t waves = nrows;
+    int64_t blocks = (waves + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)blocks), dim3(256), 0, P->stream, nrows, P->nbatch, inv, scale,
+                       P->acc, nrows, rp, cv, vv, f, flen, u);
+    VP_LAUNCH_CHECK();
+}
+
+void finish_grad(vp_plan_s *P, double *grad) {
+    hipLaunchKernelGGL(k_unpermute_grad, dim3((unsigned)((P->m + 255) / 256)), dim3(256), 0, P->stream, P->m,
+                       P->nbatch, P->tinv, P->acc, grad);
+    VP_LAUNCH_CHECK();
+}
+
+}  // namespace vp

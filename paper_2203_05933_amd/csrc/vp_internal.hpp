@@ -1,0 +1,246 @@
+// Internal declarations of libvp: the plan object, error plumbing, device
+// helpers shared by the tree, FMM and correction kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/vp.h"
+
+namespace vp {
+
+// ----------------------------------------------------------------------------
+// Errors.  Internal code throws; the C ABI catches and maps to vp_status.
+// ----------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    vp_status status;
+    Error(vp_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] void throw_hip(hipError_t e, const char *expr, const char *file, int line);
+
+#define VP_HIP(expr)                                                   \
+    do {                                                               \
+        hipError_t _vp_e = (expr);                                     \
+        if (_vp_e != hipSuccess) ::vp::throw_hip(_vp_e, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define VP_LAUNCH_CHECK() VP_HIP(hipGetLastError())
+
+// ----------------------------------------------------------------------------
+// Constants
+// ----------------------------------------------------------------------------
+constexpr int LBITS = 30;              // quantisation bits per coordinate
+constexpr int NOFF = 40;               // M2L offsets: [-3,3]^2 minus [-1,1]^2
+constexpr int MAX_BATCH = 64;
+constexpr double INV_2PI = 0.15915494309189533576888376337251436;
+constexpr double INV_4PI = 0.07957747154594766788444188168625718;
+
+// offset code of (dx, dy) in [-3,3]^2 with max(|dx|,|dy|) >= 2, else -1
+__host__ __device__ inline int offset_code(int dx, int dy) {
+    if (dx < -3 || dx > 3 || dy < -3 || dy > 3) return -1;
+    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) return -1;
+    int c = (dy + 3) * 7 + (dx + 3);  // 0..48
+    // remove the 9 inner codes (dy in -1..1, dx in -1..1) from the numbering
+    int inner_before = 0;
+    if (dy > 1) inner_before = 9;
+    else if (dy >= -1) inner_before = (dy + 1) * 3 + (dx > 1 ? 3 : 0);
+    return c - inner_before;
+}
+
+// ----------------------------------------------------------------------------
+// Device memory owned by a plan
+// ----------------------------------------------------------------------------
+struct DeviceArena {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    template <class T>
+    T *alloc(size_t count) {
+        if (count == 0) count = 1;
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(VP_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+        ptrs.push_back(p);
+        bytes += count * sizeof(T);
+        return static_cast<T *>(p);
+    }
+    void release(void *p) {
+        for (auto &q : ptrs)
+            if (q == p) {
+                (void)hipFree(q);
+                q = nullptr;
+            }
+    }
+    void free_all() {
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+// Temporary device buffers freed at scope exit (plan time only).
+struct TempArena {
+    std::vector<void *> ptrs;
+    template <class T>
+    T *alloc(size_t count) {
+        if (count == 0) count = 1;
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(VP_ENOMEM, "hipMalloc (temporary) failed");
+        }
+        ptrs.push_back(p);
+        return static_cast<T *>(p);
+    }
+    ~TempArena() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+};
+
+// ----------------------------------------------------------------------------
+// Tree and lists as held on the device
+// ----------------------------------------------------------------------------
+struct Tree {
+    int nbox = 0, nlevels = 0, nleaf = 0;
+    std::vector<int32_t> level_begin;  // host copy, nlevels+1
+    std::vector<double> side;          // host, per level
+    int32_t *d_level_begin = nullptr;
+    int32_t *level = nullptr, *ix = nullptr, *iy = nullptr, *parent = nullptr;
+    int32_t *child = nullptr, *nchild = nullptr;
+    int32_t *sb = nullptr, *se = nullptr, *tb = nullptr, *te = nullptr;
+    uint64_t *key = nullptr;           // Morton key of (ix, iy) on its level
+    double *cx = nullptr, *cy = nullptr;
+    double *d_side = nullptr;          // per level
+    double *d_logside = nullptr;       // per level
+    int32_t *leaves = nullptr;         // leaf box indices
+    // lists, CSR over all boxes
+    int32_t *lptr[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t *lidx[4] = {nullptr, nullptr, nullptr, nullptr};
+    int64_t llen[4] = {0, 0, 0, 0};
+    int32_t *v_off = nullptr;          // offset code of each V entry
+    int32_t *v_slot = nullptr;         // [nbox][NOFF] source box or -1
+};
+
+// Translation operators in real PD x PD form (see vp_ops.cpp).
+struct Operators {
+    int P = 0, PD = 0;
+    // A-fragment order for the MFMA kernels: [op][rb][s][lane]
+    double *m2l_f64 = nullptr;  // NOFF ops
+    float *m2l_f32 = nullptr;
+    float *m2l_f32_lo = nullptr;
+    // row-major [op][PD][PD] for the VALU kernels
+    double *m2m_f64 = nullptr, *l2l_f64 = nullptr;  // 4 ops each
+    float *m2m_f32 = nullptr, *l2l_f32 = nullptr;
+    double *inv_k = nullptr;  // 1/k, k = 0..P-1 (0 for k = 0)
+    float *inv_k_f32 = nullptr;
+};
+
+// Near-field tables for congruent leaves (uniform box grids).
+struct NearTables {
+    bool active = false;
+    int npat = 0;               // points per pattern leaf
+    int nleaf_tab = 0;          // number of table-served target leaves
+    int32_t *tab_leaves = nullptr;   // target leaves served by tables
+    int32_t *tab_nbr = nullptr;      // [nleaf_tab][9] neighbour leaf (or -1) per offset
+    int32_t *pair_leaves = nullptr;  // leaves served by the pairwise kernel
+    int npair_leaves = 0;
+    int32_t *pair_uptr = nullptr;    // U list of pairwise leaves minus table-served entries
+    int32_t *pair_uidx = nullptr;
+    double *K = nullptr;        // per level group: [9][npat][npat] in MFMA A-fragment order
+    int nlev_tab = 0;
+    std::vector<int> tab_level_of;  // level per K block
+};
+
+}  // namespace vp
+
+// ----------------------------------------------------------------------------
+// The plan
+// ----------------------------------------------------------------------------
+struct vp_plan_s {
+    vp_options opt{};
+    int p = 30, P = 31, PD = 64;
+    int64_t n = 0, m = 0, nnz = 0;
+    int nbatch = 1;
+    bool self = false;
+    bool fp32 = false;
+    int m2l_mode = VP_M2L_FP64_MFMA;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    bool poisoned = false;
+
+    vp::DeviceArena mem;
+    // points in sorted (Morton) order
+    double *sx = nullptr, *sy = nullptr, *sw = nullptr;
+    int32_t *sperm = nullptr, *sinv = nullptr;
+    uint64_t *skeys = nullptr;
+    double *tx = nullptr, *ty = nullptr;
+    int32_t *tperm = nullptr, *tinv = nullptr;
+    uint64_t *tkeys = nullptr;
+    double *w_user = nullptr;  // weights in user order (adjoint)
+    // correction matrix (user order) and its transpose
+    int64_t *rowptr = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr;
+    int64_t *rowptrT = nullptr;
+    int32_t *colT = nullptr;
+    double *valT = nullptr;
+
+    vp::Tree tree;
+    vp::Operators ops;
+    vp::NearTables near;
+    int64_t near_pairs = 0;
+
+    // evaluation workspace
+    double *q = nullptr;     // [nbatch][max(n,m)] charges, sorted order
+    double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order
+    void *Mexp = nullptr;    // [nbox][nbatch][PD] (double or float)
+    void *Lexp = nullptr;
+    int32_t *m2l_cols = nullptr;  // boxes with a V list, grouped by child class
+    int n_m2l_boxes = 0;
+    int32_t *lvl_boxes = nullptr;  // boxes of each level >= 1 grouped by class (L2L)
+    std::vector<int> lvl_box_begin;  // per level offsets into lvl_boxes
+    int32_t *m2m_parents = nullptr;  // non-leaf boxes per level
+    std::vector<int> m2m_begin;
+    int32_t *p2m_leaves = nullptr;   // leaves at level >= 2 with sources
+    int n_p2m = 0;
+    int32_t *x_boxes = nullptr;      // boxes with a non-empty X list
+    int n_x_boxes = 0;
+    int32_t *w_leaves = nullptr;     // leaves with non-empty W list
+    int n_w_leaves = 0;
+    int32_t *err_flag = nullptr;     // device error flag (list traversal overflow)
+};
+
+namespace vp {
+// vp_tree.hip
+void build_tree(vp_plan_s *P, const double *hx, const double *hy, const double *htx,
+                const double *hty);
+// vp_ops.cpp
+void build_operators(vp_plan_s *P);
+// vp_near.hip
+void build_near_tables(vp_plan_s *P);  // vp_near.hip
+// vp_fmm.hip
+void build_schedules(vp_plan_s *P);
+void run_fmm(vp_plan_s *P, bool adjoint, bool grad);
+void prepare_charges(vp_plan_s *P, const double *f, bool adjoint);
+void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint);
+void finish_grad(vp_plan_s *P, double *grad);
+// vp_csr.hip
+void build_csr_transpose(vp_plan_s *P);
+// utilities (vp_tree.hip)
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int n, hipStream_t s);
+void radix_sort_pairs_u64(uint64_t *keys, int32_t *vals, int n, int nbits, hipStream_t s);
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void fill_f64(double *p, double v, int64_t n, hipStream_t s);
+void fill_f32(float *p, float v, int64_t n, hipStream_t s);
+}  // namespace vp

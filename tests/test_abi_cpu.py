@@ -1,0 +1,93 @@
+"""The C-ABI library loads, exports every symbol include/vp.h declares, and
+rejects invalid arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2203_05933_amd import vp
+    return vp, vp.load_library()
+
+
+def test_exports_match_header():
+    vp, lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "vp.h")).read()
+    declared = set(re.findall(r"\b(vp_[a-z_]+)\s*\(", hdr))
+    assert declared == set(vp.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_options_struct_layout():
+    vp, lib = _lib()
+    o = vp.default_options()
+    assert (o.order, o.max_leaf, o.nbatch, o.precision) == (30, 64, 1, 0)
+    assert ctypes.sizeof(vp.Options) == 8 * 4 + 3 * 8 + 8
+
+
+def _plan(lib, vp, x, y, w, n, tx=None, ty=None, m=None, rowptr=None, col=None, val=None, **opt):
+    o = vp.default_options()
+    for k, v in opt.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    p = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    st = lib.vp_plan(p(x), p(y), p(w), n, p(tx), p(ty), n if m is None else m, p(rowptr), p(col), p(val),
+                     ctypes.byref(o), ctypes.byref(h))
+    return st, h, lib.vp_last_error(None).decode()
+
+
+@pytest.mark.parametrize("case", ["n0", "nan", "m_mismatch", "rowptr0", "rowptr_dec", "col_range",
+                                  "order", "nbatch", "leaf", "fp32_mode", "flags"])
+def test_plan_rejects_invalid(case):
+    vp, lib = _lib()
+    x = np.linspace(0, 1, 8)
+    y = np.linspace(0, 1, 8)[::-1].copy()
+    w = np.ones(8)
+    rowptr = np.arange(0, 17, 2, dtype=np.int64)
+    col = np.zeros(16, dtype=np.int32)
+    val = np.ones(16)
+    kw = {}
+    n = 8
+    if case == "n0":
+        n = 0
+    elif case == "nan":
+        x = x.copy(); x[3] = np.nan
+    elif case == "rowptr0":
+        rowptr = rowptr + 1
+    elif case == "rowptr_dec":
+        rowptr = rowptr.copy(); rowptr[4] = 1
+    elif case == "col_range":
+        col = col.copy(); col[5] = 8
+    elif case == "order":
+        kw["order"] = 0
+    elif case == "nbatch":
+        kw["nbatch"] = 65
+    elif case == "leaf":
+        kw["max_leaf"] = 0
+    elif case == "fp32_mode":
+        kw["m2l_mode"] = 2  # FP32 M2L with precision FP64
+    elif case == "flags":
+        kw["flags"] = 1
+    if case == "m_mismatch":
+        st, h, msg = _plan(lib, vp, x, y, w, n, m=7, rowptr=rowptr, col=col, val=val)
+    else:
+        st, h, msg = _plan(lib, vp, x, y, w, n, rowptr=rowptr, col=col, val=val, **kw)
+    assert st == vp.VP_EINVAL, (st, msg)
+    assert h.value is None
+    assert len(msg) > 0
+
+
+def test_null_plan_calls():
+    vp, lib = _lib()
+    assert lib.vp_eval(None, None, None) == vp.VP_EINVAL
+    assert lib.vp_eval_adjoint(None, None, None) == vp.VP_EINVAL
+    assert lib.vp_eval_grad_targets(None, None, None) == vp.VP_EINVAL
+    assert lib.vp_destroy(None) == vp.VP_OK
+    assert lib.vp_set_stream(None, None) == vp.VP_EINVAL
+    assert b"NULL" in lib.vp_last_error(None)
