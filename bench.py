@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the volume-potential evaluation hot path on one MI355X.
+
+Workload (default): the star-shaped domain r = 1 + 0.3 cos 5 theta with an
+adaptive box quadtree and a boundary band of triangles, 1,488,064 nodes,
+targets = nodes, own-cell correction matrix, one density, FMM order p = 30
+in float64.  A step is one full evaluation u = V f + C f (charges, upward
+pass, M2L, downward pass, near field, far-field evaluation, correction and
+un-permutation) with inputs resident in HBM; the plan (tree, lists,
+operators) is built once beforehand, as the paper excludes set-up from its
+timings.  The FP32-bulk form (p = 14) is measured on the same workload and
+reported alongside.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpoints/s volume-potential eval at rel err 1e-12 (FP64) vs 1e-6 (FP32 form)"
+FP64_VECTOR_TFLOPS = 78.6   # MI355X published peak, FP64 vector
+FP64_MFMA_TFLOPS = 78.6     # MI355X published peak, FP64 matrix (dense)
+FP32_MFMA_TFLOPS = 157.3    # MI355X published peak, FP32 matrix (dense)
+P2P_FLOPS_PER_PAIR = 27     # 2 differences, 3 for r^2, 20 for log(r^2), 2 for the update
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from vp_workloads import generators as gen
+    if name == "star":
+        return gen.config1()
+    if name == "uniform128":
+        return gen.config2()
+    if name == "uniform16":
+        return gen.config0()
+    if name == "uniform256x16":
+        return gen.config3()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_evals(plan, f, u, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.eval(f, out=u)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.eval(f, out=u)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tim = plan.timing()
+    plan.set_timing(False)
+    return dt, tim
+
+
+def roofline(plan, tim, precision):
+    """Roofline record of the stage with the largest device time."""
+    info = plan.info()
+    ms = tim["ms"]
+    n = max(tim["evals"], 1)
+    stage = max(ms, key=lambda k: ms[k])
+    avg_s = ms[stage] / n / 1e3
+    P = info["order"] + 1
+    nb = info["nbatch"]
+    if stage == "p2p":
+        flops = info["near_pairs"] * nb * P2P_FLOPS_PER_PAIR
+        return stage, {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP64_VECTOR_TFLOPS,
+                       "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / FP64_VECTOR_TFLOPS, "traffic": None,
+                       "kernel": "k_p2p", "avg_ms": avg_s * 1e3,
+                       "work": f"{info['near_pairs']} pairs x {nb} densities x {P2P_FLOPS_PER_PAIR} flops"}
+    if stage == "m2l":
+        flops = info["list_len"][1] * nb * 8 * P * P
+        peak = FP64_MFMA_TFLOPS if precision == "fp64" else FP32_MFMA_TFLOPS
+        return stage, {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+                       "frac": flops / avg_s / 1e12 / peak, "traffic": None, "kernel": "k_m2l",
+                       "avg_ms": avg_s * 1e3,
+                       "work": f"{info['list_len'][1]} translations x {nb} densities x 8 P^2 flops (P={P})"}
+    if stage == "finish":
+        nnz = info["nnz"]
+        bytes_ = nnz * 12 + info["m"] * 8 * (2 * nb) + info["m"] * 8 + nnz * 8 * nb
+        return stage, {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                       "frac": bytes_ / avg_s / 1e9 / 8000.0, "traffic": None, "kernel": "k_finish",
+                       "avg_ms": avg_s * 1e3}
+    return stage, {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                   "traffic": None, "kernel": stage, "avg_ms": avg_s * 1e3}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="star", choices=["star", "uniform128", "uniform16", "uniform256x16"])
+    ap.add_argument("--order", type=int, default=30)
+    ap.add_argument("--order-fp32", type=int, default=14)
+    ap.add_argument("--max-leaf", type=int, default=64)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (cpu_baseline and errors)")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="targets the oracle evaluates")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
+              "(the evaluation is single-device; see the design notes on sharding).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2203_05933_amd import vp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"[bench] generating workload {args.workload}")
+    wl = workload(args.workload)
+    nb = wl.nbatch
+    log(f"[bench] n={wl.n} m={wl.m} nbatch={nb} nnz={0 if wl.rowptr is None else int(wl.rowptr[-1])}")
+
+    f = torch.tensor(wl.f, dtype=torch.float64, device="cuda:0")
+    u = torch.empty((nb, wl.m), dtype=torch.float64, device="cuda:0")
+
+    t0 = time.perf_counter()
+    plan = vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=args.order,
+                   max_leaf=args.max_leaf, nbatch=nb, precision="fp64", root=wl.root)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+    log(f"[bench] fp64 plan {plan_ms:.0f} ms: boxes={info['nbox']} leaves={info['nleaf']} "
+        f"levels={info['nlevels']} lists={info['list_len']} near_pairs={info['near_pairs']}")
+    dt, tim = time_evals(plan, f, u, args.steps, args.warmup)
+    ms_per_step = dt / args.steps * 1e3
+    value = wl.m * nb / (dt / args.steps) / 1e6
+    log(f"[bench] fp64: {ms_per_step:.3f} ms/eval, {value:.1f} Mpoints/s; stages(ms/eval)="
+        + json.dumps({k: round(v / max(tim['evals'], 1), 4) for k, v in tim["ms"].items()}))
+    stage, roof = roofline(plan, tim, "fp64")
+    u64 = u.clone()
+
+    out32 = None
+    if not args.no_fp32:
+        plan32 = vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=args.order_fp32,
+                         max_leaf=args.max_leaf, nbatch=nb, precision="fp32", root=wl.root)
+        u32 = torch.empty_like(u)
+        dt32, tim32 = time_evals(plan32, f, u32, args.steps, args.warmup)
+        v32 = wl.m * nb / (dt32 / args.steps) / 1e6
+        out32 = {"value": v32, "ms_per_step": dt32 / args.steps * 1e3, "order": args.order_fp32,
+                 "m2l": "fp32 mfma", "stages_ms": {k: v / max(tim32["evals"], 1) for k, v in tim32["ms"].items()},
+                 "speedup_vs_fp64": v32 / value}
+        log(f"[bench] fp32-bulk: {out32['ms_per_step']:.3f} ms/eval, {v32:.1f} Mpoints/s")
+        plan32_u = u32
+    cpu = None
+    rel64 = rel32 = None
+    if not args.no_cpu:
+        from oracle import direct
+        sample = wl.sample if wl.sample is not None else np.arange(wl.m)
+        sample = sample[: args.cpu_sample]
+        log(f"[bench] oracle on {len(sample)} sampled targets x {wl.n} nodes ({direct.num_threads()} threads)")
+        t0 = time.perf_counter()
+        ref = direct.evaluate(wl.x, wl.y, wl.w, wl.f, wl.rowptr, wl.col, wl.val, wl.tx, wl.ty, tidx=sample)
+        tc = time.perf_counter() - t0
+        cpu = {"value": len(sample) * nb / tc / 1e6, "unit": "Mpoints/s", "cores": direct.num_threads(),
+               "kind": "oracle",
+               "sample": f"{len(sample)} seeded targets of the same workload against all {wl.n} nodes "
+                         f"(direct float64 sum with compensated summation + CSR row), {tc:.1f} s"}
+        got = u64.cpu().numpy()[:, sample]
+        rel64 = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        if out32 is not None:
+            got32 = plan32_u.cpu().numpy()[:, sample]
+            rel32 = float(np.max(np.abs(got32 - ref)) / np.max(np.abs(ref)))
+            out32["rel_err"] = rel32
+        log(f"[bench] rel_inf err fp64={rel64:.3e} fp32={rel32}")
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.n} nodes, targets=nodes, {nb} density, p={args.order} float64, "
+                               f"max_leaf={args.max_leaf}", "n": wl.n, "m": wl.m, "nbatch": nb,
+                   "order": args.order, "nnz": int(info["nnz"]), "parallelism": "single GPU"},
+        "rel_err": rel64,
+        "plan_ms": plan_ms,
+        "stages_ms": {k: v / max(tim["evals"], 1) for k, v in tim["ms"].items()},
+        "dominant_stage": stage,
+        "roofline": roof,
+        "fp32_form": out32,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

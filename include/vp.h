@@ -177,6 +177,22 @@ enum {
 };
 vp_status vp_get_array(vp_plan_t plan, int32_t which, void *out, int64_t *count);
 
+/*
+ * Per-stage device timing of evaluations (profiling aid).  When enabled, each
+ * stage of vp_eval / vp_eval_adjoint / vp_eval_grad_targets is bracketed by
+ * HIP events recorded on the plan's stream (no host synchronisation inside
+ * the evaluation).  vp_set_timing(plan, 1) creates the events and clears the
+ * accumulators, (plan, 0) releases them.  vp_get_timing synchronises the
+ * stream and returns the summed milliseconds per stage (ms[VP_NSTAGES]) and
+ * the number of timed evaluations.
+ */
+enum {
+    VP_STAGE_CHARGE = 0, VP_STAGE_P2M = 1, VP_STAGE_M2M = 2, VP_STAGE_M2L = 3, VP_STAGE_P2L = 4,
+    VP_STAGE_L2L = 5, VP_STAGE_P2P = 6, VP_STAGE_FAR = 7, VP_STAGE_FINISH = 8, VP_NSTAGES = 9
+};
+vp_status vp_set_timing(vp_plan_t plan, int32_t enable);
+vp_status vp_get_timing(vp_plan_t plan, double *ms, int64_t *nevals);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,39 @@ namespace vp {
 
 using vp::Error;
 
+// ---------------------------------------------------------------------------
+// per-stage timing
+// ---------------------------------------------------------------------------
+void vp_plan_s::timing_eval_begin() {
+    if (!timing) return;
+    if (tcount - tdone >= TRING) timing_collect(tcount - TRING + 1);
+    tcur = (int)(tcount % TRING);
+    tslot_used[tcur] = 0;
+    ++tcount;
+}
+void vp_plan_s::stage_begin(int st) {
+    if (!timing || tcur < 0) return;
+    VP_HIP(hipEventRecord(tev[((size_t)tcur * VP_NSTAGES + st) * 2], stream));
+    tslot_used[tcur] |= 1 << st;
+}
+void vp_plan_s::stage_end(int st) {
+    if (!timing || tcur < 0) return;
+    VP_HIP(hipEventRecord(tev[((size_t)tcur * VP_NSTAGES + st) * 2 + 1], stream));
+}
+void vp_plan_s::timing_collect(int64_t upto) {
+    for (; tdone < upto; ++tdone) {
+        int slot = (int)(tdone % TRING);
+        for (int st = 0; st < VP_NSTAGES; ++st) {
+            if (!(tslot_used[slot] & (1 << st))) continue;
+            hipEvent_t a = tev[((size_t)slot * VP_NSTAGES + st) * 2], b = tev[((size_t)slot * VP_NSTAGES + st) * 2 + 1];
+            VP_HIP(hipEventSynchronize(b));
+            float ms = 0.f;
+            VP_HIP(hipEventElapsedTime(&ms, a, b));
+            tms[st] += ms;
+        }
+    }
+}
+
 static thread_local std::string g_last_error;
 
 static vp_status set_err(vp_plan_s *P, vp_status st, const std::string &msg) {
@@ -112,10 +145,17 @@ static void validate_plan_args(const double *x, const double *y, const double *w
         bad("non-finite root square");
 }
 
+static void release_timing(vp_plan_s *P) {
+    for (hipEvent_t e : P->tev) (void)hipEventDestroy(e);
+    P->tev.clear();
+    P->timing = false;
+}
+
 static void free_plan(vp_plan_s *P) {
     if (!P) return;
     if (P->stream) (void)hipStreamSynchronize(P->stream);
     else (void)hipDeviceSynchronize();
+    release_timing(P);
     P->mem.free_all();
     delete P;
 }
@@ -200,10 +240,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         }
     });
     if (st != VP_OK) {
-        if (P) {
-            g_last_error = P->err;
-            free_plan(P);
-        }
+        free_plan(P);  // the message is already in the thread-local slot
         return st;
     }
     *out = P;
@@ -222,6 +259,7 @@ extern "C" vp_status vp_eval(vp_plan_t P, const double *f, double *u) {
     if (overlaps(f, 8 * (size_t)P->nbatch * P->n, u, 8 * (size_t)P->nbatch * P->m))
         return set_err(P, VP_EINVAL, "f and u overlap");
     return guarded(P, [&] {
+        P->timing_eval_begin();
         vp::prepare_charges(P, f, false);
         vp::run_fmm(P, false, false);
         vp::finish_output(P, f, u, false);
@@ -235,6 +273,7 @@ extern "C" vp_status vp_eval_adjoint(vp_plan_t P, const double *g, double *df) {
     if (overlaps(g, 8 * (size_t)P->nbatch * P->m, df, 8 * (size_t)P->nbatch * P->n))
         return set_err(P, VP_EINVAL, "g and df overlap");
     return guarded(P, [&] {
+        P->timing_eval_begin();
         vp::prepare_charges(P, g, true);
         vp::run_fmm(P, true, false);
         vp::finish_output(P, g, df, true);
@@ -248,6 +287,7 @@ extern "C" vp_status vp_eval_grad_targets(vp_plan_t P, const double *f, double *
     if (overlaps(f, 8 * (size_t)P->nbatch * P->n, grad, 16 * (size_t)P->nbatch * P->m))
         return set_err(P, VP_EINVAL, "f and grad overlap");
     return guarded(P, [&] {
+        P->timing_eval_begin();
         vp::prepare_charges(P, f, false);
         vp::run_fmm(P, false, true);
         vp::finish_grad(P, grad);
@@ -259,6 +299,32 @@ extern "C" vp_status vp_set_stream(vp_plan_t P, void *stream) {
     P->stream = static_cast<hipStream_t>(stream);
     P->opt.stream = stream;
     return VP_OK;
+}
+
+extern "C" vp_status vp_set_timing(vp_plan_t P, int32_t enable) {
+    if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
+    return guarded(P, [&] {
+        VP_HIP(P->stream ? hipStreamSynchronize(P->stream) : hipDeviceSynchronize());
+        release_timing(P);
+        P->tcount = P->tdone = 0;
+        P->tcur = -1;
+        for (double &v : P->tms) v = 0.0;
+        if (enable) {
+            P->tev.assign((size_t)vp_plan_s::TRING * VP_NSTAGES * 2, nullptr);
+            for (auto &e : P->tev) VP_HIP(hipEventCreate(&e));
+            P->tslot_used.assign(vp_plan_s::TRING, 0);
+            P->timing = true;
+        }
+    });
+}
+
+extern "C" vp_status vp_get_timing(vp_plan_t P, double *ms, int64_t *nevals) {
+    if (!P || !ms || !nevals) return set_err(P, VP_EINVAL, "plan, ms and nevals must not be NULL");
+    return guarded(P, [&] {
+        if (P->timing) P->timing_collect(P->tcount);
+        for (int st = 0; st < VP_NSTAGES; ++st) ms[st] = P->tms[st];
+        *nevals = P->tdone;
+    });
 }
 
 extern "C" vp_status vp_destroy(vp_plan_t P) {

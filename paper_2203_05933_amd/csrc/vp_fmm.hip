@@ -706,9 +706,11 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
     int64_t len = adjoint ? P->m : P->n;
     const int32_t *perm = adjoint ? P->tperm : P->sperm;
     const double *w = adjoint ? nullptr : P->sw;
+    P->stage_begin(VP_STAGE_CHARGE);
     hipLaunchKernelGGL(k_charge, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, P->stream, f, perm, w,
                        P->q, len, P->nbatch);
     VP_LAUNCH_CHECK();
+    P->stage_end(VP_STAGE_CHARGE);
 }
 
 template <class E>
@@ -724,11 +726,14 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
     const E *Rl2l = f32 ? (const E *)P->ops.l2l_f32 : (const E *)P->ops.l2l_f64;
     const size_t lds = sizeof(E) * 2 * 64 * Pn;
     if (T.nlevels < 3) return;  // no box is well separated from another
+    P->stage_begin(VP_STAGE_P2M);
     if (P->n_p2m > 0) {
         hipLaunchKernelGGL(k_p2m<E>, dim3(P->n_p2m), dim3(64), lds, s, R, G, P->p2m_leaves, P->n_p2m,
                            P->q, nb, Pn, PD, invk, M);
         VP_LAUNCH_CHECK();
     }
+    P->stage_end(VP_STAGE_P2M);
+    P->stage_begin(VP_STAGE_M2M);
     for (int l = T.nlevels - 2; l >= 2; --l) {
         int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
         if (c1 > c0) {
@@ -737,6 +742,8 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
             VP_LAUNCH_CHECK();
         }
     }
+    P->stage_end(VP_STAGE_M2M);
+    P->stage_begin(VP_STAGE_M2L);
     const int ncols = P->n_m2l_boxes * nb;
     const unsigned ntiles = (unsigned)((ncols + 15) / 16);
     if (ncols > 0) {
@@ -773,11 +780,15 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
         }
         VP_LAUNCH_CHECK();
     }
+    P->stage_end(VP_STAGE_M2L);
+    P->stage_begin(VP_STAGE_P2L);
     if (P->n_x_boxes > 0) {
         hipLaunchKernelGGL(k_p2l<E>, dim3(P->n_x_boxes), dim3(64), lds, s, R, G, P->x_boxes, T.lptr[3],
                            T.lidx[3], P->q, nb, Pn, PD, invk, L);
         VP_LAUNCH_CHECK();
     }
+    P->stage_end(VP_STAGE_P2L);
+    P->stage_begin(VP_STAGE_L2L);
     for (int l = 3; l < T.nlevels; ++l) {
         int c0 = P->lvl_box_begin[l], c1 = P->lvl_box_begin[l + 1];
         if (c1 > c0) {
@@ -786,6 +797,7 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
             VP_LAUNCH_CHECK();
         }
     }
+    P->stage_end(VP_STAGE_L2L);
 }
 
 template <int NB, bool GRAD>
@@ -798,6 +810,7 @@ static void launch_p2p(vp_plan_s *P, const PointRoles &R, int bt0, double *acc) 
 
 template <bool GRAD>
 static void run_p2p(vp_plan_s *P, const PointRoles &R, double *acc) {
+    P->stage_begin(VP_STAGE_P2P);
     int nb = P->nbatch;
     for (int bt0 = 0; bt0 < nb;) {
         int left = nb - bt0;
@@ -818,14 +831,17 @@ static void run_p2p(vp_plan_s *P, const PointRoles &R, double *acc) {
             bt0 += 1;
         }
     }
+    P->stage_end(VP_STAGE_P2P);
 }
 
 template <class E, bool GRAD>
 static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *acc) {
     Tree &T = P->tree;
+    P->stage_begin(VP_STAGE_FAR);
     hipLaunchKernelGGL((k_far<E, GRAD>), dim3(T.nleaf), dim3(64), 0, P->stream, R, G, T.leaves, T.lptr[2],
                        T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp, (const E *)P->Lexp, acc);
     VP_LAUNCH_CHECK();
+    P->stage_end(VP_STAGE_FAR);
 }
 
 void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
@@ -859,15 +875,19 @@ void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint) {
     int64_t waves = nrows;
     int64_t blocks = (waves + 3) / 4;
     if (blocks > 65536) blocks = 65536;
+    P->stage_begin(VP_STAGE_FINISH);
     hipLaunchKernelGGL(k_finish, dim3((unsigned)blocks), dim3(256), 0, P->stream, nrows, P->nbatch, inv, scale,
                        P->acc, nrows, rp, cv, vv, f, flen, u);
     VP_LAUNCH_CHECK();
+    P->stage_end(VP_STAGE_FINISH);
 }
 
 void finish_grad(vp_plan_s *P, double *grad) {
+    P->stage_begin(VP_STAGE_FINISH);
     hipLaunchKernelGGL(k_unpermute_grad, dim3((unsigned)((P->m + 255) / 256)), dim3(256), 0, P->stream, P->m,
                        P->nbatch, P->tinv, P->acc, grad);
     VP_LAUNCH_CHECK();
+    P->stage_end(VP_STAGE_FINISH);
 }
 
 }  // namespace vp

@@ -219,6 +219,20 @@ struct vp_plan_s {
     int32_t *w_leaves = nullptr;     // leaves with non-empty W list
     int n_w_leaves = 0;
     int32_t *err_flag = nullptr;     // device error flag (list traversal overflow)
+
+    // optional per-stage timing (HIP events on the plan's stream)
+    static constexpr int TRING = 32;
+    bool timing = false;
+    std::vector<hipEvent_t> tev;     // [TRING][VP_NSTAGES][2]
+    std::vector<int> tslot_used;     // stages recorded in a ring slot (bit mask)
+    int64_t tcount = 0;              // evaluations started with timing on
+    int64_t tdone = 0;               // evaluations folded into tms
+    double tms[VP_NSTAGES] = {0};
+    int tcur = -1;
+    void stage_begin(int st);
+    void stage_end(int st);
+    void timing_eval_begin();
+    void timing_collect(int64_t upto);
 };
 
 namespace vp {

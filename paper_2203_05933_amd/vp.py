@@ -32,7 +32,9 @@ _ARR_DTYPE = {0: np.int32, 1: np.int32, 2: np.int32, 3: np.int32, 4: np.int32, 5
 
 # Every entry point declared in include/vp.h.
 EXPORTS = ("vp_default_options", "vp_plan", "vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets",
-           "vp_set_stream", "vp_destroy", "vp_last_error", "vp_get_info", "vp_get_array")
+           "vp_set_stream", "vp_destroy", "vp_last_error", "vp_get_info", "vp_get_array",
+           "vp_set_timing", "vp_get_timing")
+STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish")
 
 
 class VPError(RuntimeError):
@@ -97,6 +99,10 @@ def load_library(path: str = LIB_PATH):
     lib.vp_get_info.restype = ctypes.c_int
     lib.vp_get_array.argtypes = [vp, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
     lib.vp_get_array.restype = ctypes.c_int
+    lib.vp_set_timing.argtypes = [vp, ctypes.c_int32]
+    lib.vp_set_timing.restype = ctypes.c_int
+    lib.vp_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.vp_get_timing.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -227,6 +233,17 @@ class Plan:
         out = np.empty(cnt.value, dtype=_ARR_DTYPE[which])
         self._check(self._lib.vp_get_array(self._h, which, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(cnt)))
         return out
+
+    def set_timing(self, enable: bool = True):
+        """Enable (and clear) or disable per-stage HIP-event timing."""
+        self._check(self._lib.vp_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """Summed milliseconds per stage and the number of timed evaluations."""
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = ctypes.c_int64()
+        self._check(self._lib.vp_get_timing(self._h, ms, ctypes.byref(cnt)))
+        return {"evals": cnt.value, "ms": dict(zip(STAGES, list(ms)))}
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
