@@ -223,21 +223,9 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
             vp::fill_f64((double *)P->Lexp, 0.0, (int64_t)ecount, P->stream);
         }
         VP_HIP(hipStreamSynchronize(P->stream));
-        // near-field pair count (host estimate from the U lists)
-        {
-            vp::Tree &T = P->tree;
-            std::vector<int32_t> up(T.nbox + 1), ui(T.llen[0]), sb(T.nbox), se(T.nbox), tb(T.nbox), te(T.nbox);
-            VP_HIP(hipMemcpy(up.data(), T.lptr[0], 4 * (T.nbox + 1), hipMemcpyDeviceToHost));
-            if (T.llen[0]) VP_HIP(hipMemcpy(ui.data(), T.lidx[0], 4 * T.llen[0], hipMemcpyDeviceToHost));
-            VP_HIP(hipMemcpy(sb.data(), T.sb, 4 * T.nbox, hipMemcpyDeviceToHost));
-            VP_HIP(hipMemcpy(se.data(), T.se, 4 * T.nbox, hipMemcpyDeviceToHost));
-            VP_HIP(hipMemcpy(tb.data(), T.tb, 4 * T.nbox, hipMemcpyDeviceToHost));
-            VP_HIP(hipMemcpy(te.data(), T.te, 4 * T.nbox, hipMemcpyDeviceToHost));
-            int64_t pairs = 0;
-            for (int b = 0; b < T.nbox; ++b)
-                for (int e = up[b]; e < up[b + 1]; ++e) pairs += (int64_t)(te[b] - tb[b]) * (se[ui[e]] - sb[ui[e]]);
-            P->near_pairs = pairs;
-        }
+        vp::build_near_tables(P);
+        if (o.p2p_mode == VP_P2P_TABLES && !P->near.active)
+            throw Error(VP_EUNSUPPORTED, "p2p_mode TABLES needs targets = nodes and congruent leaves");
     });
     if (st != VP_OK) {
         free_plan(P);  // the message is already in the thread-local slot

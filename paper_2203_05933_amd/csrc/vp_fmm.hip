@@ -5,10 +5,10 @@
 // Green's function of Section 2.1; correction matrix of Section 4) runs as:
 //   charge     q_b[j] = w_j f_b[perm[j]]                (sorted source order)
 //   P2M        leaf multipoles                         (VALU, LDS reduction)
-//   M2M        upward pass, level by level             (VALU)
+//   M2M        upward pass, level by level             (MFMA gather-GEMM)
 //   M2L        V lists, one launch for all levels      (MFMA, operators in FP64)
 //   P2L        X lists                                 (VALU)
-//   L2L        downward pass, level by level           (VALU)
+//   L2L        downward pass, level by level           (MFMA gather-GEMM)
 //   P2P        U lists, LDS-staged source tiles        (FP64 VALU)
 //   L2P + M2P  local expansion and W lists at targets  (VALU)
 //   finish     u = acc[inverse perm] + C f             (HBM bound)
@@ -19,6 +19,7 @@
 // FP32-bulk form.  Every reduction has a fixed order: no atomics.
 
 #include "vp_internal.hpp"
+#include "vp_translate.hpp"
 
 namespace vp {
 
@@ -118,179 +119,6 @@ __global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_
 }
 
 // ----------------------------------------------------------------------------
-// M2M: one wave per parent box of a level; lane r forms row r of
-// sum over children of R_q M_child (R_q row-major PD x PD).
-// ----------------------------------------------------------------------------
-template <class E>
-__global__ void __launch_bounds__(64) k_m2m(BoxGeo G, const int32_t *__restrict__ boxes, int nboxes,
-                                            int nbatch, int P, int PD, const E *__restrict__ Rm2m,
-                                            E *__restrict__ Mexp) {
-    const int lane = threadIdx.x;
-    const int b = boxes[blockIdx.x];
-    const int c0 = G.child[b], nc = G.nchild[b];
-    for (int bt = 0; bt < nbatch; ++bt) {
-        for (int r = lane; r < PD; r += 64) {
-            E acc = (E)0;
-            if (r < 2 * P) {
-                for (int c = c0; c < c0 + nc; ++c) {
-                    int qd = (G.ix[c] & 1) | ((G.iy[c] & 1) << 1);
-                    const E *Rr = Rm2m + ((int64_t)qd * PD + r) * PD;
-                    const E *Mc = Mexp + ((int64_t)c * nbatch + bt) * PD;
-                    for (int k = 0; k < 2 * P; ++k) acc += Rr[k] * Mc[k];
-                }
-            }
-            Mexp[((int64_t)b * nbatch + bt) * PD + r] = acc;
-        }
-    }
-}
-
-// ----------------------------------------------------------------------------
-// M2L with matrix cores.  One wave computes a 16-column tile of
-//   L[:, col] = sum_o R_o M[:, src(col, o)]   (+ A_0 log s on row 0)
-// where a column is a (box, density) pair and o runs over the 40 outer
-// offsets.  R_o are stored in A-fragment order, so each MFMA reads one
-// contiguous 512-byte (f64) fragment.  Both 16x16x4 instructions take
-// A[l%16][l/16] and B[l/16][l%16] from lane l; the 16x16 result sits in
-// element i of lane l as D[4i + l/16][l%16] for v_mfma_f64_16x16x4 and as
-// D[4(l/16) + i][l%16] for v_mfma_f32_16x16x4 (both measured on gfx950).
-// ----------------------------------------------------------------------------
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <int RB>
-__global__ void __launch_bounds__(64) k_m2l_f64(const int32_t *__restrict__ cols_box, int ncols,
-                                                int nbatch, int P, const int32_t *__restrict__ vslot,
-                                                const int32_t *__restrict__ level,
-                                                const double *__restrict__ logside,
-                                                const double *__restrict__ Afrag,
-                                                const double *__restrict__ Mexp,
-                                                double *__restrict__ Lexp) {
-    constexpr int PD = RB * 16;
-    constexpr int S = PD / 4;
-    const int lane = threadIdx.x;
-    const int cl = lane & 15, g = lane >> 4;
-    const int col = blockIdx.x * 16 + cl;
-    const bool valid = col < ncols;
-    const int box = valid ? cols_box[col / nbatch] : 0;
-    const int bt = valid ? col % nbatch : 0;
-    v4d acc[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) acc[r] = (v4d){0.0, 0.0, 0.0, 0.0};
-    for (int o = 0; o < NOFF; ++o) {
-        int src = valid ? vslot[(int64_t)box * NOFF + o] : -1;
-        if (__ballot(src >= 0) == 0ull) continue;
-        double bv[S];
-        const double *Ms = Mexp + ((int64_t)(src >= 0 ? src : 0) * nbatch + bt) * PD + g;
-#pragma unroll
-        for (int s = 0; s < S; ++s) bv[s] = (src >= 0) ? Ms[4 * s] : 0.0;
-        const double *Ao = Afrag + (int64_t)o * PD * PD + lane;
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                double a = Ao[((r * S) + s) * 64];
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[s], acc[r], 0, 0, 0);
-            }
-        }
-    }
-    // row 2P holds sum Re A_0: add A_0 log s to row 0
-    const int r2 = 2 * P;
-    const int rb2 = r2 >> 4, g2 = r2 & 3, i2 = (r2 & 15) >> 2;
-    double sumA0 = 0.0;
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-        if (r == rb2) sumA0 = acc[r][i2];
-    sumA0 = __shfl(sumA0, g2 * 16 + cl, 64);
-    if (g == 0 && valid) acc[0][0] += sumA0 * logside[level[box]];
-    if (valid) {
-        double *Lo = Lexp + ((int64_t)box * nbatch + bt) * PD;
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int row = r * 16 + 4 * i + g;
-                Lo[row] = (row < 2 * P) ? acc[r][i] : 0.0;
-            }
-    }
-}
-
-// FP32-bulk form: mode 0 = one FP32 product, 1 = T_hi M + T_lo M (split
-// operator), 2 = widen to FP64 and use the FP64 operators.
-template <int RB, int MODE>
-__global__ void __launch_bounds__(64) k_m2l_f32(const int32_t *__restrict__ cols_box, int ncols,
-                                                int nbatch, int P, const int32_t *__restrict__ vslot,
-                                                const int32_t *__restrict__ level,
-                                                const double *__restrict__ logside,
-                                                const float *__restrict__ Ahi,
-                                                const float *__restrict__ Alo,
-                                                const double *__restrict__ A64,
-                                                const float *__restrict__ Mexp,
-                                                float *__restrict__ Lexp) {
-    constexpr int PD = RB * 16;
-    constexpr int S = PD / 4;
-    const int lane = threadIdx.x;
-    const int cl = lane & 15, g = lane >> 4;
-    const int col = blockIdx.x * 16 + cl;
-    const bool valid = col < ncols;
-    const int box = valid ? cols_box[col / nbatch] : 0;
-    const int bt = valid ? col % nbatch : 0;
-    v4f acc[RB];
-    v4d acc64[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        acc[r] = (v4f){0.f, 0.f, 0.f, 0.f};
-        acc64[r] = (v4d){0.0, 0.0, 0.0, 0.0};
-    }
-    for (int o = 0; o < NOFF; ++o) {
-        int src = valid ? vslot[(int64_t)box * NOFF + o] : -1;
-        if (__ballot(src >= 0) == 0ull) continue;
-        float bv[S];
-        const float *Ms = Mexp + ((int64_t)(src >= 0 ? src : 0) * nbatch + bt) * PD + g;
-#pragma unroll
-        for (int s = 0; s < S; ++s) bv[s] = (src >= 0) ? Ms[4 * s] : 0.f;
-        const int64_t ob = (int64_t)o * PD * PD + lane;
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const int64_t ai = ob + ((r * S) + s) * 64;
-                if (MODE == 2) {
-                    acc64[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(A64[ai], (double)bv[s], acc64[r], 0, 0, 0);
-                } else {
-                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ahi[ai], bv[s], acc[r], 0, 0, 0);
-                    if (MODE == 1) acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(Alo[ai], bv[s], acc[r], 0, 0, 0);
-                }
-            }
-        }
-    }
-    const int r2 = 2 * P;
-    const int rb2 = r2 >> 4;
-    const int g2 = (MODE == 2) ? (r2 & 3) : ((r2 & 15) >> 2);
-    const int i2 = (MODE == 2) ? ((r2 & 15) >> 2) : (r2 & 3);
-    double vals[RB][4];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) vals[r][i] = (MODE == 2) ? acc64[r][i] : (double)acc[r][i];
-    double sumA0 = 0.0;
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-        if (r == rb2) sumA0 = vals[r][i2];
-    sumA0 = __shfl(sumA0, g2 * 16 + cl, 64);
-    if (g == 0 && valid) vals[0][0] += sumA0 * logside[level[box]];
-    if (valid) {
-        float *Lo = Lexp + ((int64_t)box * nbatch + bt) * PD;
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int row = (MODE == 2) ? (r * 16 + 4 * i + g) : (r * 16 + 4 * g + i);
-                Lo[row] = (row < 2 * P) ? (float)vals[r][i] : 0.f;
-            }
-    }
-}
-
-// ----------------------------------------------------------------------------
 // P2L (X lists): sources of a coarser leaf straight into the local expansion
 // of box b: B_0 += sum q log|c - z|, B_l += -(1/l) sum q (s/(z - c))^l.
 // ----------------------------------------------------------------------------
@@ -352,28 +180,6 @@ __global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_
 }
 
 // ----------------------------------------------------------------------------
-// L2L: one wave per child box of a level; lane r adds row r of R_q L_parent.
-// ----------------------------------------------------------------------------
-template <class E>
-__global__ void __launch_bounds__(64) k_l2l(BoxGeo G, const int32_t *__restrict__ boxes, int nboxes,
-                                            int nbatch, int P, int PD, const E *__restrict__ Rl2l,
-                                            E *__restrict__ Lexp) {
-    const int lane = threadIdx.x;
-    const int b = boxes[blockIdx.x];
-    const int par = G.parent[b];
-    const int qd = (G.ix[b] & 1) | ((G.iy[b] & 1) << 1);
-    for (int r = lane; r < 2 * P; r += 64) {
-        const E *Rr = Rl2l + ((int64_t)qd * PD + r) * PD;
-        for (int bt = 0; bt < nbatch; ++bt) {
-            const E *Lp = Lexp + ((int64_t)par * nbatch + bt) * PD;
-            E acc = (E)0;
-            for (int k = 0; k < 2 * P; ++k) acc += Rr[k] * Lp[k];
-            Lexp[((int64_t)b * nbatch + bt) * PD + r] += acc;
-        }
-    }
-}
-
-// ----------------------------------------------------------------------------
 // L2P + M2P at the targets of one leaf (one wave, lane = target):
 //   u += -(1/2pi) Re[ sum_l B_l w^l + sum_{a in W} (A_0 log(z - c_a) +
 //                    sum_k A_k (s_a/(z - c_a))^k) ]
@@ -384,7 +190,9 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
                                             const int32_t *__restrict__ wptr,
                                             const int32_t *__restrict__ widx, int nbatch, int P,
                                             int PD, const E *__restrict__ Mexp,
-                                            const E *__restrict__ Lexp, double *__restrict__ acc) {
+                                            const E *__restrict__ Lexp,
+                                            const int32_t *__restrict__ local_done,
+                                            double *__restrict__ acc) {
     const int lane = threadIdx.x;
     const int b = leaves[blockIdx.x];
     const int t0 = R.tb[b], t1 = R.te[b];
@@ -392,7 +200,7 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
     const double cx = G.cx[b], cy = G.cy[b];
     const int lb = G.level[b];
     const double s = G.side[lb];
-    const bool has_local = lb >= 2;
+    const bool has_local = lb >= 2 && !(local_done && local_done[b]);
     for (int base = t0; base < t1; base += 64) {
         const int t = base + lane;
         const bool act = t < t1;
@@ -471,7 +279,7 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
 // ----------------------------------------------------------------------------
 constexpr int P2P_TILE = 256;
 
-template <int NB, bool GRAD>
+template <int NB, bool GRAD, bool ACCUM>
 __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restrict__ leaves,
                                             const int32_t *__restrict__ uptr,
                                             const int32_t *__restrict__ uidx,
@@ -572,6 +380,8 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
                 if (GRAD) {
                     acc[((int64_t)(bt0 + k) * 2 + 0) * R.ntgt + t] = INV_2PI * gxa[k];
                     acc[((int64_t)(bt0 + k) * 2 + 1) * R.ntgt + t] = INV_2PI * gya[k];
+                } else if (ACCUM) {
+                    acc[(int64_t)(bt0 + k) * R.ntgt + t] += -INV_4PI * a[k];
                 } else {
                     acc[(int64_t)(bt0 + k) * R.ntgt + t] = -INV_4PI * a[k];
                 }
@@ -633,11 +443,14 @@ void build_schedules(vp_plan_s *P) {
     Tree &T = P->tree;
     hipStream_t s = P->stream;
     const int nbox = T.nbox;
-    std::vector<int32_t> lev(nbox), ix(nbox), iy(nbox), nch(nbox), xp(nbox + 1), wp(nbox + 1);
+    std::vector<int32_t> lev(nbox), ix(nbox), iy(nbox), nch(nbox), chb(nbox), par(nbox), xp(nbox + 1),
+        wp(nbox + 1);
     VP_HIP(hipMemcpyAsync(lev.data(), T.level, 4 * nbox, hipMemcpyDeviceToHost, s));
     VP_HIP(hipMemcpyAsync(ix.data(), T.ix, 4 * nbox, hipMemcpyDeviceToHost, s));
     VP_HIP(hipMemcpyAsync(iy.data(), T.iy, 4 * nbox, hipMemcpyDeviceToHost, s));
     VP_HIP(hipMemcpyAsync(nch.data(), T.nchild, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(chb.data(), T.child, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(par.data(), T.parent, 4 * nbox, hipMemcpyDeviceToHost, s));
     VP_HIP(hipMemcpyAsync(xp.data(), T.lptr[3], 4 * (nbox + 1), hipMemcpyDeviceToHost, s));
     VP_HIP(hipMemcpyAsync(wp.data(), T.lptr[2], 4 * (nbox + 1), hipMemcpyDeviceToHost, s));
     VP_HIP(hipStreamSynchronize(s));
@@ -646,28 +459,40 @@ void build_schedules(vp_plan_s *P) {
         if (!h.empty()) VP_HIP(hipMemcpyAsync(d, h.data(), 4 * h.size(), hipMemcpyHostToDevice, s));
         return d;
     };
-    // M2L columns and L2L boxes: levels >= 2 grouped by child class, level order kept
+    auto cls = [&](int b) { return (ix[b] & 1) | ((iy[b] & 1) << 1); };
+    // M2L columns: boxes of levels >= 2 grouped by child class (boxes of one
+    // class share their 27 V-list offsets in a uniform region)
     std::vector<int32_t> m2l;
     for (int c = 0; c < 4; ++c)
         for (int b = 0; b < nbox; ++b)
-            if (lev[b] >= 2 && ((ix[b] & 1) | ((iy[b] & 1) << 1)) == c) m2l.push_back(b);
+            if (lev[b] >= 2 && cls(b) == c) m2l.push_back(b);
     P->n_m2l_boxes = (int)m2l.size();
     P->m2l_cols = up(m2l);
-    std::vector<int32_t> lb, par;
+    // per level: boxes grouped by class (L2L), non-leaf boxes (M2M)
+    std::vector<int32_t> lb, parents;
     P->lvl_box_begin.assign(T.nlevels + 1, 0);
     P->m2m_begin.assign(T.nlevels + 1, 0);
     for (int l = 0; l < T.nlevels; ++l) {
         P->lvl_box_begin[l] = (int)lb.size();
-        P->m2m_begin[l] = (int)par.size();
-        for (int b = T.level_begin[l]; b < T.level_begin[l + 1]; ++b) {
-            lb.push_back(b);
-            if (nch[b] > 0) par.push_back(b);
-        }
+        P->m2m_begin[l] = (int)parents.size();
+        for (int c = 0; c < 4; ++c)
+            for (int b = T.level_begin[l]; b < T.level_begin[l + 1]; ++b)
+                if (cls(b) == c) lb.push_back(b);
+        for (int b = T.level_begin[l]; b < T.level_begin[l + 1]; ++b)
+            if (nch[b] > 0) parents.push_back(b);
     }
     P->lvl_box_begin[T.nlevels] = (int)lb.size();
-    P->m2m_begin[T.nlevels] = (int)par.size();
+    P->m2m_begin[T.nlevels] = (int)parents.size();
     P->lvl_boxes = up(lb);
-    P->m2m_parents = up(par);
+    P->m2m_parents = up(parents);
+    // slot tables: child in each quadrant (M2M); parent in the class slot (L2L)
+    std::vector<int32_t> cs((size_t)nbox * 4, -1), ls((size_t)nbox * 4, -1);
+    for (int b = 0; b < nbox; ++b) {
+        for (int c = chb[b]; nch[b] > 0 && c < chb[b] + nch[b]; ++c) cs[(size_t)b * 4 + cls(c)] = c;
+        if (par[b] >= 0) ls[(size_t)b * 4 + cls(b)] = par[b];
+    }
+    P->child_slot = up(cs);
+    P->l2l_slot = up(ls);
     std::vector<int32_t> p2m, xb, wl;
     for (int b = 0; b < nbox; ++b) {
         if (nch[b] == 0 && lev[b] >= 2) p2m.push_back(b);
@@ -681,6 +506,55 @@ void build_schedules(vp_plan_s *P) {
     P->n_w_leaves = (int)wl.size();
     P->w_leaves = up(wl);
     VP_HIP(hipStreamSynchronize(s));
+}
+
+// ----------------------------------------------------------------------------
+// Gather-GEMM launches (square PD x PD operators of the expansion stages)
+// ----------------------------------------------------------------------------
+template <class TI, class TO, class TM, bool SPLIT, bool ACCUM, int RB>
+static void launch_sq(hipStream_t s, const TranslateArgs &a, const TM *Ahi, const TM *Alo, const TI *in,
+                      TO *out) {
+    constexpr int S = RB * 4;
+    constexpr size_t lds = (size_t)RB * S * 64 * sizeof(TM) * (SPLIT ? 2 : 1);
+    constexpr bool LDSA = lds <= 65536;
+    const unsigned blocks = (unsigned)((a.ncols + 63) / 64);
+    hipLaunchKernelGGL((k_translate<TI, TO, TM, RB, S, SPLIT, ACCUM, LDSA>), dim3(blocks), dim3(256),
+                       LDSA ? lds : 0, s, a, Ahi, Alo, in, out);
+    VP_LAUNCH_CHECK();
+}
+
+template <class TI, class TO, class TM, bool SPLIT, bool ACCUM>
+static void translate_sq(hipStream_t s, int PD, const TranslateArgs &a, const TM *Ahi, const TM *Alo,
+                         const TI *in, TO *out) {
+    if (a.ncols <= 0) return;
+    switch (PD) {
+        case 16: launch_sq<TI, TO, TM, SPLIT, ACCUM, 1>(s, a, Ahi, Alo, in, out); break;
+        case 32: launch_sq<TI, TO, TM, SPLIT, ACCUM, 2>(s, a, Ahi, Alo, in, out); break;
+        case 48: launch_sq<TI, TO, TM, SPLIT, ACCUM, 3>(s, a, Ahi, Alo, in, out); break;
+        case 64: launch_sq<TI, TO, TM, SPLIT, ACCUM, 4>(s, a, Ahi, Alo, in, out); break;
+        case 80: launch_sq<TI, TO, TM, SPLIT, ACCUM, 5>(s, a, Ahi, Alo, in, out); break;
+        case 96: launch_sq<TI, TO, TM, SPLIT, ACCUM, 6>(s, a, Ahi, Alo, in, out); break;
+        case 112: launch_sq<TI, TO, TM, SPLIT, ACCUM, 7>(s, a, Ahi, Alo, in, out); break;
+        case 128: launch_sq<TI, TO, TM, SPLIT, ACCUM, 8>(s, a, Ahi, Alo, in, out); break;
+        default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
+    }
+}
+
+static TranslateArgs expansion_args(vp_plan_s *P, const int32_t *cols, int nboxes, const int32_t *slots, int nops,
+                                    int logrow) {
+    TranslateArgs a;
+    a.cols_box = cols;
+    a.ncols = nboxes * P->nbatch;
+    a.nbatch = P->nbatch;
+    a.slots = slots;
+    a.nops = nops;
+    a.in = ColAddr{P->PD, (int64_t)P->nbatch * P->PD, nullptr};
+    a.out = a.in;
+    a.nrows_out = P->PD;
+    a.logrow = logrow;
+    a.level = P->tree.level;
+    a.logside = P->tree.d_logside;
+    return a;
 }
 
 // ----------------------------------------------------------------------------
@@ -714,7 +588,10 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
 }
 
 template <class E>
-static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
+static void run_pattern_op(vp_plan_s *P, const PointRoles &R, bool p2m);
+
+template <class E>
+static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool tables) {
     Tree &T = P->tree;
     hipStream_t s = P->stream;
     const int nb = P->nbatch, Pn = P->P, PD = P->PD;
@@ -724,10 +601,18 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
     const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
     const E *Rm2m = f32 ? (const E *)P->ops.m2m_f32 : (const E *)P->ops.m2m_f64;
     const E *Rl2l = f32 ? (const E *)P->ops.l2l_f32 : (const E *)P->ops.l2l_f64;
+    (void)G;
     const size_t lds = sizeof(E) * 2 * 64 * Pn;
     if (T.nlevels < 3) return;  // no box is well separated from another
     P->stage_begin(VP_STAGE_P2M);
-    if (P->n_p2m > 0) {
+    if (tables) {
+        run_pattern_op<E>(P, R, true);
+        if (P->near.n_p2m_rest > 0) {
+            hipLaunchKernelGGL(k_p2m<E>, dim3(P->near.n_p2m_rest), dim3(64), lds, s, R, G, P->near.p2m_rest,
+                               P->near.n_p2m_rest, P->q, nb, Pn, PD, invk, M);
+            VP_LAUNCH_CHECK();
+        }
+    } else if (P->n_p2m > 0) {
         hipLaunchKernelGGL(k_p2m<E>, dim3(P->n_p2m), dim3(64), lds, s, R, G, P->p2m_leaves, P->n_p2m,
                            P->q, nb, Pn, PD, invk, M);
         VP_LAUNCH_CHECK();
@@ -736,49 +621,26 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
     P->stage_begin(VP_STAGE_M2M);
     for (int l = T.nlevels - 2; l >= 2; --l) {
         int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
-        if (c1 > c0) {
-            hipLaunchKernelGGL(k_m2m<E>, dim3(c1 - c0), dim3(64), 0, s, G, P->m2m_parents + c0, c1 - c0, nb,
-                               Pn, PD, Rm2m, M);
-            VP_LAUNCH_CHECK();
-        }
+        TranslateArgs a = expansion_args(P, P->m2m_parents + c0, c1 - c0, P->child_slot, 4, -1);
+        translate_sq<E, E, E, false, false>(s, PD, a, Rm2m, (const E *)nullptr, M, M);
     }
     P->stage_end(VP_STAGE_M2M);
     P->stage_begin(VP_STAGE_M2L);
-    const int ncols = P->n_m2l_boxes * nb;
-    const unsigned ntiles = (unsigned)((ncols + 15) / 16);
-    if (ncols > 0) {
+    {
+        TranslateArgs a = expansion_args(P, P->m2l_cols, P->n_m2l_boxes, T.v_slot, NOFF, 2 * Pn);
         if (!f32) {
-            switch (PD) {
-#define VP_M2L64(RBV)                                                                                   \
-    case RBV * 16:                                                                                      \
-        hipLaunchKernelGGL(k_m2l_f64<RBV>, dim3(ntiles), dim3(64), 0, s, P->m2l_cols, ncols, nb, Pn,     \
-                           T.v_slot, T.level, T.d_logside, P->ops.m2l_f64, (const double *)M, (double *)L); \
-        break;
-                VP_M2L64(1) VP_M2L64(2) VP_M2L64(3) VP_M2L64(4) VP_M2L64(5) VP_M2L64(6) VP_M2L64(7)
-                VP_M2L64(8)
-#undef VP_M2L64
-                default:
-                    throw Error(VP_EUNSUPPORTED, "order too large for the M2L kernel");
-            }
+            translate_sq<double, double, double, false, false>(s, PD, a, P->ops.m2l_f64, nullptr,
+                                                               (const double *)M, (double *)L);
+        } else if (P->m2l_mode == VP_M2L_FP32_SPLIT) {
+            translate_sq<float, float, float, true, false>(s, PD, a, P->ops.m2l_f32, P->ops.m2l_f32_lo,
+                                                           (const float *)M, (float *)L);
+        } else if (P->m2l_mode == VP_M2L_FP64_MFMA) {
+            translate_sq<float, float, double, false, false>(s, PD, a, P->ops.m2l_f64, nullptr,
+                                                             (const float *)M, (float *)L);
         } else {
-            int mode = P->m2l_mode == VP_M2L_FP32_SPLIT ? 1 : (P->m2l_mode == VP_M2L_FP64_MFMA ? 2 : 0);
-            switch (PD * 4 + mode) {
-#define VP_M2L32(RBV, MD)                                                                              \
-    case RBV * 64 + MD:                                                                                \
-        hipLaunchKernelGGL((k_m2l_f32<RBV, MD>), dim3(ntiles), dim3(64), 0, s, P->m2l_cols, ncols, nb,  \
-                           Pn, T.v_slot, T.level, T.d_logside, P->ops.m2l_f32, P->ops.m2l_f32_lo,       \
-                           P->ops.m2l_f64, (const float *)M, (float *)L);                              \
-        break;
-                VP_M2L32(1, 0) VP_M2L32(1, 1) VP_M2L32(1, 2) VP_M2L32(2, 0) VP_M2L32(2, 1) VP_M2L32(2, 2)
-                VP_M2L32(3, 0) VP_M2L32(3, 1) VP_M2L32(3, 2) VP_M2L32(4, 0) VP_M2L32(4, 1) VP_M2L32(4, 2)
-                VP_M2L32(5, 0) VP_M2L32(5, 1) VP_M2L32(5, 2) VP_M2L32(6, 0) VP_M2L32(6, 1) VP_M2L32(6, 2)
-                VP_M2L32(7, 0) VP_M2L32(7, 1) VP_M2L32(7, 2) VP_M2L32(8, 0) VP_M2L32(8, 1) VP_M2L32(8, 2)
-#undef VP_M2L32
-                default:
-                    throw Error(VP_EUNSUPPORTED, "order too large for the M2L kernel");
-            }
+            translate_sq<float, float, float, false, false>(s, PD, a, P->ops.m2l_f32, nullptr,
+                                                            (const float *)M, (float *)L);
         }
-        VP_LAUNCH_CHECK();
     }
     P->stage_end(VP_STAGE_M2L);
     P->stage_begin(VP_STAGE_P2L);
@@ -791,75 +653,196 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
     P->stage_begin(VP_STAGE_L2L);
     for (int l = 3; l < T.nlevels; ++l) {
         int c0 = P->lvl_box_begin[l], c1 = P->lvl_box_begin[l + 1];
-        if (c1 > c0) {
-            hipLaunchKernelGGL(k_l2l<E>, dim3(c1 - c0), dim3(64), 0, s, G, P->lvl_boxes + c0, c1 - c0, nb, Pn,
-                               PD, Rl2l, L);
-            VP_LAUNCH_CHECK();
-        }
+        TranslateArgs a = expansion_args(P, P->lvl_boxes + c0, c1 - c0, P->l2l_slot, 4, -1);
+        translate_sq<E, E, E, false, true>(s, PD, a, Rl2l, (const E *)nullptr, L, L);
     }
     P->stage_end(VP_STAGE_L2L);
 }
 
-template <int NB, bool GRAD>
-static void launch_p2p(vp_plan_s *P, const PointRoles &R, int bt0, double *acc) {
-    Tree &T = P->tree;
-    hipLaunchKernelGGL((k_p2p<NB, GRAD>), dim3(T.nleaf), dim3(64), 0, P->stream, R, T.leaves, T.lptr[0],
-                       T.lidx[0], P->q, P->nbatch, bt0, acc);
+template <int NB, bool GRAD, bool ACCUM>
+static void launch_p2p(vp_plan_s *P, const PointRoles &R, const int32_t *leaves, int nleaves, const int32_t *uptr,
+                       const int32_t *uidx, int bt0, double *acc) {
+    if (nleaves <= 0) return;
+    hipLaunchKernelGGL((k_p2p<NB, GRAD, ACCUM>), dim3(nleaves), dim3(64), 0, P->stream, R, leaves, uptr, uidx, P->q,
+                       P->nbatch, bt0, acc);
     VP_LAUNCH_CHECK();
 }
 
-template <bool GRAD>
-static void run_p2p(vp_plan_s *P, const PointRoles &R, double *acc) {
-    P->stage_begin(VP_STAGE_P2P);
+// Pairwise near field over (leaves, U lists); densities in groups of 16/8/4/2/1.
+template <bool GRAD, bool ACCUM>
+static void run_p2p(vp_plan_s *P, const PointRoles &R, const int32_t *leaves, int nleaves, const int32_t *uptr,
+                    const int32_t *uidx, double *acc) {
     int nb = P->nbatch;
     for (int bt0 = 0; bt0 < nb;) {
         int left = nb - bt0;
         if (left >= 16) {
-            launch_p2p<16, GRAD>(P, R, bt0, acc);
+            launch_p2p<16, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
             bt0 += 16;
         } else if (left >= 8) {
-            launch_p2p<8, GRAD>(P, R, bt0, acc);
+            launch_p2p<8, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
             bt0 += 8;
         } else if (left >= 4) {
-            launch_p2p<4, GRAD>(P, R, bt0, acc);
+            launch_p2p<4, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
             bt0 += 4;
         } else if (left >= 2) {
-            launch_p2p<2, GRAD>(P, R, bt0, acc);
+            launch_p2p<2, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
             bt0 += 2;
         } else {
-            launch_p2p<1, GRAD>(P, R, bt0, acc);
+            launch_p2p<1, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
             bt0 += 1;
         }
     }
-    P->stage_end(VP_STAGE_P2P);
+}
+
+// Near-field tables of congruent leaves: acc[:, leaf] += sum_o K_{l,o} q[:, nbr_o(leaf)]
+template <int RB>
+static void launch_tables(vp_plan_s *P, const PointRoles &R) {
+    NearTables &N = P->near;
+    constexpr int S = RB * 4;
+    constexpr size_t lds = (size_t)RB * S * 64 * sizeof(double);
+    const size_t opsz = (size_t)N.npat * N.npat;
+    for (size_t li = 0; li < N.tab_levels.size(); ++li) {
+        TranslateArgs a;
+        a.cols_box = N.tab_cols + N.tab_cols_begin[li];
+        a.ncols = (N.tab_cols_begin[li + 1] - N.tab_cols_begin[li]) * P->nbatch;
+        a.nbatch = P->nbatch;
+        a.slots = N.tab_slot;
+        a.nops = 9;
+        a.in = ColAddr{R.nsrc, 0, R.sb};
+        a.out = ColAddr{R.ntgt, 0, R.tb};
+        a.nrows_out = N.npat;
+        a.logrow = -1;
+        a.level = P->tree.level;
+        a.logside = P->tree.d_logside;
+        if (a.ncols <= 0) continue;
+        hipLaunchKernelGGL((k_translate<double, double, double, RB, S, false, true, true>),
+                           dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a,
+                           N.K + li * 9 * opsz, (const double *)nullptr, P->q, P->acc);
+        VP_LAUNCH_CHECK();
+    }
+}
+
+static void run_tables(vp_plan_s *P, const PointRoles &R) {
+    switch (P->near.npat) {
+        case 16: launch_tables<1>(P, R); break;
+        case 32: launch_tables<2>(P, R); break;
+        case 48: launch_tables<3>(P, R); break;
+        case 64: launch_tables<4>(P, R); break;
+        case 80: launch_tables<5>(P, R); break;
+        case 96: launch_tables<6>(P, R); break;
+        case 112: launch_tables<7>(P, R); break;
+        case 128: launch_tables<8>(P, R); break;
+        default: throw Error(VP_EINTERNAL, "unsupported pattern size");
+    }
+}
+
+// One-operator launches on pattern leaves: P2M (q -> M) and L2P (L -> acc)
+template <class E, int RBP, int RBE>
+static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, bool p2m) {
+    NearTables &N = P->near;
+    const bool f32 = sizeof(E) == 4;
+    TranslateArgs a;
+    a.nbatch = P->nbatch;
+    a.slots = N.ident_slot;
+    a.nops = 1;
+    a.logrow = -1;
+    a.level = P->tree.level;
+    a.logside = P->tree.d_logside;
+    if (p2m) {
+        // rows = expansion (RBE blocks), cols = pattern points (RBP*16)
+        constexpr int RB = RBE, S = RBP * 4;
+        constexpr size_t lds = (size_t)RB * S * 64 * sizeof(E);
+        a.cols_box = N.p2m_pat;
+        a.ncols = N.n_p2m_pat * P->nbatch;
+        a.in = ColAddr{R.nsrc, 0, R.sb};
+        a.out = ColAddr{P->PD, (int64_t)P->nbatch * P->PD, nullptr};
+        a.nrows_out = P->PD;
+        if (a.ncols <= 0) return;
+        const E *op = f32 ? (const E *)N.p2m_op_f32 : (const E *)N.p2m_op;
+        hipLaunchKernelGGL((k_translate<double, E, E, RB, S, false, false, true>),
+                           dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
+                           P->q, static_cast<E *>(P->Mexp));
+    } else {
+        constexpr int RB = RBP, S = RBE * 4;
+        constexpr size_t lds = (size_t)RB * S * 64 * sizeof(E);
+        a.cols_box = N.l2p_pat;
+        a.ncols = N.n_l2p_pat * P->nbatch;
+        a.in = ColAddr{P->PD, (int64_t)P->nbatch * P->PD, nullptr};
+        a.out = ColAddr{R.ntgt, 0, R.tb};
+        a.nrows_out = N.npat;
+        if (a.ncols <= 0) return;
+        const E *op = f32 ? (const E *)N.l2p_op_f32 : (const E *)N.l2p_op;
+        hipLaunchKernelGGL((k_translate<E, double, E, RB, S, false, true, true>),
+                           dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
+                           static_cast<const E *>(P->Lexp), P->acc);
+    }
+    VP_LAUNCH_CHECK();
+}
+
+template <class E>
+static void run_pattern_op(vp_plan_s *P, const PointRoles &R, bool p2m) {
+    const int key = P->near.npat / 16 * 16 + P->PD / 16;
+    switch (key) {
+        case 4 * 16 + 4: launch_pattern_ops<E, 4, 4>(P, R, p2m); break;   // 64 points, p <= 31
+        case 4 * 16 + 2: launch_pattern_ops<E, 4, 2>(P, R, p2m); break;   // 64 points, p <= 15
+        case 4 * 16 + 3: launch_pattern_ops<E, 4, 3>(P, R, p2m); break;
+        case 4 * 16 + 1: launch_pattern_ops<E, 4, 1>(P, R, p2m); break;
+        case 1 * 16 + 4: launch_pattern_ops<E, 1, 4>(P, R, p2m); break;   // 16 points
+        case 1 * 16 + 2: launch_pattern_ops<E, 1, 2>(P, R, p2m); break;
+        case 2 * 16 + 4: launch_pattern_ops<E, 2, 4>(P, R, p2m); break;   // 32 points
+        case 2 * 16 + 2: launch_pattern_ops<E, 2, 2>(P, R, p2m); break;
+        default: throw Error(VP_EUNSUPPORTED, "pattern/order combination without a pattern operator");
+    }
 }
 
 template <class E, bool GRAD>
-static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *acc) {
+static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *acc, bool tables) {
     Tree &T = P->tree;
+    NearTables &N = P->near;
     P->stage_begin(VP_STAGE_FAR);
-    hipLaunchKernelGGL((k_far<E, GRAD>), dim3(T.nleaf), dim3(64), 0, P->stream, R, G, T.leaves, T.lptr[2],
-                       T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp, (const E *)P->Lexp, acc);
-    VP_LAUNCH_CHECK();
+    if (tables) {
+        run_pattern_op<E>(P, R, false);
+        if (N.n_far_leaves > 0) {
+            hipLaunchKernelGGL((k_far<E, GRAD>), dim3(N.n_far_leaves), dim3(64), 0, P->stream, R, G, N.far_leaves,
+                               T.lptr[2], T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp,
+                               (const E *)P->Lexp, N.local_done, acc);
+            VP_LAUNCH_CHECK();
+        }
+    } else {
+        hipLaunchKernelGGL((k_far<E, GRAD>), dim3(T.nleaf), dim3(64), 0, P->stream, R, G, T.leaves, T.lptr[2],
+                           T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp, (const E *)P->Lexp,
+                           (const int32_t *)nullptr, acc);
+        VP_LAUNCH_CHECK();
+    }
     P->stage_end(VP_STAGE_FAR);
 }
 
 void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
     PointRoles R = roles(P, adjoint);
     BoxGeo G = geo(P);
-    if (P->fp32) run_expansions<float>(P, R, G);
-    else run_expansions<double>(P, R, G);
+    Tree &T = P->tree;
+    NearTables &N = P->near;
+    const bool tables = N.active && !grad;
+    if (P->fp32) run_expansions<float>(P, R, G, tables);
+    else run_expansions<double>(P, R, G, tables);
+    P->stage_begin(VP_STAGE_P2P);
     if (grad) {
-        run_p2p<true>(P, R, P->acc);
-        if (P->tree.nlevels >= 3) {
-            if (P->fp32) run_far<float, true>(P, R, G, P->acc);
-            else run_far<double, true>(P, R, G, P->acc);
-        }
+        run_p2p<true, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0], P->acc);
+    } else if (tables) {
+        fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
+        run_tables(P, R);
+        run_p2p<false, true>(P, R, N.rest_leaves, N.n_rest_leaves, N.pair_uptr, N.pair_uidx, P->acc);
     } else {
-        run_p2p<false>(P, R, P->acc);
-        if (P->tree.nlevels >= 3) {
-            if (P->fp32) run_far<float, false>(P, R, G, P->acc);
-            else run_far<double, false>(P, R, G, P->acc);
+        run_p2p<false, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0], P->acc);
+    }
+    P->stage_end(VP_STAGE_P2P);
+    if (T.nlevels >= 3) {
+        if (grad) {
+            if (P->fp32) run_far<float, true>(P, R, G, P->acc, false);
+            else run_far<double, true>(P, R, G, P->acc, false);
+        } else {
+            if (P->fp32) run_far<float, false>(P, R, G, P->acc, tables);
+            else run_far<double, false>(P, R, G, P->acc, tables);
         }
     }
 }

@@ -138,27 +138,39 @@ struct Operators {
     double *m2l_f64 = nullptr;  // NOFF ops
     float *m2l_f32 = nullptr;
     float *m2l_f32_lo = nullptr;
-    // row-major [op][PD][PD] for the VALU kernels
-    double *m2m_f64 = nullptr, *l2l_f64 = nullptr;  // 4 ops each
+    // shift operators, same order, 4 ops each (child quadrant / child class)
+    double *m2m_f64 = nullptr, *l2l_f64 = nullptr;
     float *m2m_f32 = nullptr, *l2l_f32 = nullptr;
     double *inv_k = nullptr;  // 1/k, k = 0..P-1 (0 for k = 0)
     float *inv_k_f32 = nullptr;
 };
 
-// Near-field tables for congruent leaves (uniform box grids).
+// Congruent-leaf path (uniform box grids): near-field tables, P2M/L2P
+// operators of the node pattern, and the leftover pairwise lists.
 struct NearTables {
     bool active = false;
-    int npat = 0;               // points per pattern leaf
-    int nleaf_tab = 0;          // number of table-served target leaves
-    int32_t *tab_leaves = nullptr;   // target leaves served by tables
-    int32_t *tab_nbr = nullptr;      // [nleaf_tab][9] neighbour leaf (or -1) per offset
-    int32_t *pair_leaves = nullptr;  // leaves served by the pairwise kernel
-    int npair_leaves = 0;
-    int32_t *pair_uptr = nullptr;    // U list of pairwise leaves minus table-served entries
+    int npat = 0;                     // points per pattern leaf
+    int nleaf_tab = 0;                // target leaves with at least one table slot
+    std::vector<int> tab_levels;      // levels holding table columns
+    std::vector<int> tab_cols_begin;  // per entry of tab_levels, offsets into tab_cols
+    int32_t *tab_cols = nullptr;      // table target leaves, grouped by level
+    int32_t *tab_slot = nullptr;      // [nbox][9] neighbour leaf per offset or -1
+    double *K = nullptr;              // [tab level][9] near matrices, A-fragment order
+    int32_t *pair_uptr = nullptr;     // U lists minus the table-served entries
     int32_t *pair_uidx = nullptr;
-    double *K = nullptr;        // per level group: [9][npat][npat] in MFMA A-fragment order
-    int nlev_tab = 0;
-    std::vector<int> tab_level_of;  // level per K block
+    int64_t rest_len = 0;
+    int32_t *rest_leaves = nullptr;   // leaves with a non-empty leftover list
+    int n_rest_leaves = 0;
+    int32_t *ident_slot = nullptr;    // [nbox] slot table b -> b (one-operator launches)
+    int32_t *p2m_pat = nullptr, *p2m_rest = nullptr;  // leaves (level >= 2) by kind
+    int n_p2m_pat = 0, n_p2m_rest = 0;
+    int32_t *l2p_pat = nullptr;       // pattern target leaves (level >= 2)
+    int n_l2p_pat = 0;
+    int32_t *far_leaves = nullptr;    // leaves needing the series far-field kernel
+    int n_far_leaves = 0;
+    int32_t *local_done = nullptr;    // [nbox] 1: local expansion evaluated by the L2P operator
+    double *p2m_op = nullptr, *l2p_op = nullptr;      // float64 forms
+    float *p2m_op_f32 = nullptr, *l2p_op_f32 = nullptr;  // FP32-bulk forms
 };
 
 }  // namespace vp
@@ -206,9 +218,11 @@ struct vp_plan_s {
     double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order
     void *Mexp = nullptr;    // [nbox][nbatch][PD] (double or float)
     void *Lexp = nullptr;
-    int32_t *m2l_cols = nullptr;  // boxes with a V list, grouped by child class
+    int32_t *m2l_cols = nullptr;  // boxes of levels >= 2, grouped by child class
+    int32_t *child_slot = nullptr;   // [nbox][4] child in each quadrant or -1
+    int32_t *l2l_slot = nullptr;     // [nbox][4] parent in the slot of the box's class
     int n_m2l_boxes = 0;
-    int32_t *lvl_boxes = nullptr;  // boxes of each level >= 1 grouped by class (L2L)
+    int32_t *lvl_boxes = nullptr;  // boxes of each level, grouped by class inside a level (L2L)
     std::vector<int> lvl_box_begin;  // per level offsets into lvl_boxes
     int32_t *m2m_parents = nullptr;  // non-leaf boxes per level
     std::vector<int> m2m_begin;
@@ -234,6 +248,8 @@ struct vp_plan_s {
     void timing_eval_begin();
     void timing_collect(int64_t upto);
 };
+
+void vp_to_frag(const double *R, int rows, int cols, int ld, double *F);
 
 namespace vp {
 // vp_tree.hip

@@ -1,0 +1,282 @@
+// Plan-time set-up of the congruent-leaf path.
+//
+// The paper's box cells all carry one reference rule mapped by
+// R^k(zeta) = o_k + h zeta (Section 4.2, eq. Rk_box), and it builds its box
+// corrections once as a lookup table because G(r, r0) = G(r - r0) is
+// translation invariant (Section 4.2, eq. Vkhat_box).  The same invariance
+// makes the smooth-rule near field between two leaves that are congruent
+// copies of one node pattern a FIXED matrix per (level, neighbour offset):
+//     u_i += sum_j K_o[i][j] q_j,  K_o[i][j] = -(1/(4 pi)) log(h^2 |xi_j + o - xi_i|^2)
+// (zero for a zero-distance pair), where xi are pattern coordinates in box
+// units.  Likewise the scaled P2M and L2P of such a leaf are fixed matrices
+// (powers of the pattern).  All three run on matrix cores through the
+// gather-GEMM kernel.  Leaves that are not copies of the pattern, and pairs
+// across levels, keep the pairwise / series kernels.
+//
+// A leaf matches the reference pattern when it holds exactly npat points
+// whose box-relative coordinates (x - c)/h agree with the pattern's to
+// PATTERN_TOL; the matrices use the pattern coordinates, so the deviation
+// (a few ulps of the node coordinates) changes a logarithm by about
+// PATTERN_TOL / (nearest-pair distance in box units).
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <vector>
+
+#include "vp_internal.hpp"
+
+namespace vp {
+
+constexpr double PATTERN_TOL = 5e-13;
+
+__global__ void k_match_pattern(const int32_t *__restrict__ leaves, int nleaf, const int32_t *__restrict__ b0,
+                                const int32_t *__restrict__ b1, const double *__restrict__ px,
+                                const double *__restrict__ py, const double *__restrict__ cx,
+                                const double *__restrict__ cy, const int32_t *__restrict__ level,
+                                const double *__restrict__ side, const double *__restrict__ rx,
+                                const double *__restrict__ ry, int npat, int32_t *__restrict__ flag) {
+    const int lane = threadIdx.x;
+    const int k = blockIdx.x;
+    const int b = leaves[k];
+    const int s0 = b0[b], cnt = b1[b] - s0;
+    if (cnt != npat) {
+        if (lane == 0) flag[b] = 0;
+        return;
+    }
+    const double h = side[level[b]];
+    bool ok = true;
+    for (int j = lane; j < npat; j += 64) {
+        const double ex = (px[s0 + j] - cx[b]) / h - rx[j];
+        const double ey = (py[s0 + j] - cy[b]) / h - ry[j];
+        ok = ok && fabs(ex) <= PATTERN_TOL && fabs(ey) <= PATTERN_TOL;
+    }
+    const uint64_t all = __ballot(ok);
+    if (lane == 0) flag[b] = (all == ~0ull) ? 1 : 0;
+}
+
+template <class T>
+static T *upload(vp_plan_s *P, const std::vector<T> &h) {
+    T *d = P->mem.alloc<T>(h.size());
+    if (!h.empty()) VP_HIP(hipMemcpyAsync(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, P->stream));
+    return d;
+}
+
+void build_near_tables(vp_plan_s *P) {
+    Tree &T = P->tree;
+    NearTables &N = P->near;
+    hipStream_t s = P->stream;
+    const int nbox = T.nbox;
+    std::vector<int32_t> lev(nbox), ix(nbox), iy(nbox), sb(nbox), se(nbox), nch(nbox), leaves(T.nleaf);
+    std::vector<int32_t> uptr(nbox + 1), uidx(T.llen[0]), wptr(nbox + 1);
+    VP_HIP(hipMemcpyAsync(lev.data(), T.level, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(ix.data(), T.ix, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(iy.data(), T.iy, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(sb.data(), T.sb, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(se.data(), T.se, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(nch.data(), T.nchild, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(leaves.data(), T.leaves, 4 * T.nleaf, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(uptr.data(), T.lptr[0], 4 * (nbox + 1), hipMemcpyDeviceToHost, s));
+    if (T.llen[0]) VP_HIP(hipMemcpyAsync(uidx.data(), T.lidx[0], 4 * T.llen[0], hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(wptr.data(), T.lptr[2], 4 * (nbox + 1), hipMemcpyDeviceToHost, s));
+    VP_HIP(hipStreamSynchronize(s));
+
+    std::vector<int32_t> flag(nbox, 0);
+    int npat = 0;
+    std::vector<double> rx, ry;
+    const bool want = P->self && P->opt.p2p_mode != VP_P2P_PAIRWISE && T.nlevels >= 1;
+    if (want) {
+        // most frequent leaf size that the matrix cores can take
+        std::map<int, int> hist;
+        for (int b : leaves) hist[se[b] - sb[b]]++;
+        int best = 0, bestc = 0;
+        for (auto &kv : hist)
+            if (kv.first >= 16 && kv.first <= 128 && kv.first % 16 == 0 && kv.second > bestc) {
+                best = kv.first;
+                bestc = kv.second;
+            }
+        if (best > 0 && bestc >= 2) {
+            TempArena tmp;
+            double *drx = tmp.alloc<double>(best), *dry = tmp.alloc<double>(best);
+            int32_t *dflag = tmp.alloc<int32_t>(nbox);
+            fill_i32(dflag, 0, nbox, s);
+            int tried = 0, best_match = -1;
+            std::vector<double> hx(best), hy(best), bx, by;
+            for (int b : leaves) {
+                if (se[b] - sb[b] != best || tried >= 4) continue;
+                ++tried;
+                // reference coordinates from this leaf
+                double cx, cy;
+                VP_HIP(hipMemcpy(hx.data(), P->sx + sb[b], 8 * best, hipMemcpyDeviceToHost));
+                VP_HIP(hipMemcpy(hy.data(), P->sy + sb[b], 8 * best, hipMemcpyDeviceToHost));
+                VP_HIP(hipMemcpy(&cx, T.cx + b, 8, hipMemcpyDeviceToHost));
+                VP_HIP(hipMemcpy(&cy, T.cy + b, 8, hipMemcpyDeviceToHost));
+                const double h = T.side[lev[b]];
+                for (int j = 0; j < best; ++j) {
+                    hx[j] = (hx[j] - cx) / h;
+                    hy[j] = (hy[j] - cy) / h;
+                }
+                VP_HIP(hipMemcpyAsync(drx, hx.data(), 8 * best, hipMemcpyHostToDevice, s));
+                VP_HIP(hipMemcpyAsync(dry, hy.data(), 8 * best, hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_match_pattern, dim3(T.nleaf), dim3(64), 0, s, T.leaves, T.nleaf, T.sb, T.se,
+                                   P->sx, P->sy, T.cx, T.cy, T.level, T.d_side, drx, dry, best, dflag);
+                VP_LAUNCH_CHECK();
+                std::vector<int32_t> hf(nbox);
+                VP_HIP(hipMemcpyAsync(hf.data(), dflag, 4 * nbox, hipMemcpyDeviceToHost, s));
+                VP_HIP(hipStreamSynchronize(s));
+                int cnt = 0;
+                for (int v : hf) cnt += v;
+                if (cnt > best_match) {
+                    best_match = cnt;
+                    flag = hf;
+                    bx = hx;
+                    by = hy;
+                }
+                if (2 * cnt >= bestc) break;
+            }
+            if (best_match >= 2) {
+                npat = best;
+                rx = bx;
+                ry = by;
+            } else {
+                std::fill(flag.begin(), flag.end(), 0);
+            }
+        }
+    }
+    N.active = npat > 0;
+    N.npat = npat;
+
+    // --- U lists split: table slots for same-level pattern pairs, rest pairwise
+    std::vector<int32_t> tslot((size_t)nbox * 9, -1), rptr(nbox + 1, 0), ridx;
+    ridx.reserve(uidx.size());
+    std::vector<int> tab_levels;
+    std::vector<std::vector<int32_t>> cols_by_level(T.nlevels);
+    for (int b = 0; b < nbox; ++b) {
+        rptr[b] = (int32_t)ridx.size();
+        const bool pt = N.active && nch[b] == 0 && flag[b];
+        bool used = false;
+        for (int e = uptr[b]; e < uptr[b + 1]; ++e) {
+            const int a = uidx[e];
+            if (pt && flag[a] && lev[a] == lev[b]) {
+                const int o = (iy[a] - iy[b] + 1) * 3 + (ix[a] - ix[b] + 1);
+                tslot[(size_t)b * 9 + o] = a;
+                used = true;
+            } else {
+                ridx.push_back(a);
+            }
+        }
+        if (used) cols_by_level[lev[b]].push_back(b);
+    }
+    rptr[nbox] = (int32_t)ridx.size();
+    N.pair_uptr = upload(P, rptr);
+    N.pair_uidx = upload(P, ridx);
+    N.rest_len = (int64_t)ridx.size();
+    std::vector<int32_t> rest_leaves;
+    for (int b : leaves)
+        if (rptr[b + 1] > rptr[b]) rest_leaves.push_back(b);
+    N.rest_leaves = upload(P, rest_leaves);
+    N.n_rest_leaves = (int)rest_leaves.size();
+
+    // near-field pair count served by the pairwise kernel
+    int64_t pairs = 0;
+    for (int b = 0; b < nbox; ++b)
+        for (int e = rptr[b]; e < rptr[b + 1]; ++e) pairs += (int64_t)(se[b] - sb[b]) * (se[ridx[e]] - sb[ridx[e]]);
+    P->near_pairs = pairs;
+
+    std::vector<int32_t> ident(nbox);
+    for (int b = 0; b < nbox; ++b) ident[b] = b;
+    N.ident_slot = upload(P, ident);
+
+    // lists for P2M / L2P / far evaluation
+    std::vector<int32_t> p2m_pat, p2m_rest, l2p_pat, far_leaves, local_done(nbox, 0);
+    for (int b : leaves) {
+        const bool pt = N.active && flag[b];
+        if (lev[b] >= 2) (pt ? p2m_pat : p2m_rest).push_back(b);
+        if (pt && lev[b] >= 2) {
+            l2p_pat.push_back(b);
+            local_done[b] = 1;
+        }
+        if (!(pt && lev[b] >= 2) || wptr[b + 1] > wptr[b]) far_leaves.push_back(b);
+    }
+    N.p2m_pat = upload(P, p2m_pat);
+    N.n_p2m_pat = (int)p2m_pat.size();
+    N.p2m_rest = upload(P, p2m_rest);
+    N.n_p2m_rest = (int)p2m_rest.size();
+    N.l2p_pat = upload(P, l2p_pat);
+    N.n_l2p_pat = (int)l2p_pat.size();
+    N.far_leaves = upload(P, far_leaves);
+    N.n_far_leaves = (int)far_leaves.size();
+    N.local_done = upload(P, local_done);
+
+    N.nleaf_tab = 0;
+    N.tab_levels.clear();
+    N.tab_cols_begin.clear();
+    std::vector<int32_t> tcols;
+    for (int l = 0; l < T.nlevels; ++l)
+        if (!cols_by_level[l].empty()) {
+            N.tab_levels.push_back(l);
+            N.tab_cols_begin.push_back((int)tcols.size());
+            tcols.insert(tcols.end(), cols_by_level[l].begin(), cols_by_level[l].end());
+            N.nleaf_tab += (int)cols_by_level[l].size();
+        }
+    N.tab_cols_begin.push_back((int)tcols.size());
+    N.tab_cols = upload(P, tcols);
+    N.tab_slot = upload(P, tslot);
+
+    if (N.active) {
+        const int np = npat;
+        // near-field matrices per level, A-fragment order (rows = targets, cols = sources)
+        std::vector<double> K((size_t)N.tab_levels.size() * 9 * np * np), R((size_t)np * np);
+        for (size_t li = 0; li < N.tab_levels.size(); ++li) {
+            const double h = T.side[N.tab_levels[li]];
+            const double two_log_h = 2.0 * std::log(h);
+            for (int o = 0; o < 9; ++o) {
+                const double dx = (o % 3) - 1, dy = (o / 3) - 1;
+                for (int i = 0; i < np; ++i)
+                    for (int j = 0; j < np; ++j) {
+                        const double ex = rx[j] + dx - rx[i], ey = ry[j] + dy - ry[i];
+                        const double r2 = ex * ex + ey * ey;
+                        R[(size_t)i * np + j] = (r2 == 0.0) ? 0.0 : -INV_4PI * (std::log(r2) + two_log_h);
+                    }
+                vp_to_frag(R.data(), np, np, np, K.data() + ((size_t)li * 9 + o) * np * np);
+            }
+        }
+        N.K = upload(P, K);
+        // P2M of a pattern leaf: rows = expansion (PD), cols = pattern points
+        const int Pn = P->P, PD = P->PD;
+        std::vector<double> A((size_t)PD * np, 0.0), Af((size_t)PD * np);
+        for (int j = 0; j < np; ++j) {
+            std::complex<double> w(rx[j], ry[j]), pw(1.0, 0.0);
+            A[(size_t)0 * np + j] = 1.0;
+            for (int k = 1; k < Pn; ++k) {
+                pw *= w;
+                A[(size_t)k * np + j] = -pw.real() / k;
+                A[(size_t)(Pn + k) * np + j] = -pw.imag() / k;
+            }
+        }
+        vp_to_frag(A.data(), PD, np, np, Af.data());
+        // L2P of a pattern leaf: rows = pattern points, cols = expansion (PD)
+        std::vector<double> B((size_t)np * PD, 0.0), Bf((size_t)np * PD);
+        for (int i = 0; i < np; ++i) {
+            std::complex<double> w(rx[i], ry[i]), pw(1.0, 0.0);
+            for (int l = 0; l < Pn; ++l) {
+                B[(size_t)i * PD + l] = -INV_2PI * pw.real();
+                B[(size_t)i * PD + Pn + l] = INV_2PI * pw.imag();
+                pw *= w;
+            }
+        }
+        vp_to_frag(B.data(), np, PD, PD, Bf.data());
+        if (P->fp32) {
+            std::vector<float> af(Af.begin(), Af.end()), bf(Bf.begin(), Bf.end());
+            N.p2m_op_f32 = upload(P, af);
+            N.l2p_op_f32 = upload(P, bf);
+        } else {
+            N.p2m_op = upload(P, Af);
+            N.l2p_op = upload(P, Bf);
+        }
+    }
+    VP_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace vp

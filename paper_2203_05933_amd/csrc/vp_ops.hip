@@ -108,15 +108,21 @@ static void offset_of_code(int code, int &dx, int &dy) {
     dx = dy = 0;
 }
 
-// row-major PD x PD -> MFMA A-fragment order [rb][s][lane]:
-// element (row = rb*16 + lane%16, col = 4 s + lane/16)
-static void to_frag(const double *R, int PD, double *F) {
-    int RB = PD / 16, S = PD / 4;
+}  // namespace vp
+
+// row-major rows x cols (leading dimension ld) -> MFMA A-fragment order
+// [rb][s][lane]: element (row rb*16 + lane%16, col 4 s + lane/16)
+void vp_to_frag(const double *R, int rows, int cols, int ld, double *F) {
+    int RB = rows / 16, S = cols / 4;
     for (int rb = 0; rb < RB; ++rb)
         for (int s = 0; s < S; ++s)
             for (int lane = 0; lane < 64; ++lane)
-                F[((size_t)rb * S + s) * 64 + lane] = R[(size_t)(rb * 16 + lane % 16) * PD + 4 * s + lane / 16];
+                F[((size_t)rb * S + s) * 64 + lane] = R[(size_t)(rb * 16 + lane % 16) * ld + 4 * s + lane / 16];
 }
+
+namespace vp {
+
+static void to_frag(const double *R, int PD, double *F) { vp_to_frag(R, PD, PD, PD, F); }
 
 void build_operators(vp_plan_s *P) {
     const int Pn = P->P, PD = P->PD;
@@ -140,9 +146,11 @@ void build_operators(vp_plan_s *P) {
     for (int q = 0; q < 4; ++q) {
         double sx = (q & 1) ? 1.0 : -1.0, sy = (q >> 1) ? 1.0 : -1.0;
         auto Tm = m2m_complex(cd(0.5 * sx, 0.5 * sy), Pn, C, N);
-        to_real(Tm, Pn, PD, M2M.data() + q * mat);
+        to_real(Tm, Pn, PD, R.data());
+        to_frag(R.data(), PD, M2M.data() + q * mat);
         auto Tl = l2l_complex(cd(0.25 * sx, 0.25 * sy), Pn, C, N);
-        to_real(Tl, Pn, PD, L2L.data() + q * mat);
+        to_real(Tl, Pn, PD, R.data());
+        to_frag(R.data(), PD, L2L.data() + q * mat);
     }
     std::vector<double> invk(Pn, 0.0);
     for (int k = 1; k < Pn; ++k) invk[k] = 1.0 / k;

@@ -1,0 +1,168 @@
+// Gather-GEMM on matrix cores: the one kernel behind every dense, fixed-
+// operator step of the evaluation.
+//
+//   out[:, col] (+)= sum_o A_o in[:, src(col, o)]
+//
+// A column is a (box, density) pair; src(col, o) is the box in slot o of the
+// column's box (or none).  Uses:
+//   M2L          40 outer offsets, A_o = M2L operator (+ the A_0 log s row)
+//   M2M          4 child quadrants, A_q = child-to-parent shift
+//   L2L          4 child classes, A_q = parent-to-child shift
+//   near tables  9 neighbour offsets of congruent leaves, A_o = G matrix
+//   P2M / L2P    1 operator on congruent leaves (powers of the pattern)
+// The operator of the current slot is staged once in LDS and shared by the
+// four waves of a workgroup; each wave owns 16 columns.  Operators are
+// stored in A-fragment order [o][rb][s][lane], element (row rb*16 + l%16,
+// k = 4 s + l/16), so staging is a straight coalesced copy.
+#pragma once
+
+#include "vp_internal.hpp"
+
+namespace vp {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Column addressing: element r of the column (box a, density b) is at
+// base + off(a) + b * bstride + r, with off(a) = box_mult * a (expansion
+// arrays) or start[a] (point arrays in sorted order).
+struct ColAddr {
+    int64_t bstride;
+    int64_t box_mult;
+    const int32_t *start;
+    __device__ inline int64_t off(int a) const { return start ? (int64_t)start[a] : box_mult * (int64_t)a; }
+};
+
+template <class TM>
+struct Mfma;
+
+// v_mfma_f64_16x16x4: result element i of lane l is D[4i + l/16][l%16]
+template <>
+struct Mfma<double> {
+    typedef v4d acc_t;
+    static __device__ inline acc_t zero() { return (v4d){0.0, 0.0, 0.0, 0.0}; }
+    static __device__ inline acc_t op(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int i, int g) { return 4 * i + g; }
+    static __device__ inline int item_of(int r16) { return r16 >> 2; }
+    static __device__ inline int group_of(int r16) { return r16 & 3; }
+};
+
+// v_mfma_f32_16x16x4: result element i of lane l is D[4(l/16) + i][l%16]
+template <>
+struct Mfma<float> {
+    typedef v4f acc_t;
+    static __device__ inline acc_t zero() { return (v4f){0.f, 0.f, 0.f, 0.f}; }
+    static __device__ inline acc_t op(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int i, int g) { return 4 * g + i; }
+    static __device__ inline int item_of(int r16) { return r16 & 3; }
+    static __device__ inline int group_of(int r16) { return r16 >> 2; }
+};
+
+struct TranslateArgs {
+    const int32_t *cols_box;  // box of column group c / nbatch
+    int ncols;                // number of (box, density) columns
+    int nbatch;
+    const int32_t *slots;     // [box][nops] source box or -1
+    int nops;
+    ColAddr in, out;
+    int nrows_out;            // rows written per output column
+    int logrow;               // >= 0: row holding sum Re A_0 (M2L); -1 otherwise
+    const int32_t *level;
+    const double *logside;
+};
+
+// TI/TO: element types of input/output columns; TM: matrix-core type;
+// RB: 16-row blocks of the output; S: 4-row steps of the input;
+// SPLIT: add the A_lo product; ACCUM: out += instead of out =;
+// LDSA: stage operators in LDS (off for very large operators).
+template <class TI, class TO, class TM, int RB, int S, bool SPLIT, bool ACCUM, bool LDSA>
+__global__ void __launch_bounds__(256) k_translate(TranslateArgs a, const TM *__restrict__ Ahi,
+                                                   const TM *__restrict__ Alo, const TI *__restrict__ in,
+                                                   TO *__restrict__ out) {
+    typedef Mfma<TM> M;
+    constexpr int AE = RB * S * 64;
+    extern __shared__ unsigned char smem[];
+    TM *sA = reinterpret_cast<TM *>(smem);
+    TM *sAlo = sA + AE;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cl = lane & 15, g = lane >> 4;
+    const int col = (blockIdx.x * 4 + wave) * 16 + cl;
+    const bool valid = col < a.ncols;
+    const int box = valid ? a.cols_box[col / a.nbatch] : 0;
+    const int bt = valid ? col % a.nbatch : 0;
+    typename M::acc_t acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = M::zero();
+    for (int o = 0; o < a.nops; ++o) {
+        const int src = valid ? a.slots[(int64_t)box * a.nops + o] : -1;
+        if (!__syncthreads_or(src >= 0)) continue;
+        const TM *Ao = Ahi + (int64_t)o * AE;
+        const TM *Alo_o = SPLIT ? Alo + (int64_t)o * AE : nullptr;
+        if (LDSA) {
+            for (int e = tid; e < AE; e += 256) {
+                sA[e] = Ao[e];
+                if (SPLIT) sAlo[e] = Alo_o[e];
+            }
+            __syncthreads();
+        }
+        if (__ballot(src >= 0) != 0ull) {
+            TM bv[S];
+            const TI *ip = in + (src >= 0 ? a.in.off(src) + (int64_t)bt * a.in.bstride : 0) + g;
+#pragma unroll
+            for (int s = 0; s < S; ++s) bv[s] = (src >= 0) ? (TM)ip[4 * s] : (TM)0;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const int e = (r * S + s) * 64 + lane;
+                    const TM av = LDSA ? sA[e] : Ao[e];
+                    acc[r] = M::op(av, bv[s], acc[r]);
+                    if (SPLIT) acc[r] = M::op(LDSA ? sAlo[e] : Alo_o[e], bv[s], acc[r]);
+                }
+            }
+        }
+        if (LDSA) __syncthreads();
+    }
+    double vals[RB][4];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vals[r][i] = (double)acc[r][i];
+    if (a.logrow >= 0) {
+        // add A_0 log s (level of the target box) to row 0; clear the sum row
+        const int rb2 = a.logrow >> 4, r16 = a.logrow & 15;
+        const int i2 = M::item_of(r16), g2 = M::group_of(r16);
+        double s0 = 0.0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (r == rb2 && i == i2) s0 = vals[r][i];
+        s0 = __shfl(s0, g2 * 16 + cl, 64);
+        if (g == M::group_of(0) && valid) vals[0][M::item_of(0)] += s0 * a.logside[a.level[box]];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (r == rb2 && i == i2 && g == g2) vals[r][i] = 0.0;
+    }
+    if (valid) {
+        TO *op = out + a.out.off(box) + (int64_t)bt * a.out.bstride;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = r * 16 + M::row(i, g);
+                if (row < a.nrows_out) {
+                    if (ACCUM) op[row] += (TO)vals[r][i];
+                    else op[row] = (TO)vals[r][i];
+                }
+            }
+    }
+}
+
+}  // namespace vp

@@ -270,3 +270,50 @@ def test_duplicate_points_and_deep_tree():
     ref = direct.smooth(x, y, w, f)
     assert relinf(u, ref) <= TOL64
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# congruent-leaf path (near-field tables, pattern P2M/L2P) vs pairwise path
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,order,tol", [("fp64", 30, TOL64), ("fp32", 14, TOL32)])
+def test_tables_match_pairwise_and_oracle(c0, precision, order, tol):
+    vp = _vp()
+    ref = direct.evaluate(c0.x, c0.y, c0.w, c0.f, c0.rowptr, c0.col, c0.val)
+    out = {}
+    for mode in ("tables", "pairwise"):
+        plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=order,
+                       precision=precision, p2p_mode=mode, root=c0.root)
+        info = plan.info()
+        assert info["p2p_mode_used"] == (2 if mode == "tables" else 1)
+        if mode == "tables":
+            assert info["table_leaves"] == 256 and info["near_pairs"] == 0
+        u = _host(plan.eval(_dev(c0.f)))
+        err = relinf(u, ref)
+        print(f"{precision} p={order} {mode}: rel_inf={err:.3e}")
+        assert err <= tol
+        out[mode] = u
+        g = np.random.default_rng(6).standard_normal((1, c0.n))
+        d = _host(plan.eval_adjoint(_dev(g)))
+        dref = direct.evaluate_adjoint(c0.x, c0.y, c0.w, g, c0.rowptr, c0.col, c0.val)
+        assert relinf(d, dref) <= tol
+        plan.close()
+    if precision == "fp64":
+        assert relinf(out["tables"], out["pairwise"]) <= 1e-13
+
+
+def test_tables_on_adaptive_star_subset():
+    """Pattern leaves at several levels next to non-pattern (triangle) leaves."""
+    vp = _vp()
+    wl = gen.config1()
+    # keep a window of the domain so the oracle stays cheap
+    keep = (np.abs(wl.x - 0.9) < 0.25) & (np.abs(wl.y) < 0.25)
+    x, y, w, f = wl.x[keep], wl.y[keep], wl.w[keep], wl.f[:, keep]
+    plan = vp.Plan(x, y, w, order=30, root=wl.root)
+    info = plan.info()
+    assert info["p2p_mode_used"] == 2 and info["table_leaves"] > 0 and info["near_pairs"] > 0
+    u = _host(plan.eval(_dev(f)))
+    ref = direct.smooth(x, y, w, f)
+    err = relinf(u, ref)
+    print(f"star window n={x.size} table_leaves={info['table_leaves']} rel_inf={err:.3e}")
+    assert err <= TOL64
+    plan.close()
