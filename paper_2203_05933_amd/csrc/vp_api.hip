@@ -206,6 +206,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
             VP_HIP(hipMemcpyAsync(P->val, val, sizeof(double) * P->nnz, hipMemcpyHostToDevice, P->stream));
         }
         vp::build_csr_transpose(P);
+        vp::detect_runs(P);
         vp::build_schedules(P);
         // workspace
         const int64_t len = std::max(n, m);

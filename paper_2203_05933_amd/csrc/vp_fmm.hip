@@ -393,37 +393,84 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
 
 // ----------------------------------------------------------------------------
 // finish: out[b][i] = scale_i * acc[b][inv[i]] + sum_{q in row i} val[q] f[b][col[q]]
-// one wave per row, lanes over the row's non-zeros, fixed-order reduction.
+// (the sparse correction apply of Section 4 fused with the un-permutation).
+// Sixteen lanes share a row, so a wave keeps four rows in flight; a row
+// whose columns are one contiguous run (a cell's own nodes) reads only
+// its run start instead of a column index per non-zero.  Reductions run in
+// a fixed lane order.
 // ----------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, const int32_t *__restrict__ inv,
+template <int NBG>
+__global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, int bt0,
+                                                const int32_t *__restrict__ inv,
                                                 const double *__restrict__ scale,
                                                 const double *__restrict__ acc, int64_t acc_len,
                                                 const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ colv,
+                                                const int32_t *__restrict__ run_start,
                                                 const double *__restrict__ valv,
                                                 const double *__restrict__ f, int64_t flen,
                                                 double *__restrict__ out) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t i = wave; i < nrows; i += nwaves) {
-        const int64_t p0 = rowptr ? rowptr[i] : 0, p1 = rowptr ? rowptr[i + 1] : 0;
-        const int32_t si = inv[i];
-        const double sc = scale ? scale[i] : 1.0;
-        for (int bt = 0; bt < nbatch; ++bt) {
-            double part = 0.0;
-            for (int64_t pq = p0 + lane; pq < p1; pq += 64)
-                part += valv[pq] * f[(int64_t)bt * flen + colv[pq]];
-            part = wave_sum(part);
-            if (lane == 0) out[(int64_t)bt * nrows + i] = sc * acc[(int64_t)bt * acc_len + si] + part;
+    const int l16 = threadIdx.x & 15;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    const int nbg = min(NBG, nbatch - bt0);
+    for (int64_t i = grp; i < nrows; i += ngrp) {
+        const int64_t p0 = rowptr[i], p1 = rowptr[i + 1];
+        const int32_t rs = run_start[i];
+        double part[NBG];
+#pragma unroll
+        for (int k = 0; k < NBG; ++k) part[k] = 0.0;
+        for (int64_t pq = p0 + l16; pq < p1; pq += 16) {
+            const double v = valv[pq];
+            const int64_t c = rs >= 0 ? (int64_t)rs + (pq - p0) : (int64_t)colv[pq];
+#pragma unroll
+            for (int k = 0; k < NBG; ++k)
+                if (k < nbg) part[k] += v * f[(int64_t)(bt0 + k) * flen + c];
+        }
+#pragma unroll
+        for (int k = 0; k < NBG; ++k) {
+            double v = part[k];
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 16);
+            part[k] = v;
+        }
+        if (l16 == 0) {
+            const int32_t si = inv[i];
+            const double sc = scale ? scale[i] : 1.0;
+#pragma unroll
+            for (int k = 0; k < NBG; ++k)
+                if (k < nbg)
+                    out[(int64_t)(bt0 + k) * nrows + i] = sc * acc[(int64_t)(bt0 + k) * acc_len + si] + part[k];
         }
     }
+}
+
+// run_start[i] = first column when row i's columns are c0, c0+1, ..., else -1
+__global__ void k_detect_runs(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colv,
+                              int64_t nrows, int32_t *__restrict__ run_start) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    const int64_t p0 = rowptr[i], p1 = rowptr[i + 1];
+    if (p1 == p0) {
+        run_start[i] = 0;
+        return;
+    }
+    const int32_t c0 = colv[p0];
+    bool run = true;
+    for (int64_t q = p0 + 1; q < p1 && run; ++q) run = colv[q] == c0 + (int32_t)(q - p0);
+    run_start[i] = run ? c0 : -1;
+}
+
+void detect_runs(vp_plan_s *P) {
+    hipStream_t s = P->stream;
+    P->run_start = P->mem.alloc<int32_t>(P->m);
+    P->run_startT = P->mem.alloc<int32_t>(P->n);
+    hipLaunchKernelGGL(k_detect_runs, dim3((unsigned)((P->m + 255) / 256)), dim3(256), 0, s, P->rowptr, P->col, P->m,
+                       P->run_start);
+    hipLaunchKernelGGL(k_detect_runs, dim3((unsigned)((P->n + 255) / 256)), dim3(256), 0, s, P->rowptrT, P->colT,
+                       P->n, P->run_startT);
+    VP_LAUNCH_CHECK();
+    VP_HIP(hipStreamSynchronize(s));
 }
 
 __global__ void k_unpermute_grad(int64_t m, int nbatch, const int32_t *__restrict__ inv,
@@ -853,15 +900,27 @@ void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint) {
     const double *scale = adjoint ? P->w_user : nullptr;
     const int64_t *rp = adjoint ? P->rowptrT : P->rowptr;
     const int32_t *cv = adjoint ? P->colT : P->col;
+    const int32_t *rs = adjoint ? P->run_startT : P->run_start;
     const double *vv = adjoint ? P->valT : P->val;
     const int64_t flen = adjoint ? P->m : P->n;
-    int64_t waves = nrows;
-    int64_t blocks = (waves + 3) / 4;
-    if (blocks > 65536) blocks = 65536;
+    int64_t blocks = (nrows * 16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
     P->stage_begin(VP_STAGE_FINISH);
-    hipLaunchKernelGGL(k_finish, dim3((unsigned)blocks), dim3(256), 0, P->stream, nrows, P->nbatch, inv, scale,
-                       P->acc, nrows, rp, cv, vv, f, flen, u);
-    VP_LAUNCH_CHECK();
+    for (int bt0 = 0; bt0 < P->nbatch;) {
+        const int left = P->nbatch - bt0;
+        const int g = left >= 16 ? 16 : (left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1)));
+        switch (g) {
+#define VP_FIN(G)                                                                                           \
+    case G:                                                                                                 \
+        hipLaunchKernelGGL(k_finish<G>, dim3((unsigned)blocks), dim3(256), 0, P->stream, nrows, P->nbatch,   \
+                           bt0, inv, scale, P->acc, nrows, rp, cv, rs, vv, f, flen, u);                     \
+        break;
+            VP_FIN(16) VP_FIN(8) VP_FIN(4) VP_FIN(2) VP_FIN(1)
+#undef VP_FIN
+        }
+        VP_LAUNCH_CHECK();
+        bt0 += g;
+    }
     P->stage_end(VP_STAGE_FINISH);
 }
 

@@ -207,6 +207,8 @@ struct vp_plan_s {
     int64_t *rowptrT = nullptr;
     int32_t *colT = nullptr;
     double *valT = nullptr;
+    int32_t *run_start = nullptr;   // per row: first column of a contiguous run, or -1
+    int32_t *run_startT = nullptr;
 
     vp::Tree tree;
     vp::Operators ops;
@@ -265,6 +267,7 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad);
 void prepare_charges(vp_plan_s *P, const double *f, bool adjoint);
 void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint);
 void finish_grad(vp_plan_s *P, double *grad);
+void detect_runs(vp_plan_s *P);
 // vp_csr.hip
 void build_csr_transpose(vp_plan_s *P);
 // utilities (vp_tree.hip)
