@@ -119,6 +119,56 @@ __global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_
 }
 
 // ----------------------------------------------------------------------------
+// M2M / L2L on the VALU: one wave per target box of a level.  The source
+// columns (children, or the parent) are staged in LDS; lane r forms row r
+// from the transposed operator RT[k][r], so every operator read is a
+// contiguous 64-element row shared by the wave.  Used for the per-level
+// passes, which are too small to fill the matrix cores.
+// ----------------------------------------------------------------------------
+template <class E, bool L2L>
+__global__ void __launch_bounds__(64) k_shift(const int32_t *__restrict__ boxes, int nbatch, int P, int PD,
+                                              BoxGeo G, const E *__restrict__ RT, E *__restrict__ X) {
+    __shared__ E colv[4][128];
+    const int lane = threadIdx.x;
+    const int b = boxes[blockIdx.x];
+    int nsrc = 0, srcs[4], ops[4];
+    if (L2L) {
+        nsrc = 1;
+        srcs[0] = G.parent[b];
+        ops[0] = (G.ix[b] & 1) | ((G.iy[b] & 1) << 1);
+    } else {
+        nsrc = G.nchild[b];
+        for (int c = 0; c < nsrc; ++c) {
+            srcs[c] = G.child[b] + c;
+            ops[c] = (G.ix[srcs[c]] & 1) | ((G.iy[srcs[c]] & 1) << 1);
+        }
+    }
+    const int K = 2 * P;
+    for (int bt = 0; bt < nbatch; ++bt) {
+        for (int c = 0; c < nsrc; ++c)
+            for (int k = lane; k < K; k += 64) colv[c][k] = X[((int64_t)srcs[c] * nbatch + bt) * PD + k];
+        __syncthreads();
+        for (int r = lane; r < PD; r += 64) {
+            E acc = (E)0;
+            if (r < K) {
+                for (int c = 0; c < nsrc; ++c) {
+                    const E *R = RT + (int64_t)ops[c] * PD * PD + r;
+#pragma unroll 8
+                    for (int k = 0; k < K; ++k) acc += R[(int64_t)k * PD] * colv[c][k];
+                }
+            }
+            E *o = X + ((int64_t)b * nbatch + bt) * PD + r;
+            if (L2L) {
+                if (r < K) *o += acc;
+            } else {
+                *o = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
 // P2L (X lists): sources of a coarser leaf straight into the local expansion
 // of box b: B_0 += sum q log|c - z|, B_l += -(1/l) sum q (s/(z - c))^l.
 // ----------------------------------------------------------------------------
@@ -270,14 +320,57 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
 }
 
 // ----------------------------------------------------------------------------
-// P2P (U lists), FP64: one wave per target leaf.  Source tiles of up to
-// P2P_TILE points are staged in LDS as SoA (x, y, q per density).  When a
-// leaf has few targets the lanes also split the source loop (K lane
-// groups) and the partial sums are combined in a fixed order.
-// Pairs at zero distance (the self pair) contribute nothing.
-// Writes acc = near-field value (the first writer of acc).
+// Natural logarithm of a positive normal double, for the near field.
+// Range reduction x = m 2^e with m in [1/sqrt2, sqrt2), then
+//   log m = 2 atanh(s),  s = (m - 1)/(m + 1),  |s| <= 0.1716,
+// with the Taylor series atanh(s) = s + s^3/3 + s^5/5 + ... truncated after
+// the s^23 term (remainder < 1e-17 relative).  1/(m+1) comes from the
+// hardware reciprocal refined by two Newton steps; e log 2 is added with a
+// two-part log 2.  Accuracy is a few ulps, far below the 1e-12 target.
 // ----------------------------------------------------------------------------
-constexpr int P2P_TILE = 256;
+// Series coefficients 2/(2k+3), k = 0..10, in constant memory: uniform
+// loads keep them in scalar registers, so each Horner step is one untied FMA.
+__constant__ double c_log_series[11] = {2.0 / 3.0,  2.0 / 5.0,  2.0 / 7.0,  2.0 / 9.0,
+                                        2.0 / 11.0, 2.0 / 13.0, 2.0 / 15.0, 2.0 / 17.0,
+                                        2.0 / 19.0, 2.0 / 21.0, 2.0 / 23.0};
+
+__device__ inline double vp_log(double x) {
+    const double SQRT_HALF = 0.70710678118654752440;
+    const double LN2_HI = 6.93147180369123816490e-01;  // 0x3FE62E42FEE00000
+    const double LN2_LO = 1.90821492927058770002e-10;  // log 2 - LN2_HI
+    int e = __builtin_amdgcn_frexp_exp(x);
+    double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
+    const bool lo = m < SQRT_HALF;
+    m = lo ? m + m : m;
+    e = lo ? e - 1 : e;
+    const double f = m - 1.0;  // exact
+    const double d = m + 1.0;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    const double sv = f * r;
+    const double z = sv * sv;
+    double pl = c_log_series[10];
+#pragma unroll
+    for (int k = 9; k >= 0; --k) pl = fma(pl, z, c_log_series[k]);
+    const double logm = fma(sv * z, pl, 2.0 * sv);
+    const double de = (double)e;
+    return fma(de, LN2_HI, fma(de, LN2_LO, logm));
+}
+
+// ----------------------------------------------------------------------------
+// P2P (U lists), FP64: one wave per target leaf.  All source points of the
+// leaf's list are staged in LDS (SoA x, y, q per density) in tiles of
+// P2P_CAP points, so a leaf with many small neighbours pays one barrier
+// pair per tile.  When a leaf has few targets the lanes also split the
+// source loop (K lane groups) and the partial sums are combined in a fixed
+// order.  Pairs at zero distance (the self pair) contribute nothing; the
+// logarithm is branch-free (log 1 = 0 stands in for them).
+// ----------------------------------------------------------------------------
+template <int NB>
+struct P2PCap {
+    static constexpr int value = NB <= 1 ? 512 : (NB <= 2 ? 384 : (NB <= 4 ? 256 : (NB <= 8 ? 160 : 96)));
+};
 
 template <int NB, bool GRAD, bool ACCUM>
 __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restrict__ leaves,
@@ -285,8 +378,9 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
                                             const int32_t *__restrict__ uidx,
                                             const double *__restrict__ q, int nbatch, int bt0,
                                             double *__restrict__ acc) {
-    __shared__ double xs[P2P_TILE], ys[P2P_TILE];
-    __shared__ double qs[NB][P2P_TILE];
+    constexpr int CAP = P2PCap<NB>::value;
+    __shared__ double xs[CAP], ys[CAP];
+    __shared__ double qs[NB][CAP];
     __shared__ double red[GRAD ? 2 * NB : NB][64];
     const int lane = threadIdx.x;
     const int b = leaves[blockIdx.x];
@@ -298,45 +392,61 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
     const int K = 64 / T2;
     const int tl = lane % T2, kg = lane / T2;
     const int nbh = min(NB, nbatch - bt0);
+    const int e0 = uptr[b], e1 = uptr[b + 1];
     for (int base = t0; base < t1; base += 64) {
         const int t = base + tl;
-        const bool act = t < t1 && (T2 < 64 || true);
+        const bool act = t < t1;
         const double px = act ? R.tx[t] : 0.0, py = act ? R.ty[t] : 0.0;
         double a[NB], gxa[NB], gya[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) a[k] = gxa[k] = gya[k] = 0.0;
-        for (int e = uptr[b]; e < uptr[b + 1]; ++e) {
-            const int src = uidx[e];
-            const int s0 = R.sb[src], s1 = R.se[src];
-            for (int sbase = s0; sbase < s1; sbase += P2P_TILE) {
-                const int cnt = min(P2P_TILE, s1 - sbase);
-                __syncthreads();
-                for (int j = lane; j < cnt; j += 64) {
-                    xs[j] = R.sx[sbase + j];
-                    ys[j] = R.sy[sbase + j];
+        int e = e0, eoff = 0;
+        while (e < e1) {
+            // fill one tile from the list, continuing inside a leaf if needed
+            __syncthreads();
+            int fill = 0;
+            while (e < e1 && fill < CAP) {
+                const int src = uidx[e];
+                const int s0 = R.sb[src] + eoff, s1 = R.se[src];
+                const int take = min(s1 - s0, CAP - fill);
+                for (int j = lane; j < take; j += 64) {
+                    xs[fill + j] = R.sx[s0 + j];
+                    ys[fill + j] = R.sy[s0 + j];
 #pragma unroll
                     for (int k = 0; k < NB; ++k)
-                        qs[k][j] = (k < nbh) ? q[(int64_t)(bt0 + k) * R.nsrc + sbase + j] : 0.0;
+                        qs[k][fill + j] = (k < nbh) ? q[(int64_t)(bt0 + k) * R.nsrc + s0 + j] : 0.0;
                 }
-                __syncthreads();
-                if (act) {
-                    for (int j = kg; j < cnt; j += K) {
-                        const double dx = xs[j] - px, dy = ys[j] - py;
-                        const double r2 = dx * dx + dy * dy;
-                        if (r2 == 0.0) continue;
-                        if (GRAD) {
-                            const double ir2 = 1.0 / r2;
+                fill += take;
+                if (s0 + take == s1) {
+                    ++e;
+                    eoff = 0;
+                } else {
+                    eoff += take;
+                }
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll 2
+                for (int j = kg; j < fill; j += K) {
+                    const double dx = xs[j] - px, dy = ys[j] - py;
+                    const double r2 = fma(dx, dx, dy * dy);
+                    const bool nz = r2 > 0.0;
+                    if (GRAD) {
+                        const double rr = nz ? r2 : 1.0;
+                        double ir2 = __builtin_amdgcn_rcp(rr);
+                        ir2 = fma(fma(-rr, ir2, 1.0), ir2, ir2);
+                        ir2 = fma(fma(-rr, ir2, 1.0), ir2, ir2);
+                        ir2 = nz ? ir2 : 0.0;
 #pragma unroll
-                            for (int k = 0; k < NB; ++k) {
-                                const double c = qs[k][j] * ir2;
-                                gxa[k] += c * dx;
-                                gya[k] += c * dy;
-                            }
-                        } else {
-                            const double lg = log(r2);
-#pragma unroll
-                            for (int k = 0; k < NB; ++k) a[k] += qs[k][j] * lg;
+                        for (int k = 0; k < NB; ++k) {
+                            const double c = qs[k][j] * ir2;
+                            gxa[k] = fma(c, dx, gxa[k]);
+                            gya[k] = fma(c, dy, gya[k]);
                         }
+                    } else {
+                        const double lg = vp_log(nz ? r2 : 1.0);
+#pragma unroll
+                        for (int k = 0; k < NB; ++k) a[k] = fma(qs[k][j], lg, a[k]);
                     }
                 }
             }
@@ -562,8 +672,8 @@ template <class TI, class TO, class TM, bool SPLIT, bool ACCUM, int RB>
 static void launch_sq(hipStream_t s, const TranslateArgs &a, const TM *Ahi, const TM *Alo, const TI *in,
                       TO *out) {
     constexpr int S = RB * 4;
-    constexpr size_t lds = (size_t)RB * S * 64 * sizeof(TM) * (SPLIT ? 2 : 1);
-    constexpr bool LDSA = lds <= 65536;
+    constexpr bool LDSA = translate_ldsa<TM, RB, S, SPLIT>();
+    constexpr size_t lds = translate_lds_bytes<TM, RB, S, SPLIT>();
     const unsigned blocks = (unsigned)((a.ncols + 63) / 64);
     hipLaunchKernelGGL((k_translate<TI, TO, TM, RB, S, SPLIT, ACCUM, LDSA>), dim3(blocks), dim3(256),
                        LDSA ? lds : 0, s, a, Ahi, Alo, in, out);
@@ -648,7 +758,6 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
     const E *Rm2m = f32 ? (const E *)P->ops.m2m_f32 : (const E *)P->ops.m2m_f64;
     const E *Rl2l = f32 ? (const E *)P->ops.l2l_f32 : (const E *)P->ops.l2l_f64;
-    (void)G;
     const size_t lds = sizeof(E) * 2 * 64 * Pn;
     if (T.nlevels < 3) return;  // no box is well separated from another
     P->stage_begin(VP_STAGE_P2M);
@@ -666,10 +775,15 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     }
     P->stage_end(VP_STAGE_P2M);
     P->stage_begin(VP_STAGE_M2M);
+    const E *RTm = f32 ? (const E *)P->ops.m2m_t32 : (const E *)P->ops.m2m_t64;
+    const E *RTl = f32 ? (const E *)P->ops.l2l_t32 : (const E *)P->ops.l2l_t64;
     for (int l = T.nlevels - 2; l >= 2; --l) {
         int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
-        TranslateArgs a = expansion_args(P, P->m2m_parents + c0, c1 - c0, P->child_slot, 4, -1);
-        translate_sq<E, E, E, false, false>(s, PD, a, Rm2m, (const E *)nullptr, M, M);
+        if (c1 > c0) {
+            hipLaunchKernelGGL((k_shift<E, false>), dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0, nb, Pn, PD,
+                               G, RTm, M);
+            VP_LAUNCH_CHECK();
+        }
     }
     P->stage_end(VP_STAGE_M2M);
     P->stage_begin(VP_STAGE_M2L);
@@ -700,8 +814,11 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     P->stage_begin(VP_STAGE_L2L);
     for (int l = 3; l < T.nlevels; ++l) {
         int c0 = P->lvl_box_begin[l], c1 = P->lvl_box_begin[l + 1];
-        TranslateArgs a = expansion_args(P, P->lvl_boxes + c0, c1 - c0, P->l2l_slot, 4, -1);
-        translate_sq<E, E, E, false, true>(s, PD, a, Rl2l, (const E *)nullptr, L, L);
+        if (c1 > c0) {
+            hipLaunchKernelGGL((k_shift<E, true>), dim3(c1 - c0), dim3(64), 0, s, P->lvl_boxes + c0, nb, Pn, PD, G,
+                               RTl, L);
+            VP_LAUNCH_CHECK();
+        }
     }
     P->stage_end(VP_STAGE_L2L);
 }
@@ -746,7 +863,8 @@ template <int RB>
 static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     NearTables &N = P->near;
     constexpr int S = RB * 4;
-    constexpr size_t lds = (size_t)RB * S * 64 * sizeof(double);
+    constexpr bool LDSA = translate_ldsa<double, RB, S, false>();
+    constexpr size_t lds = LDSA ? translate_lds_bytes<double, RB, S, false>() : 0;
     const size_t opsz = (size_t)N.npat * N.npat;
     for (size_t li = 0; li < N.tab_levels.size(); ++li) {
         TranslateArgs a;
@@ -762,7 +880,7 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
         a.level = P->tree.level;
         a.logside = P->tree.d_logside;
         if (a.ncols <= 0) continue;
-        hipLaunchKernelGGL((k_translate<double, double, double, RB, S, false, true, true>),
+        hipLaunchKernelGGL((k_translate<double, double, double, RB, S, false, true, LDSA>),
                            dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a,
                            N.K + li * 9 * opsz, (const double *)nullptr, P->q, P->acc);
         VP_LAUNCH_CHECK();
@@ -798,7 +916,8 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, bool p2m) {
     if (p2m) {
         // rows = expansion (RBE blocks), cols = pattern points (RBP*16)
         constexpr int RB = RBE, S = RBP * 4;
-        constexpr size_t lds = (size_t)RB * S * 64 * sizeof(E);
+        constexpr bool LDSA = translate_ldsa<E, RB, S, false>();
+        constexpr size_t lds = LDSA ? translate_lds_bytes<E, RB, S, false>() : 0;
         a.cols_box = N.p2m_pat;
         a.ncols = N.n_p2m_pat * P->nbatch;
         a.in = ColAddr{R.nsrc, 0, R.sb};
@@ -806,12 +925,13 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, bool p2m) {
         a.nrows_out = P->PD;
         if (a.ncols <= 0) return;
         const E *op = f32 ? (const E *)N.p2m_op_f32 : (const E *)N.p2m_op;
-        hipLaunchKernelGGL((k_translate<double, E, E, RB, S, false, false, true>),
+        hipLaunchKernelGGL((k_translate<double, E, E, RB, S, false, false, LDSA>),
                            dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
                            P->q, static_cast<E *>(P->Mexp));
     } else {
         constexpr int RB = RBP, S = RBE * 4;
-        constexpr size_t lds = (size_t)RB * S * 64 * sizeof(E);
+        constexpr bool LDSA = translate_ldsa<E, RB, S, false>();
+        constexpr size_t lds = LDSA ? translate_lds_bytes<E, RB, S, false>() : 0;
         a.cols_box = N.l2p_pat;
         a.ncols = N.n_l2p_pat * P->nbatch;
         a.in = ColAddr{P->PD, (int64_t)P->nbatch * P->PD, nullptr};
@@ -819,7 +939,7 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, bool p2m) {
         a.nrows_out = N.npat;
         if (a.ncols <= 0) return;
         const E *op = f32 ? (const E *)N.l2p_op_f32 : (const E *)N.l2p_op;
-        hipLaunchKernelGGL((k_translate<E, double, E, RB, S, false, true, true>),
+        hipLaunchKernelGGL((k_translate<E, double, E, RB, S, false, true, LDSA>),
                            dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
                            static_cast<const E *>(P->Lexp), P->acc);
     }

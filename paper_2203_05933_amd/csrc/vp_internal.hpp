@@ -141,6 +141,9 @@ struct Operators {
     // shift operators, same order, 4 ops each (child quadrant / child class)
     double *m2m_f64 = nullptr, *l2l_f64 = nullptr;
     float *m2m_f32 = nullptr, *l2l_f32 = nullptr;
+    // the same shifts transposed ([op][k][r], r fastest) for the VALU kernel
+    double *m2m_t64 = nullptr, *l2l_t64 = nullptr;
+    float *m2m_t32 = nullptr, *l2l_t32 = nullptr;
     double *inv_k = nullptr;  // 1/k, k = 0..P-1 (0 for k = 0)
     float *inv_k_f32 = nullptr;
 };

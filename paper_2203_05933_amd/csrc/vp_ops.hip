@@ -142,15 +142,21 @@ void build_operators(vp_plan_s *P) {
         R[(size_t)(2 * Pn) * PD + 0] = 1.0;  // sum of Re A_0 (log s term)
         to_frag(R.data(), PD, F.data() + code * mat);
     }
-    std::vector<double> M2M(4 * mat), L2L(4 * mat);
+    std::vector<double> M2M(4 * mat), L2L(4 * mat), M2Mt(4 * mat), L2Lt(4 * mat);
+    auto transpose = [&](const double *Rm, double *out) {
+        for (int r = 0; r < PD; ++r)
+            for (int k = 0; k < PD; ++k) out[(size_t)k * PD + r] = Rm[(size_t)r * PD + k];
+    };
     for (int q = 0; q < 4; ++q) {
         double sx = (q & 1) ? 1.0 : -1.0, sy = (q >> 1) ? 1.0 : -1.0;
         auto Tm = m2m_complex(cd(0.5 * sx, 0.5 * sy), Pn, C, N);
         to_real(Tm, Pn, PD, R.data());
         to_frag(R.data(), PD, M2M.data() + q * mat);
+        transpose(R.data(), M2Mt.data() + q * mat);
         auto Tl = l2l_complex(cd(0.25 * sx, 0.25 * sy), Pn, C, N);
         to_real(Tl, Pn, PD, R.data());
         to_frag(R.data(), PD, L2L.data() + q * mat);
+        transpose(R.data(), L2Lt.data() + q * mat);
     }
     std::vector<double> invk(Pn, 0.0);
     for (int k = 1; k < Pn; ++k) invk[k] = 1.0 / k;
@@ -169,6 +175,8 @@ void build_operators(vp_plan_s *P) {
     O.m2l_f64 = up(F);
     O.m2m_f64 = up(M2M);
     O.l2l_f64 = up(L2L);
+    O.m2m_t64 = up(M2Mt);
+    O.l2l_t64 = up(L2Lt);
     O.inv_k = up(invk);
     if (P->fp32) {
         std::vector<float> hi(F.size()), lo(F.size());
@@ -181,6 +189,9 @@ void build_operators(vp_plan_s *P) {
         std::vector<float> a(M2M.begin(), M2M.end()), b(L2L.begin(), L2L.end()), c(invk.begin(), invk.end());
         O.m2m_f32 = upf(a);
         O.l2l_f32 = upf(b);
+        std::vector<float> at(M2Mt.begin(), M2Mt.end()), bt(L2Lt.begin(), L2Lt.end());
+        O.m2m_t32 = upf(at);
+        O.l2l_t32 = upf(bt);
         O.inv_k_f32 = upf(c);
     }
     VP_HIP(hipStreamSynchronize(s));

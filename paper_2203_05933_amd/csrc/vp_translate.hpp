@@ -165,4 +165,14 @@ __global__ void __launch_bounds__(256) k_translate(TranslateArgs a, const TM *__
     }
 }
 
+// Dynamic LDS bytes of a k_translate launch (0 when operators stay in global memory).
+template <class TM, int RB, int S, bool SPLIT>
+constexpr size_t translate_lds_bytes() {
+    return (size_t)(SPLIT ? 2 : 1) * RB * S * 64 * sizeof(TM);
+}
+template <class TM, int RB, int S, bool SPLIT>
+constexpr bool translate_ldsa() {
+    return translate_lds_bytes<TM, RB, S, SPLIT>() <= 61440;
+}
+
 }  // namespace vp
