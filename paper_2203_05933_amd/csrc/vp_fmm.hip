@@ -37,6 +37,8 @@ __device__ inline C2<E> cmul(C2<E> a, C2<E> b) {
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 
+__device__ inline double vp_log(double x);  // defined with the near-field kernel
+
 // Point-set view: which points act as sources and which as targets.
 struct PointRoles {
     const double *sx, *sy;         // source coordinates (sorted)
@@ -65,9 +67,50 @@ __global__ void k_charge(const double *__restrict__ f, const int32_t *__restrict
 }
 
 // ----------------------------------------------------------------------------
-// P2M: one wave per leaf.  Lane j of a chunk builds the row
-// W[j][k] = -(1/k) ((z_j - c)/s)^k (W[j][0] = 1) in LDS; lane r then forms
-// A_r = sum_j q_j W[j][r] for each density, in source order.
+// Power tables for P2M / P2L.  Sources come in chunks of 16; lane
+// (j = l % 16, g = l / 16) fills entries k in [g*KP, (g+1)*KP) of row j,
+// starting from w^(g*KP) obtained by repeated squaring, so all 64 lanes
+// work.  Row j holds c_k w_j^k (c_0 = the k = 0 entry, c_k = -1/k).
+// ----------------------------------------------------------------------------
+template <class E>
+__device__ inline C2<E> cpow_int(C2<E> w, int n) {
+    C2<E> r = {(E)1, (E)0};
+    while (n > 0) {
+        if (n & 1) r = cmul(r, w);
+        w = cmul(w, w);
+        n >>= 1;
+    }
+    return r;
+}
+
+template <class E>
+__device__ inline void fill_power_rows(C2<E> w, E k0re, bool valid, int j, int g, int P,
+                                       const E *__restrict__ invk, E *Wre, E *Wim) {
+    const int KP = (P + 3) / 4;
+    const int k0 = g * KP, k1 = min(P, k0 + KP);
+    if (!valid) {
+        for (int k = k0; k < k1; ++k) {
+            Wre[j * P + k] = (E)0;
+            Wim[j * P + k] = (E)0;
+        }
+        return;
+    }
+    C2<E> pw = cpow_int(w, k0);
+    for (int k = k0; k < k1; ++k) {
+        if (k == 0) {
+            Wre[j * P] = k0re;
+            Wim[j * P] = (E)0;
+        } else {
+            Wre[j * P + k] = -pw.re * invk[k];
+            Wim[j * P + k] = -pw.im * invk[k];
+        }
+        pw = cmul(pw, w);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// P2M: one wave per leaf; A_r = sum_j q_j W[j][r] in source order, with
+// W[j][0] = 1 and W[j][k] = -(1/k) ((z_j - c)/s)^k.
 // ----------------------------------------------------------------------------
 template <class E>
 __global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_t *__restrict__ boxes,
@@ -75,46 +118,40 @@ __global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_
                                             int P, int PD, const E *__restrict__ invk,
                                             E *__restrict__ Mexp) {
     extern __shared__ unsigned char smem[];
-    E *Wre = reinterpret_cast<E *>(smem);   // [64][P]
-    E *Wim = Wre + 64 * P;                  // [64][P]
-    const int lane = threadIdx.x;
+    E *Wre = reinterpret_cast<E *>(smem);   // [16][P]
+    E *Wim = Wre + 16 * P;                  // [16][P]
+    __shared__ E sq[16][16];                // charges of the chunk [density][source]
+    const int lane = threadIdx.x, j = lane & 15, g = lane >> 4;
     const int b = boxes[blockIdx.x];
     const int s0 = R.sb[b], s1 = R.se[b];
     const double cx = G.cx[b], cy = G.cy[b];
     const double inv_s = 1.0 / G.side[G.level[b]];
     E *out = Mexp + (int64_t)b * nbatch * PD;
-    for (int base = s0; base < s1 || base == s0; base += 64) {
-        int cnt = min(64, s1 - base);
-        if (lane < cnt) {
-            int j = base + lane;
-            C2<E> w = {(E)((R.sx[j] - cx) * inv_s), (E)((R.sy[j] - cy) * inv_s)};
-            C2<E> pw = {(E)1, (E)0};
-            Wre[lane * P] = (E)1;
-            Wim[lane * P] = (E)0;
-            for (int k = 1; k < P; ++k) {
-                pw = cmul(pw, w);
-                Wre[lane * P + k] = -pw.re * invk[k];
-                Wim[lane * P + k] = -pw.im * invk[k];
-            }
-        }
-        __syncthreads();
-        for (int r = lane; r < PD; r += 64) {
-            if (r < 2 * P) {
+    for (int bt0 = 0; bt0 < nbatch; bt0 += 16) {
+        const int nbg = min(16, nbatch - bt0);
+        E acc[2][16];
+        for (int k = 0; k < 16; ++k) acc[0][k] = acc[1][k] = (E)0;
+        for (int base = s0; base < s1; base += 16) {
+            const int cnt = min(16, s1 - base);
+            __syncthreads();
+            const bool v = j < cnt;
+            const int jj = base + (v ? j : 0);
+            const C2<E> w = {(E)((R.sx[jj] - cx) * inv_s), (E)((R.sy[jj] - cy) * inv_s)};
+            fill_power_rows<E>(w, (E)1, v, j, g, P, invk, Wre, Wim);
+            for (int bb = g; bb < nbg; bb += 4) sq[bb][j] = v ? (E)q[(int64_t)(bt0 + bb) * R.nsrc + jj] : (E)0;
+            __syncthreads();
+            for (int r = lane, ri = 0; r < 2 * P; r += 64, ++ri) {
                 const int k = r < P ? r : r - P;
                 const E *Wc = r < P ? Wre : Wim;
-                for (int bt = 0; bt < nbatch; ++bt) {
-                    const double *qb = q + (int64_t)bt * R.nsrc + base;
-                    E acc = (E)0;
-                    for (int j = 0; j < cnt; ++j) acc += (E)qb[j] * Wc[j * P + k];
-                    if (base == s0) out[bt * PD + r] = acc;
-                    else out[bt * PD + r] += acc;
+                for (int bb = 0; bb < nbg; ++bb) {
+                    E t = (E)0;
+                    for (int jx = 0; jx < cnt; ++jx) t += sq[bb][jx] * Wc[jx * P + k];
+                    acc[ri][bb] += t;
                 }
-            } else if (base == s0) {
-                for (int bt = 0; bt < nbatch; ++bt) out[bt * PD + r] = (E)0;
             }
         }
-        __syncthreads();
-        if (cnt <= 0) break;
+        for (int r = lane, ri = 0; r < PD; r += 64, ++ri)
+            for (int bb = 0; bb < nbg; ++bb) out[(bt0 + bb) * PD + r] = (r < 2 * P) ? acc[ri][bb] : (E)0;
     }
 }
 
@@ -179,49 +216,42 @@ __global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_
                                             const double *__restrict__ q, int nbatch, int P, int PD,
                                             const E *__restrict__ invk, E *__restrict__ Lexp) {
     extern __shared__ unsigned char smem[];
-    E *Wre = reinterpret_cast<E *>(smem);
-    E *Wim = Wre + 64 * P;
-    const int lane = threadIdx.x;
+    E *Wre = reinterpret_cast<E *>(smem);  // [16][P]
+    E *Wim = Wre + 16 * P;
+    __shared__ E sq[16][16];               // charges of the chunk [density][source]
+    const int lane = threadIdx.x, j = lane & 15, g = lane >> 4;
     const int b = boxes[blockIdx.x];
     const double cx = G.cx[b], cy = G.cy[b];
     const double s = G.side[G.level[b]];
     E *Lo = Lexp + (int64_t)b * nbatch * PD;
-    E acc[2][16];  // rows lane and lane + 64 (2P <= 128), 16 densities at a time
     for (int bt0 = 0; bt0 < nbatch; bt0 += 16) {
         const int nb = min(16, nbatch - bt0);
+        E acc[2][16];
         for (int k = 0; k < 16; ++k) acc[0][k] = acc[1][k] = (E)0;
         for (int e = xptr[b]; e < xptr[b + 1]; ++e) {
             const int a = xidx[e];
             const int s0 = R.sb[a], s1 = R.se[a];
-            for (int base = s0; base < s1; base += 64) {
-                const int cnt = min(64, s1 - base);
-                if (lane < cnt) {
-                    int j = base + lane;
-                    double dx = R.sx[j] - cx, dy = R.sy[j] - cy;
-                    double d2 = dx * dx + dy * dy;
-                    // s / (z - c) = s (dx - i dy) / d2
-                    C2<E> iw = {(E)(s * dx / d2), (E)(-s * dy / d2)};
-                    C2<E> pw = {(E)1, (E)0};
-                    Wre[lane * P] = (E)(0.5 * log(d2));
-                    Wim[lane * P] = (E)0;
-                    for (int k = 1; k < P; ++k) {
-                        pw = cmul(pw, iw);
-                        Wre[lane * P + k] = -pw.re * invk[k];
-                        Wim[lane * P + k] = -pw.im * invk[k];
-                    }
-                }
+            for (int base = s0; base < s1; base += 16) {
+                const int cnt = min(16, s1 - base);
+                __syncthreads();
+                const bool v = j < cnt;
+                const int jj = base + (v ? j : 0);
+                const double dx = R.sx[jj] - cx, dy = R.sy[jj] - cy;
+                const double d2 = dx * dx + dy * dy;
+                // s / (z - c) = s (dx - i dy) / d2
+                const C2<E> iw = {(E)(s * dx / d2), (E)(-s * dy / d2)};
+                fill_power_rows<E>(iw, (E)(0.5 * vp_log(d2)), v, j, g, P, invk, Wre, Wim);
+                for (int bb = g; bb < nb; bb += 4) sq[bb][j] = v ? (E)q[(int64_t)(bt0 + bb) * R.nsrc + jj] : (E)0;
                 __syncthreads();
                 for (int r = lane, ri = 0; r < 2 * P; r += 64, ++ri) {
                     const int k = r < P ? r : r - P;
                     const E *Wc = r < P ? Wre : Wim;
                     for (int bb = 0; bb < nb; ++bb) {
-                        const double *qb = q + (int64_t)(bt0 + bb) * R.nsrc + base;
                         E t = (E)0;
-                        for (int j = 0; j < cnt; ++j) t += (E)qb[j] * Wc[j * P + k];
+                        for (int jx = 0; jx < cnt; ++jx) t += sq[bb][jx] * Wc[jx * P + k];
                         acc[ri][bb] += t;
                     }
                 }
-                __syncthreads();
             }
         }
         for (int r = lane, ri = 0; r < 2 * P; r += 64, ++ri)
@@ -243,6 +273,7 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
                                             const E *__restrict__ Lexp,
                                             const int32_t *__restrict__ local_done,
                                             double *__restrict__ acc) {
+    __shared__ E col[128];  // one expansion column, staged for broadcast reads
     const int lane = threadIdx.x;
     const int b = leaves[blockIdx.x];
     const int t0 = R.tb[b], t1 = R.te[b];
@@ -251,6 +282,7 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
     const int lb = G.level[b];
     const double s = G.side[lb];
     const bool has_local = lb >= 2 && !(local_done && local_done[b]);
+    const int w0 = wptr[b], w1 = wptr[b + 1];
     for (int base = t0; base < t1; base += 64) {
         const int t = base + lane;
         const bool act = t < t1;
@@ -259,16 +291,20 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
         for (int bt = 0; bt < nbatch; ++bt) {
             C2<E> phi = {(E)0, (E)0}, dphi = {(E)0, (E)0};
             if (has_local) {
-                const E *Lb = Lexp + ((int64_t)b * nbatch + bt) * PD;
+                __syncthreads();
+                for (int k = lane; k < 2 * P; k += 64) col[k] = Lexp[((int64_t)b * nbatch + bt) * PD + k];
+                __syncthreads();
+#pragma unroll 4
                 for (int l = P - 1; l >= 0; --l) {
+                    const E cre = col[l], cim = col[P + l];
                     if (GRAD && l >= 1) {
                         dphi = cmul(dphi, w);
-                        dphi.re += (E)l * Lb[l];
-                        dphi.im += (E)l * Lb[P + l];
+                        dphi.re += (E)l * cre;
+                        dphi.im += (E)l * cim;
                     }
                     phi = cmul(phi, w);
-                    phi.re += Lb[l];
-                    phi.im += Lb[P + l];
+                    phi.re += cre;
+                    phi.im += cim;
                 }
                 if (GRAD) {
                     dphi.re /= (E)s;
@@ -277,30 +313,35 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
             }
             double u = (double)phi.re;
             double gx = (double)dphi.re, gy = -(double)dphi.im;
-            for (int e = wptr[b]; e < wptr[b + 1]; ++e) {
+            for (int e = w0; e < w1; ++e) {
                 const int a = widx[e];
+                __syncthreads();
+                for (int k = lane; k < 2 * P; k += 64) col[k] = Mexp[((int64_t)a * nbatch + bt) * PD + k];
+                __syncthreads();
                 const double ax = G.cx[a], ay = G.cy[a], sa = G.side[G.level[a]];
                 const double dx = px - ax, dy = py - ay, d2 = dx * dx + dy * dy;
-                const E *Ma = Mexp + ((int64_t)a * nbatch + bt) * PD;
                 // iw = s_a / (z - c_a)
                 const C2<E> iw = {(E)(sa * dx / d2), (E)(-sa * dy / d2)};
                 C2<E> ser = {(E)0, (E)0}, dser = {(E)0, (E)0};
+#pragma unroll 4
                 for (int k = P - 1; k >= 1; --k) {
+                    const E cre = col[k], cim = col[P + k];
                     ser = cmul(ser, iw);
-                    ser.re += Ma[k];
-                    ser.im += Ma[P + k];
+                    ser.re += cre;
+                    ser.im += cim;
                     if (GRAD) {
                         dser = cmul(dser, iw);
-                        dser.re += (E)k * Ma[k];
-                        dser.im += (E)k * Ma[P + k];
+                        dser.re += (E)k * cre;
+                        dser.im += (E)k * cim;
                     }
                 }
                 ser = cmul(ser, iw);
-                u += (double)ser.re + (double)Ma[0] * 0.5 * log(d2);
+                const double a0 = (double)col[0];
+                u += (double)ser.re + a0 * 0.5 * vp_log(d2);
                 if (GRAD) {
                     // phi' = (A_0 - sum_k k A_k iw^k) / (z - c)
                     dser = cmul(dser, iw);
-                    double nre = (double)Ma[0] - (double)dser.re, nim = -(double)dser.im;
+                    double nre = a0 - (double)dser.re, nim = -(double)dser.im;
                     // 1/(z - c) = (dx - i dy)/d2
                     double ire = dx / d2, iim = -dy / d2;
                     gx += nre * ire - nim * iim;
@@ -680,6 +721,34 @@ static void launch_sq(hipStream_t s, const TranslateArgs &a, const TM *Ahi, cons
     VP_LAUNCH_CHECK();
 }
 
+template <class TI, class TO, class TM, bool SPLIT, int RB>
+static void launch_split(hipStream_t s, const TranslateArgs &a, const TM *Ahi, const TM *Alo, const TI *in,
+                         TO *out) {
+    constexpr int S = RB * 4;
+    const unsigned blocks = (unsigned)((a.ncols + 15) / 16);
+    hipLaunchKernelGGL((k_translate_split<TI, TO, TM, RB, S, SPLIT>), dim3(blocks), dim3(256), 0, s, a, Ahi, Alo,
+                       in, out);
+    VP_LAUNCH_CHECK();
+}
+
+// M2L: operators split across the waves of a workgroup (overwrite only)
+template <class TI, class TO, class TM, bool SPLIT>
+static void translate_m2l(hipStream_t s, int PD, const TranslateArgs &a, const TM *Ahi, const TM *Alo,
+                          const TI *in, TO *out) {
+    if (a.ncols <= 0) return;
+    switch (PD) {
+        case 16: launch_split<TI, TO, TM, SPLIT, 1>(s, a, Ahi, Alo, in, out); break;
+        case 32: launch_split<TI, TO, TM, SPLIT, 2>(s, a, Ahi, Alo, in, out); break;
+        case 48: launch_split<TI, TO, TM, SPLIT, 3>(s, a, Ahi, Alo, in, out); break;
+        case 64: launch_split<TI, TO, TM, SPLIT, 4>(s, a, Ahi, Alo, in, out); break;
+        case 80: launch_split<TI, TO, TM, SPLIT, 5>(s, a, Ahi, Alo, in, out); break;
+        case 96: launch_split<TI, TO, TM, SPLIT, 6>(s, a, Ahi, Alo, in, out); break;
+        case 112: launch_split<TI, TO, TM, SPLIT, 7>(s, a, Ahi, Alo, in, out); break;
+        case 128: launch_split<TI, TO, TM, SPLIT, 8>(s, a, Ahi, Alo, in, out); break;
+        default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
+    }
+}
+
 template <class TI, class TO, class TM, bool SPLIT, bool ACCUM>
 static void translate_sq(hipStream_t s, int PD, const TranslateArgs &a, const TM *Ahi, const TM *Alo,
                          const TI *in, TO *out) {
@@ -758,7 +827,7 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
     const E *Rm2m = f32 ? (const E *)P->ops.m2m_f32 : (const E *)P->ops.m2m_f64;
     const E *Rl2l = f32 ? (const E *)P->ops.l2l_f32 : (const E *)P->ops.l2l_f64;
-    const size_t lds = sizeof(E) * 2 * 64 * Pn;
+    const size_t lds = sizeof(E) * 2 * 16 * Pn;
     if (T.nlevels < 3) return;  // no box is well separated from another
     P->stage_begin(VP_STAGE_P2M);
     if (tables) {
@@ -790,17 +859,17 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     {
         TranslateArgs a = expansion_args(P, P->m2l_cols, P->n_m2l_boxes, T.v_slot, NOFF, 2 * Pn);
         if (!f32) {
-            translate_sq<double, double, double, false, false>(s, PD, a, P->ops.m2l_f64, nullptr,
-                                                               (const double *)M, (double *)L);
+            translate_m2l<double, double, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const double *)M,
+                                                         (double *)L);
         } else if (P->m2l_mode == VP_M2L_FP32_SPLIT) {
-            translate_sq<float, float, float, true, false>(s, PD, a, P->ops.m2l_f32, P->ops.m2l_f32_lo,
-                                                           (const float *)M, (float *)L);
+            translate_m2l<float, float, float, true>(s, PD, a, P->ops.m2l_f32, P->ops.m2l_f32_lo,
+                                                     (const float *)M, (float *)L);
         } else if (P->m2l_mode == VP_M2L_FP64_MFMA) {
-            translate_sq<float, float, double, false, false>(s, PD, a, P->ops.m2l_f64, nullptr,
-                                                             (const float *)M, (float *)L);
+            translate_m2l<float, float, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const float *)M,
+                                                       (float *)L);
         } else {
-            translate_sq<float, float, float, false, false>(s, PD, a, P->ops.m2l_f32, nullptr,
-                                                            (const float *)M, (float *)L);
+            translate_m2l<float, float, float, false>(s, PD, a, P->ops.m2l_f32, nullptr, (const float *)M,
+                                                      (float *)L);
         }
     }
     P->stage_end(VP_STAGE_M2L);

@@ -165,6 +165,94 @@ __global__ void __launch_bounds__(256) k_translate(TranslateArgs a, const TM *__
     }
 }
 
+// Split-operator variant for the large M2L launch: the four waves of a
+// workgroup share ONE 16-column tile and take every fourth active operator,
+// reading operator fragments straight from L2 (no barriers in the main
+// loop, four times more waves in flight); their partial tiles are summed
+// through LDS in a fixed order at the end.
+template <class TI, class TO, class TM, int RB, int S, bool SPLIT>
+__global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const TM *__restrict__ Ahi,
+                                                         const TM *__restrict__ Alo,
+                                                         const TI *__restrict__ in, TO *__restrict__ out) {
+    typedef Mfma<TM> M;
+    constexpr int AE = RB * S * 64;
+    __shared__ double red[3][RB * 4][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cl = lane & 15, g = lane >> 4;
+    const int col = blockIdx.x * 16 + cl;
+    const bool valid = col < a.ncols;
+    const int box = valid ? a.cols_box[col / a.nbatch] : 0;
+    const int bt = valid ? col % a.nbatch : 0;
+    typename M::acc_t acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = M::zero();
+    int it = 0;  // index among the tile's active operators
+    for (int o = 0; o < a.nops; ++o) {
+        const int src = valid ? a.slots[(int64_t)box * a.nops + o] : -1;
+        if (__ballot(src >= 0) == 0ull) continue;
+        const bool mine = (it & 3) == wave;
+        ++it;
+        if (!mine) continue;
+        TM bv[S];
+        const TI *ip = in + (src >= 0 ? a.in.off(src) + (int64_t)bt * a.in.bstride : 0) + g;
+#pragma unroll
+        for (int s = 0; s < S; ++s) bv[s] = (src >= 0) ? (TM)ip[4 * s] : (TM)0;
+        const TM *Ao = Ahi + (int64_t)o * AE + lane;
+        const TM *Alo_o = SPLIT ? Alo + (int64_t)o * AE + lane : nullptr;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                acc[r] = M::op(Ao[(r * S + s) * 64], bv[s], acc[r]);
+                if (SPLIT) acc[r] = M::op(Alo_o[(r * S + s) * 64], bv[s], acc[r]);
+            }
+        }
+    }
+    // fixed-order sum of the four partial tiles: wave 0 + 1 + 2 + 3
+    if (wave > 0) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[wave - 1][r * 4 + i][lane] = (double)acc[r][i];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    double vals[RB][4];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            vals[r][i] = (((double)acc[r][i] + red[0][r * 4 + i][lane]) + red[1][r * 4 + i][lane]) +
+                         red[2][r * 4 + i][lane];
+    if (a.logrow >= 0) {
+        const int rb2 = a.logrow >> 4, r16 = a.logrow & 15;
+        const int i2 = M::item_of(r16), g2 = M::group_of(r16);
+        double s0 = 0.0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (r == rb2 && i == i2) s0 = vals[r][i];
+        s0 = __shfl(s0, g2 * 16 + cl, 64);
+        if (g == M::group_of(0) && valid) vals[0][M::item_of(0)] += s0 * a.logside[a.level[box]];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (r == rb2 && i == i2 && g == g2) vals[r][i] = 0.0;
+    }
+    if (valid) {
+        TO *op = out + a.out.off(box) + (int64_t)bt * a.out.bstride;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = r * 16 + M::row(i, g);
+                if (row < a.nrows_out) op[row] = (TO)vals[r][i];
+            }
+    }
+}
+
 // Dynamic LDS bytes of a k_translate launch (0 when operators stay in global memory).
 template <class TM, int RB, int S, bool SPLIT>
 constexpr size_t translate_lds_bytes() {
