@@ -726,8 +726,8 @@ static void launch_split(hipStream_t s, const TranslateArgs &a, const TM *Ahi, c
                          TO *out) {
     constexpr int S = RB * 4;
     const unsigned blocks = (unsigned)((a.ncols + 15) / 16);
-    hipLaunchKernelGGL((k_translate_split<TI, TO, TM, RB, S, SPLIT>), dim3(blocks), dim3(256), 0, s, a, Ahi, Alo,
-                       in, out);
+    hipLaunchKernelGGL((k_translate_split<TI, TO, TM, RB, S, SPLIT, false>), dim3(blocks), dim3(256), 0, s, a, Ahi,
+                       Alo, in, out);
     VP_LAUNCH_CHECK();
 }
 
@@ -927,33 +927,29 @@ static void run_p2p(vp_plan_s *P, const PointRoles &R, const int32_t *leaves, in
     }
 }
 
-// Near-field tables of congruent leaves: acc[:, leaf] += sum_o K_{l,o} q[:, nbr_o(leaf)]
+// Near-field tables of congruent leaves: acc[:, leaf] += sum_o K_{l,o} q[:, nbr_o(leaf)],
+// all table levels in one launch (operator index = level block * 9 + offset).
 template <int RB>
 static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     NearTables &N = P->near;
     constexpr int S = RB * 4;
-    constexpr bool LDSA = translate_ldsa<double, RB, S, false>();
-    constexpr size_t lds = LDSA ? translate_lds_bytes<double, RB, S, false>() : 0;
-    const size_t opsz = (size_t)N.npat * N.npat;
-    for (size_t li = 0; li < N.tab_levels.size(); ++li) {
-        TranslateArgs a;
-        a.cols_box = N.tab_cols + N.tab_cols_begin[li];
-        a.ncols = (N.tab_cols_begin[li + 1] - N.tab_cols_begin[li]) * P->nbatch;
-        a.nbatch = P->nbatch;
-        a.slots = N.tab_slot;
-        a.nops = 9;
-        a.in = ColAddr{R.nsrc, 0, R.sb};
-        a.out = ColAddr{R.ntgt, 0, R.tb};
-        a.nrows_out = N.npat;
-        a.logrow = -1;
-        a.level = P->tree.level;
-        a.logside = P->tree.d_logside;
-        if (a.ncols <= 0) continue;
-        hipLaunchKernelGGL((k_translate<double, double, double, RB, S, false, true, LDSA>),
-                           dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a,
-                           N.K + li * 9 * opsz, (const double *)nullptr, P->q, P->acc);
-        VP_LAUNCH_CHECK();
-    }
+    TranslateArgs a;
+    a.cols_box = N.tab_cols;
+    a.ncols = N.tab_cols_begin.back() * P->nbatch;
+    a.nbatch = P->nbatch;
+    a.slots = N.tab_slot;
+    a.nops = 9 * (int)N.tab_levels.size();
+    a.in = ColAddr{R.nsrc, 0, R.sb};
+    a.out = ColAddr{R.ntgt, 0, R.tb};
+    a.nrows_out = N.npat;
+    a.logrow = -1;
+    a.level = P->tree.level;
+    a.logside = P->tree.d_logside;
+    if (a.ncols <= 0) return;
+    hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, true>),
+                       dim3((unsigned)((a.ncols + 15) / 16)), dim3(256), 0, P->stream, a, N.K, (const double *)nullptr,
+                       P->q, P->acc);
+    VP_LAUNCH_CHECK();
 }
 
 static void run_tables(vp_plan_s *P, const PointRoles &R) {

@@ -222,7 +222,20 @@ void build_near_tables(vp_plan_s *P) {
         }
     N.tab_cols_begin.push_back((int)tcols.size());
     N.tab_cols = upload(P, tcols);
-    N.tab_slot = upload(P, tslot);
+    {
+        // one slot row per box spanning all table levels: the 9 slots of the
+        // box's own level block hold its neighbours, every other slot is -1
+        const int nt = (int)N.tab_levels.size();
+        std::vector<int32_t> lvl_block(T.nlevels, -1);
+        for (int li = 0; li < nt; ++li) lvl_block[N.tab_levels[li]] = li;
+        std::vector<int32_t> wide((size_t)nbox * 9 * std::max(nt, 1), -1);
+        for (int b = 0; b < nbox; ++b) {
+            const int li = lvl_block[lev[b]];
+            if (li < 0) continue;
+            for (int o = 0; o < 9; ++o) wide[((size_t)b * nt + li) * 9 + o] = tslot[(size_t)b * 9 + o];
+        }
+        N.tab_slot = upload(P, wide);
+    }
 
     if (N.active) {
         const int np = npat;

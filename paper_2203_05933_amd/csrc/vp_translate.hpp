@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) k_translate(TranslateArgs a, const TM *__
 // reading operator fragments straight from L2 (no barriers in the main
 // loop, four times more waves in flight); their partial tiles are summed
 // through LDS in a fixed order at the end.
-template <class TI, class TO, class TM, int RB, int S, bool SPLIT>
+template <class TI, class TO, class TM, int RB, int S, bool SPLIT, bool ACCUM>
 __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const TM *__restrict__ Ahi,
                                                          const TM *__restrict__ Alo,
                                                          const TI *__restrict__ in, TO *__restrict__ out) {
@@ -248,7 +248,10 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = r * 16 + M::row(i, g);
-                if (row < a.nrows_out) op[row] = (TO)vals[r][i];
+                if (row < a.nrows_out) {
+                    if (ACCUM) op[row] += (TO)vals[r][i];
+                    else op[row] = (TO)vals[r][i];
+                }
             }
     }
 }
