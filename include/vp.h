@@ -54,7 +54,16 @@ typedef enum {
 } vp_status;
 
 enum { VP_FP64 = 0, VP_FP32_BULK = 1 };
-enum { VP_M2L_AUTO = 0, VP_M2L_FP64_MFMA = 1, VP_M2L_FP32_MFMA = 2, VP_M2L_FP32_SPLIT = 3 };
+enum {
+    VP_M2L_AUTO = 0,
+    VP_M2L_FP64_MFMA = 1,   /* one real 2P x 2P operator per interaction offset, FP64 matrix cores */
+    VP_M2L_FP32_MFMA = 2,   /* the same in FP32 (VP_FP32_BULK only) */
+    VP_M2L_FP32_SPLIT = 3,  /* the same with hi/lo FP32 products (VP_FP32_BULK only) */
+    VP_M2L_FP64_SCALED = 4, /* diagonally scaled form: complex scalings by powers of the
+                               offset around one real P x P binomial matrix shared by all
+                               offsets, FP64 matrix cores */
+    VP_M2L_FP32_SCALED = 5  /* the scaled form in FP32 (VP_FP32_BULK only) */
+};
 enum { VP_P2P_AUTO = 0, VP_P2P_PAIRWISE = 1, VP_P2P_TABLES = 2 };
 
 typedef struct {
@@ -67,9 +76,9 @@ typedef struct {
                           expansion stages (P2M, M2M, M2L, L2L, L2P, M2P, P2L)
                           in float32; charges, near field, translation
                           operator set-up and final accumulation in float64 */
-    int32_t m2l_mode;  /* VP_M2L_*; AUTO = FP64 MFMA for VP_FP64, FP32 MFMA
-                          for VP_FP32_BULK.  FP32_SPLIT forms T_hi M_hi +
-                          T_hi M_lo + T_lo M_hi with FP32 MFMA (VP_FP32_BULK only) */
+    int32_t m2l_mode;  /* VP_M2L_*; AUTO = FP64_SCALED for VP_FP64,
+                          FP32_SCALED for VP_FP32_BULK.  FP32_SPLIT forms
+                          T_hi M_hi + T_hi M_lo + T_lo M_hi with FP32 MFMA */
     int32_t p2p_mode;  /* VP_P2P_*; AUTO uses precomputed near-field tables on
                           leaves whose nodes are congruent copies of one
                           pattern (uniform box grids) and the pairwise kernel
@@ -188,7 +197,9 @@ vp_status vp_get_array(vp_plan_t plan, int32_t which, void *out, int64_t *count)
  */
 enum {
     VP_STAGE_CHARGE = 0, VP_STAGE_P2M = 1, VP_STAGE_M2M = 2, VP_STAGE_M2L = 3, VP_STAGE_P2L = 4,
-    VP_STAGE_L2L = 5, VP_STAGE_P2P = 6, VP_STAGE_FAR = 7, VP_STAGE_FINISH = 8, VP_NSTAGES = 9
+    VP_STAGE_L2L = 5, VP_STAGE_P2P = 6, VP_STAGE_FAR = 7, VP_STAGE_FINISH = 8,
+    VP_STAGE_TABLES = 9, /* near-field tables of congruent leaves (P2P holds the pairwise kernel) */
+    VP_NSTAGES = 10
 };
 vp_status vp_set_timing(vp_plan_t plan, int32_t enable);
 vp_status vp_get_timing(vp_plan_t plan, double *ms, int64_t *nevals);

@@ -135,8 +135,9 @@ static void validate_plan_args(const double *x, const double *y, const double *w
     if (o.max_leaf < 1 || o.max_leaf > 256) bad("max_leaf must be in 1..256");
     if (o.nbatch < 1 || o.nbatch > vp::MAX_BATCH) bad("nbatch must be in 1..64");
     if (o.precision != VP_FP64 && o.precision != VP_FP32_BULK) bad("unknown precision");
-    if (o.m2l_mode < 0 || o.m2l_mode > 3) bad("unknown m2l_mode");
-    if (o.precision == VP_FP64 && (o.m2l_mode == VP_M2L_FP32_MFMA || o.m2l_mode == VP_M2L_FP32_SPLIT))
+    if (o.m2l_mode < 0 || o.m2l_mode > 5) bad("unknown m2l_mode");
+    if (o.precision == VP_FP64 && (o.m2l_mode == VP_M2L_FP32_MFMA || o.m2l_mode == VP_M2L_FP32_SPLIT ||
+                                   o.m2l_mode == VP_M2L_FP32_SCALED))
         bad("FP32 M2L modes need precision VP_FP32_BULK");
     if (o.p2p_mode < 0 || o.p2p_mode > 2) bad("unknown p2p_mode");
     if (o.max_level < 0 || o.max_level > vp::LBITS) bad("max_level must be in 0..30");
@@ -181,7 +182,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->PD = ((2 * P->P + 1 + 15) / 16) * 16;
         if (P->PD > 128) throw Error(VP_EUNSUPPORTED, "order too large (2(p+1)+1 must be <= 128)");
         P->fp32 = (o.precision == VP_FP32_BULK);
-        P->m2l_mode = o.m2l_mode == VP_M2L_AUTO ? (P->fp32 ? VP_M2L_FP32_MFMA : VP_M2L_FP64_MFMA) : o.m2l_mode;
+        P->m2l_mode = o.m2l_mode == VP_M2L_AUTO ? (P->fp32 ? VP_M2L_FP32_SCALED : VP_M2L_FP64_SCALED) : o.m2l_mode;
         P->stream = static_cast<hipStream_t>(o.stream);
         VP_HIP(hipGetDevice(&P->device));
         P->err_flag = P->mem.alloc<int32_t>(1);

@@ -20,6 +20,7 @@
 
 #include "vp_internal.hpp"
 #include "vp_translate.hpp"
+#include "vp_m2l_scaled.hpp"
 
 namespace vp {
 
@@ -571,12 +572,23 @@ __global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, int b
         double part[NBG];
 #pragma unroll
         for (int k = 0; k < NBG; ++k) part[k] = 0.0;
-        for (int64_t pq = p0 + l16; pq < p1; pq += 16) {
-            const double v = valv[pq];
-            const int64_t c = rs >= 0 ? (int64_t)rs + (pq - p0) : (int64_t)colv[pq];
+        // four independent 16-wide slices in flight per pass (64 entries)
+        for (int64_t pb = p0; pb < p1; pb += 64) {
+            double v[4];
+            int64_t c[4];
+            bool in[4];
 #pragma unroll
-            for (int k = 0; k < NBG; ++k)
-                if (k < nbg) part[k] += v * f[(int64_t)(bt0 + k) * flen + c];
+            for (int u = 0; u < 4; ++u) {
+                const int64_t pq = pb + l16 + 16 * u;
+                in[u] = pq < p1;
+                v[u] = in[u] ? valv[pq] : 0.0;
+                c[u] = !in[u] ? 0 : (rs >= 0 ? (int64_t)rs + (pq - p0) : (int64_t)colv[pq]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < NBG; ++k)
+                    if (k < nbg && in[u]) part[k] += v[u] * f[(int64_t)(bt0 + k) * flen + c[u]];
         }
 #pragma unroll
         for (int k = 0; k < NBG; ++k) {
@@ -749,6 +761,21 @@ static void translate_m2l(hipStream_t s, int PD, const TranslateArgs &a, const T
     }
 }
 
+template <class TI, class TO, class TM>
+static void m2l_scaled(hipStream_t s, int PQ, const M2LScaledArgs &a, const TM *Q, const TM *tin, const TM *tout,
+                       const double *logt, const TI *in, TO *out) {
+    if (a.ncols <= 0) return;
+    const unsigned blocks = (unsigned)((a.ncols + 15) / 16);
+    switch (PQ) {
+        case 16: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 1>), dim3(blocks), dim3(256), 0, s, a, Q, tin, tout, logt, in, out); break;
+        case 32: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 2>), dim3(blocks), dim3(256), 0, s, a, Q, tin, tout, logt, in, out); break;
+        case 48: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 3>), dim3(blocks), dim3(256), 0, s, a, Q, tin, tout, logt, in, out); break;
+        case 64: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 4>), dim3(blocks), dim3(256), 0, s, a, Q, tin, tout, logt, in, out); break;
+        default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
+    }
+    VP_LAUNCH_CHECK();
+}
+
 template <class TI, class TO, class TM, bool SPLIT, bool ACCUM>
 static void translate_sq(hipStream_t s, int PD, const TranslateArgs &a, const TM *Ahi, const TM *Alo,
                          const TI *in, TO *out) {
@@ -858,7 +885,29 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     P->stage_begin(VP_STAGE_M2L);
     {
         TranslateArgs a = expansion_args(P, P->m2l_cols, P->n_m2l_boxes, T.v_slot, NOFF, 2 * Pn);
-        if (!f32) {
+        if (P->m2l_mode == VP_M2L_FP64_SCALED || P->m2l_mode == VP_M2L_FP32_SCALED) {
+            M2LScaledArgs sa;
+            sa.cols_box = P->m2l_cols;
+            sa.ncols = a.ncols;
+            sa.nbatch = nb;
+            sa.slots = T.v_slot;
+            sa.P = Pn;
+            sa.in = a.in;
+            sa.out = a.out;
+            sa.PD = PD;
+            sa.level = T.level;
+            sa.logside = T.d_logside;
+            const Operators &O = P->ops;
+            if (!f32)
+                m2l_scaled<double, double, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
+                                                   (const double *)M, (double *)L);
+            else if (P->m2l_mode == VP_M2L_FP32_SCALED)
+                m2l_scaled<float, float, float>(s, O.PQ, sa, O.m2l_q32, O.m2l_tin32, O.m2l_tout32, O.m2l_logt,
+                                                (const float *)M, (float *)L);
+            else
+                m2l_scaled<float, float, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
+                                                 (const float *)M, (float *)L);
+        } else if (!f32) {
             translate_m2l<double, double, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const double *)M,
                                                          (double *)L);
         } else if (P->m2l_mode == VP_M2L_FP32_SPLIT) {
@@ -1011,18 +1060,20 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, bool p2m) {
     VP_LAUNCH_CHECK();
 }
 
+bool pattern_op_supported(int npat, int PD) {
+    return (npat == 16 || npat == 32 || npat == 64) && PD >= 16 && PD <= 64 && PD % 16 == 0;
+}
+
 template <class E>
 static void run_pattern_op(vp_plan_s *P, const PointRoles &R, bool p2m) {
     const int key = P->near.npat / 16 * 16 + P->PD / 16;
     switch (key) {
-        case 4 * 16 + 4: launch_pattern_ops<E, 4, 4>(P, R, p2m); break;   // 64 points, p <= 31
-        case 4 * 16 + 2: launch_pattern_ops<E, 4, 2>(P, R, p2m); break;   // 64 points, p <= 15
-        case 4 * 16 + 3: launch_pattern_ops<E, 4, 3>(P, R, p2m); break;
-        case 4 * 16 + 1: launch_pattern_ops<E, 4, 1>(P, R, p2m); break;
-        case 1 * 16 + 4: launch_pattern_ops<E, 1, 4>(P, R, p2m); break;   // 16 points
-        case 1 * 16 + 2: launch_pattern_ops<E, 1, 2>(P, R, p2m); break;
-        case 2 * 16 + 4: launch_pattern_ops<E, 2, 4>(P, R, p2m); break;   // 32 points
-        case 2 * 16 + 2: launch_pattern_ops<E, 2, 2>(P, R, p2m); break;
+#define VP_PAT(NP, NE) \
+    case NP * 16 + NE: launch_pattern_ops<E, NP, NE>(P, R, p2m); break;
+        VP_PAT(1, 1) VP_PAT(1, 2) VP_PAT(1, 3) VP_PAT(1, 4)
+        VP_PAT(2, 1) VP_PAT(2, 2) VP_PAT(2, 3) VP_PAT(2, 4)
+        VP_PAT(4, 1) VP_PAT(4, 2) VP_PAT(4, 3) VP_PAT(4, 4)
+#undef VP_PAT
         default: throw Error(VP_EUNSUPPORTED, "pattern/order combination without a pattern operator");
     }
 }
@@ -1057,12 +1108,16 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
     const bool tables = N.active && !grad;
     if (P->fp32) run_expansions<float>(P, R, G, tables);
     else run_expansions<double>(P, R, G, tables);
+    if (tables) {
+        P->stage_begin(VP_STAGE_TABLES);
+        fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
+        run_tables(P, R);
+        P->stage_end(VP_STAGE_TABLES);
+    }
     P->stage_begin(VP_STAGE_P2P);
     if (grad) {
         run_p2p<true, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0], P->acc);
     } else if (tables) {
-        fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
-        run_tables(P, R);
         run_p2p<false, true>(P, R, N.rest_leaves, N.n_rest_leaves, N.pair_uptr, N.pair_uidx, P->acc);
     } else {
         run_p2p<false, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0], P->acc);

@@ -146,6 +146,12 @@ struct Operators {
     float *m2m_t32 = nullptr, *l2l_t32 = nullptr;
     double *inv_k = nullptr;  // 1/k, k = 0..P-1 (0 for k = 0)
     float *inv_k_f32 = nullptr;
+    // M2L in diagonally scaled form: one real matrix Q (A-fragment order,
+    // PQ = roundup(P, 16) rows and columns), per-offset complex scalings
+    // tin[o][k] = (-t)^-k and tout[o][l] = t^-l ([NOFF][PQ][2]), log(-t)
+    int PQ = 0;
+    double *m2l_q64 = nullptr, *m2l_tin64 = nullptr, *m2l_tout64 = nullptr, *m2l_logt = nullptr;
+    float *m2l_q32 = nullptr, *m2l_tin32 = nullptr, *m2l_tout32 = nullptr;
 };
 
 // Congruent-leaf path (uniform box grids): near-field tables, P2M/L2P
@@ -266,6 +272,8 @@ void build_operators(vp_plan_s *P);
 void build_near_tables(vp_plan_s *P);  // vp_near.hip
 // vp_fmm.hip
 void build_schedules(vp_plan_s *P);
+// congruent-leaf operators exist for this pattern size and expansion size
+bool pattern_op_supported(int npat, int PD);
 void run_fmm(vp_plan_s *P, bool adjoint, bool grad);
 void prepare_charges(vp_plan_s *P, const double *f, bool adjoint);
 void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint);

@@ -92,7 +92,7 @@ void build_near_tables(vp_plan_s *P) {
         for (int b : leaves) hist[se[b] - sb[b]]++;
         int best = 0, bestc = 0;
         for (auto &kv : hist)
-            if (kv.first >= 16 && kv.first <= 128 && kv.first % 16 == 0 && kv.second > bestc) {
+            if (pattern_op_supported(kv.first, P->PD) && kv.second > bestc) {
                 best = kv.first;
                 bestc = kv.second;
             }

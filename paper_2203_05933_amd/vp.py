@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libvp.so")
 
 VP_OK, VP_EINVAL, VP_ENOMEM, VP_EDEVICE, VP_EUNSUPPORTED, VP_EINTERNAL = range(6)
 VP_FP64, VP_FP32_BULK = 0, 1
-M2L_MODES = {"auto": 0, "fp64": 1, "fp32": 2, "split": 3}
+M2L_MODES = {"auto": 0, "fp64": 1, "fp32": 2, "split": 3, "fp64_scaled": 4, "fp32_scaled": 5}
 P2P_MODES = {"auto": 0, "pairwise": 1, "tables": 2}
 ARR = {
     "src_perm": 0, "tgt_perm": 1, "box": 2, "level_begin": 3,
@@ -34,7 +34,7 @@ _ARR_DTYPE = {0: np.int32, 1: np.int32, 2: np.int32, 3: np.int32, 4: np.int32, 5
 EXPORTS = ("vp_default_options", "vp_plan", "vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets",
            "vp_set_stream", "vp_destroy", "vp_last_error", "vp_get_info", "vp_get_array",
            "vp_set_timing", "vp_get_timing")
-STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish")
+STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish", "tables")
 
 
 class VPError(RuntimeError):

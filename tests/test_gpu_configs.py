@@ -54,17 +54,18 @@ def c2_ref(c2):
     return direct.evaluate(c2.x, c2.y, c2.w, c2.f, c2.rowptr, c2.col, c2.val, tidx=c2.sample)
 
 
-def test_config2_fp64(c2, c2_ref):
+@pytest.mark.parametrize("mode", ["fp64_scaled", "fp64"])
+def test_config2_fp64(c2, c2_ref, mode):
     vp = _vp()
-    plan = _plan(vp, c2, order=30)
+    plan = _plan(vp, c2, order=30, m2l_mode=mode)
     u = _host(plan.eval(_dev(c2.f)))[:, c2.sample]
     err = relinf(u, c2_ref)
-    print(f"config2 fp64 p=30: rel_inf={err:.3e}")
+    print(f"config2 fp64 p=30 m2l={mode}: rel_inf={err:.3e}")
     assert err <= TOL64
     plan.close()
 
 
-@pytest.mark.parametrize("mode", ["fp32", "split", "fp64"])
+@pytest.mark.parametrize("mode", ["fp32", "split", "fp64", "fp32_scaled"])
 def test_config2_fp32_bulk(c2, c2_ref, mode):
     vp = _vp()
     plan = _plan(vp, c2, order=14, precision="fp32", m2l_mode=mode)

@@ -224,7 +224,7 @@ def test_batched_densities(c0):
     plan.close()
 
 
-@pytest.mark.parametrize("mode", ["fp32", "split", "fp64"])
+@pytest.mark.parametrize("mode", ["fp32", "split", "fp64", "fp32_scaled", "fp64_scaled"])
 def test_fp32_bulk_form(c0, mode):
     vp = _vp()
     plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=14, precision="fp32",
@@ -235,6 +235,25 @@ def test_fp32_bulk_form(c0, mode):
     print(f"fp32-bulk m2l={mode} p=14 rel_inf={err:.3e}")
     assert err <= TOL32
     plan.close()
+
+
+@pytest.mark.parametrize("order", [4, 15, 30, 47, 60])
+def test_m2l_scaled_matches_per_offset_operators(c0, order):
+    """The diagonally scaled M2L (complex scalings by powers of the offset
+    around one real binomial matrix) gives the same local expansions and
+    potentials as the per-offset real operators at every expansion size
+    (16, 32, 48 and 64 padded rows)."""
+    vp = _vp()
+    res = []
+    for mode in ("fp64", "fp64_scaled"):
+        plan = vp.Plan(c0.x, c0.y, c0.w, order=order, m2l_mode=mode, root=c0.root)
+        u = _host(plan.eval(_dev(c0.f)))
+        res.append((plan.get_array("local"), u))
+        plan.close()
+    (l1, u1), (l2, u2) = res
+    print(f"order {order}: locals {relinf(l2, l1):.2e}, potentials {relinf(u2, u1):.2e}")
+    assert relinf(l2, l1) <= 1e-13
+    assert relinf(u2, u1) <= 1e-13
 
 
 @pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65])
