@@ -214,14 +214,16 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->q = P->mem.alloc<double>((size_t)P->nbatch * len);
         P->acc = P->mem.alloc<double>((size_t)P->nbatch * 2 * len);
         const size_t esz = P->fp32 ? 4 : 8;
+        // multipoles also for the virtual children of X-list sources
         const size_t ecount = (size_t)P->tree.nbox * P->nbatch * P->PD;
-        P->Mexp = P->mem.alloc<unsigned char>(ecount * esz);
+        const size_t mcount = (size_t)(P->tree.nbox + 4 * (size_t)P->n_vleaf) * P->nbatch * P->PD;
+        P->Mexp = P->mem.alloc<unsigned char>(mcount * esz);
         P->Lexp = P->mem.alloc<unsigned char>(ecount * esz);
         if (P->fp32) {
-            vp::fill_f32((float *)P->Mexp, 0.f, (int64_t)ecount, P->stream);
+            vp::fill_f32((float *)P->Mexp, 0.f, (int64_t)mcount, P->stream);
             vp::fill_f32((float *)P->Lexp, 0.f, (int64_t)ecount, P->stream);
         } else {
-            vp::fill_f64((double *)P->Mexp, 0.0, (int64_t)ecount, P->stream);
+            vp::fill_f64((double *)P->Mexp, 0.0, (int64_t)mcount, P->stream);
             vp::fill_f64((double *)P->Lexp, 0.0, (int64_t)ecount, P->stream);
         }
         VP_HIP(hipStreamSynchronize(P->stream));

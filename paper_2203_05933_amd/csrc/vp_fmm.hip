@@ -114,20 +114,11 @@ __device__ inline void fill_power_rows(C2<E> w, E k0re, bool valid, int j, int g
 // W[j][0] = 1 and W[j][k] = -(1/k) ((z_j - c)/s)^k.
 // ----------------------------------------------------------------------------
 template <class E>
-__global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_t *__restrict__ boxes,
-                                            int nboxes, const double *__restrict__ q, int nbatch,
-                                            int P, int PD, const E *__restrict__ invk,
-                                            E *__restrict__ Mexp) {
-    extern __shared__ unsigned char smem[];
-    E *Wre = reinterpret_cast<E *>(smem);   // [16][P]
-    E *Wim = Wre + 16 * P;                  // [16][P]
-    __shared__ E sq[16][16];                // charges of the chunk [density][source]
+__device__ inline void p2m_range(const PointRoles &R, int s0, int s1, double cx, double cy, double inv_s,
+                                 const double *__restrict__ q, int nbatch, int P, int PD,
+                                 const E *__restrict__ invk, E *__restrict__ out, E *Wre, E *Wim,
+                                 E (*sq)[16]) {
     const int lane = threadIdx.x, j = lane & 15, g = lane >> 4;
-    const int b = boxes[blockIdx.x];
-    const int s0 = R.sb[b], s1 = R.se[b];
-    const double cx = G.cx[b], cy = G.cy[b];
-    const double inv_s = 1.0 / G.side[G.level[b]];
-    E *out = Mexp + (int64_t)b * nbatch * PD;
     for (int bt0 = 0; bt0 < nbatch; bt0 += 16) {
         const int nbg = min(16, nbatch - bt0);
         E acc[2][16];
@@ -141,19 +132,68 @@ __global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_
             fill_power_rows<E>(w, (E)1, v, j, g, P, invk, Wre, Wim);
             for (int bb = g; bb < nbg; bb += 4) sq[bb][j] = v ? (E)q[(int64_t)(bt0 + bb) * R.nsrc + jj] : (E)0;
             __syncthreads();
-            for (int r = lane, ri = 0; r < 2 * P; r += 64, ++ri) {
-                const int k = r < P ? r : r - P;
-                const E *Wc = r < P ? Wre : Wim;
-                for (int bb = 0; bb < nbg; ++bb) {
-                    E t = (E)0;
-                    for (int jx = 0; jx < cnt; ++jx) t += sq[bb][jx] * Wc[jx * P + k];
-                    acc[ri][bb] += t;
+            // static register indexing (rows r = lane + 64 ri, densities bb)
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri) {
+                const int r = lane + 64 * ri;
+                if (r < 2 * P) {
+                    const int k = r < P ? r : r - P;
+                    const E *Wc = r < P ? Wre : Wim;
+#pragma unroll
+                    for (int bb = 0; bb < 16; ++bb) {
+                        if (bb < nbg) {
+                            E t = (E)0;
+                            for (int jx = 0; jx < cnt; ++jx) t += sq[bb][jx] * Wc[jx * P + k];
+                            acc[ri][bb] += t;
+                        }
+                    }
                 }
             }
         }
-        for (int r = lane, ri = 0; r < PD; r += 64, ++ri)
-            for (int bb = 0; bb < nbg; ++bb) out[(bt0 + bb) * PD + r] = (r < 2 * P) ? acc[ri][bb] : (E)0;
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri) {
+            const int r = lane + 64 * ri;
+            if (r < PD) {
+#pragma unroll
+                for (int bb = 0; bb < 16; ++bb)
+                    if (bb < nbg) out[(bt0 + bb) * PD + r] = (r < 2 * P) ? acc[ri][bb] : (E)0;
+            }
+        }
     }
+}
+
+template <class E>
+__global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_t *__restrict__ boxes,
+                                            int nboxes, const double *__restrict__ q, int nbatch,
+                                            int P, int PD, const E *__restrict__ invk,
+                                            E *__restrict__ Mexp) {
+    extern __shared__ unsigned char smem[];
+    E *Wre = reinterpret_cast<E *>(smem);   // [16][P]
+    E *Wim = Wre + 16 * P;                  // [16][P]
+    __shared__ E sq[16][16];                // charges of the chunk [density][source]
+    const int b = boxes[blockIdx.x];
+    p2m_range<E>(R, R.sb[b], R.se[b], G.cx[b], G.cy[b], 1.0 / G.side[G.level[b]], q, nbatch, P, PD, invk,
+                 Mexp + (int64_t)b * nbatch * PD, Wre, Wim, sq);
+}
+
+// P2M of the four virtual children of an X-list source leaf (block 4 v + quadrant):
+// the quadrant's sources, about the quadrant centre, at the children's scale.
+template <class E>
+__global__ void __launch_bounds__(64) k_p2m_quad(PointRoles R, BoxGeo G, const int32_t *__restrict__ vleaf,
+                                                 const int32_t *__restrict__ vsplit, int nbox,
+                                                 const double *__restrict__ q, int nbatch, int P, int PD,
+                                                 const E *__restrict__ invk, E *__restrict__ Mexp) {
+    extern __shared__ unsigned char smem[];
+    E *Wre = reinterpret_cast<E *>(smem);
+    E *Wim = Wre + 16 * P;
+    __shared__ E sq[16][16];
+    const int v = blockIdx.x >> 2, qd = blockIdx.x & 3;
+    const int a = vleaf[v];
+    const double h = G.side[G.level[a]];
+    const double cx = G.cx[a] + ((qd & 1) ? 0.25 : -0.25) * h;
+    const double cy = G.cy[a] + ((qd >> 1) ? 0.25 : -0.25) * h;
+    p2m_range<E>(R, vsplit[5 * v + qd], vsplit[5 * v + qd + 1], cx, cy, 2.0 / h, q, nbatch, P, PD, invk,
+                 Mexp + (int64_t)(nbox + blockIdx.x) * nbatch * PD, Wre, Wim, sq);
 }
 
 // ----------------------------------------------------------------------------
@@ -244,19 +284,33 @@ __global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_
                 fill_power_rows<E>(iw, (E)(0.5 * vp_log(d2)), v, j, g, P, invk, Wre, Wim);
                 for (int bb = g; bb < nb; bb += 4) sq[bb][j] = v ? (E)q[(int64_t)(bt0 + bb) * R.nsrc + jj] : (E)0;
                 __syncthreads();
-                for (int r = lane, ri = 0; r < 2 * P; r += 64, ++ri) {
-                    const int k = r < P ? r : r - P;
-                    const E *Wc = r < P ? Wre : Wim;
-                    for (int bb = 0; bb < nb; ++bb) {
-                        E t = (E)0;
-                        for (int jx = 0; jx < cnt; ++jx) t += sq[bb][jx] * Wc[jx * P + k];
-                        acc[ri][bb] += t;
+#pragma unroll
+                for (int ri = 0; ri < 2; ++ri) {
+                    const int r = lane + 64 * ri;
+                    if (r < 2 * P) {
+                        const int k = r < P ? r : r - P;
+                        const E *Wc = r < P ? Wre : Wim;
+#pragma unroll
+                        for (int bb = 0; bb < 16; ++bb) {
+                            if (bb < nb) {
+                                E t = (E)0;
+                                for (int jx = 0; jx < cnt; ++jx) t += sq[bb][jx] * Wc[jx * P + k];
+                                acc[ri][bb] += t;
+                            }
+                        }
                     }
                 }
             }
         }
-        for (int r = lane, ri = 0; r < 2 * P; r += 64, ++ri)
-            for (int bb = 0; bb < nb; ++bb) Lo[(bt0 + bb) * PD + r] += acc[ri][bb];
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri) {
+            const int r = lane + 64 * ri;
+            if (r < 2 * P) {
+#pragma unroll
+                for (int bb = 0; bb < 16; ++bb)
+                    if (bb < nb) Lo[(bt0 + bb) * PD + r] += acc[ri][bb];
+            }
+        }
     }
 }
 
@@ -706,11 +760,82 @@ void build_schedules(vp_plan_s *P) {
     std::vector<int32_t> p2m, xb, wl;
     for (int b = 0; b < nbox; ++b) {
         if (nch[b] == 0 && lev[b] >= 2) p2m.push_back(b);
-        if (xp[b + 1] > xp[b]) xb.push_back(b);
         if (nch[b] == 0 && wp[b + 1] > wp[b]) wl.push_back(b);
     }
     P->n_p2m = (int)p2m.size();
     P->p2m_leaves = up(p2m);
+
+    // X list, one level apart: the source leaf a (level l-1) splits into four
+    // virtual children on the target's level l.  None of them is adjacent to
+    // the target b (a is not), and they lie in b's 7x7 neighbourhood (b's
+    // parent is adjacent to a), i.e. at outer offsets where the target has
+    // no V-list box (a is a leaf, so no real box exists there).  Their
+    // multipoles (P2M over the points of each quadrant) enter the target's
+    // M2L slots; entries further apart stay on the P2L kernel.
+    const int64_t nx = T.llen[3];
+    std::vector<int32_t> xidx(nx), vslot((size_t)nbox * NOFF), sb(nbox), se(nbox), tb(nbox), te(nbox);
+    std::vector<uint64_t> skey(P->n), tkey(P->m);
+    if (nx) VP_HIP(hipMemcpyAsync(xidx.data(), T.lidx[3], 4 * nx, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(vslot.data(), T.v_slot, 4 * vslot.size(), hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(sb.data(), T.sb, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(se.data(), T.se, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(tb.data(), T.tb, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(te.data(), T.te, 4 * nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(skey.data(), P->skeys, 8 * P->n, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(tkey.data(), P->tkeys, 8 * P->m, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> vindex(nbox, -1), vleaf, vsplit_s, vsplit_t, xr_ptr(1, 0), xr_idx;
+    // quadrant boundaries of a leaf's sorted points (Morton order keeps each
+    // quadrant contiguous): split[0..4]
+    auto splits = [&](const std::vector<uint64_t> &key, int b0, int b1, int la, std::vector<int32_t> &out) {
+        const int shift = 2 * (LBITS - la - 1);
+        out.push_back(b0);
+        for (int qd = 1; qd < 4; ++qd) {
+            int lo = b0, hi = b1;  // first index with quadrant >= qd
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((int)((key[mid] >> shift) & 3) < qd) lo = mid + 1;
+                else hi = mid;
+            }
+            out.push_back(lo);
+        }
+        out.push_back(b1);
+    };
+    for (int b = 0; b < nbox; ++b) {
+        for (int e = xp[b]; e < xp[b + 1]; ++e) {
+            const int a = xidx[e];
+            if (lev[b] - lev[a] != 1 || lev[a] + 1 > LBITS) {
+                xr_idx.push_back(a);
+                continue;
+            }
+            if (vindex[a] < 0) {
+                vindex[a] = (int)vleaf.size();
+                vleaf.push_back(a);
+                splits(skey, sb[a], se[a], lev[a], vsplit_s);
+                splits(tkey, tb[a], te[a], lev[a], vsplit_t);
+            }
+            const int va = vindex[a];
+            for (int qd = 0; qd < 4; ++qd) {
+                const int ns = vsplit_s[5 * va + qd + 1] - vsplit_s[5 * va + qd];
+                const int nt = vsplit_t[5 * va + qd + 1] - vsplit_t[5 * va + qd];
+                if (ns + nt == 0) continue;
+                const int dx = 2 * ix[a] + (qd & 1) - ix[b], dy = 2 * iy[a] + (qd >> 1) - iy[b];
+                const int code = offset_code(dx, dy);
+                if (code < 0 || vslot[(size_t)b * NOFF + code] >= 0)
+                    throw Error(VP_EINTERNAL, "X-list entry outside the interaction offsets");
+                vslot[(size_t)b * NOFF + code] = nbox + 4 * va + qd;
+            }
+        }
+        xr_ptr.push_back((int32_t)xr_idx.size());
+        if (xr_ptr[b + 1] > xr_ptr[b]) xb.push_back(b);
+    }
+    P->n_vleaf = (int)vleaf.size();
+    P->vleaf = up(vleaf);
+    P->vsplit_s = up(vsplit_s);
+    P->vsplit_t = up(vsplit_t);
+    VP_HIP(hipMemcpyAsync(T.v_slot, vslot.data(), 4 * vslot.size(), hipMemcpyHostToDevice, s));
+    P->xr_ptr = up(xr_ptr);
+    P->xr_idx = up(xr_idx);
     P->n_x_boxes = (int)xb.size();
     P->x_boxes = up(xb);
     P->n_w_leaves = (int)wl.size();
@@ -869,6 +994,13 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
                            P->q, nb, Pn, PD, invk, M);
         VP_LAUNCH_CHECK();
     }
+    if (P->n_vleaf > 0) {
+        // virtual children of X-list sources (their points in this evaluation's source role)
+        const int32_t *split = R.sb == T.sb ? P->vsplit_s : P->vsplit_t;
+        hipLaunchKernelGGL(k_p2m_quad<E>, dim3(4 * P->n_vleaf), dim3(64), lds, s, R, G, P->vleaf, split, T.nbox,
+                           P->q, nb, Pn, PD, invk, M);
+        VP_LAUNCH_CHECK();
+    }
     P->stage_end(VP_STAGE_P2M);
     P->stage_begin(VP_STAGE_M2M);
     const E *RTm = f32 ? (const E *)P->ops.m2m_t32 : (const E *)P->ops.m2m_t64;
@@ -924,8 +1056,8 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     P->stage_end(VP_STAGE_M2L);
     P->stage_begin(VP_STAGE_P2L);
     if (P->n_x_boxes > 0) {
-        hipLaunchKernelGGL(k_p2l<E>, dim3(P->n_x_boxes), dim3(64), lds, s, R, G, P->x_boxes, T.lptr[3],
-                           T.lidx[3], P->q, nb, Pn, PD, invk, L);
+        hipLaunchKernelGGL(k_p2l<E>, dim3(P->n_x_boxes), dim3(64), lds, s, R, G, P->x_boxes, P->xr_ptr,
+                           P->xr_idx, P->q, nb, Pn, PD, invk, L);
         VP_LAUNCH_CHECK();
     }
     P->stage_end(VP_STAGE_P2L);

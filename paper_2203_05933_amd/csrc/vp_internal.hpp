@@ -227,7 +227,7 @@ struct vp_plan_s {
     // evaluation workspace
     double *q = nullptr;     // [nbatch][max(n,m)] charges, sorted order
     double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order
-    void *Mexp = nullptr;    // [nbox][nbatch][PD] (double or float)
+    void *Mexp = nullptr;    // [nbox + 4 n_vleaf][nbatch][PD] (double or float)
     void *Lexp = nullptr;
     int32_t *m2l_cols = nullptr;  // boxes of levels >= 2, grouped by child class
     int32_t *child_slot = nullptr;   // [nbox][4] child in each quadrant or -1
@@ -239,8 +239,16 @@ struct vp_plan_s {
     std::vector<int> m2m_begin;
     int32_t *p2m_leaves = nullptr;   // leaves at level >= 2 with sources
     int n_p2m = 0;
-    int32_t *x_boxes = nullptr;      // boxes with a non-empty X list
+    int32_t *x_boxes = nullptr;      // boxes whose X list keeps entries for the P2L kernel
     int n_x_boxes = 0;
+    int32_t *xr_ptr = nullptr;       // those X entries (two or more levels apart), CSR over boxes
+    int32_t *xr_idx = nullptr;
+    // X-list source leaves one level above their targets: four virtual
+    // children each (expansion columns nbox + 4 v + quadrant), with the
+    // quadrant boundaries [5] of their sorted sources and targets
+    int n_vleaf = 0;
+    int32_t *vleaf = nullptr;
+    int32_t *vsplit_s = nullptr, *vsplit_t = nullptr;
     int32_t *w_leaves = nullptr;     // leaves with non-empty W list
     int n_w_leaves = 0;
     int32_t *err_flag = nullptr;     // device error flag (list traversal overflow)
