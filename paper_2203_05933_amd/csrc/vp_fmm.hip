@@ -4,13 +4,16 @@
 // (smooth rule of Section 3.2, eq. Tk_smooth_quad; box rule of Section 4.2;
 // Green's function of Section 2.1; correction matrix of Section 4) runs as:
 //   charge     q_b[j] = w_j f_b[perm[j]]                (sorted source order)
-//   P2M        leaf multipoles                         (VALU, LDS reduction)
-//   M2M        upward pass, level by level             (MFMA gather-GEMM)
-//   M2L        V lists, one launch for all levels      (MFMA, operators in FP64)
-//   P2L        X lists                                 (VALU)
-//   L2L        downward pass, level by level           (MFMA gather-GEMM)
-//   P2P        U lists, LDS-staged source tiles        (FP64 VALU)
-//   L2P + M2P  local expansion and W lists at targets  (VALU)
+//   P2M        leaf multipoles; congruent leaves by one matrix (MFMA), others
+//              and the virtual children of X-list sources on the VALU
+//   M2M        upward pass, level by level             (VALU, scaled form)
+//   M2L        V lists, one launch for all levels      (MFMA, scaled form)
+//   P2L        X lists two or more levels apart        (VALU)
+//   L2L        downward pass, level by level           (VALU, scaled form)
+//   tables     near field of congruent leaves          (MFMA, FP64)
+//   P2P        remaining U-list pairs, LDS-staged      (FP64 VALU)
+//   L2P + M2P  local expansion and W lists at targets  (VALU; MFMA for
+//              congruent leaves)
 //   finish     u = acc[inverse perm] + C f             (HBM bound)
 // The adjoint runs the same passes with the point roles swapped (charges
 // g at the targets, evaluated at the nodes, times w) plus C^T g.
@@ -197,50 +200,112 @@ __global__ void __launch_bounds__(64) k_p2m_quad(PointRoles R, BoxGeo G, const i
 }
 
 // ----------------------------------------------------------------------------
-// M2M / L2L on the VALU: one wave per target box of a level.  The source
-// columns (children, or the parent) are staged in LDS; lane r forms row r
-// from the transposed operator RT[k][r], so every operator read is a
-// contiguous 64-element row shared by the wave.  Used for the per-level
-// passes, which are too small to fill the matrix cores.
+// M2M on the VALU in diagonally scaled form: one wave per parent box of a
+// level.  Every child column is scaled by tin[class][k], multiplied by the
+// real matrix Q (shared by all classes; read transposed so a wave's loads are
+// contiguous), scaled by tout[class][l] and summed.  A lane owns output row l
+// of one group of children; with P <= 32 the wave's halves (quarters for
+// P <= 16) take alternate children and are added through LDS in a fixed order.
 // ----------------------------------------------------------------------------
-template <class E, bool L2L>
-__global__ void __launch_bounds__(64) k_shift(const int32_t *__restrict__ boxes, int nbatch, int P, int PD,
-                                              BoxGeo G, const E *__restrict__ RT, E *__restrict__ X) {
-    __shared__ E colv[4][128];
+template <class E>
+__global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, int nbatch, int P, int PD, int PR,
+                                            BoxGeo G, const E *__restrict__ QT, const E *__restrict__ tin,
+                                            const E *__restrict__ tout, E *__restrict__ X) {
+    __shared__ E ys[4][2][64];   // scaled child columns (re, im)
+    __shared__ E red[4][2][64];  // per-group partial rows
     const int lane = threadIdx.x;
     const int b = boxes[blockIdx.x];
-    int nsrc = 0, srcs[4], ops[4];
-    if (L2L) {
-        nsrc = 1;
-        srcs[0] = G.parent[b];
-        ops[0] = (G.ix[b] & 1) | ((G.iy[b] & 1) << 1);
-    } else {
-        nsrc = G.nchild[b];
-        for (int c = 0; c < nsrc; ++c) {
-            srcs[c] = G.child[b] + c;
-            ops[c] = (G.ix[srcs[c]] & 1) | ((G.iy[srcs[c]] & 1) << 1);
-        }
+    const int nsrc = G.nchild[b];
+    int srcs[4], ops[4];
+    for (int c = 0; c < nsrc; ++c) {
+        srcs[c] = G.child[b] + c;
+        ops[c] = (G.ix[srcs[c]] & 1) | ((G.iy[srcs[c]] & 1) << 1);
     }
-    const int K = 2 * P;
+    const int H = 64 / PR;  // row groups in the wave
+    const int gi = lane / PR, l = lane % PR;
     for (int bt = 0; bt < nbatch; ++bt) {
         for (int c = 0; c < nsrc; ++c)
-            for (int k = lane; k < K; k += 64) colv[c][k] = X[((int64_t)srcs[c] * nbatch + bt) * PD + k];
+            for (int k = lane; k < P; k += 64) {
+                const E *x = X + ((int64_t)srcs[c] * nbatch + bt) * PD;
+                const E xr = x[k], xi = x[P + k];
+                const E wr = tin[(ops[c] * P + k) * 2], wi = tin[(ops[c] * P + k) * 2 + 1];
+                ys[c][0][k] = xr * wr - xi * wi;
+                ys[c][1][k] = xr * wi + xi * wr;
+            }
         __syncthreads();
-        for (int r = lane; r < PD; r += 64) {
-            E acc = (E)0;
-            if (r < K) {
-                for (int c = 0; c < nsrc; ++c) {
-                    const E *R = RT + (int64_t)ops[c] * PD * PD + r;
-#pragma unroll 8
-                    for (int k = 0; k < K; ++k) acc += R[(int64_t)k * PD] * colv[c][k];
+        E br = (E)0, bi = (E)0;
+        if (l < P) {
+            for (int c = gi; c < nsrc; c += H) {
+                E zr = (E)0, zi = (E)0;
+#pragma unroll 4
+                for (int k = 0; k < P; ++k) {
+                    const E qv = QT[k * PR + l];
+                    zr += qv * ys[c][0][k];
+                    zi += qv * ys[c][1][k];
+                }
+                const E vr = tout[(ops[c] * P + l) * 2], vi = tout[(ops[c] * P + l) * 2 + 1];
+                br += zr * vr - zi * vi;
+                bi += zr * vi + zi * vr;
+            }
+        }
+        if (H > 1) {
+            red[gi][0][l] = br;
+            red[gi][1][l] = bi;
+            __syncthreads();
+            if (gi == 0) {
+                for (int h = 1; h < H; ++h) {
+                    br += red[h][0][l];
+                    bi += red[h][1][l];
                 }
             }
-            E *o = X + ((int64_t)b * nbatch + bt) * PD + r;
-            if (L2L) {
-                if (r < K) *o += acc;
-            } else {
-                *o = acc;
+        }
+        E *o = X + ((int64_t)b * nbatch + bt) * PD;
+        if (gi == 0 && l < P) {
+            o[l] = br;
+            o[P + l] = bi;
+        }
+        for (int r = 2 * P + lane; r < PD; r += 64) o[r] = (E)0;
+        __syncthreads();
+    }
+}
+
+// L2L in the same scaled form (Q upper triangular), one target box per row group: a wave serves
+// 64 / PR boxes of a level (each row group stages its own parent column).
+template <class E>
+__global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, int nboxes, int nbatch, int P,
+                                            int PD, int PR, BoxGeo G, const E *__restrict__ QT,
+                                            const E *__restrict__ tin, const E *__restrict__ tout,
+                                            E *__restrict__ X) {
+    __shared__ E ys[4][2][64];
+    const int lane = threadIdx.x;
+    const int H = 64 / PR;
+    const int gi = lane / PR, l = lane % PR;
+    const int idx = blockIdx.x * H + gi;
+    const bool act = idx < nboxes;
+    const int b = act ? boxes[idx] : 0;
+    const int src = act ? G.parent[b] : 0;
+    const int cls = act ? ((G.ix[b] & 1) | ((G.iy[b] & 1) << 1)) : 0;
+    for (int bt = 0; bt < nbatch; ++bt) {
+        if (act && l < P) {
+            const E *x = X + ((int64_t)src * nbatch + bt) * PD;
+            const E xr = x[l], xi = x[P + l];
+            const E wr = tin[(cls * P + l) * 2], wi = tin[(cls * P + l) * 2 + 1];
+            ys[gi][0][l] = xr * wr - xi * wi;
+            ys[gi][1][l] = xr * wi + xi * wr;
+        }
+        __syncthreads();
+        if (act && l < P) {
+            E zr = (E)0, zi = (E)0;
+#pragma unroll 4
+            for (int k = l; k < P; ++k) {  // Q[l][k] = C(k, l) vanishes for k < l
+                const E qv = QT[k * PR + l];
+                zr += qv * ys[gi][0][k];
+                zi += qv * ys[gi][1][k];
             }
+            const E vr = tout[(cls * P + l) * 2], vi = tout[(cls * P + l) * 2 + 1];
+            E *o = X + ((int64_t)b * nbatch + bt) * PD;
+            o[l] += zr * vr - zi * vi;
+            o[P + l] += zr * vi + zi * vr;
         }
         __syncthreads();
     }
@@ -977,8 +1042,6 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     E *L = static_cast<E *>(P->Lexp);
     const bool f32 = sizeof(E) == 4;
     const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
-    const E *Rm2m = f32 ? (const E *)P->ops.m2m_f32 : (const E *)P->ops.m2m_f64;
-    const E *Rl2l = f32 ? (const E *)P->ops.l2l_f32 : (const E *)P->ops.l2l_f64;
     const size_t lds = sizeof(E) * 2 * 16 * Pn;
     if (T.nlevels < 3) return;  // no box is well separated from another
     P->stage_begin(VP_STAGE_P2M);
@@ -1003,13 +1066,18 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     }
     P->stage_end(VP_STAGE_P2M);
     P->stage_begin(VP_STAGE_M2M);
-    const E *RTm = f32 ? (const E *)P->ops.m2m_t32 : (const E *)P->ops.m2m_t64;
-    const E *RTl = f32 ? (const E *)P->ops.l2l_t32 : (const E *)P->ops.l2l_t64;
+    const Operators &O = P->ops;
+    const E *shq[2], *shi[2], *sho[2];
+    for (int w = 0; w < 2; ++w) {
+        shq[w] = f32 ? (const E *)O.sh_qt32[w] : (const E *)O.sh_qt64[w];
+        shi[w] = f32 ? (const E *)O.sh_tin32[w] : (const E *)O.sh_tin64[w];
+        sho[w] = f32 ? (const E *)O.sh_tout32[w] : (const E *)O.sh_tout64[w];
+    }
     for (int l = T.nlevels - 2; l >= 2; --l) {
         int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
         if (c1 > c0) {
-            hipLaunchKernelGGL((k_shift<E, false>), dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0, nb, Pn, PD,
-                               G, RTm, M);
+            hipLaunchKernelGGL(k_m2m<E>, dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0, nb, Pn, PD,
+                               O.PR, G, shq[0], shi[0], sho[0], M);
             VP_LAUNCH_CHECK();
         }
     }
@@ -1065,8 +1133,9 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     for (int l = 3; l < T.nlevels; ++l) {
         int c0 = P->lvl_box_begin[l], c1 = P->lvl_box_begin[l + 1];
         if (c1 > c0) {
-            hipLaunchKernelGGL((k_shift<E, true>), dim3(c1 - c0), dim3(64), 0, s, P->lvl_boxes + c0, nb, Pn, PD, G,
-                               RTl, L);
+            const int H = 64 / O.PR;
+            hipLaunchKernelGGL(k_l2l<E>, dim3((c1 - c0 + H - 1) / H), dim3(64), 0, s, P->lvl_boxes + c0, c1 - c0, nb,
+                               Pn, PD, O.PR, G, shq[1], shi[1], sho[1], L);
             VP_LAUNCH_CHECK();
         }
     }

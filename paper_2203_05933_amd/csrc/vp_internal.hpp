@@ -138,12 +138,13 @@ struct Operators {
     double *m2l_f64 = nullptr;  // NOFF ops
     float *m2l_f32 = nullptr;
     float *m2l_f32_lo = nullptr;
-    // shift operators, same order, 4 ops each (child quadrant / child class)
-    double *m2m_f64 = nullptr, *l2l_f64 = nullptr;
-    float *m2m_f32 = nullptr, *l2l_f32 = nullptr;
-    // the same shifts transposed ([op][k][r], r fastest) for the VALU kernel
-    double *m2m_t64 = nullptr, *l2l_t64 = nullptr;
-    float *m2m_t32 = nullptr, *l2l_t32 = nullptr;
+    // M2M / L2L in diagonally scaled form (index 0 = M2M, 1 = L2L): a real
+    // P x P matrix stored transposed, QT[k][l] with row stride PR (power of
+    // two >= P), and per child class complex scalings tin[c][k], tout[c][l]
+    // ([4][P][2])
+    int PR = 0;
+    double *sh_qt64[2] = {nullptr, nullptr}, *sh_tin64[2] = {nullptr, nullptr}, *sh_tout64[2] = {nullptr, nullptr};
+    float *sh_qt32[2] = {nullptr, nullptr}, *sh_tin32[2] = {nullptr, nullptr}, *sh_tout32[2] = {nullptr, nullptr};
     double *inv_k = nullptr;  // 1/k, k = 0..P-1 (0 for k = 0)
     float *inv_k_f32 = nullptr;
     // M2L in diagonally scaled form: one real matrix Q (A-fragment order,

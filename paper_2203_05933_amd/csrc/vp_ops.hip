@@ -69,33 +69,6 @@ static std::vector<cd> m2l_complex(cd t, int P, const std::vector<double> &C, in
     return T;
 }
 
-static std::vector<cd> m2m_complex(cd t, int P, const std::vector<double> &C, int N) {
-    std::vector<cd> T((size_t)P * P, cd(0, 0));
-    std::vector<cd> tp(P + 1);
-    tp[0] = 1.0;
-    for (int n = 1; n <= P; ++n) tp[n] = tp[n - 1] * t;
-    T[0] = 1.0;
-    for (int l = 1; l < P; ++l) {
-        double sc = std::ldexp(1.0, -l);
-        T[(size_t)l * P] = -tp[l] / (double)l * sc;
-        for (int k = 1; k <= l; ++k)
-            T[(size_t)l * P + k] = C[(size_t)(l - 1) * (N + 1) + k - 1] * tp[l - k] * sc;
-    }
-    return T;
-}
-
-static std::vector<cd> l2l_complex(cd t, int P, const std::vector<double> &C, int N) {
-    std::vector<cd> T((size_t)P * P, cd(0, 0));
-    std::vector<cd> tp(P + 1);
-    tp[0] = 1.0;
-    for (int n = 1; n <= P; ++n) tp[n] = tp[n - 1] * t;
-    for (int l = 0; l < P; ++l) {
-        double sc = std::ldexp(1.0, -l);
-        for (int k = l; k < P; ++k) T[(size_t)l * P + k] = C[(size_t)k * (N + 1) + l] * tp[k - l] * sc;
-    }
-    return T;
-}
-
 // outer offsets in code order
 static void offset_of_code(int code, int &dx, int &dy) {
     for (int y = -3; y <= 3; ++y)
@@ -142,21 +115,47 @@ void build_operators(vp_plan_s *P) {
         R[(size_t)(2 * Pn) * PD + 0] = 1.0;  // sum of Re A_0 (log s term)
         to_frag(R.data(), PD, F.data() + code * mat);
     }
-    std::vector<double> M2M(4 * mat), L2L(4 * mat), M2Mt(4 * mat), L2Lt(4 * mat);
-    auto transpose = [&](const double *Rm, double *out) {
-        for (int r = 0; r < PD; ++r)
-            for (int k = 0; k < PD; ++k) out[(size_t)k * PD + r] = Rm[(size_t)r * PD + k];
-    };
+    // M2M and L2L in diagonally scaled form, per child class q (bit 0: +x, bit 1: +y):
+    //   M2M, t = child offset / child side = (+-1/2, +-1/2):
+    //       B_l = 2^-l t^l [ -A_0 / l + sum_{k=1..l} C(l-1, k-1) t^-k A_k ],  B_0 = A_0
+    //   L2L, t = child offset / parent side = (+-1/4, +-1/4):
+    //       B'_l = 2^-l t^-l sum_{k>=l} C(k, l) t^k B_k
+    int PR = 16;
+    while (PR < Pn) PR *= 2;
+    O.PR = PR;
+    std::vector<double> shq[2], shin[2], shout[2];
+    for (int w = 0; w < 2; ++w) {
+        shq[w].assign((size_t)Pn * PR, 0.0);
+        shin[w].assign((size_t)4 * Pn * 2, 0.0);
+        shout[w].assign((size_t)4 * Pn * 2, 0.0);
+    }
+    // QT[k][l] = Q[l][k]
+    shq[0][0] = 1.0;
+    for (int l = 1; l < Pn; ++l) {
+        shq[0][(size_t)0 * PR + l] = -1.0 / l;
+        for (int k = 1; k <= l; ++k) shq[0][(size_t)k * PR + l] = C[(size_t)(l - 1) * (N + 1) + k - 1];
+    }
+    for (int l = 0; l < Pn; ++l)
+        for (int k = l; k < Pn; ++k) shq[1][(size_t)k * PR + l] = C[(size_t)k * (N + 1) + l];
     for (int q = 0; q < 4; ++q) {
-        double sx = (q & 1) ? 1.0 : -1.0, sy = (q >> 1) ? 1.0 : -1.0;
-        auto Tm = m2m_complex(cd(0.5 * sx, 0.5 * sy), Pn, C, N);
-        to_real(Tm, Pn, PD, R.data());
-        to_frag(R.data(), PD, M2M.data() + q * mat);
-        transpose(R.data(), M2Mt.data() + q * mat);
-        auto Tl = l2l_complex(cd(0.25 * sx, 0.25 * sy), Pn, C, N);
-        to_real(Tl, Pn, PD, R.data());
-        to_frag(R.data(), PD, L2L.data() + q * mat);
-        transpose(R.data(), L2Lt.data() + q * mat);
+        const double sx = (q & 1) ? 1.0 : -1.0, sy = (q >> 1) ? 1.0 : -1.0;
+        const cd tm(0.5 * sx, 0.5 * sy), tl(0.25 * sx, 0.25 * sy);
+        cd a_in = 1.0, a_out = 1.0, b_in = 1.0, b_out = 1.0;
+        for (int k = 0; k < Pn; ++k) {
+            const size_t e = ((size_t)q * Pn + k) * 2;
+            shin[0][e] = a_in.real();
+            shin[0][e + 1] = a_in.imag();
+            shout[0][e] = a_out.real();
+            shout[0][e + 1] = a_out.imag();
+            shin[1][e] = b_in.real();
+            shin[1][e + 1] = b_in.imag();
+            shout[1][e] = b_out.real();
+            shout[1][e + 1] = b_out.imag();
+            a_in /= tm;          // t^-k
+            a_out *= 0.5 * tm;   // 2^-l t^l
+            b_in *= tl;          // t^k
+            b_out /= 2.0 * tl;   // 2^-l t^-l
+        }
     }
     // diagonally scaled M2L: Q, (-t)^-k, t^-l and log(-t) per offset
     const int PQ = (Pn + 15) / 16 * 16;
@@ -201,10 +200,11 @@ void build_operators(vp_plan_s *P) {
         return d;
     };
     O.m2l_f64 = up(F);
-    O.m2m_f64 = up(M2M);
-    O.l2l_f64 = up(L2L);
-    O.m2m_t64 = up(M2Mt);
-    O.l2l_t64 = up(L2Lt);
+    for (int w = 0; w < 2; ++w) {
+        O.sh_qt64[w] = up(shq[w]);
+        O.sh_tin64[w] = up(shin[w]);
+        O.sh_tout64[w] = up(shout[w]);
+    }
     O.inv_k = up(invk);
     O.m2l_q64 = up(Qf);
     O.m2l_tin64 = up(tin);
@@ -223,13 +223,17 @@ void build_operators(vp_plan_s *P) {
         }
         O.m2l_f32 = upf(hi);
         O.m2l_f32_lo = upf(lo);
-        std::vector<float> a(M2M.begin(), M2M.end()), b(L2L.begin(), L2L.end()), c(invk.begin(), invk.end());
-        O.m2m_f32 = upf(a);
-        O.l2l_f32 = upf(b);
-        std::vector<float> at(M2Mt.begin(), M2Mt.end()), bt(L2Lt.begin(), L2Lt.end());
-        O.m2m_t32 = upf(at);
-        O.l2l_t32 = upf(bt);
+        std::vector<float> c(invk.begin(), invk.end());
         O.inv_k_f32 = upf(c);
+        std::vector<float> fq[2], fi[2], fo[2];
+        for (int w = 0; w < 2; ++w) {
+            fq[w].assign(shq[w].begin(), shq[w].end());
+            fi[w].assign(shin[w].begin(), shin[w].end());
+            fo[w].assign(shout[w].begin(), shout[w].end());
+            O.sh_qt32[w] = upf(fq[w]);
+            O.sh_tin32[w] = upf(fi[w]);
+            O.sh_tout32[w] = upf(fo[w]);
+        }
         VP_HIP(hipStreamSynchronize(s));  // before the host copies above go out of scope
     }
     VP_HIP(hipStreamSynchronize(s));
