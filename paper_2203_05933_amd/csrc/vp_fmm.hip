@@ -88,8 +88,7 @@ __device__ inline C2<E> cpow_int(C2<E> w, int n) {
 }
 
 template <class E>
-__device__ inline void fill_power_rows(C2<E> w, E k0re, bool valid, int j, int g, int P,
-                                       const E *__restrict__ invk, E *Wre, E *Wim) {
+__device__ inline void fill_power_rows(C2<E> w, E k0re, bool valid, int j, int g, int P, E *Wre, E *Wim) {
     const int KP = (P + 3) / 4;
     const int k0 = g * KP, k1 = min(P, k0 + KP);
     if (!valid) {
@@ -105,16 +104,16 @@ __device__ inline void fill_power_rows(C2<E> w, E k0re, bool valid, int j, int g
             Wre[j * P] = k0re;
             Wim[j * P] = (E)0;
         } else {
-            Wre[j * P + k] = -pw.re * invk[k];
-            Wim[j * P + k] = -pw.im * invk[k];
+            Wre[j * P + k] = pw.re;  // the factor -1/k is applied to the sums
+            Wim[j * P + k] = pw.im;
         }
         pw = cmul(pw, w);
     }
 }
 
 // ----------------------------------------------------------------------------
-// P2M: one wave per leaf; A_r = sum_j q_j W[j][r] in source order, with
-// W[j][0] = 1 and W[j][k] = -(1/k) ((z_j - c)/s)^k.
+// P2M: one wave per leaf; A_k = -(1/k) sum_j q_j W[j][k] in source order
+// (A_0 = sum_j q_j), with W[j][k] = ((z_j - c)/s)^k.
 // ----------------------------------------------------------------------------
 template <class E>
 __device__ inline void p2m_range(const PointRoles &R, int s0, int s1, double cx, double cy, double inv_s,
@@ -132,7 +131,7 @@ __device__ inline void p2m_range(const PointRoles &R, int s0, int s1, double cx,
             const bool v = j < cnt;
             const int jj = base + (v ? j : 0);
             const C2<E> w = {(E)((R.sx[jj] - cx) * inv_s), (E)((R.sy[jj] - cy) * inv_s)};
-            fill_power_rows<E>(w, (E)1, v, j, g, P, invk, Wre, Wim);
+            fill_power_rows<E>(w, (E)1, v, j, g, P, Wre, Wim);
             for (int bb = g; bb < nbg; bb += 4) sq[bb][j] = v ? (E)q[(int64_t)(bt0 + bb) * R.nsrc + jj] : (E)0;
             __syncthreads();
             // static register indexing (rows r = lane + 64 ri, densities bb)
@@ -157,9 +156,11 @@ __device__ inline void p2m_range(const PointRoles &R, int s0, int s1, double cx,
         for (int ri = 0; ri < 2; ++ri) {
             const int r = lane + 64 * ri;
             if (r < PD) {
+                const int k = r < P ? r : r - P;
+                const E sc = r >= 2 * P ? (E)0 : (k == 0 ? (E)1 : -invk[k]);
 #pragma unroll
                 for (int bb = 0; bb < 16; ++bb)
-                    if (bb < nbg) out[(bt0 + bb) * PD + r] = (r < 2 * P) ? acc[ri][bb] : (E)0;
+                    if (bb < nbg) out[(bt0 + bb) * PD + r] = sc * acc[ri][bb];
             }
         }
     }
@@ -207,55 +208,59 @@ __global__ void __launch_bounds__(64) k_p2m_quad(PointRoles R, BoxGeo G, const i
 // of one group of children; with P <= 32 the wave's halves (quarters for
 // P <= 16) take alternate children and are added through LDS in a fixed order.
 // ----------------------------------------------------------------------------
-template <class E>
-__global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, int nbatch, int P, int PD, int PR,
+template <class E, int PR>
+__global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, int nbatch, int P, int PD,
                                             BoxGeo G, const E *__restrict__ QT, const E *__restrict__ tin,
                                             const E *__restrict__ tout, E *__restrict__ X) {
-    __shared__ E ys[4][2][64];   // scaled child columns (re, im)
-    __shared__ E red[4][2][64];  // per-group partial rows
+    constexpr int H = 64 / PR;       // row groups in the wave
+    __shared__ E ys[4][PR][2];       // scaled child columns (re, im interleaved)
+    __shared__ E red[H][PR][2];      // per-group partial rows
     const int lane = threadIdx.x;
-    const int b = boxes[blockIdx.x];
-    const int nsrc = G.nchild[b];
-    int srcs[4], ops[4];
-    for (int c = 0; c < nsrc; ++c) {
-        srcs[c] = G.child[b] + c;
-        ops[c] = (G.ix[srcs[c]] & 1) | ((G.iy[srcs[c]] & 1) << 1);
-    }
-    const int H = 64 / PR;  // row groups in the wave
     const int gi = lane / PR, l = lane % PR;
+    E qc[PR];  // this lane's row of Q (column l of QT), kept in registers
+#pragma unroll
+    for (int k = 0; k < PR; ++k) qc[k] = (k < P && l < P) ? QT[k * PR + l] : (E)0;
+    const int b = boxes[blockIdx.x];
+    const int nsrc = G.nchild[b], c0 = G.child[b];
     for (int bt = 0; bt < nbatch; ++bt) {
-        for (int c = 0; c < nsrc; ++c)
-            for (int k = lane; k < P; k += 64) {
-                const E *x = X + ((int64_t)srcs[c] * nbatch + bt) * PD;
-                const E xr = x[k], xi = x[P + k];
-                const E wr = tin[(ops[c] * P + k) * 2], wi = tin[(ops[c] * P + k) * 2 + 1];
-                ys[c][0][k] = xr * wr - xi * wi;
-                ys[c][1][k] = xr * wi + xi * wr;
+        for (int c = gi; c < nsrc; c += H) {
+            const int ch = c0 + c, cls = (G.ix[ch] & 1) | ((G.iy[ch] & 1) << 1);
+            E yr = (E)0, yi = (E)0;
+            if (l < P) {
+                const E *x = X + ((int64_t)ch * nbatch + bt) * PD;
+                const E xr = x[l], xi = x[P + l];
+                const E wr = tin[(cls * P + l) * 2], wi = tin[(cls * P + l) * 2 + 1];
+                yr = xr * wr - xi * wi;
+                yi = xr * wi + xi * wr;
             }
+            ys[c][l][0] = yr;
+            ys[c][l][1] = yi;
+        }
         __syncthreads();
         E br = (E)0, bi = (E)0;
-        if (l < P) {
-            for (int c = gi; c < nsrc; c += H) {
-                E zr = (E)0, zi = (E)0;
-#pragma unroll 4
-                for (int k = 0; k < P; ++k) {
-                    const E qv = QT[k * PR + l];
-                    zr += qv * ys[c][0][k];
-                    zi += qv * ys[c][1][k];
-                }
-                const E vr = tout[(ops[c] * P + l) * 2], vi = tout[(ops[c] * P + l) * 2 + 1];
+        for (int c = gi; c < nsrc; c += H) {
+            const int ch = c0 + c, cls = (G.ix[ch] & 1) | ((G.iy[ch] & 1) << 1);
+            E zr = (E)0, zi = (E)0;
+#pragma unroll
+            for (int k = 0; k < PR; ++k) {
+                zr += qc[k] * ys[c][k][0];
+                zi += qc[k] * ys[c][k][1];
+            }
+            if (l < P) {
+                const E vr = tout[(cls * P + l) * 2], vi = tout[(cls * P + l) * 2 + 1];
                 br += zr * vr - zi * vi;
                 bi += zr * vi + zi * vr;
             }
         }
         if (H > 1) {
-            red[gi][0][l] = br;
-            red[gi][1][l] = bi;
+            red[gi][l][0] = br;
+            red[gi][l][1] = bi;
             __syncthreads();
             if (gi == 0) {
+#pragma unroll
                 for (int h = 1; h < H; ++h) {
-                    br += red[h][0][l];
-                    bi += red[h][1][l];
+                    br += red[h][l][0];
+                    bi += red[h][l][1];
                 }
             }
         }
@@ -269,40 +274,52 @@ __global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, i
     }
 }
 
-// L2L in the same scaled form (Q upper triangular), one target box per row group: a wave serves
-// 64 / PR boxes of a level (each row group stages its own parent column).
-template <class E>
+// L2L in the same scaled form (Q upper triangular), one target box per row
+// group: a wave serves 64 / PR boxes of a level, each row group staging its
+// own parent column.
+template <class E, int PR>
 __global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, int nboxes, int nbatch, int P,
-                                            int PD, int PR, BoxGeo G, const E *__restrict__ QT,
+                                            int PD, BoxGeo G, const E *__restrict__ QT,
                                             const E *__restrict__ tin, const E *__restrict__ tout,
                                             E *__restrict__ X) {
-    __shared__ E ys[4][2][64];
+    constexpr int H = 64 / PR;
+    __shared__ E ys[H][PR][2];
     const int lane = threadIdx.x;
-    const int H = 64 / PR;
     const int gi = lane / PR, l = lane % PR;
+    E qc[PR];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) qc[k] = (k < P && l < P) ? QT[k * PR + l] : (E)0;
     const int idx = blockIdx.x * H + gi;
     const bool act = idx < nboxes;
     const int b = act ? boxes[idx] : 0;
     const int src = act ? G.parent[b] : 0;
     const int cls = act ? ((G.ix[b] & 1) | ((G.iy[b] & 1) << 1)) : 0;
+    const bool row = act && l < P;
+    E wr = (E)0, wi = (E)0, vr = (E)0, vi = (E)0;
+    if (row) {
+        wr = tin[(cls * P + l) * 2];
+        wi = tin[(cls * P + l) * 2 + 1];
+        vr = tout[(cls * P + l) * 2];
+        vi = tout[(cls * P + l) * 2 + 1];
+    }
     for (int bt = 0; bt < nbatch; ++bt) {
-        if (act && l < P) {
+        E yr = (E)0, yi = (E)0;
+        if (row) {
             const E *x = X + ((int64_t)src * nbatch + bt) * PD;
             const E xr = x[l], xi = x[P + l];
-            const E wr = tin[(cls * P + l) * 2], wi = tin[(cls * P + l) * 2 + 1];
-            ys[gi][0][l] = xr * wr - xi * wi;
-            ys[gi][1][l] = xr * wi + xi * wr;
+            yr = xr * wr - xi * wi;
+            yi = xr * wi + xi * wr;
         }
+        ys[gi][l][0] = yr;
+        ys[gi][l][1] = yi;
         __syncthreads();
-        if (act && l < P) {
-            E zr = (E)0, zi = (E)0;
-#pragma unroll 4
-            for (int k = l; k < P; ++k) {  // Q[l][k] = C(k, l) vanishes for k < l
-                const E qv = QT[k * PR + l];
-                zr += qv * ys[gi][0][k];
-                zi += qv * ys[gi][1][k];
-            }
-            const E vr = tout[(cls * P + l) * 2], vi = tout[(cls * P + l) * 2 + 1];
+        E zr = (E)0, zi = (E)0;
+#pragma unroll
+        for (int k = 0; k < PR; ++k) {
+            zr += qc[k] * ys[gi][k][0];
+            zi += qc[k] * ys[gi][k][1];
+        }
+        if (row) {
             E *o = X + ((int64_t)b * nbatch + bt) * PD;
             o[l] += zr * vr - zi * vi;
             o[P + l] += zr * vi + zi * vr;
@@ -346,7 +363,7 @@ __global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_
                 const double d2 = dx * dx + dy * dy;
                 // s / (z - c) = s (dx - i dy) / d2
                 const C2<E> iw = {(E)(s * dx / d2), (E)(-s * dy / d2)};
-                fill_power_rows<E>(iw, (E)(0.5 * vp_log(d2)), v, j, g, P, invk, Wre, Wim);
+                fill_power_rows<E>(iw, (E)(0.5 * vp_log(d2)), v, j, g, P, Wre, Wim);
                 for (int bb = g; bb < nb; bb += 4) sq[bb][j] = v ? (E)q[(int64_t)(bt0 + bb) * R.nsrc + jj] : (E)0;
                 __syncthreads();
 #pragma unroll
@@ -371,9 +388,11 @@ __global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_
         for (int ri = 0; ri < 2; ++ri) {
             const int r = lane + 64 * ri;
             if (r < 2 * P) {
+                const int k = r < P ? r : r - P;
+                const E sc = k == 0 ? (E)1 : -invk[k];
 #pragma unroll
                 for (int bb = 0; bb < 16; ++bb)
-                    if (bb < nb) Lo[(bt0 + bb) * PD + r] += acc[ri][bb];
+                    if (bb < nb) Lo[(bt0 + bb) * PD + r] += sc * acc[ri][bb];
             }
         }
     }
@@ -1076,8 +1095,16 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     for (int l = T.nlevels - 2; l >= 2; --l) {
         int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
         if (c1 > c0) {
-            hipLaunchKernelGGL(k_m2m<E>, dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0, nb, Pn, PD,
-                               O.PR, G, shq[0], shi[0], sho[0], M);
+            switch (O.PR) {
+#define VP_M2M(PR)                                                                                               \
+    case PR:                                                                                                     \
+        hipLaunchKernelGGL((k_m2m<E, PR>), dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0, nb, Pn, PD, G,   \
+                           shq[0], shi[0], sho[0], M);                                                           \
+        break;
+                VP_M2M(16) VP_M2M(32) VP_M2M(64)
+#undef VP_M2M
+                default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
+            }
             VP_LAUNCH_CHECK();
         }
     }
@@ -1133,9 +1160,17 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     for (int l = 3; l < T.nlevels; ++l) {
         int c0 = P->lvl_box_begin[l], c1 = P->lvl_box_begin[l + 1];
         if (c1 > c0) {
-            const int H = 64 / O.PR;
-            hipLaunchKernelGGL(k_l2l<E>, dim3((c1 - c0 + H - 1) / H), dim3(64), 0, s, P->lvl_boxes + c0, c1 - c0, nb,
-                               Pn, PD, O.PR, G, shq[1], shi[1], sho[1], L);
+            const unsigned nblk = (unsigned)((c1 - c0 + 64 / O.PR - 1) / (64 / O.PR));
+            switch (O.PR) {
+#define VP_L2L(PR)                                                                                               \
+    case PR:                                                                                                     \
+        hipLaunchKernelGGL((k_l2l<E, PR>), dim3(nblk), dim3(64), 0, s, P->lvl_boxes + c0, c1 - c0, nb, Pn, PD, G, \
+                           shq[1], shi[1], sho[1], L);                                                           \
+        break;
+                VP_L2L(16) VP_L2L(32) VP_L2L(64)
+#undef VP_L2L
+                default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
+            }
             VP_LAUNCH_CHECK();
         }
     }
