@@ -700,48 +700,74 @@ __global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, int b
                                                 const double *__restrict__ valv,
                                                 const double *__restrict__ f, int64_t flen,
                                                 double *__restrict__ out) {
+    // 16 lanes per row; a group takes R consecutive rows at a time and issues
+    // all their loads (row metadata, 64-entry slices, near/far sums) before
+    // any reduction, so no load waits on another row's arithmetic.
+    constexpr int R = NBG >= 16 ? 1 : (NBG >= 8 ? 2 : 4);  // registers: R x NBG partial sums
     const int l16 = threadIdx.x & 15;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
     const int nbg = min(NBG, nbatch - bt0);
-    for (int64_t i = grp; i < nrows; i += ngrp) {
-        const int64_t p0 = rowptr[i], p1 = rowptr[i + 1];
-        const int32_t rs = run_start[i];
-        double part[NBG];
+    for (int64_t i0 = grp * R; i0 < nrows; i0 += ngrp * R) {
+        // lane r < R fetches row i0 + r's metadata and FMM sums
+        const int64_t im = i0 + l16;
+        const bool mrow = l16 < R && im < nrows;
+        int64_t mp0 = 0, mp1 = 0;
+        int32_t mrs = 0;
+        double msc = 1.0, macc[NBG];
+        if (mrow) {
+            mp0 = rowptr[im];
+            mp1 = rowptr[im + 1];
+            mrs = run_start[im];
+            const int32_t si = inv[im];
+            if (scale) msc = scale[im];
 #pragma unroll
-        for (int k = 0; k < NBG; ++k) part[k] = 0.0;
-        // four independent 16-wide slices in flight per pass (64 entries)
-        for (int64_t pb = p0; pb < p1; pb += 64) {
-            double v[4];
-            int64_t c[4];
-            bool in[4];
+            for (int k = 0; k < NBG; ++k) macc[k] = k < nbg ? acc[(int64_t)(bt0 + k) * acc_len + si] : 0.0;
+        }
+        double part[R][NBG];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t pq = pb + l16 + 16 * u;
-                in[u] = pq < p1;
-                v[u] = in[u] ? valv[pq] : 0.0;
-                c[u] = !in[u] ? 0 : (rs >= 0 ? (int64_t)rs + (pq - p0) : (int64_t)colv[pq]);
+        for (int r = 0; r < R; ++r) {
+            const int64_t p0 = __shfl(mp0, r, 16), p1 = __shfl(mp1, r, 16);
+            const int32_t rs = __shfl(mrs, r, 16);
+#pragma unroll
+            for (int k = 0; k < NBG; ++k) part[r][k] = 0.0;
+            for (int64_t pb = p0; pb < p1; pb += 64) {
+                double v[4];
+                int64_t c[4];
+                bool in[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t pq = pb + l16 + 16 * u;
+                    in[u] = pq < p1;
+                    v[u] = in[u] ? valv[pq] : 0.0;
+                    c[u] = !in[u] ? 0 : (rs >= 0 ? (int64_t)rs + (pq - p0) : (int64_t)colv[pq]);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int k = 0; k < NBG; ++k)
+                        if (k < nbg && in[u]) part[r][k] += v[u] * f[(int64_t)(bt0 + k) * flen + c[u]];
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int k = 0; k < NBG; ++k)
-                    if (k < nbg && in[u]) part[k] += v[u] * f[(int64_t)(bt0 + k) * flen + c[u]];
         }
 #pragma unroll
-        for (int k = 0; k < NBG; ++k) {
-            double v = part[k];
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 16);
-            part[k] = v;
-        }
-        if (l16 == 0) {
-            const int32_t si = inv[i];
-            const double sc = scale ? scale[i] : 1.0;
+            for (int k = 0; k < NBG; ++k) {
+                double v = part[r][k];
 #pragma unroll
-            for (int k = 0; k < NBG; ++k)
-                if (k < nbg)
-                    out[(int64_t)(bt0 + k) * nrows + i] = sc * acc[(int64_t)(bt0 + k) * acc_len + si] + part[k];
+                for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 16);
+                part[r][k] = v;
+            }
+        // lane r writes row i0 + r
+        if (mrow) {
+#pragma unroll
+            for (int k = 0; k < NBG; ++k) {
+                double pr = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (r == l16) pr = part[r][k];
+                if (k < nbg) out[(int64_t)(bt0 + k) * nrows + im] = msc * macc[k] + pr;
+            }
         }
     }
 }
