@@ -944,6 +944,25 @@ void build_schedules(vp_plan_s *P) {
     P->vsplit_s = up(vsplit_s);
     P->vsplit_t = up(vsplit_t);
     VP_HIP(hipMemcpyAsync(T.v_slot, vslot.data(), 4 * vslot.size(), hipMemcpyHostToDevice, s));
+    // offsets present in each 16-column M2L tile (columns = box x density)
+    {
+        const int64_t ncols = (int64_t)m2l.size() * P->nbatch;
+        const int64_t ntiles = (ncols + 15) / 16;
+        std::vector<int32_t> tptr(1, 0), tops;
+        for (int64_t t = 0; t < ntiles; ++t) {
+            uint64_t mask = 0;
+            for (int64_t c = 16 * t; c < std::min(ncols, 16 * t + 16); ++c) {
+                const int b = m2l[c / P->nbatch];
+                for (int o = 0; o < NOFF; ++o)
+                    if (vslot[(size_t)b * NOFF + o] >= 0) mask |= 1ull << o;
+            }
+            for (int o = 0; o < NOFF; ++o)
+                if (mask >> o & 1) tops.push_back(o);
+            tptr.push_back((int32_t)tops.size());
+        }
+        P->m2l_tptr = up(tptr);
+        P->m2l_tops = up(tops);
+    }
     P->xr_ptr = up(xr_ptr);
     P->xr_idx = up(xr_idx);
     P->n_x_boxes = (int)xb.size();
@@ -1144,6 +1163,8 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
             sa.ncols = a.ncols;
             sa.nbatch = nb;
             sa.slots = T.v_slot;
+            sa.tile_ptr = P->m2l_tptr;
+            sa.tile_ops = P->m2l_tops;
             sa.P = Pn;
             sa.in = a.in;
             sa.out = a.out;

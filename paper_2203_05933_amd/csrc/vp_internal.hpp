@@ -231,6 +231,8 @@ struct vp_plan_s {
     void *Mexp = nullptr;    // [nbox + 4 n_vleaf][nbatch][PD] (double or float)
     void *Lexp = nullptr;
     int32_t *m2l_cols = nullptr;  // boxes of levels >= 2, grouped by child class
+    int32_t *m2l_tptr = nullptr;  // offsets present per 16-column tile of (box, density) columns
+    int32_t *m2l_tops = nullptr;
     int32_t *child_slot = nullptr;   // [nbox][4] child in each quadrant or -1
     int32_t *l2l_slot = nullptr;     // [nbox][4] parent in the slot of the box's class
     int n_m2l_boxes = 0;

@@ -16,8 +16,8 @@
 //
 // Work split: a 16-column tile (boxes x densities, grouped by child class
 // so the tile shares its offsets) per workgroup; the four waves take every
-// fourth offset present in the tile and their partial sums are added
-// through LDS in a fixed order.
+// fourth offset present in the tile (listed at plan time) and their partial
+// sums are added through LDS in a fixed order.
 #pragma once
 
 #include "vp_translate.hpp"
@@ -29,6 +29,8 @@ struct M2LScaledArgs {
     int ncols;                // (box, density) columns
     int nbatch;
     const int32_t *slots;     // [box][NOFF] source box or -1
+    const int32_t *tile_ptr;  // offsets present in 16-column tile t: tile_ops[tile_ptr[t] .. tile_ptr[t+1])
+    const int32_t *tile_ops;
     int P;                    // complex coefficients per expansion
     ColAddr in, out;          // expansion columns (PD rows: re 0..P-1, im P..2P-1)
     int PD;
@@ -69,36 +71,58 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
         for (int i = 0; i < 4; ++i) br[r][i] = bi[r][i] = 0.0;
     double a0r = 0.0, a0i = 0.0;  // sum of A_0 over the sources (lanes g == 0)
 
-    int it = 0;
-    for (int o = 0; o < NOFF; ++o) {
-        const int src = valid ? a.slots[(int64_t)box * NOFF + o] : -1;
-        if (__ballot(src >= 0) == 0ull) continue;
-        const bool mine = (it & 3) == wave;
-        ++it;
-        if (!mine) continue;
+    // this wave's offsets: every fourth one present in the tile; the source
+    // columns of the next offset are loaded while the current one is on the
+    // matrix cores
+    const int e1 = a.tile_ptr[blockIdx.x + 1];
+    int e = a.tile_ptr[blockIdx.x] + wave;
+    int o = 0, src = -1;
+    TM xr[S], xi[S];
+    if (e < e1) {
+        o = a.tile_ops[e];
+        src = valid ? a.slots[(int64_t)box * NOFF + o] : -1;
         const TI *ip = in + (src >= 0 ? a.in.off(src) + (int64_t)bt * a.in.bstride : 0);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int k = 4 * s + g;
+            const bool ok = src >= 0 && k < P;
+            xr[s] = ok ? (TM)ip[k] : (TM)0;
+            xi[s] = ok ? (TM)ip[P + k] : (TM)0;
+        }
+    }
+    while (e < e1) {
         const TM *ti = tin + (size_t)o * PQ * 2;
         TM yr[S], yi[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int k = 4 * s + g;
-            TM xr = (TM)0, xi = (TM)0;
-            if (src >= 0 && k < P) {
-                xr = (TM)ip[k];
-                xi = (TM)ip[P + k];
-            }
             const TM wr = ti[2 * k], wi = ti[2 * k + 1];
-            yr[s] = xr * wr - xi * wi;
-            yi[s] = xr * wi + xi * wr;
+            yr[s] = xr[s] * wr - xi[s] * wi;
+            yi[s] = xr[s] * wi + xi[s] * wr;
         }
         if (g == 0 && src >= 0) {
             // A_0 log(-t): the offset-dependent part of the k = 0 column
-            const double xr = (double)ip[0], xi = (double)ip[P];
+            const double x0r = (double)xr[0], x0i = (double)xi[0];
             const double lr = logt[2 * o], li = logt[2 * o + 1];
-            br[0][M::item_of(0)] += xr * lr - xi * li;
-            bi[0][M::item_of(0)] += xr * li + xi * lr;
-            a0r += xr;
-            a0i += xi;
+            br[0][M::item_of(0)] += x0r * lr - x0i * li;
+            bi[0][M::item_of(0)] += x0r * li + x0i * lr;
+            a0r += x0r;
+            a0i += x0i;
+        }
+        // prefetch the next offset's source columns
+        const int en = e + 4;
+        int on = 0, srcn = -1;
+        if (en < e1) {
+            on = a.tile_ops[en];
+            srcn = valid ? a.slots[(int64_t)box * NOFF + on] : -1;
+            const TI *ip = in + (srcn >= 0 ? a.in.off(srcn) + (int64_t)bt * a.in.bstride : 0);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int k = 4 * s + g;
+                const bool ok = srcn >= 0 && k < P;
+                xr[s] = ok ? (TM)ip[k] : (TM)0;
+                xi[s] = ok ? (TM)ip[P + k] : (TM)0;
+            }
         }
         typename M::acc_t zr[RB], zi[RB];
 #pragma unroll
@@ -120,10 +144,13 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
             for (int i = 0; i < 4; ++i) {
                 const int l = r * 16 + M::row(i, g);
                 const double vr = (double)to[2 * l], vi = (double)to[2 * l + 1];
-                const double xr = (double)zr[r][i], xi = (double)zi[r][i];
-                br[r][i] += xr * vr - xi * vi;
-                bi[r][i] += xr * vi + xi * vr;
+                const double zre = (double)zr[r][i], zim = (double)zi[r][i];
+                br[r][i] += zre * vr - zim * vi;
+                bi[r][i] += zre * vi + zim * vr;
             }
+        e = en;
+        o = on;
+        src = srcn;
     }
     // fixed-order sum of the four waves' partial results
     if (wave > 0) {
