@@ -1157,6 +1157,8 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     P->stage_begin(VP_STAGE_M2L);
     {
         TranslateArgs a = expansion_args(P, P->m2l_cols, P->n_m2l_boxes, T.v_slot, NOFF, 2 * Pn);
+        a.tile_ptr = P->m2l_tptr;
+        a.tile_ops = P->m2l_tops;
         if (P->m2l_mode == VP_M2L_FP64_SCALED || P->m2l_mode == VP_M2L_FP32_SCALED) {
             M2LScaledArgs sa;
             sa.cols_box = P->m2l_cols;
@@ -1260,7 +1262,7 @@ static void run_p2p(vp_plan_s *P, const PointRoles &R, const int32_t *leaves, in
 }
 
 // Near-field tables of congruent leaves: acc[:, leaf] += sum_o K_{l,o} q[:, nbr_o(leaf)],
-// all table levels in one launch (operator index = level block * 9 + offset).
+// all table levels in one launch (operator index = level block * NTOPS + slot).
 template <int RB>
 static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     NearTables &N = P->near;
@@ -1270,7 +1272,9 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     a.ncols = N.tab_cols_begin.back() * P->nbatch;
     a.nbatch = P->nbatch;
     a.slots = N.tab_slot;
-    a.nops = 9 * (int)N.tab_levels.size();
+    a.nops = NTOPS * (int)N.tab_levels.size();
+    a.tile_ptr = N.tile_ptr;
+    a.tile_ops = N.tile_ops;
     a.in = ColAddr{R.nsrc, 0, R.sb};
     a.out = ColAddr{R.ntgt, 0, R.tb};
     a.nrows_out = N.npat;

@@ -155,6 +155,9 @@ struct Operators {
     float *m2l_q32 = nullptr, *m2l_tin32 = nullptr, *m2l_tout32 = nullptr;
 };
 
+// near-field table slots per target level: 9 same level, 16 coarser, 16 finer
+constexpr int NTOPS = 41;
+
 // Congruent-leaf path (uniform box grids): near-field tables, P2M/L2P
 // operators of the node pattern, and the leftover pairwise lists.
 struct NearTables {
@@ -164,8 +167,10 @@ struct NearTables {
     std::vector<int> tab_levels;      // levels holding table columns
     std::vector<int> tab_cols_begin;  // per entry of tab_levels, offsets into tab_cols
     int32_t *tab_cols = nullptr;      // table target leaves, grouped by level
-    int32_t *tab_slot = nullptr;      // [nbox][9] neighbour leaf per offset or -1
-    double *K = nullptr;              // [tab level][9] near matrices, A-fragment order
+    int32_t *tab_slot = nullptr;      // [nbox][41 * table levels] table source per slot or -1
+    int32_t *tile_ptr = nullptr;      // slots present per 16-column tile of table columns
+    int32_t *tile_ops = nullptr;
+    double *K = nullptr;              // [tab level][41] near matrices, A-fragment order
     int32_t *pair_uptr = nullptr;     // U lists minus the table-served entries
     int32_t *pair_uidx = nullptr;
     int64_t rest_len = 0;

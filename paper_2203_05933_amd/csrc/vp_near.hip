@@ -5,13 +5,16 @@
 // corrections once as a lookup table because G(r, r0) = G(r - r0) is
 // translation invariant (Section 4.2, eq. Vkhat_box).  The same invariance
 // makes the smooth-rule near field between two leaves that are congruent
-// copies of one node pattern a FIXED matrix per (level, neighbour offset):
-//     u_i += sum_j K_o[i][j] q_j,  K_o[i][j] = -(1/(4 pi)) log(h^2 |xi_j + o - xi_i|^2)
+// copies of one node pattern a FIXED matrix per (level, relative position):
+//     u_i += sum_j K_o[i][j] q_j,  K_o[i][j] = -(1/(4 pi)) log(h^2 |c_o + m xi_j - xi_i|^2)
 // (zero for a zero-distance pair), where xi are pattern coordinates in box
-// units.  Likewise the scaled P2M and L2P of such a leaf are fixed matrices
-// (powers of the pattern).  All three run on matrix cores through the
-// gather-GEMM kernel.  Leaves that are not copies of the pattern, and pairs
-// across levels, keep the pairwise / series kernels.
+// units, h the target leaf's side, m the source/target size ratio (1, or 2
+// and 1/2 for adjacent leaves one level apart) and c_o the source centre
+// relative to the target's in units of h.  Likewise the scaled P2M and L2P
+// of such a leaf are fixed matrices (powers of the pattern).  All three run
+// on matrix cores through the gather-GEMM kernel.  Leaves that are not
+// copies of the pattern, and pairs further apart in level, keep the
+// pairwise / series kernels.
 //
 // A leaf matches the reference pattern when it holds exactly npat points
 // whose box-relative coordinates (x - c)/h agree with the pattern's to
@@ -147,10 +150,14 @@ void build_near_tables(vp_plan_s *P) {
     N.active = npat > 0;
     N.npat = npat;
 
-    // --- U lists split: table slots for same-level pattern pairs, rest pairwise
-    std::vector<int32_t> tslot((size_t)nbox * 9, -1), rptr(nbox + 1, 0), ridx;
+    // --- U lists split: table slots for pattern-leaf pairs on the same level
+    // or one level apart, the rest pairwise.  Slot layout per target level
+    // (NTOPS = 41): 0..8 same-level neighbour (dx, dy) in -1..1; 9..24 a coarser
+    // leaf (side 2h) whose corner lies at (ox, oy) target widths from the
+    // target's corner, ox, oy in -2..1; 25..40 a finer leaf (side h/2) at
+    // (ox, oy) half widths, ox, oy in -1..2.
+    std::vector<int32_t> tslot((size_t)nbox * NTOPS, -1), rptr(nbox + 1, 0), ridx;
     ridx.reserve(uidx.size());
-    std::vector<int> tab_levels;
     std::vector<std::vector<int32_t>> cols_by_level(T.nlevels);
     for (int b = 0; b < nbox; ++b) {
         rptr[b] = (int32_t)ridx.size();
@@ -158,9 +165,20 @@ void build_near_tables(vp_plan_s *P) {
         bool used = false;
         for (int e = uptr[b]; e < uptr[b + 1]; ++e) {
             const int a = uidx[e];
-            if (pt && flag[a] && lev[a] == lev[b]) {
-                const int o = (iy[a] - iy[b] + 1) * 3 + (ix[a] - ix[b] + 1);
-                tslot[(size_t)b * 9 + o] = a;
+            int o = -1;
+            if (pt && flag[a]) {
+                if (lev[a] == lev[b]) {
+                    o = (iy[a] - iy[b] + 1) * 3 + (ix[a] - ix[b] + 1);
+                } else if (lev[a] == lev[b] - 1) {
+                    const int ox = 2 * ix[a] - ix[b], oy = 2 * iy[a] - iy[b];
+                    if (ox >= -2 && ox <= 1 && oy >= -2 && oy <= 1) o = 9 + (oy + 2) * 4 + (ox + 2);
+                } else if (lev[a] == lev[b] + 1) {
+                    const int ox = ix[a] - 2 * ix[b], oy = iy[a] - 2 * iy[b];
+                    if (ox >= -1 && ox <= 2 && oy >= -1 && oy <= 2) o = 25 + (oy + 1) * 4 + (ox + 1);
+                }
+            }
+            if (o >= 0) {
+                tslot[(size_t)b * NTOPS + o] = a;
                 used = true;
             } else {
                 ridx.push_back(a);
@@ -223,36 +241,71 @@ void build_near_tables(vp_plan_s *P) {
     N.tab_cols_begin.push_back((int)tcols.size());
     N.tab_cols = upload(P, tcols);
     {
-        // one slot row per box spanning all table levels: the 9 slots of the
-        // box's own level block hold its neighbours, every other slot is -1
+        // one slot row per box spanning all table levels: the NTOPS slots of
+        // the box's own level block hold its table sources, every other slot is -1
         const int nt = (int)N.tab_levels.size();
         std::vector<int32_t> lvl_block(T.nlevels, -1);
         for (int li = 0; li < nt; ++li) lvl_block[N.tab_levels[li]] = li;
-        std::vector<int32_t> wide((size_t)nbox * 9 * std::max(nt, 1), -1);
+        const size_t wrow = (size_t)NTOPS * std::max(nt, 1);
+        std::vector<int32_t> wide((size_t)nbox * wrow, -1);
         for (int b = 0; b < nbox; ++b) {
             const int li = lvl_block[lev[b]];
             if (li < 0) continue;
-            for (int o = 0; o < 9; ++o) wide[((size_t)b * nt + li) * 9 + o] = tslot[(size_t)b * 9 + o];
+            for (int o = 0; o < NTOPS; ++o) wide[(size_t)b * wrow + (size_t)li * NTOPS + o] = tslot[(size_t)b * NTOPS + o];
         }
         N.tab_slot = upload(P, wide);
+        // operators present per 16-column tile of (table leaf, density) columns
+        const int64_t ncols = (int64_t)tcols.size() * P->nbatch;
+        std::vector<int32_t> tptr(1, 0), tops;
+        std::vector<char> seen(wrow);
+        for (int64_t t = 0; t * 16 < ncols; ++t) {
+            std::fill(seen.begin(), seen.end(), 0);
+            for (int64_t c = 16 * t; c < std::min(ncols, 16 * t + 16); ++c) {
+                const int b = tcols[c / P->nbatch];
+                for (size_t o = 0; o < wrow; ++o)
+                    if (wide[(size_t)b * wrow + o] >= 0) seen[o] = 1;
+            }
+            for (size_t o = 0; o < wrow; ++o)
+                if (seen[o]) tops.push_back((int32_t)o);
+            tptr.push_back((int32_t)tops.size());
+        }
+        N.tile_ptr = upload(P, tptr);
+        N.tile_ops = upload(P, tops);
     }
 
     if (N.active) {
         const int np = npat;
-        // near-field matrices per level, A-fragment order (rows = targets, cols = sources)
-        std::vector<double> K((size_t)N.tab_levels.size() * 9 * np * np), R((size_t)np * np);
+        // near-field matrices per target level and slot, A-fragment order
+        // (rows = targets, cols = sources).  In units of the target side h a
+        // source j sits at c + m xi_j relative to the target centre, target i
+        // at xi_i: same level m = 1, c = (dx, dy); coarser m = 2,
+        // c = (ox + 1/2, oy + 1/2); finer m = 1/2, c = ((ox - 1/2)/2, (oy - 1/2)/2).
+        std::vector<double> K((size_t)N.tab_levels.size() * NTOPS * np * np, 0.0), R((size_t)np * np);
         for (size_t li = 0; li < N.tab_levels.size(); ++li) {
             const double h = T.side[N.tab_levels[li]];
             const double two_log_h = 2.0 * std::log(h);
-            for (int o = 0; o < 9; ++o) {
-                const double dx = (o % 3) - 1, dy = (o / 3) - 1;
+            for (int o = 0; o < NTOPS; ++o) {
+                double cxo, cyo, m;
+                if (o < 9) {
+                    cxo = (o % 3) - 1;
+                    cyo = (o / 3) - 1;
+                    m = 1.0;
+                } else if (o < 25) {
+                    cxo = ((o - 9) % 4 - 2) + 0.5;
+                    cyo = ((o - 9) / 4 - 2) + 0.5;
+                    m = 2.0;
+                } else {
+                    cxo = (((o - 25) % 4 - 1) - 0.5) * 0.5;
+                    cyo = (((o - 25) / 4 - 1) - 0.5) * 0.5;
+                    m = 0.5;
+                }
                 for (int i = 0; i < np; ++i)
                     for (int j = 0; j < np; ++j) {
-                        const double ex = rx[j] + dx - rx[i], ey = ry[j] + dy - ry[i];
+                        const double ex = cxo + m * rx[j] - rx[i], ey = cyo + m * ry[j] - ry[i];
                         const double r2 = ex * ex + ey * ey;
                         R[(size_t)i * np + j] = (r2 == 0.0) ? 0.0 : -INV_4PI * (std::log(r2) + two_log_h);
                     }
-                vp_to_frag(R.data(), np, np, np, K.data() + ((size_t)li * 9 + o) * np * np);
+                vp_to_frag(R.data(), np, np, np, K.data() + ((size_t)li * NTOPS + o) * np * np);
             }
         }
         N.K = upload(P, K);

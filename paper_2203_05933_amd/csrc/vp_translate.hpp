@@ -73,6 +73,10 @@ struct TranslateArgs {
     int logrow;               // >= 0: row holding sum Re A_0 (M2L); -1 otherwise
     const int32_t *level;
     const double *logside;
+    // optional: operators present in 16-column tile t, tile_ops[tile_ptr[t] ..
+    // tile_ptr[t+1]) (k_translate_split only; null = scan all nops slots)
+    const int32_t *tile_ptr = nullptr;
+    const int32_t *tile_ops = nullptr;
 };
 
 // TI/TO: element types of input/output columns; TM: matrix-core type;
@@ -186,13 +190,19 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
     typename M::acc_t acc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r] = M::zero();
+    const bool listed = a.tile_ptr != nullptr;
+    const int e0 = listed ? a.tile_ptr[blockIdx.x] : 0;
+    const int e1 = listed ? a.tile_ptr[blockIdx.x + 1] : a.nops;
     int it = 0;  // index among the tile's active operators
-    for (int o = 0; o < a.nops; ++o) {
+    for (int e = e0 + (listed ? wave : 0); e < e1; e += listed ? 4 : 1) {
+        const int o = listed ? a.tile_ops[e] : e;
         const int src = valid ? a.slots[(int64_t)box * a.nops + o] : -1;
-        if (__ballot(src >= 0) == 0ull) continue;
-        const bool mine = (it & 3) == wave;
-        ++it;
-        if (!mine) continue;
+        if (!listed) {
+            if (__ballot(src >= 0) == 0ull) continue;
+            const bool mine = (it & 3) == wave;
+            ++it;
+            if (!mine) continue;
+        }
         TM bv[S];
         const TI *ip = in + (src >= 0 ? a.in.off(src) + (int64_t)bt * a.in.bstride : 0) + g;
 #pragma unroll
