@@ -538,28 +538,56 @@ __device__ inline double vp_log(double x) {
     return fma(de, LN2_HI, fma(de, LN2_LO, logm));
 }
 
+// Table-driven logarithm for the pairwise near field (the table-lookup
+// scheme of P. T. P. Tang, ACM TOMS 16, 1990, with our own table and series):
+// x = 2^e m, m in [1/2, 1); the top 7 fraction bits i of m select
+// inv_c = fl(1/c_i), c_i the centre of m's interval of width 2^-8, and
+// L_i = -log(inv_c) (both from the host, LOG_TABLE entries);
+// u = m inv_c - 1 (one rounding, |u| <= 2^-8) and
+// log x = e log 2 + L_i + log1p(u), log1p by its Taylor series through u^6
+// (truncation below 2^-60).
+__device__ inline double vp_log_tab(double x, const double2 *__restrict__ tab) {
+    const double LN2_HI = 6.93147180369123816490e-01;
+    const double LN2_LO = 1.90821492927058770002e-10;
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const double m = __builtin_amdgcn_frexp_mant(x);
+    const int i = (__double2hiint(m) >> 13) & (LOG_TABLE - 1);
+    const double2 t = tab[i];
+    const double u = fma(m, t.x, -1.0);
+    double p = fma(u, -1.0 / 6.0, 1.0 / 5.0);
+    p = fma(u, p, -0.25);
+    p = fma(u, p, 1.0 / 3.0);
+    p = fma(u, p, -0.5);
+    p = fma(u, p, 1.0);
+    const double de = (double)e;
+    return fma(de, LN2_HI, fma(de, LN2_LO, fma(u, p, t.y)));
+}
+
 // ----------------------------------------------------------------------------
 // P2P (U lists), FP64: one wave per target leaf.  All source points of the
 // leaf's list are staged in LDS (SoA x, y, q per density) in tiles of
-// P2P_CAP points, so a leaf with many small neighbours pays one barrier
+// P2PCap points, so a leaf with many small neighbours pays one barrier
 // pair per tile.  When a leaf has few targets the lanes also split the
 // source loop (K lane groups) and the partial sums are combined in a fixed
-// order.  Pairs at zero distance (the self pair) contribute nothing; the
-// logarithm is branch-free (log 1 = 0 stands in for them).
+// order.  Pairs at zero distance (the self pair) contribute nothing (a
+// select after the branch-free logarithm).
 // ----------------------------------------------------------------------------
 template <int NB>
 struct P2PCap {
-    static constexpr int value = NB <= 1 ? 512 : (NB <= 2 ? 384 : (NB <= 4 ? 256 : (NB <= 8 ? 160 : 96)));
+    // small tiles keep a one-wave block's LDS at a few KB, so many waves share a CU
+    static constexpr int value = NB <= 2 ? 128 : (NB <= 4 ? 96 : (NB <= 8 ? 64 : 48));
 };
 
-template <int NB, bool GRAD, bool ACCUM>
+template <int NB, bool GRAD, bool ACCUM, bool GATHER>
 __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restrict__ leaves,
                                             const int32_t *__restrict__ uptr,
-                                            const int32_t *__restrict__ uidx,
+                                            const int32_t *__restrict__ uidx, P2PGather gs,
                                             const double *__restrict__ q, int nbatch, int bt0,
-                                            double *__restrict__ acc) {
+                                            const double2 *__restrict__ logtab, double *__restrict__ acc) {
     constexpr int CAP = P2PCap<NB>::value;
     __shared__ double xs[CAP], ys[CAP];
+    __shared__ double2 ltab[LOG_TABLE];
+    for (int i = threadIdx.x; i < LOG_TABLE; i += 64) ltab[i] = logtab[i];
     __shared__ double qs[NB][CAP];
     __shared__ double red[GRAD ? 2 * NB : NB][64];
     const int lane = threadIdx.x;
@@ -581,11 +609,25 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
 #pragma unroll
         for (int k = 0; k < NB; ++k) a[k] = gxa[k] = gya[k] = 0.0;
         int e = e0, eoff = 0;
-        while (e < e1) {
+        int64_t gp = GATHER ? gs.ptr[blockIdx.x] : 0;
+        const int64_t gend = GATHER ? gs.ptr[blockIdx.x + 1] : 0;
+        while (GATHER ? gp < gend : e < e1) {
             // fill one tile from the list, continuing inside a leaf if needed
             __syncthreads();
             int fill = 0;
-            while (e < e1 && fill < CAP) {
+            if (GATHER) {
+                // sources gathered at plan time: contiguous coordinates, indexed charges
+                fill = (int)min((int64_t)CAP, gend - gp);
+                for (int j = lane; j < fill; j += 64) {
+                    xs[j] = gs.x[gp + j];
+                    ys[j] = gs.y[gp + j];
+                    const int sj = gs.idx[gp + j];
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) qs[k][j] = (k < nbh) ? q[(int64_t)(bt0 + k) * R.nsrc + sj] : 0.0;
+                }
+                gp += fill;
+            }
+            while (!GATHER && e < e1 && fill < CAP) {
                 const int src = uidx[e];
                 const int s0 = R.sb[src] + eoff, s1 = R.se[src];
                 const int take = min(s1 - s0, CAP - fill);
@@ -606,7 +648,7 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
             }
             __syncthreads();
             if (act) {
-#pragma unroll 2
+#pragma unroll 4
                 for (int j = kg; j < fill; j += K) {
                     const double dx = xs[j] - px, dy = ys[j] - py;
                     const double r2 = fma(dx, dx, dy * dy);
@@ -624,7 +666,7 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
                             gya[k] = fma(c, dy, gya[k]);
                         }
                     } else {
-                        const double lg = vp_log(nz ? r2 : 1.0);
+                        const double lg = nz ? vp_log_tab(r2, ltab) : 0.0;
 #pragma unroll
                         for (int k = 0; k < NB; ++k) a[k] = fma(qs[k][j], lg, a[k]);
                     }
@@ -1228,34 +1270,39 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
 
 template <int NB, bool GRAD, bool ACCUM>
 static void launch_p2p(vp_plan_s *P, const PointRoles &R, const int32_t *leaves, int nleaves, const int32_t *uptr,
-                       const int32_t *uidx, int bt0, double *acc) {
+                       const int32_t *uidx, const P2PGather *gs, int bt0, double *acc) {
     if (nleaves <= 0) return;
-    hipLaunchKernelGGL((k_p2p<NB, GRAD, ACCUM>), dim3(nleaves), dim3(64), 0, P->stream, R, leaves, uptr, uidx, P->q,
-                       P->nbatch, bt0, acc);
+    const double2 *lt = (const double2 *)P->ops.log_table;
+    if (gs && gs->ptr)
+        hipLaunchKernelGGL((k_p2p<NB, GRAD, ACCUM, true>), dim3(nleaves), dim3(64), 0, P->stream, R, leaves, uptr,
+                           uidx, *gs, P->q, P->nbatch, bt0, lt, acc);
+    else
+        hipLaunchKernelGGL((k_p2p<NB, GRAD, ACCUM, false>), dim3(nleaves), dim3(64), 0, P->stream, R, leaves, uptr,
+                           uidx, P2PGather(), P->q, P->nbatch, bt0, lt, acc);
     VP_LAUNCH_CHECK();
 }
 
 // Pairwise near field over (leaves, U lists); densities in groups of 16/8/4/2/1.
 template <bool GRAD, bool ACCUM>
 static void run_p2p(vp_plan_s *P, const PointRoles &R, const int32_t *leaves, int nleaves, const int32_t *uptr,
-                    const int32_t *uidx, double *acc) {
+                    const int32_t *uidx, const P2PGather *gs, double *acc) {
     int nb = P->nbatch;
     for (int bt0 = 0; bt0 < nb;) {
-        int left = nb - bt0;
+        const int left = nb - bt0;
         if (left >= 16) {
-            launch_p2p<16, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
+            launch_p2p<16, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, gs, bt0, acc);
             bt0 += 16;
         } else if (left >= 8) {
-            launch_p2p<8, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
+            launch_p2p<8, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, gs, bt0, acc);
             bt0 += 8;
         } else if (left >= 4) {
-            launch_p2p<4, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
+            launch_p2p<4, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, gs, bt0, acc);
             bt0 += 4;
         } else if (left >= 2) {
-            launch_p2p<2, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
+            launch_p2p<2, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, gs, bt0, acc);
             bt0 += 2;
         } else {
-            launch_p2p<1, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, bt0, acc);
+            launch_p2p<1, GRAD, ACCUM>(P, R, leaves, nleaves, uptr, uidx, gs, bt0, acc);
             bt0 += 1;
         }
     }
@@ -1403,11 +1450,13 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
     }
     P->stage_begin(VP_STAGE_P2P);
     if (grad) {
-        run_p2p<true, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0], P->acc);
+        run_p2p<true, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0], nullptr, P->acc);
     } else if (tables) {
-        run_p2p<false, true>(P, R, N.rest_leaves, N.n_rest_leaves, N.pair_uptr, N.pair_uidx, P->acc);
+        run_p2p<false, true>(P, R, N.rest_leaves, N.n_rest_leaves, N.pair_uptr, N.pair_uidx, &N.g_rest, P->acc);
     } else {
-        run_p2p<false, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0], P->acc);
+        run_p2p<false, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0],
+                              adjoint && !P->self ? &P->g_adj : &P->g_fwd,
+                              P->acc);
     }
     P->stage_end(VP_STAGE_P2P);
     if (T.nlevels >= 3) {

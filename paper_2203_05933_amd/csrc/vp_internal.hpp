@@ -145,6 +145,7 @@ struct Operators {
     int PR = 0;
     double *sh_qt64[2] = {nullptr, nullptr}, *sh_tin64[2] = {nullptr, nullptr}, *sh_tout64[2] = {nullptr, nullptr};
     float *sh_qt32[2] = {nullptr, nullptr}, *sh_tin32[2] = {nullptr, nullptr}, *sh_tout32[2] = {nullptr, nullptr};
+    double *log_table = nullptr;  // [LOG_TABLE][2]: fl(1/c_i), -log(fl(1/c_i)) (pairwise logarithm)
     double *inv_k = nullptr;  // 1/k, k = 0..P-1 (0 for k = 0)
     float *inv_k_f32 = nullptr;
     // M2L in diagonally scaled form: one real matrix Q (A-fragment order,
@@ -157,6 +158,20 @@ struct Operators {
 
 // near-field table slots per target level: 9 same level, 16 coarser, 16 finer
 constexpr int NTOPS = 41;
+// entries of the logarithm table of the pairwise near field (top fraction bits of the mantissa)
+constexpr int LOG_TABLE = 128;
+
+// Pairwise near-field sources of a list of target leaves, gathered once at
+// plan time (static geometry): for leaf k of the list, entries
+// [ptr[k], ptr[k+1]) hold the sorted indices and coordinates of every source
+// point in its U list, in list order, so the kernel stages them with
+// contiguous loads.
+struct P2PGather {
+    int64_t *ptr = nullptr;
+    int32_t *idx = nullptr;
+    double *x = nullptr, *y = nullptr;
+    int64_t len = 0;
+};
 
 // Congruent-leaf path (uniform box grids): near-field tables, P2M/L2P
 // operators of the node pattern, and the leftover pairwise lists.
@@ -176,6 +191,7 @@ struct NearTables {
     int64_t rest_len = 0;
     int32_t *rest_leaves = nullptr;   // leaves with a non-empty leftover list
     int n_rest_leaves = 0;
+    P2PGather g_rest;                 // sources of the leftover lists
     int32_t *ident_slot = nullptr;    // [nbox] slot table b -> b (one-operator launches)
     int32_t *p2m_pat = nullptr, *p2m_rest = nullptr;  // leaves (level >= 2) by kind
     int n_p2m_pat = 0, n_p2m_rest = 0;
@@ -235,6 +251,7 @@ struct vp_plan_s {
     double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order
     void *Mexp = nullptr;    // [nbox + 4 n_vleaf][nbatch][PD] (double or float)
     void *Lexp = nullptr;
+    vp::P2PGather g_fwd, g_adj;   // full U-list sources (nodes / targets as sources) without tables
     int32_t *m2l_cols = nullptr;  // boxes of levels >= 2, grouped by child class
     int32_t *m2l_tptr = nullptr;  // offsets present per 16-column tile of (box, density) columns
     int32_t *m2l_tops = nullptr;
@@ -290,6 +307,10 @@ void build_near_tables(vp_plan_s *P);  // vp_near.hip
 void build_schedules(vp_plan_s *P);
 // congruent-leaf operators exist for this pattern size and expansion size
 bool pattern_op_supported(int npat, int PD);
+// gather the U-list sources of `leaves` (host CSR uptr/uidx, source ranges sb/se; device coordinates sx/sy)
+void build_p2p_gather(vp_plan_s *P, const std::vector<int32_t> &leaves, const std::vector<int32_t> &uptr,
+                      const std::vector<int32_t> &uidx, const std::vector<int32_t> &sb, const std::vector<int32_t> &se,
+                      const double *sx, const double *sy, P2PGather &g);
 void run_fmm(vp_plan_s *P, bool adjoint, bool grad);
 void prepare_charges(vp_plan_s *P, const double *f, bool adjoint);
 void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint);

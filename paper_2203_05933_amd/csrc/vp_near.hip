@@ -66,6 +66,41 @@ static T *upload(vp_plan_s *P, const std::vector<T> &h) {
     return d;
 }
 
+__global__ void k_gather_idx_f64(const double *__restrict__ in, const int32_t *__restrict__ idx,
+                                 double *__restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[idx[i]];
+}
+
+void build_p2p_gather(vp_plan_s *P, const std::vector<int32_t> &leaves, const std::vector<int32_t> &uptr,
+                      const std::vector<int32_t> &uidx, const std::vector<int32_t> &sb, const std::vector<int32_t> &se,
+                      const double *sx, const double *sy, P2PGather &g) {
+    std::vector<int64_t> ptr(1, 0);
+    ptr.reserve(leaves.size() + 1);
+    for (int b : leaves) {
+        int64_t c = 0;
+        for (int e = uptr[b]; e < uptr[b + 1]; ++e) c += se[uidx[e]] - sb[uidx[e]];
+        ptr.push_back(ptr.back() + c);
+    }
+    std::vector<int32_t> idx((size_t)ptr.back());
+    size_t k = 0;
+    for (int b : leaves)
+        for (int e = uptr[b]; e < uptr[b + 1]; ++e)
+            for (int j = sb[uidx[e]]; j < se[uidx[e]]; ++j) idx[k++] = j;
+    g.len = ptr.back();
+    g.ptr = upload(P, ptr);
+    g.idx = upload(P, idx);
+    g.x = P->mem.alloc<double>((size_t)std::max<int64_t>(g.len, 1));
+    g.y = P->mem.alloc<double>((size_t)std::max<int64_t>(g.len, 1));
+    if (g.len > 0) {
+        const unsigned blocks = (unsigned)((g.len + 255) / 256);
+        hipLaunchKernelGGL(k_gather_idx_f64, dim3(blocks), dim3(256), 0, P->stream, sx, g.idx, g.x, g.len);
+        hipLaunchKernelGGL(k_gather_idx_f64, dim3(blocks), dim3(256), 0, P->stream, sy, g.idx, g.y, g.len);
+        VP_LAUNCH_CHECK();
+    }
+    VP_HIP(hipStreamSynchronize(P->stream));  // host vectors leave scope
+}
+
 void build_near_tables(vp_plan_s *P) {
     Tree &T = P->tree;
     NearTables &N = P->near;
@@ -195,6 +230,20 @@ void build_near_tables(vp_plan_s *P) {
         if (rptr[b + 1] > rptr[b]) rest_leaves.push_back(b);
     N.rest_leaves = upload(P, rest_leaves);
     N.n_rest_leaves = (int)rest_leaves.size();
+    if (N.active) {
+        build_p2p_gather(P, rest_leaves, rptr, ridx, sb, se, P->sx, P->sy, N.g_rest);
+    } else {
+        // no tables: the full U lists, with nodes as sources (evaluation) and,
+        // for separate targets, targets as sources (adjoint)
+        build_p2p_gather(P, leaves, uptr, uidx, sb, se, P->sx, P->sy, P->g_fwd);
+        if (!P->self) {
+            std::vector<int32_t> tb(nbox), te(nbox);
+            VP_HIP(hipMemcpyAsync(tb.data(), T.tb, 4 * nbox, hipMemcpyDeviceToHost, s));
+            VP_HIP(hipMemcpyAsync(te.data(), T.te, 4 * nbox, hipMemcpyDeviceToHost, s));
+            VP_HIP(hipStreamSynchronize(s));
+            build_p2p_gather(P, leaves, uptr, uidx, tb, te, P->tx, P->ty, P->g_adj);
+        }
+    }
 
     // near-field pair count served by the pairwise kernel
     int64_t pairs = 0;

@@ -21,6 +21,7 @@
 // 2P, that sums Re A_0 so that the kernel can add A_0 log s for the
 // level of each target box.
 
+#include <cmath>
 #include <complex>
 #include <vector>
 
@@ -185,6 +186,15 @@ void build_operators(vp_plan_s *P) {
         logt[2 * code] = lg.real();
         logt[2 * code + 1] = lg.imag();
     }
+    // logarithm table of the pairwise near field: m in [1/2, 1) with top fraction
+    // bits i lies in [1/2 + i/256, 1/2 + (i+1)/256); c_i is that interval's centre
+    std::vector<double> ltab(2 * LOG_TABLE);
+    for (int i = 0; i < LOG_TABLE; ++i) {
+        const double c = 0.5 + (i + 0.5) / (2.0 * LOG_TABLE);
+        const double inv_c = 1.0 / c;
+        ltab[2 * i] = inv_c;
+        ltab[2 * i + 1] = (double)(-logl((long double)inv_c));
+    }
     std::vector<double> invk(Pn, 0.0);
     for (int k = 1; k < Pn; ++k) invk[k] = 1.0 / k;
 
@@ -206,6 +216,7 @@ void build_operators(vp_plan_s *P) {
         O.sh_tout64[w] = up(shout[w]);
     }
     O.inv_k = up(invk);
+    O.log_table = up(ltab);
     O.m2l_q64 = up(Qf);
     O.m2l_tin64 = up(tin);
     O.m2l_tout64 = up(tout);
