@@ -32,6 +32,42 @@ FP32_MFMA_TFLOPS = 157.3    # MI355X published peak, FP32 matrix (dense)
 P2P_FLOPS_PER_PAIR = 27     # 2 differences, 3 for r^2, 20 for log(r^2), 2 for the update
 
 
+# HBM bytes per launch of the star-workload kernels, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE) of this script, each scaled by what the
+# counter reads for a plain 1 GiB device copy in the same run (FETCH_SIZE
+# reads half the bytes, WRITE_SIZE all of them).  Valid only for the kernel
+# sources they were taken on: the digest below covers every file of the
+# library's source directory, and any change there turns traffic into null.
+TRAFFIC_DIGEST = "5e4bbe428415cd546034f8e6a9eaa60fe903a9bf1c3364d9791b05979483bee8"
+TRAFFIC_WORKLOAD = "star_adaptive"
+TRAFFIC = {  # stage -> (read bytes, written bytes) per launch, FP64 p = 30, one density
+    "finish": (795388880, 11904188),
+    "m2l": (211248016, 20255193),
+    "p2p": (94245385, 3550304),
+}
+
+
+def source_digest():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_05933_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage, workload_name, order, nbatch):
+    """Counter-measured HBM bytes per launch, or None when they do not apply."""
+    if stage not in TRAFFIC or workload_name != TRAFFIC_WORKLOAD or order != 30 or nbatch != 1:
+        return None
+    if source_digest() != TRAFFIC_DIGEST:
+        return None
+    r, w = TRAFFIC[stage]
+    return r + w
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -70,8 +106,17 @@ def time_evals(plan, f, u, steps, warmup):
     return dt, tim
 
 
-def stage_roofline(plan, tim, precision, stage):
+def stage_roofline(plan, tim, precision, stage, workload_name=None):
     """Roofline record of one single-kernel stage, or None when the stage has no model."""
+    rec = _stage_roofline(plan, tim, precision, stage)
+    if rec is not None and precision == "fp64":
+        info = plan.info()
+        rec["traffic"] = measured_traffic(stage, workload_name, info["order"], info["nbatch"])
+        rec["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
+    return rec
+
+
+def _stage_roofline(plan, tim, precision, stage):
     info = plan.info()
     n = max(tim["evals"], 1)
     avg_s = tim["ms"][stage] / n / 1e3
@@ -108,11 +153,11 @@ def stage_roofline(plan, tim, precision, stage):
     return None
 
 
-def roofline(plan, tim, precision):
+def roofline(plan, tim, precision, workload_name=None):
     """Roofline record of the single-kernel stage with the largest device time."""
     recs = {}
     for st in ("m2l", "p2p", "finish"):
-        r = stage_roofline(plan, tim, precision, st)
+        r = stage_roofline(plan, tim, precision, st, workload_name)
         if r is not None:
             recs[st] = r
     stage = max(recs, key=lambda k: recs[k]["avg_ms"])
@@ -131,6 +176,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (cpu_baseline and errors)")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="targets the oracle evaluates")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed loops, run one plain device copy (y = 2 x) of this many MiB read and "
+                         "written, as the calibration kernel for hardware byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -164,7 +212,7 @@ def main():
     value = wl.m * nb / (dt / args.steps) / 1e6
     log(f"[bench] fp64: {ms_per_step:.3f} ms/eval, {value:.1f} Mpoints/s; stages(ms/eval)="
         + json.dumps({k: round(v / max(tim['evals'], 1), 4) for k, v in tim["ms"].items()}))
-    stage, roof, roofs = roofline(plan, tim, "fp64")
+    stage, roof, roofs = roofline(plan, tim, "fp64", wl.name)
     u64 = u.clone()
 
     out32 = None
@@ -200,6 +248,16 @@ def main():
             rel32 = float(np.max(np.abs(got32 - ref)) / np.max(np.abs(ref)))
             out32["rel_err"] = rel32
         log(f"[bench] rel_inf err fp64={rel64:.3e} fp32={rel32}")
+
+    if args.copy_mib > 0:
+        n_el = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n_el, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.copy_mib} MiB read, {args.copy_mib} MiB written")
+        del src, dst
 
     rec = {
         "metric": METRIC,
