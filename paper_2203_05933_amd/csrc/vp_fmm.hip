@@ -405,22 +405,32 @@ __global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_
 // and, with grad, the gradient -(1/2pi) (Re phi', -Im phi').
 // ----------------------------------------------------------------------------
 template <class E, bool GRAD>
-__global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_t *__restrict__ leaves,
-                                            const int32_t *__restrict__ wptr,
-                                            const int32_t *__restrict__ widx, int nbatch, int P,
-                                            int PD, const E *__restrict__ Mexp,
-                                            const E *__restrict__ Lexp,
-                                            const int32_t *__restrict__ local_done,
-                                            double *__restrict__ acc) {
-    __shared__ E col[128];  // one expansion column, staged for broadcast reads
-    const int lane = threadIdx.x;
+__global__ void __launch_bounds__(256) k_far(PointRoles R, BoxGeo G, const int32_t *__restrict__ leaves,
+                                             const int32_t *__restrict__ wptr,
+                                             const int32_t *__restrict__ widx, int nbatch, int P,
+                                             int PD, const E *__restrict__ Mexp,
+                                             const E *__restrict__ Lexp,
+                                             const int32_t *__restrict__ local_done,
+                                             double *__restrict__ acc) {
+    // Four waves per leaf, all on the same 64 targets: wave 0 evaluates the
+    // local expansion, wave w takes every fourth W-list multipole from the
+    // w-th on (long W lists of large leaves no longer run on one wave), and
+    // the partial sums are added through LDS in a fixed order.  Each wave
+    // stages its current coefficient column in its own LDS row (a wave-local
+    // barrier suffices, so waves with different list lengths never wait on
+    // one another inside the loop).
+    constexpr int NR = GRAD ? 2 : 1;
+    __shared__ E colw[4][128];
+    __shared__ double red[3][NR][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    E *col = colw[wave];
     const int b = leaves[blockIdx.x];
     const int t0 = R.tb[b], t1 = R.te[b];
     if (t1 <= t0) return;
     const double cx = G.cx[b], cy = G.cy[b];
     const int lb = G.level[b];
     const double s = G.side[lb];
-    const bool has_local = lb >= 2 && !(local_done && local_done[b]);
+    const bool has_local = wave == 0 && lb >= 2 && !(local_done && local_done[b]);
     const int w0 = wptr[b], w1 = wptr[b + 1];
     for (int base = t0; base < t1; base += 64) {
         const int t = base + lane;
@@ -430,9 +440,10 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
         for (int bt = 0; bt < nbatch; ++bt) {
             C2<E> phi = {(E)0, (E)0}, dphi = {(E)0, (E)0};
             if (has_local) {
-                __syncthreads();
                 for (int k = lane; k < 2 * P; k += 64) col[k] = Lexp[((int64_t)b * nbatch + bt) * PD + k];
-                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll 4
                 for (int l = P - 1; l >= 0; --l) {
                     const E cre = col[l], cim = col[P + l];
@@ -449,14 +460,16 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
                     dphi.re /= (E)s;
                     dphi.im /= (E)s;
                 }
+                __builtin_amdgcn_wave_barrier();
             }
             double u = (double)phi.re;
             double gx = (double)dphi.re, gy = -(double)dphi.im;
-            for (int e = w0; e < w1; ++e) {
+            for (int e = w0 + wave; e < w1; e += 4) {
                 const int a = widx[e];
-                __syncthreads();
                 for (int k = lane; k < 2 * P; k += 64) col[k] = Mexp[((int64_t)a * nbatch + bt) * PD + k];
-                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 const double ax = G.cx[a], ay = G.cy[a], sa = G.side[G.level[a]];
                 const double dx = px - ax, dy = py - ay, d2 = dx * dx + dy * dy;
                 // iw = s_a / (z - c_a)
@@ -476,6 +489,7 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
                 }
                 ser = cmul(ser, iw);
                 const double a0 = (double)col[0];
+                __builtin_amdgcn_wave_barrier();  // all lanes done reading col before the next entry's writes
                 u += (double)ser.re + a0 * 0.5 * vp_log(d2);
                 if (GRAD) {
                     // phi' = (A_0 - sum_k k A_k iw^k) / (z - c)
@@ -487,11 +501,25 @@ __global__ void __launch_bounds__(64) k_far(PointRoles R, BoxGeo G, const int32_
                     gy -= nre * iim + nim * ire;
                 }
             }
-            if (act) {
+            // fixed-order sum of the four waves' partial results
+            __syncthreads();
+            if (wave > 0) {
                 if (GRAD) {
+                    red[wave - 1][0][lane] = gx;
+                    red[wave - 1][1][lane] = gy;
+                } else {
+                    red[wave - 1][0][lane] = u;
+                }
+            }
+            __syncthreads();
+            if (wave == 0 && act) {
+                if (GRAD) {
+                    gx = ((gx + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
+                    gy = ((gy + red[0][NR - 1][lane]) + red[1][NR - 1][lane]) + red[2][NR - 1][lane];
                     acc[((int64_t)bt * 2 + 0) * R.ntgt + t] += -INV_2PI * gx;
                     acc[((int64_t)bt * 2 + 1) * R.ntgt + t] += -INV_2PI * gy;
                 } else {
+                    u = ((u + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
                     acc[(int64_t)bt * R.ntgt + t] += -INV_2PI * u;
                 }
             }
@@ -1420,13 +1448,13 @@ static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *
     if (tables) {
         run_pattern_op<E>(P, R, false);
         if (N.n_far_leaves > 0) {
-            hipLaunchKernelGGL((k_far<E, GRAD>), dim3(N.n_far_leaves), dim3(64), 0, P->stream, R, G, N.far_leaves,
+            hipLaunchKernelGGL((k_far<E, GRAD>), dim3(N.n_far_leaves), dim3(256), 0, P->stream, R, G, N.far_leaves,
                                T.lptr[2], T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp,
                                (const E *)P->Lexp, N.local_done, acc);
             VP_LAUNCH_CHECK();
         }
     } else {
-        hipLaunchKernelGGL((k_far<E, GRAD>), dim3(T.nleaf), dim3(64), 0, P->stream, R, G, T.leaves, T.lptr[2],
+        hipLaunchKernelGGL((k_far<E, GRAD>), dim3(T.nleaf), dim3(256), 0, P->stream, R, G, T.leaves, T.lptr[2],
                            T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp, (const E *)P->Lexp,
                            (const int32_t *)nullptr, acc);
         VP_LAUNCH_CHECK();
