@@ -228,6 +228,13 @@ void build_near_tables(vp_plan_s *P) {
     std::vector<int32_t> rest_leaves;
     for (int b : leaves)
         if (rptr[b + 1] > rptr[b]) rest_leaves.push_back(b);
+    // longest lists first: the most expensive leaves start in the first wave of blocks
+    {
+        std::vector<int64_t> work(nbox, 0);
+        for (int b : rest_leaves)
+            for (int e = rptr[b]; e < rptr[b + 1]; ++e) work[b] += (int64_t)(se[b] - sb[b]) * (se[ridx[e]] - sb[ridx[e]]);
+        std::stable_sort(rest_leaves.begin(), rest_leaves.end(), [&](int x, int y) { return work[x] > work[y]; });
+    }
     N.rest_leaves = upload(P, rest_leaves);
     N.n_rest_leaves = (int)rest_leaves.size();
     if (N.active) {
@@ -272,6 +279,8 @@ void build_near_tables(vp_plan_s *P) {
     N.n_p2m_rest = (int)p2m_rest.size();
     N.l2p_pat = upload(P, l2p_pat);
     N.n_l2p_pat = (int)l2p_pat.size();
+    std::stable_sort(far_leaves.begin(), far_leaves.end(),
+                     [&](int x, int y) { return wptr[x + 1] - wptr[x] > wptr[y + 1] - wptr[y]; });
     N.far_leaves = upload(P, far_leaves);
     N.n_far_leaves = (int)far_leaves.size();
     N.local_done = upload(P, local_done);
