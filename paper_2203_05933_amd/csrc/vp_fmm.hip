@@ -883,6 +883,16 @@ __global__ void k_unpermute_grad(int64_t m, int nbatch, const int32_t *__restric
 // ----------------------------------------------------------------------------
 // Schedules (plan time): box groups for each pass.
 // ----------------------------------------------------------------------------
+std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr) {
+    const int nt = (int)tile_ptr.size() - 1;
+    std::vector<int32_t> ord(std::max(nt, 0));
+    for (int t = 0; t < nt; ++t) ord[t] = t;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+        return tile_ptr[x + 1] - tile_ptr[x] > tile_ptr[y + 1] - tile_ptr[y];
+    });
+    return ord;
+}
+
 void build_schedules(vp_plan_s *P) {
     Tree &T = P->tree;
     hipStream_t s = P->stream;
@@ -1030,8 +1040,11 @@ void build_schedules(vp_plan_s *P) {
                 if (mask >> o & 1) tops.push_back(o);
             tptr.push_back((int32_t)tops.size());
         }
+        const std::vector<int32_t> order = tile_order_by_work(tptr);
         P->m2l_tptr = up(tptr);
         P->m2l_tops = up(tops);
+        P->m2l_torder = up(order);
+        VP_HIP(hipStreamSynchronize(s));  // the host vectors leave scope
     }
     P->xr_ptr = up(xr_ptr);
     P->xr_idx = up(xr_idx);
@@ -1229,6 +1242,7 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
         TranslateArgs a = expansion_args(P, P->m2l_cols, P->n_m2l_boxes, T.v_slot, NOFF, 2 * Pn);
         a.tile_ptr = P->m2l_tptr;
         a.tile_ops = P->m2l_tops;
+        a.tile_order = P->m2l_torder;
         if (P->m2l_mode == VP_M2L_FP64_SCALED || P->m2l_mode == VP_M2L_FP32_SCALED) {
             M2LScaledArgs sa;
             sa.cols_box = P->m2l_cols;
@@ -1237,6 +1251,7 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
             sa.slots = T.v_slot;
             sa.tile_ptr = P->m2l_tptr;
             sa.tile_ops = P->m2l_tops;
+            sa.tile_order = P->m2l_torder;
             sa.P = Pn;
             sa.in = a.in;
             sa.out = a.out;
@@ -1350,6 +1365,7 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     a.nops = NTOPS * (int)N.tab_levels.size();
     a.tile_ptr = N.tile_ptr;
     a.tile_ops = N.tile_ops;
+    a.tile_order = N.tile_order;
     a.in = ColAddr{R.nsrc, 0, R.sb};
     a.out = ColAddr{R.ntgt, 0, R.tb};
     a.nrows_out = N.npat;

@@ -185,6 +185,7 @@ struct NearTables {
     int32_t *tab_slot = nullptr;      // [nbox][41 * table levels] table source per slot or -1
     int32_t *tile_ptr = nullptr;      // slots present per 16-column tile of table columns
     int32_t *tile_ops = nullptr;
+    int32_t *tile_order = nullptr;    // tiles by decreasing operator count
     double *K = nullptr;              // [tab level][41] near matrices, A-fragment order
     int32_t *pair_uptr = nullptr;     // U lists minus the table-served entries
     int32_t *pair_uidx = nullptr;
@@ -255,6 +256,7 @@ struct vp_plan_s {
     int32_t *m2l_cols = nullptr;  // boxes of levels >= 2, grouped by child class
     int32_t *m2l_tptr = nullptr;  // offsets present per 16-column tile of (box, density) columns
     int32_t *m2l_tops = nullptr;
+    int32_t *m2l_torder = nullptr;  // tiles by decreasing offset count
     int32_t *child_slot = nullptr;   // [nbox][4] child in each quadrant or -1
     int32_t *l2l_slot = nullptr;     // [nbox][4] parent in the slot of the box's class
     int n_m2l_boxes = 0;
@@ -311,6 +313,8 @@ bool pattern_op_supported(int npat, int PD);
 void build_p2p_gather(vp_plan_s *P, const std::vector<int32_t> &leaves, const std::vector<int32_t> &uptr,
                       const std::vector<int32_t> &uidx, const std::vector<int32_t> &sb, const std::vector<int32_t> &se,
                       const double *sx, const double *sy, P2PGather &g);
+// launch order of tiles with tile_ptr[t+1] - tile_ptr[t] operators: most operators first
+std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr);
 void run_fmm(vp_plan_s *P, bool adjoint, bool grad);
 void prepare_charges(vp_plan_s *P, const double *f, bool adjoint);
 void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint);

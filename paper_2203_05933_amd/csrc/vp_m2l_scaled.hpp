@@ -31,6 +31,7 @@ struct M2LScaledArgs {
     const int32_t *slots;     // [box][NOFF] source box or -1
     const int32_t *tile_ptr;  // offsets present in 16-column tile t: tile_ops[tile_ptr[t] .. tile_ptr[t+1])
     const int32_t *tile_ops;
+    const int32_t *tile_order;  // launch order of the tiles (most offsets first)
     int P;                    // complex coefficients per expansion
     ColAddr in, out;          // expansion columns (PD rows: re 0..P-1, im P..2P-1)
     int PD;
@@ -52,7 +53,8 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
     __shared__ double red[3][NR][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cl = lane & 15, g = lane >> 4;
-    const int col = blockIdx.x * 16 + cl;
+    const int tile = a.tile_order[blockIdx.x];
+    const int col = tile * 16 + cl;
     const bool valid = col < a.ncols;
     const int box = valid ? a.cols_box[col / a.nbatch] : 0;
     const int bt = valid ? col % a.nbatch : 0;
@@ -74,8 +76,8 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
     // this wave's offsets: every fourth one present in the tile; the source
     // columns of the next offset are loaded while the current one is on the
     // matrix cores
-    const int e1 = a.tile_ptr[blockIdx.x + 1];
-    int e = a.tile_ptr[blockIdx.x] + wave;
+    const int e1 = a.tile_ptr[tile + 1];
+    int e = a.tile_ptr[tile] + wave;
     int o = 0, src = -1;
     TM xr[S], xi[S];
     if (e < e1) {

@@ -327,8 +327,11 @@ void build_near_tables(vp_plan_s *P) {
                 if (seen[o]) tops.push_back((int32_t)o);
             tptr.push_back((int32_t)tops.size());
         }
+        const std::vector<int32_t> order = tile_order_by_work(tptr);
         N.tile_ptr = upload(P, tptr);
         N.tile_ops = upload(P, tops);
+        N.tile_order = upload(P, order);
+        VP_HIP(hipStreamSynchronize(s));  // the host vectors leave scope
     }
 
     if (N.active) {
@@ -395,10 +398,12 @@ void build_near_tables(vp_plan_s *P) {
             std::vector<float> af(Af.begin(), Af.end()), bf(Bf.begin(), Bf.end());
             N.p2m_op_f32 = upload(P, af);
             N.l2p_op_f32 = upload(P, bf);
+            VP_HIP(hipStreamSynchronize(s));  // af, bf leave scope
         } else {
             N.p2m_op = upload(P, Af);
             N.l2p_op = upload(P, Bf);
         }
+        VP_HIP(hipStreamSynchronize(s));  // K, Af, Bf leave scope
     }
     VP_HIP(hipStreamSynchronize(s));
 }

@@ -77,6 +77,7 @@ struct TranslateArgs {
     // tile_ptr[t+1]) (k_translate_split only; null = scan all nops slots)
     const int32_t *tile_ptr = nullptr;
     const int32_t *tile_ops = nullptr;
+    const int32_t *tile_order = nullptr;  // optional launch order of the tiles (most operators first)
 };
 
 // TI/TO: element types of input/output columns; TM: matrix-core type;
@@ -183,7 +184,8 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
     __shared__ double red[3][RB * 4][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cl = lane & 15, g = lane >> 4;
-    const int col = blockIdx.x * 16 + cl;
+    const int tile = a.tile_order ? a.tile_order[blockIdx.x] : (int)blockIdx.x;
+    const int col = tile * 16 + cl;
     const bool valid = col < a.ncols;
     const int box = valid ? a.cols_box[col / a.nbatch] : 0;
     const int bt = valid ? col % a.nbatch : 0;
@@ -191,8 +193,8 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r] = M::zero();
     const bool listed = a.tile_ptr != nullptr;
-    const int e0 = listed ? a.tile_ptr[blockIdx.x] : 0;
-    const int e1 = listed ? a.tile_ptr[blockIdx.x + 1] : a.nops;
+    const int e0 = listed ? a.tile_ptr[tile] : 0;
+    const int e1 = listed ? a.tile_ptr[tile + 1] : a.nops;
     int it = 0;  // index among the tile's active operators
     for (int e = e0 + (listed ? wave : 0); e < e1; e += listed ? 4 : 1) {
         const int o = listed ? a.tile_ops[e] : e;
