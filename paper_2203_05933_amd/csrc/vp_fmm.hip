@@ -773,7 +773,7 @@ __global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, int b
     // 16 lanes per row; a group takes R consecutive rows at a time and issues
     // all their loads (row metadata, 64-entry slices, near/far sums) before
     // any reduction, so no load waits on another row's arithmetic.
-    constexpr int R = NBG >= 16 ? 1 : (NBG >= 8 ? 2 : (NBG >= 2 ? 4 : 8));  // registers: R x NBG partial sums
+    constexpr int R = NBG >= 16 ? 1 : (NBG >= 8 ? 2 : 4);  // registers: R x NBG partial sums
     const int l16 = threadIdx.x & 15;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
