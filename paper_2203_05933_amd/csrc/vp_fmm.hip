@@ -1024,6 +1024,21 @@ void build_schedules(vp_plan_s *P) {
     P->vsplit_s = up(vsplit_s);
     P->vsplit_t = up(vsplit_t);
     VP_HIP(hipMemcpyAsync(T.v_slot, vslot.data(), 4 * vslot.size(), hipMemcpyHostToDevice, s));
+    // within each child class, order the M2L columns by their set of offsets
+    // (stable, so equal sets keep their tree order): tiles of 16 columns then
+    // share their offsets wherever the tree is not uniform
+    {
+        std::vector<uint64_t> omask(nbox, 0);
+        for (int b : m2l)
+            for (int o = 0; o < NOFF; ++o)
+                if (vslot[(size_t)b * NOFF + o] >= 0) omask[b] |= 1ull << o;
+        std::stable_sort(m2l.begin(), m2l.end(), [&](int x, int y) {
+            const int cx = cls(x), cy = cls(y);
+            return cx != cy ? cx < cy : omask[x] < omask[y];
+        });
+        if (!m2l.empty())
+            VP_HIP(hipMemcpyAsync(P->m2l_cols, m2l.data(), 4 * m2l.size(), hipMemcpyHostToDevice, s));
+    }
     // offsets present in each 16-column M2L tile (columns = box x density)
     {
         const int64_t ncols = (int64_t)m2l.size() * P->nbatch;
