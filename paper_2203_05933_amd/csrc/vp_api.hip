@@ -156,6 +156,12 @@ static void free_plan(vp_plan_s *P) {
     if (!P) return;
     if (P->stream) (void)hipStreamSynchronize(P->stream);
     else (void)hipDeviceSynchronize();
+    if (P->aux) {
+        (void)hipStreamSynchronize(P->aux);
+        (void)hipStreamDestroy(P->aux);
+    }
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     release_timing(P);
     P->mem.free_all();
     delete P;
@@ -185,6 +191,9 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->m2l_mode = o.m2l_mode == VP_M2L_AUTO ? (P->fp32 ? VP_M2L_FP32_SCALED : VP_M2L_FP64_SCALED) : o.m2l_mode;
         P->stream = static_cast<hipStream_t>(o.stream);
         VP_HIP(hipGetDevice(&P->device));
+        VP_HIP(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
+        VP_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+        VP_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
         P->err_flag = P->mem.alloc<int32_t>(1);
         P->w_user = P->mem.alloc<double>(n);
         VP_HIP(hipMemcpyAsync(P->w_user, w, sizeof(double) * n, hipMemcpyHostToDevice, P->stream));

@@ -1499,8 +1499,16 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
     Tree &T = P->tree;
     NearTables &N = P->near;
     const bool tables = N.active && !grad;
-    if (P->fp32) run_expansions<float>(P, R, G, tables);
-    else run_expansions<double>(P, R, G, tables);
+    // near field on the auxiliary stream, concurrent with the expansion passes
+    hipStream_t main_stream = P->stream;
+    VP_HIP(hipEventRecord(P->ev_fork, main_stream));
+    VP_HIP(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
+    struct Restore {
+        vp_plan_s *P;
+        hipStream_t s;
+        ~Restore() { P->stream = s; }
+    } restore{P, main_stream};
+    P->stream = P->aux;
     if (tables) {
         P->stage_begin(VP_STAGE_TABLES);
         fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
@@ -1518,6 +1526,11 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
                               P->acc);
     }
     P->stage_end(VP_STAGE_P2P);
+    VP_HIP(hipEventRecord(P->ev_join, P->aux));
+    P->stream = main_stream;
+    if (P->fp32) run_expansions<float>(P, R, G, tables);
+    else run_expansions<double>(P, R, G, tables);
+    VP_HIP(hipStreamWaitEvent(main_stream, P->ev_join, 0));
     if (T.nlevels >= 3) {
         if (grad) {
             if (P->fp32) run_far<float, true>(P, R, G, P->acc, false);

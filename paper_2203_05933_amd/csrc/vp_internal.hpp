@@ -219,6 +219,10 @@ struct vp_plan_s {
     bool fp32 = false;
     int m2l_mode = VP_M2L_FP64_MFMA;
     hipStream_t stream = nullptr;
+    // the near field runs on its own stream, forked after the charges and
+    // joined before the far-field evaluation (both default priority)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
     std::string err;
     bool poisoned = false;
