@@ -199,7 +199,8 @@ enum {
     VP_STAGE_CHARGE = 0, VP_STAGE_P2M = 1, VP_STAGE_M2M = 2, VP_STAGE_M2L = 3, VP_STAGE_P2L = 4,
     VP_STAGE_L2L = 5, VP_STAGE_P2P = 6, VP_STAGE_FAR = 7, VP_STAGE_FINISH = 8,
     VP_STAGE_TABLES = 9, /* near-field tables of congruent leaves (P2P holds the pairwise kernel) */
-    VP_NSTAGES = 10
+    VP_STAGE_CORR = 10,  /* sparse correction apply C f (FINISH: adding the un-permuted FMM sums) */
+    VP_NSTAGES = 11
 };
 vp_status vp_set_timing(vp_plan_t plan, int32_t enable);
 vp_status vp_get_timing(vp_plan_t plan, double *ms, int64_t *nevals);

@@ -262,8 +262,7 @@ extern "C" vp_status vp_eval(vp_plan_t P, const double *f, double *u) {
     return guarded(P, [&] {
         P->timing_eval_begin();
         vp::prepare_charges(P, f, false);
-        vp::run_fmm(P, false, false);
-        vp::finish_output(P, f, u, false);
+        vp::run_fmm(P, false, false, f, u);
     });
 }
 
@@ -276,8 +275,7 @@ extern "C" vp_status vp_eval_adjoint(vp_plan_t P, const double *g, double *df) {
     return guarded(P, [&] {
         P->timing_eval_begin();
         vp::prepare_charges(P, g, true);
-        vp::run_fmm(P, true, false);
-        vp::finish_output(P, g, df, true);
+        vp::run_fmm(P, true, false, g, df);
     });
 }
 

@@ -759,7 +759,7 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
 // its run start instead of a column index per non-zero.  Reductions run in
 // a fixed lane order.
 // ----------------------------------------------------------------------------
-template <int NBG>
+template <int NBG, bool WITH_ACC>
 __global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, int bt0,
                                                 const int32_t *__restrict__ inv,
                                                 const double *__restrict__ scale,
@@ -789,10 +789,12 @@ __global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, int b
             mp0 = rowptr[im];
             mp1 = rowptr[im + 1];
             mrs = run_start[im];
-            const int32_t si = inv[im];
-            if (scale) msc = scale[im];
+            if (WITH_ACC) {
+                const int32_t si = inv[im];
+                if (scale) msc = scale[im];
 #pragma unroll
-            for (int k = 0; k < NBG; ++k) macc[k] = k < nbg ? acc[(int64_t)(bt0 + k) * acc_len + si] : 0.0;
+                for (int k = 0; k < NBG; ++k) macc[k] = k < nbg ? acc[(int64_t)(bt0 + k) * acc_len + si] : 0.0;
+            }
         }
         double part[R][NBG];
 #pragma unroll
@@ -836,9 +838,24 @@ __global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, int b
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (r == l16) pr = part[r][k];
-                if (k < nbg) out[(int64_t)(bt0 + k) * nrows + im] = msc * macc[k] + pr;
+                if (k < nbg) out[(int64_t)(bt0 + k) * nrows + im] = WITH_ACC ? msc * macc[k] + pr : pr;
             }
         }
+    }
+}
+
+// out[b][i] += scale_i * acc[b][inv[i]]: the FMM sums (sorted order) added to
+// the correction already in out (user order)
+__global__ void k_add_acc(int64_t nrows, int nbatch, const int32_t *__restrict__ inv,
+                          const double *__restrict__ scale, const double *__restrict__ acc, int64_t acc_len,
+                          double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    const int32_t si = inv[i];
+    const double sc = scale ? scale[i] : 1.0;
+    for (int b = 0; b < nbatch; ++b) {
+        double *o = out + (int64_t)b * nrows + i;
+        *o = sc * acc[(int64_t)b * acc_len + si] + *o;
     }
 }
 
@@ -1493,7 +1510,10 @@ static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *
     P->stage_end(VP_STAGE_FAR);
 }
 
-void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
+static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjoint);
+static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint);
+
+void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) {
     PointRoles R = roles(P, adjoint);
     BoxGeo G = geo(P);
     Tree &T = P->tree;
@@ -1526,6 +1546,7 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
                               P->acc);
     }
     P->stage_end(VP_STAGE_P2P);
+    if (u) correction_apply(P, f, u, adjoint);
     VP_HIP(hipEventRecord(P->ev_join, P->aux));
     P->stream = main_stream;
     if (P->fp32) run_expansions<float>(P, R, G, tables);
@@ -1540,12 +1561,13 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad) {
             else run_far<double, false>(P, R, G, P->acc, tables);
         }
     }
+    if (u) add_fmm_sums(P, u, adjoint);
 }
 
-void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint) {
+// The sparse correction (Section 4): out = C f (adjoint: C^T g), on the
+// current stream; it needs no FMM result, so it runs beside the expansions.
+static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjoint) {
     const int64_t nrows = adjoint ? P->n : P->m;
-    const int32_t *inv = adjoint ? P->sinv : P->tinv;
-    const double *scale = adjoint ? P->w_user : nullptr;
     const int64_t *rp = adjoint ? P->rowptrT : P->rowptr;
     const int32_t *cv = adjoint ? P->colT : P->col;
     const int32_t *rs = adjoint ? P->run_startT : P->run_start;
@@ -1553,15 +1575,16 @@ void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint) {
     const int64_t flen = adjoint ? P->m : P->n;
     int64_t blocks = (nrows * 16 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    P->stage_begin(VP_STAGE_FINISH);
+    P->stage_begin(VP_STAGE_CORR);
     for (int bt0 = 0; bt0 < P->nbatch;) {
         const int left = P->nbatch - bt0;
         const int g = left >= 16 ? 16 : (left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1)));
         switch (g) {
-#define VP_FIN(G)                                                                                           \
-    case G:                                                                                                 \
-        hipLaunchKernelGGL(k_finish<G>, dim3((unsigned)blocks), dim3(256), 0, P->stream, nrows, P->nbatch,   \
-                           bt0, inv, scale, P->acc, nrows, rp, cv, rs, vv, f, flen, u);                     \
+#define VP_FIN(G)                                                                                              \
+    case G:                                                                                                    \
+        hipLaunchKernelGGL((k_finish<G, false>), dim3((unsigned)blocks), dim3(256), 0, P->stream, nrows,        \
+                           P->nbatch, bt0, (const int32_t *)nullptr, (const double *)nullptr,                  \
+                           (const double *)nullptr, nrows, rp, cv, rs, vv, f, flen, u);                        \
         break;
             VP_FIN(16) VP_FIN(8) VP_FIN(4) VP_FIN(2) VP_FIN(1)
 #undef VP_FIN
@@ -1569,6 +1592,18 @@ void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint) {
         VP_LAUNCH_CHECK();
         bt0 += g;
     }
+    P->stage_end(VP_STAGE_CORR);
+}
+
+// out += (adjoint: w times) the FMM sums, un-permuted to user order
+static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint) {
+    const int64_t nrows = adjoint ? P->n : P->m;
+    const int32_t *inv = adjoint ? P->sinv : P->tinv;
+    const double *scale = adjoint ? P->w_user : nullptr;
+    P->stage_begin(VP_STAGE_FINISH);
+    hipLaunchKernelGGL(k_add_acc, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, P->stream, nrows, P->nbatch,
+                       inv, scale, P->acc, nrows, u);
+    VP_LAUNCH_CHECK();
     P->stage_end(VP_STAGE_FINISH);
 }
 

@@ -319,9 +319,10 @@ void build_p2p_gather(vp_plan_s *P, const std::vector<int32_t> &leaves, const st
                       const double *sx, const double *sy, P2PGather &g);
 // launch order of tiles with tile_ptr[t+1] - tile_ptr[t] operators: most operators first
 std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr);
-void run_fmm(vp_plan_s *P, bool adjoint, bool grad);
+// one evaluation after prepare_charges; with u: the correction C f (adjoint C^T f) runs
+// beside the FMM and u = FMM sums (un-permuted; adjoint: times w) + correction
+void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f = nullptr, double *u = nullptr);
 void prepare_charges(vp_plan_s *P, const double *f, bool adjoint);
-void finish_output(vp_plan_s *P, const double *f, double *u, bool adjoint);
 void finish_grad(vp_plan_s *P, double *grad);
 void detect_runs(vp_plan_s *P);
 // vp_csr.hip
