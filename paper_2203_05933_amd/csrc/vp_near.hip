@@ -285,6 +285,17 @@ void build_near_tables(vp_plan_s *P) {
     N.n_far_leaves = (int)far_leaves.size();
     N.local_done = upload(P, local_done);
 
+    // within a level, order the table leaves by their set of slots (stable):
+    // 16-column tiles then share their operators where the tree is not uniform
+    for (auto &cl : cols_by_level) {
+        auto key = [&](int b) {
+            uint64_t m = 0;
+            for (int o = 0; o < NTOPS; ++o)
+                if (tslot[(size_t)b * NTOPS + o] >= 0) m |= 1ull << o;
+            return m;
+        };
+        std::stable_sort(cl.begin(), cl.end(), [&](int x, int y) { return key(x) < key(y); });
+    }
     N.nleaf_tab = 0;
     N.tab_levels.clear();
     N.tab_cols_begin.clear();
