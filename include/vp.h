@@ -156,6 +156,10 @@ typedef struct {
     int64_t table_leaves;      /* leaves served by near-field tables */
     int64_t near_pairs;        /* pairwise near-field interactions per density */
     int64_t workspace_bytes;   /* device memory held by the plan */
+    int64_t m2l_translations;  /* M2L translations per density, V lists plus the
+                                  virtual children of X-list sources */
+    int64_t m2l_tile_ops;      /* (16-column tile, offset) products the M2L launch issues */
+    int64_t table_tile_ops;    /* (16-column tile, slot) products of the near tables */
     double root[3];
 } vp_plan_info_t;
 

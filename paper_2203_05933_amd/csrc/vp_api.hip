@@ -357,6 +357,9 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->table_leaves = P->near.nleaf_tab;
     info->near_pairs = P->near_pairs;
     info->workspace_bytes = (int64_t)P->mem.bytes;
+    info->m2l_translations = P->m2l_translations;
+    info->m2l_tile_ops = P->m2l_tile_ops;
+    info->table_tile_ops = P->near.table_tile_ops;
     for (int k = 0; k < 3; ++k) info->root[k] = P->opt.root[k];
     return VP_OK;
 }

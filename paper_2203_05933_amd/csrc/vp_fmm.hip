@@ -21,6 +21,8 @@
 // P..2P-1 imaginary parts, zero padding; float64, or float32 in the
 // FP32-bulk form.  Every reduction has a fixed order: no atomics.
 
+#include <algorithm>
+
 #include "vp_internal.hpp"
 #include "vp_translate.hpp"
 #include "vp_m2l_scaled.hpp"
@@ -759,76 +761,92 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
 // its run start instead of a column index per non-zero.  Reductions run in
 // a fixed lane order.
 // ----------------------------------------------------------------------------
-template <int NBG, bool WITH_ACC>
-__global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, int bt0,
-                                                const int32_t *__restrict__ inv,
-                                                const double *__restrict__ scale,
-                                                const double *__restrict__ acc, int64_t acc_len,
-                                                const int64_t *__restrict__ rowptr,
-                                                const int32_t *__restrict__ colv,
-                                                const int32_t *__restrict__ run_start,
-                                                const double *__restrict__ valv,
-                                                const double *__restrict__ f, int64_t flen,
-                                                double *__restrict__ out) {
-    // 16 lanes per row; a group takes R consecutive rows at a time and issues
-    // all their loads (row metadata, 64-entry slices, near/far sums) before
-    // any reduction, so no load waits on another row's arithmetic.
-    constexpr int R = NBG >= 16 ? 1 : (NBG >= 8 ? 2 : 4);  // registers: R x NBG partial sums
+template <int NBG, bool RUNS>
+__global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0, int64_t nnz,
+                                              const int64_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ colv,
+                                              const int32_t *__restrict__ run_start,
+                                              const double *__restrict__ valv,
+                                              const double *__restrict__ f, int64_t flen,
+                                              double *__restrict__ out) {
+    // out[b][i] = sum_{q in row i} val[q] f[b][col[q]] (nnz >= 1).  16 lanes
+    // per row; a group takes R consecutive rows and issues the loads of the
+    // first 64 entries of all R rows before any arithmetic (indices clamped
+    // to valid entries, terms past a row's end multiplied by zero, so no
+    // load sits behind a branch); longer rows continue in a loop.  With RUNS
+    // every row's columns are one contiguous run and the column array is
+    // never read.  A non-finite value makes its row (or, in f, every
+    // potential) non-finite either way.
+    constexpr int R = NBG >= 4 ? 1 : (NBG == 2 ? 2 : 4);  // registers: R x 4 loads and R x NBG sums
     const int l16 = threadIdx.x & 15;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
     const int nbg = min(NBG, nbatch - bt0);
     for (int64_t i0 = grp * R; i0 < nrows; i0 += ngrp * R) {
-        // lane r < R fetches row i0 + r's metadata and FMM sums
+        // lane r < R fetches row i0 + r's extent
         const int64_t im = i0 + l16;
         const bool mrow = l16 < R && im < nrows;
         int64_t mp0 = 0, mp1 = 0;
         int32_t mrs = 0;
-        double msc = 1.0, macc[NBG];
         if (mrow) {
             mp0 = rowptr[im];
             mp1 = rowptr[im + 1];
-            mrs = run_start[im];
-            if (WITH_ACC) {
-                const int32_t si = inv[im];
-                if (scale) msc = scale[im];
-#pragma unroll
-                for (int k = 0; k < NBG; ++k) macc[k] = k < nbg ? acc[(int64_t)(bt0 + k) * acc_len + si] : 0.0;
-            }
+            if (RUNS) mrs = run_start[im];
         }
-        double part[R][NBG];
+        int64_t p0[R], p1[R];
+        int32_t rs[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int64_t p0 = __shfl(mp0, r, 16), p1 = __shfl(mp1, r, 16);
-            const int32_t rs = __shfl(mrs, r, 16);
+            p0[r] = __shfl(mp0, r, 16);
+            p1[r] = __shfl(mp1, r, 16);
+            rs[r] = __shfl(mrs, r, 16);
+        }
+        double v[R][4];
+        int64_t c[R][4];
 #pragma unroll
-            for (int k = 0; k < NBG; ++k) part[r][k] = 0.0;
-            for (int64_t pb = p0; pb < p1; pb += 64) {
-                double v[4];
-                int64_t c[4];
-                bool in[4];
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t pq = pb + l16 + 16 * u;
-                    in[u] = pq < p1;
-                    v[u] = in[u] ? __builtin_nontemporal_load(valv + pq) : 0.0;  // streamed once
-                    c[u] = !in[u] ? 0 : (rs >= 0 ? (int64_t)rs + (pq - p0) : (int64_t)colv[pq]);
-                }
+            for (int u = 0; u < 4; ++u) {
+                const int64_t pq = p0[r] + l16 + 16 * u;
+                const bool in = pq < p1[r];
+                const int64_t pc = min(max(in ? pq : p1[r] - 1, (int64_t)0), nnz - 1);
+                v[r][u] = __builtin_nontemporal_load(valv + pc) * (in ? 1.0 : 0.0);  // streamed once
+                c[r][u] = RUNS ? (in ? (int64_t)rs[r] + (pq - p0[r]) : (int64_t)0) : (int64_t)colv[pc];
+            }
+        double part[R][NBG];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < NBG; ++k) {
+                // densities past nbg read a valid row and are never stored
+                const double *fk = f + (int64_t)(bt0 + min(k, nbg - 1)) * flen;
+                double a = 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a = fma(v[r][u], fk[c[r][u]], a);
+                part[r][k] = a;
+            }
+        // rows longer than 64 entries
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            for (int64_t pb = p0[r] + 64; pb < p1[r]; pb += 16) {
+                const int64_t pq = pb + l16;
+                if (pq < p1[r]) {
+                    const double vv = __builtin_nontemporal_load(valv + pq);
+                    const int64_t cc = RUNS ? (int64_t)rs[r] + (pq - p0[r]) : (int64_t)colv[pq];
 #pragma unroll
                     for (int k = 0; k < NBG; ++k)
-                        if (k < nbg && in[u]) part[r][k] += v[u] * f[(int64_t)(bt0 + k) * flen + c[u]];
+                        part[r][k] = fma(vv, f[(int64_t)(bt0 + min(k, nbg - 1)) * flen + cc], part[r][k]);
+                }
             }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int k = 0; k < NBG; ++k) {
-                double v = part[r][k];
+                double t = part[r][k];
 #pragma unroll
-                for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 16);
-                part[r][k] = v;
+                for (int off = 8; off >= 1; off >>= 1) t += __shfl_xor(t, off, 16);
+                part[r][k] = t;
             }
         // lane r writes row i0 + r
         if (mrow) {
@@ -838,7 +856,7 @@ __global__ void __launch_bounds__(256) k_finish(int64_t nrows, int nbatch, int b
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (r == l16) pr = part[r][k];
-                if (k < nbg) out[(int64_t)(bt0 + k) * nrows + im] = WITH_ACC ? msc * macc[k] + pr : pr;
+                if (k < nbg) out[(int64_t)(bt0 + k) * nrows + im] = pr;
             }
         }
     }
@@ -884,7 +902,14 @@ void detect_runs(vp_plan_s *P) {
     hipLaunchKernelGGL(k_detect_runs, dim3((unsigned)((P->n + 255) / 256)), dim3(256), 0, s, P->rowptrT, P->colT,
                        P->n, P->run_startT);
     VP_LAUNCH_CHECK();
+    // every row a run: the apply kernel never reads the column array
+    std::vector<int32_t> h(std::max(P->m, P->n));
+    VP_HIP(hipMemcpyAsync(h.data(), P->run_start, 4 * P->m, hipMemcpyDeviceToHost, s));
     VP_HIP(hipStreamSynchronize(s));
+    P->all_runs = std::all_of(h.begin(), h.begin() + P->m, [](int32_t v) { return v >= 0; });
+    VP_HIP(hipMemcpyAsync(h.data(), P->run_startT, 4 * P->n, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipStreamSynchronize(s));
+    P->all_runsT = std::all_of(h.begin(), h.begin() + P->n, [](int32_t v) { return v >= 0; });
 }
 
 __global__ void k_unpermute_grad(int64_t m, int nbatch, const int32_t *__restrict__ inv,
@@ -1073,6 +1098,10 @@ void build_schedules(vp_plan_s *P) {
             tptr.push_back((int32_t)tops.size());
         }
         const std::vector<int32_t> order = tile_order_by_work(tptr);
+        P->m2l_tile_ops = (int64_t)tops.size();
+        P->m2l_translations = 0;
+        for (int b : m2l)
+            for (int o = 0; o < NOFF; ++o) P->m2l_translations += vslot[(size_t)b * NOFF + o] >= 0;
         P->m2l_tptr = up(tptr);
         P->m2l_tops = up(tops);
         P->m2l_torder = up(order);
@@ -1572,25 +1601,33 @@ static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjo
     const int32_t *cv = adjoint ? P->colT : P->col;
     const int32_t *rs = adjoint ? P->run_startT : P->run_start;
     const double *vv = adjoint ? P->valT : P->val;
+    const bool runs = adjoint ? P->all_runsT : P->all_runs;
     const int64_t flen = adjoint ? P->m : P->n;
     int64_t blocks = (nrows * 16 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     P->stage_begin(VP_STAGE_CORR);
-    for (int bt0 = 0; bt0 < P->nbatch;) {
-        const int left = P->nbatch - bt0;
-        const int g = left >= 16 ? 16 : (left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1)));
-        switch (g) {
+    if (P->nnz == 0) {
+        fill_f64(u, 0.0, (int64_t)P->nbatch * nrows, P->stream);
+    } else {
+        for (int bt0 = 0; bt0 < P->nbatch;) {
+            const int left = P->nbatch - bt0;
+            const int g = left >= 16 ? 16 : (left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1)));
+            switch (g) {
 #define VP_FIN(G)                                                                                              \
     case G:                                                                                                    \
-        hipLaunchKernelGGL((k_finish<G, false>), dim3((unsigned)blocks), dim3(256), 0, P->stream, nrows,        \
-                           P->nbatch, bt0, (const int32_t *)nullptr, (const double *)nullptr,                  \
-                           (const double *)nullptr, nrows, rp, cv, rs, vv, f, flen, u);                        \
+        if (runs)                                                                                              \
+            hipLaunchKernelGGL((k_corr<G, true>), dim3((unsigned)blocks), dim3(256), 0, P->stream, nrows,      \
+                               P->nbatch, bt0, (int64_t)P->nnz, rp, cv, rs, vv, f, flen, u);                   \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_corr<G, false>), dim3((unsigned)blocks), dim3(256), 0, P->stream, nrows,     \
+                               P->nbatch, bt0, (int64_t)P->nnz, rp, cv, rs, vv, f, flen, u);                  \
         break;
-            VP_FIN(16) VP_FIN(8) VP_FIN(4) VP_FIN(2) VP_FIN(1)
+                VP_FIN(16) VP_FIN(8) VP_FIN(4) VP_FIN(2) VP_FIN(1)
 #undef VP_FIN
+            }
+            VP_LAUNCH_CHECK();
+            bt0 += g;
         }
-        VP_LAUNCH_CHECK();
-        bt0 += g;
     }
     P->stage_end(VP_STAGE_CORR);
 }

@@ -186,6 +186,7 @@ struct NearTables {
     int32_t *tile_ptr = nullptr;      // slots present per 16-column tile of table columns
     int32_t *tile_ops = nullptr;
     int32_t *tile_order = nullptr;    // tiles by decreasing operator count
+    int64_t table_tile_ops = 0;
     double *K = nullptr;              // [tab level][41] near matrices, A-fragment order
     int32_t *pair_uptr = nullptr;     // U lists minus the table-served entries
     int32_t *pair_uidx = nullptr;
@@ -244,6 +245,7 @@ struct vp_plan_s {
     int32_t *colT = nullptr;
     double *valT = nullptr;
     int32_t *run_start = nullptr;   // per row: first column of a contiguous run, or -1
+    bool all_runs = false, all_runsT = false;  // every row (of C, of C^T) is a run
     int32_t *run_startT = nullptr;
 
     vp::Tree tree;
@@ -261,6 +263,7 @@ struct vp_plan_s {
     int32_t *m2l_tptr = nullptr;  // offsets present per 16-column tile of (box, density) columns
     int32_t *m2l_tops = nullptr;
     int32_t *m2l_torder = nullptr;  // tiles by decreasing offset count
+    int64_t m2l_translations = 0, m2l_tile_ops = 0;
     int32_t *child_slot = nullptr;   // [nbox][4] child in each quadrant or -1
     int32_t *l2l_slot = nullptr;     // [nbox][4] parent in the slot of the box's class
     int n_m2l_boxes = 0;

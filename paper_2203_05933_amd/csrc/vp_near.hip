@@ -339,6 +339,7 @@ void build_near_tables(vp_plan_s *P) {
             tptr.push_back((int32_t)tops.size());
         }
         const std::vector<int32_t> order = tile_order_by_work(tptr);
+        N.table_tile_ops = (int64_t)tops.size();
         N.tile_ptr = upload(P, tptr);
         N.tile_ops = upload(P, tops);
         N.tile_order = upload(P, order);

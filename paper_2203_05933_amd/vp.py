@@ -57,7 +57,8 @@ class PlanInfo(ctypes.Structure):
                 ("nbox", ctypes.c_int32), ("nleaf", ctypes.c_int32), ("nlevels", ctypes.c_int32),
                 ("self_targets", ctypes.c_int32), ("list_len", ctypes.c_int64 * 4),
                 ("table_leaves", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64), ("root", ctypes.c_double * 3)]
+                ("workspace_bytes", ctypes.c_int64), ("m2l_translations", ctypes.c_int64),
+                ("m2l_tile_ops", ctypes.c_int64), ("table_tile_ops", ctypes.c_int64), ("root", ctypes.c_double * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -256,6 +256,36 @@ def test_m2l_scaled_matches_per_offset_operators(c0, order):
     assert relinf(u2, u1) <= 1e-13
 
 
+@pytest.mark.parametrize("nbatch", [1, 2, 3, 5])
+def test_correction_general_csr(nbatch):
+    """A correction matrix that is not run-structured: rows of 0 to 150 entries
+    (empty rows, rows longer than one 64-entry pass), unsorted random
+    columns, with separate targets; forward and adjoint against the oracle."""
+    vp = _vp()
+    rng = np.random.default_rng(11 + nbatch)
+    n, m = 900, 700
+    x = rng.uniform(-1, 1, n)
+    y = rng.uniform(-1, 1, n)
+    w = rng.uniform(0.1, 1, n) / n
+    tx = rng.uniform(-1, 1, m)
+    ty = rng.uniform(-1, 1, m)
+    lens = rng.integers(0, 151, m)
+    lens[::7] = 0
+    rowptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = rng.integers(0, n, int(rowptr[-1])).astype(np.int32)
+    val = rng.standard_normal(int(rowptr[-1]))
+    f = rng.standard_normal((nbatch, n))
+    plan = vp.Plan(x, y, w, tx, ty, rowptr, col, val, order=30, max_leaf=32, nbatch=nbatch, root=(-1.0, -1.0, 2.0))
+    u = _host(plan.eval(_dev(f)))
+    ref = direct.evaluate(x, y, w, f, rowptr, col, val, tx, ty)
+    assert max(relinf(u[b], ref[b]) for b in range(nbatch)) <= TOL64
+    g = rng.standard_normal((nbatch, m))
+    d = _host(plan.eval_adjoint(_dev(g)))
+    dref = direct.evaluate_adjoint(x, y, w, g, rowptr, col, val, tx, ty)
+    assert max(relinf(d[b], dref[b]) for b in range(nbatch)) <= TOL64
+    plan.close()
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65])
 def test_small_inputs(n):
     vp = _vp()
