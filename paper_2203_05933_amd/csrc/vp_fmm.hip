@@ -599,8 +599,8 @@ __device__ inline double vp_log_tab(double x, const double2 *__restrict__ tab) {
 // P2PCap points, so a leaf with many small neighbours pays one barrier
 // pair per tile.  When a leaf has few targets the lanes also split the
 // source loop (K lane groups) and the partial sums are combined in a fixed
-// order.  Pairs at zero distance (the self pair) contribute nothing (a
-// select after the branch-free logarithm).
+// order.  Pairs at zero distance (the self pair) contribute nothing (their
+// logarithm is multiplied by zero, so the loop has no branch).
 // ----------------------------------------------------------------------------
 template <int NB>
 struct P2PCap {
@@ -696,7 +696,8 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
                             gya[k] = fma(c, dy, gya[k]);
                         }
                     } else {
-                        const double lg = nz ? vp_log_tab(r2, ltab) : 0.0;
+                        // branch-free: the zero-distance pair takes log(1) times zero
+                        const double lg = vp_log_tab(nz ? r2 : 1.0, ltab) * (nz ? 1.0 : 0.0);
 #pragma unroll
                         for (int k = 0; k < NB; ++k) a[k] = fma(qs[k][j], lg, a[k]);
                     }

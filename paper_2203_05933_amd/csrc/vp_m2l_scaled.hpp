@@ -73,16 +73,29 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
         for (int i = 0; i < 4; ++i) br[r][i] = bi[r][i] = 0.0;
     double a0r = 0.0, a0i = 0.0;  // sum of A_0 over the sources (lanes g == 0)
 
+    // the tile's offsets and each column's source per offset, staged in LDS
+    // once (no dependent global loads inside the loop)
+    __shared__ int32_t s_ops[NOFF];
+    __shared__ int32_t s_src[NOFF][16];
+    const int e0 = a.tile_ptr[tile], nt = a.tile_ptr[tile + 1] - e0;
+    for (int i = tid; i < nt; i += 256) s_ops[i] = a.tile_ops[e0 + i];
+    __syncthreads();
+    for (int i = tid; i < nt * 16; i += 256) {
+        const int oi = i >> 4, c = i & 15, cc = tile * 16 + c;
+        s_src[oi][c] = cc < a.ncols ? a.slots[(int64_t)a.cols_box[cc / a.nbatch] * NOFF + s_ops[oi]] : -1;
+    }
+    __syncthreads();
+
     // this wave's offsets: every fourth one present in the tile; the source
     // columns of the next offset are loaded while the current one is on the
     // matrix cores
-    const int e1 = a.tile_ptr[tile + 1];
-    int e = a.tile_ptr[tile] + wave;
+    const int e1 = nt;
+    int e = wave;
     int o = 0, src = -1;
     TM xr[S], xi[S];
     if (e < e1) {
-        o = a.tile_ops[e];
-        src = valid ? a.slots[(int64_t)box * NOFF + o] : -1;
+        o = s_ops[e];
+        src = s_src[e][cl];
         const TI *ip = in + (src >= 0 ? a.in.off(src) + (int64_t)bt * a.in.bstride : 0);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -115,8 +128,8 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
         const int en = e + 4;
         int on = 0, srcn = -1;
         if (en < e1) {
-            on = a.tile_ops[en];
-            srcn = valid ? a.slots[(int64_t)box * NOFF + on] : -1;
+            on = s_ops[en];
+            srcn = s_src[en][cl];
             const TI *ip = in + (srcn >= 0 ? a.in.off(srcn) + (int64_t)bt * a.in.bstride : 0);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
