@@ -192,19 +192,7 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
     typename M::acc_t acc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r] = M::zero();
-    const bool listed = a.tile_ptr != nullptr;
-    const int e0 = listed ? a.tile_ptr[tile] : 0;
-    const int e1 = listed ? a.tile_ptr[tile + 1] : a.nops;
-    int it = 0;  // index among the tile's active operators
-    for (int e = e0 + (listed ? wave : 0); e < e1; e += listed ? 4 : 1) {
-        const int o = listed ? a.tile_ops[e] : e;
-        const int src = valid ? a.slots[(int64_t)box * a.nops + o] : -1;
-        if (!listed) {
-            if (__ballot(src >= 0) == 0ull) continue;
-            const bool mine = (it & 3) == wave;
-            ++it;
-            if (!mine) continue;
-        }
+    auto product = [&](int o, int src) {
         TM bv[S];
         const TI *ip = in + (src >= 0 ? a.in.off(src) + (int64_t)bt * a.in.bstride : 0) + g;
 #pragma unroll
@@ -218,6 +206,34 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
                 acc[r] = M::op(Ao[(r * S + s) * 64], bv[s], acc[r]);
                 if (SPLIT) acc[r] = M::op(Alo_o[(r * S + s) * 64], bv[s], acc[r]);
             }
+        }
+    };
+    if (a.tile_ptr) {
+        // the tile's operators and each column's source per operator, staged in
+        // LDS 64 operators at a time (no dependent global loads in the loop)
+        __shared__ int32_t s_ops[64];
+        __shared__ int32_t s_src[64][16];
+        const int e0 = a.tile_ptr[tile], nt = a.tile_ptr[tile + 1] - e0;
+        for (int c0 = 0; c0 < nt; c0 += 64) {
+            const int nc = min(64, nt - c0);
+            __syncthreads();
+            for (int i = tid; i < nc; i += 256) s_ops[i] = a.tile_ops[e0 + c0 + i];
+            __syncthreads();
+            for (int i = tid; i < nc * 16; i += 256) {
+                const int oi = i >> 4, c = i & 15, cc = tile * 16 + c;
+                s_src[oi][c] = cc < a.ncols ? a.slots[(int64_t)a.cols_box[cc / a.nbatch] * a.nops + s_ops[oi]] : -1;
+            }
+            __syncthreads();
+            for (int e = wave; e < nc; e += 4) product(s_ops[e], s_src[e][cl]);
+        }
+    } else {
+        int it = 0;  // index among the tile's active operators
+        for (int o = 0; o < a.nops; ++o) {
+            const int src = valid ? a.slots[(int64_t)box * a.nops + o] : -1;
+            if (__ballot(src >= 0) == 0ull) continue;
+            const bool mine = (it & 3) == wave;
+            ++it;
+            if (mine) product(o, src);
         }
     }
     // fixed-order sum of the four partial tiles: wave 0 + 1 + 2 + 3
