@@ -1243,7 +1243,8 @@ template <class E>
 static void run_pattern_op(vp_plan_s *P, const PointRoles &R, bool p2m);
 
 template <class E>
-static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool tables) {
+// upward (P2M, M2M) or downward (M2L, P2L, L2L) half of the expansion passes
+static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool tables, bool upward) {
     Tree &T = P->tree;
     hipStream_t s = P->stream;
     const int nb = P->nbatch, Pn = P->P, PD = P->PD;
@@ -1253,6 +1254,14 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
     const size_t lds = sizeof(E) * 2 * 16 * Pn;
     if (T.nlevels < 3) return;  // no box is well separated from another
+    const Operators &O = P->ops;
+    const E *shq[2], *shi[2], *sho[2];
+    for (int w = 0; w < 2; ++w) {
+        shq[w] = f32 ? (const E *)O.sh_qt32[w] : (const E *)O.sh_qt64[w];
+        shi[w] = f32 ? (const E *)O.sh_tin32[w] : (const E *)O.sh_tin64[w];
+        sho[w] = f32 ? (const E *)O.sh_tout32[w] : (const E *)O.sh_tout64[w];
+    }
+    if (upward) {
     P->stage_begin(VP_STAGE_P2M);
     if (tables) {
         run_pattern_op<E>(P, R, true);
@@ -1275,13 +1284,6 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     }
     P->stage_end(VP_STAGE_P2M);
     P->stage_begin(VP_STAGE_M2M);
-    const Operators &O = P->ops;
-    const E *shq[2], *shi[2], *sho[2];
-    for (int w = 0; w < 2; ++w) {
-        shq[w] = f32 ? (const E *)O.sh_qt32[w] : (const E *)O.sh_qt64[w];
-        shi[w] = f32 ? (const E *)O.sh_tin32[w] : (const E *)O.sh_tin64[w];
-        sho[w] = f32 ? (const E *)O.sh_tout32[w] : (const E *)O.sh_tout64[w];
-    }
     for (int l = T.nlevels - 2; l >= 2; --l) {
         int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
         if (c1 > c0) {
@@ -1299,6 +1301,8 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
         }
     }
     P->stage_end(VP_STAGE_M2M);
+    return;
+    }
     P->stage_begin(VP_STAGE_M2L);
     {
         TranslateArgs a = expansion_args(P, P->m2l_cols, P->n_m2l_boxes, T.v_slot, NOFF, 2 * Pn);
@@ -1320,7 +1324,6 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
             sa.PD = PD;
             sa.level = T.level;
             sa.logside = T.d_logside;
-            const Operators &O = P->ops;
             if (!f32)
                 m2l_scaled<double, double, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
                                                    (const double *)M, (double *)L);
@@ -1549,7 +1552,8 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) 
     Tree &T = P->tree;
     NearTables &N = P->near;
     const bool tables = N.active && !grad;
-    // near field on the auxiliary stream, concurrent with the expansion passes
+    // correction and near field on the auxiliary stream (the HBM-bound
+    // correction first), concurrent with the expansion passes
     hipStream_t main_stream = P->stream;
     VP_HIP(hipEventRecord(P->ev_fork, main_stream));
     VP_HIP(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
@@ -1559,6 +1563,7 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) 
         ~Restore() { P->stream = s; }
     } restore{P, main_stream};
     P->stream = P->aux;
+    if (u) correction_apply(P, f, u, adjoint);
     if (tables) {
         P->stage_begin(VP_STAGE_TABLES);
         fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
@@ -1576,11 +1581,12 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) 
                               P->acc);
     }
     P->stage_end(VP_STAGE_P2P);
-    if (u) correction_apply(P, f, u, adjoint);
     VP_HIP(hipEventRecord(P->ev_join, P->aux));
     P->stream = main_stream;
-    if (P->fp32) run_expansions<float>(P, R, G, tables);
-    else run_expansions<double>(P, R, G, tables);
+    if (P->fp32) run_expansions<float>(P, R, G, tables, true);
+    else run_expansions<double>(P, R, G, tables, true);
+    if (P->fp32) run_expansions<float>(P, R, G, tables, false);
+    else run_expansions<double>(P, R, G, tables, false);
     VP_HIP(hipStreamWaitEvent(main_stream, P->ev_join, 0));
     if (T.nlevels >= 3) {
         if (grad) {
