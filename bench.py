@@ -222,17 +222,25 @@ def main():
     u64 = u.clone()
 
     out32 = None
+    forms32 = {}
     if not args.no_fp32:
-        plan32 = vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=args.order_fp32,
-                         max_leaf=args.max_leaf, nbatch=nb, precision="fp32", root=wl.root)
-        u32 = torch.empty_like(u)
-        dt32, tim32 = time_evals(plan32, f, u32, args.steps, args.warmup)
-        v32 = wl.m * nb / (dt32 / args.steps) / 1e6
-        out32 = {"value": v32, "ms_per_step": dt32 / args.steps * 1e3, "order": args.order_fp32,
-                 "m2l": "fp32 mfma", "stages_ms": {k: v / max(tim32["evals"], 1) for k, v in tim32["ms"].items()},
-                 "speedup_vs_fp64": v32 / value}
-        log(f"[bench] fp32-bulk: {out32['ms_per_step']:.3f} ms/eval, {v32:.1f} Mpoints/s")
-        plan32_u = u32
+        # FP32-bulk form: the default (scaled M2L in FP32) and the split hi/lo FP32
+        # M2L products (T_hi M_hi + T_hi M_lo + T_lo M_hi per offset)
+        for name, mode, desc in (("fp32_scaled", "auto", "fp32 mfma, scaled form"),
+                                 ("split_hi_lo", "split", "split hi/lo fp32 mfma, per-offset operators")):
+            plan32 = vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=args.order_fp32,
+                             max_leaf=args.max_leaf, nbatch=nb, precision="fp32", m2l_mode=mode, root=wl.root)
+            u32 = torch.empty_like(u)
+            dt32, tim32 = time_evals(plan32, f, u32, args.steps, args.warmup)
+            v32 = wl.m * nb / (dt32 / args.steps) / 1e6
+            forms32[name] = ({"value": v32, "ms_per_step": dt32 / args.steps * 1e3, "order": args.order_fp32,
+                              "m2l": desc,
+                              "stages_ms": {k: v / max(tim32["evals"], 1) for k, v in tim32["ms"].items()},
+                              "speedup_vs_fp64": v32 / value}, u32)
+            log(f"[bench] fp32-bulk ({name}): {dt32 / args.steps * 1e3:.3f} ms/eval, {v32:.1f} Mpoints/s")
+            plan32.close()
+        out32 = forms32["fp32_scaled"][0]
+        out32["split_hi_lo"] = forms32["split_hi_lo"][0]
     cpu = None
     rel64 = rel32 = None
     if not args.no_cpu:
@@ -249,10 +257,11 @@ def main():
                          f"(direct float64 sum with compensated summation + CSR row), {tc:.1f} s"}
         got = u64.cpu().numpy()[:, sample]
         rel64 = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        for name, (rec32, u32) in forms32.items():
+            got32 = u32.cpu().numpy()[:, sample]
+            rec32["rel_err"] = float(np.max(np.abs(got32 - ref)) / np.max(np.abs(ref)))
         if out32 is not None:
-            got32 = plan32_u.cpu().numpy()[:, sample]
-            rel32 = float(np.max(np.abs(got32 - ref)) / np.max(np.abs(ref)))
-            out32["rel_err"] = rel32
+            rel32 = out32["rel_err"]
         log(f"[bench] rel_inf err fp64={rel64:.3e} fp32={rel32}")
 
     if args.copy_mib > 0:

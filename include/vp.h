@@ -65,6 +65,13 @@ enum {
     VP_M2L_FP32_SCALED = 5  /* the scaled form in FP32 (VP_FP32_BULK only) */
 };
 enum { VP_P2P_AUTO = 0, VP_P2P_PAIRWISE = 1, VP_P2P_TABLES = 2 };
+/* VP_FLAG_AUTOTUNE: with m2l_mode VP_M2L_AUTO, vp_plan times every M2L kernel
+   variant that meets the precision's accuracy (FP64: scaled and per-offset
+   FP64 products; FP32-bulk: scaled FP32, per-offset FP32 and scaled FP64
+   products) on this plan's interaction lists and keeps the fastest
+   (vp_get_info reports it).  The plan call then synchronises the stream a
+   few more times; results differ only by rounding. */
+enum { VP_FLAG_AUTOTUNE = 1 };
 
 typedef struct {
     int32_t order;     /* p: highest power kept in the expansions (p+1 complex
@@ -84,7 +91,7 @@ typedef struct {
                           pattern (uniform box grids) and the pairwise kernel
                           elsewhere */
     int32_t max_level; /* deepest tree level; 1..30; 0 = 30 */
-    int32_t flags;     /* reserved, must be 0 */
+    int32_t flags;     /* VP_FLAG_* bits; 0 = none */
     double root[3];    /* x0, y0, side of the root square; side <= 0 selects
                           the bounding square of sources and targets */
     void *stream;      /* hipStream_t for plan-time copies and evaluations;

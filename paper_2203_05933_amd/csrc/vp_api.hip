@@ -141,7 +141,7 @@ static void validate_plan_args(const double *x, const double *y, const double *w
         bad("FP32 M2L modes need precision VP_FP32_BULK");
     if (o.p2p_mode < 0 || o.p2p_mode > 2) bad("unknown p2p_mode");
     if (o.max_level < 0 || o.max_level > vp::LBITS) bad("max_level must be in 0..30");
-    if (o.flags != 0) bad("flags must be 0");
+    if (o.flags & ~VP_FLAG_AUTOTUNE) bad("unknown flags");
     if (o.root[2] > 0 && (!std::isfinite(o.root[0]) || !std::isfinite(o.root[1]) || !std::isfinite(o.root[2])))
         bad("non-finite root square");
 }
@@ -239,6 +239,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         vp::build_near_tables(P);
         if (o.p2p_mode == VP_P2P_TABLES && !P->near.active)
             throw Error(VP_EUNSUPPORTED, "p2p_mode TABLES needs targets = nodes and congruent leaves");
+        if ((o.flags & VP_FLAG_AUTOTUNE) && o.m2l_mode == VP_M2L_AUTO) vp::autotune_m2l(P);
     });
     if (st != VP_OK) {
         free_plan(P);  // the message is already in the thread-local slot

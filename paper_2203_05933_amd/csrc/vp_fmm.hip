@@ -1242,6 +1242,62 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
 template <class E>
 static void run_pattern_op(vp_plan_s *P, const PointRoles &R, bool p2m);
 
+// M2L of all V lists (and X-list virtual children) in one launch, by the
+// plan's M2L mode
+template <class E>
+static void launch_m2l(vp_plan_s *P) {
+    Tree &T = P->tree;
+    hipStream_t s = P->stream;
+    const int nb = P->nbatch, Pn = P->P, PD = P->PD;
+    E *M = static_cast<E *>(P->Mexp);
+    E *L = static_cast<E *>(P->Lexp);
+    const bool f32 = sizeof(E) == 4;
+    const Operators &O = P->ops;
+    {
+        TranslateArgs a = expansion_args(P, P->m2l_cols, P->n_m2l_boxes, T.v_slot, NOFF, 2 * Pn);
+        a.tile_ptr = P->m2l_tptr;
+        a.tile_ops = P->m2l_tops;
+        a.tile_order = P->m2l_torder;
+        if (P->m2l_mode == VP_M2L_FP64_SCALED || P->m2l_mode == VP_M2L_FP32_SCALED) {
+            M2LScaledArgs sa;
+            sa.cols_box = P->m2l_cols;
+            sa.ncols = a.ncols;
+            sa.nbatch = nb;
+            sa.slots = T.v_slot;
+            sa.tile_ptr = P->m2l_tptr;
+            sa.tile_ops = P->m2l_tops;
+            sa.tile_order = P->m2l_torder;
+            sa.P = Pn;
+            sa.in = a.in;
+            sa.out = a.out;
+            sa.PD = PD;
+            sa.level = T.level;
+            sa.logside = T.d_logside;
+            if (!f32)
+                m2l_scaled<double, double, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
+                                                   (const double *)M, (double *)L);
+            else if (P->m2l_mode == VP_M2L_FP32_SCALED)
+                m2l_scaled<float, float, float>(s, O.PQ, sa, O.m2l_q32, O.m2l_tin32, O.m2l_tout32, O.m2l_logt,
+                                                (const float *)M, (float *)L);
+            else
+                m2l_scaled<float, float, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
+                                                 (const float *)M, (float *)L);
+        } else if (!f32) {
+            translate_m2l<double, double, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const double *)M,
+                                                         (double *)L);
+        } else if (P->m2l_mode == VP_M2L_FP32_SPLIT) {
+            translate_m2l<float, float, float, true>(s, PD, a, P->ops.m2l_f32, P->ops.m2l_f32_lo,
+                                                     (const float *)M, (float *)L);
+        } else if (P->m2l_mode == VP_M2L_FP64_MFMA) {
+            translate_m2l<float, float, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const float *)M,
+                                                       (float *)L);
+        } else {
+            translate_m2l<float, float, float, false>(s, PD, a, P->ops.m2l_f32, nullptr, (const float *)M,
+                                                      (float *)L);
+        }
+    }
+}
+
 template <class E>
 // upward (P2M, M2M) or downward (M2L, P2L, L2L) half of the expansion passes
 static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool tables, bool upward) {
@@ -1304,49 +1360,7 @@ static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, b
     return;
     }
     P->stage_begin(VP_STAGE_M2L);
-    {
-        TranslateArgs a = expansion_args(P, P->m2l_cols, P->n_m2l_boxes, T.v_slot, NOFF, 2 * Pn);
-        a.tile_ptr = P->m2l_tptr;
-        a.tile_ops = P->m2l_tops;
-        a.tile_order = P->m2l_torder;
-        if (P->m2l_mode == VP_M2L_FP64_SCALED || P->m2l_mode == VP_M2L_FP32_SCALED) {
-            M2LScaledArgs sa;
-            sa.cols_box = P->m2l_cols;
-            sa.ncols = a.ncols;
-            sa.nbatch = nb;
-            sa.slots = T.v_slot;
-            sa.tile_ptr = P->m2l_tptr;
-            sa.tile_ops = P->m2l_tops;
-            sa.tile_order = P->m2l_torder;
-            sa.P = Pn;
-            sa.in = a.in;
-            sa.out = a.out;
-            sa.PD = PD;
-            sa.level = T.level;
-            sa.logside = T.d_logside;
-            if (!f32)
-                m2l_scaled<double, double, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
-                                                   (const double *)M, (double *)L);
-            else if (P->m2l_mode == VP_M2L_FP32_SCALED)
-                m2l_scaled<float, float, float>(s, O.PQ, sa, O.m2l_q32, O.m2l_tin32, O.m2l_tout32, O.m2l_logt,
-                                                (const float *)M, (float *)L);
-            else
-                m2l_scaled<float, float, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
-                                                 (const float *)M, (float *)L);
-        } else if (!f32) {
-            translate_m2l<double, double, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const double *)M,
-                                                         (double *)L);
-        } else if (P->m2l_mode == VP_M2L_FP32_SPLIT) {
-            translate_m2l<float, float, float, true>(s, PD, a, P->ops.m2l_f32, P->ops.m2l_f32_lo,
-                                                     (const float *)M, (float *)L);
-        } else if (P->m2l_mode == VP_M2L_FP64_MFMA) {
-            translate_m2l<float, float, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const float *)M,
-                                                       (float *)L);
-        } else {
-            translate_m2l<float, float, float, false>(s, PD, a, P->ops.m2l_f32, nullptr, (const float *)M,
-                                                      (float *)L);
-        }
-    }
+    launch_m2l<E>(P);
     P->stage_end(VP_STAGE_M2L);
     P->stage_begin(VP_STAGE_P2L);
     if (P->n_x_boxes > 0) {
@@ -1649,6 +1663,36 @@ static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint) {
                        inv, scale, P->acc, nrows, u);
     VP_LAUNCH_CHECK();
     P->stage_end(VP_STAGE_FINISH);
+}
+
+void autotune_m2l(vp_plan_s *P) {
+    std::vector<int> cand;
+    if (P->fp32) cand = {VP_M2L_FP32_SCALED, VP_M2L_FP32_MFMA, VP_M2L_FP64_SCALED};
+    else cand = {VP_M2L_FP64_SCALED, VP_M2L_FP64_MFMA};
+    hipEvent_t e0, e1;
+    VP_HIP(hipEventCreate(&e0));
+    VP_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_mode = P->m2l_mode;
+    for (int mode : cand) {
+        P->m2l_mode = mode;
+        for (int rep = 0; rep < 4; ++rep) {  // first launch warms up
+            VP_HIP(hipEventRecord(e0, P->stream));
+            if (P->fp32) launch_m2l<float>(P);
+            else launch_m2l<double>(P);
+            VP_HIP(hipEventRecord(e1, P->stream));
+            VP_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            VP_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0 && ms < best) {
+                best = ms;
+                best_mode = mode;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P->m2l_mode = best_mode;
 }
 
 void finish_grad(vp_plan_s *P, double *grad) {

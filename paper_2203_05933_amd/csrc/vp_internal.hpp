@@ -314,6 +314,8 @@ void build_operators(vp_plan_s *P);
 void build_near_tables(vp_plan_s *P);  // vp_near.hip
 // vp_fmm.hip
 void build_schedules(vp_plan_s *P);
+// time the M2L variants valid for the plan's precision and keep the fastest
+void autotune_m2l(vp_plan_s *P);
 // congruent-leaf operators exist for this pattern size and expansion size
 bool pattern_op_supported(int npat, int PD);
 // gather the U-list sources of `leaves` (host CSR uptr/uidx, source ranges sb/se; device coordinates sx/sy)

@@ -256,6 +256,23 @@ def test_m2l_scaled_matches_per_offset_operators(c0, order):
     assert relinf(u2, u1) <= 1e-13
 
 
+@pytest.mark.parametrize("precision,order,tol", [("fp64", 30, TOL64), ("fp32", 14, TOL32)])
+def test_autotuned_m2l(c0, precision, order, tol):
+    """The plan-time M2L autotuner picks one of the valid kernels for the
+    precision, and the evaluation still meets the oracle tolerance."""
+    vp = _vp()
+    plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=order, precision=precision,
+                   autotune=True, root=c0.root)
+    mode = plan.info()["m2l_mode"]
+    assert mode in ((4, 1) if precision == "fp64" else (5, 2, 4)), mode
+    u = _host(plan.eval(_dev(c0.f)))
+    ref = direct.evaluate(c0.x, c0.y, c0.w, c0.f, c0.rowptr, c0.col, c0.val)
+    err = relinf(u, ref)
+    print(f"autotuned {precision}: m2l mode {mode}, rel_inf={err:.3e}")
+    assert err <= tol
+    plan.close()
+
+
 @pytest.mark.parametrize("nbatch", [1, 2, 3, 5])
 def test_correction_general_csr(nbatch):
     """A correction matrix that is not run-structured: rows of 0 to 150 entries
