@@ -153,7 +153,7 @@ def _stage_roofline(plan, tim, precision, stage):
         nnz, m, n_ = info["nnz"], info["m"], info["n"]
         bytes_ = nnz * 8 + (m + 1) * 8 + m * 4 + m * 8 * nb + n_ * 8 * nb
         return {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": 8000.0, "unit": "GB/s",
-                "frac": bytes_ / avg_s / 1e9 / 8000.0, "traffic": None, "kernel": "k_finish<G, false>",
+                "frac": bytes_ / avg_s / 1e9 / 8000.0, "traffic": None, "kernel": "k_corr",
                 "avg_ms": avg_s * 1e3,
                 "work": f"{nnz} values x 8 B + row pointers and runs, f read once, {nb} output rows written"}
     return None
@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--max-leaf", type=int, default=64)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (cpu_baseline and errors)")
+    ap.add_argument("--no-one-stream", action="store_true",
+                    help="skip the one-stream run (per-stage times without the second stream's overlap)")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="targets the oracle evaluates")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed loops, run one plain device copy (y = 2 x) of this many MiB read and "
@@ -220,6 +222,23 @@ def main():
         + json.dumps({k: round(v / max(tim['evals'], 1), 4) for k, v in tim["ms"].items()}))
     stage, roof, roofs = roofline(plan, tim, "fp64", wl.name)
     u64 = u.clone()
+
+    one = None
+    if not args.no_one_stream:
+        # the same evaluation with every kernel on one stream: stage times
+        # without contention from the overlapped second stream
+        plan1 = vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=args.order,
+                        max_leaf=args.max_leaf, nbatch=nb, precision="fp64", one_stream=True, root=wl.root)
+        u1 = torch.empty_like(u)
+        dt1, tim1 = time_evals(plan1, f, u1, args.steps, args.warmup)
+        one = {"ms_per_step": dt1 / args.steps * 1e3,
+               "stages_ms": {k: v / max(tim1["evals"], 1) for k, v in tim1["ms"].items()},
+               "stage_rooflines": {st: r for st in ("m2l", "p2p", "corr")
+                                   if (r := _stage_roofline(plan1, tim1, "fp64", st)) is not None}}
+        log(f"[bench] fp64 one stream: {one['ms_per_step']:.3f} ms/eval; stages(ms/eval)="
+            + json.dumps({k: round(v, 4) for k, v in one["stages_ms"].items()}))
+        plan1.close()
+        del u1
 
     out32 = None
     forms32 = {}
@@ -296,6 +315,7 @@ def main():
         "dominant_stage": stage,
         "roofline": roof,
         "stage_rooflines": roofs,
+        "one_stream": one,
         "fp32_form": out32,
         "cpu_baseline": cpu,
     }

@@ -71,7 +71,13 @@ enum { VP_P2P_AUTO = 0, VP_P2P_PAIRWISE = 1, VP_P2P_TABLES = 2 };
    products) on this plan's interaction lists and keeps the fastest
    (vp_get_info reports it).  The plan call then synchronises the stream a
    few more times; results differ only by rounding. */
-enum { VP_FLAG_AUTOTUNE = 1 };
+/* VP_FLAG_ONE_STREAM: run every kernel of an evaluation on the plan's stream,
+   in sequence.  By default the correction apply and the near field run on a
+   second stream owned by the plan, beside the expansion passes, and join the
+   plan's stream before the far field; with this flag nothing overlaps (for
+   callers that need all work on one stream, and for per-stage timings
+   without contention).  Results are identical either way. */
+enum { VP_FLAG_AUTOTUNE = 1, VP_FLAG_ONE_STREAM = 2 };
 
 typedef struct {
     int32_t order;     /* p: highest power kept in the expansions (p+1 complex

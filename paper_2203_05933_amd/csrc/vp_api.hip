@@ -141,7 +141,7 @@ static void validate_plan_args(const double *x, const double *y, const double *w
         bad("FP32 M2L modes need precision VP_FP32_BULK");
     if (o.p2p_mode < 0 || o.p2p_mode > 2) bad("unknown p2p_mode");
     if (o.max_level < 0 || o.max_level > vp::LBITS) bad("max_level must be in 0..30");
-    if (o.flags & ~VP_FLAG_AUTOTUNE) bad("unknown flags");
+    if (o.flags & ~(VP_FLAG_AUTOTUNE | VP_FLAG_ONE_STREAM)) bad("unknown flags");
     if (o.root[2] > 0 && (!std::isfinite(o.root[0]) || !std::isfinite(o.root[1]) || !std::isfinite(o.root[2])))
         bad("non-finite root square");
 }
@@ -188,6 +188,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->PD = ((2 * P->P + 1 + 15) / 16) * 16;
         if (P->PD > 128) throw Error(VP_EUNSUPPORTED, "order too large (2(p+1)+1 must be <= 128)");
         P->fp32 = (o.precision == VP_FP32_BULK);
+        P->one_stream = (o.flags & VP_FLAG_ONE_STREAM) != 0;
         P->m2l_mode = o.m2l_mode == VP_M2L_AUTO ? (P->fp32 ? VP_M2L_FP32_SCALED : VP_M2L_FP64_SCALED) : o.m2l_mode;
         P->stream = static_cast<hipStream_t>(o.stream);
         VP_HIP(hipGetDevice(&P->device));
@@ -228,6 +229,8 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         const size_t mcount = (size_t)(P->tree.nbox + 4 * (size_t)P->n_vleaf) * P->nbatch * P->PD;
         P->Mexp = P->mem.alloc<unsigned char>(mcount * esz);
         P->Lexp = P->mem.alloc<unsigned char>(ecount * esz);
+        P->zero_col = P->mem.alloc<double>(P->PD);  // read by M2L for absent sources
+        vp::fill_f64((double *)P->zero_col, 0.0, P->PD, P->stream);
         if (P->fp32) {
             vp::fill_f32((float *)P->Mexp, 0.f, (int64_t)mcount, P->stream);
             vp::fill_f32((float *)P->Lexp, 0.f, (int64_t)ecount, P->stream);

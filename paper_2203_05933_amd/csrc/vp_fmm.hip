@@ -1086,7 +1086,7 @@ void build_schedules(vp_plan_s *P) {
     {
         const int64_t ncols = (int64_t)m2l.size() * P->nbatch;
         const int64_t ntiles = (ncols + 15) / 16;
-        std::vector<int32_t> tptr(1, 0), tops;
+        std::vector<int32_t> tptr(1, 0), tops, tsrc;
         for (int64_t t = 0; t < ntiles; ++t) {
             uint64_t mask = 0;
             for (int64_t c = 16 * t; c < std::min(ncols, 16 * t + 16); ++c) {
@@ -1095,7 +1095,12 @@ void build_schedules(vp_plan_s *P) {
                     if (vslot[(size_t)b * NOFF + o] >= 0) mask |= 1ull << o;
             }
             for (int o = 0; o < NOFF; ++o)
-                if (mask >> o & 1) tops.push_back(o);
+                if (mask >> o & 1) {
+                    tops.push_back(o);
+                    // each column's source box for this offset (-1: none)
+                    for (int64_t c = 16 * t; c < 16 * t + 16; ++c)
+                        tsrc.push_back(c < ncols ? vslot[(size_t)m2l[c / P->nbatch] * NOFF + o] : -1);
+                }
             tptr.push_back((int32_t)tops.size());
         }
         const std::vector<int32_t> order = tile_order_by_work(tptr);
@@ -1105,6 +1110,7 @@ void build_schedules(vp_plan_s *P) {
             for (int o = 0; o < NOFF; ++o) P->m2l_translations += vslot[(size_t)b * NOFF + o] >= 0;
         P->m2l_tptr = up(tptr);
         P->m2l_tops = up(tops);
+        P->m2l_tsrc = up(tsrc);
         P->m2l_torder = up(order);
         VP_HIP(hipStreamSynchronize(s));  // the host vectors leave scope
     }
@@ -1263,14 +1269,15 @@ static void launch_m2l(vp_plan_s *P) {
             sa.cols_box = P->m2l_cols;
             sa.ncols = a.ncols;
             sa.nbatch = nb;
-            sa.slots = T.v_slot;
             sa.tile_ptr = P->m2l_tptr;
             sa.tile_ops = P->m2l_tops;
+            sa.tile_src = P->m2l_tsrc;
             sa.tile_order = P->m2l_torder;
             sa.P = Pn;
-            sa.in = a.in;
-            sa.out = a.out;
+            sa.box_stride = (int64_t)nb * PD;
+            sa.bt_stride = PD;
             sa.PD = PD;
+            sa.zero_col = P->zero_col;
             sa.level = T.level;
             sa.logside = T.d_logside;
             if (!f32)
@@ -1569,14 +1576,16 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) 
     // correction and near field on the auxiliary stream (the HBM-bound
     // correction first), concurrent with the expansion passes
     hipStream_t main_stream = P->stream;
-    VP_HIP(hipEventRecord(P->ev_fork, main_stream));
-    VP_HIP(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
+    if (!P->one_stream) {
+        VP_HIP(hipEventRecord(P->ev_fork, main_stream));
+        VP_HIP(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
+    }
     struct Restore {
         vp_plan_s *P;
         hipStream_t s;
         ~Restore() { P->stream = s; }
     } restore{P, main_stream};
-    P->stream = P->aux;
+    if (!P->one_stream) P->stream = P->aux;
     if (u) correction_apply(P, f, u, adjoint);
     if (tables) {
         P->stage_begin(VP_STAGE_TABLES);
@@ -1595,13 +1604,13 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) 
                               P->acc);
     }
     P->stage_end(VP_STAGE_P2P);
-    VP_HIP(hipEventRecord(P->ev_join, P->aux));
+    if (!P->one_stream) VP_HIP(hipEventRecord(P->ev_join, P->aux));
     P->stream = main_stream;
     if (P->fp32) run_expansions<float>(P, R, G, tables, true);
     else run_expansions<double>(P, R, G, tables, true);
     if (P->fp32) run_expansions<float>(P, R, G, tables, false);
     else run_expansions<double>(P, R, G, tables, false);
-    VP_HIP(hipStreamWaitEvent(main_stream, P->ev_join, 0));
+    if (!P->one_stream) VP_HIP(hipStreamWaitEvent(main_stream, P->ev_join, 0));
     if (T.nlevels >= 3) {
         if (grad) {
             if (P->fp32) run_far<float, true>(P, R, G, P->acc, false);

@@ -219,6 +219,7 @@ struct vp_plan_s {
     bool self = false;
     bool fp32 = false;
     int m2l_mode = VP_M2L_FP64_MFMA;
+    bool one_stream = false;  // no second stream: every kernel on the plan's stream
     hipStream_t stream = nullptr;
     // the near field runs on its own stream, forked after the charges and
     // joined before the far-field evaluation (both default priority)
@@ -258,10 +259,12 @@ struct vp_plan_s {
     double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order
     void *Mexp = nullptr;    // [nbox + 4 n_vleaf][nbatch][PD] (double or float)
     void *Lexp = nullptr;
+    void *zero_col = nullptr;  // PD zeros (enough for either element type)
     vp::P2PGather g_fwd, g_adj;   // full U-list sources (nodes / targets as sources) without tables
     int32_t *m2l_cols = nullptr;  // boxes of levels >= 2, grouped by child class
     int32_t *m2l_tptr = nullptr;  // offsets present per 16-column tile of (box, density) columns
     int32_t *m2l_tops = nullptr;
+    int32_t *m2l_tsrc = nullptr;    // [tile op][16] source box per column, or -1
     int32_t *m2l_torder = nullptr;  // tiles by decreasing offset count
     int64_t m2l_translations = 0, m2l_tile_ops = 0;
     int32_t *child_slot = nullptr;   // [nbox][4] child in each quadrant or -1

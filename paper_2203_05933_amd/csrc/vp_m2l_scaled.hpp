@@ -16,8 +16,12 @@
 //
 // Work split: a 16-column tile (boxes x densities, grouped by child class
 // so the tile shares its offsets) per workgroup; the four waves take every
-// fourth offset present in the tile (listed at plan time) and their partial
-// sums are added through LDS in a fixed order.
+// fourth offset present in the tile (listed at plan time, with each column's
+// source box) and their partial sums are added through LDS in a fixed order.
+// The diagonal scalings of all 40 offsets sit in LDS for the whole tile, and
+// the next offset's source columns are loaded while the current offset is on
+// the matrix cores; the loop has no branch around a load and no dependent
+// global load.
 #pragma once
 
 #include "vp_translate.hpp"
@@ -28,18 +32,36 @@ struct M2LScaledArgs {
     const int32_t *cols_box;  // box of column group c / nbatch
     int ncols;                // (box, density) columns
     int nbatch;
-    const int32_t *slots;     // [box][NOFF] source box or -1
     const int32_t *tile_ptr;  // offsets present in 16-column tile t: tile_ops[tile_ptr[t] .. tile_ptr[t+1])
     const int32_t *tile_ops;
+    const int32_t *tile_src;  // [tile op][16]: source box of each column of the tile, or -1
     const int32_t *tile_order;  // launch order of the tiles (most offsets first)
     int P;                    // complex coefficients per expansion
-    ColAddr in, out;          // expansion columns (PD rows: re 0..P-1, im P..2P-1)
-    int PD;
+    int64_t box_stride;       // elements between the columns of consecutive boxes
+    int64_t bt_stride;        // elements between the densities of one box
+    int PD;                   // rows per column (re 0..P-1, im P..2P-1, zero padding)
     const int32_t *level;
     const double *logside;    // log of the box side per level
+    const void *zero_col;     // PD zeros of the input type (the column of an absent source)
 };
 
-// Q in A-fragment order [rb][s][lane]; tin/tout [NOFF][RB*16][2] (re, im);
+// Column of one source for the k-steps of lane group g (k = g*S + s).  An
+// absent source reads a column of zeros, and k >= P reads coefficient P-1,
+// which the zero rows k >= P of the input scaling then remove: every lane
+// loads, no load sits behind a branch, and no select waits on a load.
+template <class TI, class TM, int S>
+__device__ inline void m2l_load_col(const TI *__restrict__ ip, int g, int P, TM (&xr)[S], TM (&xi)[S]) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int k = g * S + s;
+        const int kk = k < P ? k : P - 1;
+        xr[s] = (TM)ip[kk];
+        xi[s] = (TM)ip[P + kk];
+    }
+}
+
+// Q in A-fragment order [rb][s][lane] for k = 4 s + lane/16 (regathered here
+// for k = (lane/16) S + s); tin/tout [NOFF][RB*16][2] (re, im);
 // logt [NOFF][2] = log(-t).
 template <class TI, class TO, class TM, int RB>
 __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *__restrict__ Qf,
@@ -47,10 +69,21 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
                                                     const double *__restrict__ logt, const TI *__restrict__ in,
                                                     TO *__restrict__ out) {
     typedef Mfma<TM> M;
-    constexpr int S = RB * 4;  // 4-row steps of the input (RB*16 rows)
+    constexpr int S = RB * 4;  // k-steps: lane group g takes k = g*S + s
     constexpr int PQ = RB * 16;
     constexpr int NR = RB * 4 * 2 + 2;  // reduced values per lane: B re/im per item, A_0 sum re/im
-    __shared__ double red[3][NR][64];
+    constexpr int TAB = NOFF * PQ * 2;  // elements of one scaling table
+    constexpr int TBYTES = 2 * TAB * (int)sizeof(TM) + NOFF * 2 * (int)sizeof(double);
+    constexpr int RBYTES = 3 * NR * 64 * (int)sizeof(double);
+    // scaling tables during the loop, the cross-wave partial sums after it
+    __shared__ __align__(16) unsigned char s_raw[TBYTES > RBYTES ? TBYTES : RBYTES];
+    __shared__ int32_t s_ops[NOFF];
+    __shared__ int32_t s_src[NOFF][16];
+    TM *s_tin = reinterpret_cast<TM *>(s_raw);
+    TM *s_tout = s_tin + TAB;
+    double *s_logt = reinterpret_cast<double *>(s_raw + 2 * TAB * sizeof(TM));
+    double(*red)[NR][64] = reinterpret_cast<double(*)[NR][64]>(s_raw);
+
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cl = lane & 15, g = lane >> 4;
     const int tile = a.tile_order[blockIdx.x];
@@ -60,11 +93,29 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
     const int bt = valid ? col % a.nbatch : 0;
     const int P = a.P;
 
+    // stage the tile's offsets and sources and the tables of all offsets
+    const int e0 = a.tile_ptr[tile], nt = a.tile_ptr[tile + 1] - e0;
+    for (int i = tid; i < nt; i += 256) s_ops[i] = a.tile_ops[e0 + i];
+    for (int i = tid; i < nt * 16; i += 256) s_src[i >> 4][i & 15] = a.tile_src[(int64_t)e0 * 16 + i];
+    {
+        constexpr int CH = TAB * (int)sizeof(TM) / 16;  // 16-byte chunks per table
+        const uint4 *gi = reinterpret_cast<const uint4 *>(tin), *go = reinterpret_cast<const uint4 *>(tout);
+        uint4 *si = reinterpret_cast<uint4 *>(s_tin), *so = reinterpret_cast<uint4 *>(s_tout);
+        for (int i = tid; i < CH; i += 256) {
+            si[i] = gi[i];
+            so[i] = go[i];
+        }
+        if (tid < 2 * NOFF) s_logt[tid] = logt[tid];
+    }
     TM q[RB][S];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int s = 0; s < S; ++s) q[r][s] = Qf[(r * S + s) * 64 + lane];
+        for (int s = 0; s < S; ++s) {
+            const int k = g * S + s;
+            q[r][s] = Qf[(r * S + (k >> 2)) * 64 + (k & 3) * 16 + cl];
+        }
+    __syncthreads();
 
     double br[RB][4], bi[RB][4];
 #pragma unroll
@@ -72,72 +123,43 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
 #pragma unroll
         for (int i = 0; i < 4; ++i) br[r][i] = bi[r][i] = 0.0;
     double a0r = 0.0, a0i = 0.0;  // sum of A_0 over the sources (lanes g == 0)
+    const int64_t bt_off = (int64_t)bt * a.bt_stride;
 
-    // the tile's offsets and each column's source per offset, staged in LDS
-    // once (no dependent global loads inside the loop)
-    __shared__ int32_t s_ops[NOFF];
-    __shared__ int32_t s_src[NOFF][16];
-    const int e0 = a.tile_ptr[tile], nt = a.tile_ptr[tile + 1] - e0;
-    for (int i = tid; i < nt; i += 256) s_ops[i] = a.tile_ops[e0 + i];
-    __syncthreads();
-    for (int i = tid; i < nt * 16; i += 256) {
-        const int oi = i >> 4, c = i & 15, cc = tile * 16 + c;
-        s_src[oi][c] = cc < a.ncols ? a.slots[(int64_t)a.cols_box[cc / a.nbatch] * NOFF + s_ops[oi]] : -1;
-    }
-    __syncthreads();
-
-    // this wave's offsets: every fourth one present in the tile; the source
-    // columns of the next offset are loaded while the current one is on the
-    // matrix cores
-    const int e1 = nt;
+    // this wave's offsets: every fourth one present in the tile
     int e = wave;
-    int o = 0, src = -1;
+    const TI *zc = static_cast<const TI *>(a.zero_col);
     TM xr[S], xi[S];
-    if (e < e1) {
-        o = s_ops[e];
-        src = s_src[e][cl];
-        const TI *ip = in + (src >= 0 ? a.in.off(src) + (int64_t)bt * a.in.bstride : 0);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = 4 * s + g;
-            const bool ok = src >= 0 && k < P;
-            xr[s] = ok ? (TM)ip[k] : (TM)0;
-            xi[s] = ok ? (TM)ip[P + k] : (TM)0;
-        }
+    {
+        const int src = e < nt ? s_src[e][cl] : -1;
+        m2l_load_col<TI, TM, S>(src >= 0 ? in + (int64_t)src * a.box_stride + bt_off : zc, g, P, xr, xi);
     }
-    while (e < e1) {
-        const TM *ti = tin + (size_t)o * PQ * 2;
+    const double m0 = g == 0 ? 1.0 : 0.0;  // lanes holding k = 0 at step 0
+    for (; e < nt; e += 4) {
+        const int o = s_ops[e];
+        const TM *ti = s_tin + o * PQ * 2;
         TM yr[S], yi[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const int k = 4 * s + g;
+            const int k = g * S + s;
             const TM wr = ti[2 * k], wi = ti[2 * k + 1];
             yr[s] = xr[s] * wr - xi[s] * wi;
             yi[s] = xr[s] * wi + xi[s] * wr;
         }
-        if (g == 0 && src >= 0) {
+        {
             // A_0 log(-t): the offset-dependent part of the k = 0 column
-            const double x0r = (double)xr[0], x0i = (double)xi[0];
-            const double lr = logt[2 * o], li = logt[2 * o + 1];
+            // (step 0 of lane group 0); other lanes add exact zeros
+            const double x0r = (double)xr[0] * m0, x0i = (double)xi[0] * m0;
+            const double lr = s_logt[2 * o], li = s_logt[2 * o + 1];
             br[0][M::item_of(0)] += x0r * lr - x0i * li;
             bi[0][M::item_of(0)] += x0r * li + x0i * lr;
             a0r += x0r;
             a0i += x0i;
         }
-        // prefetch the next offset's source columns
-        const int en = e + 4;
-        int on = 0, srcn = -1;
-        if (en < e1) {
-            on = s_ops[en];
-            srcn = s_src[en][cl];
-            const TI *ip = in + (srcn >= 0 ? a.in.off(srcn) + (int64_t)bt * a.in.bstride : 0);
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const int k = 4 * s + g;
-                const bool ok = srcn >= 0 && k < P;
-                xr[s] = ok ? (TM)ip[k] : (TM)0;
-                xi[s] = ok ? (TM)ip[P + k] : (TM)0;
-            }
+        // the next offset's source columns, in flight during the products
+        {
+            const int en = e + 4;
+            const int srcn = en < nt ? s_src[en][cl] : -1;
+            m2l_load_col<TI, TM, S>(srcn >= 0 ? in + (int64_t)srcn * a.box_stride + bt_off : zc, g, P, xr, xi);
         }
         typename M::acc_t zr[RB], zi[RB];
 #pragma unroll
@@ -152,7 +174,7 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
                 zr[r] = M::op(q[r][s], yr[s], zr[r]);
                 zi[r] = M::op(q[r][s], yi[s], zi[r]);
             }
-        const TM *to = tout + (size_t)o * PQ * 2;
+        const TM *to = s_tout + o * PQ * 2;
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -163,11 +185,10 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
                 br[r][i] += zre * vr - zim * vi;
                 bi[r][i] += zre * vi + zim * vr;
             }
-        e = en;
-        o = on;
-        src = srcn;
     }
-    // fixed-order sum of the four waves' partial results
+    // fixed-order sum of the four waves' partial results (the tables' LDS is
+    // reused once every wave has left the loop)
+    __syncthreads();
     if (wave > 0) {
 #pragma unroll
         for (int r = 0; r < RB; ++r)
@@ -196,7 +217,7 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
         br[0][M::item_of(0)] += a0r * ls;
         bi[0][M::item_of(0)] += a0i * ls;
     }
-    TO *op = out + a.out.off(box) + (int64_t)bt * a.out.bstride;
+    TO *op = out + (int64_t)box * a.box_stride + (int64_t)bt * a.bt_stride;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll

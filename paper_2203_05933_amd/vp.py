@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libvp.so")
 VP_OK, VP_EINVAL, VP_ENOMEM, VP_EDEVICE, VP_EUNSUPPORTED, VP_EINTERNAL = range(6)
 VP_FP64, VP_FP32_BULK = 0, 1
 VP_FLAG_AUTOTUNE = 1
+VP_FLAG_ONE_STREAM = 2
 M2L_MODES = {"auto": 0, "fp64": 1, "fp32": 2, "split": 3, "fp64_scaled": 4, "fp32_scaled": 5}
 P2P_MODES = {"auto": 0, "pairwise": 1, "tables": 2}
 ARR = {
@@ -142,7 +143,8 @@ class Plan:
 
     def __init__(self, x, y, w, tx=None, ty=None, rowptr=None, col=None, val=None, *, order: int = 30,
                  max_leaf: int = 64, nbatch: int = 1, precision: str = "fp64", m2l_mode: str = "auto",
-                 p2p_mode: str = "auto", root=None, max_level: int = 0, autotune: bool = False, stream=None):
+                 p2p_mode: str = "auto", root=None, max_level: int = 0, autotune: bool = False,
+                 one_stream: bool = False, stream=None):
         lib = load_library()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -164,7 +166,7 @@ class Plan:
         o.m2l_mode = M2L_MODES[m2l_mode]
         o.p2p_mode = P2P_MODES[p2p_mode]
         o.max_level = max_level
-        o.flags = VP_FLAG_AUTOTUNE if autotune else 0
+        o.flags = (VP_FLAG_AUTOTUNE if autotune else 0) | (VP_FLAG_ONE_STREAM if one_stream else 0)
         if root is not None:
             o.root[0], o.root[1], o.root[2] = root
         o.stream = _current_stream() if stream is None else ctypes.c_void_p(stream)

@@ -73,7 +73,7 @@ def test_plan_rejects_invalid(case):
     elif case == "fp32_mode":
         kw["m2l_mode"] = 2  # FP32 M2L with precision FP64
     elif case == "flags":
-        kw["flags"] = 2  # unknown bit
+        kw["flags"] = 4  # unknown bit
     if case == "m_mismatch":
         st, h, msg = _plan(lib, vp, x, y, w, n, m=7, rowptr=rowptr, col=col, val=val)
     else:

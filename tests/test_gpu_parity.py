@@ -273,6 +273,26 @@ def test_autotuned_m2l(c0, precision, order, tol):
     plan.close()
 
 
+@pytest.mark.parametrize("precision,order", [("fp64", 30), ("fp32", 14)])
+def test_one_stream_matches_two_streams(c0, precision, order):
+    """VP_FLAG_ONE_STREAM runs the correction and the near field on the plan's
+    stream in sequence; every kernel computes the same sums in the same
+    order, so forward and adjoint results are bitwise identical to the
+    overlapped default, and both meet the oracle tolerance."""
+    vp = _vp()
+    out = []
+    for one in (False, True):
+        plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=order,
+                       precision=precision, one_stream=one, root=c0.root)
+        out.append((_host(plan.eval(_dev(c0.f))), _host(plan.eval_adjoint(_dev(c0.f)))))
+        plan.close()
+    (u2, a2), (u1, a1) = out
+    assert np.array_equal(u1, u2)
+    assert np.array_equal(a1, a2)
+    ref = direct.evaluate(c0.x, c0.y, c0.w, c0.f, c0.rowptr, c0.col, c0.val)
+    assert relinf(u1, ref) <= (TOL64 if precision == "fp64" else TOL32)
+
+
 @pytest.mark.parametrize("nbatch", [1, 2, 3, 5])
 def test_correction_general_csr(nbatch):
     """A correction matrix that is not run-structured: rows of 0 to 150 entries
