@@ -229,8 +229,10 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         const size_t mcount = (size_t)(P->tree.nbox + 4 * (size_t)P->n_vleaf) * P->nbatch * P->PD;
         P->Mexp = P->mem.alloc<unsigned char>(mcount * esz);
         P->Lexp = P->mem.alloc<unsigned char>(ecount * esz);
-        P->zero_col = P->mem.alloc<double>(P->PD);  // read by M2L for absent sources
-        vp::fill_f64((double *)P->zero_col, 0.0, P->PD, P->stream);
+        // zeros read in place of an absent source column (M2L, near tables)
+        const int64_t nzero = std::max<int64_t>(P->PD, 128);
+        P->zero_col = P->mem.alloc<double>(nzero);
+        vp::fill_f64((double *)P->zero_col, 0.0, nzero, P->stream);
         if (P->fp32) {
             vp::fill_f32((float *)P->Mexp, 0.f, (int64_t)mcount, P->stream);
             vp::fill_f32((float *)P->Lexp, 0.f, (int64_t)ecount, P->stream);

@@ -1212,6 +1212,7 @@ static TranslateArgs expansion_args(vp_plan_s *P, const int32_t *cols, int nboxe
     a.logrow = logrow;
     a.level = P->tree.level;
     a.logside = P->tree.d_logside;
+    a.zero_col = P->zero_col;
     return a;
 }
 
@@ -1458,6 +1459,7 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     a.logrow = -1;
     a.level = P->tree.level;
     a.logside = P->tree.d_logside;
+    a.zero_col = P->zero_col;
     if (a.ncols <= 0) return;
     hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, true>),
                        dim3((unsigned)((a.ncols + 15) / 16)), dim3(256), 0, P->stream, a, N.K, (const double *)nullptr,

@@ -259,7 +259,7 @@ struct vp_plan_s {
     double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order
     void *Mexp = nullptr;    // [nbox + 4 n_vleaf][nbatch][PD] (double or float)
     void *Lexp = nullptr;
-    void *zero_col = nullptr;  // PD zeros (enough for either element type)
+    void *zero_col = nullptr;  // max(PD, 128) zero doubles (an absent source column, either element type)
     vp::P2PGather g_fwd, g_adj;   // full U-list sources (nodes / targets as sources) without tables
     int32_t *m2l_cols = nullptr;  // boxes of levels >= 2, grouped by child class
     int32_t *m2l_tptr = nullptr;  // offsets present per 16-column tile of (box, density) columns

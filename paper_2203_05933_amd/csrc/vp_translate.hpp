@@ -78,6 +78,7 @@ struct TranslateArgs {
     const int32_t *tile_ptr = nullptr;
     const int32_t *tile_ops = nullptr;
     const int32_t *tile_order = nullptr;  // optional launch order of the tiles (most operators first)
+    const void *zero_col = nullptr;       // zeros of the input type, at least 4 S long (absent sources)
 };
 
 // TI/TO: element types of input/output columns; TM: matrix-core type;
@@ -192,20 +193,42 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
     typename M::acc_t acc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r] = M::zero();
+    const TI *zc = static_cast<const TI *>(a.zero_col);
     auto product = [&](int o, int src) {
+        // an absent source reads the zero column: no branch around the loads
+        const TI *ip = (src >= 0 ? in + a.in.off(src) + (int64_t)bt * a.in.bstride : zc) + g;
         TM bv[S];
-        const TI *ip = in + (src >= 0 ? a.in.off(src) + (int64_t)bt * a.in.bstride : 0) + g;
 #pragma unroll
-        for (int s = 0; s < S; ++s) bv[s] = (src >= 0) ? (TM)ip[4 * s] : (TM)0;
+        for (int s = 0; s < S; ++s) bv[s] = (TM)ip[4 * s];
         const TM *Ao = Ahi + (int64_t)o * AE + lane;
         const TM *Alo_o = SPLIT ? Alo + (int64_t)o * AE + lane : nullptr;
+        // operator fragments one 16-row block at a time: the loads of block
+        // r + 1 are in flight while block r is on the matrix cores (the
+        // scheduling barriers keep the compiler from pairing every load with
+        // its product and a full wait)
+        TM ah[2][S], al[2][SPLIT ? S : 1];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            ah[0][s] = Ao[s * 64];
+            if (SPLIT) al[0][s] = Alo_o[s * 64];
+        }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
+            const int c = r & 1;
+            if (r + 1 < RB) {
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    ah[c ^ 1][s] = Ao[((r + 1) * S + s) * 64];
+                    if (SPLIT) al[c ^ 1][s] = Alo_o[((r + 1) * S + s) * 64];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                acc[r] = M::op(Ao[(r * S + s) * 64], bv[s], acc[r]);
-                if (SPLIT) acc[r] = M::op(Alo_o[(r * S + s) * 64], bv[s], acc[r]);
+                acc[r] = M::op(ah[c][s], bv[s], acc[r]);
+                if (SPLIT) acc[r] = M::op(al[c][s], bv[s], acc[r]);
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     };
     if (a.tile_ptr) {
