@@ -131,7 +131,10 @@ def _stage_roofline(plan, tim, precision, stage):
                 "avg_ms": avg_s * 1e3,
                 "work": f"{info['near_pairs']} pairs x {nb} densities x {P2P_FLOPS_PER_PAIR} flops"}
     if stage == "m2l":
-        nv = info["m2l_translations"]
+        # the "m2l" stage times the launch over the levels from split_level on;
+        # the levels below run in the "coarse" stage on the third stream
+        nv = info["m2l_translations"] - info["m2l_coarse_translations"]
+        tile_ops = info["m2l_tile_ops"] - info["m2l_coarse_tile_ops"]
         scaled = info["m2l_mode"] in (4, 5)
         fp64_core = info["m2l_mode"] in (1, 4)
         per = 4 * P * P + 12 * P if scaled else 8 * P * P
@@ -142,13 +145,13 @@ def _stage_roofline(plan, tim, precision, stage):
         # PQ x PQ products (scaled form) or one PD x PD product
         PQ = (P + 15) // 16 * 16
         PDm = (2 * P + 1 + 15) // 16 * 16
-        issued = info["m2l_tile_ops"] * (64 * PQ * PQ if scaled else 32 * PDm * PDm)
+        issued = tile_ops * (64 * PQ * PQ if scaled else 32 * PDm * PDm)
         return {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
                 "frac": flops / avg_s / 1e12 / peak, "traffic": None,
                 "kernel": "k_m2l_scaled" if scaled else "k_translate_split", "avg_ms": avg_s * 1e3,
                 "issued_tflops": issued / avg_s / 1e12,
-                "work": f"{nv} translations (V lists and X-list virtual children) x {nb} densities x {per} flops "
-                        f"({form}, P={P}); {info['m2l_tile_ops']} tile products issued"}
+                "work": f"{nv} translations (V lists and X-list virtual children, levels >= {info['split_level']}) "
+                        f"x {nb} densities x {per} flops ({form}, P={P}); {tile_ops} tile products issued"}
     if stage == "corr":
         nnz, m, n_ = info["nnz"], info["m"], info["n"]
         bytes_ = nnz * 8 + (m + 1) * 8 + m * 4 + m * 8 * nb + n_ * 8 * nb

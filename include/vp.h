@@ -171,8 +171,13 @@ typedef struct {
     int64_t workspace_bytes;   /* device memory held by the plan */
     int64_t m2l_translations;  /* M2L translations per density, V lists plus the
                                   virtual children of X-list sources */
-    int64_t m2l_tile_ops;      /* (16-column tile, offset) products the M2L launch issues */
+    int64_t m2l_tile_ops;      /* (16-column tile, offset) products the M2L launches issue */
     int64_t table_tile_ops;    /* (16-column tile, slot) products of the near tables */
+    int64_t m2l_coarse_translations;  /* of m2l_translations, those into boxes below split_level */
+    int64_t m2l_coarse_tile_ops;      /* of m2l_tile_ops, those of the launch below split_level */
+    int32_t split_level;       /* expansion passes of the levels below it run on a third stream
+                                  beside the M2L of the levels from it on (2: none below) */
+    int32_t reserved;
     double root[3];
 } vp_plan_info_t;
 
@@ -217,7 +222,9 @@ enum {
     VP_STAGE_L2L = 5, VP_STAGE_P2P = 6, VP_STAGE_FAR = 7, VP_STAGE_FINISH = 8,
     VP_STAGE_TABLES = 9, /* near-field tables of congruent leaves (P2P holds the pairwise kernel) */
     VP_STAGE_CORR = 10,  /* sparse correction apply C f (FINISH: adding the un-permuted FMM sums) */
-    VP_NSTAGES = 11
+    VP_STAGE_COARSE = 11,/* M2M, M2L and L2L of the levels below split_level (third stream);
+                            M2M, M2L and L2L hold the levels from split_level on */
+    VP_NSTAGES = 12
 };
 vp_status vp_set_timing(vp_plan_t plan, int32_t enable);
 vp_status vp_get_timing(vp_plan_t plan, double *ms, int64_t *nevals);

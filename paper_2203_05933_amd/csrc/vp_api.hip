@@ -4,12 +4,59 @@
 
 #include <cmath>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "vp_internal.hpp"
 
 namespace vp {
+
+// The two auxiliary streams are shared by every plan on a device (created
+// with the first plan, destroyed with the last): each stream takes a
+// hardware queue, and a process has few (GPU_MAX_HW_QUEUES, 4 by default);
+// streams beyond that share queues and serialise kernels that were meant to
+// overlap.  Sharing only adds ordering: every cross-stream wait of an
+// evaluation is on an event recorded before the wait, so concurrent plans
+// cannot deadlock.
+struct SharedStreams {
+    hipStream_t aux = nullptr, aux2 = nullptr;
+    int refs = 0;
+};
+static std::mutex g_streams_mu;
+static std::map<int, SharedStreams> g_streams;
+
+static void acquire_streams(vp_plan_s *P) {
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    SharedStreams &S = g_streams[P->device];
+    if (S.refs == 0) {
+        VP_HIP(hipStreamCreateWithFlags(&S.aux, hipStreamNonBlocking));
+        hipError_t e = hipStreamCreateWithFlags(&S.aux2, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(S.aux);
+            S.aux = nullptr;
+            VP_HIP(e);
+        }
+    }
+    ++S.refs;
+    P->aux = S.aux;
+    P->aux2 = S.aux2;
+}
+
+static void release_streams(vp_plan_s *P) {
+    if (!P->aux) return;
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    SharedStreams &S = g_streams[P->device];
+    (void)hipStreamSynchronize(P->aux);
+    (void)hipStreamSynchronize(P->aux2);
+    P->aux = P->aux2 = nullptr;
+    if (--S.refs == 0) {
+        (void)hipStreamDestroy(S.aux);
+        (void)hipStreamDestroy(S.aux2);
+        S.aux = S.aux2 = nullptr;
+    }
+}
 
 [[noreturn]] void throw_hip(hipError_t e, const char *expr, const char *file, int line) {
     char buf[512];
@@ -156,12 +203,9 @@ static void free_plan(vp_plan_s *P) {
     if (!P) return;
     if (P->stream) (void)hipStreamSynchronize(P->stream);
     else (void)hipDeviceSynchronize();
-    if (P->aux) {
-        (void)hipStreamSynchronize(P->aux);
-        (void)hipStreamDestroy(P->aux);
-    }
-    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
-    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+    vp::release_streams(P);
+    for (hipEvent_t e : {P->ev_fork, P->ev_join, P->ev_p2l, P->ev_upper, P->ev_coarse})
+        if (e) (void)hipEventDestroy(e);
     release_timing(P);
     P->mem.free_all();
     delete P;
@@ -192,9 +236,9 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->m2l_mode = o.m2l_mode == VP_M2L_AUTO ? (P->fp32 ? VP_M2L_FP32_SCALED : VP_M2L_FP64_SCALED) : o.m2l_mode;
         P->stream = static_cast<hipStream_t>(o.stream);
         VP_HIP(hipGetDevice(&P->device));
-        VP_HIP(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
-        VP_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
-        VP_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+        vp::acquire_streams(P);
+        for (hipEvent_t *e : {&P->ev_fork, &P->ev_join, &P->ev_p2l, &P->ev_upper, &P->ev_coarse})
+            VP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
         P->err_flag = P->mem.alloc<int32_t>(1);
         P->w_user = P->mem.alloc<double>(n);
         VP_HIP(hipMemcpyAsync(P->w_user, w, sizeof(double) * n, hipMemcpyHostToDevice, P->stream));
@@ -365,6 +409,9 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->workspace_bytes = (int64_t)P->mem.bytes;
     info->m2l_translations = P->m2l_translations;
     info->m2l_tile_ops = P->m2l_tile_ops;
+    info->m2l_coarse_translations = P->m2l[1].translations;
+    info->m2l_coarse_tile_ops = P->m2l[1].tile_ops;
+    info->split_level = P->split_level;
     info->table_tile_ops = P->near.table_tile_ops;
     for (int k = 0; k < 3; ++k) info->root[k] = P->opt.root[k];
     return VP_OK;

@@ -186,6 +186,7 @@ __global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_
 // the quadrant's sources, about the quadrant centre, at the children's scale.
 template <class E>
 __global__ void __launch_bounds__(64) k_p2m_quad(PointRoles R, BoxGeo G, const int32_t *__restrict__ vleaf,
+                                                 const int32_t *__restrict__ vsel,
                                                  const int32_t *__restrict__ vsplit, int nbox,
                                                  const double *__restrict__ q, int nbatch, int P, int PD,
                                                  const E *__restrict__ invk, E *__restrict__ Mexp) {
@@ -193,13 +194,14 @@ __global__ void __launch_bounds__(64) k_p2m_quad(PointRoles R, BoxGeo G, const i
     E *Wre = reinterpret_cast<E *>(smem);
     E *Wim = Wre + 16 * P;
     __shared__ E sq[16][16];
-    const int v = blockIdx.x >> 2, qd = blockIdx.x & 3;
+    // vsel: the selected source leaves (indices v), null = all
+    const int v = vsel ? vsel[blockIdx.x >> 2] : (int)(blockIdx.x >> 2), qd = blockIdx.x & 3;
     const int a = vleaf[v];
     const double h = G.side[G.level[a]];
     const double cx = G.cx[a] + ((qd & 1) ? 0.25 : -0.25) * h;
     const double cy = G.cy[a] + ((qd >> 1) ? 0.25 : -0.25) * h;
     p2m_range<E>(R, vsplit[5 * v + qd], vsplit[5 * v + qd + 1], cx, cy, 2.0 / h, q, nbatch, P, PD, invk,
-                 Mexp + (int64_t)(nbox + blockIdx.x) * nbatch * PD, Wre, Wim, sq);
+                 Mexp + (int64_t)(nbox + 4 * v + qd) * nbatch * PD, Wre, Wim, sq);
 }
 
 // ----------------------------------------------------------------------------
@@ -331,8 +333,9 @@ __global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, i
 }
 
 // ----------------------------------------------------------------------------
-// P2L (X lists): sources of a coarser leaf straight into the local expansion
-// of box b: B_0 += sum q log|c - z|, B_l += -(1/l) sum q (s/(z - c))^l.
+// P2L (X lists): sources of coarser leaves straight into the local expansion
+// of box b: B_0 = sum q log|c - z|, B_l = -(1/l) sum q (s/(z - c))^l over all
+// of b's entries.  It writes the column; M2L then adds its translations.
 // ----------------------------------------------------------------------------
 template <class E>
 __global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_t *__restrict__ boxes,
@@ -394,7 +397,7 @@ __global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_
                 const E sc = k == 0 ? (E)1 : -invk[k];
 #pragma unroll
                 for (int bb = 0; bb < 16; ++bb)
-                    if (bb < nb) Lo[(bt0 + bb) * PD + r] += sc * acc[ri][bb];
+                    if (bb < nb) Lo[(bt0 + bb) * PD + r] = sc * acc[ri][bb];
             }
         }
     }
@@ -957,14 +960,25 @@ void build_schedules(vp_plan_s *P) {
         return d;
     };
     auto cls = [&](int b) { return (ix[b] & 1) | ((iy[b] & 1) << 1); };
-    // M2L columns: boxes of levels >= 2 grouped by child class (boxes of one
-    // class share their 27 V-list offsets in a uniform region)
-    std::vector<int32_t> m2l;
-    for (int c = 0; c < 4; ++c)
+    // split level: the expansion passes below it (few boxes per level, each
+    // launch latency bound) run on a third stream beside the M2L of the
+    // levels from it on, which hold at least 85% of the M2L columns
+    {
+        std::vector<int64_t> per_level(T.nlevels + 1, 0);
+        int64_t total = 0;
         for (int b = 0; b < nbox; ++b)
-            if (lev[b] >= 2 && cls(b) == c) m2l.push_back(b);
-    P->n_m2l_boxes = (int)m2l.size();
-    P->m2l_cols = up(m2l);
+            if (lev[b] >= 2) ++per_level[lev[b]], ++total;
+        int L0 = 2;
+        int64_t above = 0;
+        for (int l = T.nlevels - 1; l >= 2; --l) {
+            above += per_level[l];
+            if (above >= (total * 85 + 99) / 100) {
+                L0 = l;
+                break;
+            }
+        }
+        P->split_level = std::max(2, std::min(L0, T.nlevels - 1));
+    }
     // per level: boxes grouped by class (L2L), non-leaf boxes (M2M)
     std::vector<int32_t> lb, parents;
     P->lvl_box_begin.assign(T.nlevels + 1, 0);
@@ -1067,10 +1081,18 @@ void build_schedules(vp_plan_s *P) {
     P->vsplit_s = up(vsplit_s);
     P->vsplit_t = up(vsplit_t);
     VP_HIP(hipMemcpyAsync(T.v_slot, vslot.data(), 4 * vslot.size(), hipMemcpyHostToDevice, s));
-    // within each child class, order the M2L columns by their set of offsets
-    // (stable, so equal sets keep their tree order): tiles of 16 columns then
-    // share their offsets wherever the tree is not uniform
-    {
+    // M2L launches (levels from the split level on; levels 2 .. split - 1):
+    // columns grouped by child class (boxes of one class share their 27
+    // V-list offsets in a uniform region), within a class ordered by their
+    // set of offsets (stable, so equal sets keep their tree order), so that
+    // 16-column tiles share their offsets wherever the tree is not uniform
+    P->m2l_translations = P->m2l_tile_ops = 0;
+    for (int part = 0; part < 2; ++part) {
+        M2LSched &S = P->m2l[part];
+        std::vector<int32_t> m2l;
+        for (int c = 0; c < 4; ++c)
+            for (int b = 0; b < nbox; ++b)
+                if (lev[b] >= 2 && cls(b) == c && (lev[b] >= P->split_level) == (part == 0)) m2l.push_back(b);
         std::vector<uint64_t> omask(nbox, 0);
         for (int b : m2l)
             for (int o = 0; o < NOFF; ++o)
@@ -1079,21 +1101,13 @@ void build_schedules(vp_plan_s *P) {
             const int cx = cls(x), cy = cls(y);
             return cx != cy ? cx < cy : omask[x] < omask[y];
         });
-        if (!m2l.empty())
-            VP_HIP(hipMemcpyAsync(P->m2l_cols, m2l.data(), 4 * m2l.size(), hipMemcpyHostToDevice, s));
-    }
-    // offsets present in each 16-column M2L tile (columns = box x density)
-    {
+        // offsets present in each 16-column tile (columns = box x density)
         const int64_t ncols = (int64_t)m2l.size() * P->nbatch;
         const int64_t ntiles = (ncols + 15) / 16;
         std::vector<int32_t> tptr(1, 0), tops, tsrc;
         for (int64_t t = 0; t < ntiles; ++t) {
             uint64_t mask = 0;
-            for (int64_t c = 16 * t; c < std::min(ncols, 16 * t + 16); ++c) {
-                const int b = m2l[c / P->nbatch];
-                for (int o = 0; o < NOFF; ++o)
-                    if (vslot[(size_t)b * NOFF + o] >= 0) mask |= 1ull << o;
-            }
+            for (int64_t c = 16 * t; c < std::min(ncols, 16 * t + 16); ++c) mask |= omask[m2l[c / P->nbatch]];
             for (int o = 0; o < NOFF; ++o)
                 if (mask >> o & 1) {
                     tops.push_back(o);
@@ -1104,20 +1118,30 @@ void build_schedules(vp_plan_s *P) {
             tptr.push_back((int32_t)tops.size());
         }
         const std::vector<int32_t> order = tile_order_by_work(tptr);
-        P->m2l_tile_ops = (int64_t)tops.size();
-        P->m2l_translations = 0;
-        for (int b : m2l)
-            for (int o = 0; o < NOFF; ++o) P->m2l_translations += vslot[(size_t)b * NOFF + o] >= 0;
-        P->m2l_tptr = up(tptr);
-        P->m2l_tops = up(tops);
-        P->m2l_tsrc = up(tsrc);
-        P->m2l_torder = up(order);
+        S.nboxes = (int)m2l.size();
+        S.tile_ops = (int64_t)tops.size();
+        S.translations = 0;
+        for (int b : m2l) S.translations += __builtin_popcountll(omask[b]);
+        S.cols = up(m2l);
+        S.tptr = up(tptr);
+        S.tops = up(tops);
+        S.tsrc = up(tsrc);
+        S.torder = up(order);
+        P->m2l_translations += S.translations;
+        P->m2l_tile_ops += S.tile_ops;
         VP_HIP(hipStreamSynchronize(s));  // the host vectors leave scope
     }
     P->xr_ptr = up(xr_ptr);
     P->xr_idx = up(xr_idx);
     P->n_x_boxes = (int)xb.size();
     P->x_boxes = up(xb);
+    // P2L writes these boxes' local expansions first; M2L then adds to them
+    std::vector<int32_t> xinit(nbox, 0);
+    for (int b : xb) {
+        if (lev[b] < 2) throw Error(VP_EINTERNAL, "P2L target above level 2");
+        xinit[b] = 1;
+    }
+    P->x_init = up(xinit);
     P->n_w_leaves = (int)wl.size();
     P->w_leaves = up(wl);
     VP_HIP(hipStreamSynchronize(s));
@@ -1247,155 +1271,177 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
 }
 
 template <class E>
-static void run_pattern_op(vp_plan_s *P, const PointRoles &R, bool p2m);
+static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind);
 
-// M2L of all V lists (and X-list virtual children) in one launch, by the
-// plan's M2L mode
+// M2L of the V lists (and X-list virtual children) of one level range
+// (part 0: levels from the split level on, part 1: the levels below) in one
+// launch, by the plan's M2L mode
 template <class E>
-static void launch_m2l(vp_plan_s *P) {
+static void launch_m2l(vp_plan_s *P, int part) {
     Tree &T = P->tree;
+    const M2LSched &S = P->m2l[part];
+    if (S.nboxes == 0) return;
     hipStream_t s = P->stream;
     const int nb = P->nbatch, Pn = P->P, PD = P->PD;
     E *M = static_cast<E *>(P->Mexp);
     E *L = static_cast<E *>(P->Lexp);
     const bool f32 = sizeof(E) == 4;
     const Operators &O = P->ops;
-    {
-        TranslateArgs a = expansion_args(P, P->m2l_cols, P->n_m2l_boxes, T.v_slot, NOFF, 2 * Pn);
-        a.tile_ptr = P->m2l_tptr;
-        a.tile_ops = P->m2l_tops;
-        a.tile_order = P->m2l_torder;
-        if (P->m2l_mode == VP_M2L_FP64_SCALED || P->m2l_mode == VP_M2L_FP32_SCALED) {
-            M2LScaledArgs sa;
-            sa.cols_box = P->m2l_cols;
-            sa.ncols = a.ncols;
-            sa.nbatch = nb;
-            sa.tile_ptr = P->m2l_tptr;
-            sa.tile_ops = P->m2l_tops;
-            sa.tile_src = P->m2l_tsrc;
-            sa.tile_order = P->m2l_torder;
-            sa.P = Pn;
-            sa.box_stride = (int64_t)nb * PD;
-            sa.bt_stride = PD;
-            sa.PD = PD;
-            sa.zero_col = P->zero_col;
-            sa.level = T.level;
-            sa.logside = T.d_logside;
-            if (!f32)
-                m2l_scaled<double, double, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
-                                                   (const double *)M, (double *)L);
-            else if (P->m2l_mode == VP_M2L_FP32_SCALED)
-                m2l_scaled<float, float, float>(s, O.PQ, sa, O.m2l_q32, O.m2l_tin32, O.m2l_tout32, O.m2l_logt,
-                                                (const float *)M, (float *)L);
-            else
-                m2l_scaled<float, float, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
-                                                 (const float *)M, (float *)L);
-        } else if (!f32) {
-            translate_m2l<double, double, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const double *)M,
-                                                         (double *)L);
-        } else if (P->m2l_mode == VP_M2L_FP32_SPLIT) {
-            translate_m2l<float, float, float, true>(s, PD, a, P->ops.m2l_f32, P->ops.m2l_f32_lo,
-                                                     (const float *)M, (float *)L);
-        } else if (P->m2l_mode == VP_M2L_FP64_MFMA) {
-            translate_m2l<float, float, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const float *)M,
-                                                       (float *)L);
-        } else {
-            translate_m2l<float, float, float, false>(s, PD, a, P->ops.m2l_f32, nullptr, (const float *)M,
-                                                      (float *)L);
-        }
+    TranslateArgs a = expansion_args(P, S.cols, S.nboxes, T.v_slot, NOFF, 2 * Pn);
+    a.tile_ptr = S.tptr;
+    a.tile_ops = S.tops;
+    a.tile_order = S.torder;
+    a.xinit = P->x_init;
+    if (P->m2l_mode == VP_M2L_FP64_SCALED || P->m2l_mode == VP_M2L_FP32_SCALED) {
+        M2LScaledArgs sa;
+        sa.cols_box = S.cols;
+        sa.ncols = a.ncols;
+        sa.nbatch = nb;
+        sa.tile_ptr = S.tptr;
+        sa.tile_ops = S.tops;
+        sa.tile_src = S.tsrc;
+        sa.tile_order = S.torder;
+        sa.P = Pn;
+        sa.box_stride = (int64_t)nb * PD;
+        sa.bt_stride = PD;
+        sa.PD = PD;
+        sa.zero_col = P->zero_col;
+        sa.xinit = P->x_init;
+        sa.level = T.level;
+        sa.logside = T.d_logside;
+        if (!f32)
+            m2l_scaled<double, double, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
+                                               (const double *)M, (double *)L);
+        else if (P->m2l_mode == VP_M2L_FP32_SCALED)
+            m2l_scaled<float, float, float>(s, O.PQ, sa, O.m2l_q32, O.m2l_tin32, O.m2l_tout32, O.m2l_logt,
+                                            (const float *)M, (float *)L);
+        else
+            m2l_scaled<float, float, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
+                                             (const float *)M, (float *)L);
+    } else if (!f32) {
+        translate_m2l<double, double, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const double *)M,
+                                                     (double *)L);
+    } else if (P->m2l_mode == VP_M2L_FP32_SPLIT) {
+        translate_m2l<float, float, float, true>(s, PD, a, P->ops.m2l_f32, P->ops.m2l_f32_lo, (const float *)M,
+                                                 (float *)L);
+    } else if (P->m2l_mode == VP_M2L_FP64_MFMA) {
+        translate_m2l<float, float, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const float *)M,
+                                                   (float *)L);
+    } else {
+        translate_m2l<float, float, float, false>(s, PD, a, P->ops.m2l_f32, nullptr, (const float *)M,
+                                                  (float *)L);
     }
 }
 
+// Leaf multipoles: congruent leaves by one matrix, the others and the
+// virtual children of X-list sources on the VALU
 template <class E>
-// upward (P2M, M2M) or downward (M2L, P2L, L2L) half of the expansion passes
-static void run_expansions(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool tables, bool upward) {
+static void run_p2m(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool tables) {
     Tree &T = P->tree;
     hipStream_t s = P->stream;
     const int nb = P->nbatch, Pn = P->P, PD = P->PD;
     E *M = static_cast<E *>(P->Mexp);
-    E *L = static_cast<E *>(P->Lexp);
     const bool f32 = sizeof(E) == 4;
     const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
     const size_t lds = sizeof(E) * 2 * 16 * Pn;
-    if (T.nlevels < 3) return;  // no box is well separated from another
-    const Operators &O = P->ops;
-    const E *shq[2], *shi[2], *sho[2];
-    for (int w = 0; w < 2; ++w) {
-        shq[w] = f32 ? (const E *)O.sh_qt32[w] : (const E *)O.sh_qt64[w];
-        shi[w] = f32 ? (const E *)O.sh_tin32[w] : (const E *)O.sh_tin64[w];
-        sho[w] = f32 ? (const E *)O.sh_tout32[w] : (const E *)O.sh_tout64[w];
-    }
-    if (upward) {
-    P->stage_begin(VP_STAGE_P2M);
     if (tables) {
-        run_pattern_op<E>(P, R, true);
+        run_pattern_op<E>(P, R, 0);
         if (P->near.n_p2m_rest > 0) {
             hipLaunchKernelGGL(k_p2m<E>, dim3(P->near.n_p2m_rest), dim3(64), lds, s, R, G, P->near.p2m_rest,
                                P->near.n_p2m_rest, P->q, nb, Pn, PD, invk, M);
             VP_LAUNCH_CHECK();
         }
     } else if (P->n_p2m > 0) {
-        hipLaunchKernelGGL(k_p2m<E>, dim3(P->n_p2m), dim3(64), lds, s, R, G, P->p2m_leaves, P->n_p2m,
-                           P->q, nb, Pn, PD, invk, M);
+        hipLaunchKernelGGL(k_p2m<E>, dim3(P->n_p2m), dim3(64), lds, s, R, G, P->p2m_leaves, P->n_p2m, P->q, nb,
+                           Pn, PD, invk, M);
         VP_LAUNCH_CHECK();
     }
-    if (P->n_vleaf > 0) {
-        // virtual children of X-list sources (their points in this evaluation's source role)
-        const int32_t *split = R.sb == T.sb ? P->vsplit_s : P->vsplit_t;
-        hipLaunchKernelGGL(k_p2m_quad<E>, dim3(4 * P->n_vleaf), dim3(64), lds, s, R, G, P->vleaf, split, T.nbox,
-                           P->q, nb, Pn, PD, invk, M);
-        VP_LAUNCH_CHECK();
-    }
-    P->stage_end(VP_STAGE_P2M);
-    P->stage_begin(VP_STAGE_M2M);
-    for (int l = T.nlevels - 2; l >= 2; --l) {
-        int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
-        if (c1 > c0) {
-            switch (O.PR) {
-#define VP_M2M(PR)                                                                                               \
-    case PR:                                                                                                     \
-        hipLaunchKernelGGL((k_m2m<E, PR>), dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0, nb, Pn, PD, G,   \
-                           shq[0], shi[0], sho[0], M);                                                           \
-        break;
-                VP_M2M(16) VP_M2M(32) VP_M2M(64)
-#undef VP_M2M
-                default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
-            }
+    // virtual children of X-list sources (their points in this evaluation's
+    // source role): pattern leaves by the quadrant matrices, the rest on the VALU
+    const int32_t *split = R.sb == T.sb ? P->vsplit_s : P->vsplit_t;
+    if (tables) {
+        if (P->near.n_quad_cols > 0) run_pattern_op<E>(P, R, 2);
+        if (P->near.n_vrest > 0) {
+            hipLaunchKernelGGL(k_p2m_quad<E>, dim3(4 * P->near.n_vrest), dim3(64), lds, s, R, G, P->vleaf,
+                               P->near.vrest, split, T.nbox, P->q, nb, Pn, PD, invk, M);
             VP_LAUNCH_CHECK();
         }
-    }
-    P->stage_end(VP_STAGE_M2M);
-    return;
-    }
-    P->stage_begin(VP_STAGE_M2L);
-    launch_m2l<E>(P);
-    P->stage_end(VP_STAGE_M2L);
-    P->stage_begin(VP_STAGE_P2L);
-    if (P->n_x_boxes > 0) {
-        hipLaunchKernelGGL(k_p2l<E>, dim3(P->n_x_boxes), dim3(64), lds, s, R, G, P->x_boxes, P->xr_ptr,
-                           P->xr_idx, P->q, nb, Pn, PD, invk, L);
+    } else if (P->n_vleaf > 0) {
+        hipLaunchKernelGGL(k_p2m_quad<E>, dim3(4 * P->n_vleaf), dim3(64), lds, s, R, G, P->vleaf,
+                           (const int32_t *)nullptr, split, T.nbox, P->q, nb, Pn, PD, invk, M);
         VP_LAUNCH_CHECK();
     }
-    P->stage_end(VP_STAGE_P2L);
-    P->stage_begin(VP_STAGE_L2L);
-    for (int l = 3; l < T.nlevels; ++l) {
-        int c0 = P->lvl_box_begin[l], c1 = P->lvl_box_begin[l + 1];
-        if (c1 > c0) {
-            const unsigned nblk = (unsigned)((c1 - c0 + 64 / O.PR - 1) / (64 / O.PR));
-            switch (O.PR) {
+}
+
+// M2M for the parents on levels l_hi down to l_lo (one launch per level)
+template <class E>
+static void run_m2m(vp_plan_s *P, const BoxGeo &G, int l_hi, int l_lo) {
+    hipStream_t s = P->stream;
+    const int nb = P->nbatch, Pn = P->P, PD = P->PD;
+    E *M = static_cast<E *>(P->Mexp);
+    const bool f32 = sizeof(E) == 4;
+    const Operators &O = P->ops;
+    const E *shq = f32 ? (const E *)O.sh_qt32[0] : (const E *)O.sh_qt64[0];
+    const E *shi = f32 ? (const E *)O.sh_tin32[0] : (const E *)O.sh_tin64[0];
+    const E *sho = f32 ? (const E *)O.sh_tout32[0] : (const E *)O.sh_tout64[0];
+    for (int l = l_hi; l >= l_lo; --l) {
+        const int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
+        if (c1 <= c0) continue;
+        switch (O.PR) {
+#define VP_M2M(PR)                                                                                                 \
+    case PR:                                                                                                       \
+        hipLaunchKernelGGL((k_m2m<E, PR>), dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0, nb, Pn, PD, G, shq, \
+                           shi, sho, M);                                                                           \
+        break;
+            VP_M2M(16) VP_M2M(32) VP_M2M(64)
+#undef VP_M2M
+            default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
+        }
+        VP_LAUNCH_CHECK();
+    }
+}
+
+// L2L into the boxes of levels l_lo .. l_hi (one launch per level)
+template <class E>
+static void run_l2l(vp_plan_s *P, const BoxGeo &G, int l_lo, int l_hi) {
+    hipStream_t s = P->stream;
+    const int nb = P->nbatch, Pn = P->P, PD = P->PD;
+    E *L = static_cast<E *>(P->Lexp);
+    const bool f32 = sizeof(E) == 4;
+    const Operators &O = P->ops;
+    const E *shq = f32 ? (const E *)O.sh_qt32[1] : (const E *)O.sh_qt64[1];
+    const E *shi = f32 ? (const E *)O.sh_tin32[1] : (const E *)O.sh_tin64[1];
+    const E *sho = f32 ? (const E *)O.sh_tout32[1] : (const E *)O.sh_tout64[1];
+    for (int l = std::max(l_lo, 3); l <= l_hi; ++l) {
+        const int c0 = P->lvl_box_begin[l], c1 = P->lvl_box_begin[l + 1];
+        if (c1 <= c0) continue;
+        const unsigned nblk = (unsigned)((c1 - c0 + 64 / O.PR - 1) / (64 / O.PR));
+        switch (O.PR) {
 #define VP_L2L(PR)                                                                                               \
     case PR:                                                                                                     \
         hipLaunchKernelGGL((k_l2l<E, PR>), dim3(nblk), dim3(64), 0, s, P->lvl_boxes + c0, c1 - c0, nb, Pn, PD, G, \
-                           shq[1], shi[1], sho[1], L);                                                           \
+                           shq, shi, sho, L);                                                                    \
         break;
-                VP_L2L(16) VP_L2L(32) VP_L2L(64)
+            VP_L2L(16) VP_L2L(32) VP_L2L(64)
 #undef VP_L2L
-                default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
-            }
-            VP_LAUNCH_CHECK();
+            default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
         }
+        VP_LAUNCH_CHECK();
     }
-    P->stage_end(VP_STAGE_L2L);
+}
+
+// P2L of the X-list entries two or more levels apart (writes those boxes'
+// local expansions before M2L adds to them)
+template <class E>
+static void run_p2l(vp_plan_s *P, const PointRoles &R, const BoxGeo &G) {
+    if (P->n_x_boxes <= 0) return;
+    const int Pn = P->P;
+    const bool f32 = sizeof(E) == 4;
+    const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
+    const size_t lds = sizeof(E) * 2 * 16 * Pn;
+    hipLaunchKernelGGL(k_p2l<E>, dim3(P->n_x_boxes), dim3(64), lds, P->stream, R, G, P->x_boxes, P->xr_ptr,
+                       P->xr_idx, P->q, P->nbatch, Pn, P->PD, invk, static_cast<E *>(P->Lexp));
+    VP_LAUNCH_CHECK();
 }
 
 template <int NB, bool GRAD, bool ACCUM>
@@ -1481,9 +1527,11 @@ static void run_tables(vp_plan_s *P, const PointRoles &R) {
     }
 }
 
-// One-operator launches on pattern leaves: P2M (q -> M) and L2P (L -> acc)
+// Fixed-matrix launches on pattern leaves: P2M (q -> M), L2P (L -> acc), and
+// the quadrant P2M of pattern X-list sources (q -> virtual-child columns)
+enum { PAT_P2M = 0, PAT_L2P = 1, PAT_QUAD = 2 };
 template <class E, int RBP, int RBE>
-static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, bool p2m) {
+static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind) {
     NearTables &N = P->near;
     const bool f32 = sizeof(E) == 4;
     TranslateArgs a;
@@ -1493,7 +1541,7 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, bool p2m) {
     a.logrow = -1;
     a.level = P->tree.level;
     a.logside = P->tree.d_logside;
-    if (p2m) {
+    if (kind == PAT_P2M) {
         // rows = expansion (RBE blocks), cols = pattern points (RBP*16)
         constexpr int RB = RBE, S = RBP * 4;
         constexpr bool LDSA = translate_ldsa<E, RB, S, false>();
@@ -1505,6 +1553,25 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, bool p2m) {
         a.nrows_out = P->PD;
         if (a.ncols <= 0) return;
         const E *op = f32 ? (const E *)N.p2m_op_f32 : (const E *)N.p2m_op;
+        hipLaunchKernelGGL((k_translate<double, E, E, RB, S, false, false, LDSA>),
+                           dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
+                           P->q, static_cast<E *>(P->Mexp));
+    } else if (kind == PAT_QUAD) {
+        // four operators (one per quadrant, RBP*4 points each); the columns are
+        // grouped by quadrant, so a 64-column block uses one operator (two at
+        // a group boundary) and skips the others
+        constexpr int RB = RBE, S = RBP;
+        constexpr bool LDSA = translate_ldsa<E, RB, S, false>();
+        constexpr size_t lds = LDSA ? translate_lds_bytes<E, RB, S, false>() : 0;
+        a.cols_box = N.quad_cols;
+        a.ncols = N.n_quad_cols * P->nbatch;
+        a.slots = N.quad_slot;
+        a.nops = 4;
+        a.in = ColAddr{R.nsrc, 0, R.sb == P->tree.sb ? P->vsplit_s : P->vsplit_t};
+        a.out = ColAddr{P->PD, (int64_t)P->nbatch * P->PD, nullptr};
+        a.nrows_out = P->PD;
+        if (a.ncols <= 0) return;
+        const E *op = f32 ? (const E *)N.quad_op_f32 : (const E *)N.quad_op;
         hipLaunchKernelGGL((k_translate<double, E, E, RB, S, false, false, LDSA>),
                            dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
                            P->q, static_cast<E *>(P->Mexp));
@@ -1531,11 +1598,11 @@ bool pattern_op_supported(int npat, int PD) {
 }
 
 template <class E>
-static void run_pattern_op(vp_plan_s *P, const PointRoles &R, bool p2m) {
+static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind) {
     const int key = P->near.npat / 16 * 16 + P->PD / 16;
     switch (key) {
 #define VP_PAT(NP, NE) \
-    case NP * 16 + NE: launch_pattern_ops<E, NP, NE>(P, R, p2m); break;
+    case NP * 16 + NE: launch_pattern_ops<E, NP, NE>(P, R, kind); break;
         VP_PAT(1, 1) VP_PAT(1, 2) VP_PAT(1, 3) VP_PAT(1, 4)
         VP_PAT(2, 1) VP_PAT(2, 2) VP_PAT(2, 3) VP_PAT(2, 4)
         VP_PAT(4, 1) VP_PAT(4, 2) VP_PAT(4, 3) VP_PAT(4, 4)
@@ -1550,7 +1617,7 @@ static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *
     NearTables &N = P->near;
     P->stage_begin(VP_STAGE_FAR);
     if (tables) {
-        run_pattern_op<E>(P, R, false);
+        run_pattern_op<E>(P, R, 1);
         if (N.n_far_leaves > 0) {
             hipLaunchKernelGGL((k_far<E, GRAD>), dim3(N.n_far_leaves), dim3(256), 0, P->stream, R, G, N.far_leaves,
                                T.lptr[2], T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp,
@@ -1569,60 +1636,124 @@ static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *
 static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjoint);
 static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint);
 
-void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) {
-    PointRoles R = roles(P, adjoint);
-    BoxGeo G = geo(P);
+// One evaluation on three streams (default priority; with VP_FLAG_ONE_STREAM
+// everything runs on the plan's stream in the order written here):
+//   third stream: P2L | wait(upper) M2M, M2L, L2L of the levels below the split
+//   second stream: correction C f, near tables, pairwise near field
+//   plan's stream: P2M, M2M from the finest level to the split level |
+//                  wait(P2L) M2L of the levels from the split on | wait(coarse)
+//                  L2L from the split level down | wait(near) far field, finish
+template <class E>
+static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool adjoint, bool grad, const double *f,
+                       double *u) {
     Tree &T = P->tree;
     NearTables &N = P->near;
     const bool tables = N.active && !grad;
-    // correction and near field on the auxiliary stream (the HBM-bound
-    // correction first), concurrent with the expansion passes
-    hipStream_t main_stream = P->stream;
-    if (!P->one_stream) {
-        VP_HIP(hipEventRecord(P->ev_fork, main_stream));
-        VP_HIP(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
-    }
+    const bool one = P->one_stream;
+    const bool fmm = T.nlevels >= 3;  // otherwise no box is well separated from another
+    const int L0 = P->split_level, Lmax = T.nlevels - 1;
+    const bool coarse = fmm && L0 > 2;
+    hipStream_t ms = P->stream;
+    hipStream_t s2 = one ? ms : P->aux, s3 = one ? ms : P->aux2;
     struct Restore {
         vp_plan_s *P;
         hipStream_t s;
         ~Restore() { P->stream = s; }
-    } restore{P, main_stream};
-    if (!P->one_stream) P->stream = P->aux;
-    if (u) correction_apply(P, f, u, adjoint);
-    if (tables) {
-        P->stage_begin(VP_STAGE_TABLES);
-        fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
-        run_tables(P, R);
-        P->stage_end(VP_STAGE_TABLES);
+    } restore{P, ms};
+    if (!one) {
+        VP_HIP(hipEventRecord(P->ev_fork, ms));
+        VP_HIP(hipStreamWaitEvent(s2, P->ev_fork, 0));
+        VP_HIP(hipStreamWaitEvent(s3, P->ev_fork, 0));
     }
-    P->stage_begin(VP_STAGE_P2P);
-    if (grad) {
-        run_p2p<true, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0], nullptr, P->acc);
-    } else if (tables) {
-        run_p2p<false, true>(P, R, N.rest_leaves, N.n_rest_leaves, N.pair_uptr, N.pair_uidx, &N.g_rest, P->acc);
-    } else {
-        run_p2p<false, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0],
-                              adjoint && !P->self ? &P->g_adj : &P->g_fwd,
-                              P->acc);
+    // third stream: P2L (needs only the charges)
+    P->stream = s3;
+    if (fmm) {
+        P->stage_begin(VP_STAGE_P2L);
+        run_p2l<E>(P, R, G);
+        P->stage_end(VP_STAGE_P2L);
     }
-    P->stage_end(VP_STAGE_P2P);
-    if (!P->one_stream) VP_HIP(hipEventRecord(P->ev_join, P->aux));
-    P->stream = main_stream;
-    if (P->fp32) run_expansions<float>(P, R, G, tables, true);
-    else run_expansions<double>(P, R, G, tables, true);
-    if (P->fp32) run_expansions<float>(P, R, G, tables, false);
-    else run_expansions<double>(P, R, G, tables, false);
-    if (!P->one_stream) VP_HIP(hipStreamWaitEvent(main_stream, P->ev_join, 0));
-    if (T.nlevels >= 3) {
-        if (grad) {
-            if (P->fp32) run_far<float, true>(P, R, G, P->acc, false);
-            else run_far<double, true>(P, R, G, P->acc, false);
-        } else {
-            if (P->fp32) run_far<float, false>(P, R, G, P->acc, tables);
-            else run_far<double, false>(P, R, G, P->acc, tables);
+    if (!one) VP_HIP(hipEventRecord(P->ev_p2l, s3));
+    // second stream: correction (HBM bound) and the near field
+    P->stream = s2;
+    auto corr = [&] {
+        if (u) correction_apply(P, f, u, adjoint);
+    };
+    auto tab = [&] {
+        if (tables) {
+            P->stage_begin(VP_STAGE_TABLES);
+            run_tables(P, R);
+            P->stage_end(VP_STAGE_TABLES);
         }
+    };
+    auto pair = [&] {
+        P->stage_begin(VP_STAGE_P2P);
+        if (grad) {
+            run_p2p<true, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0], nullptr, P->acc);
+        } else if (tables) {
+            run_p2p<false, true>(P, R, N.rest_leaves, N.n_rest_leaves, N.pair_uptr, N.pair_uidx, &N.g_rest,
+                                 P->acc);
+        } else {
+            run_p2p<false, false>(P, R, T.leaves, T.nleaf, T.lptr[0], T.lidx[0],
+                                  adjoint && !P->self ? &P->g_adj : &P->g_fwd, P->acc);
+        }
+        P->stage_end(VP_STAGE_P2P);
+    };
+    // with tables both near-field kernels add to zeroed potentials
+    if (tables) fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
+    corr();
+    tab();
+    pair();
+    if (!one) VP_HIP(hipEventRecord(P->ev_join, s2));
+    // plan's stream: leaf multipoles and the upward pass down to the split level
+    P->stream = ms;
+    if (fmm) {
+        P->stage_begin(VP_STAGE_P2M);
+        run_p2m<E>(P, R, G, tables);
+        P->stage_end(VP_STAGE_P2M);
+        P->stage_begin(VP_STAGE_M2M);
+        run_m2m<E>(P, G, Lmax - 1, L0);
+        P->stage_end(VP_STAGE_M2M);
+    }
+    if (coarse) {
+        // third stream: the levels below the split, upward, M2L and downward
+        if (!one) {
+            VP_HIP(hipEventRecord(P->ev_upper, ms));
+            VP_HIP(hipStreamWaitEvent(s3, P->ev_upper, 0));
+        }
+        P->stream = s3;
+        P->stage_begin(VP_STAGE_COARSE);
+        run_m2m<E>(P, G, L0 - 1, 2);
+        launch_m2l<E>(P, 1);
+        run_l2l<E>(P, G, 3, L0 - 1);
+        P->stage_end(VP_STAGE_COARSE);
+        if (!one) VP_HIP(hipEventRecord(P->ev_coarse, s3));
+        P->stream = ms;
+    }
+    if (fmm) {
+        if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_p2l, 0));
+        P->stage_begin(VP_STAGE_M2L);
+        launch_m2l<E>(P, 0);
+        P->stage_end(VP_STAGE_M2L);
+        if (coarse && !one) VP_HIP(hipStreamWaitEvent(ms, P->ev_coarse, 0));
+        P->stage_begin(VP_STAGE_L2L);
+        run_l2l<E>(P, G, L0, Lmax);
+        P->stage_end(VP_STAGE_L2L);
+    } else if (!one) {
+        VP_HIP(hipStreamWaitEvent(ms, P->ev_p2l, 0));  // join the third stream
+    }
+    if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_join, 0));
+    if (fmm) {
+        if (grad) run_far<E, true>(P, R, G, P->acc, false);
+        else run_far<E, false>(P, R, G, P->acc, tables);
     }
     if (u) add_fmm_sums(P, u, adjoint);
+}
+
+void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) {
+    PointRoles R = roles(P, adjoint);
+    BoxGeo G = geo(P);
+    if (P->fp32) run_passes<float>(P, R, G, adjoint, grad, f, u);
+    else run_passes<double>(P, R, G, adjoint, grad, f, u);
 }
 
 // The sparse correction (Section 4): out = C f (adjoint: C^T g), on the
@@ -1689,8 +1820,10 @@ void autotune_m2l(vp_plan_s *P) {
         P->m2l_mode = mode;
         for (int rep = 0; rep < 4; ++rep) {  // first launch warms up
             VP_HIP(hipEventRecord(e0, P->stream));
-            if (P->fp32) launch_m2l<float>(P);
-            else launch_m2l<double>(P);
+            for (int part = 0; part < 2; ++part) {
+                if (P->fp32) launch_m2l<float>(P, part);
+                else launch_m2l<double>(P, part);
+            }
             VP_HIP(hipEventRecord(e1, P->stream));
             VP_HIP(hipEventSynchronize(e1));
             float ms = 0.f;

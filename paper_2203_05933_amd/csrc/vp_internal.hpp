@@ -173,6 +173,19 @@ struct P2PGather {
     int64_t len = 0;
 };
 
+// One M2L launch over the boxes of a range of levels: (box, density)
+// columns in 16-column tiles, with the offsets present in each tile and each
+// column's source box per offset.
+struct M2LSched {
+    int32_t *cols = nullptr;    // boxes, grouped by child class, then by their set of offsets
+    int nboxes = 0;
+    int32_t *tptr = nullptr;    // offsets of tile t: tops[tptr[t] .. tptr[t+1])
+    int32_t *tops = nullptr;
+    int32_t *tsrc = nullptr;    // [tile offset][16] source box per column, or -1
+    int32_t *torder = nullptr;  // tiles by decreasing offset count
+    int64_t translations = 0, tile_ops = 0;
+};
+
 // Congruent-leaf path (uniform box grids): near-field tables, P2M/L2P
 // operators of the node pattern, and the leftover pairwise lists.
 struct NearTables {
@@ -204,6 +217,15 @@ struct NearTables {
     int32_t *local_done = nullptr;    // [nbox] 1: local expansion evaluated by the L2P operator
     double *p2m_op = nullptr, *l2p_op = nullptr;      // float64 forms
     float *p2m_op_f32 = nullptr, *l2p_op_f32 = nullptr;  // FP32-bulk forms
+    // virtual children of pattern X-list sources: the quadrant's P2M is one
+    // of four fixed matrices (npat/4 points each); columns grouped by quadrant
+    int32_t *quad_cols = nullptr;     // virtual-child expansion columns nbox + 4 v + quadrant
+    int n_quad_cols = 0;
+    int32_t *quad_slot = nullptr;     // [nbox + 4 n_vleaf][4]: 5 v + quadrant in the quadrant's slot, or -1
+    double *quad_op = nullptr;        // [4][PD x npat/4] A-fragment order
+    float *quad_op_f32 = nullptr;
+    int32_t *vrest = nullptr;         // the other X-list source leaves (indices v), VALU kernel
+    int n_vrest = 0;
 };
 
 }  // namespace vp
@@ -224,7 +246,11 @@ struct vp_plan_s {
     // the near field runs on its own stream, forked after the charges and
     // joined before the far-field evaluation (both default priority)
     hipStream_t aux = nullptr;
+    // third stream: P2L, then the expansion passes of the levels below
+    // split_level (few boxes, latency bound) beside the M2L of the levels above
+    hipStream_t aux2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_p2l = nullptr, ev_upper = nullptr, ev_coarse = nullptr;
     int device = 0;
     std::string err;
     bool poisoned = false;
@@ -261,15 +287,13 @@ struct vp_plan_s {
     void *Lexp = nullptr;
     void *zero_col = nullptr;  // max(PD, 128) zero doubles (an absent source column, either element type)
     vp::P2PGather g_fwd, g_adj;   // full U-list sources (nodes / targets as sources) without tables
-    int32_t *m2l_cols = nullptr;  // boxes of levels >= 2, grouped by child class
-    int32_t *m2l_tptr = nullptr;  // offsets present per 16-column tile of (box, density) columns
-    int32_t *m2l_tops = nullptr;
-    int32_t *m2l_tsrc = nullptr;    // [tile op][16] source box per column, or -1
-    int32_t *m2l_torder = nullptr;  // tiles by decreasing offset count
-    int64_t m2l_translations = 0, m2l_tile_ops = 0;
+    // M2L launches: [0] levels >= split_level, [1] levels 2 .. split_level-1
+    vp::M2LSched m2l[2];
+    int split_level = 2;
+    int64_t m2l_translations = 0, m2l_tile_ops = 0;  // both launches
+    int32_t *x_init = nullptr;  // [nbox] 1: P2L writes the local expansion before M2L adds to it
     int32_t *child_slot = nullptr;   // [nbox][4] child in each quadrant or -1
     int32_t *l2l_slot = nullptr;     // [nbox][4] parent in the slot of the box's class
-    int n_m2l_boxes = 0;
     int32_t *lvl_boxes = nullptr;  // boxes of each level, grouped by class inside a level (L2L)
     std::vector<int> lvl_box_begin;  // per level offsets into lvl_boxes
     int32_t *m2m_parents = nullptr;  // non-leaf boxes per level

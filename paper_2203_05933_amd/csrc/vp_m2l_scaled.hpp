@@ -43,6 +43,7 @@ struct M2LScaledArgs {
     const int32_t *level;
     const double *logside;    // log of the box side per level
     const void *zero_col;     // PD zeros of the input type (the column of an absent source)
+    const int32_t *xinit;     // [box] nonzero: the output column already holds P2L terms; add to it
 };
 
 // Column of one source for the k-steps of lane group g (k = g*S + s).  An
@@ -218,14 +219,15 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
         bi[0][M::item_of(0)] += a0i * ls;
     }
     TO *op = out + (int64_t)box * a.box_stride + (int64_t)bt * a.bt_stride;
+    const bool add = a.xinit[box] != 0;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int l = r * 16 + M::row(i, g);
             if (l < P) {
-                op[l] = (TO)br[r][i];
-                op[P + l] = (TO)bi[r][i];
+                op[l] = (TO)(add ? (double)op[l] + br[r][i] : br[r][i]);
+                op[P + l] = (TO)(add ? (double)op[P + l] + bi[r][i] : bi[r][i]);
             }
         }
     for (int row = 2 * P + g; row < a.PD; row += 4) op[row] = (TO)0;

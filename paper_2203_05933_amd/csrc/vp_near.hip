@@ -417,6 +417,79 @@ void build_near_tables(vp_plan_s *P) {
         }
         VP_HIP(hipStreamSynchronize(s));  // K, Af, Bf leave scope
     }
+
+    // Virtual children of X-list source leaves that are pattern leaves: the
+    // P2M of quadrant qd is a fixed PD x (npat/4) matrix (powers of the
+    // pattern points about the quadrant centre, at the children's scale).
+    // Needs the reference pattern's points to fall in quadrant order, npat/4
+    // per quadrant, none on a dividing line (the source order of every
+    // pattern leaf is the reference order, so its quadrant ranges agree).
+    {
+        const int nv = P->n_vleaf, nq = npat / 4;
+        bool quad_ok = N.active && nv > 0 && npat % 16 == 0;
+        for (int j = 0; quad_ok && j < npat; ++j) {
+            const int qd = (rx[j] > 0.0 ? 1 : 0) | (ry[j] > 0.0 ? 2 : 0);
+            quad_ok = qd == j / nq && std::fabs(rx[j]) > 1e-6 && std::fabs(ry[j]) > 1e-6;
+        }
+        std::vector<int32_t> hv(nv), hsplit((size_t)5 * nv), qcols[4], vrest;
+        if (nv > 0) {
+            VP_HIP(hipMemcpyAsync(hv.data(), P->vleaf, 4 * (size_t)nv, hipMemcpyDeviceToHost, s));
+            VP_HIP(hipMemcpyAsync(hsplit.data(), P->vsplit_s, 4 * hsplit.size(), hipMemcpyDeviceToHost, s));
+            VP_HIP(hipStreamSynchronize(s));
+        }
+        const size_t ncol_all = (size_t)nbox + 4 * (size_t)nv;
+        std::vector<int32_t> qslot;
+        if (quad_ok) qslot.assign(ncol_all * 4, -1);
+        for (int v = 0; v < nv; ++v) {
+            const int a = hv[v];
+            bool pat = quad_ok && flag[a];
+            for (int qd = 0; pat && qd <= 4; ++qd) pat = hsplit[5 * v + qd] - sb[a] == qd * nq;
+            if (!pat) {
+                vrest.push_back(v);
+                continue;
+            }
+            for (int qd = 0; qd < 4; ++qd) {
+                const int c = nbox + 4 * v + qd;
+                qcols[qd].push_back(c);
+                qslot[(size_t)c * 4 + qd] = 5 * v + qd;
+            }
+        }
+        N.vrest = upload(P, vrest);
+        N.n_vrest = (int)vrest.size();
+        std::vector<int32_t> cols;
+        for (int qd = 0; qd < 4; ++qd) cols.insert(cols.end(), qcols[qd].begin(), qcols[qd].end());
+        N.n_quad_cols = (int)cols.size();
+        if (N.n_quad_cols > 0) {
+            N.quad_cols = upload(P, cols);
+            N.quad_slot = upload(P, qslot);
+            const int Pn = P->P, PD = P->PD;
+            std::vector<double> A((size_t)PD * nq), Af((size_t)4 * PD * nq);
+            for (int qd = 0; qd < 4; ++qd) {
+                const double dx = (qd & 1) ? 0.25 : -0.25, dy = (qd & 2) ? 0.25 : -0.25;
+                std::fill(A.begin(), A.end(), 0.0);
+                for (int j = 0; j < nq; ++j) {
+                    const int pj = qd * nq + j;
+                    const std::complex<double> w(2.0 * (rx[pj] - dx), 2.0 * (ry[pj] - dy));
+                    std::complex<double> pw(1.0, 0.0);
+                    A[j] = 1.0;
+                    for (int k = 1; k < Pn; ++k) {
+                        pw *= w;
+                        A[(size_t)k * nq + j] = -pw.real() / k;
+                        A[(size_t)(Pn + k) * nq + j] = -pw.imag() / k;
+                    }
+                }
+                vp_to_frag(A.data(), PD, nq, nq, Af.data() + (size_t)qd * PD * nq);
+            }
+            if (P->fp32) {
+                std::vector<float> af(Af.begin(), Af.end());
+                N.quad_op_f32 = upload(P, af);
+                VP_HIP(hipStreamSynchronize(s));  // af leaves scope
+            } else {
+                N.quad_op = upload(P, Af);
+            }
+        }
+        VP_HIP(hipStreamSynchronize(s));  // host vectors leave scope
+    }
     VP_HIP(hipStreamSynchronize(s));
 }
 

@@ -79,6 +79,7 @@ struct TranslateArgs {
     const int32_t *tile_ops = nullptr;
     const int32_t *tile_order = nullptr;  // optional launch order of the tiles (most operators first)
     const void *zero_col = nullptr;       // zeros of the input type, at least 4 S long (absent sources)
+    const int32_t *xinit = nullptr;       // optional [box] nonzero: add to the output column (k_translate_split)
 };
 
 // TI/TO: element types of input/output columns; TM: matrix-core type;
@@ -294,13 +295,14 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
     }
     if (valid) {
         TO *op = out + a.out.off(box) + (int64_t)bt * a.out.bstride;
+        const bool add = ACCUM || (a.xinit && a.xinit[box]);
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = r * 16 + M::row(i, g);
                 if (row < a.nrows_out) {
-                    if (ACCUM) op[row] += (TO)vals[r][i];
+                    if (add) op[row] += (TO)vals[r][i];
                     else op[row] = (TO)vals[r][i];
                 }
             }

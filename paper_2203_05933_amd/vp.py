@@ -36,7 +36,7 @@ _ARR_DTYPE = {0: np.int32, 1: np.int32, 2: np.int32, 3: np.int32, 4: np.int32, 5
 EXPORTS = ("vp_default_options", "vp_plan", "vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets",
            "vp_set_stream", "vp_destroy", "vp_last_error", "vp_get_info", "vp_get_array",
            "vp_set_timing", "vp_get_timing")
-STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish", "tables", "corr")
+STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish", "tables", "corr", "coarse")
 
 
 class VPError(RuntimeError):
@@ -60,7 +60,9 @@ class PlanInfo(ctypes.Structure):
                 ("self_targets", ctypes.c_int32), ("list_len", ctypes.c_int64 * 4),
                 ("table_leaves", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("m2l_translations", ctypes.c_int64),
-                ("m2l_tile_ops", ctypes.c_int64), ("table_tile_ops", ctypes.c_int64), ("root", ctypes.c_double * 3)]
+                ("m2l_tile_ops", ctypes.c_int64), ("table_tile_ops", ctypes.c_int64),
+                ("m2l_coarse_translations", ctypes.c_int64), ("m2l_coarse_tile_ops", ctypes.c_int64),
+                ("split_level", ctypes.c_int32), ("reserved", ctypes.c_int32), ("root", ctypes.c_double * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -403,3 +403,24 @@ def test_tables_on_adaptive_star_subset():
     print(f"star window n={x.size} table_leaves={info['table_leaves']} rel_inf={err:.3e}")
     assert err <= TOL64
     plan.close()
+
+
+def test_tables_match_pairwise_with_x_lists():
+    """An adaptive window with X lists (leaves next to finer leaves): the
+    congruent-leaf path (near tables, pattern P2M/L2P and the quadrant
+    matrices for the virtual children of pattern X-list sources) against the
+    general path (pairwise near field, VALU P2M of every quadrant)."""
+    vp = _vp()
+    wl = gen.config1()
+    keep = (np.abs(wl.x - 0.9) < 0.25) & (np.abs(wl.y) < 0.25)
+    x, y, w, f = wl.x[keep], wl.y[keep], wl.w[keep], wl.f[:, keep]
+    out = {}
+    for mode in ("tables", "pairwise"):
+        plan = vp.Plan(x, y, w, order=30, p2p_mode=mode, root=wl.root)
+        info = plan.info()
+        assert info["list_len"][3] > 0
+        out[mode] = _host(plan.eval(_dev(f)))
+        plan.close()
+    d = relinf(out["tables"], out["pairwise"])
+    print(f"star window: tables vs pairwise {d:.2e}")
+    assert d <= 1e-13
