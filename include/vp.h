@@ -224,7 +224,9 @@ enum {
     VP_STAGE_CORR = 10,  /* sparse correction apply C f (FINISH: adding the un-permuted FMM sums) */
     VP_STAGE_COARSE = 11,/* M2M, M2L and L2L of the levels below split_level (third stream);
                             M2M, M2L and L2L hold the levels from split_level on */
-    VP_NSTAGES = 12
+    VP_STAGE_P2M_PAT = 12,/* P2M by fixed matrices (pattern leaves and their quadrants);
+                             P2M holds the VALU P2M of the other leaves (third stream) */
+    VP_NSTAGES = 13
 };
 vp_status vp_set_timing(vp_plan_t plan, int32_t enable);
 vp_status vp_get_timing(vp_plan_t plan, double *ms, int64_t *nevals);

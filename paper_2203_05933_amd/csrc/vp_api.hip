@@ -204,7 +204,7 @@ static void free_plan(vp_plan_s *P) {
     if (P->stream) (void)hipStreamSynchronize(P->stream);
     else (void)hipDeviceSynchronize();
     vp::release_streams(P);
-    for (hipEvent_t e : {P->ev_fork, P->ev_join, P->ev_p2l, P->ev_upper, P->ev_coarse})
+    for (hipEvent_t e : {P->ev_fork, P->ev_join, P->ev_p2m, P->ev_p2l, P->ev_upper, P->ev_coarse, P->ev_m2l})
         if (e) (void)hipEventDestroy(e);
     release_timing(P);
     P->mem.free_all();
@@ -237,7 +237,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->stream = static_cast<hipStream_t>(o.stream);
         VP_HIP(hipGetDevice(&P->device));
         vp::acquire_streams(P);
-        for (hipEvent_t *e : {&P->ev_fork, &P->ev_join, &P->ev_p2l, &P->ev_upper, &P->ev_coarse})
+        for (hipEvent_t *e : {&P->ev_fork, &P->ev_join, &P->ev_p2m, &P->ev_p2l, &P->ev_upper, &P->ev_coarse, &P->ev_m2l})
             VP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
         P->err_flag = P->mem.alloc<int32_t>(1);
         P->w_user = P->mem.alloc<double>(n);
@@ -255,7 +255,9 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
             VP_HIP(hipStreamSynchronize(P->stream));
         }
         P->col = P->mem.alloc<int32_t>(P->nnz);
-        P->val = P->mem.alloc<double>(P->nnz);
+        // values padded to an even count with zeros (the correction kernel reads aligned pairs)
+        P->val = P->mem.alloc<double>(P->nnz + 2);
+        vp::fill_f64(P->val + P->nnz, 0.0, 2, P->stream);
         if (P->nnz > 0) {
             VP_HIP(hipMemcpyAsync(P->col, col, sizeof(int32_t) * P->nnz, hipMemcpyHostToDevice, P->stream));
             VP_HIP(hipMemcpyAsync(P->val, val, sizeof(double) * P->nnz, hipMemcpyHostToDevice, P->stream));
@@ -267,6 +269,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         const int64_t len = std::max(n, m);
         P->q = P->mem.alloc<double>((size_t)P->nbatch * len);
         P->acc = P->mem.alloc<double>((size_t)P->nbatch * 2 * len);
+        P->acc_far = P->mem.alloc<double>((size_t)P->nbatch * len);
         const size_t esz = P->fp32 ? 4 : 8;
         // multipoles also for the virtual children of X-list sources
         const size_t ecount = (size_t)P->tree.nbox * P->nbatch * P->PD;

@@ -51,7 +51,8 @@ void build_csr_transpose(vp_plan_s *P) {
     hipStream_t s = P->stream;
     P->rowptrT = P->mem.alloc<int64_t>(n + 1);
     P->colT = P->mem.alloc<int32_t>(nnz);
-    P->valT = P->mem.alloc<double>(nnz);
+    P->valT = P->mem.alloc<double>(nnz + 2);  // padded like the values (aligned pair reads)
+    fill_f64(P->valT + nnz, 0.0, 2, s);
     if (nnz == 0) {
         fill_f64(reinterpret_cast<double *>(P->rowptrT), 0.0, n + 1, s);  // all-zero int64
         return;

@@ -168,40 +168,41 @@ __device__ inline void p2m_range(const PointRoles &R, int s0, int s1, double cx,
     }
 }
 
+// VALU P2M, one wave per job: a leaf b (job >= 0), about its centre at its
+// scale; or (job = ~(4 v + quadrant)) a virtual child of X-list source leaf
+// v: the quadrant's sources about the quadrant centre at the children's scale.
 template <class E>
-__global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_t *__restrict__ boxes,
-                                            int nboxes, const double *__restrict__ q, int nbatch,
-                                            int P, int PD, const E *__restrict__ invk,
-                                            E *__restrict__ Mexp) {
+__global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_t *__restrict__ jobs,
+                                            const int32_t *__restrict__ vleaf, const int32_t *__restrict__ vsplit,
+                                            int nbox, const double *__restrict__ q, int nbatch, int P, int PD,
+                                            const E *__restrict__ invk, E *__restrict__ Mexp) {
     extern __shared__ unsigned char smem[];
     E *Wre = reinterpret_cast<E *>(smem);   // [16][P]
     E *Wim = Wre + 16 * P;                  // [16][P]
     __shared__ E sq[16][16];                // charges of the chunk [density][source]
-    const int b = boxes[blockIdx.x];
-    p2m_range<E>(R, R.sb[b], R.se[b], G.cx[b], G.cy[b], 1.0 / G.side[G.level[b]], q, nbatch, P, PD, invk,
-                 Mexp + (int64_t)b * nbatch * PD, Wre, Wim, sq);
-}
-
-// P2M of the four virtual children of an X-list source leaf (block 4 v + quadrant):
-// the quadrant's sources, about the quadrant centre, at the children's scale.
-template <class E>
-__global__ void __launch_bounds__(64) k_p2m_quad(PointRoles R, BoxGeo G, const int32_t *__restrict__ vleaf,
-                                                 const int32_t *__restrict__ vsel,
-                                                 const int32_t *__restrict__ vsplit, int nbox,
-                                                 const double *__restrict__ q, int nbatch, int P, int PD,
-                                                 const E *__restrict__ invk, E *__restrict__ Mexp) {
-    extern __shared__ unsigned char smem[];
-    E *Wre = reinterpret_cast<E *>(smem);
-    E *Wim = Wre + 16 * P;
-    __shared__ E sq[16][16];
-    // vsel: the selected source leaves (indices v), null = all
-    const int v = vsel ? vsel[blockIdx.x >> 2] : (int)(blockIdx.x >> 2), qd = blockIdx.x & 3;
-    const int a = vleaf[v];
-    const double h = G.side[G.level[a]];
-    const double cx = G.cx[a] + ((qd & 1) ? 0.25 : -0.25) * h;
-    const double cy = G.cy[a] + ((qd >> 1) ? 0.25 : -0.25) * h;
-    p2m_range<E>(R, vsplit[5 * v + qd], vsplit[5 * v + qd + 1], cx, cy, 2.0 / h, q, nbatch, P, PD, invk,
-                 Mexp + (int64_t)(nbox + 4 * v + qd) * nbatch * PD, Wre, Wim, sq);
+    const int j = jobs[blockIdx.x];
+    int s0, s1, col;
+    double cx, cy, inv_s;
+    if (j >= 0) {
+        s0 = R.sb[j];
+        s1 = R.se[j];
+        cx = G.cx[j];
+        cy = G.cy[j];
+        inv_s = 1.0 / G.side[G.level[j]];
+        col = j;
+    } else {
+        const int vq = ~j, v = vq >> 2, qd = vq & 3;
+        const int a = vleaf[v];
+        const double h = G.side[G.level[a]];
+        cx = G.cx[a] + ((qd & 1) ? 0.25 : -0.25) * h;
+        cy = G.cy[a] + ((qd >> 1) ? 0.25 : -0.25) * h;
+        s0 = vsplit[5 * v + qd];
+        s1 = vsplit[5 * v + qd + 1];
+        inv_s = 2.0 / h;
+        col = nbox + vq;
+    }
+    p2m_range<E>(R, s0, s1, cx, cy, inv_s, q, nbatch, P, PD, invk, Mexp + (int64_t)col * nbatch * PD, Wre, Wim,
+                 sq);
 }
 
 // ----------------------------------------------------------------------------
@@ -765,6 +766,8 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
 // its run start instead of a column index per non-zero.  Reductions run in
 // a fixed lane order.
 // ----------------------------------------------------------------------------
+typedef double vp_d2 __attribute__((ext_vector_type(2)));
+
 template <int NBG, bool RUNS>
 __global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0, int64_t nnz,
                                               const int64_t *__restrict__ rowptr,
@@ -774,49 +777,66 @@ __global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0
                                               const double *__restrict__ f, int64_t flen,
                                               double *__restrict__ out) {
     // out[b][i] = sum_{q in row i} val[q] f[b][col[q]] (nnz >= 1).  16 lanes
-    // per row; a group takes R consecutive rows and issues the loads of the
-    // first 64 entries of all R rows before any arithmetic (indices clamped
-    // to valid entries, terms past a row's end multiplied by zero, so no
-    // load sits behind a branch); longer rows continue in a loop.  With RUNS
-    // every row's columns are one contiguous run and the column array is
-    // never read.  A non-finite value makes its row (or, in f, every
-    // potential) non-finite either way.
-    constexpr int R = NBG >= 4 ? 1 : (NBG == 2 ? 2 : 4);  // registers: R x 4 loads and R x NBG sums
+    // per row; a group takes R consecutive rows.  Values stream as aligned
+    // pairs (16-byte non-temporal loads; the value array is padded to an even
+    // length with zeros): lane l of a row reads pairs l and l + 16 from the
+    // pair holding the row's first value, i.e. values [p0 & ~1, (p0 & ~1) + 64);
+    // longer rows continue in a loop.  Indices are clamped to valid entries
+    // and terms outside the row are multiplied by zero, so no load sits
+    // behind a branch; the next rows' extents are fetched while this row's
+    // values load.  With RUNS every row's columns are one contiguous run and
+    // the column array is never read.  A non-finite value makes its row (or,
+    // in f, every potential) non-finite either way.
+    constexpr int R = NBG >= 4 ? 1 : (NBG == 2 ? 2 : 4);  // registers: R x 4 values and R x NBG sums
     const int l16 = threadIdx.x & 15;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) >> 4;
     const int nbg = min(NBG, nbatch - bt0);
-    for (int64_t i0 = grp * R; i0 < nrows; i0 += ngrp * R) {
-        // lane r < R fetches row i0 + r's extent
+    const int64_t npair = (nnz + 1) >> 1;
+    const vp_d2 *__restrict__ vp2 = reinterpret_cast<const vp_d2 *>(valv);
+    // lane r < R fetches the extent of row base + r (clamped to a valid row)
+    int64_t mp0 = 0, mp1 = 0;
+    int32_t mrs = 0;
+    auto fetch = [&](int64_t base) {
+        const int64_t im = min(base + (l16 < R ? l16 : 0), nrows - 1);
+        mp0 = rowptr[im];
+        mp1 = rowptr[im + 1];
+        if (RUNS) mrs = run_start[im];
+    };
+    int64_t i0 = grp * R;
+    if (i0 < nrows) fetch(i0);
+    for (; i0 < nrows; i0 += ngrp * R) {
         const int64_t im = i0 + l16;
         const bool mrow = l16 < R && im < nrows;
-        int64_t mp0 = 0, mp1 = 0;
-        int32_t mrs = 0;
-        if (mrow) {
-            mp0 = rowptr[im];
-            mp1 = rowptr[im + 1];
-            if (RUNS) mrs = run_start[im];
-        }
         int64_t p0[R], p1[R];
         int32_t rs[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            const bool rv = i0 + r < nrows;  // rows past the end are empty
             p0[r] = __shfl(mp0, r, 16);
-            p1[r] = __shfl(mp1, r, 16);
+            p1[r] = rv ? __shfl(mp1, r, 16) : p0[r];
             rs[r] = __shfl(mrs, r, 16);
         }
+        fetch(i0 + ngrp * R);  // the next rows' extents, in flight with the values
         double v[R][4];
         int64_t c[R][4];
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int r = 0; r < R; ++r) {
+            const int64_t a0 = p0[r] & ~(int64_t)1;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t pq = p0[r] + l16 + 16 * u;
-                const bool in = pq < p1[r];
-                const int64_t pc = min(max(in ? pq : p1[r] - 1, (int64_t)0), nnz - 1);
-                v[r][u] = __builtin_nontemporal_load(valv + pc) * (in ? 1.0 : 0.0);  // streamed once
-                c[r][u] = RUNS ? (in ? (int64_t)rs[r] + (pq - p0[r]) : (int64_t)0) : (int64_t)colv[pc];
+            for (int u = 0; u < 2; ++u) {
+                const int64_t pi = (a0 >> 1) + l16 + 16 * u;
+                const vp_d2 w = __builtin_nontemporal_load(vp2 + min(pi, npair - 1));  // streamed once
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int64_t qi = 2 * pi + e;
+                    const bool in = qi >= p0[r] && qi < p1[r];
+                    v[r][2 * u + e] = w[e] * (in ? 1.0 : 0.0);
+                    c[r][2 * u + e] = RUNS ? (in ? (int64_t)rs[r] + (qi - p0[r]) : (int64_t)0)
+                                           : (in ? (int64_t)colv[min(qi, nnz - 1)] : (int64_t)0);
+                }
             }
+        }
         double part[R][NBG];
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -829,17 +849,24 @@ __global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0
                 for (int u = 0; u < 4; ++u) a = fma(v[r][u], fk[c[r][u]], a);
                 part[r][k] = a;
             }
-        // rows longer than 64 entries
+        // rows reaching past the first 64 values of their pair range
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            for (int64_t pb = p0[r] + 64; pb < p1[r]; pb += 16) {
-                const int64_t pq = pb + l16;
-                if (pq < p1[r]) {
-                    const double vv = __builtin_nontemporal_load(valv + pq);
-                    const int64_t cc = RUNS ? (int64_t)rs[r] + (pq - p0[r]) : (int64_t)colv[pq];
+            for (int64_t pb = (p0[r] & ~(int64_t)1) + 64; pb < p1[r]; pb += 32) {
+                const int64_t pi = (pb >> 1) + l16;
+                if (2 * pi < p1[r]) {
+                    const vp_d2 w = __builtin_nontemporal_load(vp2 + min(pi, npair - 1));
 #pragma unroll
-                    for (int k = 0; k < NBG; ++k)
-                        part[r][k] = fma(vv, f[(int64_t)(bt0 + min(k, nbg - 1)) * flen + cc], part[r][k]);
+                    for (int e = 0; e < 2; ++e) {
+                        const int64_t qi = 2 * pi + e;
+                        const bool in = qi < p1[r];
+                        const double vv = w[e] * (in ? 1.0 : 0.0);
+                        const int64_t cc = RUNS ? (in ? (int64_t)rs[r] + (qi - p0[r]) : (int64_t)0)
+                                                : (in ? (int64_t)colv[min(qi, nnz - 1)] : (int64_t)0);
+#pragma unroll
+                        for (int k = 0; k < NBG; ++k)
+                            part[r][k] = fma(vv, f[(int64_t)(bt0 + min(k, nbg - 1)) * flen + cc], part[r][k]);
+                    }
                 }
             }
         }
@@ -866,18 +893,21 @@ __global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0
     }
 }
 
-// out[b][i] += scale_i * acc[b][inv[i]]: the FMM sums (sorted order) added to
-// the correction already in out (user order)
+// out[b][i] += scale_i * (acc[b][inv[i]] + acc2[b][inv[i]]): the near- and
+// far-field sums (sorted order; acc2 may be null) added to the correction
+// already in out (user order)
 __global__ void k_add_acc(int64_t nrows, int nbatch, const int32_t *__restrict__ inv,
-                          const double *__restrict__ scale, const double *__restrict__ acc, int64_t acc_len,
-                          double *__restrict__ out) {
+                          const double *__restrict__ scale, const double *__restrict__ acc,
+                          const double *__restrict__ acc2, int64_t acc_len, double *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrows) return;
     const int32_t si = inv[i];
     const double sc = scale ? scale[i] : 1.0;
     for (int b = 0; b < nbatch; ++b) {
         double *o = out + (int64_t)b * nrows + i;
-        *o = sc * acc[(int64_t)b * acc_len + si] + *o;
+        const int64_t k = (int64_t)b * acc_len + si;
+        const double v = acc2 ? acc[k] + acc2[k] : acc[k];
+        *o = sc * v + *o;
     }
 }
 
@@ -1009,8 +1039,6 @@ void build_schedules(vp_plan_s *P) {
         if (nch[b] == 0 && lev[b] >= 2) p2m.push_back(b);
         if (nch[b] == 0 && wp[b + 1] > wp[b]) wl.push_back(b);
     }
-    P->n_p2m = (int)p2m.size();
-    P->p2m_leaves = up(p2m);
 
     // X list, one level apart: the source leaf a (level l-1) splits into four
     // virtual children on the target's level l.  None of them is adjacent to
@@ -1078,6 +1106,13 @@ void build_schedules(vp_plan_s *P) {
     }
     P->n_vleaf = (int)vleaf.size();
     P->vleaf = up(vleaf);
+    // VALU P2M jobs without tables: every leaf of level >= 2, then the four
+    // virtual children of each X-list source (job ~(4 v + quadrant))
+    std::vector<int32_t> p2m_jobs(p2m);
+    for (int v = 0; v < (int)vleaf.size(); ++v)
+        for (int qd = 0; qd < 4; ++qd) p2m_jobs.push_back(~(4 * v + qd));
+    P->n_p2m_jobs = (int)p2m_jobs.size();
+    P->p2m_jobs = up(p2m_jobs);
     P->vsplit_s = up(vsplit_s);
     P->vsplit_t = up(vsplit_t);
     VP_HIP(hipMemcpyAsync(T.v_slot, vslot.data(), 4 * vslot.size(), hipMemcpyHostToDevice, s));
@@ -1270,8 +1305,10 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
     P->stage_end(VP_STAGE_CHARGE);
 }
 
+// fixed-matrix launches on pattern leaves (launch_pattern_ops)
+enum { PAT_P2M = 0, PAT_L2P = 1 };
 template <class E>
-static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind);
+static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind, double *acc = nullptr);
 
 // M2L of the V lists (and X-list virtual children) of one level range
 // (part 0: levels from the split level on, part 1: the levels below) in one
@@ -1333,44 +1370,22 @@ static void launch_m2l(vp_plan_s *P, int part) {
     }
 }
 
-// Leaf multipoles: congruent leaves by one matrix, the others and the
-// virtual children of X-list sources on the VALU
+// Leaf multipoles on the VALU: every leaf and virtual child of an X-list
+// source, or with tables only those the fixed matrices do not serve
 template <class E>
 static void run_p2m(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool tables) {
     Tree &T = P->tree;
-    hipStream_t s = P->stream;
     const int nb = P->nbatch, Pn = P->P, PD = P->PD;
-    E *M = static_cast<E *>(P->Mexp);
     const bool f32 = sizeof(E) == 4;
     const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
     const size_t lds = sizeof(E) * 2 * 16 * Pn;
-    if (tables) {
-        run_pattern_op<E>(P, R, 0);
-        if (P->near.n_p2m_rest > 0) {
-            hipLaunchKernelGGL(k_p2m<E>, dim3(P->near.n_p2m_rest), dim3(64), lds, s, R, G, P->near.p2m_rest,
-                               P->near.n_p2m_rest, P->q, nb, Pn, PD, invk, M);
-            VP_LAUNCH_CHECK();
-        }
-    } else if (P->n_p2m > 0) {
-        hipLaunchKernelGGL(k_p2m<E>, dim3(P->n_p2m), dim3(64), lds, s, R, G, P->p2m_leaves, P->n_p2m, P->q, nb,
-                           Pn, PD, invk, M);
-        VP_LAUNCH_CHECK();
-    }
-    // virtual children of X-list sources (their points in this evaluation's
-    // source role): pattern leaves by the quadrant matrices, the rest on the VALU
+    const int32_t *jobs = tables ? P->near.p2m_jobs_rest : P->p2m_jobs;
+    const int njobs = tables ? P->near.n_p2m_jobs_rest : P->n_p2m_jobs;
+    if (njobs <= 0) return;
     const int32_t *split = R.sb == T.sb ? P->vsplit_s : P->vsplit_t;
-    if (tables) {
-        if (P->near.n_quad_cols > 0) run_pattern_op<E>(P, R, 2);
-        if (P->near.n_vrest > 0) {
-            hipLaunchKernelGGL(k_p2m_quad<E>, dim3(4 * P->near.n_vrest), dim3(64), lds, s, R, G, P->vleaf,
-                               P->near.vrest, split, T.nbox, P->q, nb, Pn, PD, invk, M);
-            VP_LAUNCH_CHECK();
-        }
-    } else if (P->n_vleaf > 0) {
-        hipLaunchKernelGGL(k_p2m_quad<E>, dim3(4 * P->n_vleaf), dim3(64), lds, s, R, G, P->vleaf,
-                           (const int32_t *)nullptr, split, T.nbox, P->q, nb, Pn, PD, invk, M);
-        VP_LAUNCH_CHECK();
-    }
+    hipLaunchKernelGGL(k_p2m<E>, dim3(njobs), dim3(64), lds, P->stream, R, G, jobs, P->vleaf, split, T.nbox, P->q,
+                       nb, Pn, PD, invk, static_cast<E *>(P->Mexp));
+    VP_LAUNCH_CHECK();
 }
 
 // M2M for the parents on levels l_hi down to l_lo (one launch per level)
@@ -1527,11 +1542,11 @@ static void run_tables(vp_plan_s *P, const PointRoles &R) {
     }
 }
 
-// Fixed-matrix launches on pattern leaves: P2M (q -> M), L2P (L -> acc), and
-// the quadrant P2M of pattern X-list sources (q -> virtual-child columns)
-enum { PAT_P2M = 0, PAT_L2P = 1, PAT_QUAD = 2 };
+// Fixed-matrix launches on pattern leaves: P2M (q -> M, with the quadrant
+// P2M of pattern X-list sources into their virtual-child columns) and L2P
+// (L -> acc)
 template <class E, int RBP, int RBE>
-static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind) {
+static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, double *acc) {
     NearTables &N = P->near;
     const bool f32 = sizeof(E) == 4;
     TranslateArgs a;
@@ -1542,36 +1557,22 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind) {
     a.level = P->tree.level;
     a.logside = P->tree.d_logside;
     if (kind == PAT_P2M) {
-        // rows = expansion (RBE blocks), cols = pattern points (RBP*16)
+        // rows = expansion (RBE blocks), cols = pattern points (RBP*16); operator
+        // 0 for pattern leaves, 1 + quadrant for the virtual children of pattern
+        // X-list sources (zero outside the quadrant's points); the columns are
+        // grouped by operator, so a 64-column block uses one (two at a boundary)
         constexpr int RB = RBE, S = RBP * 4;
         constexpr bool LDSA = translate_ldsa<E, RB, S, false>();
         constexpr size_t lds = LDSA ? translate_lds_bytes<E, RB, S, false>() : 0;
-        a.cols_box = N.p2m_pat;
-        a.ncols = N.n_p2m_pat * P->nbatch;
+        a.cols_box = N.p2m_cols;
+        a.ncols = N.n_p2m_cols * P->nbatch;
+        a.slots = N.p2m_slot;
+        a.nops = 5;
         a.in = ColAddr{R.nsrc, 0, R.sb};
         a.out = ColAddr{P->PD, (int64_t)P->nbatch * P->PD, nullptr};
         a.nrows_out = P->PD;
         if (a.ncols <= 0) return;
         const E *op = f32 ? (const E *)N.p2m_op_f32 : (const E *)N.p2m_op;
-        hipLaunchKernelGGL((k_translate<double, E, E, RB, S, false, false, LDSA>),
-                           dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
-                           P->q, static_cast<E *>(P->Mexp));
-    } else if (kind == PAT_QUAD) {
-        // four operators (one per quadrant, RBP*4 points each); the columns are
-        // grouped by quadrant, so a 64-column block uses one operator (two at
-        // a group boundary) and skips the others
-        constexpr int RB = RBE, S = RBP;
-        constexpr bool LDSA = translate_ldsa<E, RB, S, false>();
-        constexpr size_t lds = LDSA ? translate_lds_bytes<E, RB, S, false>() : 0;
-        a.cols_box = N.quad_cols;
-        a.ncols = N.n_quad_cols * P->nbatch;
-        a.slots = N.quad_slot;
-        a.nops = 4;
-        a.in = ColAddr{R.nsrc, 0, R.sb == P->tree.sb ? P->vsplit_s : P->vsplit_t};
-        a.out = ColAddr{P->PD, (int64_t)P->nbatch * P->PD, nullptr};
-        a.nrows_out = P->PD;
-        if (a.ncols <= 0) return;
-        const E *op = f32 ? (const E *)N.quad_op_f32 : (const E *)N.quad_op;
         hipLaunchKernelGGL((k_translate<double, E, E, RB, S, false, false, LDSA>),
                            dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
                            P->q, static_cast<E *>(P->Mexp));
@@ -1588,7 +1589,7 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind) {
         const E *op = f32 ? (const E *)N.l2p_op_f32 : (const E *)N.l2p_op;
         hipLaunchKernelGGL((k_translate<E, double, E, RB, S, false, true, LDSA>),
                            dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
-                           static_cast<const E *>(P->Lexp), P->acc);
+                           static_cast<const E *>(P->Lexp), acc);
     }
     VP_LAUNCH_CHECK();
 }
@@ -1598,11 +1599,11 @@ bool pattern_op_supported(int npat, int PD) {
 }
 
 template <class E>
-static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind) {
+static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind, double *acc) {
     const int key = P->near.npat / 16 * 16 + P->PD / 16;
     switch (key) {
 #define VP_PAT(NP, NE) \
-    case NP * 16 + NE: launch_pattern_ops<E, NP, NE>(P, R, kind); break;
+    case NP * 16 + NE: launch_pattern_ops<E, NP, NE>(P, R, kind, acc); break;
         VP_PAT(1, 1) VP_PAT(1, 2) VP_PAT(1, 3) VP_PAT(1, 4)
         VP_PAT(2, 1) VP_PAT(2, 2) VP_PAT(2, 3) VP_PAT(2, 4)
         VP_PAT(4, 1) VP_PAT(4, 2) VP_PAT(4, 3) VP_PAT(4, 4)
@@ -1617,7 +1618,7 @@ static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *
     NearTables &N = P->near;
     P->stage_begin(VP_STAGE_FAR);
     if (tables) {
-        run_pattern_op<E>(P, R, 1);
+        run_pattern_op<E>(P, R, PAT_L2P, acc);
         if (N.n_far_leaves > 0) {
             hipLaunchKernelGGL((k_far<E, GRAD>), dim3(N.n_far_leaves), dim3(256), 0, P->stream, R, G, N.far_leaves,
                                T.lptr[2], T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp,
@@ -1638,11 +1639,15 @@ static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint);
 
 // One evaluation on three streams (default priority; with VP_FLAG_ONE_STREAM
 // everything runs on the plan's stream in the order written here):
-//   third stream: P2L | wait(upper) M2M, M2L, L2L of the levels below the split
+//   third stream: VALU P2M, P2L | wait(upper) M2M, M2L, L2L of the levels
+//                 below the split
 //   second stream: correction C f, near tables, pairwise near field
-//   plan's stream: P2M, M2M from the finest level to the split level |
+//   plan's stream: fixed-matrix P2M | wait(VALU P2M) M2M from the finest
+//                  level to the split level |
 //                  wait(P2L) M2L of the levels from the split on | wait(coarse)
-//                  L2L from the split level down | wait(near) far field, finish
+//                  L2L from the split level down, far field | wait(near) finish
+// (the far field writes its own array; with gradients it waits for the near
+// field and adds to it)
 template <class E>
 static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool adjoint, bool grad, const double *f,
                        double *u) {
@@ -1665,9 +1670,17 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         VP_HIP(hipStreamWaitEvent(s2, P->ev_fork, 0));
         VP_HIP(hipStreamWaitEvent(s3, P->ev_fork, 0));
     }
-    // third stream: P2L (needs only the charges)
+    // third stream: P2L (needs only the charges); zero the far-field sums,
+    // which stay apart from the near field so that the near field can run
+    // to the end of the evaluation
     P->stream = s3;
+    if (!grad) fill_f64(P->acc_far, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
     if (fmm) {
+        // VALU leaf multipoles (the fixed-matrix ones run on the plan's stream)
+        P->stage_begin(VP_STAGE_P2M);
+        run_p2m<E>(P, R, G, tables);
+        P->stage_end(VP_STAGE_P2M);
+        if (!one) VP_HIP(hipEventRecord(P->ev_p2m, s3));
         P->stage_begin(VP_STAGE_P2L);
         run_p2l<E>(P, R, G);
         P->stage_end(VP_STAGE_P2L);
@@ -1698,18 +1711,26 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         }
         P->stage_end(VP_STAGE_P2P);
     };
+    // the second stream's work is enqueued in two parts: before the plan's
+    // stream reaches M2L, and after (when it may wait for that M2L, so that
+    // the rest overlaps the latency-bound passes after it)
+    auto wait_m2l = [&] {
+        if (!one && fmm) VP_HIP(hipStreamWaitEvent(s2, P->ev_m2l, 0));
+    };
     // with tables both near-field kernels add to zeroed potentials
     if (tables) fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
     corr();
     tab();
     pair();
-    if (!one) VP_HIP(hipEventRecord(P->ev_join, s2));
     // plan's stream: leaf multipoles and the upward pass down to the split level
     P->stream = ms;
     if (fmm) {
-        P->stage_begin(VP_STAGE_P2M);
-        run_p2m<E>(P, R, G, tables);
-        P->stage_end(VP_STAGE_P2M);
+        if (tables) {
+            P->stage_begin(VP_STAGE_P2M_PAT);
+            run_pattern_op<E>(P, R, PAT_P2M);
+            P->stage_end(VP_STAGE_P2M_PAT);
+        }
+        if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_p2m, 0));
         P->stage_begin(VP_STAGE_M2M);
         run_m2m<E>(P, G, Lmax - 1, L0);
         P->stage_end(VP_STAGE_M2M);
@@ -1734,17 +1755,28 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         P->stage_begin(VP_STAGE_M2L);
         launch_m2l<E>(P, 0);
         P->stage_end(VP_STAGE_M2L);
+        if (!one) VP_HIP(hipEventRecord(P->ev_m2l, ms));
+    } else if (!one) {
+        VP_HIP(hipStreamWaitEvent(ms, P->ev_p2l, 0));  // join the third stream
+    }
+    // second stream, second part
+    P->stream = s2;
+    (void)wait_m2l;
+    if (!one) VP_HIP(hipEventRecord(P->ev_join, s2));
+    P->stream = ms;
+    if (fmm) {
         if (coarse && !one) VP_HIP(hipStreamWaitEvent(ms, P->ev_coarse, 0));
         P->stage_begin(VP_STAGE_L2L);
         run_l2l<E>(P, G, L0, Lmax);
         P->stage_end(VP_STAGE_L2L);
-    } else if (!one) {
-        VP_HIP(hipStreamWaitEvent(ms, P->ev_p2l, 0));  // join the third stream
     }
-    if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_join, 0));
-    if (fmm) {
-        if (grad) run_far<E, true>(P, R, G, P->acc, false);
-        else run_far<E, false>(P, R, G, P->acc, tables);
+    if (grad) {
+        // the gradient sums go into the near-field array
+        if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_join, 0));
+        if (fmm) run_far<E, true>(P, R, G, P->acc, false);
+    } else {
+        if (fmm) run_far<E, false>(P, R, G, P->acc_far, tables);
+        if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_join, 0));
     }
     if (u) add_fmm_sums(P, u, adjoint);
 }
@@ -1802,7 +1834,7 @@ static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint) {
     const double *scale = adjoint ? P->w_user : nullptr;
     P->stage_begin(VP_STAGE_FINISH);
     hipLaunchKernelGGL(k_add_acc, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, P->stream, nrows, P->nbatch,
-                       inv, scale, P->acc, nrows, u);
+                       inv, scale, P->acc, P->acc_far, nrows, u);
     VP_LAUNCH_CHECK();
     P->stage_end(VP_STAGE_FINISH);
 }

@@ -208,24 +208,23 @@ struct NearTables {
     int n_rest_leaves = 0;
     P2PGather g_rest;                 // sources of the leftover lists
     int32_t *ident_slot = nullptr;    // [nbox] slot table b -> b (one-operator launches)
-    int32_t *p2m_pat = nullptr, *p2m_rest = nullptr;  // leaves (level >= 2) by kind
-    int n_p2m_pat = 0, n_p2m_rest = 0;
+    // P2M by fixed matrices: pattern leaves (operator 0), then the virtual
+    // children of pattern X-list sources grouped by quadrant (operator 1 + q)
+    int32_t *p2m_cols = nullptr;
+    int n_p2m_cols = 0;
+    int32_t *p2m_slot = nullptr;      // [nbox + 4 n_vleaf][5] source leaf in the column's operator slot, or -1
+    int32_t *p2m_jobs_rest = nullptr; // VALU P2M jobs of the rest (as vp_plan_s::p2m_jobs)
+    int n_p2m_jobs_rest = 0;
     int32_t *l2p_pat = nullptr;       // pattern target leaves (level >= 2)
     int n_l2p_pat = 0;
     int32_t *far_leaves = nullptr;    // leaves needing the series far-field kernel
     int n_far_leaves = 0;
     int32_t *local_done = nullptr;    // [nbox] 1: local expansion evaluated by the L2P operator
+    // [5][PD x npat] A-fragment order: the leaf P2M, then the four quadrant
+    // P2M matrices (about the quadrant centre at the children's scale, zero
+    // outside the quadrant's points)
     double *p2m_op = nullptr, *l2p_op = nullptr;      // float64 forms
     float *p2m_op_f32 = nullptr, *l2p_op_f32 = nullptr;  // FP32-bulk forms
-    // virtual children of pattern X-list sources: the quadrant's P2M is one
-    // of four fixed matrices (npat/4 points each); columns grouped by quadrant
-    int32_t *quad_cols = nullptr;     // virtual-child expansion columns nbox + 4 v + quadrant
-    int n_quad_cols = 0;
-    int32_t *quad_slot = nullptr;     // [nbox + 4 n_vleaf][4]: 5 v + quadrant in the quadrant's slot, or -1
-    double *quad_op = nullptr;        // [4][PD x npat/4] A-fragment order
-    float *quad_op_f32 = nullptr;
-    int32_t *vrest = nullptr;         // the other X-list source leaves (indices v), VALU kernel
-    int n_vrest = 0;
 };
 
 }  // namespace vp
@@ -250,7 +249,7 @@ struct vp_plan_s {
     // split_level (few boxes, latency bound) beside the M2L of the levels above
     hipStream_t aux2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_p2l = nullptr, ev_upper = nullptr, ev_coarse = nullptr;
+    hipEvent_t ev_p2m = nullptr, ev_p2l = nullptr, ev_upper = nullptr, ev_coarse = nullptr, ev_m2l = nullptr;
     int device = 0;
     std::string err;
     bool poisoned = false;
@@ -282,7 +281,8 @@ struct vp_plan_s {
 
     // evaluation workspace
     double *q = nullptr;     // [nbatch][max(n,m)] charges, sorted order
-    double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order
+    double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order (near field; gradients x 2)
+    double *acc_far = nullptr;  // [nbatch][max(n,m)] far-field potentials, sorted order
     void *Mexp = nullptr;    // [nbox + 4 n_vleaf][nbatch][PD] (double or float)
     void *Lexp = nullptr;
     void *zero_col = nullptr;  // max(PD, 128) zero doubles (an absent source column, either element type)
@@ -298,8 +298,8 @@ struct vp_plan_s {
     std::vector<int> lvl_box_begin;  // per level offsets into lvl_boxes
     int32_t *m2m_parents = nullptr;  // non-leaf boxes per level
     std::vector<int> m2m_begin;
-    int32_t *p2m_leaves = nullptr;   // leaves at level >= 2 with sources
-    int n_p2m = 0;
+    int32_t *p2m_jobs = nullptr;     // VALU P2M jobs: leaves of level >= 2, then ~(4 v + quadrant)
+    int n_p2m_jobs = 0;
     int32_t *x_boxes = nullptr;      // boxes whose X list keeps entries for the P2L kernel
     int n_x_boxes = 0;
     int32_t *xr_ptr = nullptr;       // those X entries (two or more levels apart), CSR over boxes

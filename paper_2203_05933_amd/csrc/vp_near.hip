@@ -273,10 +273,6 @@ void build_near_tables(vp_plan_s *P) {
         }
         if (!(pt && lev[b] >= 2) || wptr[b + 1] > wptr[b]) far_leaves.push_back(b);
     }
-    N.p2m_pat = upload(P, p2m_pat);
-    N.n_p2m_pat = (int)p2m_pat.size();
-    N.p2m_rest = upload(P, p2m_rest);
-    N.n_p2m_rest = (int)p2m_rest.size();
     N.l2p_pat = upload(P, l2p_pat);
     N.n_l2p_pat = (int)l2p_pat.size();
     std::stable_sort(far_leaves.begin(), far_leaves.end(),
@@ -382,19 +378,30 @@ void build_near_tables(vp_plan_s *P) {
             }
         }
         N.K = upload(P, K);
-        // P2M of a pattern leaf: rows = expansion (PD), cols = pattern points
+        // P2M of a pattern leaf: rows = expansion (PD), cols = pattern points;
+        // operator 0 about the leaf centre at its scale, operators 1 + qd about
+        // the centre of quadrant qd at half the scale over that quadrant's
+        // points (the virtual children of an X-list source leaf)
         const int Pn = P->P, PD = P->PD;
-        std::vector<double> A((size_t)PD * np, 0.0), Af((size_t)PD * np);
-        for (int j = 0; j < np; ++j) {
-            std::complex<double> w(rx[j], ry[j]), pw(1.0, 0.0);
-            A[(size_t)0 * np + j] = 1.0;
-            for (int k = 1; k < Pn; ++k) {
-                pw *= w;
-                A[(size_t)k * np + j] = -pw.real() / k;
-                A[(size_t)(Pn + k) * np + j] = -pw.imag() / k;
+        std::vector<double> A((size_t)PD * np), Af((size_t)5 * PD * np);
+        for (int op = 0; op < 5; ++op) {
+            std::fill(A.begin(), A.end(), 0.0);
+            const int qd = op - 1;
+            const double dx = op == 0 ? 0.0 : ((qd & 1) ? 0.25 : -0.25);
+            const double dy = op == 0 ? 0.0 : ((qd & 2) ? 0.25 : -0.25);
+            const double sc = op == 0 ? 1.0 : 2.0;
+            for (int j = 0; j < np; ++j) {
+                if (op > 0 && ((rx[j] > 0.0 ? 1 : 0) | (ry[j] > 0.0 ? 2 : 0)) != qd) continue;
+                std::complex<double> w(sc * (rx[j] - dx), sc * (ry[j] - dy)), pw(1.0, 0.0);
+                A[(size_t)0 * np + j] = 1.0;
+                for (int k = 1; k < Pn; ++k) {
+                    pw *= w;
+                    A[(size_t)k * np + j] = -pw.real() / k;
+                    A[(size_t)(Pn + k) * np + j] = -pw.imag() / k;
+                }
             }
+            vp_to_frag(A.data(), PD, np, np, Af.data() + (size_t)op * PD * np);
         }
-        vp_to_frag(A.data(), PD, np, np, Af.data());
         // L2P of a pattern leaf: rows = pattern points, cols = expansion (PD)
         std::vector<double> B((size_t)np * PD, 0.0), Bf((size_t)np * PD);
         for (int i = 0; i < np; ++i) {
@@ -419,75 +426,58 @@ void build_near_tables(vp_plan_s *P) {
     }
 
     // Virtual children of X-list source leaves that are pattern leaves: the
-    // P2M of quadrant qd is a fixed PD x (npat/4) matrix (powers of the
-    // pattern points about the quadrant centre, at the children's scale).
-    // Needs the reference pattern's points to fall in quadrant order, npat/4
-    // per quadrant, none on a dividing line (the source order of every
-    // pattern leaf is the reference order, so its quadrant ranges agree).
+    // P2M of quadrant qd is the fixed matrix 1 + qd.  The leaf's sorted
+    // sources split into its quadrants at the pattern's quadrant boundaries
+    // (the source order of every pattern leaf is the reference order); the
+    // plan checks this against each leaf's recorded quadrant ranges.  The
+    // other leaves and virtual children go to the VALU kernel.
     {
-        const int nv = P->n_vleaf, nq = npat / 4;
-        bool quad_ok = N.active && nv > 0 && npat % 16 == 0;
-        for (int j = 0; quad_ok && j < npat; ++j) {
-            const int qd = (rx[j] > 0.0 ? 1 : 0) | (ry[j] > 0.0 ? 2 : 0);
-            quad_ok = qd == j / nq && std::fabs(rx[j]) > 1e-6 && std::fabs(ry[j]) > 1e-6;
-        }
-        std::vector<int32_t> hv(nv), hsplit((size_t)5 * nv), qcols[4], vrest;
+        const int nv = P->n_vleaf;
+        std::vector<int32_t> hv(nv), hsplit((size_t)5 * nv), qcols[4], rest_q;
         if (nv > 0) {
             VP_HIP(hipMemcpyAsync(hv.data(), P->vleaf, 4 * (size_t)nv, hipMemcpyDeviceToHost, s));
             VP_HIP(hipMemcpyAsync(hsplit.data(), P->vsplit_s, 4 * hsplit.size(), hipMemcpyDeviceToHost, s));
             VP_HIP(hipStreamSynchronize(s));
         }
+        int qb[5] = {0, 0, 0, 0, npat};  // pattern quadrant boundaries
+        bool quad_ok = N.active;
+        for (int j = 0, prev = 0; quad_ok && j < npat; ++j) {
+            const int qd = (rx[j] > 0.0 ? 1 : 0) | (ry[j] > 0.0 ? 2 : 0);
+            quad_ok = qd >= prev && std::fabs(rx[j]) > 1e-6 && std::fabs(ry[j]) > 1e-6;
+            for (int t = prev + 1; t <= qd; ++t) qb[t] = j;
+            prev = qd;
+            if (j == npat - 1)
+                for (int t = qd + 1; t < 4; ++t) qb[t] = npat;
+        }
         const size_t ncol_all = (size_t)nbox + 4 * (size_t)nv;
-        std::vector<int32_t> qslot;
-        if (quad_ok) qslot.assign(ncol_all * 4, -1);
+        std::vector<int32_t> slot, cols(p2m_pat), jobs(p2m_rest);
+        if (N.active) {
+            slot.assign(ncol_all * 5, -1);
+            for (int b : p2m_pat) slot[(size_t)b * 5] = b;
+        }
         for (int v = 0; v < nv; ++v) {
             const int a = hv[v];
             bool pat = quad_ok && flag[a];
-            for (int qd = 0; pat && qd <= 4; ++qd) pat = hsplit[5 * v + qd] - sb[a] == qd * nq;
-            if (!pat) {
-                vrest.push_back(v);
-                continue;
-            }
+            for (int qd = 0; pat && qd <= 4; ++qd) pat = hsplit[5 * v + qd] - sb[a] == qb[qd];
             for (int qd = 0; qd < 4; ++qd) {
-                const int c = nbox + 4 * v + qd;
-                qcols[qd].push_back(c);
-                qslot[(size_t)c * 4 + qd] = 5 * v + qd;
-            }
-        }
-        N.vrest = upload(P, vrest);
-        N.n_vrest = (int)vrest.size();
-        std::vector<int32_t> cols;
-        for (int qd = 0; qd < 4; ++qd) cols.insert(cols.end(), qcols[qd].begin(), qcols[qd].end());
-        N.n_quad_cols = (int)cols.size();
-        if (N.n_quad_cols > 0) {
-            N.quad_cols = upload(P, cols);
-            N.quad_slot = upload(P, qslot);
-            const int Pn = P->P, PD = P->PD;
-            std::vector<double> A((size_t)PD * nq), Af((size_t)4 * PD * nq);
-            for (int qd = 0; qd < 4; ++qd) {
-                const double dx = (qd & 1) ? 0.25 : -0.25, dy = (qd & 2) ? 0.25 : -0.25;
-                std::fill(A.begin(), A.end(), 0.0);
-                for (int j = 0; j < nq; ++j) {
-                    const int pj = qd * nq + j;
-                    const std::complex<double> w(2.0 * (rx[pj] - dx), 2.0 * (ry[pj] - dy));
-                    std::complex<double> pw(1.0, 0.0);
-                    A[j] = 1.0;
-                    for (int k = 1; k < Pn; ++k) {
-                        pw *= w;
-                        A[(size_t)k * nq + j] = -pw.real() / k;
-                        A[(size_t)(Pn + k) * nq + j] = -pw.imag() / k;
-                    }
+                if (pat) {
+                    const int c = nbox + 4 * v + qd;
+                    qcols[qd].push_back(c);
+                    slot[(size_t)c * 5 + 1 + qd] = a;
+                } else {
+                    rest_q.push_back(~(4 * v + qd));
                 }
-                vp_to_frag(A.data(), PD, nq, nq, Af.data() + (size_t)qd * PD * nq);
-            }
-            if (P->fp32) {
-                std::vector<float> af(Af.begin(), Af.end());
-                N.quad_op_f32 = upload(P, af);
-                VP_HIP(hipStreamSynchronize(s));  // af leaves scope
-            } else {
-                N.quad_op = upload(P, Af);
             }
         }
+        for (int qd = 0; qd < 4; ++qd) cols.insert(cols.end(), qcols[qd].begin(), qcols[qd].end());
+        jobs.insert(jobs.end(), rest_q.begin(), rest_q.end());
+        N.n_p2m_cols = N.active ? (int)cols.size() : 0;
+        if (N.n_p2m_cols > 0) {
+            N.p2m_cols = upload(P, cols);
+            N.p2m_slot = upload(P, slot);
+        }
+        N.n_p2m_jobs_rest = (int)jobs.size();
+        N.p2m_jobs_rest = upload(P, jobs);
         VP_HIP(hipStreamSynchronize(s));  // host vectors leave scope
     }
     VP_HIP(hipStreamSynchronize(s));
