@@ -819,7 +819,7 @@ __global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0
         }
         fetch(i0 + ngrp * R);  // the next rows' extents, in flight with the values
         double v[R][4];
-        int64_t c[R][4];
+        int32_t c[R][4];  // column indices (< 2^31, the f length)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t a0 = p0[r] & ~(int64_t)1;
@@ -832,8 +832,8 @@ __global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0
                     const int64_t qi = 2 * pi + e;
                     const bool in = qi >= p0[r] && qi < p1[r];
                     v[r][2 * u + e] = w[e] * (in ? 1.0 : 0.0);
-                    c[r][2 * u + e] = RUNS ? (in ? (int64_t)rs[r] + (qi - p0[r]) : (int64_t)0)
-                                           : (in ? (int64_t)colv[min(qi, nnz - 1)] : (int64_t)0);
+                    c[r][2 * u + e] = RUNS ? (in ? rs[r] + (int32_t)(qi - p0[r]) : 0)
+                                           : (in ? colv[min(qi, nnz - 1)] : 0);
                 }
             }
         }
@@ -861,8 +861,8 @@ __global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0
                         const int64_t qi = 2 * pi + e;
                         const bool in = qi < p1[r];
                         const double vv = w[e] * (in ? 1.0 : 0.0);
-                        const int64_t cc = RUNS ? (in ? (int64_t)rs[r] + (qi - p0[r]) : (int64_t)0)
-                                                : (in ? (int64_t)colv[min(qi, nnz - 1)] : (int64_t)0);
+                        const int32_t cc = RUNS ? (in ? rs[r] + (int32_t)(qi - p0[r]) : 0)
+                                                : (in ? colv[min(qi, nnz - 1)] : 0);
 #pragma unroll
                         for (int k = 0; k < NBG; ++k)
                             part[r][k] = fma(vv, f[(int64_t)(bt0 + min(k, nbg - 1)) * flen + cc], part[r][k]);
