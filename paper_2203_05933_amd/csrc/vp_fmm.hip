@@ -893,6 +893,79 @@ __global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0
     }
 }
 
+// The correction apply for a matrix made of cells (consecutive rows sharing
+// one column run of at most 64): one wave per cell, lane = column, so a row
+// is one contiguous 8-byte-per-lane load and the cell's densities stay in
+// registers (no per-value gather of f).  R rows are loaded together; their
+// sums across the 64 lanes use a butterfly: at each step a lane keeps half
+// of its rows and adds its partner's share of them, then the remaining
+// lanes of each row are summed (a fixed order: deterministic).
+template <int NBG>
+__global__ void __launch_bounds__(256) k_corr_cells(int ncell, const int32_t *__restrict__ cell_row,
+                                                    const int32_t *__restrict__ cell_col, int nbatch, int bt0,
+                                                    const int64_t *__restrict__ rowptr,
+                                                    const double *__restrict__ valv,
+                                                    const double *__restrict__ f, int64_t flen, int64_t nrows,
+                                                    double *__restrict__ out) {
+    constexpr int R = NBG == 1 ? 4 : (NBG == 2 ? 2 : 1);  // rows per batch (R x NBG sums in registers)
+    const int lane = threadIdx.x & 63;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int nbg = min(NBG, nbatch - bt0);
+    for (int64_t cc = w; cc < ncell; cc += nw) {
+        const int r0 = cell_row[cc], r1 = cell_row[cc + 1], c0 = cell_col[cc];
+        const int64_t vb = rowptr[r0];
+        const int len = (int)(rowptr[r0 + 1] - vb);
+        const bool inc = lane < len;
+        double fc[NBG];
+#pragma unroll
+        for (int k = 0; k < NBG; ++k)
+            fc[k] = inc ? f[(int64_t)(bt0 + min(k, nbg - 1)) * flen + c0 + lane] : 0.0;
+        for (int i = r0; i < r1; i += R) {
+            double p[NBG][R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int row = min(i + r, r1 - 1);
+                const double v =
+                    __builtin_nontemporal_load(valv + vb + (int64_t)(row - r0) * len + (inc ? lane : 0));
+#pragma unroll
+                for (int k = 0; k < NBG; ++k) p[k][r] = v * fc[k];  // fc is zero past the run
+            }
+#pragma unroll
+            for (int k = 0; k < NBG; ++k) {
+                int m = R;
+#pragma unroll
+                for (int b = 0; (1 << b) < R; ++b) {
+                    const int bit = 32 >> b;
+                    const bool hi = (lane & bit) != 0;
+                    m >>= 1;
+#pragma unroll
+                    for (int j = 0; j < R / 2; ++j) {
+                        if (j < m) {
+                            const double keep = hi ? p[k][m + j] : p[k][j];
+                            const double give = hi ? p[k][j] : p[k][m + j];
+                            p[k][j] = keep + __shfl_xor(give, bit, 64);
+                        }
+                    }
+                }
+                double t = p[k][0];
+#pragma unroll
+                for (int bit = 32 / R; bit >= 1; bit >>= 1) t += __shfl_xor(t, bit, 64);
+                p[k][0] = t;
+            }
+            // lane's row: lane bits 5, 4, .. (one per butterfly step), high bit first
+            int rr = 0;
+#pragma unroll
+            for (int b = 0; (1 << b) < R; ++b) rr = rr * 2 + ((lane >> (5 - b)) & 1);
+            if ((lane & (64 / R - 1)) == 0 && i + rr < r1) {
+#pragma unroll
+                for (int k = 0; k < NBG; ++k)
+                    if (k < nbg) out[(int64_t)(bt0 + k) * nrows + i + rr] = p[k][0];
+            }
+        }
+    }
+}
+
 // out[b][i] += scale_i * (acc[b][inv[i]] + acc2[b][inv[i]]): the near- and
 // far-field sums (sorted order; acc2 may be null) added to the correction
 // already in out (user order)
@@ -927,6 +1000,8 @@ __global__ void k_detect_runs(const int64_t *__restrict__ rowptr, const int32_t 
     run_start[i] = run ? c0 : -1;
 }
 
+void build_cells(vp_plan_s *P, bool transposed);
+
 void detect_runs(vp_plan_s *P) {
     hipStream_t s = P->stream;
     P->run_start = P->mem.alloc<int32_t>(P->m);
@@ -944,6 +1019,46 @@ void detect_runs(vp_plan_s *P) {
     VP_HIP(hipMemcpyAsync(h.data(), P->run_startT, 4 * P->n, hipMemcpyDeviceToHost, s));
     VP_HIP(hipStreamSynchronize(s));
     P->all_runsT = std::all_of(h.begin(), h.begin() + P->n, [](int32_t v) { return v >= 0; });
+    build_cells(P, false);
+    build_cells(P, true);
+}
+
+// Cells of a run-structured matrix: maximal groups of consecutive rows whose
+// columns are the same run of at most 64 (a cell's own nodes, for the
+// own-cell corrections of Section 4).  Used when the cells average at least
+// 8 rows; otherwise (or when some row is not such a run) the row kernel
+// applies the matrix.
+void build_cells(vp_plan_s *P, bool transposed) {
+    hipStream_t s = P->stream;
+    const int64_t nrows = transposed ? P->n : P->m;
+    const bool runs = transposed ? P->all_runsT : P->all_runs;
+    int32_t *&cell_row = transposed ? P->cell_rowT : P->cell_row;
+    int32_t *&cell_col = transposed ? P->cell_colT : P->cell_col;
+    int &ncell = transposed ? P->ncellT : P->ncell;
+    ncell = 0;
+    if (!runs || P->nnz == 0 || nrows >= (int64_t)1 << 31) return;
+    std::vector<int64_t> rp(nrows + 1);
+    std::vector<int32_t> rs(nrows);
+    VP_HIP(hipMemcpyAsync(rp.data(), transposed ? P->rowptrT : P->rowptr, 8 * (nrows + 1), hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(rs.data(), transposed ? P->run_startT : P->run_start, 4 * nrows, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> row0, col0;
+    for (int64_t i = 0; i < nrows; ++i) {
+        const int64_t len = rp[i + 1] - rp[i];
+        if (len > 64) return;
+        if (i == 0 || rs[i] != rs[i - 1] || len != rp[i] - rp[i - 1]) {
+            row0.push_back((int32_t)i);
+            col0.push_back(rs[i]);
+        }
+    }
+    if ((int64_t)row0.size() * 8 > nrows) return;
+    row0.push_back((int32_t)nrows);
+    cell_row = P->mem.alloc<int32_t>(row0.size());
+    cell_col = P->mem.alloc<int32_t>(col0.size());
+    VP_HIP(hipMemcpyAsync(cell_row, row0.data(), 4 * row0.size(), hipMemcpyHostToDevice, s));
+    VP_HIP(hipMemcpyAsync(cell_col, col0.data(), 4 * col0.size(), hipMemcpyHostToDevice, s));
+    VP_HIP(hipStreamSynchronize(s));  // host vectors leave scope
+    ncell = (int)col0.size();
 }
 
 __global__ void k_unpermute_grad(int64_t m, int nbatch, const int32_t *__restrict__ inv,
@@ -1800,9 +1915,29 @@ static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjo
     const int64_t flen = adjoint ? P->m : P->n;
     int64_t blocks = (nrows * 16 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
+    const int ncell = adjoint ? P->ncellT : P->ncell;
     P->stage_begin(VP_STAGE_CORR);
     if (P->nnz == 0) {
         fill_f64(u, 0.0, (int64_t)P->nbatch * nrows, P->stream);
+    } else if (ncell > 0) {
+        const int32_t *crow = adjoint ? P->cell_rowT : P->cell_row;
+        const int32_t *ccol = adjoint ? P->cell_colT : P->cell_col;
+        const unsigned cblocks = (unsigned)std::min<int64_t>((ncell + 3) / 4, 16384);
+        for (int bt0 = 0; bt0 < P->nbatch;) {
+            const int left = P->nbatch - bt0;
+            const int g = left >= 16 ? 16 : (left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1)));
+            switch (g) {
+#define VP_CELLS(G)                                                                                              \
+    case G:                                                                                                      \
+        hipLaunchKernelGGL((k_corr_cells<G>), dim3(cblocks), dim3(256), 0, P->stream, ncell, crow, ccol,         \
+                           P->nbatch, bt0, rp, vv, f, flen, nrows, u);                                           \
+        break;
+                VP_CELLS(16) VP_CELLS(8) VP_CELLS(4) VP_CELLS(2) VP_CELLS(1)
+#undef VP_CELLS
+            }
+            VP_LAUNCH_CHECK();
+            bt0 += g;
+        }
     } else {
         for (int bt0 = 0; bt0 < P->nbatch;) {
             const int left = P->nbatch - bt0;

@@ -273,6 +273,10 @@ struct vp_plan_s {
     int32_t *run_start = nullptr;   // per row: first column of a contiguous run, or -1
     bool all_runs = false, all_runsT = false;  // every row (of C, of C^T) is a run
     int32_t *run_startT = nullptr;
+    // cells (consecutive rows sharing one column run of <= 64): [ncell + 1]
+    // first rows, [ncell] first columns; ncell = 0: the row kernel applies C
+    int32_t *cell_row = nullptr, *cell_col = nullptr, *cell_rowT = nullptr, *cell_colT = nullptr;
+    int ncell = 0, ncellT = 0;
 
     vp::Tree tree;
     vp::Operators ops;

@@ -323,6 +323,42 @@ def test_correction_general_csr(nbatch):
     plan.close()
 
 
+@pytest.mark.parametrize("nbatch", [1, 3, 16])
+def test_correction_cells(nbatch):
+    """A block-diagonal correction (cells of 1 to 64 nodes, each row's columns
+    its own cell's nodes, plus a few empty rows), which the plan applies
+    cell by cell in both directions; forward and adjoint against the oracle."""
+    vp = _vp()
+    rng = np.random.default_rng(31 + nbatch)
+    sizes = rng.integers(1, 65, 40)
+    n = int(sizes.sum())
+    x = rng.uniform(-1, 1, n)
+    y = rng.uniform(-1, 1, n)
+    w = rng.uniform(0.1, 1, n) / n
+    lens, cols, start = [], [], 0
+    for k, sz in enumerate(sizes):
+        empty = k % 9 == 4  # a cell whose rows have no entries
+        for _ in range(sz):
+            lens.append(0 if empty else sz)
+            if not empty:
+                cols.extend(range(start, start + sz))
+        start += sz
+    rowptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.asarray(cols, dtype=np.int32)
+    val = rng.standard_normal(col.size)
+    f = rng.standard_normal((nbatch, n))
+    plan = vp.Plan(x, y, w, rowptr=rowptr, col=col, val=val, order=30, max_leaf=32, nbatch=nbatch,
+                   root=(-1.0, -1.0, 2.0))
+    u = _host(plan.eval(_dev(f)))
+    ref = direct.evaluate(x, y, w, f, rowptr, col, val)
+    assert max(relinf(u[b], ref[b]) for b in range(nbatch)) <= TOL64
+    g = rng.standard_normal((nbatch, n))
+    d = _host(plan.eval_adjoint(_dev(g)))
+    dref = direct.evaluate_adjoint(x, y, w, g, rowptr, col, val)
+    assert max(relinf(d[b], dref[b]) for b in range(nbatch)) <= TOL64
+    plan.close()
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65])
 def test_small_inputs(n):
     vp = _vp()
