@@ -210,13 +210,17 @@ __global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_
 // level.  Every child column is scaled by tin[class][k], multiplied by the
 // real matrix Q (shared by all classes; read transposed so a wave's loads are
 // contiguous), scaled by tout[class][l] and summed.  A lane owns output row l
-// of one group of children; with P <= 32 the wave's halves (quarters for
-// P <= 16) take alternate children and are added through LDS in a fixed order.
+// of one group of quadrants; with P <= 32 the wave's halves (quarters for
+// P <= 16) take alternate quadrants and are added through LDS in a fixed
+// order.  The children come from a plan-time table [parent][quadrant] (the
+// quadrant is the child's class), so the child columns load one round trip
+// after the launch-list entry.
 // ----------------------------------------------------------------------------
 template <class E, int PR>
-__global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, int nbatch, int P, int PD,
-                                            BoxGeo G, const E *__restrict__ QT, const E *__restrict__ tin,
-                                            const E *__restrict__ tout, E *__restrict__ X) {
+__global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, const int4 *__restrict__ cslot,
+                                            int nbatch, int P, int PD, const E *__restrict__ QT,
+                                            const E *__restrict__ tin, const E *__restrict__ tout,
+                                            E *__restrict__ X) {
     constexpr int H = 64 / PR;       // row groups in the wave
     __shared__ E ys[4][PR][2];       // scaled child columns (re, im interleaved)
     __shared__ E red[H][PR][2];      // per-group partial rows
@@ -226,15 +230,17 @@ __global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, i
 #pragma unroll
     for (int k = 0; k < PR; ++k) qc[k] = (k < P && l < P) ? QT[k * PR + l] : (E)0;
     const int b = boxes[blockIdx.x];
-    const int nsrc = G.nchild[b], c0 = G.child[b];
+    const int4 cs = cslot[blockIdx.x];
+    auto child = [&](int c) { return c == 0 ? cs.x : (c == 1 ? cs.y : (c == 2 ? cs.z : cs.w)); };
     for (int bt = 0; bt < nbatch; ++bt) {
-        for (int c = gi; c < nsrc; c += H) {
-            const int ch = c0 + c, cls = (G.ix[ch] & 1) | ((G.iy[ch] & 1) << 1);
+#pragma unroll
+        for (int j = 0; j < 4 / H; ++j) {
+            const int c = gi + H * j, ch = child(c);
             E yr = (E)0, yi = (E)0;
-            if (l < P) {
+            if (l < P && ch >= 0) {
                 const E *x = X + ((int64_t)ch * nbatch + bt) * PD;
                 const E xr = x[l], xi = x[P + l];
-                const E wr = tin[(cls * P + l) * 2], wi = tin[(cls * P + l) * 2 + 1];
+                const E wr = tin[(c * P + l) * 2], wi = tin[(c * P + l) * 2 + 1];
                 yr = xr * wr - xi * wi;
                 yi = xr * wi + xi * wr;
             }
@@ -243,8 +249,10 @@ __global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, i
         }
         __syncthreads();
         E br = (E)0, bi = (E)0;
-        for (int c = gi; c < nsrc; c += H) {
-            const int ch = c0 + c, cls = (G.ix[ch] & 1) | ((G.iy[ch] & 1) << 1);
+#pragma unroll
+        for (int j = 0; j < 4 / H; ++j) {
+            const int c = gi + H * j;
+            if (child(c) < 0) continue;
             E zr = (E)0, zi = (E)0;
 #pragma unroll
             for (int k = 0; k < PR; ++k) {
@@ -252,7 +260,7 @@ __global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, i
                 zi += qc[k] * ys[c][k][1];
             }
             if (l < P) {
-                const E vr = tout[(cls * P + l) * 2], vi = tout[(cls * P + l) * 2 + 1];
+                const E vr = tout[(c * P + l) * 2], vi = tout[(c * P + l) * 2 + 1];
                 br += zr * vr - zi * vi;
                 bi += zr * vi + zi * vr;
             }
@@ -281,10 +289,12 @@ __global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, i
 
 // L2L in the same scaled form (Q upper triangular), one target box per row
 // group: a wave serves 64 / PR boxes of a level, each row group staging its
-// own parent column.
+// own parent column.  The launch list carries parent * 4 + class beside each
+// box, so the parent column, the box's own column and the scalings all load
+// one round trip after the list entry.
 template <class E, int PR>
-__global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, int nboxes, int nbatch, int P,
-                                            int PD, BoxGeo G, const E *__restrict__ QT,
+__global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, const int32_t *__restrict__ pcls,
+                                            int nboxes, int nbatch, int P, int PD, const E *__restrict__ QT,
                                             const E *__restrict__ tin, const E *__restrict__ tout,
                                             E *__restrict__ X) {
     constexpr int H = 64 / PR;
@@ -297,8 +307,8 @@ __global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, i
     const int idx = blockIdx.x * H + gi;
     const bool act = idx < nboxes;
     const int b = act ? boxes[idx] : 0;
-    const int src = act ? G.parent[b] : 0;
-    const int cls = act ? ((G.ix[b] & 1) | ((G.iy[b] & 1) << 1)) : 0;
+    const int pc = act ? pcls[idx] : 0;
+    const int src = pc >> 2, cls = pc & 3;
     const bool row = act && l < P;
     E wr = (E)0, wi = (E)0, vr = (E)0, vi = (E)0;
     if (row) {
@@ -308,10 +318,13 @@ __global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, i
         vi = tout[(cls * P + l) * 2 + 1];
     }
     for (int bt = 0; bt < nbatch; ++bt) {
-        E yr = (E)0, yi = (E)0;
+        E yr = (E)0, yi = (E)0, or_ = (E)0, oi = (E)0;
+        E *o = X + ((int64_t)b * nbatch + bt) * PD;
         if (row) {
             const E *x = X + ((int64_t)src * nbatch + bt) * PD;
             const E xr = x[l], xi = x[P + l];
+            or_ = o[l];
+            oi = o[P + l];
             yr = xr * wr - xi * wi;
             yi = xr * wi + xi * wr;
         }
@@ -325,9 +338,8 @@ __global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, i
             zi += qc[k] * ys[gi][k][1];
         }
         if (row) {
-            E *o = X + ((int64_t)b * nbatch + bt) * PD;
-            o[l] += zr * vr - zi * vi;
-            o[P + l] += zr * vi + zi * vr;
+            o[l] = or_ + (zr * vr - zi * vi);
+            o[P + l] = oi + (zr * vi + zi * vr);
         }
         __syncthreads();
     }
@@ -1141,14 +1153,16 @@ void build_schedules(vp_plan_s *P) {
     P->m2m_begin[T.nlevels] = (int)parents.size();
     P->lvl_boxes = up(lb);
     P->m2m_parents = up(parents);
-    // slot tables: child in each quadrant (M2M); parent in the class slot (L2L)
-    std::vector<int32_t> cs((size_t)nbox * 4, -1), ls((size_t)nbox * 4, -1);
-    for (int b = 0; b < nbox; ++b) {
-        for (int c = chb[b]; nch[b] > 0 && c < chb[b] + nch[b]; ++c) cs[(size_t)b * 4 + cls(c)] = c;
-        if (par[b] >= 0) ls[(size_t)b * 4 + cls(b)] = par[b];
+    // beside the launch lists: each parent's child per quadrant (M2M; the
+    // quadrant is the child's class), each box's parent * 4 + class (L2L)
+    std::vector<int32_t> cs(parents.size() * 4, -1), pcls(lb.size(), 0);
+    for (size_t k = 0; k < parents.size(); ++k) {
+        const int b = parents[k];
+        for (int c = chb[b]; c < chb[b] + nch[b]; ++c) cs[k * 4 + cls(c)] = c;
     }
-    P->child_slot = up(cs);
-    P->l2l_slot = up(ls);
+    for (size_t k = 0; k < lb.size(); ++k) pcls[k] = par[lb[k]] >= 0 ? par[lb[k]] * 4 + cls(lb[k]) : 0;
+    P->m2m_cslot = up(cs);
+    P->lvl_pcls = up(pcls);
     std::vector<int32_t> p2m, xb, wl;
     for (int b = 0; b < nbox; ++b) {
         if (nch[b] == 0 && lev[b] >= 2) p2m.push_back(b);
@@ -1520,8 +1534,8 @@ static void run_m2m(vp_plan_s *P, const BoxGeo &G, int l_hi, int l_lo) {
         switch (O.PR) {
 #define VP_M2M(PR)                                                                                                 \
     case PR:                                                                                                       \
-        hipLaunchKernelGGL((k_m2m<E, PR>), dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0, nb, Pn, PD, G, shq, \
-                           shi, sho, M);                                                                           \
+        hipLaunchKernelGGL((k_m2m<E, PR>), dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0,                   \
+                           reinterpret_cast<const int4 *>(P->m2m_cslot) + c0, nb, Pn, PD, shq, shi, sho, M);       \
         break;
             VP_M2M(16) VP_M2M(32) VP_M2M(64)
 #undef VP_M2M
@@ -1549,8 +1563,8 @@ static void run_l2l(vp_plan_s *P, const BoxGeo &G, int l_lo, int l_hi) {
         switch (O.PR) {
 #define VP_L2L(PR)                                                                                               \
     case PR:                                                                                                     \
-        hipLaunchKernelGGL((k_l2l<E, PR>), dim3(nblk), dim3(64), 0, s, P->lvl_boxes + c0, c1 - c0, nb, Pn, PD, G, \
-                           shq, shi, sho, L);                                                                    \
+        hipLaunchKernelGGL((k_l2l<E, PR>), dim3(nblk), dim3(64), 0, s, P->lvl_boxes + c0, P->lvl_pcls + c0,      \
+                           c1 - c0, nb, Pn, PD, shq, shi, sho, L);                                               \
         break;
             VP_L2L(16) VP_L2L(32) VP_L2L(64)
 #undef VP_L2L

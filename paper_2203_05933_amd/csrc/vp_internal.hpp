@@ -296,8 +296,8 @@ struct vp_plan_s {
     int split_level = 2;
     int64_t m2l_translations = 0, m2l_tile_ops = 0;  // both launches
     int32_t *x_init = nullptr;  // [nbox] 1: P2L writes the local expansion before M2L adds to it
-    int32_t *child_slot = nullptr;   // [nbox][4] child in each quadrant or -1
-    int32_t *l2l_slot = nullptr;     // [nbox][4] parent in the slot of the box's class
+    int32_t *m2m_cslot = nullptr;    // [m2m_parents][4] child in each quadrant or -1
+    int32_t *lvl_pcls = nullptr;     // [lvl_boxes] parent * 4 + class
     int32_t *lvl_boxes = nullptr;  // boxes of each level, grouped by class inside a level (L2L)
     std::vector<int> lvl_box_begin;  // per level offsets into lvl_boxes
     int32_t *m2m_parents = nullptr;  // non-leaf boxes per level
