@@ -417,7 +417,7 @@ __global__ void __launch_bounds__(64) k_p2l(PointRoles R, BoxGeo G, const int32_
 }
 
 // ----------------------------------------------------------------------------
-// L2P + M2P at the targets of one leaf (one wave, lane = target):
+// L2P and/or M2P at the targets of one leaf (one wave, lane = target):
 //   u += -(1/2pi) Re[ sum_l B_l w^l + sum_{a in W} (A_0 log(z - c_a) +
 //                    sum_k A_k (s_a/(z - c_a))^k) ]
 // and, with grad, the gradient -(1/2pi) (Re phi', -Im phi').
@@ -429,9 +429,9 @@ __global__ void __launch_bounds__(256) k_far(PointRoles R, BoxGeo G, const int32
                                              int PD, const E *__restrict__ Mexp,
                                              const E *__restrict__ Lexp,
                                              const int32_t *__restrict__ local_done,
-                                             double *__restrict__ acc) {
-    // Four waves per leaf, all on the same 64 targets: wave 0 evaluates the
-    // local expansion, wave w takes every fourth W-list multipole from the
+                                             double *__restrict__ acc, int parts) {
+    // Up to four waves per leaf, all on the same 64 targets: wave 0 evaluates
+    // the local expansion, wave w takes every nw-th W-list multipole from the
     // w-th on (long W lists of large leaves no longer run on one wave), and
     // the partial sums are added through LDS in a fixed order.  Each wave
     // stages its current coefficient column in its own LDS row (a wave-local
@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(256) k_far(PointRoles R, BoxGeo G, const int32
     constexpr int NR = GRAD ? 2 : 1;
     __shared__ E colw[4][128];
     __shared__ double red[3][NR][64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     E *col = colw[wave];
     const int b = leaves[blockIdx.x];
     const int t0 = R.tb[b], t1 = R.te[b];
@@ -448,8 +448,9 @@ __global__ void __launch_bounds__(256) k_far(PointRoles R, BoxGeo G, const int32
     const double cx = G.cx[b], cy = G.cy[b];
     const int lb = G.level[b];
     const double s = G.side[lb];
-    const bool has_local = wave == 0 && lb >= 2 && !(local_done && local_done[b]);
-    const int w0 = wptr[b], w1 = wptr[b + 1];
+    // parts: bit 0 the local expansion, bit 1 the W list
+    const bool has_local = (parts & 1) && wave == 0 && lb >= 2 && !(local_done && local_done[b]);
+    const int w0 = wptr[b], w1 = (parts & 2) ? wptr[b + 1] : w0;
     for (int base = t0; base < t1; base += 64) {
         const int t = base + lane;
         const bool act = t < t1;
@@ -482,7 +483,7 @@ __global__ void __launch_bounds__(256) k_far(PointRoles R, BoxGeo G, const int32
             }
             double u = (double)phi.re;
             double gx = (double)dphi.re, gy = -(double)dphi.im;
-            for (int e = w0 + wave; e < w1; e += 4) {
+            for (int e = w0 + wave; e < w1; e += nw) {
                 const int a = widx[e];
                 for (int k = lane; k < 2 * P; k += 64) col[k] = Mexp[((int64_t)a * nbatch + bt) * PD + k];
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -519,25 +520,33 @@ __global__ void __launch_bounds__(256) k_far(PointRoles R, BoxGeo G, const int32
                     gy -= nre * iim + nim * ire;
                 }
             }
-            // fixed-order sum of the four waves' partial results
-            __syncthreads();
-            if (wave > 0) {
-                if (GRAD) {
-                    red[wave - 1][0][lane] = gx;
-                    red[wave - 1][1][lane] = gy;
-                } else {
-                    red[wave - 1][0][lane] = u;
+            // fixed-order sum of the waves' partial results (one-wave blocks,
+            // used for local expansions alone, skip it)
+            if (nw > 1) {
+                __syncthreads();
+                if (wave > 0) {
+                    if (GRAD) {
+                        red[wave - 1][0][lane] = gx;
+                        red[wave - 1][1][lane] = gy;
+                    } else {
+                        red[wave - 1][0][lane] = u;
+                    }
                 }
+                __syncthreads();
             }
-            __syncthreads();
             if (wave == 0 && act) {
+                for (int w2 = 1; w2 < nw; ++w2) {
+                    if (GRAD) {
+                        gx += red[w2 - 1][0][lane];
+                        gy += red[w2 - 1][NR - 1][lane];
+                    } else {
+                        u += red[w2 - 1][0][lane];
+                    }
+                }
                 if (GRAD) {
-                    gx = ((gx + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
-                    gy = ((gy + red[0][NR - 1][lane]) + red[1][NR - 1][lane]) + red[2][NR - 1][lane];
                     acc[((int64_t)bt * 2 + 0) * R.ntgt + t] += -INV_2PI * gx;
                     acc[((int64_t)bt * 2 + 1) * R.ntgt + t] += -INV_2PI * gy;
                 } else {
-                    u = ((u + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
                     acc[(int64_t)bt * R.ntgt + t] += -INV_2PI * u;
                 }
             }
@@ -1168,6 +1177,8 @@ void build_schedules(vp_plan_s *P) {
         if (nch[b] == 0 && lev[b] >= 2) p2m.push_back(b);
         if (nch[b] == 0 && wp[b + 1] > wp[b]) wl.push_back(b);
     }
+    // longest W lists first (they run in their own launch)
+    std::stable_sort(wl.begin(), wl.end(), [&](int x, int y) { return wp[x + 1] - wp[x] > wp[y + 1] - wp[y]; });
 
     // X list, one level apart: the source leaf a (level l-1) splits into four
     // virtual children on the target's level l.  None of them is adjacent to
@@ -1742,25 +1753,36 @@ static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind, double *
 }
 
 template <class E, bool GRAD>
-static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *acc, bool tables) {
+static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *acc, bool tables, int parts) {
+    // parts: bit 0 the local expansions at the targets (L2P), bit 1 the W lists (M2P)
     Tree &T = P->tree;
     NearTables &N = P->near;
-    P->stage_begin(VP_STAGE_FAR);
-    if (tables) {
-        run_pattern_op<E>(P, R, PAT_L2P, acc);
-        if (N.n_far_leaves > 0) {
-            hipLaunchKernelGGL((k_far<E, GRAD>), dim3(N.n_far_leaves), dim3(256), 0, P->stream, R, G, N.far_leaves,
-                               T.lptr[2], T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp,
-                               (const E *)P->Lexp, N.local_done, acc);
-            VP_LAUNCH_CHECK();
+    auto far = [&](const int32_t *leaves, int nleaves, const int32_t *done, int pt) {
+        if (nleaves <= 0) return;
+        // four waves share a leaf's W list; local expansions alone take one wave
+        const unsigned threads = pt == 1 ? 64 : 256;
+        hipLaunchKernelGGL((k_far<E, GRAD>), dim3(nleaves), dim3(threads), 0, P->stream, R, G, leaves, T.lptr[2],
+                           T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp, (const E *)P->Lexp, done, acc, pt);
+        VP_LAUNCH_CHECK();
+    };
+    if (parts == 3) {
+        // both in one launch per leaf
+        if (tables) {
+            run_pattern_op<E>(P, R, PAT_L2P, acc);
+            far(N.far_leaves, N.n_far_leaves, N.local_done, 3);
+        } else {
+            far(T.leaves, T.nleaf, nullptr, 3);
+        }
+    } else if (parts == 1) {
+        if (tables) {
+            run_pattern_op<E>(P, R, PAT_L2P, acc);
+            far(N.l2p_rest, N.n_l2p_rest, nullptr, 1);
+        } else {
+            far(T.leaves, T.nleaf, nullptr, 1);
         }
     } else {
-        hipLaunchKernelGGL((k_far<E, GRAD>), dim3(T.nleaf), dim3(256), 0, P->stream, R, G, T.leaves, T.lptr[2],
-                           T.lidx[2], P->nbatch, P->P, P->PD, (const E *)P->Mexp, (const E *)P->Lexp,
-                           (const int32_t *)nullptr, acc);
-        VP_LAUNCH_CHECK();
+        far(P->w_leaves, P->n_w_leaves, nullptr, 2);
     }
-    P->stage_end(VP_STAGE_FAR);
 }
 
 static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjoint);
@@ -1769,14 +1791,15 @@ static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint);
 // One evaluation on three streams (default priority; with VP_FLAG_ONE_STREAM
 // everything runs on the plan's stream in the order written here):
 //   third stream: VALU P2M, P2L | wait(upper) M2M, M2L, L2L of the levels
-//                 below the split
+//                 below the split, W lists at the targets (M2P)
 //   second stream: correction C f, near tables, pairwise near field
 //   plan's stream: fixed-matrix P2M | wait(VALU P2M) M2M from the finest
 //                  level to the split level |
 //                  wait(P2L) M2L of the levels from the split on | wait(coarse)
-//                  L2L from the split level down, far field | wait(near) finish
-// (the far field writes its own array; with gradients it waits for the near
-// field and adds to it)
+//                  L2L from the split level down | wait(M2P) local expansions
+//                  at the targets | wait(near) finish
+// (the far field writes its own array; with gradients it runs whole on the
+// plan's stream after the near field and adds to it)
 template <class E>
 static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool adjoint, bool grad, const double *f,
                        double *u) {
@@ -1864,19 +1887,31 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         run_m2m<E>(P, G, Lmax - 1, L0);
         P->stage_end(VP_STAGE_M2M);
     }
-    if (coarse) {
-        // third stream: the levels below the split, upward, M2L and downward
+    // the W lists (M2P) need every multipole: after the upward pass; they go
+    // on the third stream too (not with gradients, whose far field adds to the
+    // near-field array)
+    const bool w_apart = fmm && !grad;
+    if (coarse || w_apart) {
         if (!one) {
             VP_HIP(hipEventRecord(P->ev_upper, ms));
             VP_HIP(hipStreamWaitEvent(s3, P->ev_upper, 0));
         }
         P->stream = s3;
-        P->stage_begin(VP_STAGE_COARSE);
-        run_m2m<E>(P, G, L0 - 1, 2);
-        launch_m2l<E>(P, 1);
-        run_l2l<E>(P, G, 3, L0 - 1);
-        P->stage_end(VP_STAGE_COARSE);
-        if (!one) VP_HIP(hipEventRecord(P->ev_coarse, s3));
+        if (coarse) {
+            // the levels below the split, upward, M2L and downward
+            P->stage_begin(VP_STAGE_COARSE);
+            run_m2m<E>(P, G, L0 - 1, 2);
+            launch_m2l<E>(P, 1);
+            run_l2l<E>(P, G, 3, L0 - 1);
+            P->stage_end(VP_STAGE_COARSE);
+            if (!one) VP_HIP(hipEventRecord(P->ev_coarse, s3));
+        }
+        if (w_apart) {
+            P->stage_begin(VP_STAGE_M2P);
+            run_far<E, false>(P, R, G, P->acc_far, tables, 2);
+            P->stage_end(VP_STAGE_M2P);
+            if (!one) VP_HIP(hipEventRecord(P->ev_m2p, s3));
+        }
         P->stream = ms;
     }
     if (fmm) {
@@ -1899,14 +1934,18 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         run_l2l<E>(P, G, L0, Lmax);
         P->stage_end(VP_STAGE_L2L);
     }
+    P->stage_begin(VP_STAGE_FAR);
     if (grad) {
         // the gradient sums go into the near-field array
         if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_join, 0));
-        if (fmm) run_far<E, true>(P, R, G, P->acc, false);
+        if (fmm) run_far<E, true>(P, R, G, P->acc, false, 3);
     } else {
-        if (fmm) run_far<E, false>(P, R, G, P->acc_far, tables);
+        // local expansions at the targets, after the W lists (same array)
+        if (fmm && !one) VP_HIP(hipStreamWaitEvent(ms, P->ev_m2p, 0));
+        if (fmm) run_far<E, false>(P, R, G, P->acc_far, tables, 1);
         if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_join, 0));
     }
+    P->stage_end(VP_STAGE_FAR);
     if (u) add_fmm_sums(P, u, adjoint);
 }
 

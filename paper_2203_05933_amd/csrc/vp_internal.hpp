@@ -219,6 +219,8 @@ struct NearTables {
     int n_l2p_pat = 0;
     int32_t *far_leaves = nullptr;    // leaves needing the series far-field kernel
     int n_far_leaves = 0;
+    int32_t *l2p_rest = nullptr;      // leaves (level >= 2) whose local expansion is evaluated by the series
+    int n_l2p_rest = 0;
     int32_t *local_done = nullptr;    // [nbox] 1: local expansion evaluated by the L2P operator
     // [5][PD x npat] A-fragment order: the leaf P2M, then the four quadrant
     // P2M matrices (about the quadrant centre at the children's scale, zero
@@ -249,7 +251,8 @@ struct vp_plan_s {
     // split_level (few boxes, latency bound) beside the M2L of the levels above
     hipStream_t aux2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_p2m = nullptr, ev_p2l = nullptr, ev_upper = nullptr, ev_coarse = nullptr, ev_m2l = nullptr;
+    hipEvent_t ev_p2m = nullptr, ev_p2l = nullptr, ev_upper = nullptr, ev_coarse = nullptr, ev_m2l = nullptr,
+               ev_m2p = nullptr;
     int device = 0;
     std::string err;
     bool poisoned = false;

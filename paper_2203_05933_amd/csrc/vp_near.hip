@@ -274,6 +274,8 @@ void build_near_tables(vp_plan_s *P) {
         if (!(pt && lev[b] >= 2) || wptr[b + 1] > wptr[b]) far_leaves.push_back(b);
     }
     N.l2p_pat = upload(P, l2p_pat);
+    N.l2p_rest = upload(P, p2m_rest);  // the non-pattern leaves of level >= 2
+    N.n_l2p_rest = (int)p2m_rest.size();
     N.n_l2p_pat = (int)l2p_pat.size();
     std::stable_sort(far_leaves.begin(), far_leaves.end(),
                      [&](int x, int y) { return wptr[x + 1] - wptr[x] > wptr[y + 1] - wptr[y]; });

@@ -36,7 +36,7 @@ _ARR_DTYPE = {0: np.int32, 1: np.int32, 2: np.int32, 3: np.int32, 4: np.int32, 5
 EXPORTS = ("vp_default_options", "vp_plan", "vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets",
            "vp_set_stream", "vp_destroy", "vp_last_error", "vp_get_info", "vp_get_array",
            "vp_set_timing", "vp_get_timing")
-STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish", "tables", "corr", "coarse", "p2m_pat")
+STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish", "tables", "corr", "coarse", "p2m_pat", "m2p")
 
 
 class VPError(RuntimeError):
