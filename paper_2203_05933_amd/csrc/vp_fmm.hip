@@ -168,41 +168,20 @@ __device__ inline void p2m_range(const PointRoles &R, int s0, int s1, double cx,
     }
 }
 
-// VALU P2M, one wave per job: a leaf b (job >= 0), about its centre at its
-// scale; or (job = ~(4 v + quadrant)) a virtual child of X-list source leaf
-// v: the quadrant's sources about the quadrant centre at the children's scale.
+// VALU P2M, one wave per job (a leaf about its centre at its scale, or the
+// quadrant of an X-list source leaf about the quadrant centre at the
+// children's scale), from a plan-time descriptor.
 template <class E>
-__global__ void __launch_bounds__(64) k_p2m(PointRoles R, BoxGeo G, const int32_t *__restrict__ jobs,
-                                            const int32_t *__restrict__ vleaf, const int32_t *__restrict__ vsplit,
-                                            int nbox, const double *__restrict__ q, int nbatch, int P, int PD,
+__global__ void __launch_bounds__(64) k_p2m(PointRoles R, const P2MJob *__restrict__ jobs,
+                                            const double *__restrict__ q, int nbatch, int P, int PD,
                                             const E *__restrict__ invk, E *__restrict__ Mexp) {
     extern __shared__ unsigned char smem[];
     E *Wre = reinterpret_cast<E *>(smem);   // [16][P]
     E *Wim = Wre + 16 * P;                  // [16][P]
     __shared__ E sq[16][16];                // charges of the chunk [density][source]
-    const int j = jobs[blockIdx.x];
-    int s0, s1, col;
-    double cx, cy, inv_s;
-    if (j >= 0) {
-        s0 = R.sb[j];
-        s1 = R.se[j];
-        cx = G.cx[j];
-        cy = G.cy[j];
-        inv_s = 1.0 / G.side[G.level[j]];
-        col = j;
-    } else {
-        const int vq = ~j, v = vq >> 2, qd = vq & 3;
-        const int a = vleaf[v];
-        const double h = G.side[G.level[a]];
-        cx = G.cx[a] + ((qd & 1) ? 0.25 : -0.25) * h;
-        cy = G.cy[a] + ((qd >> 1) ? 0.25 : -0.25) * h;
-        s0 = vsplit[5 * v + qd];
-        s1 = vsplit[5 * v + qd + 1];
-        inv_s = 2.0 / h;
-        col = nbox + vq;
-    }
-    p2m_range<E>(R, s0, s1, cx, cy, inv_s, q, nbatch, P, PD, invk, Mexp + (int64_t)col * nbatch * PD, Wre, Wim,
-                 sq);
+    const P2MJob jb = jobs[blockIdx.x];
+    p2m_range<E>(R, jb.s0, jb.s1, jb.cx, jb.cy, jb.inv_s, q, nbatch, P, PD, invk,
+                 Mexp + (int64_t)jb.col * nbatch * PD, Wre, Wim, sq);
 }
 
 // ----------------------------------------------------------------------------
@@ -1095,6 +1074,49 @@ __global__ void k_unpermute_grad(int64_t m, int nbatch, const int32_t *__restric
 // ----------------------------------------------------------------------------
 // Schedules (plan time): box groups for each pass.
 // ----------------------------------------------------------------------------
+std::vector<P2MJob> p2m_job_descs(vp_plan_s *P, const std::vector<int32_t> &codes, bool target_role) {
+    Tree &T = P->tree;
+    hipStream_t s = P->stream;
+    const int nbox = T.nbox, nv = P->n_vleaf;
+    std::vector<int32_t> lev(nbox), b0(nbox), b1(nbox), vl(nv), vs(5 * (size_t)nv);
+    std::vector<double> cx(nbox), cy(nbox);
+    VP_HIP(hipMemcpyAsync(lev.data(), T.level, 4 * (size_t)nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(b0.data(), target_role ? T.tb : T.sb, 4 * (size_t)nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(b1.data(), target_role ? T.te : T.se, 4 * (size_t)nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(cx.data(), T.cx, 8 * (size_t)nbox, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(cy.data(), T.cy, 8 * (size_t)nbox, hipMemcpyDeviceToHost, s));
+    if (nv > 0) {
+        VP_HIP(hipMemcpyAsync(vl.data(), P->vleaf, 4 * (size_t)nv, hipMemcpyDeviceToHost, s));
+        VP_HIP(hipMemcpyAsync(vs.data(), target_role ? P->vsplit_t : P->vsplit_s, 4 * vs.size(),
+                              hipMemcpyDeviceToHost, s));
+    }
+    VP_HIP(hipStreamSynchronize(s));
+    std::vector<P2MJob> out(codes.size());
+    for (size_t i = 0; i < codes.size(); ++i) {
+        const int c = codes[i];
+        P2MJob &j = out[i];
+        j.pad = 0;
+        if (c >= 0) {
+            j.cx = cx[c];
+            j.cy = cy[c];
+            j.inv_s = 1.0 / T.side[lev[c]];
+            j.s0 = b0[c];
+            j.s1 = b1[c];
+            j.col = c;
+        } else {
+            const int vq = ~c, v = vq >> 2, qd = vq & 3, a = vl[v];
+            const double h = T.side[lev[a]];
+            j.cx = cx[a] + ((qd & 1) ? 0.25 : -0.25) * h;
+            j.cy = cy[a] + ((qd >> 1) ? 0.25 : -0.25) * h;
+            j.inv_s = 2.0 / h;
+            j.s0 = vs[5 * (size_t)v + qd];
+            j.s1 = vs[5 * (size_t)v + qd + 1];
+            j.col = nbox + vq;
+        }
+    }
+    return out;
+}
+
 std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr) {
     const int nt = (int)tile_ptr.size() - 1;
     std::vector<int32_t> ord(std::max(nt, 0));
@@ -1252,7 +1274,6 @@ void build_schedules(vp_plan_s *P) {
     for (int v = 0; v < (int)vleaf.size(); ++v)
         for (int qd = 0; qd < 4; ++qd) p2m_jobs.push_back(~(4 * v + qd));
     P->n_p2m_jobs = (int)p2m_jobs.size();
-    P->p2m_jobs = up(p2m_jobs);
     P->vsplit_s = up(vsplit_s);
     P->vsplit_t = up(vsplit_t);
     VP_HIP(hipMemcpyAsync(T.v_slot, vslot.data(), 4 * vslot.size(), hipMemcpyHostToDevice, s));
@@ -1305,6 +1326,18 @@ void build_schedules(vp_plan_s *P) {
         P->m2l_translations += S.translations;
         P->m2l_tile_ops += S.tile_ops;
         VP_HIP(hipStreamSynchronize(s));  // the host vectors leave scope
+    }
+    {
+        // VALU P2M descriptors (the virtual-children tables are on the device now)
+        VP_HIP(hipStreamSynchronize(s));
+        const std::vector<P2MJob> ds = p2m_job_descs(P, p2m_jobs, false), dt = p2m_job_descs(P, p2m_jobs, true);
+        P->p2m_jobs = P->mem.alloc<P2MJob>(ds.size());
+        P->p2m_jobs_t = P->mem.alloc<P2MJob>(dt.size());
+        if (!ds.empty()) {
+            VP_HIP(hipMemcpyAsync(P->p2m_jobs, ds.data(), sizeof(P2MJob) * ds.size(), hipMemcpyHostToDevice, s));
+            VP_HIP(hipMemcpyAsync(P->p2m_jobs_t, dt.data(), sizeof(P2MJob) * dt.size(), hipMemcpyHostToDevice, s));
+        }
+        VP_HIP(hipStreamSynchronize(s));  // ds, dt leave scope
     }
     P->xr_ptr = up(xr_ptr);
     P->xr_idx = up(xr_idx);
@@ -1519,12 +1552,11 @@ static void run_p2m(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool tab
     const bool f32 = sizeof(E) == 4;
     const E *invk = f32 ? (const E *)P->ops.inv_k_f32 : (const E *)P->ops.inv_k;
     const size_t lds = sizeof(E) * 2 * 16 * Pn;
-    const int32_t *jobs = tables ? P->near.p2m_jobs_rest : P->p2m_jobs;
+    const P2MJob *jobs = tables ? P->near.p2m_jobs_rest : (R.sb == T.sb ? P->p2m_jobs : P->p2m_jobs_t);
     const int njobs = tables ? P->near.n_p2m_jobs_rest : P->n_p2m_jobs;
     if (njobs <= 0) return;
-    const int32_t *split = R.sb == T.sb ? P->vsplit_s : P->vsplit_t;
-    hipLaunchKernelGGL(k_p2m<E>, dim3(njobs), dim3(64), lds, P->stream, R, G, jobs, P->vleaf, split, T.nbox, P->q,
-                       nb, Pn, PD, invk, static_cast<E *>(P->Mexp));
+    hipLaunchKernelGGL(k_p2m<E>, dim3(njobs), dim3(64), lds, P->stream, R, jobs, P->q, nb, Pn, PD, invk,
+                       static_cast<E *>(P->Mexp));
     VP_LAUNCH_CHECK();
 }
 

@@ -173,6 +173,13 @@ struct P2PGather {
     int64_t len = 0;
 };
 
+// One VALU P2M job: sources [s0, s1) (sorted order) about (cx, cy) at scale
+// 1 / inv_s into expansion column col (a leaf, or a virtual child nbox + 4 v + q).
+struct P2MJob {
+    double cx, cy, inv_s;
+    int32_t s0, s1, col, pad;
+};
+
 // One M2L launch over the boxes of a range of levels: (box, density)
 // columns in 16-column tiles, with the offsets present in each tile and each
 // column's source box per offset.
@@ -213,7 +220,7 @@ struct NearTables {
     int32_t *p2m_cols = nullptr;
     int n_p2m_cols = 0;
     int32_t *p2m_slot = nullptr;      // [nbox + 4 n_vleaf][5] source leaf in the column's operator slot, or -1
-    int32_t *p2m_jobs_rest = nullptr; // VALU P2M jobs of the rest (as vp_plan_s::p2m_jobs)
+    P2MJob *p2m_jobs_rest = nullptr;  // VALU P2M jobs of the rest (source role)
     int n_p2m_jobs_rest = 0;
     int32_t *l2p_pat = nullptr;       // pattern target leaves (level >= 2)
     int n_l2p_pat = 0;
@@ -305,7 +312,9 @@ struct vp_plan_s {
     std::vector<int> lvl_box_begin;  // per level offsets into lvl_boxes
     int32_t *m2m_parents = nullptr;  // non-leaf boxes per level
     std::vector<int> m2m_begin;
-    int32_t *p2m_jobs = nullptr;     // VALU P2M jobs: leaves of level >= 2, then ~(4 v + quadrant)
+    // VALU P2M jobs without tables: leaves of level >= 2, then the virtual
+    // children of X-list sources, for the nodes and for the targets as sources
+    vp::P2MJob *p2m_jobs = nullptr, *p2m_jobs_t = nullptr;
     int n_p2m_jobs = 0;
     int32_t *x_boxes = nullptr;      // boxes whose X list keeps entries for the P2L kernel
     int n_x_boxes = 0;
@@ -350,6 +359,9 @@ void build_near_tables(vp_plan_s *P);  // vp_near.hip
 void build_schedules(vp_plan_s *P);
 // time the M2L variants valid for the plan's precision and keep the fastest
 void autotune_m2l(vp_plan_s *P);
+// P2M job descriptors for job codes (leaf b >= 0, or ~(4 v + quadrant)) in
+// the source role (nodes) or the target role (targets as sources)
+std::vector<P2MJob> p2m_job_descs(vp_plan_s *P, const std::vector<int32_t> &codes, bool target_role);
 // congruent-leaf operators exist for this pattern size and expansion size
 bool pattern_op_supported(int npat, int PD);
 // gather the U-list sources of `leaves` (host CSR uptr/uidx, source ranges sb/se; device coordinates sx/sy)

@@ -479,7 +479,8 @@ void build_near_tables(vp_plan_s *P) {
             N.p2m_slot = upload(P, slot);
         }
         N.n_p2m_jobs_rest = (int)jobs.size();
-        N.p2m_jobs_rest = upload(P, jobs);
+        const std::vector<P2MJob> jd = p2m_job_descs(P, jobs, false);
+        N.p2m_jobs_rest = upload(P, jd);
         VP_HIP(hipStreamSynchronize(s));  // host vectors leave scope
     }
     VP_HIP(hipStreamSynchronize(s));
