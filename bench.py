@@ -38,12 +38,12 @@ P2P_FLOPS_PER_PAIR = 27     # 2 differences, 3 for r^2, 20 for log(r^2), 2 for t
 # reads half the bytes, WRITE_SIZE all of them).  Valid only for the kernel
 # sources they were taken on: the digest below covers every file of the
 # library's source directory, and any change there turns traffic into null.
-TRAFFIC_DIGEST = "827228795fa9f1429fb5d403f992ed5eb41fa50fe341eba3f22b36a0cb4e5dea"
+TRAFFIC_DIGEST = "c4b72a918e67c245b9ce8521e8c59b2c5c96796cc017dcd13794be5250541c24"
 TRAFFIC_WORKLOAD = "star_adaptive"
 TRAFFIC = {  # stage -> (read bytes, written bytes) per launch, FP64 p = 30, one density
-    "corr": (780119171, 11904248),
-    "m2l": (278740330, 20255327),
-    "p2p": (92375563, 3546065),
+    "corr": (754246900, 11968898),  # k_corr_cells
+    "m2l": (244275436, 18868847),  # k_m2l_scaled, levels from the split level on
+    "p2p": (92348511, 3545972),
 }
 
 
@@ -153,12 +153,17 @@ def _stage_roofline(plan, tim, precision, stage):
                 "work": f"{nv} translations (V lists and X-list virtual children, levels >= {info['split_level']}) "
                         f"x {nb} densities x {per} flops ({form}, P={P}); {tile_ops} tile products issued"}
     if stage == "corr":
-        nnz, m, n_ = info["nnz"], info["m"], info["n"]
-        bytes_ = nnz * 8 + (m + 1) * 8 + m * 4 + m * 8 * nb + n_ * 8 * nb
+        nnz, m, n_, cells = info["nnz"], info["m"], info["n"], info["corr_cells"]
+        if cells > 0:
+            # per cell: first row, run start, two row pointers; f read once, outputs written
+            bytes_ = nnz * 8 + cells * (4 + 4 + 16) + m * 8 * nb + n_ * 8 * nb
+            kern, what = "k_corr_cells", f"{nnz} values x 8 B + {cells} cell records"
+        else:
+            bytes_ = nnz * 8 + (m + 1) * 8 + m * 4 + m * 8 * nb + n_ * 8 * nb
+            kern, what = "k_corr", f"{nnz} values x 8 B + row pointers and runs"
         return {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": 8000.0, "unit": "GB/s",
-                "frac": bytes_ / avg_s / 1e9 / 8000.0, "traffic": None, "kernel": "k_corr",
-                "avg_ms": avg_s * 1e3,
-                "work": f"{nnz} values x 8 B + row pointers and runs, f read once, {nb} output rows written"}
+                "frac": bytes_ / avg_s / 1e9 / 8000.0, "traffic": None, "kernel": kern,
+                "avg_ms": avg_s * 1e3, "work": f"{what}, f read once, {nb} output rows written"}
     return None
 
 

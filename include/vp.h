@@ -177,7 +177,8 @@ typedef struct {
     int64_t m2l_coarse_tile_ops;      /* of m2l_tile_ops, those of the launch below split_level */
     int32_t split_level;       /* expansion passes of the levels below it run on a third stream
                                   beside the M2L of the levels from it on (2: none below) */
-    int32_t reserved;
+    int32_t corr_cells;        /* cells of C applied cell by cell (consecutive rows sharing one
+                                  column run); 0: the row kernel applies C */
     double root[3];
 } vp_plan_info_t;
 

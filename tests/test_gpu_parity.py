@@ -313,6 +313,7 @@ def test_correction_general_csr(nbatch):
     val = rng.standard_normal(int(rowptr[-1]))
     f = rng.standard_normal((nbatch, n))
     plan = vp.Plan(x, y, w, tx, ty, rowptr, col, val, order=30, max_leaf=32, nbatch=nbatch, root=(-1.0, -1.0, 2.0))
+    assert plan.info()["corr_cells"] == 0  # not run-structured: the row kernel applies C
     u = _host(plan.eval(_dev(f)))
     ref = direct.evaluate(x, y, w, f, rowptr, col, val, tx, ty)
     assert max(relinf(u[b], ref[b]) for b in range(nbatch)) <= TOL64
@@ -349,6 +350,7 @@ def test_correction_cells(nbatch):
     f = rng.standard_normal((nbatch, n))
     plan = vp.Plan(x, y, w, rowptr=rowptr, col=col, val=val, order=30, max_leaf=32, nbatch=nbatch,
                    root=(-1.0, -1.0, 2.0))
+    assert plan.info()["corr_cells"] == len(sizes)  # the cell kernel applies C
     u = _host(plan.eval(_dev(f)))
     ref = direct.evaluate(x, y, w, f, rowptr, col, val)
     assert max(relinf(u[b], ref[b]) for b in range(nbatch)) <= TOL64
