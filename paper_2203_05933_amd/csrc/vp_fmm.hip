@@ -578,23 +578,37 @@ __device__ inline double vp_log(double x) {
 // inv_c = fl(1/c_i), c_i the centre of m's interval of width 2^-8, and
 // L_i = -log(inv_c) (both from the host, LOG_TABLE entries);
 // u = m inv_c - 1 (one rounding, |u| <= 2^-8) and
-// log x = e log 2 + L_i + log1p(u), log1p by its Taylor series through u^6
-// (truncation below 2^-60).
+// log x = e log 2 + L_i + u p(u), with p(u) = log1p(u)/u by its Taylor
+// series through u^5 (truncation of log1p below 2^-60).
+//
+// Table layout in LDS: the entry of fraction bits i sits at LOG_BASE + i,
+// found from bits 13..21 of m's high word (the 7 fraction bits and the two
+// lowest exponent bits, 01 for every m in [1/2, 1)).  x = 0 has m = 0 and
+// e = 0 and so selects entry 0, which holds (0, p(-1)): u = -1 and the sum
+// -p(-1) + p(-1) is exactly zero.  A zero distance (the self pair) thus
+// contributes exactly nothing without a compare or select in the pair loop.
+// Entries 1 .. LOG_BASE-1 are never read; the kernel keeps its source tiles
+// there.
+constexpr int LOG_BASE = 256;
+
+__device__ inline double log1p_over_u(double u) {
+    double p = fma(u, -1.0 / 6.0, 1.0 / 5.0);
+    p = fma(u, p, -0.25);
+    p = fma(u, p, 1.0 / 3.0);
+    p = fma(u, p, -0.5);
+    return fma(u, p, 1.0);
+}
+
 __device__ inline double vp_log_tab(double x, const double2 *__restrict__ tab) {
     const double LN2_HI = 6.93147180369123816490e-01;
     const double LN2_LO = 1.90821492927058770002e-10;
     const int e = __builtin_amdgcn_frexp_exp(x);
     const double m = __builtin_amdgcn_frexp_mant(x);
-    const int i = (__double2hiint(m) >> 13) & (LOG_TABLE - 1);
+    const unsigned i = ((unsigned)__double2hiint(m) >> 13) & 511u;
     const double2 t = tab[i];
     const double u = fma(m, t.x, -1.0);
-    double p = fma(u, -1.0 / 6.0, 1.0 / 5.0);
-    p = fma(u, p, -0.25);
-    p = fma(u, p, 1.0 / 3.0);
-    p = fma(u, p, -0.5);
-    p = fma(u, p, 1.0);
     const double de = (double)e;
-    return fma(de, LN2_HI, fma(de, LN2_LO, fma(u, p, t.y)));
+    return fma(de, LN2_HI, fma(de, LN2_LO, fma(u, log1p_over_u(u), t.y)));
 }
 
 // ----------------------------------------------------------------------------
@@ -603,8 +617,9 @@ __device__ inline double vp_log_tab(double x, const double2 *__restrict__ tab) {
 // P2PCap points, so a leaf with many small neighbours pays one barrier
 // pair per tile.  When a leaf has few targets the lanes also split the
 // source loop (K lane groups) and the partial sums are combined in a fixed
-// order.  Pairs at zero distance (the self pair) contribute nothing (their
-// logarithm is multiplied by zero, so the loop has no branch).
+// order.  Pairs at zero distance (the self pair) contribute nothing: the
+// logarithm returns exactly zero there (the table's zero entry), and the
+// gradient multiplies its reciprocal by zero, so the loop has no branch.
 // ----------------------------------------------------------------------------
 template <int NB>
 struct P2PCap {
@@ -619,10 +634,17 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
                                             const double *__restrict__ q, int nbatch, int bt0,
                                             const double2 *__restrict__ logtab, double *__restrict__ acc) {
     constexpr int CAP = P2PCap<NB>::value;
-    __shared__ double xs[CAP], ys[CAP];
-    __shared__ double2 ltab[LOG_TABLE];
-    for (int i = threadIdx.x; i < LOG_TABLE; i += 64) ltab[i] = logtab[i];
-    __shared__ double qs[NB][CAP];
+    // the source tile lives in the logarithm table's unused entries when it fits
+    constexpr int SRC = (2 + NB) * CAP;  // doubles: x, y, q per density
+    constexpr bool IN_GAP = SRC * 8 <= (LOG_BASE - 1) * 16;
+    __shared__ double2 ltab[LOG_BASE + LOG_TABLE + (IN_GAP ? 0 : (SRC + 1) / 2)];
+    double *xs = reinterpret_cast<double *>(IN_GAP ? ltab + 1 : ltab + LOG_BASE + LOG_TABLE);
+    double *ys = xs + CAP;
+    double(*qs)[CAP] = reinterpret_cast<double(*)[CAP]>(ys + CAP);
+    if (!GRAD) {
+        for (int i = threadIdx.x; i < LOG_TABLE; i += 64) ltab[LOG_BASE + i] = logtab[i];
+        if (threadIdx.x == 0) ltab[0] = make_double2(0.0, log1p_over_u(-1.0));
+    }
     __shared__ double red[GRAD ? 2 * NB : NB][64];
     const int lane = threadIdx.x;
     const int b = leaves[blockIdx.x];
@@ -686,8 +708,8 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
                 for (int j = kg; j < fill; j += K) {
                     const double dx = xs[j] - px, dy = ys[j] - py;
                     const double r2 = fma(dx, dx, dy * dy);
-                    const bool nz = r2 > 0.0;
                     if (GRAD) {
+                        const bool nz = r2 > 0.0;
                         const double rr = nz ? r2 : 1.0;
                         double ir2 = __builtin_amdgcn_rcp(rr);
                         ir2 = fma(fma(-rr, ir2, 1.0), ir2, ir2);
@@ -700,8 +722,8 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
                             gya[k] = fma(c, dy, gya[k]);
                         }
                     } else {
-                        // branch-free: the zero-distance pair takes log(1) times zero
-                        const double lg = vp_log_tab(nz ? r2 : 1.0, ltab) * (nz ? 1.0 : 0.0);
+                        // a zero distance gives exactly zero (see vp_log_tab)
+                        const double lg = vp_log_tab(r2, ltab);
 #pragma unroll
                         for (int k = 0; k < NB; ++k) a[k] = fma(qs[k][j], lg, a[k]);
                     }
