@@ -572,14 +572,16 @@ __device__ inline double vp_log(double x) {
     return fma(de, LN2_HI, fma(de, LN2_LO, logm));
 }
 
-// Table-driven logarithm for the pairwise near field (the table-lookup
-// scheme of P. T. P. Tang, ACM TOMS 16, 1990, with our own table and series):
-// x = 2^e m, m in [1/2, 1); the top 7 fraction bits i of m select
-// inv_c = fl(1/c_i), c_i the centre of m's interval of width 2^-8, and
-// L_i = -log(inv_c) (both from the host, LOG_TABLE entries);
+// Table-driven base-2 logarithm for the pairwise near field (the
+// table-lookup scheme of P. T. P. Tang, ACM TOMS 16, 1990, with our own
+// table and series): x = 2^e m, m in [1/2, 1); the top 7 fraction bits i of
+// m select inv_c = fl(1/c_i), c_i the centre of m's interval of width 2^-8,
+// and L_i = -log2(inv_c) (both from the host, LOG_TABLE entries);
 // u = m inv_c - 1 (one rounding, |u| <= 2^-8) and
-// log x = e log 2 + L_i + u p(u), with p(u) = log1p(u)/u by its Taylor
-// series through u^5 (truncation of log1p below 2^-60).
+// log2 x = e + L_i + u p(u), with p(u) = log2(1 + u)/u by its Taylor series
+// through u^5 (truncation below 2^-60).  The pair loop sums base-2
+// logarithms and each target's sum is multiplied by log 2 once, so the
+// exponent enters as one add instead of a two-part product.
 //
 // Table layout in LDS: the entry of fraction bits i sits at LOG_BASE + i,
 // found from bits 13..21 of m's high word (the 7 fraction bits and the two
@@ -591,24 +593,22 @@ __device__ inline double vp_log(double x) {
 // there.
 constexpr int LOG_BASE = 256;
 
-__device__ inline double log1p_over_u(double u) {
-    double p = fma(u, -1.0 / 6.0, 1.0 / 5.0);
-    p = fma(u, p, -0.25);
-    p = fma(u, p, 1.0 / 3.0);
-    p = fma(u, p, -0.5);
-    return fma(u, p, 1.0);
+__device__ inline double log2p1_over_u(double u) {
+    constexpr double IL2 = 1.44269504088896340736;  // 1 / log 2
+    double p = fma(u, -IL2 / 6.0, IL2 / 5.0);
+    p = fma(u, p, -IL2 / 4.0);
+    p = fma(u, p, IL2 / 3.0);
+    p = fma(u, p, -IL2 / 2.0);
+    return fma(u, p, IL2);
 }
 
-__device__ inline double vp_log_tab(double x, const double2 *__restrict__ tab) {
-    const double LN2_HI = 6.93147180369123816490e-01;
-    const double LN2_LO = 1.90821492927058770002e-10;
+__device__ inline double vp_log2_tab(double x, const double2 *__restrict__ tab) {
     const int e = __builtin_amdgcn_frexp_exp(x);
     const double m = __builtin_amdgcn_frexp_mant(x);
     const unsigned i = ((unsigned)__double2hiint(m) >> 13) & 511u;
     const double2 t = tab[i];
     const double u = fma(m, t.x, -1.0);
-    const double de = (double)e;
-    return fma(de, LN2_HI, fma(de, LN2_LO, fma(u, log1p_over_u(u), t.y)));
+    return (double)e + fma(u, log2p1_over_u(u), t.y);
 }
 
 // ----------------------------------------------------------------------------
@@ -643,7 +643,7 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
     double(*qs)[CAP] = reinterpret_cast<double(*)[CAP]>(ys + CAP);
     if (!GRAD) {
         for (int i = threadIdx.x; i < LOG_TABLE; i += 64) ltab[LOG_BASE + i] = logtab[i];
-        if (threadIdx.x == 0) ltab[0] = make_double2(0.0, log1p_over_u(-1.0));
+        if (threadIdx.x == 0) ltab[0] = make_double2(0.0, log2p1_over_u(-1.0));
     }
     __shared__ double red[GRAD ? 2 * NB : NB][64];
     const int lane = threadIdx.x;
@@ -651,15 +651,14 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
     const int t0 = R.tb[b], t1 = R.te[b];
     if (t1 <= t0) return;
     const int nt = t1 - t0;
-    int T2 = 1;
-    while (T2 < nt && T2 < 64) T2 <<= 1;
-    const int K = 64 / T2;
+    const int T2 = nt < 64 ? nt : 64;  // lanes per group: one target each
+    const int K = 64 / T2;             // groups, each taking every K-th source
     const int tl = lane % T2, kg = lane / T2;
     const int nbh = min(NB, nbatch - bt0);
     const int e0 = uptr[b], e1 = uptr[b + 1];
     for (int base = t0; base < t1; base += 64) {
         const int t = base + tl;
-        const bool act = t < t1;
+        const bool act = t < t1 && kg < K;
         const double px = act ? R.tx[t] : 0.0, py = act ? R.ty[t] : 0.0;
         double a[NB], gxa[NB], gya[NB];
 #pragma unroll
@@ -722,8 +721,8 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
                             gya[k] = fma(c, dy, gya[k]);
                         }
                     } else {
-                        // a zero distance gives exactly zero (see vp_log_tab)
-                        const double lg = vp_log_tab(r2, ltab);
+                        // a zero distance gives exactly zero (see vp_log2_tab)
+                        const double lg = vp_log2_tab(r2, ltab);
 #pragma unroll
                         for (int k = 0; k < NB; ++k) a[k] = fma(qs[k][j], lg, a[k]);
                     }
@@ -770,9 +769,9 @@ __global__ void __launch_bounds__(64) k_p2p(PointRoles R, const int32_t *__restr
                     acc[((int64_t)(bt0 + k) * 2 + 0) * R.ntgt + t] = INV_2PI * gxa[k];
                     acc[((int64_t)(bt0 + k) * 2 + 1) * R.ntgt + t] = INV_2PI * gya[k];
                 } else if (ACCUM) {
-                    acc[(int64_t)(bt0 + k) * R.ntgt + t] += -INV_4PI * a[k];
+                    acc[(int64_t)(bt0 + k) * R.ntgt + t] += -LN2_4PI * a[k];
                 } else {
-                    acc[(int64_t)(bt0 + k) * R.ntgt + t] = -INV_4PI * a[k];
+                    acc[(int64_t)(bt0 + k) * R.ntgt + t] = -LN2_4PI * a[k];
                 }
             }
         }

@@ -40,6 +40,7 @@ constexpr int NOFF = 40;               // M2L offsets: [-3,3]^2 minus [-1,1]^2
 constexpr int MAX_BATCH = 64;
 constexpr double INV_2PI = 0.15915494309189533576888376337251436;
 constexpr double INV_4PI = 0.07957747154594766788444188168625718;
+constexpr double LN2_4PI = 0.05515890003816289834911410802949942;  // log(2) / (4 pi)
 
 // offset code of (dx, dy) in [-3,3]^2 with max(|dx|,|dy|) >= 2, else -1
 __host__ __device__ inline int offset_code(int dx, int dy) {
@@ -145,7 +146,7 @@ struct Operators {
     int PR = 0;
     double *sh_qt64[2] = {nullptr, nullptr}, *sh_tin64[2] = {nullptr, nullptr}, *sh_tout64[2] = {nullptr, nullptr};
     float *sh_qt32[2] = {nullptr, nullptr}, *sh_tin32[2] = {nullptr, nullptr}, *sh_tout32[2] = {nullptr, nullptr};
-    double *log_table = nullptr;  // [LOG_TABLE][2]: fl(1/c_i), -log(fl(1/c_i)) (pairwise logarithm)
+    double *log_table = nullptr;  // [LOG_TABLE][2]: fl(1/c_i), -log2(fl(1/c_i)) (pairwise logarithm)
     double *inv_k = nullptr;  // 1/k, k = 0..P-1 (0 for k = 0)
     float *inv_k_f32 = nullptr;
     // M2L in diagonally scaled form: one real matrix Q (A-fragment order,

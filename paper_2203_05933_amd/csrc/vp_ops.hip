@@ -193,7 +193,7 @@ void build_operators(vp_plan_s *P) {
         const double c = 0.5 + (i + 0.5) / (2.0 * LOG_TABLE);
         const double inv_c = 1.0 / c;
         ltab[2 * i] = inv_c;
-        ltab[2 * i + 1] = (double)(-logl((long double)inv_c));
+        ltab[2 * i + 1] = (double)(-log2l((long double)inv_c));
     }
     std::vector<double> invk(Pn, 0.0);
     for (int k = 1; k < Pn; ++k) invk[k] = 1.0 / k;
