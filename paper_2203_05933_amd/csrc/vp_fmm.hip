@@ -1749,11 +1749,14 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, doub
     a.logrow = -1;
     a.level = P->tree.level;
     a.logside = P->tree.d_logside;
+    a.zero_col = P->zero_col;
     if (kind == PAT_P2M) {
         // rows = expansion (RBE blocks), cols = pattern points (RBP*16); operator
         // 0 for pattern leaves, 1 + quadrant for the virtual children of pattern
         // X-list sources (zero outside the quadrant's points); the columns are
-        // grouped by operator, so a 64-column block uses one (two at a boundary)
+        // grouped by operator, so a 64-column block uses one (two at a boundary).
+        // This launch runs beside the VALU P2M and the correction at the start
+        // of an evaluation: the four-column-tile form (fewer waves) suits it.
         constexpr int RB = RBE, S = RBP * 4;
         constexpr bool LDSA = translate_ldsa<E, RB, S, false>();
         constexpr size_t lds = LDSA ? translate_lds_bytes<E, RB, S, false>() : 0;
@@ -1770,9 +1773,7 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, doub
                            dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
                            P->q, static_cast<E *>(P->Mexp));
     } else {
-        constexpr int RB = RBP, S = RBE * 4;
-        constexpr bool LDSA = translate_ldsa<E, RB, S, false>();
-        constexpr size_t lds = LDSA ? translate_lds_bytes<E, RB, S, false>() : 0;
+        // rows = pattern points (RBP blocks, one per wave), cols = expansions
         a.cols_box = N.l2p_pat;
         a.ncols = N.n_l2p_pat * P->nbatch;
         a.in = ColAddr{P->PD, (int64_t)P->nbatch * P->PD, nullptr};
@@ -1780,9 +1781,8 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, doub
         a.nrows_out = N.npat;
         if (a.ncols <= 0) return;
         const E *op = f32 ? (const E *)N.l2p_op_f32 : (const E *)N.l2p_op;
-        hipLaunchKernelGGL((k_translate<E, double, E, RB, S, false, true, LDSA>),
-                           dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
-                           static_cast<const E *>(P->Lexp), acc);
+        hipLaunchKernelGGL((k_pattern_op<E, double, E, RBE * 4, true>), dim3((unsigned)((a.ncols + 15) / 16)),
+                           dim3(64 * RBP), 0, P->stream, a, op, static_cast<const E *>(P->Lexp), acc);
     }
     VP_LAUNCH_CHECK();
 }

@@ -172,6 +172,55 @@ __global__ void __launch_bounds__(256) k_translate(TranslateArgs a, const TM *__
     }
 }
 
+// Fixed-matrix variant for the pattern L2P launch (few columns, latency
+// bound, at the end of an evaluation): a workgroup owns ONE 16-column tile and each of its waves
+// one 16-row block of the output (blockDim = 64 x output row blocks), so a
+// launch has four times the waves of k_translate and each wave's chain is
+// one quarter of the operator.  The wave reads its operator rows straight
+// from L2 together with the tile's input columns (an absent source reads
+// the zero column), then runs S products.  Columns whose slot o is empty
+// get exact zeros from that operator, so the per-column sum is the same as
+// in k_translate.
+template <class TI, class TO, class TM, int S, bool ACCUM>
+__global__ void __launch_bounds__(256) k_pattern_op(TranslateArgs a, const TM *__restrict__ A,
+                                                    const TI *__restrict__ in, TO *__restrict__ out) {
+    typedef Mfma<TM> M;
+    const int tid = threadIdx.x, lane = tid & 63, r = tid >> 6, nrb = blockDim.x >> 6;
+    const int cl = lane & 15, g = lane >> 4;
+    const int col = blockIdx.x * 16 + cl;
+    const bool valid = col < a.ncols;
+    const int box = valid ? a.cols_box[col / a.nbatch] : 0;
+    const int bt = valid ? col % a.nbatch : 0;
+    const TI *zc = static_cast<const TI *>(a.zero_col);
+    const int64_t AE = (int64_t)nrb * S * 64;
+    typename M::acc_t acc = M::zero();
+    for (int o = 0; o < a.nops; ++o) {
+        const int src = valid ? a.slots[(int64_t)box * a.nops + o] : -1;
+        if (__ballot(src >= 0) == 0ull) continue;  // the same for every wave of the tile
+        const TM *Ao = A + o * AE + (int64_t)r * S * 64 + lane;
+        const TI *ip = (src >= 0 ? in + a.in.off(src) + (int64_t)bt * a.in.bstride : zc) + g;
+        TM av[S], bv[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            av[s] = Ao[s * 64];
+            bv[s] = (TM)ip[4 * s];
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc = M::op(av[s], bv[s], acc);
+    }
+    if (valid) {
+        TO *op = out + a.out.off(box) + (int64_t)bt * a.out.bstride;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = r * 16 + M::row(i, g);
+            if (row < a.nrows_out) {
+                if (ACCUM) op[row] += (TO)acc[i];
+                else op[row] = (TO)acc[i];
+            }
+        }
+    }
+}
+
 // Split-operator variant for the large M2L launch: the four waves of a
 // workgroup share ONE 16-column tile and take every fourth active operator,
 // reading operator fragments straight from L2 (no barriers in the main

@@ -396,6 +396,29 @@ def test_duplicate_points_and_deep_tree():
     plan.close()
 
 
+def test_targets_on_nodes():
+    """Separate targets placed exactly on source nodes: the zero-distance pair
+    contributes nothing (the pairwise logarithm returns exactly 0 there), in
+    the forward and the adjoint evaluation and for several densities."""
+    vp = _vp()
+    x, y, w, f, rng = _clustered(12)
+    n = x.size
+    on = rng.choice(n, 300, replace=False)
+    t = np.concatenate([np.stack([x[on], y[on]], 1), rng.uniform(-1, 1, (200, 2))])
+    tx, ty = t[:, 0].copy(), t[:, 1].copy()
+    fs = np.concatenate([f, rng.standard_normal((2, n))])
+    plan = vp.Plan(x, y, w, tx, ty, order=30, max_leaf=32, nbatch=3, root=(-1.0, -1.0, 2.0))
+    u = _host(plan.eval(_dev(fs)))
+    ref = direct.smooth(x, y, w, fs, tx, ty)
+    assert np.all(np.isfinite(u))
+    assert max(relinf(u[b], ref[b]) for b in range(3)) <= TOL64
+    g = rng.standard_normal((3, t.shape[0]))
+    d = _host(plan.eval_adjoint(_dev(g)))
+    dref = direct.smooth_adjoint(x, y, w, g, tx, ty)
+    assert max(relinf(d[b], dref[b]) for b in range(3)) <= TOL64
+    plan.close()
+
+
 # ---------------------------------------------------------------------------
 # congruent-leaf path (near-field tables, pattern P2M/L2P) vs pairwise path
 # ---------------------------------------------------------------------------
