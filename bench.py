@@ -144,7 +144,7 @@ def _stage_roofline(plan, tim, precision, stage):
         # matrix-core flops the launch issues: per (16-column tile, offset) two real
         # PQ x PQ products (scaled form) or one PD x PD product
         PQ = (P + 15) // 16 * 16
-        PDm = (2 * P + 1 + 15) // 16 * 16
+        PDm = (max(2 * P + 1, P + PQ) + 15) // 16 * 16  # rows per expansion column
         issued = tile_ops * (64 * PQ * PQ if scaled else 32 * PDm * PDm)
         return {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
                 "frac": flops / avg_s / 1e12 / peak, "traffic": None,

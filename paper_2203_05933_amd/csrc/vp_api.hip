@@ -2,6 +2,7 @@
 // construction and the evaluation entry points.  Internal errors are C++
 // exceptions, caught here and turned into vp_status codes.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <map>
@@ -229,7 +230,14 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->nbatch = o.nbatch;
         P->p = o.order;
         P->P = o.order + 1;
-        P->PD = ((2 * P->P + 1 + 15) / 16) * 16;
+        // rows per expansion column: 2P values, the A_0 sum row of the
+        // per-offset M2L form, zero padding to a multiple of 16, and at least
+        // P + PQ rows (PQ = P rounded up to 16) so that the scaled M2L reads
+        // coefficient rows k < PQ of both parts without a clamp
+        {
+            const int PQ = (P->P + 15) / 16 * 16;
+            P->PD = (std::max(2 * P->P + 1, P->P + PQ) + 15) / 16 * 16;
+        }
         if (P->PD > 128) throw Error(VP_EUNSUPPORTED, "order too large (2(p+1)+1 must be <= 128)");
         P->fp32 = (o.precision == VP_FP32_BULK);
         P->one_stream = (o.flags & VP_FLAG_ONE_STREAM) != 0;

@@ -47,17 +47,18 @@ struct M2LScaledArgs {
 };
 
 // Column of one source for the k-steps of lane group g (k = g*S + s).  An
-// absent source reads a column of zeros, and k >= P reads coefficient P-1,
-// which the zero rows k >= P of the input scaling then remove: every lane
-// loads, no load sits behind a branch, and no select waits on a load.
+// absent source reads a column of zeros.  Rows k >= P of the real part (the
+// first imaginary coefficients) and of the imaginary part (zero padding; the
+// column has at least P + PQ rows) are read as they are: the zero rows
+// k >= P of the input scaling remove them.  Every lane loads from one base
+// address with constant offsets; no load sits behind a branch.
 template <class TI, class TM, int S>
 __device__ inline void m2l_load_col(const TI *__restrict__ ip, int g, int P, TM (&xr)[S], TM (&xi)[S]) {
+    const TI *pr = ip + g * S, *pi = ip + P + g * S;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const int k = g * S + s;
-        const int kk = k < P ? k : P - 1;
-        xr[s] = (TM)ip[kk];
-        xi[s] = (TM)ip[P + kk];
+        xr[s] = (TM)pr[s];
+        xi[s] = (TM)pi[s];
     }
 }
 
@@ -65,7 +66,7 @@ __device__ inline void m2l_load_col(const TI *__restrict__ ip, int g, int P, TM 
 // for k = (lane/16) S + s); tin/tout [NOFF][RB*16][2] (re, im);
 // logt [NOFF][2] = log(-t).
 template <class TI, class TO, class TM, int RB>
-__global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *__restrict__ Qf,
+__global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM *__restrict__ Qf,
                                                     const TM *__restrict__ tin, const TM *__restrict__ tout,
                                                     const double *__restrict__ logt, const TI *__restrict__ in,
                                                     TO *__restrict__ out) {
@@ -80,6 +81,7 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
     __shared__ __align__(16) unsigned char s_raw[TBYTES > RBYTES ? TBYTES : RBYTES];
     __shared__ int32_t s_ops[NOFF];
     __shared__ int32_t s_src[NOFF][16];
+    __shared__ TM s_q[RB * S][64];  // Q fragments: [r * S + s][lane], k = (lane/16) S + s
     TM *s_tin = reinterpret_cast<TM *>(s_raw);
     TM *s_tout = s_tin + TAB;
     double *s_logt = reinterpret_cast<double *>(s_raw + 2 * TAB * sizeof(TM));
@@ -108,14 +110,11 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
         }
         if (tid < 2 * NOFF) s_logt[tid] = logt[tid];
     }
-    TM q[RB][S];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = g * S + s;
-            q[r][s] = Qf[(r * S + (k >> 2)) * 64 + (k & 3) * 16 + cl];
-        }
+    for (int i = tid; i < RB * S * 64; i += 256) {
+        const int rs = i >> 6, ln = i & 63, r = rs / S, s = rs % S;
+        const int k = (ln >> 4) * S + s;
+        s_q[rs][ln] = Qf[(r * S + (k >> 2)) * 64 + (k & 3) * 16 + (ln & 15)];
+    }
     __syncthreads();
 
     double br[RB][4], bi[RB][4];
@@ -138,14 +137,6 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
     for (; e < nt; e += 4) {
         const int o = s_ops[e];
         const TM *ti = s_tin + o * PQ * 2;
-        TM yr[S], yi[S];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = g * S + s;
-            const TM wr = ti[2 * k], wi = ti[2 * k + 1];
-            yr[s] = xr[s] * wr - xi[s] * wi;
-            yi[s] = xr[s] * wi + xi[s] * wr;
-        }
         {
             // A_0 log(-t): the offset-dependent part of the k = 0 column
             // (step 0 of lane group 0); other lanes add exact zeros
@@ -156,12 +147,12 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
             a0r += x0r;
             a0i += x0i;
         }
-        // the next offset's source columns, in flight during the products
-        {
-            const int en = e + 4;
-            const int srcn = en < nt ? s_src[en][cl] : -1;
-            m2l_load_col<TI, TM, S>(srcn >= 0 ? in + (int64_t)srcn * a.box_stride + bt_off : zc, g, P, xr, xi);
-        }
+        // the next offset's source columns: coefficient s is loaded as soon
+        // as the current one is scaled, and is in flight during the products
+        const int en = e + 4;
+        const int srcn = en < nt ? s_src[en][cl] : -1;
+        const TI *ipn = srcn >= 0 ? in + (int64_t)srcn * a.box_stride + bt_off : zc;
+        const TI *pnr = ipn + g * S, *pni = ipn + P + g * S;
         typename M::acc_t zr[RB], zi[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
@@ -169,12 +160,21 @@ __global__ void __launch_bounds__(256) k_m2l_scaled(M2LScaledArgs a, const TM *_
             zi[r] = M::zero();
         }
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+        for (int s = 0; s < S; ++s) {
+            const int k = g * S + s;
+            // input scaling y_k = (-t)^-k A_k, then the next offset's coefficient
+            const TM wr = ti[2 * k], wi = ti[2 * k + 1];
+            const TM yr = xr[s] * wr - xi[s] * wi;
+            const TM yi = xr[s] * wi + xi[s] * wr;
+            xr[s] = (TM)pnr[s];
+            xi[s] = (TM)pni[s];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                zr[r] = M::op(q[r][s], yr[s], zr[r]);
-                zi[r] = M::op(q[r][s], yi[s], zi[r]);
+                const TM qv = s_q[r * S + s][lane];
+                zr[r] = M::op(qv, yr, zr[r]);
+                zi[r] = M::op(qv, yi, zi[r]);
             }
+        }
         const TM *to = s_tout + o * PQ * 2;
 #pragma unroll
         for (int r = 0; r < RB; ++r)
