@@ -1420,15 +1420,15 @@ static void translate_m2l(hipStream_t s, int PD, const TranslateArgs &a, const T
 }
 
 template <class TI, class TO, class TM>
-static void m2l_scaled(hipStream_t s, int PQ, const M2LScaledArgs &a, const TM *Q, const TM *tin, const TM *tout,
+static void m2l_scaled(hipStream_t s, int PQ, const M2LScaledArgs &a, const TM *Q, const TM *tin,
                        const double *logt, const TI *in, TO *out) {
     if (a.ncols <= 0) return;
     const unsigned blocks = (unsigned)((a.ncols + 15) / 16);
     switch (PQ) {
-        case 16: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 1>), dim3(blocks), dim3(256), 0, s, a, Q, tin, tout, logt, in, out); break;
-        case 32: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 2>), dim3(blocks), dim3(256), 0, s, a, Q, tin, tout, logt, in, out); break;
-        case 48: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 3>), dim3(blocks), dim3(256), 0, s, a, Q, tin, tout, logt, in, out); break;
-        case 64: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 4>), dim3(blocks), dim3(256), 0, s, a, Q, tin, tout, logt, in, out); break;
+        case 16: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 1>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out); break;
+        case 32: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 2>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out); break;
+        case 48: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 3>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out); break;
+        case 64: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 4>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out); break;
         default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
     }
     VP_LAUNCH_CHECK();
@@ -1541,13 +1541,13 @@ static void launch_m2l(vp_plan_s *P, int part) {
         sa.level = T.level;
         sa.logside = T.d_logside;
         if (!f32)
-            m2l_scaled<double, double, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
+            m2l_scaled<double, double, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_logt,
                                                (const double *)M, (double *)L);
         else if (P->m2l_mode == VP_M2L_FP32_SCALED)
-            m2l_scaled<float, float, float>(s, O.PQ, sa, O.m2l_q32, O.m2l_tin32, O.m2l_tout32, O.m2l_logt,
+            m2l_scaled<float, float, float>(s, O.PQ, sa, O.m2l_q32, O.m2l_tin32, O.m2l_logt,
                                             (const float *)M, (float *)L);
         else
-            m2l_scaled<float, float, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_tout64, O.m2l_logt,
+            m2l_scaled<float, float, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_logt,
                                              (const float *)M, (float *)L);
     } else if (!f32) {
         translate_m2l<double, double, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const double *)M,

@@ -153,8 +153,8 @@ struct Operators {
     // PQ = roundup(P, 16) rows and columns), per-offset complex scalings
     // tin[o][k] = (-t)^-k and tout[o][l] = t^-l ([NOFF][PQ][2]), log(-t)
     int PQ = 0;
-    double *m2l_q64 = nullptr, *m2l_tin64 = nullptr, *m2l_tout64 = nullptr, *m2l_logt = nullptr;
-    float *m2l_q32 = nullptr, *m2l_tin32 = nullptr, *m2l_tout32 = nullptr;
+    double *m2l_q64 = nullptr, *m2l_tin64 = nullptr, *m2l_logt = nullptr;  // scaled M2L (Q rows signed)
+    float *m2l_q32 = nullptr, *m2l_tin32 = nullptr;
 };
 
 // near-field table slots per target level: 9 same level, 16 coarser, 16 finer

@@ -7,7 +7,9 @@
 // with y_k = (-t)^-k A_k: a complex diagonal scaling of the source column,
 // ONE real matrix Q (Q[0][k] = 1, Q[l][0] = -1/l, Q[l][k] = C(l+k-1, k-1),
 // Q[0][0] = 0) that is the same for all 40 offsets, and a complex diagonal
-// scaling of the result.  Because Q is real it acts on the real and the
+// scaling of the result.  Since t^-l = (-1)^l (-t)^-l, the sign (-1)^l is
+// folded into row l of Q (the matrix passed here), and the one table
+// (-t)^-k serves both scalings.  Because Q is real it acts on the real and the
 // imaginary parts separately: the contraction per translation is two real
 // P x P products instead of one real 2P x 2P product, and no per-offset
 // operator is read from memory.  The terms summed are the same products as
@@ -63,11 +65,12 @@ __device__ inline void m2l_load_col(const TI *__restrict__ ip, int g, int P, TM 
 }
 
 // Q in A-fragment order [rb][s][lane] for k = 4 s + lane/16 (regathered here
-// for k = (lane/16) S + s); tin/tout [NOFF][RB*16][2] (re, im);
+// for k = (lane/16) S + s), rows multiplied by (-1)^l; tin [NOFF][RB*16][2]
+// (re, im) = (-t)^-k, the input and (with Q's row signs) the output scaling;
 // logt [NOFF][2] = log(-t).
 template <class TI, class TO, class TM, int RB>
 __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM *__restrict__ Qf,
-                                                    const TM *__restrict__ tin, const TM *__restrict__ tout,
+                                                    const TM *__restrict__ tin,
                                                     const double *__restrict__ logt, const TI *__restrict__ in,
                                                     TO *__restrict__ out) {
     typedef Mfma<TM> M;
@@ -75,7 +78,7 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
     constexpr int PQ = RB * 16;
     constexpr int NR = RB * 4 * 2 + 2;  // reduced values per lane: B re/im per item, A_0 sum re/im
     constexpr int TAB = NOFF * PQ * 2;  // elements of one scaling table
-    constexpr int TBYTES = 2 * TAB * (int)sizeof(TM) + NOFF * 2 * (int)sizeof(double);
+    constexpr int TBYTES = TAB * (int)sizeof(TM) + NOFF * 2 * (int)sizeof(double);
     constexpr int RBYTES = 3 * NR * 64 * (int)sizeof(double);
     // scaling tables during the loop, the cross-wave partial sums after it
     __shared__ __align__(16) unsigned char s_raw[TBYTES > RBYTES ? TBYTES : RBYTES];
@@ -83,8 +86,7 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
     __shared__ int32_t s_src[NOFF][16];
     __shared__ TM s_q[RB * S][64];  // Q fragments: [r * S + s][lane], k = (lane/16) S + s
     TM *s_tin = reinterpret_cast<TM *>(s_raw);
-    TM *s_tout = s_tin + TAB;
-    double *s_logt = reinterpret_cast<double *>(s_raw + 2 * TAB * sizeof(TM));
+    double *s_logt = reinterpret_cast<double *>(s_raw + TAB * sizeof(TM));
     double(*red)[NR][64] = reinterpret_cast<double(*)[NR][64]>(s_raw);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -102,12 +104,9 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
     for (int i = tid; i < nt * 16; i += 256) s_src[i >> 4][i & 15] = a.tile_src[(int64_t)e0 * 16 + i];
     {
         constexpr int CH = TAB * (int)sizeof(TM) / 16;  // 16-byte chunks per table
-        const uint4 *gi = reinterpret_cast<const uint4 *>(tin), *go = reinterpret_cast<const uint4 *>(tout);
-        uint4 *si = reinterpret_cast<uint4 *>(s_tin), *so = reinterpret_cast<uint4 *>(s_tout);
-        for (int i = tid; i < CH; i += 256) {
-            si[i] = gi[i];
-            so[i] = go[i];
-        }
+        const uint4 *gi = reinterpret_cast<const uint4 *>(tin);
+        uint4 *si = reinterpret_cast<uint4 *>(s_tin);
+        for (int i = tid; i < CH; i += 256) si[i] = gi[i];
         if (tid < 2 * NOFF) s_logt[tid] = logt[tid];
     }
     for (int i = tid; i < RB * S * 64; i += 256) {
@@ -175,7 +174,7 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
                 zi[r] = M::op(qv, yi, zi[r]);
             }
         }
-        const TM *to = s_tout + o * PQ * 2;
+        const TM *to = ti;  // (-t)^-l; the sign (-1)^l is in Q
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll

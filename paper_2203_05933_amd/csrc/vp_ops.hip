@@ -158,29 +158,28 @@ void build_operators(vp_plan_s *P) {
             b_out /= 2.0 * tl;   // 2^-l t^-l
         }
     }
-    // diagonally scaled M2L: Q, (-t)^-k, t^-l and log(-t) per offset
+    // diagonally scaled M2L: Q with row l multiplied by (-1)^l, (-t)^-k and
+    // log(-t) per offset (t^-l = (-1)^l (-t)^-l: one table scales both sides)
     const int PQ = (Pn + 15) / 16 * 16;
     O.PQ = PQ;
     std::vector<double> Qm((size_t)PQ * PQ, 0.0), Qf((size_t)PQ * PQ), tin((size_t)NOFF * PQ * 2, 0.0),
-        tout((size_t)NOFF * PQ * 2, 0.0), logt(NOFF * 2);
+        logt(NOFF * 2);
     for (int k = 1; k < Pn; ++k) Qm[k] = 1.0;
     for (int l = 1; l < Pn; ++l) {
-        Qm[(size_t)l * PQ] = -1.0 / l;
-        for (int k = 1; k < Pn; ++k) Qm[(size_t)l * PQ + k] = C[(size_t)(l + k - 1) * (N + 1) + k - 1];
+        const double sg = (l & 1) ? -1.0 : 1.0;
+        Qm[(size_t)l * PQ] = sg * (-1.0 / l);
+        for (int k = 1; k < Pn; ++k) Qm[(size_t)l * PQ + k] = sg * C[(size_t)(l + k - 1) * (N + 1) + k - 1];
     }
     vp_to_frag(Qm.data(), PQ, PQ, PQ, Qf.data());
     for (int code = 0; code < NOFF; ++code) {
         int dx, dy;
         offset_of_code(code, dx, dy);
         const cd t(dx, dy);
-        cd pin = 1.0, pout = 1.0;
+        cd pin = 1.0;
         for (int k = 0; k < Pn; ++k) {
             tin[((size_t)code * PQ + k) * 2] = pin.real();
             tin[((size_t)code * PQ + k) * 2 + 1] = pin.imag();
-            tout[((size_t)code * PQ + k) * 2] = pout.real();
-            tout[((size_t)code * PQ + k) * 2 + 1] = pout.imag();
             pin /= -t;
-            pout /= t;
         }
         const cd lg = std::log(-t);
         logt[2 * code] = lg.real();
@@ -219,14 +218,12 @@ void build_operators(vp_plan_s *P) {
     O.log_table = up(ltab);
     O.m2l_q64 = up(Qf);
     O.m2l_tin64 = up(tin);
-    O.m2l_tout64 = up(tout);
     O.m2l_logt = up(logt);
     // host copies must outlive the asynchronous uploads (synchronised below)
-    std::vector<float> q32(Qf.begin(), Qf.end()), tin32(tin.begin(), tin.end()), tout32(tout.begin(), tout.end());
+    std::vector<float> q32(Qf.begin(), Qf.end()), tin32(tin.begin(), tin.end());
     if (P->fp32) {
         O.m2l_q32 = upf(q32);
         O.m2l_tin32 = upf(tin32);
-        O.m2l_tout32 = upf(tout32);
         std::vector<float> hi(F.size()), lo(F.size());
         for (size_t i = 0; i < F.size(); ++i) {
             hi[i] = (float)F[i];
