@@ -191,7 +191,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (cpu_baseline and errors)")
     ap.add_argument("--no-one-stream", action="store_true",
                     help="skip the one-stream run (per-stage times without the second stream's overlap)")
-    ap.add_argument("--cpu-sample", type=int, default=4096, help="targets the oracle evaluates")
+    ap.add_argument("--cpu-sample", type=int, default=12288, help="targets the oracle evaluates")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed loops, run one plain device copy (y = 2 x) of this many MiB read and "
                          "written, as the calibration kernel for hardware byte counters")
@@ -273,6 +273,9 @@ def main():
     if not args.no_cpu:
         from oracle import direct
         sample = wl.sample if wl.sample is not None else np.arange(wl.m)
+        if args.cpu_sample > len(sample):
+            # a larger seeded draw, so that the timed oracle run is 10-30 s of CPU work
+            sample = gen.sample_indices(wl.m, args.cpu_sample, 110)
         sample = sample[: args.cpu_sample]
         log(f"[bench] oracle on {len(sample)} sampled targets x {wl.n} nodes ({direct.num_threads()} threads)")
         t0 = time.perf_counter()
