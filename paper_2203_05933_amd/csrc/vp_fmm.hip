@@ -937,6 +937,48 @@ __global__ void __launch_bounds__(256) k_corr_cells(int ncell, const int32_t *__
         const int r0 = cell_row[cc], r1 = cell_row[cc + 1], c0 = cell_col[cc];
         const int64_t vb = rowptr[r0];
         const int len = (int)(rowptr[r0 + 1] - vb);
+        if (NBG == 1 && len == 64 && (vb & 1) == 0) {
+            // 64-column cells with 16-byte aligned values (the box cells): a
+            // half-wave per row, each lane two adjacent columns, so one load
+            // instruction moves two rows (1 KB) and eight are in flight
+            const int h = lane >> 5, cl = lane & 31;
+            const double f0 = f[(int64_t)bt0 * flen + c0 + 2 * cl], f1 = f[(int64_t)bt0 * flen + c0 + 2 * cl + 1];
+            for (int i = r0; i < r1; i += 16) {
+                double p[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int row = min(i + 2 * j + h, r1 - 1);
+                    const vp_d2 v = __builtin_nontemporal_load(
+                        reinterpret_cast<const vp_d2 *>(valv + vb + (int64_t)(row - r0) * 64) + cl);
+                    p[j] = v.x * f0 + v.y * f1;
+                }
+                // sums over the 32 lanes of each half: three halving steps
+                // (bits 16, 8, 4) leave one row per lane, two more add it up
+                int m = 8;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const int bit = 16 >> b;
+                    const bool hi = (lane & bit) != 0;
+                    m >>= 1;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (j < m) {
+                            const double keep = hi ? p[m + j] : p[j];
+                            const double give = hi ? p[j] : p[m + j];
+                            p[j] = keep + __shfl_xor(give, bit, 64);
+                        }
+                    }
+                }
+                double t = p[0];
+                t += __shfl_xor(t, 2, 64);
+                t += __shfl_xor(t, 1, 64);
+                // lane's row pair index: bits 4, 3, 2 of the lane, high bit first
+                const int jj = ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+                const int row = i + 2 * jj + h;
+                if ((lane & 3) == 0 && row < r1) out[(int64_t)bt0 * nrows + row] = t;
+            }
+            continue;
+        }
         const bool inc = lane < len;
         double fc[NBG];
 #pragma unroll
