@@ -1885,14 +1885,15 @@ static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint);
 
 // One evaluation on three streams (default priority; with VP_FLAG_ONE_STREAM
 // everything runs on the plan's stream in the order written here):
-//   third stream: VALU P2M, P2L | wait(upper) M2M, M2L, L2L of the levels
-//                 below the split, W lists at the targets (M2P)
-//   second stream: correction C f, near tables, pairwise near field
+//   third stream: VALU P2M, P2L | wait(upper) M2M of the levels below the
+//                 split (then every multipole is done), their M2L and L2L
+//   second stream: correction C f, near tables | wait(all multipoles) W lists
+//                  at the targets (M2P), pairwise near field
 //   plan's stream: fixed-matrix P2M | wait(VALU P2M) M2M from the finest
 //                  level to the split level |
 //                  wait(P2L) M2L of the levels from the split on | wait(coarse)
-//                  L2L from the split level down | wait(M2P) local expansions
-//                  at the targets | wait(near) finish
+//                  L2L from the split level down | wait(second stream) local
+//                  expansions at the targets, finish
 // (the far field writes its own array; with gradients it runs whole on the
 // plan's stream after the near field and adds to it)
 template <class E>
@@ -1968,7 +1969,7 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
     if (tables) fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
     corr();
     tab();
-    pair();
+    // (the W lists and the pairwise near field follow once every multipole is done)
     // plan's stream: leaf multipoles and the upward pass down to the split level
     P->stream = ms;
     if (fmm) {
@@ -1986,29 +1987,32 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
     // on the third stream too (not with gradients, whose far field adds to the
     // near-field array)
     const bool w_apart = fmm && !grad;
-    if (coarse || w_apart) {
-        if (!one) {
-            VP_HIP(hipEventRecord(P->ev_upper, ms));
-            VP_HIP(hipStreamWaitEvent(s3, P->ev_upper, 0));
-        }
+    if (fmm && !one) VP_HIP(hipEventRecord(P->ev_upper, ms));
+    if (coarse) {
+        // the levels below the split, upward, M2L and downward; ev_m2p marks
+        // every multipole done
         P->stream = s3;
-        if (coarse) {
-            // the levels below the split, upward, M2L and downward
-            P->stage_begin(VP_STAGE_COARSE);
-            run_m2m<E>(P, G, L0 - 1, 2);
-            launch_m2l<E>(P, 1);
-            run_l2l<E>(P, G, 3, L0 - 1);
-            P->stage_end(VP_STAGE_COARSE);
-            if (!one) VP_HIP(hipEventRecord(P->ev_coarse, s3));
-        }
-        if (w_apart) {
-            P->stage_begin(VP_STAGE_M2P);
-            run_far<E, false>(P, R, G, P->acc_far, tables, 2);
-            P->stage_end(VP_STAGE_M2P);
-            if (!one) VP_HIP(hipEventRecord(P->ev_m2p, s3));
-        }
+        if (!one) VP_HIP(hipStreamWaitEvent(s3, P->ev_upper, 0));
+        P->stage_begin(VP_STAGE_COARSE);
+        run_m2m<E>(P, G, L0 - 1, 2);
+        if (!one) VP_HIP(hipEventRecord(P->ev_m2p, s3));
+        launch_m2l<E>(P, 1);
+        run_l2l<E>(P, G, 3, L0 - 1);
+        P->stage_end(VP_STAGE_COARSE);
+        if (!one) VP_HIP(hipEventRecord(P->ev_coarse, s3));
         P->stream = ms;
     }
+    // second stream: the W lists at the targets (far-field array) between the
+    // near tables and the pairwise near field, once every multipole is done
+    P->stream = s2;
+    if (w_apart) {
+        if (!one) VP_HIP(hipStreamWaitEvent(s2, coarse ? P->ev_m2p : P->ev_upper, 0));
+        P->stage_begin(VP_STAGE_M2P);
+        run_far<E, false>(P, R, G, P->acc_far, tables, 2);
+        P->stage_end(VP_STAGE_M2P);
+    }
+    pair();
+    P->stream = ms;
     if (fmm) {
         if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_p2l, 0));
         P->stage_begin(VP_STAGE_M2L);
@@ -2035,10 +2039,10 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_join, 0));
         if (fmm) run_far<E, true>(P, R, G, P->acc, false, 3);
     } else {
-        // local expansions at the targets, after the W lists (same array)
-        if (fmm && !one) VP_HIP(hipStreamWaitEvent(ms, P->ev_m2p, 0));
-        if (fmm) run_far<E, false>(P, R, G, P->acc_far, tables, 1);
+        // local expansions at the targets, after the W lists (same array, on
+        // the second stream: the join covers them)
         if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_join, 0));
+        if (fmm) run_far<E, false>(P, R, G, P->acc_far, tables, 1);
     }
     P->stage_end(VP_STAGE_FAR);
     if (u) add_fmm_sums(P, u, adjoint);

@@ -237,12 +237,13 @@ def test_fp32_bulk_form(c0, mode):
     plan.close()
 
 
-@pytest.mark.parametrize("order", [4, 15, 30, 47, 60])
+@pytest.mark.parametrize("order", [4, 15, 16, 30, 47, 60])
 def test_m2l_scaled_matches_per_offset_operators(c0, order):
     """The diagonally scaled M2L (complex scalings by powers of the offset
     around one real binomial matrix) gives the same local expansions and
     potentials as the per-offset real operators at every expansion size
-    (16, 32, 48 and 64 padded rows)."""
+    (16, 32, 48 and 64 padded rows), including orders whose columns carry
+    extra padding rows (P + PQ > 2P + 1: orders 4 and 16)."""
     vp = _vp()
     res = []
     for mode in ("fp64", "fp64_scaled"):
