@@ -275,6 +275,7 @@ def main():
         sample = wl.sample if wl.sample is not None else np.arange(wl.m)
         if args.cpu_sample > len(sample):
             # a larger seeded draw, so that the timed oracle run is 10-30 s of CPU work
+            from vp_workloads import generators as gen
             sample = gen.sample_indices(wl.m, args.cpu_sample, 110)
         sample = sample[: args.cpu_sample]
         log(f"[bench] oracle on {len(sample)} sampled targets x {wl.n} nodes ({direct.num_threads()} threads)")

@@ -205,7 +205,7 @@ static void free_plan(vp_plan_s *P) {
     if (P->stream) (void)hipStreamSynchronize(P->stream);
     else (void)hipDeviceSynchronize();
     vp::release_streams(P);
-    for (hipEvent_t e : {P->ev_fork, P->ev_join, P->ev_p2m, P->ev_p2l, P->ev_upper, P->ev_coarse, P->ev_m2l, P->ev_m2p})
+    for (hipEvent_t e : {P->ev_fork, P->ev_join, P->ev_p2m, P->ev_p2l, P->ev_upper, P->ev_coarse, P->ev_m2p})
         if (e) (void)hipEventDestroy(e);
     release_timing(P);
     P->mem.free_all();
@@ -245,7 +245,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->stream = static_cast<hipStream_t>(o.stream);
         VP_HIP(hipGetDevice(&P->device));
         vp::acquire_streams(P);
-        for (hipEvent_t *e : {&P->ev_fork, &P->ev_join, &P->ev_p2m, &P->ev_p2l, &P->ev_upper, &P->ev_coarse, &P->ev_m2l, &P->ev_m2p})
+        for (hipEvent_t *e : {&P->ev_fork, &P->ev_join, &P->ev_p2m, &P->ev_p2l, &P->ev_upper, &P->ev_coarse, &P->ev_m2p})
             VP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
         P->err_flag = P->mem.alloc<int32_t>(1);
         P->w_user = P->mem.alloc<double>(n);

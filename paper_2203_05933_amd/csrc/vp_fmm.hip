@@ -1959,12 +1959,6 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         }
         P->stage_end(VP_STAGE_P2P);
     };
-    // the second stream's work is enqueued in two parts: before the plan's
-    // stream reaches M2L, and after (when it may wait for that M2L, so that
-    // the rest overlaps the latency-bound passes after it)
-    auto wait_m2l = [&] {
-        if (!one && fmm) VP_HIP(hipStreamWaitEvent(s2, P->ev_m2l, 0));
-    };
     // with tables both near-field kernels add to zeroed potentials
     if (tables) fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
     corr();
@@ -2018,15 +2012,11 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         P->stage_begin(VP_STAGE_M2L);
         launch_m2l<E>(P, 0);
         P->stage_end(VP_STAGE_M2L);
-        if (!one) VP_HIP(hipEventRecord(P->ev_m2l, ms));
     } else if (!one) {
         VP_HIP(hipStreamWaitEvent(ms, P->ev_p2l, 0));  // join the third stream
     }
-    // second stream, second part
-    P->stream = s2;
-    (void)wait_m2l;
+    // the second stream's end: the near field and the W lists
     if (!one) VP_HIP(hipEventRecord(P->ev_join, s2));
-    P->stream = ms;
     if (fmm) {
         if (coarse && !one) VP_HIP(hipStreamWaitEvent(ms, P->ev_coarse, 0));
         P->stage_begin(VP_STAGE_L2L);

@@ -259,8 +259,7 @@ struct vp_plan_s {
     // split_level (few boxes, latency bound) beside the M2L of the levels above
     hipStream_t aux2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_p2m = nullptr, ev_p2l = nullptr, ev_upper = nullptr, ev_coarse = nullptr, ev_m2l = nullptr,
-               ev_m2p = nullptr;
+    hipEvent_t ev_p2m = nullptr, ev_p2l = nullptr, ev_upper = nullptr, ev_coarse = nullptr, ev_m2p = nullptr;
     int device = 0;
     std::string err;
     bool poisoned = false;
