@@ -1419,20 +1419,8 @@ void build_schedules(vp_plan_s *P) {
 }
 
 // ----------------------------------------------------------------------------
-// Gather-GEMM launches (square PD x PD operators of the expansion stages)
+// Gather-GEMM launches of the per-offset M2L form
 // ----------------------------------------------------------------------------
-template <class TI, class TO, class TM, bool SPLIT, bool ACCUM, int RB>
-static void launch_sq(hipStream_t s, const TranslateArgs &a, const TM *Ahi, const TM *Alo, const TI *in,
-                      TO *out) {
-    constexpr int S = RB * 4;
-    constexpr bool LDSA = translate_ldsa<TM, RB, S, SPLIT>();
-    constexpr size_t lds = translate_lds_bytes<TM, RB, S, SPLIT>();
-    const unsigned blocks = (unsigned)((a.ncols + 63) / 64);
-    hipLaunchKernelGGL((k_translate<TI, TO, TM, RB, S, SPLIT, ACCUM, LDSA>), dim3(blocks), dim3(256),
-                       LDSA ? lds : 0, s, a, Ahi, Alo, in, out);
-    VP_LAUNCH_CHECK();
-}
-
 template <class TI, class TO, class TM, bool SPLIT, int RB>
 static void launch_split(hipStream_t s, const TranslateArgs &a, const TM *Ahi, const TM *Alo, const TI *in,
                          TO *out) {
@@ -1474,23 +1462,6 @@ static void m2l_scaled(hipStream_t s, int PQ, const M2LScaledArgs &a, const TM *
         default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
     }
     VP_LAUNCH_CHECK();
-}
-
-template <class TI, class TO, class TM, bool SPLIT, bool ACCUM>
-static void translate_sq(hipStream_t s, int PD, const TranslateArgs &a, const TM *Ahi, const TM *Alo,
-                         const TI *in, TO *out) {
-    if (a.ncols <= 0) return;
-    switch (PD) {
-        case 16: launch_sq<TI, TO, TM, SPLIT, ACCUM, 1>(s, a, Ahi, Alo, in, out); break;
-        case 32: launch_sq<TI, TO, TM, SPLIT, ACCUM, 2>(s, a, Ahi, Alo, in, out); break;
-        case 48: launch_sq<TI, TO, TM, SPLIT, ACCUM, 3>(s, a, Ahi, Alo, in, out); break;
-        case 64: launch_sq<TI, TO, TM, SPLIT, ACCUM, 4>(s, a, Ahi, Alo, in, out); break;
-        case 80: launch_sq<TI, TO, TM, SPLIT, ACCUM, 5>(s, a, Ahi, Alo, in, out); break;
-        case 96: launch_sq<TI, TO, TM, SPLIT, ACCUM, 6>(s, a, Ahi, Alo, in, out); break;
-        case 112: launch_sq<TI, TO, TM, SPLIT, ACCUM, 7>(s, a, Ahi, Alo, in, out); break;
-        case 128: launch_sq<TI, TO, TM, SPLIT, ACCUM, 8>(s, a, Ahi, Alo, in, out); break;
-        default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
-    }
 }
 
 static TranslateArgs expansion_args(vp_plan_s *P, const int32_t *cols, int nboxes, const int32_t *slots, int nops,

@@ -5,15 +5,17 @@
 //
 // A column is a (box, density) pair; src(col, o) is the box in slot o of the
 // column's box (or none).  Uses:
-//   M2L          40 outer offsets, A_o = M2L operator (+ the A_0 log s row)
-//   M2M          4 child quadrants, A_q = child-to-parent shift
-//   L2L          4 child classes, A_q = parent-to-child shift
-//   near tables  9 neighbour offsets of congruent leaves, A_o = G matrix
-//   P2M / L2P    1 operator on congruent leaves (powers of the pattern)
-// The operator of the current slot is staged once in LDS and shared by the
-// four waves of a workgroup; each wave owns 16 columns.  Operators are
-// stored in A-fragment order [o][rb][s][lane], element (row rb*16 + l%16,
-// k = 4 s + l/16), so staging is a straight coalesced copy.
+//   M2L          40 outer offsets, A_o = M2L operator (+ the A_0 log s row):
+//                the per-offset form, k_translate_split (the default M2L is
+//                the diagonally scaled kernel of vp_m2l_scaled.hpp)
+//   near tables  neighbour positions of congruent leaves, A_o = G matrix
+//                (k_translate_split)
+//   P2M          5 operators on congruent leaves (leaf and quadrants, k_translate)
+//   L2P          1 operator on congruent leaves (k_pattern_op)
+// k_translate stages the operator of the current slot once in LDS and shares
+// it between the four waves of a workgroup, each wave owning 16 columns.
+// Operators are stored in A-fragment order [o][rb][s][lane], element
+// (row rb*16 + l%16, k = 4 s + l/16), so staging is a straight coalesced copy.
 #pragma once
 
 #include "vp_internal.hpp"
