@@ -362,6 +362,54 @@ def test_correction_cells(nbatch):
     plan.close()
 
 
+@pytest.mark.parametrize("nbatch", [1, 2])
+def test_correction_cells_64_columns(nbatch):
+    """Cells of 64 columns, the two-rows-per-load path of the cell apply
+    (one density, values 16-byte aligned; one such cell has only 20 rows, a
+    partial batch of 16), next to cells where it does not apply: a 45-node
+    cell shifts the later cells' values to odd offsets.  Forward and adjoint
+    against the oracle."""
+    vp = _vp()
+    rng = np.random.default_rng(71 + nbatch)
+    # (first row, rows, first column, columns) of each cell, in row order;
+    # values start at even offsets up to the 45-node cell, at odd ones after it
+    cells = []
+    start = 0
+    for sz in (64, 64):
+        cells.append((start, sz, start, sz))
+        start += sz
+    cells.append((start, 20, start, 64))  # 20 rows over 64 columns
+    cells.append((start + 20, 44, start + 20, 44))
+    start += 64
+    for sz in (45, 64, 64):
+        cells.append((start, sz, start, sz))
+        start += sz
+    n = start
+    x = rng.uniform(-1, 1, n)
+    y = rng.uniform(-1, 1, n)
+    w = rng.uniform(0.1, 1, n) / n
+    lens, cols = [], []
+    for r0, nr, c0, nc in cells:
+        for _ in range(nr):
+            lens.append(nc)
+            cols.extend(range(c0, c0 + nc))
+    rowptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.asarray(cols, dtype=np.int32)
+    val = rng.standard_normal(col.size)
+    f = rng.standard_normal((nbatch, n))
+    plan = vp.Plan(x, y, w, rowptr=rowptr, col=col, val=val, order=30, max_leaf=32, nbatch=nbatch,
+                   root=(-1.0, -1.0, 2.0))
+    assert plan.info()["corr_cells"] == len(cells)
+    u = _host(plan.eval(_dev(f)))
+    ref = direct.evaluate(x, y, w, f, rowptr, col, val)
+    assert max(relinf(u[b], ref[b]) for b in range(nbatch)) <= TOL64
+    g = rng.standard_normal((nbatch, n))
+    d = _host(plan.eval_adjoint(_dev(g)))
+    dref = direct.evaluate_adjoint(x, y, w, g, rowptr, col, val)
+    assert max(relinf(d[b], dref[b]) for b in range(nbatch)) <= TOL64
+    plan.close()
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65])
 def test_small_inputs(n):
     vp = _vp()
