@@ -1889,11 +1889,11 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         VP_HIP(hipStreamWaitEvent(s2, P->ev_fork, 0));
         VP_HIP(hipStreamWaitEvent(s3, P->ev_fork, 0));
     }
-    // third stream: P2L (needs only the charges); zero the far-field sums,
-    // which stay apart from the near field so that the near field can run
-    // to the end of the evaluation
+    // third stream: the VALU P2M first (the upward pass waits for it), P2L
+    // (needs only the charges), then zero the far-field sums, which stay
+    // apart from the near field so that the near field can run to the end of
+    // the evaluation (ev_p2l covers the zeroing)
     P->stream = s3;
-    if (!grad) fill_f64(P->acc_far, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
     if (fmm) {
         // VALU leaf multipoles (the fixed-matrix ones run on the plan's stream)
         P->stage_begin(VP_STAGE_P2M);
@@ -1904,6 +1904,7 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         run_p2l<E>(P, R, G);
         P->stage_end(VP_STAGE_P2L);
     }
+    if (!grad) fill_f64(P->acc_far, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
     if (!one) VP_HIP(hipEventRecord(P->ev_p2l, s3));
     // second stream: correction (HBM bound) and the near field
     P->stream = s2;
@@ -1971,7 +1972,15 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
     // near tables and the pairwise near field, once every multipole is done
     P->stream = s2;
     if (w_apart) {
-        if (!one) VP_HIP(hipStreamWaitEvent(s2, coarse ? P->ev_m2p : P->ev_upper, 0));
+        if (!one) {
+            // every multipole (and, through the third stream, the zeroed far-field sums)
+            if (coarse) {
+                VP_HIP(hipStreamWaitEvent(s2, P->ev_m2p, 0));
+            } else {
+                VP_HIP(hipStreamWaitEvent(s2, P->ev_upper, 0));
+                VP_HIP(hipStreamWaitEvent(s2, P->ev_p2l, 0));
+            }
+        }
         P->stage_begin(VP_STAGE_M2P);
         run_far<E, false>(P, R, G, P->acc_far, tables, 2);
         P->stage_end(VP_STAGE_M2P);
