@@ -227,8 +227,9 @@ enum {
                             M2M, M2L and L2L hold the levels from split_level on */
     VP_STAGE_P2M_PAT = 12,/* P2M by fixed matrices (pattern leaves and their quadrants);
                              P2M holds the VALU P2M of the other leaves (third stream) */
-    VP_STAGE_M2P = 13,   /* W-list multipoles at the targets (third stream); FAR holds the
-                            local expansions at the targets (with gradients: both) */
+    VP_STAGE_M2P = 13,   /* W-list multipoles at the targets (second stream, between the
+                            tables and the pairwise kernel); FAR holds the local expansions
+                            at the targets (with gradients: both) */
     VP_NSTAGES = 14
 };
 vp_status vp_set_timing(vp_plan_t plan, int32_t enable);
