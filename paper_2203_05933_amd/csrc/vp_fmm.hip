@@ -928,7 +928,7 @@ __global__ void __launch_bounds__(256) k_corr_cells(int ncell, const int32_t *__
                                                     const double *__restrict__ valv,
                                                     const double *__restrict__ f, int64_t flen, int64_t nrows,
                                                     double *__restrict__ out) {
-    constexpr int R = NBG == 1 ? 4 : (NBG == 2 ? 2 : 1);  // rows per batch (R x NBG sums in registers)
+    constexpr int R = 4;  // rows per batch (R x NBG sums in registers; fewer shuffles per row)
     const int lane = threadIdx.x & 63;
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
