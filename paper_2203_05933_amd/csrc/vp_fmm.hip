@@ -937,6 +937,32 @@ __global__ void __launch_bounds__(256) k_corr_cells(int ncell, const int32_t *__
         const int r0 = cell_row[cc], r1 = cell_row[cc + 1], c0 = cell_col[cc];
         const int64_t vb = rowptr[r0];
         const int len = (int)(rowptr[r0 + 1] - vb);
+        if (NBG >= 4 && len == 64) {
+            // several densities: per cell U = V F, V the cell's rows x 64 values
+            // and F its 64 columns x (up to 16) densities, on the matrix cores
+            // in 16-row blocks (A = V rows, B = F, k = 4 s + lane/16)
+            typedef Mfma<double> M;
+            const int cl = lane & 15, g = lane >> 4;
+            double bf[16];
+            const double *fp = f + (int64_t)(bt0 + min(cl, nbg - 1)) * flen + c0 + g;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) bf[s] = fp[4 * s];
+            for (int rb0 = r0; rb0 < r1; rb0 += 16) {
+                const double *vp = valv + vb + (int64_t)(min(rb0 + cl, r1 - 1) - r0) * 64 + g;
+                double av[16];
+#pragma unroll
+                for (int s = 0; s < 16; ++s) av[s] = vp[4 * s];
+                M::acc_t acc = M::zero();
+#pragma unroll
+                for (int s = 0; s < 16; ++s) acc = M::op(av[s], bf[s], acc);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = rb0 + M::row(i, g);
+                    if (row < r1 && cl < nbg) out[(int64_t)(bt0 + cl) * nrows + row] = acc[i];
+                }
+            }
+            continue;
+        }
         if (NBG == 1 && len == 64 && (vb & 1) == 0) {
             // 64-column cells with 16-byte aligned values (the box cells): a
             // half-wave per row, each lane two adjacent columns, so one load
