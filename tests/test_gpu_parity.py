@@ -212,15 +212,23 @@ def test_grad_targets():
     plan.close()
 
 
-def test_batched_densities(c0):
+@pytest.mark.parametrize("nbatch", [3, 5])
+def test_batched_densities(c0, nbatch):
+    """Several densities in one evaluation (5: the near tables and the cell
+    correction take their several-density forms)."""
     vp = _vp()
-    fs = np.stack([gen.gaussian_sum_density(c0.x, c0.y, s)[0] for s in (30, 31, 32)])
-    plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=30, nbatch=3,
+    fs = np.stack([gen.gaussian_sum_density(c0.x, c0.y, s)[0] for s in range(30, 30 + nbatch)])
+    plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=30, nbatch=nbatch,
                    root=c0.root)
     u = _host(plan.eval(_dev(fs)))
     ref = direct.evaluate(c0.x, c0.y, c0.w, fs, c0.rowptr, c0.col, c0.val)
-    for b in range(3):
+    for b in range(nbatch):
         assert relinf(u[b], ref[b]) <= TOL64
+    g = np.random.default_rng(8).standard_normal((nbatch, c0.n))
+    d = _host(plan.eval_adjoint(_dev(g)))
+    dref = direct.evaluate_adjoint(c0.x, c0.y, c0.w, g, c0.rowptr, c0.col, c0.val)
+    for b in range(nbatch):
+        assert relinf(d[b], dref[b]) <= TOL64
     plan.close()
 
 
