@@ -20,10 +20,10 @@
 // so the tile shares its offsets) per workgroup; the four waves take every
 // fourth offset present in the tile (listed at plan time, with each column's
 // source box) and their partial sums are added through LDS in a fixed order.
-// The diagonal scalings of all 40 offsets sit in LDS for the whole tile, and
-// the next offset's source columns are loaded while the current offset is on
-// the matrix cores; the loop has no branch around a load and no dependent
-// global load.
+// The diagonal scalings of all 40 offsets sit in LDS for the whole tile and
+// the lane's Q fragments in registers; the loop has no branch around a load
+// and no dependent global load, and at 166 registers three waves share each
+// SIMD, so the other waves' products cover one wave's column loads.
 #pragma once
 
 #include "vp_translate.hpp"
@@ -84,7 +84,6 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
     __shared__ __align__(16) unsigned char s_raw[TBYTES > RBYTES ? TBYTES : RBYTES];
     __shared__ int32_t s_ops[NOFF];
     __shared__ int32_t s_src[NOFF][16];
-    __shared__ TM s_q[RB * S][64];  // Q fragments: [r * S + s][lane], k = (lane/16) S + s
     TM *s_tin = reinterpret_cast<TM *>(s_raw);
     double *s_logt = reinterpret_cast<double *>(s_raw + TAB * sizeof(TM));
     double(*red)[NR][64] = reinterpret_cast<double(*)[NR][64]>(s_raw);
@@ -109,11 +108,14 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
         for (int i = tid; i < CH; i += 256) si[i] = gi[i];
         if (tid < 2 * NOFF) s_logt[tid] = logt[tid];
     }
-    for (int i = tid; i < RB * S * 64; i += 256) {
-        const int rs = i >> 6, ln = i & 63, r = rs / S, s = rs % S;
-        const int k = (ln >> 4) * S + s;
-        s_q[rs][ln] = Qf[(r * S + (k >> 2)) * 64 + (k & 3) * 16 + (ln & 15)];
-    }
+    TM q[RB][S];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int k = g * S + s;
+            q[r][s] = Qf[(r * S + (k >> 2)) * 64 + (k & 3) * 16 + cl];
+        }
     __syncthreads();
 
     double br[RB][4], bi[RB][4];
@@ -146,8 +148,9 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
             a0r += x0r;
             a0i += x0i;
         }
-        // the next offset's source columns: coefficient s is loaded as soon
-        // as the current one is scaled, and is in flight during the products
+        // the next offset's source columns, into the registers the current
+        // coefficients free once scaled (the compiler issues these loads at
+        // the top of the next iteration, as eight 16-byte loads)
         const int en = e + 4;
         const int srcn = en < nt ? s_src[en][cl] : -1;
         const TI *ipn = srcn >= 0 ? in + (int64_t)srcn * a.box_stride + bt_off : zc;
@@ -169,7 +172,7 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
             xi[s] = (TM)pni[s];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                const TM qv = s_q[r * S + s][lane];
+                const TM qv = q[r][s];
                 zr[r] = M::op(qv, yr, zr[r]);
                 zi[r] = M::op(qv, yi, zi[r]);
             }
