@@ -38,12 +38,12 @@ P2P_FLOPS_PER_PAIR = 27     # 2 differences, 3 for r^2, 20 for log(r^2), 2 for t
 # reads half the bytes, WRITE_SIZE all of them).  Valid only for the kernel
 # sources they were taken on: the digest below covers every file of the
 # library's source directory, and any change there turns traffic into null.
-TRAFFIC_DIGEST = "752ee1cbde6f28231b7f3a2e50aed8536d06f5a75750ff9e2b4a4e03191edaeb"
+TRAFFIC_DIGEST = "aed33412e026dd480a4694077231d2ab24b32eba5c6ab79fd83380e2ed8706db"
 TRAFFIC_WORKLOAD = "star_adaptive"
 TRAFFIC = {  # stage -> (read bytes, written bytes) per launch, FP64 p = 30, one density
-    "corr": (753056374, 11911958),  # k_corr_cells
-    "m2l": (251376923, 18842083),  # k_m2l_scaled, levels from the split level on
-    "p2p": (92127986, 3547124),
+    "corr": (91672277, 11910421),  # k_corr_cells
+    "m2l": (251323045, 18843162),  # k_m2l_scaled, levels from the split level on
+    "p2p": (92094663, 3548208),
 }
 
 
@@ -155,15 +155,20 @@ def _stage_roofline(plan, tim, precision, stage):
     if stage == "corr":
         nnz, m, n_, cells = info["nnz"], info["m"], info["n"], info["corr_cells"]
         if cells > 0:
-            # per cell: first row, run start, two row pointers; f read once, outputs written
-            bytes_ = nnz * 8 + cells * (4 + 4 + 16) + m * 8 * nb + n_ * 8 * nb
-            kern, what = "k_corr_cells", f"{nnz} values x 8 B + {cells} cell records"
+            # distinct values (cells with an identical block read one copy); per cell:
+            # first row, run start, value offset, two row pointers; f read once, outputs written
+            nval, shared = info["corr_values_read"], info["corr_shared_cells"]
+            bytes_ = nval * 8 + cells * (4 + 4 + 8 + 16) + m * 8 * nb + n_ * 8 * nb
+            kern, what = "k_corr_cells", (f"{nval} distinct values of {nnz} x 8 B ({shared} of {cells} cells "
+                                          f"share an identical block) + {cells} cell records")
         else:
             bytes_ = nnz * 8 + (m + 1) * 8 + m * 4 + m * 8 * nb + n_ * 8 * nb
             kern, what = "k_corr", f"{nnz} values x 8 B + row pointers and runs"
         return {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": 8000.0, "unit": "GB/s",
                 "frac": bytes_ / avg_s / 1e9 / 8000.0, "traffic": None, "kernel": kern,
-                "avg_ms": avg_s * 1e3, "work": f"{what}, f read once, {nb} output rows written"}
+                "avg_ms": avg_s * 1e3, "work": f"{what}, f read once, {nb} output rows written",
+                # every value the kernel loads, shared blocks included (those come from the caches)
+                "values_loaded_gbs": nnz * 8 / avg_s / 1e9}
     return None
 
 

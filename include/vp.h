@@ -179,6 +179,11 @@ typedef struct {
                                   beside the M2L of the levels from it on (2: none below) */
     int32_t corr_cells;        /* cells of C applied cell by cell (consecutive rows sharing one
                                   column run); 0: the row kernel applies C */
+    int32_t corr_shared_cells; /* of corr_cells, those whose value block is bit for bit that of an
+                                  earlier cell and which read that cell's copy (the box corrections
+                                  of one box size are one table, Section 4) */
+    int64_t corr_values_read;  /* distinct values of C one forward apply reads: nnz less the
+                                  values of the shared cells */
     double root[3];
 } vp_plan_info_t;
 

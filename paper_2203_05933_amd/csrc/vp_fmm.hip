@@ -22,6 +22,7 @@
 // FP32-bulk form.  Every reduction has a fixed order: no atomics.
 
 #include <algorithm>
+#include <unordered_map>
 
 #include "vp_internal.hpp"
 #include "vp_translate.hpp"
@@ -923,7 +924,8 @@ __global__ void __launch_bounds__(256) k_corr(int64_t nrows, int nbatch, int bt0
 // lanes of each row are summed (a fixed order: deterministic).
 template <int NBG>
 __global__ void __launch_bounds__(256) k_corr_cells(int ncell, const int32_t *__restrict__ cell_row,
-                                                    const int32_t *__restrict__ cell_col, int nbatch, int bt0,
+                                                    const int32_t *__restrict__ cell_col,
+                                                    const int64_t *__restrict__ cell_vb, int nbatch, int bt0,
                                                     const int64_t *__restrict__ rowptr,
                                                     const double *__restrict__ valv,
                                                     const double *__restrict__ f, int64_t flen, int64_t nrows,
@@ -935,8 +937,8 @@ __global__ void __launch_bounds__(256) k_corr_cells(int ncell, const int32_t *__
     const int nbg = min(NBG, nbatch - bt0);
     for (int64_t cc = w; cc < ncell; cc += nw) {
         const int r0 = cell_row[cc], r1 = cell_row[cc + 1], c0 = cell_col[cc];
-        const int64_t vb = rowptr[r0];
-        const int len = (int)(rowptr[r0 + 1] - vb);
+        const int64_t vb = cell_vb[cc];  // this cell's values, or an identical block's
+        const int len = (int)(rowptr[r0 + 1] - rowptr[r0]);
         if (NBG >= 4 && len == 64) {
             // several densities: per cell U = V F, V the cell's rows x 64 values
             // and F its 64 columns x (up to 16) densities, on the matrix cores
@@ -1091,6 +1093,49 @@ __global__ void k_detect_runs(const int64_t *__restrict__ rowptr, const int32_t 
 
 void build_cells(vp_plan_s *P, bool transposed);
 
+// Plan time: a 64-bit fingerprint of each cell's value block (one wave per
+// cell; every value's bits mixed with its position, xor over the block).
+__device__ inline uint64_t vp_mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+__global__ void __launch_bounds__(256) k_cell_hash(int ncell, const int32_t *__restrict__ cell_row,
+                                                   const int64_t *__restrict__ rowptr,
+                                                   const double *__restrict__ val, uint64_t *__restrict__ hash) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t cc = w; cc < ncell; cc += nw) {
+        const int64_t v0 = rowptr[cell_row[cc]], v1 = rowptr[cell_row[cc + 1]];
+        uint64_t h = 0;
+        for (int64_t e = v0 + lane; e < v1; e += 64)
+            h ^= vp_mix64((uint64_t)__double_as_longlong(val[e]) + (uint64_t)(e - v0) * 0x9e3779b97f4a7c15ull);
+        for (int b = 32; b >= 1; b >>= 1) h ^= (uint64_t)__shfl_xor((unsigned long long)h, b, 64);
+        if (lane == 0) hash[cc] = h ^ vp_mix64((uint64_t)(v1 - v0));
+    }
+}
+// Plan time: same[i] = 1 when candidate cell cand[i] holds exactly the
+// values of cell rep[i] (same length, bit for bit)
+__global__ void __launch_bounds__(256) k_cell_same(int ncand, const int32_t *__restrict__ cand,
+                                                   const int32_t *__restrict__ rep,
+                                                   const int32_t *__restrict__ cell_row,
+                                                   const int64_t *__restrict__ rowptr,
+                                                   const double *__restrict__ val, int32_t *__restrict__ same) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = w; i < ncand; i += nw) {
+        const int64_t a0 = rowptr[cell_row[cand[i]]], a1 = rowptr[cell_row[cand[i] + 1]];
+        const int64_t b0 = rowptr[cell_row[rep[i]]], b1 = rowptr[cell_row[rep[i] + 1]];
+        bool eq = (a1 - a0) == (b1 - b0);
+        for (int64_t e = lane; eq && e < a1 - a0; e += 64)
+            eq = __double_as_longlong(val[a0 + e]) == __double_as_longlong(val[b0 + e]);
+        const bool all = __all(eq);
+        if (lane == 0) same[i] = all ? 1 : 0;
+    }
+}
+
 void detect_runs(vp_plan_s *P) {
     hipStream_t s = P->stream;
     P->run_start = P->mem.alloc<int32_t>(P->m);
@@ -1146,8 +1191,63 @@ void build_cells(vp_plan_s *P, bool transposed) {
     cell_col = P->mem.alloc<int32_t>(col0.size());
     VP_HIP(hipMemcpyAsync(cell_row, row0.data(), 4 * row0.size(), hipMemcpyHostToDevice, s));
     VP_HIP(hipMemcpyAsync(cell_col, col0.data(), 4 * col0.size(), hipMemcpyHostToDevice, s));
+    const int nc = (int)col0.size();
+    // cells with identical value blocks (the box corrections of one box size
+    // are one lookup table, Section 4): each reads the first such cell's
+    // values, which then stay in the caches; found by fingerprint, then
+    // confirmed bit for bit on the device
+    const double *vv = transposed ? P->valT : P->val;
+    const int64_t *rpd = transposed ? P->rowptrT : P->rowptr;
+    uint64_t *dh = P->mem.alloc<uint64_t>(nc);
+    const unsigned hb = (unsigned)std::min<int64_t>((nc + 3) / 4, 16384);
+    hipLaunchKernelGGL(k_cell_hash, dim3(hb), dim3(256), 0, s, nc, cell_row, rpd, vv, dh);
+    VP_LAUNCH_CHECK();
+    std::vector<uint64_t> hh(nc);
+    VP_HIP(hipMemcpyAsync(hh.data(), dh, 8 * (size_t)nc, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> vbh(nc);
+    for (int k = 0; k < nc; ++k) vbh[k] = rp[row0[k]];
+    std::unordered_map<uint64_t, int> first;
+    std::vector<int32_t> cand, rep;
+    for (int k = 0; k < nc; ++k) {
+        const int rows = row0[k + 1] - row0[k];
+        const uint64_t key = hh[k] ^ ((uint64_t)rows * 0x9e3779b97f4a7c15ull);
+        auto it = first.find(key);
+        if (it == first.end()) first.emplace(key, k);
+        else {
+            cand.push_back(k);
+            rep.push_back(it->second);
+        }
+    }
+    int nshared = 0;
+    int64_t nread = P->nnz;
+    if (!cand.empty()) {
+        int32_t *dc = P->mem.alloc<int32_t>(cand.size()), *dr = P->mem.alloc<int32_t>(rep.size());
+        int32_t *ds = P->mem.alloc<int32_t>(cand.size());
+        VP_HIP(hipMemcpyAsync(dc, cand.data(), 4 * cand.size(), hipMemcpyHostToDevice, s));
+        VP_HIP(hipMemcpyAsync(dr, rep.data(), 4 * rep.size(), hipMemcpyHostToDevice, s));
+        const unsigned sb = (unsigned)std::min<int64_t>(((int64_t)cand.size() + 3) / 4, 16384);
+        hipLaunchKernelGGL(k_cell_same, dim3(sb), dim3(256), 0, s, (int)cand.size(), dc, dr, cell_row, rpd, vv, ds);
+        VP_LAUNCH_CHECK();
+        std::vector<int32_t> same(cand.size());
+        VP_HIP(hipMemcpyAsync(same.data(), ds, 4 * same.size(), hipMemcpyDeviceToHost, s));
+        VP_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < cand.size(); ++i)
+            if (same[i]) {
+                vbh[cand[i]] = rp[row0[rep[i]]];
+                ++nshared;
+                nread -= rp[row0[cand[i] + 1]] - rp[row0[cand[i]]];
+            }
+    }
+    int64_t *&cvb = transposed ? P->cell_vbT : P->cell_vb;
+    cvb = P->mem.alloc<int64_t>(nc);
+    VP_HIP(hipMemcpyAsync(cvb, vbh.data(), 8 * (size_t)nc, hipMemcpyHostToDevice, s));
     VP_HIP(hipStreamSynchronize(s));  // host vectors leave scope
-    ncell = (int)col0.size();
+    if (!transposed) {
+        P->ncell_shared = nshared;
+        P->corr_values_read = nread;
+    }
+    ncell = nc;
 }
 
 __global__ void k_unpermute_grad(int64_t m, int nbatch, const int32_t *__restrict__ inv,
@@ -2070,6 +2170,7 @@ static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjo
     } else if (ncell > 0) {
         const int32_t *crow = adjoint ? P->cell_rowT : P->cell_row;
         const int32_t *ccol = adjoint ? P->cell_colT : P->cell_col;
+        const int64_t *cvb = adjoint ? P->cell_vbT : P->cell_vb;
         const unsigned cblocks = (unsigned)std::min<int64_t>((ncell + 3) / 4, 16384);
         for (int bt0 = 0; bt0 < P->nbatch;) {
             const int left = P->nbatch - bt0;
@@ -2077,7 +2178,7 @@ static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjo
             switch (g) {
 #define VP_CELLS(G)                                                                                              \
     case G:                                                                                                      \
-        hipLaunchKernelGGL((k_corr_cells<G>), dim3(cblocks), dim3(256), 0, P->stream, ncell, crow, ccol,         \
+        hipLaunchKernelGGL((k_corr_cells<G>), dim3(cblocks), dim3(256), 0, P->stream, ncell, crow, ccol, cvb,    \
                            P->nbatch, bt0, rp, vv, f, flen, nrows, u);                                           \
         break;
                 VP_CELLS(16) VP_CELLS(8) VP_CELLS(4) VP_CELLS(2) VP_CELLS(1)

@@ -287,6 +287,11 @@ struct vp_plan_s {
     // first rows, [ncell] first columns; ncell = 0: the row kernel applies C
     int32_t *cell_row = nullptr, *cell_col = nullptr, *cell_rowT = nullptr, *cell_colT = nullptr;
     int ncell = 0, ncellT = 0;
+    // offset of the values each cell reads: its own, or those of the first
+    // cell with an identical block (found at plan time, compared exactly)
+    int64_t *cell_vb = nullptr, *cell_vbT = nullptr;
+    int ncell_shared = 0;           // cells reading another cell's identical block
+    int64_t corr_values_read = 0;   // values the forward apply reads from memory
 
     vp::Tree tree;
     vp::Operators ops;

@@ -62,7 +62,9 @@ class PlanInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_int64), ("m2l_translations", ctypes.c_int64),
                 ("m2l_tile_ops", ctypes.c_int64), ("table_tile_ops", ctypes.c_int64),
                 ("m2l_coarse_translations", ctypes.c_int64), ("m2l_coarse_tile_ops", ctypes.c_int64),
-                ("split_level", ctypes.c_int32), ("corr_cells", ctypes.c_int32), ("root", ctypes.c_double * 3)]
+                ("split_level", ctypes.c_int32), ("corr_cells", ctypes.c_int32),
+                ("corr_shared_cells", ctypes.c_int32), ("corr_values_read", ctypes.c_int64),
+                ("root", ctypes.c_double * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -370,6 +370,54 @@ def test_correction_cells(nbatch):
     plan.close()
 
 
+@pytest.mark.parametrize("nbatch", [1, 4, 16])
+def test_correction_shared_blocks(nbatch):
+    """Cells whose value blocks repeat (the box corrections of one box size are
+    one table, Section 4): a cell with a block identical bit for bit to an
+    earlier cell's reads that cell's copy, also from an odd value offset onto
+    an even one; a block that differs in one bit of one value keeps its own.
+    One density (two-rows-per-load path), 4 (matrix cores) and 16; forward and
+    adjoint against the oracle."""
+    vp = _vp()
+    rng = np.random.default_rng(97 + nbatch)
+    blocks = {k: rng.standard_normal(sz * sz) for k, sz in ((0, 64), (1, 64), (2, 45))}
+    near = blocks[0].copy()
+    near[1000] = np.nextafter(near[1000], np.inf)  # one bit away from block 0
+    blocks[3] = near
+    # (nodes, block) of each square cell, in order; the 45-node cells move the
+    # values after them to odd offsets
+    order = [(64, 0), (64, 0), (64, 1), (64, 3), (45, 2), (64, 0), (64, 1), (45, 2), (30, None)]
+    n = sum(sz for sz, _ in order)
+    x = rng.uniform(-1, 1, n)
+    y = rng.uniform(-1, 1, n)
+    w = rng.uniform(0.1, 1, n) / n
+    lens, cols, vals, start = [], [], [], 0
+    for sz, b in order:
+        for _ in range(sz):
+            lens.append(sz)
+            cols.extend(range(start, start + sz))
+        vals.append(blocks[b] if b is not None else rng.standard_normal(sz * sz))
+        start += sz
+    rowptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.asarray(cols, dtype=np.int32)
+    val = np.concatenate(vals)
+    f = rng.standard_normal((nbatch, n))
+    plan = vp.Plan(x, y, w, rowptr=rowptr, col=col, val=val, order=30, max_leaf=32, nbatch=nbatch,
+                   root=(-1.0, -1.0, 2.0))
+    info = plan.info()
+    assert info["corr_cells"] == len(order)
+    assert info["corr_shared_cells"] == 4  # the second and third block 0, second block 1, second block 2
+    assert info["corr_values_read"] == val.size - 3 * 64 * 64 - 45 * 45
+    u = _host(plan.eval(_dev(f)))
+    ref = direct.evaluate(x, y, w, f, rowptr, col, val)
+    assert max(relinf(u[b], ref[b]) for b in range(nbatch)) <= TOL64
+    g = rng.standard_normal((nbatch, n))
+    d = _host(plan.eval_adjoint(_dev(g)))
+    dref = direct.evaluate_adjoint(x, y, w, g, rowptr, col, val)
+    assert max(relinf(d[b], dref[b]) for b in range(nbatch)) <= TOL64
+    plan.close()
+
+
 @pytest.mark.parametrize("nbatch", [1, 2])
 def test_correction_cells_64_columns(nbatch):
     """Cells of 64 columns, the two-rows-per-load path of the cell apply

@@ -136,13 +136,17 @@ def gaussian_sum_density(x, y, seed: int, ncomp: int = 4, center_box: float = 0.
     return f, {"A": A, "c": c, "sigma": s}
 
 
-def own_cell_csr(cell_ptr: np.ndarray, seed: int, scale: float = 1e-3):
+def own_cell_csr(cell_ptr: np.ndarray, seed: int, scale: float = 1e-3, cell_class=None):
     """Correction matrix whose row i holds the columns of node i's own cell.
 
     cell_ptr[k]..cell_ptr[k+1] is the contiguous node range of cell k; every
     node of a cell gets one row listing all nodes of that cell (sorted,
     diagonal included).  Values are N(0, scale^2) from default_rng(seed),
-    drawn in row-major nnz order.
+    drawn in row-major nnz order.  With cell_class, the cells of one class
+    c >= 0 share one value block drawn from default_rng([seed, c + 1]) (the
+    singular corrections of boxes are one lookup table for all boxes of a
+    size, by translation invariance of G and the identical box mappings);
+    cells of class -1 keep their own values.
     """
     cell_ptr = np.asarray(cell_ptr, dtype=np.int64)
     sizes = np.diff(cell_ptr)
@@ -161,6 +165,17 @@ def own_cell_csr(cell_ptr: np.ndarray, seed: int, scale: float = 1e-3):
         pos += s * s
     rng = np.random.default_rng(seed)
     val = rng.normal(0.0, scale, nnz)
+    if cell_class is not None:
+        blocks = {}
+        pos = 0
+        for k in range(sizes.shape[0]):
+            s = int(sizes[k])
+            c = int(cell_class[k])
+            if c >= 0:
+                if c not in blocks:
+                    blocks[c] = np.random.default_rng([seed, c + 1]).normal(0.0, scale, s * s)
+                val[pos:pos + s * s] = blocks[c]
+            pos += s * s
     return rowptr, col, val
 
 
@@ -184,7 +199,8 @@ def uniform_config(nbox_side: int, f_seeds, csr_seed: Optional[int], sample_seed
         rowptr = col = val = None
     else:
         cell_ptr = np.arange(0, x.shape[0] + 1, 64, dtype=np.int64)
-        rowptr, col, val = own_cell_csr(cell_ptr, csr_seed)
+        # all boxes have one size: one shared correction block
+        rowptr, col, val = own_cell_csr(cell_ptr, csr_seed, cell_class=np.zeros(nbox_side * nbox_side, np.int64))
     sample = None if sample_seed is None else sample_indices(x.shape[0], nsample, sample_seed)
     return Workload(name=name, x=x, y=y, w=w, f=f, tx=None, ty=None, rowptr=rowptr,
                     col=col, val=val, root=(-1.0, -1.0, 2.0), sample=sample,
@@ -383,7 +399,9 @@ def config1(n_sectors: int = 2048, tri_nodes: int = 45):
     ntri = len(tris)
     cell_ptr = np.concatenate([np.arange(0, ntri * tri_nodes + 1, tri_nodes, dtype=np.int64),
                                ntri * tri_nodes + np.arange(64, 64 * len(leaves) + 1, 64, dtype=np.int64)])
-    rowptr, col, val = own_cell_csr(cell_ptr, 12)
+    # triangles: own values each; boxes: one shared block per box level
+    cell_class = np.concatenate([np.full(ntri, -1, np.int64), lv.astype(np.int64)])
+    rowptr, col, val = own_cell_csr(cell_ptr, 12, cell_class=cell_class)
     sample = sample_indices(x.shape[0], 4096, 110)
     return Workload(name="star_adaptive", x=x, y=y, w=w, f=f[None, :], tx=None, ty=None,
                     rowptr=rowptr, col=col, val=val, root=(-1.3, -1.3, 2.6), sample=sample,
