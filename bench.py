@@ -38,12 +38,12 @@ P2P_FLOPS_PER_PAIR = 27     # 2 differences, 3 for r^2, 20 for log(r^2), 2 for t
 # reads half the bytes, WRITE_SIZE all of them).  Valid only for the kernel
 # sources they were taken on: the digest below covers every file of the
 # library's source directory, and any change there turns traffic into null.
-TRAFFIC_DIGEST = "aed33412e026dd480a4694077231d2ab24b32eba5c6ab79fd83380e2ed8706db"
+TRAFFIC_DIGEST = "318eca81ecf7611c5a209f15da79585cd5afd69e2974f37b74ddc8b4f485a31c"
 TRAFFIC_WORKLOAD = "star_adaptive"
 TRAFFIC = {  # stage -> (read bytes, written bytes) per launch, FP64 p = 30, one density
-    "corr": (91672277, 11910421),  # k_corr_cells
-    "m2l": (251323045, 18843162),  # k_m2l_scaled, levels from the split level on
-    "p2p": (92094663, 3548208),
+    "corr": (83605134, 11912327),  # k_corr_group + k_corr_cells
+    "m2l": (250839465, 18844963),  # k_m2l_scaled, levels from the split level on
+    "p2p": (92101604, 3547276),
 }
 
 
@@ -161,6 +161,10 @@ def _stage_roofline(plan, tim, precision, stage):
             bytes_ = nval * 8 + cells * (4 + 4 + 8 + 16) + m * 8 * nb + n_ * 8 * nb
             kern, what = "k_corr_cells", (f"{nval} distinct values of {nnz} x 8 B ({shared} of {cells} cells "
                                           f"share an identical block) + {cells} cell records")
+            if info["corr_groups"] > 0:
+                # one density: cells of a repeated block go 16 at a time through one matrix-core product
+                kern = "k_corr_group + k_corr_cells"
+                what += f", {info['corr_groups']} groups of up to 16 cells"
         else:
             bytes_ = nnz * 8 + (m + 1) * 8 + m * 4 + m * 8 * nb + n_ * 8 * nb
             kern, what = "k_corr", f"{nnz} values x 8 B + row pointers and runs"

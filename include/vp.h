@@ -184,6 +184,9 @@ typedef struct {
                                   of one box size are one table, Section 4) */
     int64_t corr_values_read;  /* distinct values of C one forward apply reads: nnz less the
                                   values of the shared cells */
+    int32_t corr_groups;       /* one density: groups of up to 16 64-column cells reading one
+                                  block, applied together on the matrix cores (0: none) */
+    int32_t reserved0;
     double root[3];
 } vp_plan_info_t;
 

@@ -425,6 +425,8 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->split_level = P->split_level;
     info->corr_cells = P->ncell;
     info->corr_shared_cells = P->ncell_shared;
+    info->corr_groups = P->nbatch == 1 ? P->ngrp : 0;
+    info->reserved0 = 0;
     info->corr_values_read = P->ncell > 0 ? P->corr_values_read : P->nnz;
     info->table_tile_ops = P->near.table_tile_ops;
     for (int k = 0; k < 3; ++k) info->root[k] = P->opt.root[k];

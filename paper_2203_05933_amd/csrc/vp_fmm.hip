@@ -22,6 +22,7 @@
 // FP32-bulk form.  Every reduction has a fixed order: no atomics.
 
 #include <algorithm>
+#include <map>
 #include <unordered_map>
 
 #include "vp_internal.hpp"
@@ -938,6 +939,7 @@ __global__ void __launch_bounds__(256) k_corr_cells(int ncell, const int32_t *__
     for (int64_t cc = w; cc < ncell; cc += nw) {
         const int r0 = cell_row[cc], r1 = cell_row[cc + 1], c0 = cell_col[cc];
         const int64_t vb = cell_vb[cc];  // this cell's values, or an identical block's
+        if (vb < 0) continue;              // applied with its group by k_corr_group
         const int len = (int)(rowptr[r0 + 1] - rowptr[r0]);
         if (NBG >= 4 && len == 64) {
             // several densities: per cell U = V F, V the cell's rows x 64 values
@@ -1092,6 +1094,55 @@ __global__ void k_detect_runs(const int64_t *__restrict__ rowptr, const int32_t 
 }
 
 void build_cells(vp_plan_s *P, bool transposed);
+// One density, cells sharing one value block (the box corrections of one box
+// size, Section 4): U = V [f_1 .. f_16] for up to 16 such cells per wave, on
+// the matrix cores in 16-row blocks; V (rows x 64) is read once per group.
+// grp_cell[16 g + j] is the j-th cell of group g (-1: none); every cell of a
+// group has grp_rows[g] rows of 64 columns and reads the values at grp_vb[g].
+__global__ void __launch_bounds__(256) k_corr_group(int ngrp, const int32_t *__restrict__ grp_cell,
+                                                    const int64_t *__restrict__ grp_vb,
+                                                    const int32_t *__restrict__ grp_rows,
+                                                    const int32_t *__restrict__ cell_row,
+                                                    const int32_t *__restrict__ cell_col,
+                                                    const double *__restrict__ valv,
+                                                    const double *__restrict__ f, double *__restrict__ out) {
+    typedef Mfma<double> M;
+    const int lane = threadIdx.x & 63, cl = lane & 15, g = lane >> 4;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t gi = w; gi < ngrp; gi += nw) {
+        const int cell = grp_cell[gi * 16 + cl];
+        const int R = grp_rows[gi];
+        const int64_t vb = grp_vb[gi];
+        // B = F: column cl is cell `cell`'s 64 densities, k = 4 s + lane/16
+        double bf[16];
+        int r0 = 0;
+        if (cell >= 0) {
+            r0 = cell_row[cell];
+            const double *fp = f + cell_col[cell] + g;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) bf[s] = fp[4 * s];
+        } else {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) bf[s] = 0.0;
+        }
+        for (int rb = 0; rb < R; rb += 16) {
+            const double *vp = valv + vb + (int64_t)min(rb + cl, R - 1) * 64 + g;
+            double av[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) av[s] = vp[4 * s];
+            M::acc_t acc = M::zero();
+#pragma unroll
+            for (int s = 0; s < 16; ++s) acc = M::op(av[s], bf[s], acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = rb + M::row(i, g);
+                if (row < R && cell >= 0) out[r0 + row] = acc[i];
+            }
+        }
+    }
+}
+
 
 // Plan time: a 64-bit fingerprint of each cell's value block (one wave per
 // cell; every value's bits mixed with its position, xor over the block).
@@ -1242,6 +1293,43 @@ void build_cells(vp_plan_s *P, bool transposed) {
     int64_t *&cvb = transposed ? P->cell_vbT : P->cell_vb;
     cvb = P->mem.alloc<int64_t>(nc);
     VP_HIP(hipMemcpyAsync(cvb, vbh.data(), 8 * (size_t)nc, hipMemcpyHostToDevice, s));
+    // one density: 64-column cells reading one block, at least 8 of them,
+    // go to k_corr_group in groups of 16; the cell kernel skips them (-1)
+    std::map<std::pair<int64_t, int>, std::vector<int32_t>> bykey;
+    for (int k = 0; k < nc; ++k) {
+        const int rows = row0[k + 1] - row0[k];
+        if (rows > 0 && rp[row0[k] + 1] - rp[row0[k]] == 64) bykey[{vbh[k], rows}].push_back(k);
+    }
+    std::vector<int64_t> vbg(vbh), gvb;
+    std::vector<int32_t> gcell, grows;
+    for (auto &kv : bykey) {
+        if (kv.second.size() < 8) continue;
+        for (size_t i = 0; i < kv.second.size(); i += 16) {
+            for (size_t j = i; j < i + 16; ++j) {
+                const int32_t k = j < kv.second.size() ? kv.second[j] : -1;
+                gcell.push_back(k);
+                if (k >= 0) vbg[k] = -1;
+            }
+            gvb.push_back(kv.first.first);
+            grows.push_back(kv.first.second);
+        }
+    }
+    int &ng = transposed ? P->ngrpT : P->ngrp;
+    ng = (int)gvb.size();
+    if (ng > 0) {
+        int64_t *&cvbg = transposed ? P->cell_vbgT : P->cell_vbg;
+        int32_t *&gc = transposed ? P->grp_cellT : P->grp_cell;
+        int64_t *&gv = transposed ? P->grp_vbT : P->grp_vb;
+        int32_t *&gr = transposed ? P->grp_rowsT : P->grp_rows;
+        cvbg = P->mem.alloc<int64_t>(nc);
+        gc = P->mem.alloc<int32_t>(gcell.size());
+        gv = P->mem.alloc<int64_t>(ng);
+        gr = P->mem.alloc<int32_t>(ng);
+        VP_HIP(hipMemcpyAsync(cvbg, vbg.data(), 8 * (size_t)nc, hipMemcpyHostToDevice, s));
+        VP_HIP(hipMemcpyAsync(gc, gcell.data(), 4 * gcell.size(), hipMemcpyHostToDevice, s));
+        VP_HIP(hipMemcpyAsync(gv, gvb.data(), 8 * (size_t)ng, hipMemcpyHostToDevice, s));
+        VP_HIP(hipMemcpyAsync(gr, grows.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, s));
+    }
     VP_HIP(hipStreamSynchronize(s));  // host vectors leave scope
     if (!transposed) {
         P->ncell_shared = nshared;
@@ -2171,6 +2259,16 @@ static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjo
         const int32_t *crow = adjoint ? P->cell_rowT : P->cell_row;
         const int32_t *ccol = adjoint ? P->cell_colT : P->cell_col;
         const int64_t *cvb = adjoint ? P->cell_vbT : P->cell_vb;
+        const int ngrp = adjoint ? P->ngrpT : P->ngrp;
+        if (P->nbatch == 1 && ngrp > 0) {
+            // shared-block cells as groups on the matrix cores; the rest below
+            cvb = adjoint ? P->cell_vbgT : P->cell_vbg;
+            const unsigned gblocks = (unsigned)std::min<int64_t>((ngrp + 3) / 4, 16384);
+            hipLaunchKernelGGL(k_corr_group, dim3(gblocks), dim3(256), 0, P->stream, ngrp,
+                               adjoint ? P->grp_cellT : P->grp_cell, adjoint ? P->grp_vbT : P->grp_vb,
+                               adjoint ? P->grp_rowsT : P->grp_rows, crow, ccol, vv, f, u);
+            VP_LAUNCH_CHECK();
+        }
         const unsigned cblocks = (unsigned)std::min<int64_t>((ncell + 3) / 4, 16384);
         for (int bt0 = 0; bt0 < P->nbatch;) {
             const int left = P->nbatch - bt0;

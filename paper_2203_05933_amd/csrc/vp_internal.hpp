@@ -291,6 +291,12 @@ struct vp_plan_s {
     // cell with an identical block (found at plan time, compared exactly)
     int64_t *cell_vb = nullptr, *cell_vbT = nullptr;
     int ncell_shared = 0;           // cells reading another cell's identical block
+    // one density: groups of up to 16 64-column cells reading one block
+    // (cell ids, -1 padded; value offset and rows per group), and the offsets
+    // the cell kernel uses then (-1: the cell is applied by its group)
+    int32_t *grp_cell = nullptr, *grp_cellT = nullptr, *grp_rows = nullptr, *grp_rowsT = nullptr;
+    int64_t *grp_vb = nullptr, *grp_vbT = nullptr, *cell_vbg = nullptr, *cell_vbgT = nullptr;
+    int ngrp = 0, ngrpT = 0;
     int64_t corr_values_read = 0;   // values the forward apply reads from memory
 
     vp::Tree tree;

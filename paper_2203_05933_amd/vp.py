@@ -64,6 +64,7 @@ class PlanInfo(ctypes.Structure):
                 ("m2l_coarse_translations", ctypes.c_int64), ("m2l_coarse_tile_ops", ctypes.c_int64),
                 ("split_level", ctypes.c_int32), ("corr_cells", ctypes.c_int32),
                 ("corr_shared_cells", ctypes.c_int32), ("corr_values_read", ctypes.c_int64),
+                ("corr_groups", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("root", ctypes.c_double * 3)]
 
     def as_dict(self):

@@ -376,7 +376,7 @@ def test_correction_shared_blocks(nbatch):
     one table, Section 4): a cell with a block identical bit for bit to an
     earlier cell's reads that cell's copy, also from an odd value offset onto
     an even one; a block that differs in one bit of one value keeps its own.
-    One density (two-rows-per-load path), 4 (matrix cores) and 16; forward and
+    One density (grouped apply and two-rows-per-load path), 4 (matrix cores) and 16; forward and
     adjoint against the oracle."""
     vp = _vp()
     rng = np.random.default_rng(97 + nbatch)
@@ -386,7 +386,10 @@ def test_correction_shared_blocks(nbatch):
     blocks[3] = near
     # (nodes, block) of each square cell, in order; the 45-node cells move the
     # values after them to odd offsets
+    # with one density, block 1's 21 cells go to the grouped matrix-core apply
+    # (a full group of 16 and one of 5), the others stay cell by cell
     order = [(64, 0), (64, 0), (64, 1), (64, 3), (45, 2), (64, 0), (64, 1), (45, 2), (30, None)]
+    order += [(64, 1)] * 10 + [(45, None)] + [(64, 1)] * 9
     n = sum(sz for sz, _ in order)
     x = rng.uniform(-1, 1, n)
     y = rng.uniform(-1, 1, n)
@@ -406,8 +409,9 @@ def test_correction_shared_blocks(nbatch):
                    root=(-1.0, -1.0, 2.0))
     info = plan.info()
     assert info["corr_cells"] == len(order)
-    assert info["corr_shared_cells"] == 4  # the second and third block 0, second block 1, second block 2
-    assert info["corr_values_read"] == val.size - 3 * 64 * 64 - 45 * 45
+    assert info["corr_shared_cells"] == 23  # 2 of block 0, 20 of block 1, 1 of block 2
+    assert info["corr_groups"] == (2 if nbatch == 1 else 0)  # block 1's 21 cells: 16 + 5
+    assert info["corr_values_read"] == val.size - 22 * 64 * 64 - 45 * 45
     u = _host(plan.eval(_dev(f)))
     ref = direct.evaluate(x, y, w, f, rowptr, col, val)
     assert max(relinf(u[b], ref[b]) for b in range(nbatch)) <= TOL64
