@@ -1114,7 +1114,7 @@ __global__ void __launch_bounds__(256) k_corr_group(int ngrp, const int32_t *__r
         const int cell = grp_cell[gi * 16 + cl];
         const int R = grp_rows[gi];
         const int64_t vb = grp_vb[gi];
-        // B = F: column cl is cell `cell`'s 64 densities, k = 4 s + lane/16
+        // B = F: column cl holds f at cell `cell`'s 64 columns, k = 4 s + lane/16
         double bf[16];
         int r0 = 0;
         if (cell >= 0) {
