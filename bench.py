@@ -1,15 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the volume-potential evaluation hot path on one MI355X.
 
-Workload (default): the star-shaped domain r = 1 + 0.3 cos 5 theta with an
-adaptive box quadtree and a boundary band of triangles, 1,488,064 nodes,
-targets = nodes, own-cell correction matrix, one density, FMM order p = 30
-in float64.  A step is one full evaluation u = V f + C f (charges, upward
-pass, M2L, downward pass, near field, far-field evaluation, correction and
-un-permutation) with inputs resident in HBM; the plan (tree, lists,
-operators) is built once beforehand, as the paper excludes set-up from its
-timings.  The FP32-bulk form (p = 14) is measured on the same workload and
-reported alongside.
+Headline workload: the batched uniform grid -- 256 x 256 boxes on [-1,1]^2
+with an 8x8 Gauss-Legendre rule per box (4,194,304 nodes), 16 seeded
+Gaussian-sum densities evaluated in one launch, targets = nodes, own-cell
+correction matrix (64 values per row; every box carries the same 64 x 64
+block, as the box corrections of one box size form one table), FMM order
+p = 30 in float64.  The FP32-bulk form (p = 14) is measured on the same
+workload beside it.  A step is one full evaluation u = V f + C f (charges,
+upward pass, M2L, downward pass, near field, far-field evaluation,
+correction and un-permutation) with inputs resident in HBM; the plan (tree,
+lists, operators) is built once beforehand, as the paper excludes set-up
+from its timings.
+
+Secondary records in the same JSON line (skipped with --no-secondary):
+  * uniform128: 128 x 128 boxes (1,048,576 nodes, one density), FP64 p = 30
+    beside FP32-bulk p = 14 (scaled and split hi/lo M2L), each with its error
+    against the oracle on 4,096 sampled targets;
+  * star: the adaptive star-shaped domain (1,488,064 nodes), FP64 and
+    FP32-bulk, with errors against the oracle;
+  * per_entry_correction: the headline grid with every correction value
+    drawn on its own (no shared block), FP64, with the correction apply's
+    rate against the HBM peak.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -29,22 +41,21 @@ METRIC = "Mpoints/s volume-potential eval at rel err 1e-12 (FP64) vs 1e-6 (FP32 
 FP64_VECTOR_TFLOPS = 78.6   # MI355X published peak, FP64 vector
 FP64_MFMA_TFLOPS = 78.6     # MI355X published peak, FP64 matrix (dense)
 FP32_MFMA_TFLOPS = 157.3    # MI355X published peak, FP32 matrix (dense)
+HBM_GBS = 8000.0            # MI355X published HBM3E bandwidth
 P2P_FLOPS_PER_PAIR = 27     # 2 differences, 3 for r^2, 20 for log(r^2), 2 for the update
+GOLDEN_C3 = os.path.join(ROOT, "tests", "golden", "c3_sample_smooth.npy")
+C3_NAME = "uniform256x256_gl8_b16"
 
 
-# HBM bytes per launch of the star-workload kernels, from two rocprofv3 --pmc
+# HBM bytes per launch of the headline's kernels, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, then WRITE_SIZE) of this script, each scaled by what the
-# counter reads for a plain 1 GiB device copy in the same run (FETCH_SIZE
-# reads half the bytes, WRITE_SIZE all of them).  Valid only for the kernel
-# sources they were taken on: the digest below covers every file of the
-# library's source directory, and any change there turns traffic into null.
-TRAFFIC_DIGEST = "d5945a711f0af58975d4e3526ade1f21f08edad5678cf3540973a3551c72dcd3"
-TRAFFIC_WORKLOAD = "star_adaptive"
-TRAFFIC = {  # stage -> (read bytes, written bytes) per launch, FP64 p = 30, one density
-    "corr": (83605134, 11912327),  # k_corr_group + k_corr_cells
-    "m2l": (250839465, 18844963),  # k_m2l_scaled, levels from the split level on
-    "p2p": (92101604, 3547276),
-}
+# counter reads for a plain device copy of known size in the same run.  Valid
+# only for the kernel sources they were taken on: the digest covers every
+# file of the library's source directory, and any change there turns traffic
+# into null.
+TRAFFIC_DIGEST = None
+TRAFFIC_WORKLOAD = C3_NAME
+TRAFFIC = {}  # stage -> (read bytes, written bytes) per launch, FP64 p = 30, 16 densities
 
 
 def source_digest():
@@ -58,9 +69,9 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(stage, workload_name, order, nbatch):
+def measured_traffic(stage, workload_name, order):
     """Counter-measured HBM bytes per launch, or None when they do not apply."""
-    if stage not in TRAFFIC or workload_name != TRAFFIC_WORKLOAD or order != 30 or nbatch != 1:
+    if stage not in TRAFFIC or workload_name != TRAFFIC_WORKLOAD or order != 30:
         return None
     if source_digest() != TRAFFIC_DIGEST:
         return None
@@ -72,7 +83,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def workload(name):
+def workload(name, shared_blocks=True):
     from vp_workloads import generators as gen
     if name == "star":
         return gen.config1()
@@ -81,14 +92,17 @@ def workload(name):
     if name == "uniform16":
         return gen.config0()
     if name == "uniform256x16":
-        return gen.config3()
+        return gen.config3(shared_blocks=shared_blocks)
     raise SystemExit(f"unknown workload {name}")
 
 
+# ----------------------------------------------------------------------------
+# timing
+# ----------------------------------------------------------------------------
 def time_evals(plan, f, u, steps, warmup):
     """Wall-clock time of `steps` evaluations (no per-stage events inside),
-    then the same number of evaluations with per-stage HIP events on the
-    plan's stream for the stage breakdown and the roofline."""
+    then the same number of evaluations with per-stage HIP events recorded on
+    the stream each stage runs on, for the stage breakdown and the roofline."""
     import torch
     for _ in range(warmup):
         plan.eval(f, out=u)
@@ -106,31 +120,57 @@ def time_evals(plan, f, u, steps, warmup):
     return dt, tim
 
 
-def stage_roofline(plan, tim, precision, stage, workload_name=None):
-    """Roofline record of one single-kernel stage, or None when the stage has no model."""
-    rec = _stage_roofline(plan, tim, precision, stage)
-    if rec is not None and precision == "fp64":
-        info = plan.info()
-        rec["traffic"] = measured_traffic(stage, workload_name, info["order"], info["nbatch"])
-        rec["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
-    return rec
+def make_plan(wl, order, precision, m2l_mode="auto", one_stream=False, max_leaf=64):
+    from paper_2203_05933_amd import vp
+    return vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=order, max_leaf=max_leaf,
+                   nbatch=wl.nbatch, precision=precision, m2l_mode=m2l_mode, one_stream=one_stream, root=wl.root)
 
 
-def _stage_roofline(plan, tim, precision, stage):
+def run_form(wl, f, order, precision, steps, warmup, m2l_mode="auto", one_stream=False, label=""):
+    """Plan, time and return (record, result tensor, plan info, stage timing, plan)."""
+    import torch
+    t0 = time.perf_counter()
+    plan = make_plan(wl, order, precision, m2l_mode, one_stream)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    u = torch.empty((wl.nbatch, wl.m), dtype=torch.float64, device="cuda:0")
+    dt, tim = time_evals(plan, f, u, steps, warmup)
+    ms = dt / steps * 1e3
+    value = wl.m * wl.nbatch / (dt / steps) / 1e6
     info = plan.info()
+    stages = {k: v / max(tim["evals"], 1) for k, v in tim["ms"].items()}
+    rec = {"value": value, "ms_per_step": ms, "order": order, "precision": precision, "plan_ms": plan_ms,
+           "m2l_mode": info["m2l_mode"], "stages_ms": stages}
+    log(f"[bench] {label} {precision} p={order}: plan {plan_ms:.0f} ms, {ms:.3f} ms/eval, {value:.1f} Mpoints/s; "
+        "stages(ms/eval)=" + json.dumps({k: round(v, 4) for k, v in stages.items()}))
+    return rec, u, info, tim, plan
+
+
+# ----------------------------------------------------------------------------
+# roofline records
+# ----------------------------------------------------------------------------
+def stage_roofline(info, tim, stage, workload_name=None):
+    """Roofline record of one single-kernel stage, or None when the stage has no model."""
     n = max(tim["evals"], 1)
     avg_s = tim["ms"][stage] / n / 1e3
     if avg_s <= 0:
         return None
     P = info["order"] + 1
     nb = info["nbatch"]
+    fp64 = info["precision"] == 0
+    rec = None
     if stage == "p2p":
         flops = info["near_pairs"] * nb * P2P_FLOPS_PER_PAIR
-        return {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": flops / avg_s / 1e12 / FP64_VECTOR_TFLOPS, "traffic": None, "kernel": "k_p2p",
-                "avg_ms": avg_s * 1e3,
-                "work": f"{info['near_pairs']} pairs x {nb} densities x {P2P_FLOPS_PER_PAIR} flops"}
-    if stage == "m2l":
+        rec = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+               "kernel": "k_p2p",
+               "work": f"{info['near_pairs']} pairs x {nb} densities x {P2P_FLOPS_PER_PAIR} flops"}
+    elif stage == "tables":
+        # near-field tables: one multiply-add per (target, source) pair and density, FP64 matrix cores
+        flops = info["table_pairs"] * nb * 2
+        rec = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+               "kernel": "k_translate_split (near-field tables)",
+               "work": f"{info['table_pairs']} table pairs x {nb} densities x 2 flops"}
+    elif stage == "m2l":
         # the "m2l" stage times the launch over the levels from split_level on;
         # the levels below run in the "coarse" stage on the third stream
         nv = info["m2l_translations"] - info["m2l_coarse_translations"]
@@ -146,13 +186,11 @@ def _stage_roofline(plan, tim, precision, stage):
         PQ = (P + 15) // 16 * 16
         PDm = (max(2 * P + 1, P + PQ) + 15) // 16 * 16  # rows per expansion column
         issued = tile_ops * (64 * PQ * PQ if scaled else 32 * PDm * PDm)
-        return {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
-                "frac": flops / avg_s / 1e12 / peak, "traffic": None,
-                "kernel": "k_m2l_scaled" if scaled else "k_translate_split", "avg_ms": avg_s * 1e3,
-                "issued_tflops": issued / avg_s / 1e12,
-                "work": f"{nv} translations (V lists and X-list virtual children, levels >= {info['split_level']}) "
-                        f"x {nb} densities x {per} flops ({form}, P={P}); {tile_ops} tile products issued"}
-    if stage == "corr":
+        rec = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+               "kernel": "k_m2l_scaled" if scaled else "k_translate_split", "issued_tflops": issued / avg_s / 1e12,
+               "work": f"{nv} translations (V lists and X-list virtual children, levels >= {info['split_level']}) "
+                       f"x {nb} densities x {per} flops ({form}, P={P}); {tile_ops} tile products issued"}
+    elif stage == "corr":
         nnz, m, n_, cells = info["nnz"], info["m"], info["n"], info["corr_cells"]
         if cells > 0:
             # distinct values (cells with an identical block read one copy); per cell:
@@ -162,45 +200,149 @@ def _stage_roofline(plan, tim, precision, stage):
             kern, what = "k_corr_cells", (f"{nval} distinct values of {nnz} x 8 B ({shared} of {cells} cells "
                                           f"share an identical block) + {cells} cell records")
             if info["corr_groups"] > 0:
-                # one density: cells of a repeated block go 16 at a time through one matrix-core product
                 kern = "k_corr_group + k_corr_cells"
                 what += f", {info['corr_groups']} groups of up to 16 cells"
         else:
             bytes_ = nnz * 8 + (m + 1) * 8 + m * 4 + m * 8 * nb + n_ * 8 * nb
             kern, what = "k_corr", f"{nnz} values x 8 B + row pointers and runs"
-        return {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": 8000.0, "unit": "GB/s",
-                "frac": bytes_ / avg_s / 1e9 / 8000.0, "traffic": None, "kernel": kern,
-                "avg_ms": avg_s * 1e3, "work": f"{what}, f read once, {nb} output rows written",
-                # every value the kernel loads, shared blocks included (those come from the caches)
-                "values_loaded_gbs": nnz * 8 / avg_s / 1e9}
-    return None
+        rec = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": HBM_GBS, "unit": "GB/s", "kernel": kern,
+               "work": f"{what}, f read once, {nb} output rows written",
+               # every value the kernel loads, shared blocks included (those come from the caches)
+               "values_loaded_gbs": nnz * 8 / avg_s / 1e9}
+    if rec is None:
+        return None
+    rec["frac"] = rec["achieved"] / rec["peak"]
+    rec["avg_ms"] = avg_s * 1e3
+    rec["traffic"] = measured_traffic(stage, workload_name, info["order"]) if fp64 else None
+    if rec["traffic"] is not None:
+        rec["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
+    return rec
 
 
-def roofline(plan, tim, precision, workload_name=None):
-    """Roofline record of the single-kernel stage with the largest device time."""
+def rooflines(info, tim, workload_name=None):
+    """(dominant stage, its record, all records): the modelled single-kernel
+    stage with the largest device time is the dominant one."""
     recs = {}
-    for st in ("m2l", "p2p", "corr"):
-        r = stage_roofline(plan, tim, precision, st, workload_name)
+    for st in ("m2l", "tables", "p2p", "corr"):
+        r = stage_roofline(info, tim, st, workload_name)
         if r is not None:
             recs[st] = r
     stage = max(recs, key=lambda k: recs[k]["avg_ms"])
     return stage, recs[stage], recs
 
 
+# ----------------------------------------------------------------------------
+# oracle (test infrastructure: reference values and the cpu_baseline leg)
+# ----------------------------------------------------------------------------
+def reference(wl):
+    """Oracle values at the workload's sampled targets: [nbatch, nsample].  The
+    headline grid's smooth sums are stored (tests/golden, written by a script
+    that calls the oracle only); the correction rows are added here."""
+    import numpy as np
+    from oracle import direct
+    if wl.name.startswith(C3_NAME) and os.path.exists(GOLDEN_C3):
+        smooth = np.load(GOLDEN_C3)
+        assert smooth.shape == (wl.nbatch, wl.sample.size)
+        return smooth + direct.csr(wl.rowptr, wl.col, wl.val, wl.f, tidx=wl.sample)
+    return direct.evaluate(wl.x, wl.y, wl.w, wl.f, wl.rowptr, wl.col, wl.val, wl.tx, wl.ty, tidx=wl.sample)
+
+
+def rel_err(u, ref, sample):
+    import numpy as np
+    got = u.cpu().numpy()[:, sample]
+    return float(max(np.max(np.abs(got[b] - ref[b])) / np.max(np.abs(ref[b])) for b in range(ref.shape[0])))
+
+
+def cpu_baseline(wl, count):
+    """The oracle timed on the host's cores on `count` seeded targets of the
+    workload (all nodes, all densities)."""
+    from oracle import direct
+    from vp_workloads import generators as gen
+    sample = gen.sample_indices(wl.m, count, 110)
+    log(f"[bench] oracle on {len(sample)} sampled targets x {wl.n} nodes x {wl.nbatch} densities "
+        f"({direct.num_threads()} threads)")
+    t0 = time.perf_counter()
+    direct.evaluate(wl.x, wl.y, wl.w, wl.f, wl.rowptr, wl.col, wl.val, wl.tx, wl.ty, tidx=sample)
+    tc = time.perf_counter() - t0
+    return {"value": len(sample) * wl.nbatch / tc / 1e6, "unit": "Mpoints/s", "cores": direct.num_threads(),
+            "kind": "oracle",
+            "sample": f"{len(sample)} seeded targets (seed 110) of the same workload against all {wl.n} nodes and "
+                      f"{wl.nbatch} densities (direct float64 sum with compensated summation + CSR row), {tc:.1f} s"}
+
+
+# ----------------------------------------------------------------------------
+# secondary records
+# ----------------------------------------------------------------------------
+def precision_pair(name, steps, warmup, order, order32, with_cpu):
+    """FP64 beside the FP32-bulk form (scaled and split hi/lo M2L) on one workload."""
+    import torch
+    wl = workload(name)
+    f = torch.tensor(wl.f, dtype=torch.float64, device="cuda:0")
+    ref = reference(wl) if with_cpu else None
+    out = {"workload": f"{wl.name}: {wl.n} nodes, targets=nodes, {wl.nbatch} density", "n": wl.n,
+           "nbatch": wl.nbatch}
+    forms = (("fp64", order, "fp64", "auto"), ("fp32_scaled", order32, "fp32", "auto"),
+             ("fp32_split_hi_lo", order32, "fp32", "split"))
+    base = None
+    for key, p, prec, mode in forms:
+        rec, u, info, tim, plan = run_form(wl, f, p, prec, steps, warmup, mode, label=wl.name)
+        stage, roof, _ = rooflines(info, tim, wl.name)
+        rec["dominant_stage"] = stage
+        rec["roofline"] = roof
+        if ref is not None:
+            rec["rel_err"] = rel_err(u, ref, wl.sample)
+            rec["rel_err_targets"] = int(wl.sample.size)
+        if base is None:
+            base = rec["value"]
+        else:
+            rec["speedup_vs_fp64"] = rec["value"] / base
+        out[key] = rec
+        plan.close()
+        del u
+    return out
+
+
+def per_entry_correction(steps, warmup, order, with_cpu):
+    """The headline grid with every correction value drawn on its own."""
+    import torch
+    wl = workload("uniform256x16", shared_blocks=False)
+    f = torch.tensor(wl.f, dtype=torch.float64, device="cuda:0")
+    rec, u, info, tim, plan = run_form(wl, f, order, "fp64", steps, warmup, label="per-entry correction")
+    stage, roof, recs = rooflines(info, tim, wl.name)
+    rec["workload"] = (f"{wl.name}: {wl.n} nodes x {wl.nbatch} densities, {info['nnz']} correction values each "
+                       "drawn on its own")
+    rec["corr_apply"] = recs.get("corr")
+    rec["dominant_stage"] = stage
+    if with_cpu:
+        rec["rel_err"] = rel_err(u, reference(wl), wl.sample)
+    plan.close()
+    del u
+    # one stream: the apply without the other streams beside it
+    plan1 = make_plan(wl, order, "fp64", one_stream=True)
+    u1 = torch.empty((wl.nbatch, wl.m), dtype=torch.float64, device="cuda:0")
+    _, tim1 = time_evals(plan1, f, u1, steps, warmup)
+    rec["corr_apply_one_stream"] = stage_roofline(plan1.info(), tim1, "corr", wl.name)
+    plan1.close()
+    return rec
+
+
+# ----------------------------------------------------------------------------
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="star", choices=["star", "uniform128", "uniform16", "uniform256x16"])
+    ap.add_argument("--workload", default="uniform256x16",
+                    choices=["uniform256x16", "star", "uniform128", "uniform16"])
     ap.add_argument("--order", type=int, default=30)
     ap.add_argument("--order-fp32", type=int, default=14)
     ap.add_argument("--max-leaf", type=int, default=64)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (cpu_baseline and errors)")
-    ap.add_argument("--no-one-stream", action="store_true",
-                    help="skip the one-stream run (per-stage times without the second stream's overlap)")
-    ap.add_argument("--cpu-sample", type=int, default=12288, help="targets the oracle evaluates")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the secondary records")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="also run the headline with every kernel on one stream (per-stage times without overlap)")
+    ap.add_argument("--cpu-sample", type=int, default=256, help="targets the timed oracle evaluates")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed loops, run one plain device copy (y = 2 x) of this many MiB read and "
                          "written, as the calibration kernel for hardware byte counters")
@@ -211,98 +353,79 @@ def main():
               "(the evaluation is single-device; see the design notes on sharding).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2203_05933_amd import vp
+    from paper_2203_05933_amd import vp  # noqa: F401  (fails loudly without libvp.so)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log(f"[bench] generating workload {args.workload}")
     wl = workload(args.workload)
     nb = wl.nbatch
     log(f"[bench] n={wl.n} m={wl.m} nbatch={nb} nnz={0 if wl.rowptr is None else int(wl.rowptr[-1])}")
-
     f = torch.tensor(wl.f, dtype=torch.float64, device="cuda:0")
-    u = torch.empty((nb, wl.m), dtype=torch.float64, device="cuda:0")
 
-    t0 = time.perf_counter()
-    plan = vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=args.order,
-                   max_leaf=args.max_leaf, nbatch=nb, precision="fp64", root=wl.root)
-    torch.cuda.synchronize()
-    plan_ms = (time.perf_counter() - t0) * 1e3
-    info = plan.info()
-    log(f"[bench] fp64 plan {plan_ms:.0f} ms: boxes={info['nbox']} leaves={info['nleaf']} "
-        f"levels={info['nlevels']} lists={info['list_len']} near_pairs={info['near_pairs']}")
-    dt, tim = time_evals(plan, f, u, args.steps, args.warmup)
-    ms_per_step = dt / args.steps * 1e3
-    value = wl.m * nb / (dt / args.steps) / 1e6
-    log(f"[bench] fp64: {ms_per_step:.3f} ms/eval, {value:.1f} Mpoints/s; stages(ms/eval)="
-        + json.dumps({k: round(v / max(tim['evals'], 1), 4) for k, v in tim["ms"].items()}))
-    stage, roof, roofs = roofline(plan, tim, "fp64", wl.name)
-    u64 = u.clone()
+    rec64, u64, info, tim, plan = run_form(wl, f, args.order, "fp64", args.steps, args.warmup, label="headline")
+    value, ms_per_step = rec64["value"], rec64["ms_per_step"]
+    stage, roof, roofs = rooflines(info, tim, wl.name)
+    log(f"[bench] dominant stage {stage}: {roof['kernel']} {roof['avg_ms']:.3f} ms, frac {roof['frac']:.3f}")
+    plan.close()
 
     one = None
-    if not args.no_one_stream:
-        # the same evaluation with every kernel on one stream: stage times
-        # without contention from the overlapped second stream
-        plan1 = vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=args.order,
-                        max_leaf=args.max_leaf, nbatch=nb, precision="fp64", one_stream=True, root=wl.root)
-        u1 = torch.empty_like(u)
+    if args.one_stream:
+        plan1 = make_plan(wl, args.order, "fp64", one_stream=True, max_leaf=args.max_leaf)
+        u1 = torch.empty_like(u64)
         dt1, tim1 = time_evals(plan1, f, u1, args.steps, args.warmup)
+        inf1 = plan1.info()
         one = {"ms_per_step": dt1 / args.steps * 1e3,
                "stages_ms": {k: v / max(tim1["evals"], 1) for k, v in tim1["ms"].items()},
-               "stage_rooflines": {st: r for st in ("m2l", "p2p", "corr")
-                                   if (r := _stage_roofline(plan1, tim1, "fp64", st)) is not None}}
-        log(f"[bench] fp64 one stream: {one['ms_per_step']:.3f} ms/eval; stages(ms/eval)="
-            + json.dumps({k: round(v, 4) for k, v in one["stages_ms"].items()}))
+               "stage_rooflines": rooflines(inf1, tim1, wl.name)[2]}
+        log(f"[bench] fp64 one stream: {one['ms_per_step']:.3f} ms/eval")
         plan1.close()
         del u1
 
-    out32 = None
     forms32 = {}
     if not args.no_fp32:
-        # FP32-bulk form: the default (scaled M2L in FP32) and the split hi/lo FP32
-        # M2L products (T_hi M_hi + T_hi M_lo + T_lo M_hi per offset)
-        for name, mode, desc in (("fp32_scaled", "auto", "fp32 mfma, scaled form"),
-                                 ("split_hi_lo", "split", "split hi/lo fp32 mfma, per-offset operators")):
-            plan32 = vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=args.order_fp32,
-                             max_leaf=args.max_leaf, nbatch=nb, precision="fp32", m2l_mode=mode, root=wl.root)
-            u32 = torch.empty_like(u)
-            dt32, tim32 = time_evals(plan32, f, u32, args.steps, args.warmup)
-            v32 = wl.m * nb / (dt32 / args.steps) / 1e6
-            forms32[name] = ({"value": v32, "ms_per_step": dt32 / args.steps * 1e3, "order": args.order_fp32,
-                              "m2l": desc,
-                              "stages_ms": {k: v / max(tim32["evals"], 1) for k, v in tim32["ms"].items()},
-                              "speedup_vs_fp64": v32 / value}, u32)
-            log(f"[bench] fp32-bulk ({name}): {dt32 / args.steps * 1e3:.3f} ms/eval, {v32:.1f} Mpoints/s")
+        # FP32-bulk: the scaled M2L in FP32 (default) and the split hi/lo FP32
+        # products per offset (T_hi M_hi + T_hi M_lo + T_lo M_hi)
+        for key, mode, desc in (("fp32_scaled", "auto", "fp32 mfma, scaled form"),
+                                ("split_hi_lo", "split", "split hi/lo fp32 mfma, per-offset operators")):
+            r32, u32, inf32, tim32, plan32 = run_form(wl, f, args.order_fp32, "fp32", args.steps, args.warmup,
+                                                      mode, label="headline")
+            r32["m2l"] = desc
+            r32["speedup_vs_fp64"] = r32["value"] / value
+            st32, roof32, _ = rooflines(inf32, tim32, wl.name)
+            r32["dominant_stage"] = st32
+            r32["roofline"] = roof32
+            forms32[key] = (r32, u32)
             plan32.close()
+
+    cpu = None
+    rel64 = None
+    if not args.no_cpu:
+        ref = reference(wl)
+        rel64 = rel_err(u64, ref, wl.sample)
+        for key, (r32, u32) in forms32.items():
+            r32["rel_err"] = rel_err(u32, ref, wl.sample)
+        log(f"[bench] rel_inf err on {wl.sample.size} targets x {nb} densities: fp64={rel64:.3e} "
+            + " ".join(f"{k}={r['rel_err']:.3e}" for k, (r, _) in forms32.items()))
+        cpu = cpu_baseline(wl, args.cpu_sample)
+    out32 = None
+    if forms32:
         out32 = forms32["fp32_scaled"][0]
         out32["split_hi_lo"] = forms32["split_hi_lo"][0]
-    cpu = None
-    rel64 = rel32 = None
-    if not args.no_cpu:
-        from oracle import direct
-        sample = wl.sample if wl.sample is not None else np.arange(wl.m)
-        if args.cpu_sample > len(sample):
-            # a larger seeded draw, so that the timed oracle run is 10-30 s of CPU work
-            from vp_workloads import generators as gen
-            sample = gen.sample_indices(wl.m, args.cpu_sample, 110)
-        sample = sample[: args.cpu_sample]
-        log(f"[bench] oracle on {len(sample)} sampled targets x {wl.n} nodes ({direct.num_threads()} threads)")
-        t0 = time.perf_counter()
-        ref = direct.evaluate(wl.x, wl.y, wl.w, wl.f, wl.rowptr, wl.col, wl.val, wl.tx, wl.ty, tidx=sample)
-        tc = time.perf_counter() - t0
-        cpu = {"value": len(sample) * nb / tc / 1e6, "unit": "Mpoints/s", "cores": direct.num_threads(),
-               "kind": "oracle",
-               "sample": f"{len(sample)} seeded targets of the same workload against all {wl.n} nodes "
-                         f"(direct float64 sum with compensated summation + CSR row), {tc:.1f} s"}
-        got = u64.cpu().numpy()[:, sample]
-        rel64 = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-        for name, (rec32, u32) in forms32.items():
-            got32 = u32.cpu().numpy()[:, sample]
-            rec32["rel_err"] = float(np.max(np.abs(got32 - ref)) / np.max(np.abs(ref)))
-        if out32 is not None:
-            rel32 = out32["rel_err"]
-        log(f"[bench] rel_inf err fp64={rel64:.3e} fp32={rel32}")
+    del forms32
+
+    secondary = None
+    if not args.no_secondary:
+        secondary = {}
+        del u64
+        torch.cuda.empty_cache()
+        secondary["per_entry_correction"] = per_entry_correction(args.steps, args.warmup, args.order, not args.no_cpu)
+        torch.cuda.empty_cache()
+        secondary["uniform128_precision"] = precision_pair("uniform128", args.steps, args.warmup, args.order,
+                                                           args.order_fp32, not args.no_cpu)
+        torch.cuda.empty_cache()
+        secondary["star"] = precision_pair("star", args.steps, args.warmup, args.order, args.order_fp32,
+                                           not args.no_cpu)
 
     if args.copy_mib > 0:
         n_el = args.copy_mib * (1 << 20) // 8
@@ -327,18 +450,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.n} nodes, targets=nodes, {nb} density, p={args.order} float64, "
-                               f"max_leaf={args.max_leaf}", "n": wl.n, "m": wl.m, "nbatch": nb,
-                   "order": args.order, "nnz": int(info["nnz"]), "parallelism": "single GPU"},
+        "config": {"workload": f"{wl.name}: {wl.n} nodes x {nb} densities, targets=nodes, p={args.order} float64, "
+                               f"max_leaf={args.max_leaf}, own-cell correction (one shared 64x64 box block)",
+                   "n": wl.n, "m": wl.m, "nbatch": nb, "order": args.order, "nnz": int(info["nnz"]),
+                   "parallelism": "single GPU"},
         "rel_err": rel64,
-        "plan_ms": plan_ms,
-        "stages_ms": {k: v / max(tim["evals"], 1) for k, v in tim["ms"].items()},
+        "rel_err_targets": None if rel64 is None else f"{wl.sample.size} sampled targets x {nb} densities",
+        "plan_ms": rec64["plan_ms"],
+        "stages_ms": rec64["stages_ms"],
         "dominant_stage": stage,
         "roofline": roof,
         "stage_rooflines": roofs,
         "one_stream": one,
         "fp32_form": out32,
         "cpu_baseline": cpu,
+        "secondary": secondary,
     }
     print(json.dumps(rec), flush=True)
 

@@ -99,7 +99,10 @@ typedef struct {
     int32_t max_level; /* deepest tree level; 1..30; 0 = 30 */
     int32_t flags;     /* VP_FLAG_* bits; 0 = none */
     double root[3];    /* x0, y0, side of the root square; side <= 0 selects
-                          the bounding square of sources and targets */
+                          the bounding square of sources and targets.  With
+                          side > 0 every node and target must lie in the
+                          closed square [x0, x0+side] x [y0, y0+side]
+                          (VP_EINVAL otherwise) */
     void *stream;      /* hipStream_t for plan-time copies and evaluations;
                           NULL = the null stream */
 } vp_options;
@@ -120,7 +123,8 @@ void vp_default_options(vp_options *opt);
  *   opt              : options (NULL = defaults)
  *   out              : receives the plan; NULL on failure
  * Errors: VP_EINVAL (n < 1, m < 1, non-finite coordinates or weights, bad
- * CSR, options out of range, out == NULL), VP_ENOMEM, VP_EDEVICE,
+ * CSR, options out of range, a node or target outside a given root square,
+ * out == NULL), VP_ENOMEM, VP_EDEVICE,
  * VP_EINTERNAL.  The tree is built on the device with this library's kernels.
  */
 vp_status vp_plan(const double *x, const double *y, const double *w, int64_t n,
@@ -188,6 +192,8 @@ typedef struct {
                                   block, applied together on the matrix cores (0: none) */
     int32_t reserved0;
     double root[3];
+    int64_t table_pairs;       /* (target, source) pairs per density served by the near-field
+                                  tables (near_pairs holds the pairwise kernel's) */
 } vp_plan_info_t;
 
 vp_status vp_get_info(vp_plan_t plan, vp_plan_info_t *info);

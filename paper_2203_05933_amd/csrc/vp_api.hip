@@ -192,6 +192,18 @@ static void validate_plan_args(const double *x, const double *y, const double *w
     if (o.flags & ~(VP_FLAG_AUTOTUNE | VP_FLAG_ONE_STREAM)) bad("unknown flags");
     if (o.root[2] > 0 && (!std::isfinite(o.root[0]) || !std::isfinite(o.root[1]) || !std::isfinite(o.root[2])))
         bad("non-finite root square");
+    if (o.root[2] > 0) {
+        // every node and target must lie in the closed root square: a point
+        // outside would be quantised into a border box whose expansion centre
+        // it is not near, and the far field would lose its accuracy silently
+        const double x0 = o.root[0], y0 = o.root[1], x1 = o.root[0] + o.root[2], y1 = o.root[1] + o.root[2];
+        auto outside = [&](double px, double py) { return px < x0 || px > x1 || py < y0 || py > y1; };
+        for (int64_t i = 0; i < n; ++i)
+            if (outside(x[i], y[i])) bad("node " + std::to_string(i) + " lies outside the root square");
+        if (tx)
+            for (int64_t i = 0; i < m; ++i)
+                if (outside(tx[i], ty[i])) bad("target " + std::to_string(i) + " lies outside the root square");
+    }
 }
 
 static void release_timing(vp_plan_s *P) {
@@ -430,6 +442,7 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->corr_values_read = P->ncell > 0 ? P->corr_values_read : P->nnz;
     info->table_tile_ops = P->near.table_tile_ops;
     for (int k = 0; k < 3; ++k) info->root[k] = P->opt.root[k];
+    info->table_pairs = P->table_pairs;
     return VP_OK;
 }
 

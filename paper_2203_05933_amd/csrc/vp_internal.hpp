@@ -303,6 +303,7 @@ struct vp_plan_s {
     vp::Operators ops;
     vp::NearTables near;
     int64_t near_pairs = 0;
+    int64_t table_pairs = 0;
 
     // evaluation workspace
     double *q = nullptr;     // [nbatch][max(n,m)] charges, sorted order

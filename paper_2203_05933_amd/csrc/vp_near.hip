@@ -18,9 +18,14 @@
 //
 // A leaf matches the reference pattern when it holds exactly npat points
 // whose box-relative coordinates (x - c)/h agree with the pattern's to
-// PATTERN_TOL; the matrices use the pattern coordinates, so the deviation
-// (a few ulps of the node coordinates) changes a logarithm by about
-// PATTERN_TOL / (nearest-pair distance in box units).
+// within a few units in the last place of the node coordinates:
+//     |(x - c)/h - xi| <= PATTERN_ULPS * 2^-52 * (R / h + 1),
+// R the largest coordinate magnitude of the root square.  That is the
+// rounding the node coordinates themselves carry (x = c + h xi rounded, for
+// this leaf and for the reference leaf), so the matrices, which use the
+// pattern coordinates, change a logarithm by no more than the rounding of the
+// coordinate difference in the direct sum does.  A leaf whose nodes deviate
+// by more keeps the pairwise kernel, which uses its own coordinates.
 
 #include <algorithm>
 #include <cmath>
@@ -32,14 +37,15 @@
 
 namespace vp {
 
-constexpr double PATTERN_TOL = 5e-13;
+constexpr double PATTERN_ULPS = 8.0;
 
 __global__ void k_match_pattern(const int32_t *__restrict__ leaves, int nleaf, const int32_t *__restrict__ b0,
                                 const int32_t *__restrict__ b1, const double *__restrict__ px,
                                 const double *__restrict__ py, const double *__restrict__ cx,
                                 const double *__restrict__ cy, const int32_t *__restrict__ level,
                                 const double *__restrict__ side, const double *__restrict__ rx,
-                                const double *__restrict__ ry, int npat, int32_t *__restrict__ flag) {
+                                const double *__restrict__ ry, int npat, double rmax,
+                                int32_t *__restrict__ flag) {
     const int lane = threadIdx.x;
     const int k = blockIdx.x;
     const int b = leaves[k];
@@ -49,11 +55,12 @@ __global__ void k_match_pattern(const int32_t *__restrict__ leaves, int nleaf, c
         return;
     }
     const double h = side[level[b]];
+    const double tol = PATTERN_ULPS * 0x1p-52 * (rmax / h + 1.0);
     bool ok = true;
     for (int j = lane; j < npat; j += 64) {
         const double ex = (px[s0 + j] - cx[b]) / h - rx[j];
         const double ey = (py[s0 + j] - cy[b]) / h - ry[j];
-        ok = ok && fabs(ex) <= PATTERN_TOL && fabs(ey) <= PATTERN_TOL;
+        ok = ok && fabs(ex) <= tol && fabs(ey) <= tol;
     }
     const uint64_t all = __ballot(ok);
     if (lane == 0) flag[b] = (all == ~0ull) ? 1 : 0;
@@ -139,6 +146,9 @@ void build_near_tables(vp_plan_s *P) {
             double *drx = tmp.alloc<double>(best), *dry = tmp.alloc<double>(best);
             int32_t *dflag = tmp.alloc<int32_t>(nbox);
             fill_i32(dflag, 0, nbox, s);
+            const double *rt = P->opt.root;
+            const double rmax = std::max(std::max(std::fabs(rt[0]), std::fabs(rt[0] + rt[2])),
+                                         std::max(std::fabs(rt[1]), std::fabs(rt[1] + rt[2])));
             int tried = 0, best_match = -1;
             std::vector<double> hx(best), hy(best), bx, by;
             for (int b : leaves) {
@@ -158,7 +168,7 @@ void build_near_tables(vp_plan_s *P) {
                 VP_HIP(hipMemcpyAsync(drx, hx.data(), 8 * best, hipMemcpyHostToDevice, s));
                 VP_HIP(hipMemcpyAsync(dry, hy.data(), 8 * best, hipMemcpyHostToDevice, s));
                 hipLaunchKernelGGL(k_match_pattern, dim3(T.nleaf), dim3(64), 0, s, T.leaves, T.nleaf, T.sb, T.se,
-                                   P->sx, P->sy, T.cx, T.cy, T.level, T.d_side, drx, dry, best, dflag);
+                                   P->sx, P->sy, T.cx, T.cy, T.level, T.d_side, drx, dry, best, rmax, dflag);
                 VP_LAUNCH_CHECK();
                 std::vector<int32_t> hf(nbox);
                 VP_HIP(hipMemcpyAsync(hf.data(), dflag, 4 * nbox, hipMemcpyDeviceToHost, s));
@@ -257,6 +267,14 @@ void build_near_tables(vp_plan_s *P) {
     for (int b = 0; b < nbox; ++b)
         for (int e = rptr[b]; e < rptr[b + 1]; ++e) pairs += (int64_t)(se[b] - sb[b]) * (se[ridx[e]] - sb[ridx[e]]);
     P->near_pairs = pairs;
+    // (target, source) pairs the near-field tables serve, per density
+    int64_t tpairs = 0;
+    for (size_t i = 0; i < tslot.size(); ++i)
+        if (tslot[i] >= 0) {
+            const int b = (int)(i / NTOPS), a = tslot[i];
+            tpairs += (int64_t)(se[b] - sb[b]) * (se[a] - sb[a]);
+        }
+    P->table_pairs = tpairs;
 
     std::vector<int32_t> ident(nbox);
     for (int b = 0; b < nbox; ++b) ident[b] = b;

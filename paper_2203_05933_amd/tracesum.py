@@ -1,0 +1,94 @@
+"""Summarise rocprofv3 CSV output of this library's kernels per launch shape.
+
+rocprofv3's own --stats summary groups dispatches by kernel name only; one
+kernel of this library runs with different grids (per tree level, per
+workload), so this tool groups them by (kernel name, grid size) as well:
+
+  python -m paper_2203_05933_amd.tracesum trace <run_kernel_trace.csv> [--match REGEX]
+      dispatches, average / median / min / max duration (microseconds)
+  python -m paper_2203_05933_amd.tracesum pmc <run_counter_collection.csv> [--match REGEX]
+      median counter value per dispatch, per counter
+
+Prints a markdown table on stdout.  Reads text files only.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import re
+import statistics
+import sys
+from collections import defaultdict
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row and row[n] != "":
+            return row[n]
+    raise KeyError(f"none of {names} in the CSV header")
+
+
+def _short(name):
+    # drop the argument list of a demangled kernel name, keep its template arguments
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            name = name[:i]
+            break
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    return name.replace("vp::", "")
+
+
+def trace(path, match=None):
+    groups = defaultdict(list)
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            name = _short(_col(row, "Kernel_Name"))
+            if match and not re.search(match, name):
+                continue
+            grid = int(_col(row, "Grid_Size_X", "Grid_Size"))
+            dur = (int(_col(row, "End_Timestamp")) - int(_col(row, "Start_Timestamp"))) / 1e3
+            groups[(name, grid)].append(dur)
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
+    print("| kernel | grid | dispatches | avg us | median us | min us | max us | total us |")
+    print("|---|---|---|---|---|---|---|---|")
+    for (name, grid), d in rows:
+        print(f"| `{name}` | {grid} | {len(d)} | {statistics.fmean(d):.1f} | {statistics.median(d):.1f} | "
+              f"{min(d):.1f} | {max(d):.1f} | {sum(d):.1f} |")
+
+
+def pmc(path, match=None):
+    groups = defaultdict(lambda: defaultdict(list))
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            name = _short(_col(row, "Kernel_Name"))
+            if match and not re.search(match, name):
+                continue
+            grid = int(_col(row, "Grid_Size", "Grid_Size_X"))
+            groups[(name, grid)][_col(row, "Counter_Name")].append(float(_col(row, "Counter_Value")))
+    counters = sorted({c for g in groups.values() for c in g})
+    print("| kernel | grid | dispatches | " + " | ".join(f"{c} (median)" for c in counters) + " |")
+    print("|---|---|---|" + "---|" * len(counters))
+    for (name, grid), g in sorted(groups.items(), key=lambda kv: kv[0]):
+        n = max(len(v) for v in g.values())
+        vals = " | ".join(f"{statistics.median(g[c]):.0f}" if c in g else "" for c in counters)
+        print(f"| `{name}` | {grid} | {n} | {vals} |")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("kind", choices=["trace", "pmc"])
+    ap.add_argument("csv")
+    ap.add_argument("--match", default=None, help="keep kernels whose short name matches this regex")
+    a = ap.parse_args(argv)
+    (trace if a.kind == "trace" else pmc)(a.csv, a.match)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -65,7 +65,7 @@ class PlanInfo(ctypes.Structure):
                 ("split_level", ctypes.c_int32), ("corr_cells", ctypes.c_int32),
                 ("corr_shared_cells", ctypes.c_int32), ("corr_values_read", ctypes.c_int64),
                 ("corr_groups", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("root", ctypes.c_double * 3)]
+                ("root", ctypes.c_double * 3), ("table_pairs", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -43,7 +43,8 @@ def _plan(lib, vp, x, y, w, n, tx=None, ty=None, m=None, rowptr=None, col=None, 
 
 
 @pytest.mark.parametrize("case", ["n0", "nan", "m_mismatch", "rowptr0", "rowptr_dec", "col_range",
-                                  "order", "nbatch", "leaf", "fp32_mode", "flags"])
+                                  "order", "nbatch", "leaf", "fp32_mode", "flags", "root_node",
+                                  "root_target"])
 def test_plan_rejects_invalid(case):
     vp, lib = _lib()
     x = np.linspace(0, 1, 8)
@@ -74,7 +75,20 @@ def test_plan_rejects_invalid(case):
         kw["m2l_mode"] = 2  # FP32 M2L with precision FP64
     elif case == "flags":
         kw["flags"] = 4  # unknown bit
-    if case == "m_mismatch":
+    if case in ("root_node", "root_target"):
+        # a given root square must hold every node and target: [0, 1]^2 holds
+        # the nodes, and one point leaves it by one ulp
+        o = vp.default_options()
+        o.root[0], o.root[1], o.root[2] = 0.0, 0.0, 1.0
+        tx, ty = x.copy(), y.copy()
+        if case == "root_node":
+            x = x.copy(); x[7] = np.nextafter(1.0, 2.0)
+        else:
+            ty[2] = np.nextafter(0.0, -1.0)
+        kw["root"] = o.root
+        st, h, msg = _plan(lib, vp, x, y, w, n, tx=tx, ty=ty, m=8, rowptr=rowptr, col=col, val=val, **kw)
+        assert "outside the root square" in msg, msg
+    elif case == "m_mismatch":
         st, h, msg = _plan(lib, vp, x, y, w, n, m=7, rowptr=rowptr, col=col, val=val)
     else:
         st, h, msg = _plan(lib, vp, x, y, w, n, rowptr=rowptr, col=col, val=val, **kw)

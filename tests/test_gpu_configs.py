@@ -5,6 +5,8 @@ evaluates one by one (the tolerances are the workloads' accuracy targets:
 rel_inf <= 1e-12 in float64, <= 1e-6 in the FP32-bulk form, with
 rel_inf = max |u - u*| / max |u*| over the sample).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -124,18 +126,28 @@ def test_batched_small(nbatch):
     plan.close()
 
 
+GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_sample_smooth.npy")
+
+
 def test_config3_batched_sampled():
-    """4,194,304 nodes x 16 densities in one launch (fp64 p=30 and fp32-bulk p=14)."""
+    """4,194,304 nodes x 16 densities in one launch (fp64 p=30 and fp32-bulk
+    p=14), checked on all 4,096 sampled targets x 16 densities against the
+    oracle's stored smooth sums (tests/golden/make_c3_reference.py) plus the
+    oracle's correction rows; 16 of the sampled targets are re-evaluated by
+    the oracle here to confirm the file."""
     vp = _vp()
     wl = gen.config3()
-    sample = wl.sample[::8]  # 512 targets keep the oracle to a few seconds
-    ref = direct.evaluate(wl.x, wl.y, wl.w, wl.f, wl.rowptr, wl.col, wl.val, tidx=sample)
+    smooth = np.load(GOLDEN_C3)
+    assert smooth.shape == (wl.nbatch, wl.sample.size)
+    live = np.arange(0, wl.sample.size, 256)
+    assert relinf(smooth[:, live], direct.smooth(wl.x, wl.y, wl.w, wl.f, tidx=wl.sample[live])) <= 1e-15
+    ref = smooth + direct.csr(wl.rowptr, wl.col, wl.val, wl.f, tidx=wl.sample)
     f = _dev(wl.f)
     for precision, order, tol in (("fp64", 30, TOL64), ("fp32", 14, TOL32)):
         plan = _plan(vp, wl, order=order, precision=precision)
-        u = _host(plan.eval(f))[:, sample]
+        u = _host(plan.eval(f))[:, wl.sample]
         err = max(relinf(u[b], ref[b]) for b in range(wl.nbatch))
-        print(f"config3 {precision} p={order} x16: worst rel_inf={err:.3e}")
+        print(f"config3 {precision} p={order} x16 on {wl.sample.size} targets: worst rel_inf={err:.3e}")
         assert err <= tol
         plan.close()
 
@@ -189,7 +201,7 @@ def test_config4_gradients():
     refT = 2 * Vt[None, :] * dV
     err = relinf(gT, refT)
     print(f"config4 dL/dr0 vs oracle gradient: rel_inf={err:.3e}")
-    assert err <= 1e-11
+    assert err <= TOL64
     assert relinf(_host(ut)[0], Vt) <= TOL64
     # central difference of the oracle potential at a few targets (h = 1e-6)
     k = np.arange(0, 4096, 512)

@@ -191,7 +191,11 @@ def sample_indices(m: int, count: int, seed: int):
 # --------------------------------------------------------------------------
 
 def uniform_config(nbox_side: int, f_seeds, csr_seed: Optional[int], sample_seed: Optional[int],
-                   name: str, nsample: int = 4096):
+                   name: str, nsample: int = 4096, shared_blocks: bool = True):
+    """Uniform grid workload.  With shared_blocks every box carries one
+    64 x 64 correction block (all boxes have one size and one map, so their
+    singular corrections form one table); without, every value is drawn on
+    its own (normal, standard deviation 1e-3)."""
     x, y, w = uniform_grid(nbox_side)
     fs = [gaussian_sum_density(x, y, s)[0] for s in f_seeds]
     f = np.stack(fs)
@@ -199,8 +203,8 @@ def uniform_config(nbox_side: int, f_seeds, csr_seed: Optional[int], sample_seed
         rowptr = col = val = None
     else:
         cell_ptr = np.arange(0, x.shape[0] + 1, 64, dtype=np.int64)
-        # all boxes have one size: one shared correction block
-        rowptr, col, val = own_cell_csr(cell_ptr, csr_seed, cell_class=np.zeros(nbox_side * nbox_side, np.int64))
+        cls = np.zeros(nbox_side * nbox_side, np.int64) if shared_blocks else None
+        rowptr, col, val = own_cell_csr(cell_ptr, csr_seed, cell_class=cls)
     sample = None if sample_seed is None else sample_indices(x.shape[0], nsample, sample_seed)
     return Workload(name=name, x=x, y=y, w=w, f=f, tx=None, ty=None, rowptr=rowptr,
                     col=col, val=val, root=(-1.0, -1.0, 2.0), sample=sample,
@@ -217,9 +221,10 @@ def config2():
     return uniform_config(128, [20], 21, 120, "uniform128x128_gl8")
 
 
-def config3(nbatch: int = 16):
+def config3(nbatch: int = 16, shared_blocks: bool = True):
     """256x256 boxes of 8x8 GL nodes (4,194,304 nodes), 16 densities."""
-    return uniform_config(256, list(range(30, 30 + nbatch)), 46, 130, "uniform256x256_gl8_b16")
+    name = "uniform256x256_gl8_b16" + ("" if shared_blocks else "_per_entry_corr")
+    return uniform_config(256, list(range(30, 30 + nbatch)), 46, 130, name, shared_blocks=shared_blocks)
 
 
 def config4():
