@@ -154,6 +154,26 @@ vp_status vp_eval_adjoint(vp_plan_t plan, const double *g, double *df);
  */
 vp_status vp_eval_grad_targets(vp_plan_t plan, const double *f, double *grad);
 
+/*
+ * vp_eval_noalloc -- vp_eval for callers that cannot allocate device memory
+ * at evaluation time, nor have it allocated for them (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, result and stream semantics as vp_eval, with the same kernels;
+ * the evaluation workspace (charges, multipole and local expansions, the
+ * near- and far-field sums) lives in a static device array of the library
+ * instead of the plan's own workspace, so the call allocates and frees
+ * nothing (and calls no allocating library routine).
+ *   Limit: the workspace must fit in VP_NOALLOC_MAX_BYTES (vp_get_info
+ *   reports noalloc_bytes); a larger plan returns VP_EINVAL and does nothing.
+ *   Every plan on a device shares that device's one array, which keeps the
+ *   contents of the last call (each call clears what it needs zeroed): calls
+ *   that overlap on one device (two streams, two host threads, or a call
+ *   while an earlier one is still running on another stream) race and give
+ *   wrong results.  Calls on one stream in sequence are safe.
+ */
+#define VP_NOALLOC_MAX_BYTES (64u << 20)
+vp_status vp_eval_noalloc(vp_plan_t plan, const double *f, double *u);
+
 /* Change the stream later evaluations run on (hipStream_t; NULL = null stream). */
 vp_status vp_set_stream(vp_plan_t plan, void *stream);
 
@@ -194,6 +214,7 @@ typedef struct {
     double root[3];
     int64_t table_pairs;       /* (target, source) pairs per density served by the near-field
                                   tables (near_pairs holds the pairwise kernel's) */
+    int64_t noalloc_bytes;     /* static workspace vp_eval_noalloc needs for this plan */
 } vp_plan_info_t;
 
 vp_status vp_get_info(vp_plan_t plan, vp_plan_info_t *info);

@@ -66,6 +66,57 @@ static void release_streams(vp_plan_s *P) {
     throw Error(VP_EDEVICE, buf);
 }
 
+// ---------------------------------------------------------------------------
+// Static evaluation workspace (vp_eval_noalloc).  Each device that loads the
+// library's code object holds its own copy of `scratch` until the process
+// ends.  In host code the array's name is not a device address: its address
+// on a device comes from hipGetSymbolAddress, resolved once per device with
+// that device current (at plan time) and kept in g_scratch; host code passes
+// only that address on.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[VP_NOALLOC_MAX_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch;
+
+// address of this device's scratch array; the device must be current
+static void *scratch_address(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(device);
+    if (it != g_scratch.end()) return it->second;
+    void *ptr = nullptr;
+    VP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Error(VP_EDEVICE, "hipGetSymbolAddress returned no address for the static workspace");
+    g_scratch[device] = ptr;
+    return ptr;
+}
+
+// The evaluation workspace carved from one base address, each part aligned
+// to 256 bytes; returns the bytes used (base == nullptr: only the size).
+static size_t carve_workspace(vp_plan_s *P, unsigned char *base, double **q, double **acc, double **acc_far,
+                              void **M, void **L) {
+    const int64_t len = std::max(P->n, P->m);
+    const size_t esz = P->fp32 ? 4 : 8;
+    const size_t ecount = (size_t)P->tree.nbox * P->nbatch * P->PD;
+    const size_t mcount = (size_t)(P->tree.nbox + 4 * (size_t)P->n_vleaf) * P->nbatch * P->PD;
+    const size_t sizes[5] = {8 * (size_t)P->nbatch * len, 8 * (size_t)P->nbatch * len,
+                             8 * (size_t)P->nbatch * len, mcount * esz, ecount * esz};
+    void *parts[5];
+    size_t off = 0;
+    for (int k = 0; k < 5; ++k) {
+        parts[k] = base ? base + off : nullptr;
+        off += (sizes[k] + 255) / 256 * 256;
+    }
+    if (base) {
+        *q = static_cast<double *>(parts[0]);
+        *acc = static_cast<double *>(parts[1]);
+        *acc_far = static_cast<double *>(parts[2]);
+        *M = parts[3];
+        *L = parts[4];
+    }
+    return off;
+}
+
 }  // namespace vp
 
 using vp::Error;
@@ -256,6 +307,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->m2l_mode = o.m2l_mode == VP_M2L_AUTO ? (P->fp32 ? VP_M2L_FP32_SCALED : VP_M2L_FP64_SCALED) : o.m2l_mode;
         P->stream = static_cast<hipStream_t>(o.stream);
         VP_HIP(hipGetDevice(&P->device));
+        P->scratch_dev = vp::scratch_address(P->device);
         vp::acquire_streams(P);
         for (hipEvent_t *e : {&P->ev_fork, &P->ev_join, &P->ev_p2m, &P->ev_p2l, &P->ev_upper, &P->ev_coarse, &P->ev_m2p})
             VP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
@@ -337,6 +389,49 @@ extern "C" vp_status vp_eval(vp_plan_t P, const double *f, double *u) {
         vp::prepare_charges(P, f, false);
         vp::run_fmm(P, false, false, f, u);
     });
+}
+
+extern "C" vp_status vp_eval_noalloc(vp_plan_t P, const double *f, double *u) {
+    if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
+    if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned by an earlier device error: " + P->err);
+    if (!f || !u) return set_err(P, VP_EINVAL, "f and u must not be NULL");
+    if (overlaps(f, 8 * (size_t)P->nbatch * P->n, u, 8 * (size_t)P->nbatch * P->m))
+        return set_err(P, VP_EINVAL, "f and u overlap");
+    const size_t need = vp::carve_workspace(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (need > VP_NOALLOC_MAX_BYTES)
+        return set_err(P, VP_EINVAL, "the evaluation workspace of this plan (" + std::to_string(need) +
+                                         " bytes) exceeds the static workspace of vp_eval_noalloc (" +
+                                         std::to_string((size_t)VP_NOALLOC_MAX_BYTES) + " bytes)");
+    if (!P->scratch_dev) return set_err(P, VP_EINTERNAL, "static workspace address not resolved");
+    // the same evaluation as vp_eval with the plan's workspace pointers
+    // swapped for parts of the static array (restored afterwards; the kernels
+    // have taken their arguments at launch)
+    double *q0 = P->q, *acc0 = P->acc, *far0 = P->acc_far;
+    void *M0 = P->Mexp, *L0 = P->Lexp;
+    vp::carve_workspace(P, static_cast<unsigned char *>(P->scratch_dev), &P->q, &P->acc, &P->acc_far, &P->Mexp,
+                        &P->Lexp);
+    vp_status st = guarded(P, [&] {
+        // the expansions' padding rows must be zero (the plan zeroes its own
+        // arrays once; the static array holds whatever the last call left)
+        const int64_t ecount = (int64_t)P->tree.nbox * P->nbatch * P->PD;
+        const int64_t mcount = (int64_t)(P->tree.nbox + 4 * (int64_t)P->n_vleaf) * P->nbatch * P->PD;
+        if (P->fp32) {
+            vp::fill_f32(static_cast<float *>(P->Mexp), 0.f, mcount, P->stream);
+            vp::fill_f32(static_cast<float *>(P->Lexp), 0.f, ecount, P->stream);
+        } else {
+            vp::fill_f64(static_cast<double *>(P->Mexp), 0.0, mcount, P->stream);
+            vp::fill_f64(static_cast<double *>(P->Lexp), 0.0, ecount, P->stream);
+        }
+        P->timing_eval_begin();
+        vp::prepare_charges(P, f, false);
+        vp::run_fmm(P, false, false, f, u);
+    });
+    P->q = q0;
+    P->acc = acc0;
+    P->acc_far = far0;
+    P->Mexp = M0;
+    P->Lexp = L0;
+    return st;
 }
 
 extern "C" vp_status vp_eval_adjoint(vp_plan_t P, const double *g, double *df) {
@@ -443,6 +538,7 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->table_tile_ops = P->near.table_tile_ops;
     for (int k = 0; k < 3; ++k) info->root[k] = P->opt.root[k];
     info->table_pairs = P->table_pairs;
+    info->noalloc_bytes = (int64_t)vp::carve_workspace(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     return VP_OK;
 }
 

@@ -312,6 +312,7 @@ struct vp_plan_s {
     void *Mexp = nullptr;    // [nbox + 4 n_vleaf][nbatch][PD] (double or float)
     void *Lexp = nullptr;
     void *zero_col = nullptr;  // max(PD, 128) zero doubles (an absent source column, either element type)
+    void *scratch_dev = nullptr;  // this device's static workspace (vp_eval_noalloc), resolved at plan time
     vp::P2PGather g_fwd, g_adj;   // full U-list sources (nodes / targets as sources) without tables
     // M2L launches: [0] levels >= split_level, [1] levels 2 .. split_level-1
     vp::M2LSched m2l[2];

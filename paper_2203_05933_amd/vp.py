@@ -34,7 +34,7 @@ _ARR_DTYPE = {0: np.int32, 1: np.int32, 2: np.int32, 3: np.int32, 4: np.int32, 5
 
 # Every entry point declared in include/vp.h.
 EXPORTS = ("vp_default_options", "vp_plan", "vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets",
-           "vp_set_stream", "vp_destroy", "vp_last_error", "vp_get_info", "vp_get_array",
+           "vp_eval_noalloc", "vp_set_stream", "vp_destroy", "vp_last_error", "vp_get_info", "vp_get_array",
            "vp_set_timing", "vp_get_timing")
 STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish", "tables", "corr", "coarse", "p2m_pat", "m2p")
 
@@ -65,7 +65,8 @@ class PlanInfo(ctypes.Structure):
                 ("split_level", ctypes.c_int32), ("corr_cells", ctypes.c_int32),
                 ("corr_shared_cells", ctypes.c_int32), ("corr_values_read", ctypes.c_int64),
                 ("corr_groups", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("root", ctypes.c_double * 3), ("table_pairs", ctypes.c_int64)]
+                ("root", ctypes.c_double * 3), ("table_pairs", ctypes.c_int64),
+                ("noalloc_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -93,7 +94,7 @@ def load_library(path: str = LIB_PATH):
     lib.vp_plan.argtypes = [dp, dp, dp, ctypes.c_int64, dp, dp, ctypes.c_int64, dp, dp, dp,
                             ctypes.POINTER(Options), ctypes.POINTER(vp)]
     lib.vp_plan.restype = ctypes.c_int
-    for name in ("vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets"):
+    for name in ("vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets", "vp_eval_noalloc"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, dp, dp]
         fn.restype = ctypes.c_int
@@ -210,6 +211,15 @@ class Plan:
         if out is None:
             out = torch.empty((self.nbatch, self.m), dtype=torch.float64, device=f.device)
         self._check(self._lib.vp_eval(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def eval_noalloc(self, f: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """vp_eval_noalloc: as eval, with the workspace in the library's static
+        device array (the caller provides the output)."""
+        f = self._dev(f, self.n, "f")
+        out = self._dev(out, self.m, "out")
+        self._check(self._lib.vp_eval_noalloc(self._h, ctypes.c_void_p(f.data_ptr()),
+                                              ctypes.c_void_p(out.data_ptr())))
         return out
 
     def eval_adjoint(self, g: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
