@@ -1729,7 +1729,8 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
 // fixed-matrix launches on pattern leaves (launch_pattern_ops)
 enum { PAT_P2M = 0, PAT_L2P = 1 };
 template <class E>
-static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind, double *acc = nullptr);
+static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind, double *acc = nullptr,
+                           FinishArgs fin = FinishArgs());
 
 // M2L of the V lists (and X-list virtual children) of one level range
 // (part 0: levels from the split level on, part 1: the levels below) in one
@@ -1942,7 +1943,8 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     a.logside = P->tree.d_logside;
     a.zero_col = P->zero_col;
     if (a.ncols <= 0) return;
-    hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, true>),
+    // every table leaf's sums are stored by its one tile (the other leaves are zeroed)
+    hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, false>),
                        dim3((unsigned)((a.ncols + 15) / 16)), dim3(256), 0, P->stream, a, N.K, (const double *)nullptr,
                        P->q, P->acc);
     VP_LAUNCH_CHECK();
@@ -1962,11 +1964,41 @@ static void run_tables(vp_plan_s *P, const PointRoles &R) {
     }
 }
 
+// One fixed operator over ncols columns (k_fixed_apply): four waves per
+// workgroup, at most four resident workgroups per compute unit's worth of
+// tiles (the kernel walks the rest with a grid stride).
+template <class TI, class TO, class TM, int RB, int S, bool ACCUM, bool FIN = false>
+static void launch_fixed_apply(vp_plan_s *P, const int32_t *cols_box, int ncols, ColAddr ia, ColAddr oa,
+                               int nrows_out, const TM *A, const TI *in, TO *out, const int32_t *addflag = nullptr,
+                               FinishArgs fin = FinishArgs()) {
+    if (ncols <= 0) return;
+    const int ntiles = (ncols + 15) / 16;
+    const unsigned grid = (unsigned)std::min((ntiles + 3) / 4, 512);
+    hipLaunchKernelGGL((k_fixed_apply<TI, TO, TM, RB, S, ACCUM, FIN>), dim3(grid), dim3(256), 0, P->stream,
+                       cols_box, ncols, P->nbatch, ia, oa, nrows_out, A, in, out, addflag, fin);
+    VP_LAUNCH_CHECK();
+}
+
+// zero the sums of the targets of the listed leaves (all densities)
+__global__ void k_zero_leaves(const int32_t *__restrict__ leaves, const int32_t *__restrict__ tb,
+                              const int32_t *__restrict__ te, int nbatch, int64_t ntgt, double *__restrict__ acc) {
+    const int b = leaves[blockIdx.x];
+    const int t0 = tb[b], nt = te[b] - t0;
+    for (int e = threadIdx.x; e < nt * nbatch; e += blockDim.x)
+        acc[(int64_t)(e / nt) * ntgt + t0 + e % nt] = 0.0;
+}
+
+static void zero_leaves(vp_plan_s *P, const PointRoles &R, const int32_t *leaves, int n, double *acc) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_leaves, dim3(n), dim3(256), 0, P->stream, leaves, R.tb, R.te, P->nbatch, R.ntgt, acc);
+    VP_LAUNCH_CHECK();
+}
+
 // Fixed-matrix launches on pattern leaves: P2M (q -> M, with the quadrant
 // P2M of pattern X-list sources into their virtual-child columns) and L2P
 // (L -> acc)
 template <class E, int RBP, int RBE>
-static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, double *acc) {
+static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, double *acc, FinishArgs fin) {
     NearTables &N = P->near;
     const bool f32 = sizeof(E) == 4;
     TranslateArgs a;
@@ -1987,15 +2019,21 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, doub
         constexpr int RB = RBE, S = RBP * 4;
         constexpr bool LDSA = translate_ldsa<E, RB, S, false>();
         constexpr size_t lds = LDSA ? translate_lds_bytes<E, RB, S, false>() : 0;
-        a.cols_box = N.p2m_cols;
-        a.ncols = N.n_p2m_cols * P->nbatch;
-        a.slots = N.p2m_slot;
-        a.nops = 5;
         a.in = ColAddr{R.nsrc, 0, R.sb};
         a.out = ColAddr{P->PD, (int64_t)P->nbatch * P->PD, nullptr};
         a.nrows_out = P->PD;
-        if (a.ncols <= 0) return;
         const E *op = f32 ? (const E *)N.p2m_op_f32 : (const E *)N.p2m_op;
+        // the leading pattern-leaf columns all use operator 0: one fixed operator
+        const int n0 = N.n_p2m_leaf_cols;
+        if (n0 > 0)
+            launch_fixed_apply<double, E, E, RB, S, false>(P, N.p2m_cols, n0 * P->nbatch, a.in, a.out, a.nrows_out,
+                                                           op, P->q, static_cast<E *>(P->Mexp));
+        // the quadrant columns of X-list sources (operators 1..4)
+        a.cols_box = N.p2m_cols + n0;
+        a.ncols = (N.n_p2m_cols - n0) * P->nbatch;
+        a.slots = N.p2m_slot;
+        a.nops = 5;
+        if (a.ncols <= 0) return;
         hipLaunchKernelGGL((k_translate<double, E, E, RB, S, false, false, LDSA>),
                            dim3((unsigned)((a.ncols + 63) / 64)), dim3(256), lds, P->stream, a, op, (const E *)nullptr,
                            P->q, static_cast<E *>(P->Mexp));
@@ -2008,8 +2046,15 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, doub
         a.nrows_out = N.npat;
         if (a.ncols <= 0) return;
         const E *op = f32 ? (const E *)N.l2p_op_f32 : (const E *)N.l2p_op;
-        hipLaunchKernelGGL((k_pattern_op<E, double, E, RBE * 4, true>), dim3((unsigned)((a.ncols + 15) / 16)),
-                           dim3(64 * RBP), 0, P->stream, a, op, static_cast<const E *>(P->Lexp), acc);
+        if (fin.u)
+            launch_fixed_apply<E, double, E, RBP, RBE * 4, false, true>(
+                P, a.cols_box, a.ncols, a.in, a.out, a.nrows_out, op, static_cast<const E *>(P->Lexp), acc,
+                nullptr, fin);
+        else
+            launch_fixed_apply<E, double, E, RBP, RBE * 4, false>(P, a.cols_box, a.ncols, a.in, a.out, a.nrows_out,
+                                                                 op, static_cast<const E *>(P->Lexp), acc,
+                                                                 N.far_add);
+        return;
     }
     VP_LAUNCH_CHECK();
 }
@@ -2019,11 +2064,11 @@ bool pattern_op_supported(int npat, int PD) {
 }
 
 template <class E>
-static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind, double *acc) {
+static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind, double *acc, FinishArgs fin) {
     const int key = P->near.npat / 16 * 16 + P->PD / 16;
     switch (key) {
 #define VP_PAT(NP, NE) \
-    case NP * 16 + NE: launch_pattern_ops<E, NP, NE>(P, R, kind, acc); break;
+    case NP * 16 + NE: launch_pattern_ops<E, NP, NE>(P, R, kind, acc, fin); break;
         VP_PAT(1, 1) VP_PAT(1, 2) VP_PAT(1, 3) VP_PAT(1, 4)
         VP_PAT(2, 1) VP_PAT(2, 2) VP_PAT(2, 3) VP_PAT(2, 4)
         VP_PAT(4, 1) VP_PAT(4, 2) VP_PAT(4, 3) VP_PAT(4, 4)
@@ -2033,7 +2078,8 @@ static void run_pattern_op(vp_plan_s *P, const PointRoles &R, int kind, double *
 }
 
 template <class E, bool GRAD>
-static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *acc, bool tables, int parts) {
+static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *acc, bool tables, int parts,
+                    FinishArgs fin = FinishArgs()) {
     // parts: bit 0 the local expansions at the targets (L2P), bit 1 the W lists (M2P)
     Tree &T = P->tree;
     NearTables &N = P->near;
@@ -2055,7 +2101,7 @@ static void run_far(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, double *
         }
     } else if (parts == 1) {
         if (tables) {
-            run_pattern_op<E>(P, R, PAT_L2P, acc);
+            run_pattern_op<E>(P, R, PAT_L2P, acc, fin);
             far(N.l2p_rest, N.n_l2p_rest, nullptr, 1);
         } else {
             far(T.leaves, T.nleaf, nullptr, 1);
@@ -2091,6 +2137,8 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
     const bool fmm = T.nlevels >= 3;  // otherwise no box is well separated from another
     const int L0 = P->split_level, Lmax = T.nlevels - 1;
     const bool coarse = fmm && L0 > 2;
+    // forward evaluation on an all-pattern grid: the L2P launch writes the output
+    const bool fused = tables && fmm && N.fused_finish && !adjoint && u != nullptr;
     hipStream_t ms = P->stream;
     hipStream_t s2 = one ? ms : P->aux, s3 = one ? ms : P->aux2;
     struct Restore {
@@ -2118,7 +2166,8 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         run_p2l<E>(P, R, G);
         P->stage_end(VP_STAGE_P2L);
     }
-    if (!grad) fill_f64(P->acc_far, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
+    if (tables) zero_leaves(P, R, N.zero_far, N.n_zero_far, P->acc_far);
+    else if (!grad) fill_f64(P->acc_far, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
     if (!one) VP_HIP(hipEventRecord(P->ev_p2l, s3));
     // second stream: correction (HBM bound) and the near field
     P->stream = s2;
@@ -2145,8 +2194,9 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         }
         P->stage_end(VP_STAGE_P2P);
     };
-    // with tables both near-field kernels add to zeroed potentials
-    if (tables) fill_f64(P->acc, 0.0, (int64_t)P->nbatch * R.ntgt, P->stream);
+    // with tables the table launch stores its leaves' sums; the other leaves
+    // are zeroed for the pairwise kernel, which adds
+    if (tables) zero_leaves(P, R, N.zero_near, N.n_zero_near, P->acc);
     corr();
     tab();
     // (the W lists and the pairwise near field follow once every multipole is done)
@@ -2226,10 +2276,21 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
         // local expansions at the targets, after the W lists (same array, on
         // the second stream: the join covers them)
         if (!one) VP_HIP(hipStreamWaitEvent(ms, P->ev_join, 0));
-        if (fmm) run_far<E, false>(P, R, G, P->acc_far, tables, 1);
+        if (fused) {
+            // the pattern L2P adds the near field and the correction row and
+            // writes the output (the join also covers the correction)
+            FinishArgs fin;
+            fin.near = P->acc;
+            fin.perm = P->tperm;
+            fin.m = P->m;
+            fin.u = u;
+            run_far<E, false>(P, R, G, P->acc_far, tables, 1, fin);
+        } else if (fmm) {
+            run_far<E, false>(P, R, G, P->acc_far, tables, 1);
+        }
     }
     P->stage_end(VP_STAGE_FAR);
-    if (u) add_fmm_sums(P, u, adjoint);
+    if (u && !fused) add_fmm_sums(P, u, adjoint);
 }
 
 void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) {

@@ -220,6 +220,7 @@ struct NearTables {
     // children of pattern X-list sources grouped by quadrant (operator 1 + q)
     int32_t *p2m_cols = nullptr;
     int n_p2m_cols = 0;
+    int n_p2m_leaf_cols = 0;          // of p2m_cols, the leading pattern leaves (operator 0)
     int32_t *p2m_slot = nullptr;      // [nbox + 4 n_vleaf][5] source leaf in the column's operator slot, or -1
     P2MJob *p2m_jobs_rest = nullptr;  // VALU P2M jobs of the rest (source role)
     int n_p2m_jobs_rest = 0;
@@ -230,6 +231,12 @@ struct NearTables {
     int32_t *l2p_rest = nullptr;      // leaves (level >= 2) whose local expansion is evaluated by the series
     int n_l2p_rest = 0;
     int32_t *local_done = nullptr;    // [nbox] 1: local expansion evaluated by the L2P operator
+    // leaves whose near / far sums are zeroed before their first (adding)
+    // writer; the tables and the pattern L2P store the others
+    int32_t *zero_near = nullptr, *zero_far = nullptr;
+    int n_zero_near = 0, n_zero_far = 0;
+    int32_t *far_add = nullptr;       // [nbox] 1: the pattern L2P adds (W lists wrote first); null: none
+    bool fused_finish = false;        // forward: the pattern L2P writes the output (see vp_near.hip)
     // [5][PD x npat] A-fragment order: the leaf P2M, then the four quadrant
     // P2M matrices (about the quadrant centre at the children's scale, zero
     // outside the quadrant's points)

@@ -326,6 +326,36 @@ void build_near_tables(vp_plan_s *P) {
     N.tab_cols_begin.push_back((int)tcols.size());
     N.tab_cols = upload(P, tcols);
     {
+        // First writers store instead of adding to zeroed sums.  Near field:
+        // the tables store the sums of their leaves (one tile covers all of a
+        // leaf's slots), so only the other leaves are zeroed before the
+        // pairwise kernel adds.  Far field: the pattern L2P stores, or adds
+        // where the W lists (evaluated before it) have written; the leaves it
+        // does not serve and those with W lists are zeroed first.  When every
+        // leaf with targets is a pattern L2P leaf without a W list, the L2P
+        // launch also adds the near field and the correction row and writes
+        // the output (forward evaluations).
+        std::vector<char> in_tab(nbox, 0), in_l2p(nbox, 0);
+        for (int b : tcols) in_tab[b] = 1;
+        for (int b : l2p_pat) in_l2p[b] = 1;
+        std::vector<int32_t> zn, zf, fadd(nbox, 0);
+        bool any_w = false;
+        for (int b : leaves) {
+            if (se[b] <= sb[b]) continue;  // no targets (targets are the nodes here)
+            const bool w = wptr[b + 1] > wptr[b];
+            if (!in_tab[b]) zn.push_back(b);
+            if (!in_l2p[b] || w) zf.push_back(b);
+            fadd[b] = w ? 1 : 0;
+            any_w = any_w || w;
+        }
+        N.n_zero_near = (int)zn.size();
+        N.n_zero_far = (int)zf.size();
+        N.zero_near = upload(P, zn);
+        N.zero_far = upload(P, zf);
+        N.far_add = any_w ? upload(P, fadd) : nullptr;
+        N.fused_finish = N.active && zf.empty() && N.n_l2p_rest == 0 && N.n_l2p_pat > 0;
+    }
+    {
         // one slot row per box spanning all table levels: the NTOPS slots of
         // the box's own level block hold its table sources, every other slot is -1
         const int nt = (int)N.tab_levels.size();
@@ -492,6 +522,7 @@ void build_near_tables(vp_plan_s *P) {
         for (int qd = 0; qd < 4; ++qd) cols.insert(cols.end(), qcols[qd].begin(), qcols[qd].end());
         jobs.insert(jobs.end(), rest_q.begin(), rest_q.end());
         N.n_p2m_cols = N.active ? (int)cols.size() : 0;
+        N.n_p2m_leaf_cols = N.active ? (int)p2m_pat.size() : 0;
         if (N.n_p2m_cols > 0) {
             N.p2m_cols = upload(P, cols);
             N.p2m_slot = upload(P, slot);

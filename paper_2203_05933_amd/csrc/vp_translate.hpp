@@ -223,6 +223,103 @@ __global__ void __launch_bounds__(256) k_pattern_op(TranslateArgs a, const TM *_
     }
 }
 
+// One fixed operator applied to many columns: out[:, c] (+)= A in[:, c]
+// (pattern P2M of leaves, pattern L2P).  A has RB 16-row blocks and S 4-row
+// input steps (A-fragment order).  Every wave keeps the whole operator in
+// registers for the launch and owns one 16-column tile at a time, walking
+// the tiles with a grid stride; it loads the next tile's input fragments
+// before the products of the current one, so the loads are in flight while
+// the matrix cores work.  Nothing is staged in LDS and there are no
+// barriers.  The products are formed transposed, D^T = in^T A^T (the input
+// fragments as the first matrix-core operand, the operator fragments, whose
+// A-fragment order is the B-fragment order of A^T, as the second), so that
+// a lane's results are one output row of four columns and a store
+// instruction writes 16 consecutive rows of four columns instead of four
+// rows of sixteen.  Each column's products still run s = 0 .. S-1 from zero
+// per row block.  The clamped last column stands in for columns past the
+// end (no branch around the loads); they store nothing.
+// addflag (optional): columns of boxes with addflag[box] != 0 add even
+// without ACCUM.  FIN (pattern L2P of a forward evaluation whose far field
+// has no other writer): the column's value v at sorted target t goes to the
+// output in user order, u[b][perm[t]] = (near[b][t] + v) + u[b][perm[t]]
+// (u holds the correction row), the sum k_add_acc forms otherwise.
+struct FinishArgs {
+    const double *near = nullptr;  // [nbatch][ntgt] near-field sums, sorted order
+    const int32_t *perm = nullptr; // sorted target -> user index
+    int64_t m = 0;                 // output row length
+    double *u = nullptr;
+};
+
+template <class TI, class TO, class TM, int RB, int S, bool ACCUM, bool FIN>
+__global__ void __launch_bounds__(256) k_fixed_apply(const int32_t *__restrict__ cols_box, int ncols, int nbatch,
+                                                     ColAddr ia, ColAddr oa, int nrows_out,
+                                                     const TM *__restrict__ A, const TI *__restrict__ in,
+                                                     TO *__restrict__ out, const int32_t *__restrict__ addflag,
+                                                     FinishArgs fin) {
+    typedef Mfma<TM> M;
+    const int lane = threadIdx.x & 63;
+    const int cl = lane & 15, g = lane >> 4;
+    TM av[RB][S];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int s = 0; s < S; ++s) av[r][s] = A[(r * S + s) * 64 + lane];
+    const int ntiles = (ncols + 15) / 16;
+    const int tstride = gridDim.x * (blockDim.x >> 6);
+    auto load = [&](int t, TM *bv) {
+        const int col = min(t * 16 + cl, ncols - 1);
+        const int box = cols_box[col / nbatch], bt = col % nbatch;
+        const TI *ip = in + ia.off(box) + (int64_t)bt * ia.bstride + g;
+#pragma unroll
+        for (int s = 0; s < S; ++s) bv[s] = (TM)ip[4 * s];
+    };
+    int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    TM bcur[S], bnext[S];
+    load(min(t, ntiles - 1), bcur);
+    for (; t < ntiles; t += tstride) {
+        load(min(t + tstride, ntiles - 1), bnext);
+        typename M::acc_t accs[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            accs[r] = M::zero();
+#pragma unroll
+            for (int s = 0; s < S; ++s) accs[r] = M::op(bcur[s], av[r][s], accs[r]);
+        }
+        // element i of a lane: output row r * 16 + cl of tile column M::row(i, g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int col = t * 16 + M::row(i, g);
+            if (col >= ncols) continue;
+            const int box = cols_box[col / nbatch], bt = col % nbatch;
+            const int64_t t0 = oa.off(box), nb0 = (int64_t)bt * oa.bstride;
+            if (FIN) {
+                double *ub = fin.u + (int64_t)bt * fin.m;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const int row = r * 16 + cl;
+                    if (row < nrows_out) {
+                        double *o = ub + fin.perm[t0 + row];
+                        *o = (fin.near[nb0 + t0 + row] + (double)accs[r][i]) + *o;
+                    }
+                }
+            } else {
+                TO *op = out + t0 + nb0;
+                const bool add = ACCUM || (addflag && addflag[box]);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const int row = r * 16 + cl;
+                    if (row < nrows_out) {
+                        if (add) op[row] += (TO)accs[r][i];
+                        else op[row] = (TO)accs[r][i];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) bcur[s] = bnext[s];
+    }
+}
+
 // Split-operator variant for the large M2L launch: the four waves of a
 // workgroup share ONE 16-column tile and take every fourth active operator,
 // reading operator fragments straight from L2 (no barriers in the main
