@@ -9,4 +9,8 @@ share come from the seeded generators in vp_workloads.
                          adjoint, target gradient), OpenMP over targets
   tree.py              : plain quadtree and U/V/W/X lists by definition
   expansions.py        : multipole/local coefficients by definition
+  fmm_truncated.py     : what an order-p FMM computes on a uniform tree
+  oversample.py        : the box oversampling map O_{p,q} (Chebyshev values ->
+                         coefficients -> values at finer roots) and the
+                         oversampled smooth sum with its adjoint
 """

@@ -36,6 +36,11 @@ __all__ = [
     "config4",
     "uniform_config",
     "star_radius",
+    "chebyshev_roots",
+    "fejer_weights",
+    "OversampledWorkload",
+    "oversampled_grid",
+    "config5",
 ]
 
 
@@ -84,6 +89,22 @@ class Workload:
         return self.tx is None
 
 
+@dataclasses.dataclass
+class OversampledWorkload(Workload):
+    """A box grid whose density is given at p x p interpolation nodes per box
+    (the targets) and whose smooth rule sits at q x q upsampled nodes (the
+    sources, x/y/w).  f is [nbatch, m] at the targets; the correction columns
+    index those values.  Box b holds targets b p^2 .. and sources b q^2 .."""
+
+    nbox: int = 0
+    p_interp: int = 0
+    q_interp: int = 0
+
+    @property
+    def n_in(self) -> int:
+        return int(self.f.shape[1])
+
+
 # --------------------------------------------------------------------------
 # Node sets
 # --------------------------------------------------------------------------
@@ -117,6 +138,71 @@ def uniform_grid(nbox_side: int, lo: float = -1.0, hi: float = 1.0, order: int =
     y = (cy[:, None] + 0.5 * h * eta[None, :]).ravel()
     w = np.broadcast_to(wref * (0.5 * h) ** 2, (nbox_side * nbox_side, order * order)).ravel().copy()
     return x, y, w
+
+
+def chebyshev_roots(n: int) -> np.ndarray:
+    """Roots of T_n on [-1, 1], ascending: -cos((2i+1) pi / (2n))."""
+    i = np.arange(n)
+    return -np.cos((2 * i + 1) * np.pi / (2 * n))
+
+
+def fejer_weights(n: int) -> np.ndarray:
+    """Weights of Fejer's first rule on the n roots of T_n (ascending):
+    w_j = (2/n) [1 - 2 sum_{k=1}^{n/2} cos(2 k theta_j) / (4k^2 - 1)],
+    theta_j = (2j+1) pi / (2n); they integrate every polynomial of degree
+    < n exactly over [-1, 1]."""
+    j = np.arange(n)
+    theta = (2 * j + 1) * np.pi / (2 * n)
+    k = np.arange(1, n // 2 + 1)
+    s = np.cos(2 * np.outer(theta, k)) / (4 * k * k - 1)
+    w = (2.0 / n) * (1.0 - 2.0 * s.sum(axis=1))
+    return w[::-1].copy()  # theta ascending is x descending: reverse for ascending roots
+
+
+def oversampled_grid(nbox_side: int, p: int, q: int, lo: float = -1.0, hi: float = 1.0):
+    """Box grid (box b = iy*nbox_side + ix) with p x p Chebyshev-root
+    targets and q x q Chebyshev-root sources per box (node a = jy*n + jx, x
+    fastest), source weights Fejer x Fejer x (side/2)^2 (they sum to the box
+    area).  Returns (tx, ty, x, y, w)."""
+    h = (hi - lo) / nbox_side
+    ix = np.tile(np.arange(nbox_side), nbox_side)
+    iy = np.repeat(np.arange(nbox_side), nbox_side)
+    cx = lo + (ix + 0.5) * h
+    cy = lo + (iy + 0.5) * h
+
+    def nodes(n):
+        r = chebyshev_roots(n)
+        xi, eta = np.tile(r, n), np.repeat(r, n)
+        return ((cx[:, None] + 0.5 * h * xi[None, :]).ravel(), (cy[:, None] + 0.5 * h * eta[None, :]).ravel())
+
+    tx, ty = nodes(p)
+    x, y = nodes(q)
+    wq = fejer_weights(q)
+    wref = np.repeat(wq, q) * np.tile(wq, q)
+    w = np.broadcast_to(wref * (0.5 * h) ** 2, (nbox_side * nbox_side, q * q)).ravel().copy()
+    return tx, ty, x, y, w
+
+
+def config5(nbox_side: int = 64, p: int = 8, q: int = 16, f_seeds=(50,), csr_seed: Optional[int] = 51,
+            sample_seed: Optional[int] = 150, nsample: int = 4096):
+    """Oversampled boxes (the paper's twofold oversampling q = 2p): a
+    nbox_side^2 grid on [-1,1]^2, the density at 8x8 Chebyshev-root
+    interpolation nodes per box (the targets), the smooth rule at 16x16
+    Chebyshev-root nodes with Fejer weights (the sources), own-box
+    correction rows over the box's density values (one shared 64 x 64
+    block).  Default 64 x 64 boxes: 262,144 targets, 1,048,576 sources."""
+    tx, ty, x, y, w = oversampled_grid(nbox_side, p, q)
+    f = np.stack([gaussian_sum_density(tx, ty, s)[0] for s in f_seeds])
+    nbox = nbox_side * nbox_side
+    if csr_seed is None:
+        rowptr = col = val = None
+    else:
+        cell_ptr = np.arange(0, tx.shape[0] + 1, p * p, dtype=np.int64)
+        rowptr, col, val = own_cell_csr(cell_ptr, csr_seed, cell_class=np.zeros(nbox, np.int64))
+    sample = None if sample_seed is None else sample_indices(tx.shape[0], nsample, sample_seed)
+    return OversampledWorkload(name=f"oversampled{nbox_side}x{nbox_side}_cheb{p}to{q}", x=x, y=y, w=w, f=f,
+                               tx=tx, ty=ty, rowptr=rowptr, col=col, val=val, root=(-1.0, -1.0, 2.0),
+                               sample=sample, meta={"boxes": nbox}, nbox=nbox, p_interp=p, q_interp=q)
 
 
 def gaussian_sum_density(x, y, seed: int, ncomp: int = 4, center_box: float = 0.8,
