@@ -133,6 +133,48 @@ vp_status vp_plan(const double *x, const double *y, const double *w, int64_t n,
                   const vp_options *opt, vp_plan_t *out);
 
 /*
+ * Oversampled boxes (Section 4.2, eq. fk_basis and eq. Tnm: the density on a
+ * box is its tensor-product Chebyshev interpolant of order p, given by its
+ * values at the p x p roots of T_p, and the smooth rule sits at the q x q
+ * roots of T_q, q >= p, the upsampling of Section 3.2 (the map O_{p,q} next
+ * to eq. vals_to_coeffs); Section 4, eq. nsrcs, counts those q^2 sources per
+ * box).  The caller gives the sources (the q x q nodes of every box, with
+ * their smooth-rule weights), the targets, and which density values and
+ * source nodes belong to each box; the library builds O (q^2 x p^2, the
+ * tensor product of the 1D Chebyshev interpolation matrix) itself.  Within a
+ * box, density value (ix, iy) sits at in_start[b] + iy*p + ix at the node
+ * (c + h/2 xi_ix, c + h/2 xi_iy) and source (jx, jy) at out_start[b] +
+ * jy*q + jx at (c + h/2 eta_jx, c + h/2 eta_jy), with xi / eta the roots of
+ * T_p / T_q in ascending order, xi_i = -cos((2i+1) pi / 2p).
+ */
+typedef struct {
+    int32_t p;                 /* density nodes per box side (1..32) */
+    int32_t q;                 /* source nodes per box side (p..32) */
+    int64_t nbox;              /* boxes; nbox * q * q must equal n */
+    int64_t n_in;              /* density values per density (the length of f's rows) */
+    const int64_t *in_start;   /* host [nbox]: first density value of box b (p*p values,
+                                  disjoint between boxes, within [0, n_in)) */
+    const int64_t *out_start;  /* host [nbox]: first source node of box b (q*q nodes,
+                                  disjoint, together covering [0, n)) */
+} vp_oversampling;
+
+/*
+ * vp_plan_oversampled -- as vp_plan, for the oversampled smooth rule:
+ *   u[b][i] = sum_j G(r_j, t_i) w_j (O f[b])_j + sum_k C[i,k] f[b][k],
+ * f [nbatch][n_in] the density values, O applied per box, C's columns index
+ * the density values (0 <= col < n_in).  Targets must be given (tx, ty).
+ * vp_eval / vp_eval_noalloc take f [nbatch][n_in]; vp_eval_adjoint returns
+ * df [nbatch][n_in] = O^T (w * V^T g) + C^T g; vp_eval_grad_targets takes f
+ * [nbatch][n_in].  Errors: as vp_plan, and VP_EINVAL for a layout outside the
+ * rules above (os == NULL, p or q out of range, ranges out of bounds or
+ * overlapping, sources not covered, no targets).
+ */
+vp_status vp_plan_oversampled(const double *x, const double *y, const double *w, int64_t n,
+                              const double *tx, const double *ty, int64_t m,
+                              const int64_t *rowptr, const int32_t *col, const double *val,
+                              const vp_oversampling *os, const vp_options *opt, vp_plan_t *out);
+
+/*
  * vp_eval -- u[b][i] = sum_j G(r_j, t_i) w_j f[b][j] + sum_k C[i,k] f[b][k].
  *   f [nbatch][n] device, u [nbatch][m] device; f and u must not overlap.
  */
@@ -215,6 +257,8 @@ typedef struct {
     int64_t table_pairs;       /* (target, source) pairs per density served by the near-field
                                   tables (near_pairs holds the pairwise kernel's) */
     int64_t noalloc_bytes;     /* static workspace vp_eval_noalloc needs for this plan */
+    int64_t n_in;              /* density values per density (n unless oversampled) */
+    int32_t os_p, os_q;        /* oversampled plan: nodes per box side (0, 0: none) */
 } vp_plan_info_t;
 
 vp_status vp_get_info(vp_plan_t plan, vp_plan_info_t *info);

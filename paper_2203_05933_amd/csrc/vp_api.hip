@@ -200,7 +200,7 @@ extern "C" void vp_default_options(vp_options *opt) {
 static void validate_plan_args(const double *x, const double *y, const double *w, int64_t n,
                                const double *tx, const double *ty, int64_t m, const int64_t *rowptr,
                                const int32_t *col, const double *val, const vp_options &o,
-                               vp_plan_t *out) {
+                               vp_plan_t *out, int64_t nd) {
     auto bad = [](const std::string &s) { throw Error(VP_EINVAL, s); };
     if (!out) bad("out is NULL");
     if (!x || !y || !w) bad("x, y and w must not be NULL");
@@ -226,7 +226,7 @@ static void validate_plan_args(const double *x, const double *y, const double *w
         int64_t nnz = rowptr[m];
         if (nnz > 0x7FFFFFFF) throw Error(VP_EUNSUPPORTED, "more than 2^31-1 correction non-zeros");
         for (int64_t q = 0; q < nnz; ++q)
-            if (col[q] < 0 || col[q] >= n) bad("col out of range at non-zero " + std::to_string(q));
+            if (col[q] < 0 || col[q] >= nd) bad("col out of range at non-zero " + std::to_string(q));
         for (int64_t q = 0; q < nnz; ++q)
             if (!std::isfinite(val[q])) bad("non-finite correction value at non-zero " + std::to_string(q));
     }
@@ -275,20 +275,105 @@ static void free_plan(vp_plan_s *P) {
     delete P;
 }
 
-extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, int64_t n, const double *tx,
-                             const double *ty, int64_t m, const int64_t *rowptr, const int32_t *col,
-                             const double *val, const vp_options *opt, vp_plan_t *out) {
+// Oversampled boxes: checks of the layout (see vp_plan_oversampled)
+static void validate_oversampling(const vp_oversampling *os, int64_t n, const double *tx) {
+    auto bad = [](const std::string &s) { throw Error(VP_EINVAL, s); };
+    if (!tx) bad("an oversampled plan needs its targets (tx, ty): the density nodes are not the sources");
+    if (os->p < 1 || os->q < os->p || os->q > 32) bad("oversampling needs 1 <= p <= q <= 32");
+    if (os->nbox < 1) bad("oversampling needs at least one box");
+    if (!os->in_start || !os->out_start) bad("in_start and out_start must not be NULL");
+    if (os->n_in < 1 || os->n_in > 0x3FFFFFFF) bad("n_in must be in 1..2^30-1");
+    const int64_t p2 = (int64_t)os->p * os->p, q2 = (int64_t)os->q * os->q;
+    if (os->nbox * q2 != n) bad("the boxes' q x q source blocks must cover the n sources exactly");
+    std::vector<std::pair<int64_t, int64_t>> in(os->nbox), outr(os->nbox);
+    for (int64_t b = 0; b < os->nbox; ++b) {
+        if (os->in_start[b] < 0 || os->in_start[b] + p2 > os->n_in)
+            bad("box " + std::to_string(b) + ": density values out of range");
+        if (os->out_start[b] < 0 || os->out_start[b] + q2 > n)
+            bad("box " + std::to_string(b) + ": source nodes out of range");
+        in[b] = {os->in_start[b], b};
+        outr[b] = {os->out_start[b], b};
+    }
+    std::sort(in.begin(), in.end());
+    std::sort(outr.begin(), outr.end());
+    for (int64_t b = 1; b < os->nbox; ++b) {
+        if (in[b].first < in[b - 1].first + p2) bad("the boxes' density values overlap");
+        if (outr[b].first < outr[b - 1].first + q2) bad("the boxes' source nodes overlap");
+    }
+}
+
+// 1D map from the values at the p roots of T_p (ascending) to the degree
+// < p interpolant's values at the q roots of T_q, by the barycentric formula
+// with the weights of Chebyshev points of the first kind,
+// lambda_i = (-1)^i sin((2i+1) pi / 2p) (a common sign cancels); rows [q][p].
+static std::vector<long double> cheb_interp_1d(int p, int q) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> xp(p), xq(q), lam(p), L((size_t)q * p, 0.0L);
+    for (int i = 0; i < p; ++i) {
+        xp[i] = -std::cos((2 * i + 1) * pi / (2 * p));
+        lam[i] = ((i & 1) ? -1.0L : 1.0L) * std::sin((2 * i + 1) * pi / (2 * p));
+    }
+    for (int j = 0; j < q; ++j) xq[j] = -std::cos((2 * j + 1) * pi / (2 * q));
+    for (int j = 0; j < q; ++j) {
+        int hit = -1;
+        for (int i = 0; i < p; ++i)
+            if (xq[j] == xp[i]) hit = i;
+        if (hit >= 0) {
+            L[(size_t)j * p + hit] = 1.0L;
+            continue;
+        }
+        long double den = 0.0L;
+        for (int i = 0; i < p; ++i) den += lam[i] / (xq[j] - xp[i]);
+        for (int i = 0; i < p; ++i) L[(size_t)j * p + i] = lam[i] / (xq[j] - xp[i]) / den;
+    }
+    return L;
+}
+
+static void build_oversampling(vp_plan_s *P, const vp_oversampling *os) {
+    const int p = os->p, q = os->q, p2 = p * p, q2 = q * q;
+    P->os_p = p;
+    P->os_q = q;
+    P->os_nbox = os->nbox;
+    const std::vector<long double> L = cheb_interp_1d(p, q);
+    // tensor product, node a = jy * n + jx on both sides
+    std::vector<double> O((size_t)q2 * p2), OT((size_t)p2 * q2);
+    for (int jy = 0; jy < q; ++jy)
+        for (int jx = 0; jx < q; ++jx)
+            for (int iy = 0; iy < p; ++iy)
+                for (int ix = 0; ix < p; ++ix) {
+                    const double v = (double)(L[(size_t)jy * p + iy] * L[(size_t)jx * p + ix]);
+                    const int r = jy * q + jx, c = iy * p + ix;
+                    O[(size_t)r * p2 + c] = v;
+                    OT[(size_t)c * q2 + r] = v;
+                }
+    P->os_O = P->mem.alloc<double>(O.size());
+    P->os_OT = P->mem.alloc<double>(OT.size());
+    P->os_in = P->mem.alloc<int64_t>(os->nbox);
+    P->os_out = P->mem.alloc<int64_t>(os->nbox);
+    VP_HIP(hipMemcpyAsync(P->os_O, O.data(), 8 * O.size(), hipMemcpyHostToDevice, P->stream));
+    VP_HIP(hipMemcpyAsync(P->os_OT, OT.data(), 8 * OT.size(), hipMemcpyHostToDevice, P->stream));
+    VP_HIP(hipMemcpyAsync(P->os_in, os->in_start, 8 * os->nbox, hipMemcpyHostToDevice, P->stream));
+    VP_HIP(hipMemcpyAsync(P->os_out, os->out_start, 8 * os->nbox, hipMemcpyHostToDevice, P->stream));
+    VP_HIP(hipStreamSynchronize(P->stream));  // the host copies leave scope
+}
+
+static vp_status plan_impl(const double *x, const double *y, const double *w, int64_t n, const double *tx,
+                           const double *ty, int64_t m, const int64_t *rowptr, const int32_t *col,
+                           const double *val, const vp_oversampling *os, const vp_options *opt, vp_plan_t *out) {
     if (out) *out = nullptr;
     vp_options o;
     if (opt) o = *opt;
     else vp_default_options(&o);
     vp_plan_s *P = nullptr;
     vp_status st = guarded(nullptr, [&] {
-        validate_plan_args(x, y, w, n, tx, ty, m, rowptr, col, val, o, out);
+        if (os) validate_oversampling(os, n, tx);
+        const int64_t nd = os ? os->n_in : n;
+        validate_plan_args(x, y, w, n, tx, ty, m, rowptr, col, val, o, out, nd);
         P = new vp_plan_s();
         P->opt = o;
         P->n = n;
         P->m = m;
+        P->nd = nd;
         P->self = (tx == nullptr);
         P->nbatch = o.nbatch;
         P->p = o.order;
@@ -308,6 +393,7 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
         P->stream = static_cast<hipStream_t>(o.stream);
         VP_HIP(hipGetDevice(&P->device));
         P->scratch_dev = vp::scratch_address(P->device);
+        if (os) build_oversampling(P, os);
         vp::acquire_streams(P);
         for (hipEvent_t *e : {&P->ev_fork, &P->ev_join, &P->ev_p2m, &P->ev_p2l, &P->ev_upper, &P->ev_coarse, &P->ev_m2p})
             VP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
@@ -373,6 +459,23 @@ extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, 
     return VP_OK;
 }
 
+extern "C" vp_status vp_plan(const double *x, const double *y, const double *w, int64_t n, const double *tx,
+                             const double *ty, int64_t m, const int64_t *rowptr, const int32_t *col,
+                             const double *val, const vp_options *opt, vp_plan_t *out) {
+    return plan_impl(x, y, w, n, tx, ty, m, rowptr, col, val, nullptr, opt, out);
+}
+
+extern "C" vp_status vp_plan_oversampled(const double *x, const double *y, const double *w, int64_t n,
+                                         const double *tx, const double *ty, int64_t m, const int64_t *rowptr,
+                                         const int32_t *col, const double *val, const vp_oversampling *os,
+                                         const vp_options *opt, vp_plan_t *out) {
+    if (!os) {
+        if (out) *out = nullptr;
+        return set_err(nullptr, VP_EINVAL, "os is NULL");
+    }
+    return plan_impl(x, y, w, n, tx, ty, m, rowptr, col, val, os, opt, out);
+}
+
 static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
     auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
     return pa < pb + bbytes && pb < pa + abytes;
@@ -382,7 +485,7 @@ extern "C" vp_status vp_eval(vp_plan_t P, const double *f, double *u) {
     if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
     if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned by an earlier device error: " + P->err);
     if (!f || !u) return set_err(P, VP_EINVAL, "f and u must not be NULL");
-    if (overlaps(f, 8 * (size_t)P->nbatch * P->n, u, 8 * (size_t)P->nbatch * P->m))
+    if (overlaps(f, 8 * (size_t)P->nbatch * P->nd, u, 8 * (size_t)P->nbatch * P->m))
         return set_err(P, VP_EINVAL, "f and u overlap");
     return guarded(P, [&] {
         P->timing_eval_begin();
@@ -395,7 +498,7 @@ extern "C" vp_status vp_eval_noalloc(vp_plan_t P, const double *f, double *u) {
     if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
     if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned by an earlier device error: " + P->err);
     if (!f || !u) return set_err(P, VP_EINVAL, "f and u must not be NULL");
-    if (overlaps(f, 8 * (size_t)P->nbatch * P->n, u, 8 * (size_t)P->nbatch * P->m))
+    if (overlaps(f, 8 * (size_t)P->nbatch * P->nd, u, 8 * (size_t)P->nbatch * P->m))
         return set_err(P, VP_EINVAL, "f and u overlap");
     const size_t need = vp::carve_workspace(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     if (need > VP_NOALLOC_MAX_BYTES)
@@ -438,7 +541,7 @@ extern "C" vp_status vp_eval_adjoint(vp_plan_t P, const double *g, double *df) {
     if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
     if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned by an earlier device error: " + P->err);
     if (!g || !df) return set_err(P, VP_EINVAL, "g and df must not be NULL");
-    if (overlaps(g, 8 * (size_t)P->nbatch * P->m, df, 8 * (size_t)P->nbatch * P->n))
+    if (overlaps(g, 8 * (size_t)P->nbatch * P->m, df, 8 * (size_t)P->nbatch * P->nd))
         return set_err(P, VP_EINVAL, "g and df overlap");
     return guarded(P, [&] {
         P->timing_eval_begin();
@@ -451,7 +554,7 @@ extern "C" vp_status vp_eval_grad_targets(vp_plan_t P, const double *f, double *
     if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
     if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned by an earlier device error: " + P->err);
     if (!f || !grad) return set_err(P, VP_EINVAL, "f and grad must not be NULL");
-    if (overlaps(f, 8 * (size_t)P->nbatch * P->n, grad, 16 * (size_t)P->nbatch * P->m))
+    if (overlaps(f, 8 * (size_t)P->nbatch * P->nd, grad, 16 * (size_t)P->nbatch * P->m))
         return set_err(P, VP_EINVAL, "f and grad overlap");
     return guarded(P, [&] {
         P->timing_eval_begin();
@@ -538,6 +641,9 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->table_tile_ops = P->near.table_tile_ops;
     for (int k = 0; k < 3; ++k) info->root[k] = P->opt.root[k];
     info->table_pairs = P->table_pairs;
+    info->n_in = P->nd;
+    info->os_p = P->os_p;
+    info->os_q = P->os_q;
     info->noalloc_bytes = (int64_t)vp::carve_workspace(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     return VP_OK;
 }

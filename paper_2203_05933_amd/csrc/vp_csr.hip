@@ -47,7 +47,7 @@ __global__ void k_col_ptr(const uint64_t *__restrict__ skeys, int64_t nnz, int64
 }
 
 void build_csr_transpose(vp_plan_s *P) {
-    const int64_t nnz = P->nnz, n = P->n, m = P->m;
+    const int64_t nnz = P->nnz, n = P->nd, m = P->m;  // columns: the density values
     hipStream_t s = P->stream;
     P->rowptrT = P->mem.alloc<int64_t>(n + 1);
     P->colT = P->mem.alloc<int32_t>(nnz);

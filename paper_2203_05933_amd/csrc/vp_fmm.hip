@@ -1190,20 +1190,21 @@ __global__ void __launch_bounds__(256) k_cell_same(int ncand, const int32_t *__r
 void detect_runs(vp_plan_s *P) {
     hipStream_t s = P->stream;
     P->run_start = P->mem.alloc<int32_t>(P->m);
-    P->run_startT = P->mem.alloc<int32_t>(P->n);
+    // the transpose has one row per density value (nd)
+    P->run_startT = P->mem.alloc<int32_t>(P->nd);
     hipLaunchKernelGGL(k_detect_runs, dim3((unsigned)((P->m + 255) / 256)), dim3(256), 0, s, P->rowptr, P->col, P->m,
                        P->run_start);
-    hipLaunchKernelGGL(k_detect_runs, dim3((unsigned)((P->n + 255) / 256)), dim3(256), 0, s, P->rowptrT, P->colT,
-                       P->n, P->run_startT);
+    hipLaunchKernelGGL(k_detect_runs, dim3((unsigned)((P->nd + 255) / 256)), dim3(256), 0, s, P->rowptrT, P->colT,
+                       P->nd, P->run_startT);
     VP_LAUNCH_CHECK();
     // every row a run: the apply kernel never reads the column array
-    std::vector<int32_t> h(std::max(P->m, P->n));
+    std::vector<int32_t> h(std::max(P->m, P->nd));
     VP_HIP(hipMemcpyAsync(h.data(), P->run_start, 4 * P->m, hipMemcpyDeviceToHost, s));
     VP_HIP(hipStreamSynchronize(s));
     P->all_runs = std::all_of(h.begin(), h.begin() + P->m, [](int32_t v) { return v >= 0; });
-    VP_HIP(hipMemcpyAsync(h.data(), P->run_startT, 4 * P->n, hipMemcpyDeviceToHost, s));
+    VP_HIP(hipMemcpyAsync(h.data(), P->run_startT, 4 * P->nd, hipMemcpyDeviceToHost, s));
     VP_HIP(hipStreamSynchronize(s));
-    P->all_runsT = std::all_of(h.begin(), h.begin() + P->n, [](int32_t v) { return v >= 0; });
+    P->all_runsT = std::all_of(h.begin(), h.begin() + P->nd, [](int32_t v) { return v >= 0; });
     build_cells(P, false);
     build_cells(P, true);
 }
@@ -1215,7 +1216,7 @@ void detect_runs(vp_plan_s *P) {
 // applies the matrix.
 void build_cells(vp_plan_s *P, bool transposed) {
     hipStream_t s = P->stream;
-    const int64_t nrows = transposed ? P->n : P->m;
+    const int64_t nrows = transposed ? P->nd : P->m;
     const bool runs = transposed ? P->all_runsT : P->all_runs;
     int32_t *&cell_row = transposed ? P->cell_rowT : P->cell_row;
     int32_t *&cell_col = transposed ? P->cell_colT : P->cell_col;
@@ -1715,10 +1716,71 @@ static BoxGeo geo(vp_plan_s *P) {
     return BoxGeo{T.level, T.ix, T.iy, T.parent, T.child, T.nchild, T.cx, T.cy, T.d_side, T.d_logside};
 }
 
+// Oversampled boxes (Section 4.2, eq. fk_basis / eq. Tnm, upsampled as in
+// Section 3.2): the charge of source j = out_start[b] + r is
+// w_j (O f_b)_r, O the q^2 x p^2 tensor-product Chebyshev map, written
+// straight into sorted order.  One workgroup per box; the box's p^2 density
+// values of one density at a time in LDS, threads over the q^2 rows (O^T
+// read with the threads along a row of O^T: coalesced).
+__global__ void k_interp_charge(const int64_t *__restrict__ in_start, const int64_t *__restrict__ out_start,
+                                int p2, int q2, const double *__restrict__ OT, const double *__restrict__ f,
+                                int64_t nd, const int32_t *__restrict__ sinv, const double *__restrict__ w,
+                                int nbatch, int64_t n, double *__restrict__ q) {
+    __shared__ double sf[1024];
+    const int64_t b = blockIdx.x;
+    const int64_t i0 = in_start[b], j0 = out_start[b];
+    for (int bt = 0; bt < nbatch; ++bt) {
+        for (int k = threadIdx.x; k < p2; k += blockDim.x) sf[k] = f[(int64_t)bt * nd + i0 + k];
+        __syncthreads();
+        for (int r = threadIdx.x; r < q2; r += blockDim.x) {
+            double acc = 0.0;
+            for (int k = 0; k < p2; ++k) acc = fma(OT[(int64_t)k * q2 + r], sf[k], acc);
+            const int64_t j = j0 + r;
+            q[(int64_t)bt * n + sinv[j]] = w[j] * acc;
+        }
+        __syncthreads();
+    }
+}
+
+// The adjoint's finish on an oversampled plan: out[b][i0 + k] +=
+// sum_r O[r][k] w_j acc[b][sinv[j]] (j = out_start + r): O^T applied to the
+// weighted FMM sums at the box's sources, added to the transposed correction.
+__global__ void k_interp_adjoint(const int64_t *__restrict__ in_start, const int64_t *__restrict__ out_start,
+                                 int p2, int q2, const double *__restrict__ O, const double *__restrict__ acc,
+                                 const double *__restrict__ acc2, int64_t n, const int32_t *__restrict__ sinv,
+                                 const double *__restrict__ w, int nbatch, int64_t nd, double *__restrict__ out) {
+    __shared__ double sv[1024];
+    const int64_t b = blockIdx.x;
+    const int64_t i0 = in_start[b], j0 = out_start[b];
+    for (int bt = 0; bt < nbatch; ++bt) {
+        for (int r = threadIdx.x; r < q2; r += blockDim.x) {
+            const int64_t j = j0 + r, k = (int64_t)bt * n + sinv[j];
+            sv[r] = w[j] * (acc2 ? acc[k] + acc2[k] : acc[k]);
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < p2; c += blockDim.x) {
+            double s = 0.0;
+            for (int r = 0; r < q2; ++r) s = fma(O[(int64_t)r * p2 + c], sv[r], s);
+            double *o = out + (int64_t)bt * nd + i0 + c;
+            *o = s + *o;
+        }
+        __syncthreads();
+    }
+}
+
 void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
     int64_t len = adjoint ? P->m : P->n;
     const int32_t *perm = adjoint ? P->tperm : P->sperm;
     const double *w = adjoint ? nullptr : P->sw;
+    if (!adjoint && P->os_p > 0) {
+        P->stage_begin(VP_STAGE_CHARGE);
+        hipLaunchKernelGGL(k_interp_charge, dim3((unsigned)P->os_nbox), dim3(256), 0, P->stream, P->os_in, P->os_out,
+                           P->os_p * P->os_p, P->os_q * P->os_q, P->os_OT, f, P->nd, P->sinv, P->w_user,
+                           P->nbatch, P->n, P->q);
+        VP_LAUNCH_CHECK();
+        P->stage_end(VP_STAGE_CHARGE);
+        return;
+    }
     P->stage_begin(VP_STAGE_CHARGE);
     hipLaunchKernelGGL(k_charge, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, P->stream, f, perm, w,
                        P->q, len, P->nbatch);
@@ -2303,13 +2365,13 @@ void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) 
 // The sparse correction (Section 4): out = C f (adjoint: C^T g), on the
 // current stream; it needs no FMM result, so it runs beside the expansions.
 static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjoint) {
-    const int64_t nrows = adjoint ? P->n : P->m;
+    const int64_t nrows = adjoint ? P->nd : P->m;
     const int64_t *rp = adjoint ? P->rowptrT : P->rowptr;
     const int32_t *cv = adjoint ? P->colT : P->col;
     const int32_t *rs = adjoint ? P->run_startT : P->run_start;
     const double *vv = adjoint ? P->valT : P->val;
     const bool runs = adjoint ? P->all_runsT : P->all_runs;
-    const int64_t flen = adjoint ? P->m : P->n;
+    const int64_t flen = adjoint ? P->m : P->nd;
     int64_t blocks = (nrows * 16 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     const int ncell = adjoint ? P->ncellT : P->ncell;
@@ -2371,7 +2433,17 @@ static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjo
 }
 
 // out += (adjoint: w times) the FMM sums, un-permuted to user order
+// (adjoint of an oversampled plan: O^T of the weighted sums per box)
 static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint) {
+    if (adjoint && P->os_p > 0) {
+        P->stage_begin(VP_STAGE_FINISH);
+        hipLaunchKernelGGL(k_interp_adjoint, dim3((unsigned)P->os_nbox), dim3(256), 0, P->stream, P->os_in,
+                           P->os_out, P->os_p * P->os_p, P->os_q * P->os_q, P->os_O, P->acc, P->acc_far, P->n,
+                           P->sinv, P->w_user, P->nbatch, P->nd, u);
+        VP_LAUNCH_CHECK();
+        P->stage_end(VP_STAGE_FINISH);
+        return;
+    }
     const int64_t nrows = adjoint ? P->n : P->m;
     const int32_t *inv = adjoint ? P->sinv : P->tinv;
     const double *scale = adjoint ? P->w_user : nullptr;

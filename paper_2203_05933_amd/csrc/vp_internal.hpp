@@ -253,6 +253,14 @@ struct vp_plan_s {
     vp_options opt{};
     int p = 30, P = 31, PD = 64;
     int64_t n = 0, m = 0, nnz = 0;
+    int64_t nd = 0;          // density values per density: n, or n_in of an oversampled plan
+    // oversampled boxes (vp_plan_oversampled): per box, p x p density values
+    // -> q x q source nodes by the tensor-product Chebyshev map O (q^2 x p^2)
+    int os_p = 0, os_q = 0;  // 0: no oversampling (the density is given at the sources)
+    int64_t os_nbox = 0;
+    int64_t *os_in = nullptr, *os_out = nullptr;  // [os_nbox] first density value / first source node
+    double *os_O = nullptr;   // [q^2][p^2] row-major (adjoint: threads over columns)
+    double *os_OT = nullptr;  // [p^2][q^2] (forward: threads over rows)
     int nbatch = 1;
     bool self = false;
     bool fp32 = false;

@@ -33,7 +33,7 @@ _ARR_DTYPE = {0: np.int32, 1: np.int32, 2: np.int32, 3: np.int32, 4: np.int32, 5
               12: np.float64, 13: np.float64, 14: np.int64, 15: np.int64}
 
 # Every entry point declared in include/vp.h.
-EXPORTS = ("vp_default_options", "vp_plan", "vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets",
+EXPORTS = ("vp_default_options", "vp_plan", "vp_plan_oversampled", "vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets",
            "vp_eval_noalloc", "vp_set_stream", "vp_destroy", "vp_last_error", "vp_get_info", "vp_get_array",
            "vp_set_timing", "vp_get_timing")
 STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish", "tables", "corr", "coarse", "p2m_pat", "m2p")
@@ -52,6 +52,11 @@ class Options(ctypes.Structure):
                 ("stream", ctypes.c_void_p)]
 
 
+class Oversampling(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("q", ctypes.c_int32), ("nbox", ctypes.c_int64), ("n_in", ctypes.c_int64),
+                ("in_start", ctypes.c_void_p), ("out_start", ctypes.c_void_p)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("nbatch", ctypes.c_int32), ("order", ctypes.c_int32), ("precision", ctypes.c_int32),
@@ -66,7 +71,8 @@ class PlanInfo(ctypes.Structure):
                 ("corr_shared_cells", ctypes.c_int32), ("corr_values_read", ctypes.c_int64),
                 ("corr_groups", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("root", ctypes.c_double * 3), ("table_pairs", ctypes.c_int64),
-                ("noalloc_bytes", ctypes.c_int64)]
+                ("noalloc_bytes", ctypes.c_int64), ("n_in", ctypes.c_int64),
+                ("os_p", ctypes.c_int32), ("os_q", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -94,6 +100,9 @@ def load_library(path: str = LIB_PATH):
     lib.vp_plan.argtypes = [dp, dp, dp, ctypes.c_int64, dp, dp, ctypes.c_int64, dp, dp, dp,
                             ctypes.POINTER(Options), ctypes.POINTER(vp)]
     lib.vp_plan.restype = ctypes.c_int
+    lib.vp_plan_oversampled.argtypes = [dp, dp, dp, ctypes.c_int64, dp, dp, ctypes.c_int64, dp, dp, dp,
+                                        ctypes.POINTER(Oversampling), ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    lib.vp_plan_oversampled.restype = ctypes.c_int
     for name in ("vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets", "vp_eval_noalloc"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, dp, dp]
@@ -145,12 +154,17 @@ class Plan:
 
     Targets default to the nodes.  Evaluations take and return float64
     device tensors [nbatch, n] / [nbatch, m] in the caller's order.
+
+    oversampling=dict(p=, q=, in_start=, out_start=, n_in=) builds an
+    oversampled plan (vp_plan_oversampled): the nodes x, y, w are the q x q
+    sources of every box, the densities are [nbatch, n_in] values at the
+    p x p nodes, and the correction columns index those values.
     """
 
     def __init__(self, x, y, w, tx=None, ty=None, rowptr=None, col=None, val=None, *, order: int = 30,
                  max_leaf: int = 64, nbatch: int = 1, precision: str = "fp64", m2l_mode: str = "auto",
                  p2p_mode: str = "auto", root=None, max_level: int = 0, autotune: bool = False,
-                 one_stream: bool = False, stream=None):
+                 one_stream: bool = False, oversampling: Optional[dict] = None, stream=None):
         lib = load_library()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -176,11 +190,24 @@ class Plan:
         if root is not None:
             o.root[0], o.root[1], o.root[2] = root
         o.stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
-        st = lib.vp_plan(_ptr(x), _ptr(y), _ptr(w), n, _ptr(tx), _ptr(ty), m, _ptr(rowptr), _ptr(col),
-                         _ptr(val), ctypes.byref(o), ctypes.byref(self._h))
+        if oversampling is None:
+            st = lib.vp_plan(_ptr(x), _ptr(y), _ptr(w), n, _ptr(tx), _ptr(ty), m, _ptr(rowptr), _ptr(col),
+                             _ptr(val), ctypes.byref(o), ctypes.byref(self._h))
+            n_in = n
+        else:
+            ins = _host(oversampling["in_start"], np.int64)
+            outs = _host(oversampling["out_start"], np.int64)
+            n_in = int(oversampling["n_in"])
+            os_ = Oversampling(int(oversampling["p"]), int(oversampling["q"]), ins.shape[0], n_in,
+                               ins.ctypes.data, outs.ctypes.data)
+            st = lib.vp_plan_oversampled(_ptr(x), _ptr(y), _ptr(w), n, _ptr(tx), _ptr(ty), m, _ptr(rowptr),
+                                         _ptr(col), _ptr(val), ctypes.byref(os_), ctypes.byref(o),
+                                         ctypes.byref(self._h))
         if st != VP_OK:
             raise VPError(st, lib.vp_last_error(None).decode())
-        self.n, self.m, self.nbatch = n, m, nbatch
+        # n: the length of the density rows (the density values of an oversampled plan)
+        self.n, self.m, self.nbatch = n_in, m, nbatch
+        self.n_src = n
         self.precision = precision
         self.order = order
 

@@ -105,3 +105,45 @@ def test_null_plan_calls():
     assert lib.vp_destroy(None) == vp.VP_OK
     assert lib.vp_set_stream(None, None) == vp.VP_EINVAL
     assert b"NULL" in lib.vp_last_error(None)
+
+
+@pytest.mark.parametrize("case", ["null_os", "p_gt_q", "q_big", "no_targets", "in_overlap", "in_range",
+                                  "out_cover", "out_overlap", "col_range"])
+def test_plan_oversampled_rejects_invalid(case):
+    """vp_plan_oversampled checks the box layout before touching a device."""
+    from vp_workloads import generators as gen
+    vp, lib = _lib()
+    wl = gen.config5(nbox_side=2, csr_seed=3, sample_seed=None)
+    p, q, nbox = 8, 16, wl.nbox
+    ins = np.arange(nbox, dtype=np.int64) * p * p
+    outs = np.arange(nbox, dtype=np.int64) * q * q
+    n_in, n, m = wl.m, wl.n, wl.m
+    tx, ty, col = wl.tx, wl.ty, wl.col.copy()
+    pp, qq = p, q
+    if case == "p_gt_q":
+        pp, qq = 9, 8
+    elif case == "q_big":
+        qq = 33
+    elif case == "no_targets":
+        tx = ty = None
+    elif case == "in_overlap":
+        ins = ins.copy(); ins[1] = ins[0] + 1
+    elif case == "in_range":
+        ins = ins.copy(); ins[-1] = n_in - 1
+    elif case == "out_cover":
+        n = n - 1
+    elif case == "out_overlap":
+        outs = outs.copy(); outs[2] = outs[1]
+    elif case == "col_range":
+        col[5] = n_in
+    os_ = vp.Oversampling(pp, qq, nbox, n_in, ins.ctypes.data, outs.ctypes.data)
+    h = ctypes.c_void_p()
+    ptr = lambda a: None if a is None else np.ascontiguousarray(a).ctypes.data_as(ctypes.c_void_p)
+    o = vp.default_options()
+    st = lib.vp_plan_oversampled(ptr(wl.x), ptr(wl.y), ptr(wl.w), n, ptr(tx), ptr(ty), m, ptr(wl.rowptr), ptr(col),
+                                 ptr(wl.val), None if case == "null_os" else ctypes.byref(os_), ctypes.byref(o),
+                                 ctypes.byref(h))
+    msg = lib.vp_last_error(None).decode()
+    assert st == vp.VP_EINVAL, (st, msg)
+    assert h.value is None
+    assert len(msg) > 0
