@@ -21,7 +21,11 @@ Secondary records in the same JSON line (skipped with --no-secondary):
     FP32-bulk, with errors against the oracle;
   * per_entry_correction: the headline grid with every correction value
     drawn on its own (no shared block), FP64, with the correction apply's
-    rate against the HBM peak.
+    rate against the HBM peak;
+  * oversampled: 64 x 64 boxes with the density at 8 x 8 Chebyshev nodes
+    per box (262,144 targets) and the smooth rule at 16 x 16 Chebyshev
+    nodes (1,048,576 sources; the paper's twofold oversampling), FP64 and
+    FP32-bulk, with errors against the oracle on 4,096 sampled targets.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -93,6 +97,8 @@ def workload(name, shared_blocks=True):
         return gen.config0()
     if name == "uniform256x16":
         return gen.config3(shared_blocks=shared_blocks)
+    if name == "oversampled64":
+        return gen.config5()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -120,10 +126,21 @@ def time_evals(plan, f, u, steps, warmup):
     return dt, tim
 
 
+def oversampling_layout(wl):
+    """Box layout of an oversampled workload (None for the others)."""
+    import numpy as np
+    if not hasattr(wl, "p_interp"):
+        return None
+    p, q = wl.p_interp, wl.q_interp
+    return dict(p=p, q=q, n_in=wl.n_in, in_start=np.arange(wl.nbox, dtype=np.int64) * p * p,
+                out_start=np.arange(wl.nbox, dtype=np.int64) * q * q)
+
+
 def make_plan(wl, order, precision, m2l_mode="auto", one_stream=False, max_leaf=64):
     from paper_2203_05933_amd import vp
     return vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=order, max_leaf=max_leaf,
-                   nbatch=wl.nbatch, precision=precision, m2l_mode=m2l_mode, one_stream=one_stream, root=wl.root)
+                   nbatch=wl.nbatch, precision=precision, m2l_mode=m2l_mode, one_stream=one_stream, root=wl.root,
+                   oversampling=oversampling_layout(wl))
 
 
 def run_form(wl, f, order, precision, steps, warmup, m2l_mode="auto", one_stream=False, label=""):
@@ -159,6 +176,8 @@ def stage_roofline(info, tim, stage, workload_name=None):
     nb = info["nbatch"]
     fp64 = info["precision"] == 0
     rec = None
+    if (stage == "p2p" and info["near_pairs"] == 0) or (stage == "tables" and info["table_pairs"] == 0):
+        return None  # the stage did no work in this plan
     if stage == "p2p":
         flops = info["near_pairs"] * nb * P2P_FLOPS_PER_PAIR
         rec = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -244,6 +263,9 @@ def reference(wl):
         smooth = np.load(GOLDEN_C3)
         assert smooth.shape == (wl.nbatch, wl.sample.size)
         return smooth + direct.csr(wl.rowptr, wl.col, wl.val, wl.f, tidx=wl.sample)
+    if hasattr(wl, "p_interp"):
+        from oracle import oversample
+        return oversample.evaluate(wl, tidx=wl.sample)
     return direct.evaluate(wl.x, wl.y, wl.w, wl.f, wl.rowptr, wl.col, wl.val, wl.tx, wl.ty, tidx=wl.sample)
 
 
@@ -279,8 +301,12 @@ def precision_pair(name, steps, warmup, order, order32, with_cpu):
     wl = workload(name)
     f = torch.tensor(wl.f, dtype=torch.float64, device="cuda:0")
     ref = reference(wl) if with_cpu else None
-    out = {"workload": f"{wl.name}: {wl.n} nodes, targets=nodes, {wl.nbatch} density", "n": wl.n,
-           "nbatch": wl.nbatch}
+    if hasattr(wl, "p_interp"):
+        desc = (f"{wl.name}: {wl.m} targets (density at {wl.p_interp}x{wl.p_interp} Chebyshev nodes per box), "
+                f"{wl.n} sources ({wl.q_interp}x{wl.q_interp} per box), {wl.nbatch} density")
+    else:
+        desc = f"{wl.name}: {wl.n} nodes, targets=nodes, {wl.nbatch} density"
+    out = {"workload": desc, "n": wl.n, "m": wl.m, "nbatch": wl.nbatch}
     forms = (("fp64", order, "fp64", "auto"), ("fp32_scaled", order32, "fp32", "auto"),
              ("fp32_split_hi_lo", order32, "fp32", "split"))
     base = None
@@ -333,15 +359,16 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform256x16",
-                    choices=["uniform256x16", "star", "uniform128", "uniform16"])
+                    choices=["uniform256x16", "star", "uniform128", "uniform16", "oversampled64"])
     ap.add_argument("--order", type=int, default=30)
     ap.add_argument("--order-fp32", type=int, default=14)
     ap.add_argument("--max-leaf", type=int, default=64)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (cpu_baseline and errors)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary records")
-    ap.add_argument("--one-stream", action="store_true",
-                    help="also run the headline with every kernel on one stream (per-stage times without overlap)")
+    ap.add_argument("--no-one-stream", action="store_true",
+                    help="skip the serialized pass (every kernel on one stream): the roofline then comes from the "
+                         "overlapped run, whose kernel durations include contention")
     ap.add_argument("--cpu-sample", type=int, default=256, help="targets the timed oracle evaluates")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed loops, run one plain device copy (y = 2 x) of this many MiB read and "
@@ -366,21 +393,28 @@ def main():
     rec64, u64, info, tim, plan = run_form(wl, f, args.order, "fp64", args.steps, args.warmup, label="headline")
     value, ms_per_step = rec64["value"], rec64["ms_per_step"]
     stage, roof, roofs = rooflines(info, tim, wl.name)
-    log(f"[bench] dominant stage {stage}: {roof['kernel']} {roof['avg_ms']:.3f} ms, frac {roof['frac']:.3f}")
     plan.close()
 
+    # The serialized pass: the same evaluation with every kernel on one
+    # stream, timed the same way (warm-up, wall-clock loop, then the loop with
+    # per-stage HIP events).  The three-stream run overlaps the kernels, so
+    # its per-stage durations include contention; the roofline is taken from
+    # this pass, whose per-stage durations are the kernels' own (its last
+    # `steps` launches of each kernel are the event-timed ones).
     one = None
-    if args.one_stream:
+    roofs_overlapped = roofs
+    if not args.no_one_stream:
         plan1 = make_plan(wl, args.order, "fp64", one_stream=True, max_leaf=args.max_leaf)
         u1 = torch.empty_like(u64)
         dt1, tim1 = time_evals(plan1, f, u1, args.steps, args.warmup)
         inf1 = plan1.info()
+        stage, roof, roofs = rooflines(inf1, tim1, wl.name)
         one = {"ms_per_step": dt1 / args.steps * 1e3,
-               "stages_ms": {k: v / max(tim1["evals"], 1) for k, v in tim1["ms"].items()},
-               "stage_rooflines": rooflines(inf1, tim1, wl.name)[2]}
+               "stages_ms": {k: v / max(tim1["evals"], 1) for k, v in tim1["ms"].items()}}
         log(f"[bench] fp64 one stream: {one['ms_per_step']:.3f} ms/eval")
         plan1.close()
         del u1
+    log(f"[bench] dominant stage {stage}: {roof['kernel']} {roof['avg_ms']:.3f} ms, frac {roof['frac']:.3f}")
 
     forms32 = {}
     if not args.no_fp32:
@@ -426,6 +460,9 @@ def main():
         torch.cuda.empty_cache()
         secondary["star"] = precision_pair("star", args.steps, args.warmup, args.order, args.order_fp32,
                                            not args.no_cpu)
+        torch.cuda.empty_cache()
+        secondary["oversampled"] = precision_pair("oversampled64", args.steps, args.warmup, args.order,
+                                                  args.order_fp32, not args.no_cpu)
 
     if args.copy_mib > 0:
         n_el = args.copy_mib * (1 << 20) // 8
@@ -460,7 +497,10 @@ def main():
         "stages_ms": rec64["stages_ms"],
         "dominant_stage": stage,
         "roofline": roof,
+        "roofline_source": ("serialized pass (one stream): per-stage HIP events over its timed loop"
+                            if one is not None else "three-stream run: per-stage HIP events (include contention)"),
         "stage_rooflines": roofs,
+        "stage_rooflines_overlapped": roofs_overlapped,
         "one_stream": one,
         "fp32_form": out32,
         "cpu_baseline": cpu,
