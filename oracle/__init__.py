@@ -13,4 +13,6 @@ share come from the seeded generators in vp_workloads.
   oversample.py        : the box oversampling map O_{p,q} (Chebyshev values ->
                          coefficients -> values at finer roots) and the
                          oversampled smooth sum with its adjoint
+  yukawa.py            : the modified Helmholtz (Yukawa) smooth sum with
+                         G = (lambda^2 / 2 pi) K_0(lambda r), and its transpose
 """
