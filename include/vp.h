@@ -65,6 +65,18 @@ enum {
     VP_M2L_FP32_SCALED = 5  /* the scaled form in FP32 (VP_FP32_BULK only) */
 };
 enum { VP_P2P_AUTO = 0, VP_P2P_PAIRWISE = 1, VP_P2P_TABLES = 2 };
+/* Green's function (Section 2.1):
+   VP_KERNEL_LAPLACE: G(r, r0) = -(1/(2 pi)) log |r - r0|
+   VP_KERNEL_YUKAWA:  G(r, r0) = (lambda^2 / (2 pi)) K_0(lambda |r - r0|), the
+                      modified Helmholtz kernel of L = -Delta + lambda^2 in the
+                      normalisation Section 2.1 writes (divide by lambda^2 for
+                      the Green's function of -Delta + lambda^2 itself).  This
+                      build evaluates it on uniform grids of congruent 64-point
+                      leaves (targets = nodes, one leaf level, no W or X lists),
+                      in float64, by fixed matrices per level: other trees,
+                      VP_FP32_BULK and vp_eval_grad_targets return
+                      VP_EUNSUPPORTED. */
+enum { VP_KERNEL_LAPLACE = 0, VP_KERNEL_YUKAWA = 1 };
 /* VP_FLAG_AUTOTUNE: with m2l_mode VP_M2L_AUTO, vp_plan times every M2L kernel
    variant that meets the precision's accuracy (FP64: scaled and per-offset
    FP64 products; FP32-bulk: scaled FP32, per-offset FP32 and scaled FP64
@@ -105,6 +117,9 @@ typedef struct {
                           (VP_EINVAL otherwise) */
     void *stream;      /* hipStream_t for plan-time copies and evaluations;
                           NULL = the null stream */
+    int32_t kernel;    /* VP_KERNEL_*; default VP_KERNEL_LAPLACE */
+    int32_t reserved;
+    double lambda;     /* VP_KERNEL_YUKAWA: lambda > 0 (Section 5 uses lambda^2 = 100) */
 } vp_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -259,6 +274,9 @@ typedef struct {
     int64_t noalloc_bytes;     /* static workspace vp_eval_noalloc needs for this plan */
     int64_t n_in;              /* density values per density (n unless oversampled) */
     int32_t os_p, os_q;        /* oversampled plan: nodes per box side (0, 0: none) */
+    int32_t kernel;            /* VP_KERNEL_* */
+    int32_t reserved2;
+    double lambda;
 } vp_plan_info_t;
 
 vp_status vp_get_info(vp_plan_t plan, vp_plan_info_t *info);

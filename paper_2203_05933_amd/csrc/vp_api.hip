@@ -195,6 +195,8 @@ extern "C" void vp_default_options(vp_options *opt) {
     opt->flags = 0;
     opt->root[0] = opt->root[1] = opt->root[2] = 0.0;
     opt->stream = nullptr;
+    opt->kernel = VP_KERNEL_LAPLACE;
+    opt->lambda = 0.0;
 }
 
 static void validate_plan_args(const double *x, const double *y, const double *w, int64_t n,
@@ -241,6 +243,13 @@ static void validate_plan_args(const double *x, const double *y, const double *w
     if (o.p2p_mode < 0 || o.p2p_mode > 2) bad("unknown p2p_mode");
     if (o.max_level < 0 || o.max_level > vp::LBITS) bad("max_level must be in 0..30");
     if (o.flags & ~(VP_FLAG_AUTOTUNE | VP_FLAG_ONE_STREAM)) bad("unknown flags");
+    if (o.kernel != VP_KERNEL_LAPLACE && o.kernel != VP_KERNEL_YUKAWA) bad("unknown kernel");
+    if (o.kernel == VP_KERNEL_YUKAWA && !(std::isfinite(o.lambda) && o.lambda > 0))
+        bad("the modified Helmholtz kernel needs a finite lambda > 0");
+    if (o.kernel == VP_KERNEL_YUKAWA && o.precision != VP_FP64)
+        throw Error(VP_EUNSUPPORTED, "the modified Helmholtz kernel runs in float64 only");
+    if (o.kernel == VP_KERNEL_YUKAWA && o.p2p_mode == VP_P2P_PAIRWISE)
+        throw Error(VP_EUNSUPPORTED, "the modified Helmholtz kernel has no pairwise near-field kernel");
     if (o.root[2] > 0 && (!std::isfinite(o.root[0]) || !std::isfinite(o.root[1]) || !std::isfinite(o.root[2])))
         bad("non-finite root square");
     if (o.root[2] > 0) {
@@ -447,6 +456,7 @@ static vp_status plan_impl(const double *x, const double *y, const double *w, in
         }
         VP_HIP(hipStreamSynchronize(P->stream));
         vp::build_near_tables(P);
+        if (o.kernel == VP_KERNEL_YUKAWA) vp::build_yukawa(P);
         if (o.p2p_mode == VP_P2P_TABLES && !P->near.active)
             throw Error(VP_EUNSUPPORTED, "p2p_mode TABLES needs targets = nodes and congruent leaves");
         if ((o.flags & VP_FLAG_AUTOTUNE) && o.m2l_mode == VP_M2L_AUTO) vp::autotune_m2l(P);
@@ -552,6 +562,8 @@ extern "C" vp_status vp_eval_adjoint(vp_plan_t P, const double *g, double *df) {
 
 extern "C" vp_status vp_eval_grad_targets(vp_plan_t P, const double *f, double *grad) {
     if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
+    if (P->yk.active)
+        return set_err(P, VP_EUNSUPPORTED, "target gradients of the modified Helmholtz kernel are not built");
     if (P->poisoned) return set_err(P, VP_EDEVICE, "plan is poisoned by an earlier device error: " + P->err);
     if (!f || !grad) return set_err(P, VP_EINVAL, "f and grad must not be NULL");
     if (overlaps(f, 8 * (size_t)P->nbatch * P->nd, grad, 16 * (size_t)P->nbatch * P->m))
@@ -644,6 +656,13 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->n_in = P->nd;
     info->os_p = P->os_p;
     info->os_q = P->os_q;
+    info->kernel = P->opt.kernel;
+    info->lambda = P->opt.lambda;
+    if (P->yk.active) {
+        info->m2l_translations = P->yk.m2l_translations;
+        info->m2l_tile_ops = P->yk.m2l_tile_ops;
+        info->m2l_coarse_translations = info->m2l_coarse_tile_ops = 0;
+    }
     info->noalloc_bytes = (int64_t)vp::carve_workspace(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     return VP_OK;
 }

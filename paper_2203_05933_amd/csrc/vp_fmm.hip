@@ -2355,9 +2355,154 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
     if (u && !fused) add_fmm_sums(P, u, adjoint);
 }
 
+// one gather-GEMM launch over expansion columns (four operator slots per column)
+template <int RB>
+static void yk_translate(vp_plan_s *P, const TranslateArgs &a, const double *ops, const double *in, double *out,
+                         bool accum) {
+    constexpr int S = RB * 4;
+    constexpr size_t lds = translate_lds_bytes<double, RB, S, false>();
+    const unsigned grid = (unsigned)((a.ncols + 63) / 64);
+    if (accum)
+        hipLaunchKernelGGL((k_translate<double, double, double, RB, S, false, true, true>), dim3(grid), dim3(256), lds,
+                           P->stream, a, ops, (const double *)nullptr, in, out);
+    else
+        hipLaunchKernelGGL((k_translate<double, double, double, RB, S, false, false, true>), dim3(grid), dim3(256),
+                           lds, P->stream, a, ops, (const double *)nullptr, in, out);
+    VP_LAUNCH_CHECK();
+}
+
+// Modified Helmholtz kernel on a uniform grid of congruent leaves: every
+// stage a fixed matrix (vp_yukawa.hip), on the plan's stream in order --
+// correction, near tables (store), pattern P2M, M2M per level upward, M2L
+// of all levels in one launch (adding to zeroed locals), L2L per level
+// downward (adding), pattern L2P (store), finish.  Targets are the nodes,
+// so the adjoint is the same passes with the charges g and the weights
+// applied at the finish.
+static void run_yukawa(vp_plan_s *P, const PointRoles &R, bool adjoint, const double *f, double *u) {
+    Tree &T = P->tree;
+    NearTables &N = P->near;
+    YukawaPlan &Y = P->yk;
+    const int nb = P->nbatch, PD = P->PD, L = Y.leaf_level;
+    double *M = static_cast<double *>(P->Mexp), *Lx = static_cast<double *>(P->Lexp);
+    if (u) correction_apply(P, f, u, adjoint);
+    P->stage_begin(VP_STAGE_TABLES);
+    run_tables(P, R);
+    P->stage_end(VP_STAGE_TABLES);
+    const bool fmm = L >= 2;
+    if (!fmm) {
+        fill_f64(P->acc_far, 0.0, (int64_t)nb * R.ntgt, P->stream);
+    } else {
+        const ColAddr ex{PD, (int64_t)nb * PD, nullptr};
+        auto gemm = [&](const int32_t *cols, int ncolbox, const int32_t *slots, const double *ops, const double *in,
+                        double *out, bool accum) {
+            if (ncolbox <= 0) return;
+            TranslateArgs a;
+            a.cols_box = cols;
+            a.ncols = ncolbox * nb;
+            a.nbatch = nb;
+            a.slots = slots;
+            a.nops = 4;
+            a.in = ex;
+            a.out = ex;
+            a.nrows_out = PD;
+            a.logrow = -1;
+            a.level = T.level;
+            a.logside = T.d_logside;
+            a.zero_col = P->zero_col;
+            switch (PD) {
+                case 16: yk_translate<1>(P, a, ops, in, out, accum); break;
+                case 32: yk_translate<2>(P, a, ops, in, out, accum); break;
+                case 48: yk_translate<3>(P, a, ops, in, out, accum); break;
+                case 64: yk_translate<4>(P, a, ops, in, out, accum); break;
+                default: throw Error(VP_EUNSUPPORTED, "expansion size");
+            }
+        };
+        const size_t AE = (size_t)PD * PD;
+        // pattern P2M of the leaves (store)
+        P->stage_begin(VP_STAGE_P2M_PAT);
+        {
+            const ColAddr pin{R.nsrc, 0, R.sb};
+            switch (PD) {
+#define VP_YP(RB)                                                                                                  \
+    case RB * 16:                                                                                                  \
+        launch_fixed_apply<double, double, double, RB, 16, false>(P, N.l2p_pat, N.n_l2p_pat * nb, pin, ex, PD, Y.p2m, \
+                                                                  P->q, M);                                        \
+        break;
+                VP_YP(1) VP_YP(2) VP_YP(3) VP_YP(4)
+#undef VP_YP
+            }
+        }
+        P->stage_end(VP_STAGE_P2M_PAT);
+        // M2M, finest parents first (store into the parents)
+        P->stage_begin(VP_STAGE_M2M);
+        for (int l = L - 1; l >= 2; --l)
+            gemm(Y.d_parents[l], (int)Y.parents[l].size(), Y.cslot, Y.m2m + (size_t)l * 4 * AE, M, M, false);
+        P->stage_end(VP_STAGE_M2M);
+        // M2L of every level into zeroed locals
+        P->stage_begin(VP_STAGE_M2L);
+        fill_f64(Lx, 0.0, (int64_t)T.nbox * nb * PD, P->stream);
+        {
+            TranslateArgs a;
+            a.cols_box = Y.m2l_cols;
+            a.ncols = Y.n_m2l_cols * nb;
+            a.nbatch = nb;
+            a.slots = Y.m2l_slot;
+            a.nops = NOFF * T.nlevels;
+            a.tile_ptr = Y.m2l_tptr;
+            a.tile_ops = Y.m2l_tops;
+            a.tile_order = Y.m2l_torder;
+            a.in = ex;
+            a.out = ex;
+            a.nrows_out = PD;
+            a.logrow = -1;
+            a.level = T.level;
+            a.logside = T.d_logside;
+            a.zero_col = P->zero_col;
+            const unsigned grid = (unsigned)((a.ncols + 15) / 16);
+            switch (PD) {
+#define VP_YL(RB)                                                                                                 \
+    case RB * 16:                                                                                                 \
+        hipLaunchKernelGGL((k_translate_split<double, double, double, RB, RB * 4, false, true>), dim3(grid),       \
+                           dim3(256), 0, P->stream, a, Y.m2l, (const double *)nullptr, M, Lx);                   \
+        break;
+                VP_YL(1) VP_YL(2) VP_YL(3) VP_YL(4)
+#undef VP_YL
+            }
+            VP_LAUNCH_CHECK();
+        }
+        P->stage_end(VP_STAGE_M2L);
+        // L2L, coarsest first (add into the children)
+        P->stage_begin(VP_STAGE_L2L);
+        for (int l = 2; l + 1 <= L; ++l)
+            gemm(Y.d_children[l + 1], (int)Y.children[l + 1].size(), Y.pslot, Y.l2l + (size_t)l * 4 * AE, Lx, Lx,
+                 true);
+        P->stage_end(VP_STAGE_L2L);
+        // pattern L2P of the leaves (store)
+        P->stage_begin(VP_STAGE_FAR);
+        {
+            const ColAddr pout{R.ntgt, 0, R.tb};
+            switch (PD) {
+#define VP_YQ(RB)                                                                                                 \
+    case RB * 16:                                                                                                 \
+        launch_fixed_apply<double, double, double, 4, RB * 4, false>(P, N.l2p_pat, N.n_l2p_pat * nb, ex, pout, 64, \
+                                                                     Y.l2p, Lx, P->acc_far);                      \
+        break;
+                VP_YQ(1) VP_YQ(2) VP_YQ(3) VP_YQ(4)
+#undef VP_YQ
+            }
+        }
+        P->stage_end(VP_STAGE_FAR);
+    }
+    if (u) add_fmm_sums(P, u, adjoint);
+}
+
 void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f, double *u) {
     PointRoles R = roles(P, adjoint);
     BoxGeo G = geo(P);
+    if (P->yk.active) {
+        run_yukawa(P, R, adjoint, f, u);
+        return;
+    }
     if (P->fp32) run_passes<float>(P, R, G, adjoint, grad, f, u);
     else run_passes<double>(P, R, G, adjoint, grad, f, u);
 }

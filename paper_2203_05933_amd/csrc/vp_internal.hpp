@@ -237,11 +237,31 @@ struct NearTables {
     int n_zero_near = 0, n_zero_far = 0;
     int32_t *far_add = nullptr;       // [nbox] 1: the pattern L2P adds (W lists wrote first); null: none
     bool fused_finish = false;        // forward: the pattern L2P writes the output (see vp_near.hip)
+    std::vector<double> pat_rx, pat_ry;  // the node pattern, box-relative in units of the side
     // [5][PD x npat] A-fragment order: the leaf P2M, then the four quadrant
     // P2M matrices (about the quadrant centre at the children's scale, zero
     // outside the quadrant's points)
     double *p2m_op = nullptr, *l2p_op = nullptr;      // float64 forms
     float *p2m_op_f32 = nullptr, *l2p_op_f32 = nullptr;  // FP32-bulk forms
+};
+
+// Modified Helmholtz kernel (vp_yukawa.hip): fixed matrices per level on a
+// uniform grid of congruent leaves
+struct YukawaPlan {
+    bool active = false;
+    double lambda = 0.0, cG = 0.0;   // G = cG K_0(lambda r), cG = lambda^2 / (2 pi)
+    int leaf_level = -1;
+    double *p2m = nullptr, *l2p = nullptr;            // pattern operators, A-fragment order
+    double *m2m = nullptr, *l2l = nullptr;            // [level][child quadrant] PD x PD
+    double *m2l = nullptr;                            // [level][offset code] PD x PD
+    int32_t *cslot = nullptr;                         // [nbox][4] child in each quadrant (M2M)
+    int32_t *pslot = nullptr;                         // [nbox][4] parent in the box's quadrant slot (L2L)
+    std::vector<std::vector<int32_t>> parents, children;  // per level (host)
+    std::vector<int32_t *> d_parents, d_children;
+    int32_t *m2l_cols = nullptr, *m2l_slot = nullptr;     // boxes of level >= 2; [nbox][NOFF x nlevels]
+    int32_t *m2l_tptr = nullptr, *m2l_tops = nullptr, *m2l_torder = nullptr;
+    int n_m2l_cols = 0;
+    int64_t m2l_translations = 0, m2l_tile_ops = 0;
 };
 
 }  // namespace vp
@@ -317,6 +337,7 @@ struct vp_plan_s {
     vp::Tree tree;
     vp::Operators ops;
     vp::NearTables near;
+    vp::YukawaPlan yk;
     int64_t near_pairs = 0;
     int64_t table_pairs = 0;
 
@@ -383,6 +404,8 @@ void build_tree(vp_plan_s *P, const double *hx, const double *hy, const double *
 void build_operators(vp_plan_s *P);
 // vp_near.hip
 void build_near_tables(vp_plan_s *P);  // vp_near.hip
+// vp_yukawa.hip: operators and lists of the modified Helmholtz kernel
+void build_yukawa(vp_plan_s *P);
 // vp_fmm.hip
 void build_schedules(vp_plan_s *P);
 // time the M2L variants valid for the plan's precision and keep the fastest

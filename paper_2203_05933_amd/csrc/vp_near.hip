@@ -194,6 +194,8 @@ void build_near_tables(vp_plan_s *P) {
     }
     N.active = npat > 0;
     N.npat = npat;
+    N.pat_rx = rx;
+    N.pat_ry = ry;
 
     // --- U lists split: table slots for pattern-leaf pairs on the same level
     // or one level apart, the rest pairwise.  Slot layout per target level

@@ -28,7 +28,8 @@ def test_options_struct_layout():
     vp, lib = _lib()
     o = vp.default_options()
     assert (o.order, o.max_leaf, o.nbatch, o.precision) == (30, 64, 1, 0)
-    assert ctypes.sizeof(vp.Options) == 8 * 4 + 3 * 8 + 8
+    assert ctypes.sizeof(vp.Options) == 8 * 4 + 3 * 8 + 8 + 4 + 4 + 8
+    assert (o.kernel, o.lam) == (0, 0.0)
 
 
 def _plan(lib, vp, x, y, w, n, tx=None, ty=None, m=None, rowptr=None, col=None, val=None, **opt):
@@ -44,7 +45,7 @@ def _plan(lib, vp, x, y, w, n, tx=None, ty=None, m=None, rowptr=None, col=None, 
 
 @pytest.mark.parametrize("case", ["n0", "nan", "m_mismatch", "rowptr0", "rowptr_dec", "col_range",
                                   "order", "nbatch", "leaf", "fp32_mode", "flags", "root_node",
-                                  "root_target"])
+                                  "root_target", "kernel", "lambda0", "lambda_nan"])
 def test_plan_rejects_invalid(case):
     vp, lib = _lib()
     x = np.linspace(0, 1, 8)
@@ -75,6 +76,12 @@ def test_plan_rejects_invalid(case):
         kw["m2l_mode"] = 2  # FP32 M2L with precision FP64
     elif case == "flags":
         kw["flags"] = 4  # unknown bit
+    elif case == "kernel":
+        kw["kernel"] = 2
+    elif case == "lambda0":
+        kw["kernel"], kw["lam"] = 1, 0.0
+    elif case == "lambda_nan":
+        kw["kernel"], kw["lam"] = 1, float("nan")
     if case in ("root_node", "root_target"):
         # a given root square must hold every node and target: [0, 1]^2 holds
         # the nodes, and one point leaves it by one ulp
@@ -147,3 +154,21 @@ def test_plan_oversampled_rejects_invalid(case):
     assert st == vp.VP_EINVAL, (st, msg)
     assert h.value is None
     assert len(msg) > 0
+
+
+@pytest.mark.parametrize("case", ["fp32", "pairwise"])
+def test_yukawa_unsupported_forms(case):
+    """The modified Helmholtz kernel runs in float64 with near-field tables:
+    the other forms are refused before touching a device."""
+    vp, lib = _lib()
+    x = np.linspace(0, 1, 8)
+    y = np.linspace(0, 1, 8)[::-1].copy()
+    w = np.ones(8)
+    kw = {"kernel": 1, "lam": 10.0}
+    if case == "fp32":
+        kw["precision"] = 1
+    else:
+        kw["p2p_mode"] = 1
+    st, h, msg = _plan(lib, vp, x, y, w, 8, **kw)
+    assert st == vp.VP_EUNSUPPORTED, (st, msg)
+    assert h.value is None
