@@ -99,6 +99,8 @@ def workload(name, shared_blocks=True):
         return gen.config3(shared_blocks=shared_blocks)
     if name == "oversampled64":
         return gen.config5()
+    if name == "yukawa128":
+        return gen.config6()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -138,9 +140,11 @@ def oversampling_layout(wl):
 
 def make_plan(wl, order, precision, m2l_mode="auto", one_stream=False, max_leaf=64):
     from paper_2203_05933_amd import vp
+    lam = wl.meta.get("lambda")
+    kern = dict(kernel="yukawa", lam=lam) if lam else {}
     return vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=order, max_leaf=max_leaf,
                    nbatch=wl.nbatch, precision=precision, m2l_mode=m2l_mode, one_stream=one_stream, root=wl.root,
-                   oversampling=oversampling_layout(wl))
+                   oversampling=oversampling_layout(wl), **kern)
 
 
 def run_form(wl, f, order, precision, steps, warmup, m2l_mode="auto", one_stream=False, label=""):
@@ -194,8 +198,9 @@ def stage_roofline(info, tim, stage, workload_name=None):
         # the levels below run in the "coarse" stage on the third stream
         nv = info["m2l_translations"] - info["m2l_coarse_translations"]
         tile_ops = info["m2l_tile_ops"] - info["m2l_coarse_tile_ops"]
-        scaled = info["m2l_mode"] in (4, 5)
-        fp64_core = info["m2l_mode"] in (1, 4)
+        # the modified Helmholtz kernel runs the per-offset real 2P x 2P operators
+        scaled = info["m2l_mode"] in (4, 5) and info.get("kernel", 0) == 0
+        fp64_core = info["m2l_mode"] in (1, 4) or info.get("kernel", 0) == 1
         per = 4 * P * P + 12 * P if scaled else 8 * P * P
         flops = nv * nb * per
         peak = FP64_MFMA_TFLOPS if fp64_core else FP32_MFMA_TFLOPS
@@ -266,6 +271,9 @@ def reference(wl):
     if hasattr(wl, "p_interp"):
         from oracle import oversample
         return oversample.evaluate(wl, tidx=wl.sample)
+    if wl.meta.get("lambda"):
+        from oracle import yukawa
+        return yukawa.evaluate(wl, wl.meta["lambda"], tidx=wl.sample)
     return direct.evaluate(wl.x, wl.y, wl.w, wl.f, wl.rowptr, wl.col, wl.val, wl.tx, wl.ty, tidx=wl.sample)
 
 
@@ -328,6 +336,24 @@ def precision_pair(name, steps, warmup, order, order32, with_cpu):
     return out
 
 
+def yukawa_record(steps, warmup, order, with_cpu):
+    """The modified Helmholtz kernel (lambda = 10) on the 128 x 128-box grid, FP64."""
+    import torch
+    wl = workload("yukawa128")
+    f = torch.tensor(wl.f, dtype=torch.float64, device="cuda:0")
+    rec, u, info, tim, plan = run_form(wl, f, order, "fp64", steps, warmup, label=wl.name)
+    rec["workload"] = (f"{wl.name}: {wl.n} nodes, targets=nodes, {wl.nbatch} density, "
+                       f"G = lambda^2/(2 pi) K0(lambda r), lambda = {wl.meta['lambda']:g}")
+    stage, roof, _ = rooflines(info, tim, wl.name)
+    rec["dominant_stage"] = stage
+    rec["roofline"] = roof
+    if with_cpu:
+        rec["rel_err"] = rel_err(u, reference(wl), wl.sample)
+        rec["rel_err_targets"] = int(wl.sample.size)
+    plan.close()
+    return rec
+
+
 def per_entry_correction(steps, warmup, order, with_cpu):
     """The headline grid with every correction value drawn on its own."""
     import torch
@@ -359,7 +385,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform256x16",
-                    choices=["uniform256x16", "star", "uniform128", "uniform16", "oversampled64"])
+                    choices=["uniform256x16", "star", "uniform128", "uniform16", "oversampled64", "yukawa128"])
     ap.add_argument("--order", type=int, default=30)
     ap.add_argument("--order-fp32", type=int, default=14)
     ap.add_argument("--max-leaf", type=int, default=64)
@@ -463,6 +489,8 @@ def main():
         torch.cuda.empty_cache()
         secondary["oversampled"] = precision_pair("oversampled64", args.steps, args.warmup, args.order,
                                                   args.order_fp32, not args.no_cpu)
+        torch.cuda.empty_cache()
+        secondary["yukawa"] = yukawa_record(args.steps, args.warmup, args.order, not args.no_cpu)
 
     if args.copy_mib > 0:
         n_el = args.copy_mib * (1 << 20) // 8

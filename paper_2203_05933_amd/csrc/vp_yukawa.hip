@@ -49,23 +49,27 @@ T *upload_vec(vp_plan_s *P, const std::vector<T> &h) {
     return d;
 }
 
-// Bessel values at one argument: f[|k|], k = -kmax..kmax, times e^{i k arg d}
+// Bessel values at one argument times the phase: f_|k|(lambda |d|) e^{i k arg d},
+// k = -kmax..kmax, tabulated once per argument
 struct BesselRow {
-    std::vector<long double> v;
-    long double arg = 0;
-    cld at(int k) const {
-        const long double a = (long double)k * arg;
-        return v[(size_t)std::abs(k)] * cld(std::cos(a), std::sin(a));
-    }
+    std::vector<cld> v;  // index k + kmax
+    int kmax = 0;
+    cld at(int k) const { return v[(size_t)(k + kmax)]; }
 };
 
 BesselRow bessel_row(bool kind_k, long double lam, cld d, int kmax) {
-    BesselRow r;
-    r.v.resize((size_t)kmax + 1);
+    std::vector<long double> f((size_t)kmax + 1);
     const long double x = lam * std::abs(d);
-    if (kind_k) bessel_k_all(x, kmax, r.v.data());
-    else bessel_i_all(x, kmax, r.v.data());
-    r.arg = std::arg(d);
+    if (kind_k) bessel_k_all(x, kmax, f.data());
+    else bessel_i_all(x, kmax, f.data());
+    const long double arg = std::arg(d);
+    BesselRow r;
+    r.kmax = kmax;
+    r.v.resize((size_t)2 * kmax + 1);
+    for (int k = -kmax; k <= kmax; ++k) {
+        const long double a = (long double)k * arg;
+        r.v[(size_t)(k + kmax)] = f[(size_t)std::abs(k)] * cld(std::cos(a), std::sin(a));
+    }
     return r;
 }
 

@@ -41,6 +41,7 @@ __all__ = [
     "OversampledWorkload",
     "oversampled_grid",
     "config5",
+    "config6",
 ]
 
 
@@ -203,6 +204,16 @@ def config5(nbox_side: int = 64, p: int = 8, q: int = 16, f_seeds=(50,), csr_see
     return OversampledWorkload(name=f"oversampled{nbox_side}x{nbox_side}_cheb{p}to{q}", x=x, y=y, w=w, f=f,
                                tx=tx, ty=ty, rowptr=rowptr, col=col, val=val, root=(-1.0, -1.0, 2.0),
                                sample=sample, meta={"boxes": nbox}, nbox=nbox, p_interp=p, q_interp=q)
+
+
+def config6(nbox_side: int = 128, lam: float = 10.0, nsample: int = 1024):
+    """Modified Helmholtz workload: the 128 x 128-box grid of 8x8 GL nodes
+    (1,048,576 nodes, one Gaussian-sum density, own-cell corrections with one
+    shared block) with lambda = 10 (lambda^2 = 100, the value of the paper's
+    modified Helmholtz experiment); meta["lambda"] carries it."""
+    wl = uniform_config(nbox_side, [60], 61, 160, f"yukawa{nbox_side}x{nbox_side}_gl8_lambda{lam:g}", nsample=nsample)
+    wl.meta["lambda"] = lam
+    return wl
 
 
 def gaussian_sum_density(x, y, seed: int, ncomp: int = 4, center_box: float = 0.8,
