@@ -138,20 +138,37 @@ def oversampling_layout(wl):
                 out_start=np.arange(wl.nbox, dtype=np.int64) * q * q)
 
 
-def make_plan(wl, order, precision, m2l_mode="auto", one_stream=False, max_leaf=64):
+def make_plan(wl, order, precision, m2l_mode="auto", one_stream=False, max_leaf=64, tune=False, tune_leaf=False,
+              m2l_waves=0, table_waves=0):
+    """A plan of the workload; tune: the plan-time autotuner (M2L form and
+    waves per tile, near-table waves, streams), tune_leaf: also the leaf size."""
     from paper_2203_05933_amd import vp
     lam = wl.meta.get("lambda")
     kern = dict(kernel="yukawa", lam=lam) if lam else {}
     return vp.Plan(wl.x, wl.y, wl.w, wl.tx, wl.ty, wl.rowptr, wl.col, wl.val, order=order, max_leaf=max_leaf,
                    nbatch=wl.nbatch, precision=precision, m2l_mode=m2l_mode, one_stream=one_stream, root=wl.root,
-                   oversampling=oversampling_layout(wl), **kern)
+                   oversampling=oversampling_layout(wl), autotune=tune and m2l_mode == "auto",
+                   autotune_leaf=tune_leaf and m2l_mode == "auto", m2l_waves=m2l_waves, table_waves=table_waves,
+                   **kern)
 
 
-def run_form(wl, f, order, precision, steps, warmup, m2l_mode="auto", one_stream=False, label=""):
-    """Plan, time and return (record, result tensor, plan info, stage timing, plan)."""
+def tuned_choices(info):
+    """The knobs an evaluation runs with (the autotuner's choices when tuned)."""
+    from paper_2203_05933_amd import vp
+    names = {v: k for k, v in vp.M2L_MODES.items()}
+    return {"m2l_mode": names.get(info["m2l_mode"], info["m2l_mode"]), "m2l_waves": info["m2l_waves"],
+            "table_waves": info["table_waves"], "one_stream": bool(info["one_stream"]), "max_leaf": info["max_leaf"],
+            "tuned": {0: "defaults", 1: "timed at plan time", 2: "from the tuning cache"}[info["tuned"]],
+            "tune_ms": info["tune_ms"]}
+
+
+def run_form(wl, f, order, precision, steps, warmup, m2l_mode="auto", one_stream=False, label="", tune=True,
+             tune_leaf=False):
+    """Plan (autotuned unless the M2L mode is given), time and return
+    (record, result tensor, plan info, stage timing, plan)."""
     import torch
     t0 = time.perf_counter()
-    plan = make_plan(wl, order, precision, m2l_mode, one_stream)
+    plan = make_plan(wl, order, precision, m2l_mode, one_stream, tune=tune, tune_leaf=tune_leaf)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
     u = torch.empty((wl.nbatch, wl.m), dtype=torch.float64, device="cuda:0")
@@ -161,7 +178,7 @@ def run_form(wl, f, order, precision, steps, warmup, m2l_mode="auto", one_stream
     info = plan.info()
     stages = {k: v / max(tim["evals"], 1) for k, v in tim["ms"].items()}
     rec = {"value": value, "ms_per_step": ms, "order": order, "precision": precision, "plan_ms": plan_ms,
-           "m2l_mode": info["m2l_mode"], "stages_ms": stages}
+           "m2l_mode": info["m2l_mode"], "choices": tuned_choices(info), "stages_ms": stages}
     log(f"[bench] {label} {precision} p={order}: plan {plan_ms:.0f} ms, {ms:.3f} ms/eval, {value:.1f} Mpoints/s; "
         "stages(ms/eval)=" + json.dumps({k: round(v, 4) for k, v in stages.items()}))
     return rec, u, info, tim, plan
@@ -416,7 +433,9 @@ def main():
     log(f"[bench] n={wl.n} m={wl.m} nbatch={nb} nnz={0 if wl.rowptr is None else int(wl.rowptr[-1])}")
     f = torch.tensor(wl.f, dtype=torch.float64, device="cuda:0")
 
-    rec64, u64, info, tim, plan = run_form(wl, f, args.order, "fp64", args.steps, args.warmup, label="headline")
+    rec64, u64, info, tim, plan = run_form(wl, f, args.order, "fp64", args.steps, args.warmup, label="headline",
+                                           tune_leaf=True)
+    log(f"[bench] headline plan choices: {json.dumps(rec64['choices'])}")
     value, ms_per_step = rec64["value"], rec64["ms_per_step"]
     stage, roof, roofs = rooflines(info, tim, wl.name)
     plan.close()
@@ -430,7 +449,9 @@ def main():
     one = None
     roofs_overlapped = roofs
     if not args.no_one_stream:
-        plan1 = make_plan(wl, args.order, "fp64", one_stream=True, max_leaf=args.max_leaf)
+        ch = rec64["choices"]  # the same kernels as the headline plan, every one on one stream
+        plan1 = make_plan(wl, args.order, "fp64", m2l_mode=ch["m2l_mode"], one_stream=True, max_leaf=ch["max_leaf"],
+                          m2l_waves=ch["m2l_waves"], table_waves=ch["table_waves"])
         u1 = torch.empty_like(u64)
         dt1, tim1 = time_evals(plan1, f, u1, args.steps, args.warmup)
         inf1 = plan1.info()
@@ -446,10 +467,10 @@ def main():
     if not args.no_fp32:
         # FP32-bulk: the scaled M2L in FP32 (default) and the split hi/lo FP32
         # products per offset (T_hi M_hi + T_hi M_lo + T_lo M_hi)
-        for key, mode, desc in (("fp32_scaled", "auto", "fp32 mfma, scaled form"),
+        for key, mode, desc in (("fp32_scaled", "auto", "autotuned FP32-bulk form (M2L form, waves, streams, leaf)"),
                                 ("split_hi_lo", "split", "split hi/lo fp32 mfma, per-offset operators")):
             r32, u32, inf32, tim32, plan32 = run_form(wl, f, args.order_fp32, "fp32", args.steps, args.warmup,
-                                                      mode, label="headline")
+                                                      mode, label="headline", tune_leaf=True)
             r32["m2l"] = desc
             r32["speedup_vs_fp64"] = r32["value"] / value
             st32, roof32, _ = rooflines(inf32, tim32, wl.name)
@@ -516,12 +537,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.n} nodes x {nb} densities, targets=nodes, p={args.order} float64, "
-                               f"max_leaf={args.max_leaf}, own-cell correction (one shared 64x64 box block)",
+                               f"max_leaf={rec64['choices']['max_leaf']} (autotuned among {args.max_leaf} and "
+                               f"{args.max_leaf // 4}), own-cell correction (one shared 64x64 box block)",
                    "n": wl.n, "m": wl.m, "nbatch": nb, "order": args.order, "nnz": int(info["nnz"]),
                    "parallelism": "single GPU"},
         "rel_err": rel64,
         "rel_err_targets": None if rel64 is None else f"{wl.sample.size} sampled targets x {nb} densities",
         "plan_ms": rec64["plan_ms"],
+        "autotuned": rec64["choices"],
         "stages_ms": rec64["stages_ms"],
         "dominant_stage": stage,
         "roofline": roof,

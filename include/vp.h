@@ -77,19 +77,26 @@ enum { VP_P2P_AUTO = 0, VP_P2P_PAIRWISE = 1, VP_P2P_TABLES = 2 };
                       VP_FP32_BULK and vp_eval_grad_targets return
                       VP_EUNSUPPORTED. */
 enum { VP_KERNEL_LAPLACE = 0, VP_KERNEL_YUKAWA = 1 };
-/* VP_FLAG_AUTOTUNE: with m2l_mode VP_M2L_AUTO, vp_plan times every M2L kernel
-   variant that meets the precision's accuracy (FP64: scaled and per-offset
-   FP64 products; FP32-bulk: scaled FP32, per-offset FP32 and scaled FP64
-   products) on this plan's interaction lists and keeps the fastest
-   (vp_get_info reports it).  The plan call then synchronises the stream a
-   few more times; results differ only by rounding. */
+/* VP_FLAG_AUTOTUNE: with m2l_mode VP_M2L_AUTO, vp_plan tunes the evaluation
+   by coordinate descent, timing full evaluations of this plan: the M2L kernel
+   form (FP64: scaled and per-offset FP64 products; FP32-bulk: scaled FP32,
+   per-offset FP32, split hi/lo FP32 and scaled FP64 products -- every one
+   meets the precision's accuracy target), the waves per 16-column tile of the
+   M2L and near-table kernels (4 or 2; a knob set in vp_options is kept), and
+   three streams against one (kept on one stream with VP_FLAG_ONE_STREAM).
+   Choices are cached per process for plans of the same geometry and options
+   (a second such plan skips the timing).  vp_get_info reports them.
+   VP_FLAG_AUTOTUNE_LEAF: also tune the tree shape -- vp_plan builds the plan
+   with max_leaf and with max_leaf / 4 (when that is at least 4), each tuned as
+   above, times them and keeps the faster (the leaf size enters the cache key's
+   result).  Results differ only by rounding. */
 /* VP_FLAG_ONE_STREAM: run every kernel of an evaluation on the plan's stream,
    in sequence.  By default the correction apply and the near field run on a
    second stream owned by the plan, beside the expansion passes, and join the
    plan's stream before the far field; with this flag nothing overlaps (for
    callers that need all work on one stream, and for per-stage timings
    without contention).  Results are identical either way. */
-enum { VP_FLAG_AUTOTUNE = 1, VP_FLAG_ONE_STREAM = 2 };
+enum { VP_FLAG_AUTOTUNE = 1, VP_FLAG_ONE_STREAM = 2, VP_FLAG_AUTOTUNE_LEAF = 8 };
 
 typedef struct {
     int32_t order;     /* p: highest power kept in the expansions (p+1 complex
@@ -118,8 +125,12 @@ typedef struct {
     void *stream;      /* hipStream_t for plan-time copies and evaluations;
                           NULL = the null stream */
     int32_t kernel;    /* VP_KERNEL_*; default VP_KERNEL_LAPLACE */
-    int32_t reserved;
+    int32_t m2l_waves; /* waves per 16-column tile of the M2L kernels: 2 or 4;
+                          0 = 4, or the autotuner's choice */
     double lambda;     /* VP_KERNEL_YUKAWA: lambda > 0 (Section 5 uses lambda^2 = 100) */
+    int32_t table_waves; /* waves per tile of the near-table kernel: 2 or 4; 0 = 4,
+                            or the autotuner's choice */
+    int32_t reserved;
 } vp_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -277,6 +288,11 @@ typedef struct {
     int32_t kernel;            /* VP_KERNEL_* */
     int32_t reserved2;
     double lambda;
+    int32_t tuned;             /* 0: defaults; 1: tuned by timing in this call; 2: from the cache */
+    int32_t m2l_waves;         /* waves per 16-column tile of the M2L kernels */
+    int32_t table_waves;       /* waves per tile of the near-table kernel */
+    int32_t one_stream;        /* 1: every kernel of an evaluation on the plan's stream */
+    double tune_ms;            /* plan time spent timing candidates */
 } vp_plan_info_t;
 
 vp_status vp_get_info(vp_plan_t plan, vp_plan_info_t *info);

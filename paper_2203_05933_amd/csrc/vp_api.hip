@@ -3,6 +3,7 @@
 // exceptions, caught here and turned into vp_status codes.
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <map>
@@ -242,8 +243,10 @@ static void validate_plan_args(const double *x, const double *y, const double *w
         bad("FP32 M2L modes need precision VP_FP32_BULK");
     if (o.p2p_mode < 0 || o.p2p_mode > 2) bad("unknown p2p_mode");
     if (o.max_level < 0 || o.max_level > vp::LBITS) bad("max_level must be in 0..30");
-    if (o.flags & ~(VP_FLAG_AUTOTUNE | VP_FLAG_ONE_STREAM)) bad("unknown flags");
+    if (o.flags & ~(VP_FLAG_AUTOTUNE | VP_FLAG_ONE_STREAM | VP_FLAG_AUTOTUNE_LEAF)) bad("unknown flags");
     if (o.kernel != VP_KERNEL_LAPLACE && o.kernel != VP_KERNEL_YUKAWA) bad("unknown kernel");
+    if (o.m2l_waves != 0 && o.m2l_waves != 2 && o.m2l_waves != 4) bad("m2l_waves must be 0, 2 or 4");
+    if (o.table_waves != 0 && o.table_waves != 2 && o.table_waves != 4) bad("table_waves must be 0, 2 or 4");
     if (o.kernel == VP_KERNEL_YUKAWA && !(std::isfinite(o.lambda) && o.lambda > 0))
         bad("the modified Helmholtz kernel needs a finite lambda > 0");
     if (o.kernel == VP_KERNEL_YUKAWA && o.precision != VP_FP64)
@@ -282,6 +285,57 @@ static void free_plan(vp_plan_s *P) {
     release_timing(P);
     P->mem.free_all();
     delete P;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning cache: the autotuner's choices per geometry and options, for the
+// life of the process
+// ---------------------------------------------------------------------------
+struct TuneChoice {
+    int m2l_mode = 0, m2l_nw = 4, table_nw = 4, one_stream = 0, max_leaf = 0;
+    float ms = 0.f;
+};
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneChoice> g_tune;
+
+static uint64_t fnv1a(uint64_t h, const void *p, size_t bytes) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    return h;
+}
+
+// key: sizes, the options that shape the evaluation (max_leaf only when the
+// leaf size is not itself tuned) and a hash of the coordinates
+static std::string tune_key(const double *x, const double *y, int64_t n, const double *tx, const double *ty,
+                            int64_t m, int64_t nnz, const vp_oversampling *os, const vp_options &o) {
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, x, 8 * (size_t)n);
+    h = fnv1a(h, y, 8 * (size_t)n);
+    if (tx) {
+        h = fnv1a(h, tx, 8 * (size_t)m);
+        h = fnv1a(h, ty, 8 * (size_t)m);
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "%lld/%lld/%lld/%d/%d/%d/%d/%d/%d/%d/%d/%.17g/%.17g/%.17g/%.17g/%d/%d/%d/%d/%llx",
+                  (long long)n, (long long)m, (long long)nnz, o.order,
+                  (o.flags & VP_FLAG_AUTOTUNE_LEAF) ? -1 : o.max_leaf, o.nbatch, o.precision, o.p2p_mode,
+                  o.max_level, o.kernel, (o.flags & (VP_FLAG_ONE_STREAM | VP_FLAG_AUTOTUNE_LEAF)), o.root[0],
+                  o.root[1], o.root[2], o.lambda, os ? os->p : 0, os ? os->q : 0, o.m2l_waves, o.table_waves,
+                  (unsigned long long)h);
+    return buf;
+}
+
+static bool tune_lookup(const std::string &key, TuneChoice &c) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    c = it->second;
+    return true;
+}
+
+static void tune_store(const std::string &key, const TuneChoice &c) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = c;
 }
 
 // Oversampled boxes: checks of the layout (see vp_plan_oversampled)
@@ -366,9 +420,9 @@ static void build_oversampling(vp_plan_s *P, const vp_oversampling *os) {
     VP_HIP(hipStreamSynchronize(P->stream));  // the host copies leave scope
 }
 
-static vp_status plan_impl(const double *x, const double *y, const double *w, int64_t n, const double *tx,
-                           const double *ty, int64_t m, const int64_t *rowptr, const int32_t *col,
-                           const double *val, const vp_oversampling *os, const vp_options *opt, vp_plan_t *out) {
+static vp_status plan_build(const double *x, const double *y, const double *w, int64_t n, const double *tx,
+                            const double *ty, int64_t m, const int64_t *rowptr, const int32_t *col,
+                            const double *val, const vp_oversampling *os, const vp_options *opt, vp_plan_t *out) {
     if (out) *out = nullptr;
     vp_options o;
     if (opt) o = *opt;
@@ -398,6 +452,8 @@ static vp_status plan_impl(const double *x, const double *y, const double *w, in
         if (P->PD > 128) throw Error(VP_EUNSUPPORTED, "order too large (2(p+1)+1 must be <= 128)");
         P->fp32 = (o.precision == VP_FP32_BULK);
         P->one_stream = (o.flags & VP_FLAG_ONE_STREAM) != 0;
+        if (o.m2l_waves) P->m2l_nw = o.m2l_waves;
+        if (o.table_waves) P->table_nw = o.table_waves;
         P->m2l_mode = o.m2l_mode == VP_M2L_AUTO ? (P->fp32 ? VP_M2L_FP32_SCALED : VP_M2L_FP64_SCALED) : o.m2l_mode;
         P->stream = static_cast<hipStream_t>(o.stream);
         VP_HIP(hipGetDevice(&P->device));
@@ -459,13 +515,112 @@ static vp_status plan_impl(const double *x, const double *y, const double *w, in
         if (o.kernel == VP_KERNEL_YUKAWA) vp::build_yukawa(P);
         if (o.p2p_mode == VP_P2P_TABLES && !P->near.active)
             throw Error(VP_EUNSUPPORTED, "p2p_mode TABLES needs targets = nodes and congruent leaves");
-        if ((o.flags & VP_FLAG_AUTOTUNE) && o.m2l_mode == VP_M2L_AUTO) vp::autotune_m2l(P);
+        if ((o.flags & VP_FLAG_AUTOTUNE) && o.m2l_mode == VP_M2L_AUTO && !P->yk.active) {
+            const std::string key = tune_key(x, y, n, tx, ty, m, rowptr ? rowptr[m] : 0, os, o);
+            TuneChoice c;
+            if (tune_lookup(key, c)) {
+                P->m2l_mode = c.m2l_mode;
+                P->m2l_nw = c.m2l_nw;
+                P->table_nw = c.table_nw;
+                P->one_stream = c.one_stream != 0;
+                P->tuned = 2;
+            } else {
+                const auto t0 = std::chrono::steady_clock::now();
+                c.ms = vp::autotune(P);
+                P->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                P->tuned = 1;
+                c.m2l_mode = P->m2l_mode;
+                c.m2l_nw = P->m2l_nw;
+                c.table_nw = P->table_nw;
+                c.one_stream = P->one_stream ? 1 : 0;
+                tune_store(key, c);
+            }
+        }
     });
     if (st != VP_OK) {
         free_plan(P);  // the message is already in the thread-local slot
         return st;
     }
     *out = P;
+    return VP_OK;
+}
+
+// Plan with VP_FLAG_AUTOTUNE_LEAF: build the plan with max_leaf and with
+// max_leaf / 4, time a forward evaluation of each (density 1) and keep the
+// faster; the choice is cached like the other tuned knobs.
+static vp_status plan_impl(const double *x, const double *y, const double *w, int64_t n, const double *tx,
+                           const double *ty, int64_t m, const int64_t *rowptr, const int32_t *col,
+                           const double *val, const vp_oversampling *os, const vp_options *opt, vp_plan_t *out) {
+    vp_options o;
+    if (opt) o = *opt;
+    else vp_default_options(&o);
+    if (!(o.flags & VP_FLAG_AUTOTUNE_LEAF)) return plan_build(x, y, w, n, tx, ty, m, rowptr, col, val, os, &o, out);
+    if (out) *out = nullptr;
+    if (!out) return set_err(nullptr, VP_EINVAL, "out is NULL");
+    vp_options base = o;
+    base.flags &= ~VP_FLAG_AUTOTUNE_LEAF;
+    if (o.max_leaf < 1 || o.max_leaf > 256) return plan_build(x, y, w, n, tx, ty, m, rowptr, col, val, os, &base, out);
+    const std::string key = tune_key(x, y, n, tx, ty, m, rowptr ? rowptr[m] : 0, os, o);
+    TuneChoice c;
+    if (tune_lookup(key, c) && c.max_leaf > 0) {
+        base.max_leaf = c.max_leaf;
+        vp_status st = plan_build(x, y, w, n, tx, ty, m, rowptr, col, val, os, &base, out);
+        if (st == VP_OK) (*out)->tuned = 2;
+        return st;
+    }
+    std::vector<int> cand{o.max_leaf};
+    if (o.max_leaf / 4 >= 4) cand.push_back(o.max_leaf / 4);
+    const auto t0 = std::chrono::steady_clock::now();
+    vp_plan_s *best = nullptr;
+    float best_ms = 1e30f;
+    vp_status last = VP_OK;
+    std::string last_msg;
+    for (int leaf : cand) {
+        base.max_leaf = leaf;
+        vp_plan_t Pc = nullptr;
+        vp_status st = plan_build(x, y, w, n, tx, ty, m, rowptr, col, val, os, &base, &Pc);
+        if (st != VP_OK) {
+            last = st;
+            last_msg = g_last_error;
+            continue;
+        }
+        float ms = 1e30f;
+        st = guarded(Pc, [&] {
+            vp::TempArena tmp;
+            double *f = tmp.alloc<double>((size_t)Pc->nbatch * Pc->nd);
+            double *u = tmp.alloc<double>((size_t)Pc->nbatch * Pc->m);
+            vp::fill_f64(f, 1.0, (int64_t)Pc->nbatch * Pc->nd, Pc->stream);
+            ms = vp::time_forward(Pc, f, u, 3);
+            VP_HIP(hipStreamSynchronize(Pc->stream));
+        });
+        if (st != VP_OK) {
+            last = st;
+            last_msg = Pc->err;
+            free_plan(Pc);
+            continue;
+        }
+        if (ms < best_ms) {
+            if (best) free_plan(best);
+            best = Pc;
+            best_ms = ms;
+        } else {
+            free_plan(Pc);
+        }
+    }
+    if (!best) {
+        g_last_error = last_msg;
+        return last == VP_OK ? VP_EINTERNAL : last;
+    }
+    c.max_leaf = best->opt.max_leaf;
+    c.m2l_mode = best->m2l_mode;
+    c.m2l_nw = best->m2l_nw;
+    c.table_nw = best->table_nw;
+    c.one_stream = best->one_stream ? 1 : 0;
+    c.ms = best_ms;
+    tune_store(key, c);
+    if (!best->tuned) best->tuned = 1;
+    best->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = best;
     return VP_OK;
 }
 
@@ -658,6 +813,11 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->os_q = P->os_q;
     info->kernel = P->opt.kernel;
     info->lambda = P->opt.lambda;
+    info->tuned = P->tuned;
+    info->m2l_waves = P->m2l_nw;
+    info->table_waves = P->table_nw;
+    info->one_stream = P->one_stream ? 1 : 0;
+    info->tune_ms = P->tune_ms;
     if (P->yk.active) {
         info->m2l_translations = P->yk.m2l_translations;
         info->m2l_tile_ops = P->yk.m2l_tile_ops;

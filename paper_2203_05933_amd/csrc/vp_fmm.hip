@@ -1637,43 +1637,56 @@ void build_schedules(vp_plan_s *P) {
 // Gather-GEMM launches of the per-offset M2L form
 // ----------------------------------------------------------------------------
 template <class TI, class TO, class TM, bool SPLIT, int RB>
-static void launch_split(hipStream_t s, const TranslateArgs &a, const TM *Ahi, const TM *Alo, const TI *in,
+static void launch_split(hipStream_t s, int nw, const TranslateArgs &a, const TM *Ahi, const TM *Alo, const TI *in,
                          TO *out) {
     constexpr int S = RB * 4;
     const unsigned blocks = (unsigned)((a.ncols + 15) / 16);
-    hipLaunchKernelGGL((k_translate_split<TI, TO, TM, RB, S, SPLIT, false>), dim3(blocks), dim3(256), 0, s, a, Ahi,
-                       Alo, in, out);
+    if (nw == 2)
+        hipLaunchKernelGGL((k_translate_split<TI, TO, TM, RB, S, SPLIT, false, 2>), dim3(blocks), dim3(128), 0, s, a,
+                           Ahi, Alo, in, out);
+    else
+        hipLaunchKernelGGL((k_translate_split<TI, TO, TM, RB, S, SPLIT, false, 4>), dim3(blocks), dim3(256), 0, s, a,
+                           Ahi, Alo, in, out);
     VP_LAUNCH_CHECK();
 }
 
 // M2L: operators split across the waves of a workgroup (overwrite only)
 template <class TI, class TO, class TM, bool SPLIT>
-static void translate_m2l(hipStream_t s, int PD, const TranslateArgs &a, const TM *Ahi, const TM *Alo,
+static void translate_m2l(hipStream_t s, int nw, int PD, const TranslateArgs &a, const TM *Ahi, const TM *Alo,
                           const TI *in, TO *out) {
     if (a.ncols <= 0) return;
     switch (PD) {
-        case 16: launch_split<TI, TO, TM, SPLIT, 1>(s, a, Ahi, Alo, in, out); break;
-        case 32: launch_split<TI, TO, TM, SPLIT, 2>(s, a, Ahi, Alo, in, out); break;
-        case 48: launch_split<TI, TO, TM, SPLIT, 3>(s, a, Ahi, Alo, in, out); break;
-        case 64: launch_split<TI, TO, TM, SPLIT, 4>(s, a, Ahi, Alo, in, out); break;
-        case 80: launch_split<TI, TO, TM, SPLIT, 5>(s, a, Ahi, Alo, in, out); break;
-        case 96: launch_split<TI, TO, TM, SPLIT, 6>(s, a, Ahi, Alo, in, out); break;
-        case 112: launch_split<TI, TO, TM, SPLIT, 7>(s, a, Ahi, Alo, in, out); break;
-        case 128: launch_split<TI, TO, TM, SPLIT, 8>(s, a, Ahi, Alo, in, out); break;
+        case 16: launch_split<TI, TO, TM, SPLIT, 1>(s, nw, a, Ahi, Alo, in, out); break;
+        case 32: launch_split<TI, TO, TM, SPLIT, 2>(s, nw, a, Ahi, Alo, in, out); break;
+        case 48: launch_split<TI, TO, TM, SPLIT, 3>(s, nw, a, Ahi, Alo, in, out); break;
+        case 64: launch_split<TI, TO, TM, SPLIT, 4>(s, nw, a, Ahi, Alo, in, out); break;
+        case 80: launch_split<TI, TO, TM, SPLIT, 5>(s, nw, a, Ahi, Alo, in, out); break;
+        case 96: launch_split<TI, TO, TM, SPLIT, 6>(s, nw, a, Ahi, Alo, in, out); break;
+        case 112: launch_split<TI, TO, TM, SPLIT, 7>(s, nw, a, Ahi, Alo, in, out); break;
+        case 128: launch_split<TI, TO, TM, SPLIT, 8>(s, nw, a, Ahi, Alo, in, out); break;
         default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
     }
 }
 
+template <class TI, class TO, class TM, int RB>
+static void launch_m2l_scaled(hipStream_t s, int nw, unsigned blocks, const M2LScaledArgs &a, const TM *Q,
+                              const TM *tin, const double *logt, const TI *in, TO *out) {
+    if (nw == 2)
+        hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, RB, 2>), dim3(blocks), dim3(128), 0, s, a, Q, tin, logt, in, out);
+    else
+        hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, RB, 4>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out);
+}
+
 template <class TI, class TO, class TM>
-static void m2l_scaled(hipStream_t s, int PQ, const M2LScaledArgs &a, const TM *Q, const TM *tin,
+static void m2l_scaled(hipStream_t s, int nw, int PQ, const M2LScaledArgs &a, const TM *Q, const TM *tin,
                        const double *logt, const TI *in, TO *out) {
     if (a.ncols <= 0) return;
     const unsigned blocks = (unsigned)((a.ncols + 15) / 16);
     switch (PQ) {
-        case 16: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 1>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out); break;
-        case 32: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 2>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out); break;
-        case 48: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 3>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out); break;
-        case 64: hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, 4>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out); break;
+        case 16: launch_m2l_scaled<TI, TO, TM, 1>(s, nw, blocks, a, Q, tin, logt, in, out); break;
+        case 32: launch_m2l_scaled<TI, TO, TM, 2>(s, nw, blocks, a, Q, tin, logt, in, out); break;
+        case 48: launch_m2l_scaled<TI, TO, TM, 3>(s, nw, blocks, a, Q, tin, logt, in, out); break;
+        case 64: launch_m2l_scaled<TI, TO, TM, 4>(s, nw, blocks, a, Q, tin, logt, in, out); break;
         default: throw Error(VP_EUNSUPPORTED, "unsupported expansion size");
     }
     VP_LAUNCH_CHECK();
@@ -1830,27 +1843,28 @@ static void launch_m2l(vp_plan_s *P, int part) {
         sa.xinit = P->x_init;
         sa.level = T.level;
         sa.logside = T.d_logside;
+        const int nw = P->m2l_nw;
         if (!f32)
-            m2l_scaled<double, double, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_logt,
+            m2l_scaled<double, double, double>(s, nw, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_logt,
                                                (const double *)M, (double *)L);
         else if (P->m2l_mode == VP_M2L_FP32_SCALED)
-            m2l_scaled<float, float, float>(s, O.PQ, sa, O.m2l_q32, O.m2l_tin32, O.m2l_logt,
+            m2l_scaled<float, float, float>(s, nw, O.PQ, sa, O.m2l_q32, O.m2l_tin32, O.m2l_logt,
                                             (const float *)M, (float *)L);
         else
-            m2l_scaled<float, float, double>(s, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_logt,
+            m2l_scaled<float, float, double>(s, nw, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_logt,
                                              (const float *)M, (float *)L);
     } else if (!f32) {
-        translate_m2l<double, double, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const double *)M,
-                                                     (double *)L);
+        translate_m2l<double, double, double, false>(s, P->m2l_nw, PD, a, P->ops.m2l_f64, nullptr,
+                                                     (const double *)M, (double *)L);
     } else if (P->m2l_mode == VP_M2L_FP32_SPLIT) {
-        translate_m2l<float, float, float, true>(s, PD, a, P->ops.m2l_f32, P->ops.m2l_f32_lo, (const float *)M,
-                                                 (float *)L);
+        translate_m2l<float, float, float, true>(s, P->m2l_nw, PD, a, P->ops.m2l_f32, P->ops.m2l_f32_lo,
+                                                 (const float *)M, (float *)L);
     } else if (P->m2l_mode == VP_M2L_FP64_MFMA) {
-        translate_m2l<float, float, double, false>(s, PD, a, P->ops.m2l_f64, nullptr, (const float *)M,
-                                                   (float *)L);
+        translate_m2l<float, float, double, false>(s, P->m2l_nw, PD, a, P->ops.m2l_f64, nullptr,
+                                                   (const float *)M, (float *)L);
     } else {
-        translate_m2l<float, float, float, false>(s, PD, a, P->ops.m2l_f32, nullptr, (const float *)M,
-                                                  (float *)L);
+        translate_m2l<float, float, float, false>(s, P->m2l_nw, PD, a, P->ops.m2l_f32, nullptr,
+                                                  (const float *)M, (float *)L);
     }
 }
 
@@ -2006,9 +2020,13 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     a.zero_col = P->zero_col;
     if (a.ncols <= 0) return;
     // every table leaf's sums are stored by its one tile (the other leaves are zeroed)
-    hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, false>),
-                       dim3((unsigned)((a.ncols + 15) / 16)), dim3(256), 0, P->stream, a, N.K, (const double *)nullptr,
-                       P->q, P->acc);
+    const unsigned blocks = (unsigned)((a.ncols + 15) / 16);
+    if (P->table_nw == 2)
+        hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, false, 2>), dim3(blocks),
+                           dim3(128), 0, P->stream, a, N.K, (const double *)nullptr, P->q, P->acc);
+    else
+        hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, false, 4>), dim3(blocks),
+                           dim3(256), 0, P->stream, a, N.K, (const double *)nullptr, P->q, P->acc);
     VP_LAUNCH_CHECK();
 }
 
@@ -2599,36 +2617,76 @@ static void add_fmm_sums(vp_plan_s *P, double *u, bool adjoint) {
     P->stage_end(VP_STAGE_FINISH);
 }
 
-void autotune_m2l(vp_plan_s *P) {
-    std::vector<int> cand;
-    if (P->fp32) cand = {VP_M2L_FP32_SCALED, VP_M2L_FP32_MFMA, VP_M2L_FP64_SCALED};
-    else cand = {VP_M2L_FP64_SCALED, VP_M2L_FP64_MFMA};
+// Wall time of one full forward evaluation (the smallest of reps after one
+// warm-up), on the plan's stream, with device buffers f and u.
+float time_forward(vp_plan_s *P, const double *f, double *u, int reps) {
     hipEvent_t e0, e1;
     VP_HIP(hipEventCreate(&e0));
     VP_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_mode = P->m2l_mode;
-    for (int mode : cand) {
-        P->m2l_mode = mode;
-        for (int rep = 0; rep < 4; ++rep) {  // first launch warms up
-            VP_HIP(hipEventRecord(e0, P->stream));
-            for (int part = 0; part < 2; ++part) {
-                if (P->fp32) launch_m2l<float>(P, part);
-                else launch_m2l<double>(P, part);
-            }
-            VP_HIP(hipEventRecord(e1, P->stream));
-            VP_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            VP_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (rep > 0 && ms < best) {
-                best = ms;
-                best_mode = mode;
-            }
-        }
+    for (int rep = 0; rep <= reps; ++rep) {
+        VP_HIP(hipEventRecord(e0, P->stream));
+        prepare_charges(P, f, false);
+        run_fmm(P, false, false, f, u);
+        VP_HIP(hipEventRecord(e1, P->stream));
+        VP_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        VP_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) best = std::min(best, ms);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    P->m2l_mode = best_mode;
+    return best;
+}
+
+// Plan-time autotuner: coordinate descent over the evaluation's knobs, each
+// candidate timed on full evaluations of this plan (density 1 everywhere):
+//   M2L form       FP64: scaled, per-offset products;  FP32-bulk: scaled FP32,
+//                  per-offset FP32, split hi/lo FP32, scaled FP64 (every one
+//                  meets the precision's accuracy target)
+//   M2L waves per 16-column tile (4, 2), near-table waves per tile (4, 2),
+//   streams (three, one).
+// Returns the best time (ms).
+float autotune(vp_plan_s *P) {
+    TempArena tmp;
+    double *f = tmp.alloc<double>((size_t)P->nbatch * P->nd);
+    double *u = tmp.alloc<double>((size_t)P->nbatch * P->m);
+    fill_f64(f, 1.0, (int64_t)P->nbatch * P->nd, P->stream);
+    const int reps = 3;
+    float best = time_forward(P, f, u, reps);
+    auto knob = [&](int &field, const std::vector<int> &cand) {
+        int keep = field;
+        for (int v : cand) {
+            if (v == keep) continue;
+            field = v;
+            const float t = time_forward(P, f, u, reps);
+            if (t < best) {
+                best = t;
+                keep = v;
+            }
+        }
+        field = keep;
+    };
+    if (P->fp32) knob(P->m2l_mode, {VP_M2L_FP32_SCALED, VP_M2L_FP32_MFMA, VP_M2L_FP32_SPLIT, VP_M2L_FP64_SCALED});
+    else knob(P->m2l_mode, {VP_M2L_FP64_SCALED, VP_M2L_FP64_MFMA});
+    if (P->opt.m2l_waves == 0) knob(P->m2l_nw, {4, 2});
+    if (P->opt.table_waves == 0 && P->near.active) knob(P->table_nw, {4, 2});
+    int one = P->one_stream ? 1 : 0;
+    if (!(P->opt.flags & VP_FLAG_ONE_STREAM)) {
+        bool &fld = P->one_stream;
+        for (int v : {0, 1}) {
+            if (v == one) continue;
+            fld = v != 0;
+            const float t = time_forward(P, f, u, reps);
+            if (t < best) {
+                best = t;
+                one = v;
+            }
+        }
+        fld = one != 0;
+    }
+    VP_HIP(hipStreamSynchronize(P->stream));
+    return best;
 }
 
 void finish_grad(vp_plan_s *P, double *grad) {

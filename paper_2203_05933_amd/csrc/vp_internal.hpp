@@ -285,6 +285,10 @@ struct vp_plan_s {
     bool self = false;
     bool fp32 = false;
     int m2l_mode = VP_M2L_FP64_MFMA;
+    int m2l_nw = 4;           // waves per 16-column tile of the M2L kernels (4 or 2; the autotuner may pick 2)
+    int table_nw = 4;         // waves per tile of the near-table launch
+    int tuned = 0;            // 0: defaults; 1: chosen by timing at plan time; 2: from the tuning cache
+    double tune_ms = 0.0;     // plan time spent tuning
     bool one_stream = false;  // no second stream: every kernel on the plan's stream
     hipStream_t stream = nullptr;
     // the near field runs on its own stream, forked after the charges and
@@ -408,8 +412,11 @@ void build_near_tables(vp_plan_s *P);  // vp_near.hip
 void build_yukawa(vp_plan_s *P);
 // vp_fmm.hip
 void build_schedules(vp_plan_s *P);
-// time the M2L variants valid for the plan's precision and keep the fastest
-void autotune_m2l(vp_plan_s *P);
+// plan-time autotuner (M2L form and waves per tile, near-table waves per
+// tile, streams), each candidate timed on full evaluations; returns the best ms
+float autotune(vp_plan_s *P);
+// wall time of one forward evaluation (the smallest of reps after a warm-up)
+float time_forward(vp_plan_s *P, const double *f, double *u, int reps);
 // P2M job descriptors for job codes (leaf b >= 0, or ~(4 v + quadrant)) in
 // the source role (nodes) or the target role (targets as sources)
 std::vector<P2MJob> p2m_job_descs(vp_plan_s *P, const std::vector<int32_t> &codes, bool target_role);

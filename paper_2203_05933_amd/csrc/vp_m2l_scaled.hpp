@@ -17,9 +17,10 @@
 // behaviour is that of the plain operator.
 //
 // Work split: a 16-column tile (boxes x densities, grouped by child class
-// so the tile shares its offsets) per workgroup; the four waves take every
-// fourth offset present in the tile (listed at plan time, with each column's
-// source box) and their partial sums are added through LDS in a fixed order.
+// so the tile shares its offsets) per workgroup; its NW waves (4 by default,
+// 2 when the plan's autotuner finds that faster) take every NW-th offset
+// present in the tile (listed at plan time, with each column's source box)
+// and their partial sums are added through LDS in a fixed order.
 // The diagonal scalings of all 40 offsets sit in LDS for the whole tile and
 // the lane's Q fragments in registers; the loop has no branch around a load
 // and no dependent global load, and at 166 registers three waves share each
@@ -68,8 +69,8 @@ __device__ inline void m2l_load_col(const TI *__restrict__ ip, int g, int P, TM 
 // for k = (lane/16) S + s), rows multiplied by (-1)^l; tin [NOFF][RB*16][2]
 // (re, im) = (-t)^-k, the input and (with Q's row signs) the output scaling;
 // logt [NOFF][2] = log(-t).
-template <class TI, class TO, class TM, int RB>
-__global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM *__restrict__ Qf,
+template <class TI, class TO, class TM, int RB, int NW = 4>
+__global__ void __launch_bounds__(64 * NW, 12 / NW) k_m2l_scaled(M2LScaledArgs a, const TM *__restrict__ Qf,
                                                     const TM *__restrict__ tin,
                                                     const double *__restrict__ logt, const TI *__restrict__ in,
                                                     TO *__restrict__ out) {
@@ -79,7 +80,9 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
     constexpr int NR = RB * 4 * 2 + 2;  // reduced values per lane: B re/im per item, A_0 sum re/im
     constexpr int TAB = NOFF * PQ * 2;  // elements of one scaling table
     constexpr int TBYTES = TAB * (int)sizeof(TM) + NOFF * 2 * (int)sizeof(double);
-    constexpr int RBYTES = 3 * NR * 64 * (int)sizeof(double);
+    static_assert(NW == 2 || NW == 4, "two or four waves per tile");
+    constexpr int NT = 64 * NW;  // threads
+    constexpr int RBYTES = (NW - 1) * NR * 64 * (int)sizeof(double);
     // scaling tables during the loop, the cross-wave partial sums after it
     __shared__ __align__(16) unsigned char s_raw[TBYTES > RBYTES ? TBYTES : RBYTES];
     __shared__ int32_t s_ops[NOFF];
@@ -99,13 +102,13 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
 
     // stage the tile's offsets and sources and the tables of all offsets
     const int e0 = a.tile_ptr[tile], nt = a.tile_ptr[tile + 1] - e0;
-    for (int i = tid; i < nt; i += 256) s_ops[i] = a.tile_ops[e0 + i];
-    for (int i = tid; i < nt * 16; i += 256) s_src[i >> 4][i & 15] = a.tile_src[(int64_t)e0 * 16 + i];
+    for (int i = tid; i < nt; i += NT) s_ops[i] = a.tile_ops[e0 + i];
+    for (int i = tid; i < nt * 16; i += NT) s_src[i >> 4][i & 15] = a.tile_src[(int64_t)e0 * 16 + i];
     {
         constexpr int CH = TAB * (int)sizeof(TM) / 16;  // 16-byte chunks per table
         const uint4 *gi = reinterpret_cast<const uint4 *>(tin);
         uint4 *si = reinterpret_cast<uint4 *>(s_tin);
-        for (int i = tid; i < CH; i += 256) si[i] = gi[i];
+        for (int i = tid; i < CH; i += NT) si[i] = gi[i];
         if (tid < 2 * NOFF) s_logt[tid] = logt[tid];
     }
     TM q[RB][S];
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
     double a0r = 0.0, a0i = 0.0;  // sum of A_0 over the sources (lanes g == 0)
     const int64_t bt_off = (int64_t)bt * a.bt_stride;
 
-    // this wave's offsets: every fourth one present in the tile
+    // this wave's offsets: every NW-th one present in the tile
     int e = wave;
     const TI *zc = static_cast<const TI *>(a.zero_col);
     TM xr[S], xi[S];
@@ -135,7 +138,7 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
         m2l_load_col<TI, TM, S>(src >= 0 ? in + (int64_t)src * a.box_stride + bt_off : zc, g, P, xr, xi);
     }
     const double m0 = g == 0 ? 1.0 : 0.0;  // lanes holding k = 0 at step 0
-    for (; e < nt; e += 4) {
+    for (; e < nt; e += NW) {
         const int o = s_ops[e];
         const TM *ti = s_tin + o * PQ * 2;
         {
@@ -151,7 +154,7 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
         // the next offset's source columns, into the registers the current
         // coefficients free once scaled (the compiler issues these loads at
         // the top of the next iteration, as eight 16-byte loads)
-        const int en = e + 4;
+        const int en = e + NW;
         const int srcn = en < nt ? s_src[en][cl] : -1;
         const TI *ipn = srcn >= 0 ? in + (int64_t)srcn * a.box_stride + bt_off : zc;
         const TI *pnr = ipn + g * S, *pni = ipn + P + g * S;
@@ -189,7 +192,7 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
                 bi[r][i] += zre * vi + zim * vr;
             }
     }
-    // fixed-order sum of the four waves' partial results (the tables' LDS is
+    // fixed-order sum of the waves' partial results (the tables' LDS is
     // reused once every wave has left the loop)
     __syncthreads();
     if (wave > 0) {
@@ -205,16 +208,23 @@ __global__ void __launch_bounds__(256, 3) k_m2l_scaled(M2LScaledArgs a, const TM
     }
     __syncthreads();
     if (wave != 0 || !valid) return;
+    // wave 0 + 1 + ... + NW-1, left to right
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = (r * 4 + i) * 2;
-            br[r][i] = ((br[r][i] + red[0][e][lane]) + red[1][e][lane]) + red[2][e][lane];
-            bi[r][i] = ((bi[r][i] + red[0][e + 1][lane]) + red[1][e + 1][lane]) + red[2][e + 1][lane];
+#pragma unroll
+            for (int v = 0; v < NW - 1; ++v) {
+                br[r][i] += red[v][e][lane];
+                bi[r][i] += red[v][e + 1][lane];
+            }
         }
-    a0r = ((a0r + red[0][NR - 2][lane]) + red[1][NR - 2][lane]) + red[2][NR - 2][lane];
-    a0i = ((a0i + red[0][NR - 1][lane]) + red[1][NR - 1][lane]) + red[2][NR - 1][lane];
+#pragma unroll
+    for (int v = 0; v < NW - 1; ++v) {
+        a0r += red[v][NR - 2][lane];
+        a0i += red[v][NR - 1][lane];
+    }
     if (g == 0) {
         const double ls = a.logside[a.level[box]];
         br[0][M::item_of(0)] += a0r * ls;

@@ -320,18 +320,21 @@ __global__ void __launch_bounds__(256) k_fixed_apply(const int32_t *__restrict__
     }
 }
 
-// Split-operator variant for the large M2L launch: the four waves of a
-// workgroup share ONE 16-column tile and take every fourth active operator,
+// Split-operator variant for the large M2L launch and the near tables: the
+// NW waves of a workgroup (4 by default, 2 when the plan's autotuner finds
+// that faster) share ONE 16-column tile and take every NW-th active operator,
 // reading operator fragments straight from L2 (no barriers in the main
 // loop, four times more waves in flight); their partial tiles are summed
 // through LDS in a fixed order at the end.
-template <class TI, class TO, class TM, int RB, int S, bool SPLIT, bool ACCUM>
-__global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const TM *__restrict__ Ahi,
+template <class TI, class TO, class TM, int RB, int S, bool SPLIT, bool ACCUM, int NW = 4>
+__global__ void __launch_bounds__(64 * NW) k_translate_split(TranslateArgs a, const TM *__restrict__ Ahi,
                                                          const TM *__restrict__ Alo,
                                                          const TI *__restrict__ in, TO *__restrict__ out) {
     typedef Mfma<TM> M;
     constexpr int AE = RB * S * 64;
-    __shared__ double red[3][RB * 4][64];
+    static_assert(NW == 2 || NW == 4, "two or four waves per tile");
+    constexpr int NT = 64 * NW;
+    __shared__ double red[NW - 1][RB * 4][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cl = lane & 15, g = lane >> 4;
     const int tile = a.tile_order ? a.tile_order[blockIdx.x] : (int)blockIdx.x;
@@ -389,26 +392,26 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
         for (int c0 = 0; c0 < nt; c0 += 64) {
             const int nc = min(64, nt - c0);
             __syncthreads();
-            for (int i = tid; i < nc; i += 256) s_ops[i] = a.tile_ops[e0 + c0 + i];
+            for (int i = tid; i < nc; i += NT) s_ops[i] = a.tile_ops[e0 + c0 + i];
             __syncthreads();
-            for (int i = tid; i < nc * 16; i += 256) {
+            for (int i = tid; i < nc * 16; i += NT) {
                 const int oi = i >> 4, c = i & 15, cc = tile * 16 + c;
                 s_src[oi][c] = cc < a.ncols ? a.slots[(int64_t)a.cols_box[cc / a.nbatch] * a.nops + s_ops[oi]] : -1;
             }
             __syncthreads();
-            for (int e = wave; e < nc; e += 4) product(s_ops[e], s_src[e][cl]);
+            for (int e = wave; e < nc; e += NW) product(s_ops[e], s_src[e][cl]);
         }
     } else {
         int it = 0;  // index among the tile's active operators
         for (int o = 0; o < a.nops; ++o) {
             const int src = valid ? a.slots[(int64_t)box * a.nops + o] : -1;
             if (__ballot(src >= 0) == 0ull) continue;
-            const bool mine = (it & 3) == wave;
+            const bool mine = it % NW == wave;
             ++it;
             if (mine) product(o, src);
         }
     }
-    // fixed-order sum of the four partial tiles: wave 0 + 1 + 2 + 3
+    // fixed-order sum of the partial tiles: wave 0 + 1 + ... + NW-1
     if (wave > 0) {
 #pragma unroll
         for (int r = 0; r < RB; ++r)
@@ -421,9 +424,11 @@ __global__ void __launch_bounds__(256) k_translate_split(TranslateArgs a, const 
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            vals[r][i] = (((double)acc[r][i] + red[0][r * 4 + i][lane]) + red[1][r * 4 + i][lane]) +
-                         red[2][r * 4 + i][lane];
+        for (int i = 0; i < 4; ++i) {
+            vals[r][i] = (double)acc[r][i];
+#pragma unroll
+            for (int v = 0; v < NW - 1; ++v) vals[r][i] += red[v][r * 4 + i][lane];
+        }
     if (a.logrow >= 0) {
         const int rb2 = a.logrow >> 4, r16 = a.logrow & 15;
         const int i2 = M::item_of(r16), g2 = M::group_of(r16);

@@ -21,6 +21,7 @@ VP_OK, VP_EINVAL, VP_ENOMEM, VP_EDEVICE, VP_EUNSUPPORTED, VP_EINTERNAL = range(6
 VP_FP64, VP_FP32_BULK = 0, 1
 VP_FLAG_AUTOTUNE = 1
 VP_FLAG_ONE_STREAM = 2
+VP_FLAG_AUTOTUNE_LEAF = 8
 KERNELS = {"laplace": 0, "yukawa": 1}
 M2L_MODES = {"auto": 0, "fp64": 1, "fp32": 2, "split": 3, "fp64_scaled": 4, "fp32_scaled": 5}
 P2P_MODES = {"auto": 0, "pairwise": 1, "tables": 2}
@@ -50,8 +51,8 @@ class Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("max_leaf", ctypes.c_int32), ("nbatch", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("m2l_mode", ctypes.c_int32), ("p2p_mode", ctypes.c_int32),
                 ("max_level", ctypes.c_int32), ("flags", ctypes.c_int32), ("root", ctypes.c_double * 3),
-                ("stream", ctypes.c_void_p), ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("lam", ctypes.c_double)]
+                ("stream", ctypes.c_void_p), ("kernel", ctypes.c_int32), ("m2l_waves", ctypes.c_int32),
+                ("lam", ctypes.c_double), ("table_waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Oversampling(ctypes.Structure):
@@ -75,7 +76,9 @@ class PlanInfo(ctypes.Structure):
                 ("root", ctypes.c_double * 3), ("table_pairs", ctypes.c_int64),
                 ("noalloc_bytes", ctypes.c_int64), ("n_in", ctypes.c_int64),
                 ("os_p", ctypes.c_int32), ("os_q", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32), ("lam", ctypes.c_double)]
+                ("reserved2", ctypes.c_int32), ("lam", ctypes.c_double), ("tuned", ctypes.c_int32),
+                ("m2l_waves", ctypes.c_int32), ("table_waves", ctypes.c_int32), ("one_stream", ctypes.c_int32),
+                ("tune_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -168,7 +171,8 @@ class Plan:
                  max_leaf: int = 64, nbatch: int = 1, precision: str = "fp64", m2l_mode: str = "auto",
                  p2p_mode: str = "auto", root=None, max_level: int = 0, autotune: bool = False,
                  one_stream: bool = False, oversampling: Optional[dict] = None, kernel: str = "laplace",
-                 lam: float = 0.0, stream=None):
+                 lam: float = 0.0, autotune_leaf: bool = False, m2l_waves: int = 0, table_waves: int = 0,
+                 stream=None):
         lib = load_library()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -190,7 +194,10 @@ class Plan:
         o.m2l_mode = M2L_MODES[m2l_mode]
         o.p2p_mode = P2P_MODES[p2p_mode]
         o.max_level = max_level
-        o.flags = (VP_FLAG_AUTOTUNE if autotune else 0) | (VP_FLAG_ONE_STREAM if one_stream else 0)
+        o.flags = ((VP_FLAG_AUTOTUNE if autotune else 0) | (VP_FLAG_ONE_STREAM if one_stream else 0)
+                   | (VP_FLAG_AUTOTUNE_LEAF if autotune_leaf else 0))
+        o.m2l_waves = m2l_waves
+        o.table_waves = table_waves
         if root is not None:
             o.root[0], o.root[1], o.root[2] = root
         o.kernel = KERNELS[kernel]

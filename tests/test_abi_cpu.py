@@ -28,7 +28,7 @@ def test_options_struct_layout():
     vp, lib = _lib()
     o = vp.default_options()
     assert (o.order, o.max_leaf, o.nbatch, o.precision) == (30, 64, 1, 0)
-    assert ctypes.sizeof(vp.Options) == 8 * 4 + 3 * 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(vp.Options) == 8 * 4 + 3 * 8 + 8 + 4 + 4 + 8 + 4 + 4
     assert (o.kernel, o.lam) == (0, 0.0)
 
 
@@ -45,7 +45,7 @@ def _plan(lib, vp, x, y, w, n, tx=None, ty=None, m=None, rowptr=None, col=None, 
 
 @pytest.mark.parametrize("case", ["n0", "nan", "m_mismatch", "rowptr0", "rowptr_dec", "col_range",
                                   "order", "nbatch", "leaf", "fp32_mode", "flags", "root_node",
-                                  "root_target", "kernel", "lambda0", "lambda_nan"])
+                                  "root_target", "kernel", "lambda0", "lambda_nan", "tile_waves"])
 def test_plan_rejects_invalid(case):
     vp, lib = _lib()
     x = np.linspace(0, 1, 8)
@@ -78,6 +78,8 @@ def test_plan_rejects_invalid(case):
         kw["flags"] = 4  # unknown bit
     elif case == "kernel":
         kw["kernel"] = 2
+    elif case == "tile_waves":
+        kw["m2l_waves"] = 3
     elif case == "lambda0":
         kw["kernel"], kw["lam"] = 1, 0.0
     elif case == "lambda_nan":

@@ -276,18 +276,73 @@ def test_every_order_matches_truncated_fmm_oracle(c0, order):
 
 @pytest.mark.parametrize("precision,order,tol", [("fp64", 30, TOL64), ("fp32", 14, TOL32)])
 def test_autotuned_m2l(c0, precision, order, tol):
-    """The plan-time M2L autotuner picks one of the valid kernels for the
-    precision, and the evaluation still meets the oracle tolerance."""
+    """The plan-time autotuner picks a valid M2L kernel form, waves per tile
+    and stream mode for the precision; the evaluation still meets the oracle
+    tolerance, and a second plan of the same geometry takes the cached
+    choices without timing."""
     vp = _vp()
-    plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=order, precision=precision,
-                   autotune=True, root=c0.root)
-    mode = plan.info()["m2l_mode"]
-    assert mode in ((4, 1) if precision == "fp64" else (5, 2, 4)), mode
-    u = _host(plan.eval(_dev(c0.f)))
     ref = direct.evaluate(c0.x, c0.y, c0.w, c0.f, c0.rowptr, c0.col, c0.val)
-    err = relinf(u, ref)
-    print(f"autotuned {precision}: m2l mode {mode}, rel_inf={err:.3e}")
-    assert err <= tol
+    infos = []
+    for _ in range(2):
+        plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=order,
+                       precision=precision, autotune=True, root=c0.root)
+        info = plan.info()
+        infos.append(info)
+        assert info["m2l_mode"] in ((4, 1) if precision == "fp64" else (5, 2, 3, 4)), info["m2l_mode"]
+        assert info["m2l_waves"] in (2, 4) and info["table_waves"] in (2, 4) and info["one_stream"] in (0, 1)
+        u = _host(plan.eval(_dev(c0.f)))
+        err = relinf(u, ref)
+        print(f"autotuned {precision}: m2l mode {info['m2l_mode']}, waves {info['m2l_waves']}/"
+              f"{info['table_waves']}, one stream {info['one_stream']}, tuned {info['tuned']} "
+              f"({info['tune_ms']:.0f} ms), rel_inf={err:.3e}")
+        assert err <= tol
+        plan.close()
+    assert infos[1]["tuned"] == 2
+    for k in ("m2l_mode", "m2l_waves", "table_waves", "one_stream"):
+        assert infos[0][k] == infos[1][k]
+
+
+@pytest.mark.parametrize("precision,order,tol", [("fp64", 30, TOL64), ("fp32", 14, TOL32)])
+def test_two_waves_per_tile(c0, precision, order, tol):
+    """The two-wave variants of the M2L and near-table kernels (one of the
+    autotuner's choices) against the oracle and the four-wave default."""
+    vp = _vp()
+    ref = direct.evaluate(c0.x, c0.y, c0.w, c0.f, c0.rowptr, c0.col, c0.val)
+    out = {}
+    for waves in (4, 2):
+        for mode in (("fp64_scaled", "fp64") if precision == "fp64" else ("fp32_scaled", "split")):
+            plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=order,
+                           precision=precision, m2l_mode=mode, m2l_waves=waves, table_waves=waves, root=c0.root)
+            assert plan.info()["m2l_waves"] == waves and plan.info()["table_waves"] == waves
+            out[(waves, mode)] = u = _host(plan.eval(_dev(c0.f)))
+            err = relinf(u, ref)
+            print(f"{precision} {mode} {waves} waves: rel_inf={err:.3e}")
+            assert err <= tol
+            plan.close()
+    for mode in {m for _, m in out}:
+        assert relinf(out[(2, mode)], out[(4, mode)]) <= (1e-14 if precision == "fp64" else 1e-7)
+
+
+def test_autotuned_leaf_size(c0):
+    """VP_FLAG_AUTOTUNE_LEAF builds the plan with 64- and 16-point leaves and
+    keeps the faster one; either meets the oracle tolerance."""
+    vp = _vp()
+    plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=30, autotune=True,
+                   autotune_leaf=True, root=c0.root)
+    info = plan.info()
+    assert info["max_leaf"] in (64, 16) and info["tuned"] in (1, 2)
+    u = _host(plan.eval(_dev(c0.f)))
+    err = relinf(u, direct.evaluate(c0.x, c0.y, c0.w, c0.f, c0.rowptr, c0.col, c0.val))
+    print(f"leaf autotune: max_leaf {info['max_leaf']}, rel_inf={err:.3e}")
+    assert err <= TOL64
+    plan.close()
+    # 16-point leaves forced: the 8x8 box rule splits into congruent 4x4 quadrants
+    plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=30, max_leaf=16, root=c0.root)
+    info = plan.info()
+    u = _host(plan.eval(_dev(c0.f)))
+    err = relinf(u, direct.evaluate(c0.x, c0.y, c0.w, c0.f, c0.rowptr, c0.col, c0.val))
+    print(f"16-point leaves: p2p mode {info['p2p_mode_used']}, table leaves {info['table_leaves']}, rel_inf={err:.3e}")
+    assert err <= TOL64
     plan.close()
 
 
