@@ -1294,6 +1294,32 @@ void build_cells(vp_plan_s *P, bool transposed) {
     int64_t *&cvb = transposed ? P->cell_vbT : P->cell_vb;
     cvb = P->mem.alloc<int64_t>(nc);
     VP_HIP(hipMemcpyAsync(cvb, vbh.data(), 8 * (size_t)nc, hipMemcpyHostToDevice, s));
+    // every cell a 64 x 64 block reading one shared block (uniform grids: the
+    // box corrections of one box size): C is one fixed operator applied to
+    // every (cell, density) column, the fixed-operator kernel's case
+    {
+        bool one = nc > 0;
+        for (int k = 0; one && k < nc; ++k)
+            one = row0[k + 1] - row0[k] == 64 && rp[row0[k] + 1] - rp[row0[k]] == 64 && vbh[k] == vbh[0];
+        double *&op = transposed ? P->corr_opT : P->corr_op;
+        op = nullptr;
+        if (one) {
+            std::vector<double> A(64 * 64), F(64 * 64);
+            VP_HIP(hipMemcpyAsync(A.data(), vv + vbh[0], 8 * A.size(), hipMemcpyDeviceToHost, s));
+            VP_HIP(hipStreamSynchronize(s));
+            vp_to_frag(A.data(), 64, 64, 64, F.data());  // rows = cell rows, cols = the cell's column run
+            op = P->mem.alloc<double>(F.size());
+            VP_HIP(hipMemcpyAsync(op, F.data(), 8 * F.size(), hipMemcpyHostToDevice, s));
+            if (!P->cell_iota || (int)P->n_cell_iota < nc) {
+                std::vector<int32_t> io(nc);
+                for (int k = 0; k < nc; ++k) io[k] = k;
+                P->cell_iota = P->mem.alloc<int32_t>(nc);
+                P->n_cell_iota = nc;
+                VP_HIP(hipMemcpyAsync(P->cell_iota, io.data(), 4 * (size_t)nc, hipMemcpyHostToDevice, s));
+            }
+            VP_HIP(hipStreamSynchronize(s));  // A, F and io leave scope
+        }
+    }
     // one density: 64-column cells reading one block, at least 8 of them,
     // go to k_corr_group in groups of 16; the cell kernel skips them (-1)
     std::map<std::pair<int64_t, int>, std::vector<int32_t>> bykey;
@@ -2538,9 +2564,17 @@ static void correction_apply(vp_plan_s *P, const double *f, double *u, bool adjo
     int64_t blocks = (nrows * 16 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     const int ncell = adjoint ? P->ncellT : P->ncell;
+    const double *cop = adjoint ? P->corr_opT : P->corr_op;
     P->stage_begin(VP_STAGE_CORR);
     if (P->nnz == 0) {
         fill_f64(u, 0.0, (int64_t)P->nbatch * nrows, P->stream);
+    } else if (ncell > 0 && cop) {
+        // one shared 64 x 64 block: u[b][row0 + r] = sum_j V[r][j] f[b][col0 + j] per cell
+        const int32_t *crow = adjoint ? P->cell_rowT : P->cell_row;
+        const int32_t *ccol = adjoint ? P->cell_colT : P->cell_col;
+        launch_fixed_apply<double, double, double, 4, 16, false>(P, P->cell_iota, ncell * P->nbatch,
+                                                                 ColAddr{flen, 0, ccol}, ColAddr{nrows, 0, crow}, 64,
+                                                                 cop, f, u);
     } else if (ncell > 0) {
         const int32_t *crow = adjoint ? P->cell_rowT : P->cell_row;
         const int32_t *ccol = adjoint ? P->cell_colT : P->cell_col;

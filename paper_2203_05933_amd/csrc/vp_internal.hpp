@@ -337,6 +337,10 @@ struct vp_plan_s {
     int64_t *grp_vb = nullptr, *grp_vbT = nullptr, *cell_vbg = nullptr, *cell_vbgT = nullptr;
     int ngrp = 0, ngrpT = 0;
     int64_t corr_values_read = 0;   // values the forward apply reads from memory
+    // every cell one shared 64 x 64 block: that block in A-fragment order (else null)
+    double *corr_op = nullptr, *corr_opT = nullptr;
+    int32_t *cell_iota = nullptr;   // 0, 1, 2, ... (the cells as the fixed-operator kernel's columns)
+    int n_cell_iota = 0;
 
     vp::Tree tree;
     vp::Operators ops;
