@@ -2079,8 +2079,11 @@ static void launch_fixed_apply(vp_plan_s *P, const int32_t *cols_box, int ncols,
                                FinishArgs fin = FinishArgs()) {
     if (ncols <= 0) return;
     const int ntiles = (ncols + 15) / 16;
-    const unsigned grid = (unsigned)std::min((ntiles + 3) / 4, 512);
-    hipLaunchKernelGGL((k_fixed_apply<TI, TO, TM, RB, S, ACCUM, FIN>), dim3(grid), dim3(256), 0, P->stream,
+    // the operator in LDS when it fits in 32 KB (up to five workgroups per
+    // compute unit), else in registers
+    constexpr bool ALDS = (size_t)RB * S * 64 * sizeof(TM) <= 32768;
+    const unsigned grid = (unsigned)std::min((ntiles + 3) / 4, ALDS ? 1280 : 512);
+    hipLaunchKernelGGL((k_fixed_apply<TI, TO, TM, RB, S, ACCUM, FIN, ALDS>), dim3(grid), dim3(256), 0, P->stream,
                        cols_box, ncols, P->nbatch, ia, oa, nrows_out, A, in, out, addflag, fin);
     VP_LAUNCH_CHECK();
 }

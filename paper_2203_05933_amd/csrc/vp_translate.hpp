@@ -250,20 +250,31 @@ struct FinishArgs {
     double *u = nullptr;
 };
 
-template <class TI, class TO, class TM, int RB, int S, bool ACCUM, bool FIN>
-__global__ void __launch_bounds__(256) k_fixed_apply(const int32_t *__restrict__ cols_box, int ncols, int nbatch,
-                                                     ColAddr ia, ColAddr oa, int nrows_out,
-                                                     const TM *__restrict__ A, const TI *__restrict__ in,
-                                                     TO *__restrict__ out, const int32_t *__restrict__ addflag,
-                                                     FinishArgs fin) {
+// ALDS: the operator sits in LDS, copied once per workgroup, instead of in
+// every wave's registers -- fewer registers, more waves per SIMD and so more
+// loads in flight (the loads, not the products, bound these launches).
+template <class TI, class TO, class TM, int RB, int S, bool ACCUM, bool FIN, bool ALDS>
+__global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t *__restrict__ cols_box, int ncols,
+                                                                   int nbatch, ColAddr ia, ColAddr oa, int nrows_out,
+                                                                   const TM *__restrict__ A,
+                                                                   const TI *__restrict__ in, TO *__restrict__ out,
+                                                                   const int32_t *__restrict__ addflag,
+                                                                   FinishArgs fin) {
     typedef Mfma<TM> M;
+    constexpr int AE = RB * S * 64;
     const int lane = threadIdx.x & 63;
     const int cl = lane & 15, g = lane >> 4;
-    TM av[RB][S];
+    __shared__ TM sA[ALDS ? AE : 1];
+    TM av[ALDS ? 1 : RB][ALDS ? 1 : S];
+    if constexpr (ALDS) {
+        for (int e = threadIdx.x; e < AE; e += blockDim.x) sA[e] = A[e];
+        __syncthreads();
+    } else {
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+        for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int s = 0; s < S; ++s) av[r][s] = A[(r * S + s) * 64 + lane];
+            for (int s = 0; s < S; ++s) av[r][s] = A[(r * S + s) * 64 + lane];
+    }
     const int ntiles = (ncols + 15) / 16;
     const int tstride = gridDim.x * (blockDim.x >> 6);
     auto load = [&](int t, TM *bv) {
@@ -280,10 +291,21 @@ __global__ void __launch_bounds__(256) k_fixed_apply(const int32_t *__restrict__
         load(min(t + tstride, ntiles - 1), bnext);
         typename M::acc_t accs[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            accs[r] = M::zero();
+        for (int r = 0; r < RB; ++r) accs[r] = M::zero();
+        // per k-step the RB operator fragments, then the RB products (with the
+        // operator in LDS a scheduling barrier per step keeps the compiler from
+        // loading all of it into registers ahead of the products)
 #pragma unroll
-            for (int s = 0; s < S; ++s) accs[r] = M::op(bcur[s], av[r][s], accs[r]);
+        for (int s = 0; s < S; ++s) {
+            TM a_s[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                if constexpr (ALDS) a_s[r] = sA[(r * S + s) * 64 + lane];
+                else a_s[r] = av[r][s];
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) accs[r] = M::op(bcur[s], a_s[r], accs[r]);
+            if constexpr (ALDS) __builtin_amdgcn_sched_barrier(0);
         }
         // element i of a lane: output row r * 16 + cl of tile column M::row(i, g)
 #pragma unroll
