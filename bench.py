@@ -54,22 +54,51 @@ C3_NAME = "uniform256x256_gl8_b16"
 # HBM bytes per launch of the headline's kernels, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, then WRITE_SIZE) of this script, each scaled by what the
 # counter reads for a plain device copy of known size in the same run.  Valid
-# only for the kernel sources they were taken on: the digest covers every
-# file of the library's source directory, and any change there turns traffic
-# into null.
-TRAFFIC_DIGEST = None
+# only for the kernel sources they were taken on: each stage carries a digest
+# of the sources that define its kernel, its launch and its schedule (whole
+# headers, and the named functions of the .hip files), and a change there
+# turns that stage's traffic into null.
 TRAFFIC_WORKLOAD = C3_NAME
-TRAFFIC = {}  # stage -> (read bytes, written bytes) per launch, FP64 p = 30, 16 densities
+TRAFFIC = {}  # stage -> (read bytes, written bytes, digest) per launch, FP64 p = 30, 16 densities
+CSRC = os.path.join(ROOT, "paper_2203_05933_amd", "csrc")
+STAGE_SOURCES = {
+    "m2l": (["vp_m2l_scaled.hpp", "vp_translate.hpp", "vp_internal.hpp"],
+            {"vp_fmm.hip": ["build_schedules", "launch_m2l", "m2l_scaled", "launch_m2l_scaled"]}),
+    "tables": (["vp_translate.hpp", "vp_internal.hpp", "vp_near.hip"],
+               {"vp_fmm.hip": ["launch_tables", "run_tables"]}),
+    "corr": (["vp_translate.hpp", "vp_internal.hpp"],
+             {"vp_fmm.hip": ["correction_apply", "launch_fixed_apply", "build_cells"]}),
+}
 
 
-def source_digest():
-    import glob
+def _function_text(src, name):
+    """The text of the first definition of function `name` in src (signature
+    to the matching closing brace)."""
+    import re
+    m = re.search(r"\n[^\n;]*\b" + re.escape(name) + r"\([^;{]*\)\s*\{", src)
+    if not m:
+        raise KeyError(name)
+    i = src.index("{", m.end() - 1)
+    depth = 0
+    for j in range(i, len(src)):
+        depth += {"{": 1, "}": -1}.get(src[j], 0)
+        if depth == 0:
+            return src[m.start():j + 1]
+    raise KeyError(name)
+
+
+def stage_digest(stage):
     import hashlib
+    files, funcs = STAGE_SOURCES[stage]
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_05933_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    for f, names in funcs.items():
+        with open(os.path.join(CSRC, f)) as fh:
+            src = fh.read()
+        for n in names:
+            h.update((f + ":" + n).encode() + _function_text(src, n).encode())
     return h.hexdigest()
 
 
@@ -77,9 +106,9 @@ def measured_traffic(stage, workload_name, order):
     """Counter-measured HBM bytes per launch, or None when they do not apply."""
     if stage not in TRAFFIC or workload_name != TRAFFIC_WORKLOAD or order != 30:
         return None
-    if source_digest() != TRAFFIC_DIGEST:
+    r, w, digest = TRAFFIC[stage]
+    if stage_digest(stage) != digest:
         return None
-    r, w = TRAFFIC[stage]
     return r + w
 
 

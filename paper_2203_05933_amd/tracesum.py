@@ -4,10 +4,13 @@ rocprofv3's own --stats summary groups dispatches by kernel name only; one
 kernel of this library runs with different grids (per tree level, per
 workload), so this tool groups them by (kernel name, grid size) as well:
 
-  python -m paper_2203_05933_amd.tracesum trace <run_kernel_trace.csv> [--match REGEX]
+  python -m paper_2203_05933_amd.tracesum trace <run_kernel_trace.csv> [--match REGEX] [--last N]
       dispatches, average / median / min / max duration (microseconds)
-  python -m paper_2203_05933_amd.tracesum pmc <run_counter_collection.csv> [--match REGEX]
+  python -m paper_2203_05933_amd.tracesum pmc <run_counter_collection.csv> [--match REGEX] [--last N]
       median counter value per dispatch, per counter
+
+--last N keeps only the last N dispatches of every launch shape (in
+dispatch order), e.g. the event-timed loop that ends a benchmark pass.
 
 Prints a markdown table on stdout.  Reads text files only.
 """
@@ -45,16 +48,20 @@ def _short(name):
     return name.replace("vp::", "")
 
 
-def trace(path, match=None):
+def trace(path, match=None, last=None):
     groups = defaultdict(list)
     with open(path, newline="") as fh:
-        for row in csv.DictReader(fh):
-            name = _short(_col(row, "Kernel_Name"))
-            if match and not re.search(match, name):
-                continue
-            grid = int(_col(row, "Grid_Size_X", "Grid_Size"))
-            dur = (int(_col(row, "End_Timestamp")) - int(_col(row, "Start_Timestamp"))) / 1e3
-            groups[(name, grid)].append(dur)
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: int(_col(r, "Dispatch_Id")))
+    for row in rows:
+        name = _short(_col(row, "Kernel_Name"))
+        if match and not re.search(match, name):
+            continue
+        grid = int(_col(row, "Grid_Size_X", "Grid_Size"))
+        dur = (int(_col(row, "End_Timestamp")) - int(_col(row, "Start_Timestamp"))) / 1e3
+        groups[(name, grid)].append(dur)
+    if last:
+        groups = {k: v[-last:] for k, v in groups.items()}
     rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
     print("| kernel | grid | dispatches | avg us | median us | min us | max us | total us |")
     print("|---|---|---|---|---|---|---|---|")
@@ -63,15 +70,19 @@ def trace(path, match=None):
               f"{min(d):.1f} | {max(d):.1f} | {sum(d):.1f} |")
 
 
-def pmc(path, match=None):
+def pmc(path, match=None, last=None):
     groups = defaultdict(lambda: defaultdict(list))
     with open(path, newline="") as fh:
-        for row in csv.DictReader(fh):
-            name = _short(_col(row, "Kernel_Name"))
-            if match and not re.search(match, name):
-                continue
-            grid = int(_col(row, "Grid_Size", "Grid_Size_X"))
-            groups[(name, grid)][_col(row, "Counter_Name")].append(float(_col(row, "Counter_Value")))
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: int(_col(r, "Dispatch_Id")))
+    for row in rows:
+        name = _short(_col(row, "Kernel_Name"))
+        if match and not re.search(match, name):
+            continue
+        grid = int(_col(row, "Grid_Size", "Grid_Size_X"))
+        groups[(name, grid)][_col(row, "Counter_Name")].append(float(_col(row, "Counter_Value")))
+    if last:
+        groups = {k: {c: v[-last:] for c, v in g.items()} for k, g in groups.items()}
     counters = sorted({c for g in groups.values() for c in g})
     print("| kernel | grid | dispatches | " + " | ".join(f"{c} (median)" for c in counters) + " |")
     print("|---|---|---|" + "---|" * len(counters))
@@ -86,8 +97,9 @@ def main(argv=None):
     ap.add_argument("kind", choices=["trace", "pmc"])
     ap.add_argument("csv")
     ap.add_argument("--match", default=None, help="keep kernels whose short name matches this regex")
+    ap.add_argument("--last", type=int, default=None, help="keep the last N dispatches of each launch shape")
     a = ap.parse_args(argv)
-    (trace if a.kind == "trace" else pmc)(a.csv, a.match)
+    (trace if a.kind == "trace" else pmc)(a.csv, a.match, a.last)
 
 
 if __name__ == "__main__":
