@@ -1428,7 +1428,27 @@ std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr) {
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
         return tile_ptr[x + 1] - tile_ptr[x] > tile_ptr[y + 1] - tile_ptr[y];
     });
-    return ord;
+    // The chip deals workgroup b to XCD b % 8, and each XCD has its own L2.
+    // Dealt one by one, consecutive tiles (neighbouring boxes, which share
+    // most of their source columns) land on eight different L2s and every
+    // source column is fetched past L2 once per target.  Instead each XCD
+    // takes runs of XCD_RUN consecutive tiles of the order above: round r
+    // covers positions [8 r XCD_RUN, 8 (r+1) XCD_RUN), XCD x its x-th run,
+    // so the order's heaviest-first progress is kept round by round.  The
+    // last, incomplete round keeps the plain order.
+    constexpr int XCDS = 8, XCD_RUN = 256;
+    const int full = nt / (XCDS * XCD_RUN) * (XCDS * XCD_RUN);
+    std::vector<int32_t> launch(ord.size());
+    for (int p = 0; p < nt; ++p) {
+        int b = p;
+        if (p < full) {
+            const int run = p / XCD_RUN, x = run % XCDS, round = run / XCDS;
+            const int j = round * XCD_RUN + p % XCD_RUN;  // position in XCD x's sequence
+            b = j * XCDS + x;
+        }
+        launch[b] = ord[p];
+    }
+    return launch;
 }
 
 void build_schedules(vp_plan_s *P) {
@@ -1581,26 +1601,32 @@ void build_schedules(vp_plan_s *P) {
     P->vsplit_s = up(vsplit_s);
     P->vsplit_t = up(vsplit_t);
     VP_HIP(hipMemcpyAsync(T.v_slot, vslot.data(), 4 * vslot.size(), hipMemcpyHostToDevice, s));
-    // M2L launches (levels from the split level on; levels 2 .. split - 1):
-    // columns grouped by child class (boxes of one class share their 27
-    // V-list offsets in a uniform region), within a class ordered by their
-    // set of offsets (stable, so equal sets keep their tree order), so that
-    // 16-column tiles share their offsets wherever the tree is not uniform
+    // M2L launches (levels from the split level on; levels 2 .. split - 1).
+    // With fewer than 16 densities a tile holds several boxes: columns are
+    // then grouped by child class (boxes of one class share their 27 V-list
+    // offsets in a uniform region), within a class ordered by their set of
+    // offsets (stable, so equal sets keep their tree order), so that
+    // 16-column tiles share their offsets wherever the tree is not uniform.
+    // A tile of one box has nothing to share: the boxes keep their tree
+    // (Morton) order, in which neighbouring tiles share source columns.
     P->m2l_translations = P->m2l_tile_ops = 0;
+    const bool group_class = P->nbatch < 16;
     for (int part = 0; part < 2; ++part) {
         M2LSched &S = P->m2l[part];
         std::vector<int32_t> m2l;
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < (group_class ? 4 : 1); ++c)
             for (int b = 0; b < nbox; ++b)
-                if (lev[b] >= 2 && cls(b) == c && (lev[b] >= P->split_level) == (part == 0)) m2l.push_back(b);
+                if (lev[b] >= 2 && (!group_class || cls(b) == c) && (lev[b] >= P->split_level) == (part == 0))
+                    m2l.push_back(b);
         std::vector<uint64_t> omask(nbox, 0);
         for (int b : m2l)
             for (int o = 0; o < NOFF; ++o)
                 if (vslot[(size_t)b * NOFF + o] >= 0) omask[b] |= 1ull << o;
-        std::stable_sort(m2l.begin(), m2l.end(), [&](int x, int y) {
-            const int cx = cls(x), cy = cls(y);
-            return cx != cy ? cx < cy : omask[x] < omask[y];
-        });
+        if (group_class)
+            std::stable_sort(m2l.begin(), m2l.end(), [&](int x, int y) {
+                const int cx = cls(x), cy = cls(y);
+                return cx != cy ? cx < cy : omask[x] < omask[y];
+            });
         // offsets present in each 16-column tile (columns = box x density)
         const int64_t ncols = (int64_t)m2l.size() * P->nbatch;
         const int64_t ntiles = (ncols + 15) / 16;
