@@ -128,8 +128,11 @@ typedef struct {
     int32_t m2l_waves; /* waves per 16-column tile of the M2L kernels: 2 or 4;
                           0 = 4, or the autotuner's choice */
     double lambda;     /* VP_KERNEL_YUKAWA: lambda > 0 (Section 5 uses lambda^2 = 100) */
-    int32_t table_waves; /* waves per tile of the near-table kernel: 2 or 4; 0 = 4,
-                            or the autotuner's choice */
+    int32_t table_waves; /* waves per 16-column tile of the near-table kernel:
+                            2 or 4, or 1 = one wave over two tiles (each
+                            operator fragment loaded once for both; patterns
+                            of more than 64 points take 2 instead); 0 = 4, or
+                            the autotuner's choice */
     int32_t reserved;
 } vp_options;
 

@@ -2073,7 +2073,20 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     if (a.ncols <= 0) return;
     // every table leaf's sums are stored by its one tile (the other leaves are zeroed)
     const unsigned blocks = (unsigned)((a.ncols + 15) / 16);
-    if (P->table_nw == 2)
+    bool done = false;
+    if constexpr (RB <= 4) {
+        // one wave over two tiles (larger patterns would spill: the two-wave form serves them)
+        if (P->table_nw == 1) {
+            a.tile_ptr = N.tile2_ptr;
+            a.tile_ops = N.tile2_ops;
+            a.tile_order = N.tile2_order;
+            hipLaunchKernelGGL((k_tables_ct<RB, S, 2>), dim3((unsigned)((a.ncols + 31) / 32)), dim3(64), 0,
+                               P->stream, a, N.K, P->q, P->acc);
+            done = true;
+        }
+    }
+    if (done) {
+    } else if (P->table_nw <= 2)
         hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, false, 2>), dim3(blocks),
                            dim3(128), 0, P->stream, a, N.K, (const double *)nullptr, P->q, P->acc);
     else
@@ -2707,8 +2720,8 @@ float time_forward(vp_plan_s *P, const double *f, double *u, int reps) {
 //   M2L form       FP64: scaled, per-offset products;  FP32-bulk: scaled FP32,
 //                  per-offset FP32, split hi/lo FP32, scaled FP64 (every one
 //                  meets the precision's accuracy target)
-//   M2L waves per 16-column tile (4, 2), near-table waves per tile (4, 2),
-//   streams (three, one).
+//   M2L waves per 16-column tile (4, 2), near-table waves per tile (4, 2, or
+//   one wave over two tiles), streams (three, one).
 // Returns the best time (ms).
 float autotune(vp_plan_s *P) {
     TempArena tmp;
@@ -2733,7 +2746,7 @@ float autotune(vp_plan_s *P) {
     if (P->fp32) knob(P->m2l_mode, {VP_M2L_FP32_SCALED, VP_M2L_FP32_MFMA, VP_M2L_FP32_SPLIT, VP_M2L_FP64_SCALED});
     else knob(P->m2l_mode, {VP_M2L_FP64_SCALED, VP_M2L_FP64_MFMA});
     if (P->opt.m2l_waves == 0) knob(P->m2l_nw, {4, 2});
-    if (P->opt.table_waves == 0 && P->near.active) knob(P->table_nw, {4, 2});
+    if (P->opt.table_waves == 0 && P->near.active) knob(P->table_nw, {4, 2, 1});
     int one = P->one_stream ? 1 : 0;
     if (!(P->opt.flags & VP_FLAG_ONE_STREAM)) {
         bool &fld = P->one_stream;

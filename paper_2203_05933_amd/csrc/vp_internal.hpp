@@ -207,6 +207,9 @@ struct NearTables {
     int32_t *tile_ptr = nullptr;      // slots present per 16-column tile of table columns
     int32_t *tile_ops = nullptr;
     int32_t *tile_order = nullptr;    // tiles by decreasing operator count
+    int32_t *tile2_ptr = nullptr;     // the same over 32-column groups (one wave over two tiles)
+    int32_t *tile2_ops = nullptr;
+    int32_t *tile2_order = nullptr;
     int64_t table_tile_ops = 0;
     double *K = nullptr;              // [tab level][41] near matrices, A-fragment order
     int32_t *pair_uptr = nullptr;     // U lists minus the table-served entries
@@ -286,7 +289,7 @@ struct vp_plan_s {
     bool fp32 = false;
     int m2l_mode = VP_M2L_FP64_MFMA;
     int m2l_nw = 4;           // waves per 16-column tile of the M2L kernels (4 or 2; the autotuner may pick 2)
-    int table_nw = 4;         // waves per tile of the near-table launch
+    int table_nw = 4;         // waves per tile of the near-table launch (1: one wave over two tiles)
     int tuned = 0;            // 0: defaults; 1: chosen by timing at plan time; 2: from the tuning cache
     double tune_ms = 0.0;     // plan time spent tuning
     bool one_stream = false;  // no second stream: every kernel on the plan's stream

@@ -371,27 +371,31 @@ void build_near_tables(vp_plan_s *P) {
             for (int o = 0; o < NTOPS; ++o) wide[(size_t)b * wrow + (size_t)li * NTOPS + o] = tslot[(size_t)b * NTOPS + o];
         }
         N.tab_slot = upload(P, wide);
-        // operators present per 16-column tile of (table leaf, density) columns
+        // operators present per group of W (table leaf, density) columns:
+        // 16-column tiles, and 32-column pairs of tiles for the one-wave form
         const int64_t ncols = (int64_t)tcols.size() * P->nbatch;
-        std::vector<int32_t> tptr(1, 0), tops;
         std::vector<char> seen(wrow);
-        for (int64_t t = 0; t * 16 < ncols; ++t) {
-            std::fill(seen.begin(), seen.end(), 0);
-            for (int64_t c = 16 * t; c < std::min(ncols, 16 * t + 16); ++c) {
-                const int b = tcols[c / P->nbatch];
+        auto groups = [&](int64_t W, int32_t *&dptr, int32_t *&dops, int32_t *&dorder) {
+            std::vector<int32_t> tptr(1, 0), tops;
+            for (int64_t t = 0; t * W < ncols; ++t) {
+                std::fill(seen.begin(), seen.end(), 0);
+                for (int64_t c = W * t; c < std::min(ncols, W * t + W); ++c) {
+                    const int b = tcols[c / P->nbatch];
+                    for (size_t o = 0; o < wrow; ++o)
+                        if (wide[(size_t)b * wrow + o] >= 0) seen[o] = 1;
+                }
                 for (size_t o = 0; o < wrow; ++o)
-                    if (wide[(size_t)b * wrow + o] >= 0) seen[o] = 1;
+                    if (seen[o]) tops.push_back((int32_t)o);
+                tptr.push_back((int32_t)tops.size());
             }
-            for (size_t o = 0; o < wrow; ++o)
-                if (seen[o]) tops.push_back((int32_t)o);
-            tptr.push_back((int32_t)tops.size());
-        }
-        const std::vector<int32_t> order = tile_order_by_work(tptr);
-        N.table_tile_ops = (int64_t)tops.size();
-        N.tile_ptr = upload(P, tptr);
-        N.tile_ops = upload(P, tops);
-        N.tile_order = upload(P, order);
-        VP_HIP(hipStreamSynchronize(s));  // the host vectors leave scope
+            dptr = upload(P, tptr);
+            dops = upload(P, tops);
+            dorder = upload(P, tile_order_by_work(tptr));
+            VP_HIP(hipStreamSynchronize(s));  // the host vectors leave scope
+            return (int64_t)tops.size();
+        };
+        N.table_tile_ops = groups(16, N.tile_ptr, N.tile_ops, N.tile_order);
+        groups(32, N.tile2_ptr, N.tile2_ops, N.tile2_order);
     }
 
     if (N.active) {

@@ -484,6 +484,96 @@ __global__ void __launch_bounds__(64 * NW) k_translate_split(TranslateArgs a, co
     }
 }
 
+// Near-field tables, one wave per workgroup over CT 16-column tiles at once.
+// Every leaf of a table level applies the same NTOPS operators (one per
+// neighbour slot), so the wave loads each operator fragment once and applies
+// it to the CT tiles' source columns: CT times less operator traffic from L2
+// than one tile per wave, which is what bounds the one-tile form (a 64 x 64
+// FP64 operator per 16-column product asks L2 for more bytes per cycle than
+// it delivers at the matrix cores' rate).  tile_ptr / tile_ops list the
+// operators present in each group of 16 CT columns; absent sources read the
+// zero column.  Stores (each table leaf's sums come from its one group).
+template <int RB, int S, int CT>
+__global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double *__restrict__ A,
+                                                  const double *__restrict__ in, double *__restrict__ out) {
+    typedef Mfma<double> M;
+    constexpr int AE = RB * S * 64;
+    constexpr int W = 16 * CT;  // columns per group
+    __shared__ int32_t s_ops[64];
+    __shared__ int32_t s_src[64][W];
+    const int lane = threadIdx.x, cl = lane & 15, g = lane >> 4;
+    const int tile = a.tile_order[blockIdx.x];
+    int box[CT], bt[CT];
+    bool valid[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const int col = tile * W + c * 16 + cl;
+        valid[c] = col < a.ncols;
+        box[c] = valid[c] ? a.cols_box[col / a.nbatch] : 0;
+        bt[c] = valid[c] ? col % a.nbatch : 0;
+    }
+    typename M::acc_t acc[CT][RB];
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[c][r] = M::zero();
+    const double *zc = static_cast<const double *>(a.zero_col);
+    const int e0 = a.tile_ptr[tile], nt = a.tile_ptr[tile + 1] - e0;
+    for (int c0 = 0; c0 < nt; c0 += 64) {
+        const int nc = min(64, nt - c0);
+        __syncthreads();
+        for (int i = lane; i < nc; i += 64) s_ops[i] = a.tile_ops[e0 + c0 + i];
+        __syncthreads();
+        for (int i = lane; i < nc * W; i += 64) {
+            const int oi = i / W, c = i % W, cc = tile * W + c;
+            s_src[oi][c] = cc < a.ncols ? a.slots[(int64_t)a.cols_box[cc / a.nbatch] * a.nops + s_ops[oi]] : -1;
+        }
+        __syncthreads();
+        for (int e = 0; e < nc; ++e) {
+            double bv[CT][S];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int src = s_src[e][c * 16 + cl];
+                const double *ip = (src >= 0 ? in + a.in.off(src) + (int64_t)bt[c] * a.in.bstride : zc) + g;
+#pragma unroll
+                for (int s = 0; s < S; ++s) bv[c][s] = ip[4 * s];
+            }
+            const double *Ao = A + (int64_t)s_ops[e] * AE + lane;
+            // operator fragments one 16-row block at a time, the next block's
+            // loads in flight while this one is on the matrix cores
+            double ah[2][S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) ah[0][s] = Ao[s * 64];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int h = r & 1;
+                if (r + 1 < RB) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s) ah[h ^ 1][s] = Ao[((r + 1) * S + s) * 64];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) acc[c][r] = M::op(ah[h][s], bv[c][s], acc[c][r]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        if (!valid[c]) continue;
+        double *op = out + a.out.off(box[c]) + (int64_t)bt[c] * a.out.bstride;
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = r * 16 + M::row(i, g);
+                if (row < a.nrows_out) op[row] = acc[c][r][i];
+            }
+    }
+}
+
 // Dynamic LDS bytes of a k_translate launch (0 when operators stay in global memory).
 template <class TM, int RB, int S, bool SPLIT>
 constexpr size_t translate_lds_bytes() {

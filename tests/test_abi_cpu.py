@@ -45,7 +45,8 @@ def _plan(lib, vp, x, y, w, n, tx=None, ty=None, m=None, rowptr=None, col=None, 
 
 @pytest.mark.parametrize("case", ["n0", "nan", "m_mismatch", "rowptr0", "rowptr_dec", "col_range",
                                   "order", "nbatch", "leaf", "fp32_mode", "flags", "root_node",
-                                  "root_target", "kernel", "lambda0", "lambda_nan", "tile_waves"])
+                                  "root_target", "kernel", "lambda0", "lambda_nan", "tile_waves",
+                                  "table_waves"])
 def test_plan_rejects_invalid(case):
     vp, lib = _lib()
     x = np.linspace(0, 1, 8)
@@ -80,6 +81,8 @@ def test_plan_rejects_invalid(case):
         kw["kernel"] = 2
     elif case == "tile_waves":
         kw["m2l_waves"] = 3
+    elif case == "table_waves":
+        kw["table_waves"] = 3
     elif case == "lambda0":
         kw["kernel"], kw["lam"] = 1, 0.0
     elif case == "lambda_nan":
