@@ -95,16 +95,17 @@ static void *scratch_address(int device) {
 // The evaluation workspace carved from one base address, each part aligned
 // to 256 bytes; returns the bytes used (base == nullptr: only the size).
 static size_t carve_workspace(vp_plan_s *P, unsigned char *base, double **q, double **acc, double **acc_far,
-                              void **M, void **L) {
+                              void **M, void **L, double **qi) {
     const int64_t len = std::max(P->n, P->m);
     const size_t esz = P->fp32 ? 4 : 8;
     const size_t ecount = (size_t)P->tree.nbox * P->nbatch * P->PD;
     const size_t mcount = (size_t)(P->tree.nbox + 4 * (size_t)P->n_vleaf) * P->nbatch * P->PD;
-    const size_t sizes[5] = {8 * (size_t)P->nbatch * len, 8 * (size_t)P->nbatch * len,
-                             8 * (size_t)P->nbatch * len, mcount * esz, ecount * esz};
-    void *parts[5];
+    const size_t sizes[6] = {8 * (size_t)P->nbatch * len, 8 * (size_t)P->nbatch * len,
+                             8 * (size_t)P->nbatch * len, mcount * esz,
+                             ecount * esz,                 P->qi ? 8 * (size_t)P->nbatch * len : 0};
+    void *parts[6];
     size_t off = 0;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
         parts[k] = base ? base + off : nullptr;
         off += (sizes[k] + 255) / 256 * 256;
     }
@@ -114,6 +115,7 @@ static size_t carve_workspace(vp_plan_s *P, unsigned char *base, double **q, dou
         *acc_far = static_cast<double *>(parts[2]);
         *M = parts[3];
         *L = parts[4];
+        if (P->qi) *qi = static_cast<double *>(parts[5]);
     }
     return off;
 }
@@ -501,7 +503,7 @@ static vp_status plan_build(const double *x, const double *y, const double *w, i
         P->Mexp = P->mem.alloc<unsigned char>(mcount * esz);
         P->Lexp = P->mem.alloc<unsigned char>(ecount * esz);
         // zeros read in place of an absent source column (M2L, near tables)
-        const int64_t nzero = std::max<int64_t>(P->PD, 128);
+        const int64_t nzero = std::max<int64_t>(P->PD, 128 * (int64_t)P->nbatch);
         P->zero_col = P->mem.alloc<double>(nzero);
         vp::fill_f64((double *)P->zero_col, 0.0, nzero, P->stream);
         if (P->fp32) {
@@ -513,6 +515,9 @@ static vp_status plan_build(const double *x, const double *y, const double *w, i
         }
         VP_HIP(hipStreamSynchronize(P->stream));
         vp::build_near_tables(P);
+        // the near tables read their source columns from a density-fastest copy
+        // of the charges (one box's columns are one contiguous block)
+        if (P->near.active && P->nbatch > 1) P->qi = P->mem.alloc<double>((size_t)P->nbatch * len);
         if (o.kernel == VP_KERNEL_YUKAWA) vp::build_yukawa(P);
         if (o.p2p_mode == VP_P2P_TABLES && !P->near.active)
             throw Error(VP_EUNSUPPORTED, "p2p_mode TABLES needs targets = nodes and congruent leaves");
@@ -666,7 +671,7 @@ extern "C" vp_status vp_eval_noalloc(vp_plan_t P, const double *f, double *u) {
     if (!f || !u) return set_err(P, VP_EINVAL, "f and u must not be NULL");
     if (overlaps(f, 8 * (size_t)P->nbatch * P->nd, u, 8 * (size_t)P->nbatch * P->m))
         return set_err(P, VP_EINVAL, "f and u overlap");
-    const size_t need = vp::carve_workspace(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    const size_t need = vp::carve_workspace(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     if (need > VP_NOALLOC_MAX_BYTES)
         return set_err(P, VP_EINVAL, "the evaluation workspace of this plan (" + std::to_string(need) +
                                          " bytes) exceeds the static workspace of vp_eval_noalloc (" +
@@ -675,10 +680,10 @@ extern "C" vp_status vp_eval_noalloc(vp_plan_t P, const double *f, double *u) {
     // the same evaluation as vp_eval with the plan's workspace pointers
     // swapped for parts of the static array (restored afterwards; the kernels
     // have taken their arguments at launch)
-    double *q0 = P->q, *acc0 = P->acc, *far0 = P->acc_far;
+    double *q0 = P->q, *acc0 = P->acc, *far0 = P->acc_far, *qi0 = P->qi;
     void *M0 = P->Mexp, *L0 = P->Lexp;
     vp::carve_workspace(P, static_cast<unsigned char *>(P->scratch_dev), &P->q, &P->acc, &P->acc_far, &P->Mexp,
-                        &P->Lexp);
+                        &P->Lexp, &P->qi);
     vp_status st = guarded(P, [&] {
         // the expansions' padding rows must be zero (the plan zeroes its own
         // arrays once; the static array holds whatever the last call left)
@@ -698,6 +703,7 @@ extern "C" vp_status vp_eval_noalloc(vp_plan_t P, const double *f, double *u) {
     P->q = q0;
     P->acc = acc0;
     P->acc_far = far0;
+    P->qi = qi0;
     P->Mexp = M0;
     P->Lexp = L0;
     return st;
@@ -824,7 +830,7 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
         info->m2l_tile_ops = P->yk.m2l_tile_ops;
         info->m2l_coarse_translations = info->m2l_coarse_tile_ops = 0;
     }
-    info->noalloc_bytes = (int64_t)vp::carve_workspace(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    info->noalloc_bytes = (int64_t)vp::carve_workspace(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     return VP_OK;
 }
 

@@ -64,14 +64,51 @@ struct BoxGeo {
 // ----------------------------------------------------------------------------
 // charges
 // ----------------------------------------------------------------------------
+// q[b][i] = w_i f_b[perm i]
 __global__ void k_charge(const double *__restrict__ f, const int32_t *__restrict__ perm,
-                         const double *__restrict__ w, double *__restrict__ q, int64_t len,
-                         int nbatch) {
+                         const double *__restrict__ w, double *__restrict__ q, int64_t len, int nbatch) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= len) return;
     int32_t j = perm[i];
     double wi = w ? w[i] : 1.0;
     for (int b = 0; b < nbatch; ++b) q[(int64_t)b * len + i] = wi * f[(int64_t)b * len + j];
+}
+
+// The same, and qi[i][b] (density fastest) through an LDS transpose of the
+// workgroup's 64 points x nbatch densities, so that both stores write whole
+// contiguous rows.  Dynamic LDS: 64 (nbatch + 1) doubles.
+__global__ void __launch_bounds__(64) k_charge_il(const double *__restrict__ f, const int32_t *__restrict__ perm,
+                                                  const double *__restrict__ w, double *__restrict__ q,
+                                                  int64_t len, int nbatch, double *__restrict__ qi) {
+    extern __shared__ double tile[];  // [point][nbatch + 1]
+    const int ld = nbatch + 1;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int li = threadIdx.x;
+    const int64_t i = i0 + li;
+    if (i < len) {
+        const int32_t j = perm[i];
+        const double wi = w ? w[i] : 1.0;
+        for (int b = 0; b < nbatch; ++b) {
+            const double v = wi * f[(int64_t)b * len + j];
+            q[(int64_t)b * len + i] = v;
+            tile[li * ld + b] = v;
+        }
+    }
+    __syncthreads();
+    const int npts = (int)min<int64_t>(64, len - i0);
+    // element e = pi nbatch + b of the block; one division, then steps of 64
+    const int dq = 64 / nbatch, dr = 64 - dq * nbatch;
+    int pi = li / nbatch, b = li - pi * nbatch;
+    double *out = qi + i0 * nbatch;
+    for (int e = li; e < npts * nbatch; e += 64) {
+        out[e] = tile[pi * ld + b];
+        pi += dq;
+        b += dr;
+        if (b >= nbatch) {
+            b -= nbatch;
+            ++pi;
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1838,6 +1875,7 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
     const int32_t *perm = adjoint ? P->tperm : P->sperm;
     const double *w = adjoint ? nullptr : P->sw;
     if (!adjoint && P->os_p > 0) {
+        P->qi_valid = false;
         P->stage_begin(VP_STAGE_CHARGE);
         hipLaunchKernelGGL(k_interp_charge, dim3((unsigned)P->os_nbox), dim3(256), 0, P->stream, P->os_in, P->os_out,
                            P->os_p * P->os_p, P->os_q * P->os_q, P->os_OT, f, P->nd, P->sinv, P->w_user,
@@ -1847,8 +1885,14 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
         return;
     }
     P->stage_begin(VP_STAGE_CHARGE);
-    hipLaunchKernelGGL(k_charge, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, P->stream, f, perm, w,
-                       P->q, len, P->nbatch);
+    // the density-fastest copy only for the one-wave near-table kernel, its one reader
+    P->qi_valid = P->qi != nullptr && P->table_nw == 1;
+    if (P->qi_valid)
+        hipLaunchKernelGGL(k_charge_il, dim3((unsigned)((len + 63) / 64)), dim3(64),
+                           64 * (P->nbatch + 1) * sizeof(double), P->stream, f, perm, w, P->q, len, P->nbatch, P->qi);
+    else
+        hipLaunchKernelGGL(k_charge, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, P->stream, f, perm, w,
+                           P->q, len, P->nbatch);
     VP_LAUNCH_CHECK();
     P->stage_end(VP_STAGE_CHARGE);
 }
@@ -2080,8 +2124,13 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
             a.tile_ptr = N.tile2_ptr;
             a.tile_ops = N.tile2_ops;
             a.tile_order = N.tile2_order;
-            hipLaunchKernelGGL((k_tables_ct<RB, S, 2>), dim3((unsigned)((a.ncols + 31) / 32)), dim3(64), 0,
-                               P->stream, a, N.K, P->q, P->acc);
+            const dim3 grid((unsigned)((a.ncols + 31) / 32));
+            if (P->qi_valid)
+                hipLaunchKernelGGL((k_tables_ct<RB, S, 2, true>), grid, dim3(64), 0, P->stream, a, N.K, P->qi,
+                                   P->acc);
+            else
+                hipLaunchKernelGGL((k_tables_ct<RB, S, 2, false>), grid, dim3(64), 0, P->stream, a, N.K, P->q,
+                                   P->acc);
             done = true;
         }
     }

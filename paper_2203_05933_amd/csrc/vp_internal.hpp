@@ -356,9 +356,12 @@ struct vp_plan_s {
     double *q = nullptr;     // [nbatch][max(n,m)] charges, sorted order
     double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order (near field; gradients x 2)
     double *acc_far = nullptr;  // [nbatch][max(n,m)] far-field potentials, sorted order
+    double *qi = nullptr;    // [max(n,m)][nbatch] the charges again, density fastest (near tables, nbatch > 1)
+    bool qi_valid = false;   // qi holds this evaluation's charges
     void *Mexp = nullptr;    // [nbox + 4 n_vleaf][nbatch][PD] (double or float)
     void *Lexp = nullptr;
-    void *zero_col = nullptr;  // max(PD, 128) zero doubles (an absent source column, either element type)
+    void *zero_col = nullptr;  // max(PD, 128 nbatch) zero doubles (an absent source column, either element
+                               // type and either charge layout)
     void *scratch_dev = nullptr;  // this device's static workspace (vp_eval_noalloc), resolved at plan time
     vp::P2PGather g_fwd, g_adj;   // full U-list sources (nodes / targets as sources) without tables
     // M2L launches: [0] levels >= split_level, [1] levels 2 .. split_level-1

@@ -493,12 +493,26 @@ __global__ void __launch_bounds__(64 * NW) k_translate_split(TranslateArgs a, co
 // it delivers at the matrix cores' rate).  tile_ptr / tile_ops list the
 // operators present in each group of 16 CT columns; absent sources read the
 // zero column.  Stores (each table leaf's sums come from its one group).
-template <int RB, int S, int CT>
+// IL: the charges come density fastest, element (point k of box b, density
+// d) at (start[b] + k) nbatch + d, so that a load of four points of sixteen
+// densities is one contiguous 512-byte block (with one density per row the
+// sixteen densities of a box lie a whole charge array apart).
+//
+// Schedule: k-steps outermost, so each step issues RB * CT independent
+// products (no product waits on the one before it).  Operator fragments
+// stream PF k-steps ahead of the products, across operator boundaries (the
+// first steps of the next operator load during the last steps of this one),
+// and the next operator's source columns load one step at a time beside
+// them (loads complete in issue order, so spreading them keeps every wait
+// short).
+template <int RB, int S, int CT, bool IL>
 __global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double *__restrict__ A,
                                                   const double *__restrict__ in, double *__restrict__ out) {
     typedef Mfma<double> M;
     constexpr int AE = RB * S * 64;
     constexpr int W = 16 * CT;  // columns per group
+    constexpr int PF = 3, NBUF = PF + 1;  // operator prefetch distance (k-steps), ring slots
+    static_assert(S % NBUF == 0, "the ring wraps at operator boundaries");
     __shared__ int32_t s_ops[64];
     __shared__ int32_t s_src[64][W];
     const int lane = threadIdx.x, cl = lane & 15, g = lane >> 4;
@@ -518,6 +532,17 @@ __global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double 
 #pragma unroll
         for (int r = 0; r < RB; ++r) acc[c][r] = M::zero();
     const double *zc = static_cast<const double *>(a.zero_col);
+    // element k = 4 s + g of a source column is at src_col(e, c)[s * kst]
+    const int64_t kst = IL ? 4 * (int64_t)a.nbatch : 4;
+    // source column of tile c for operator entry e (absent: the zero column)
+    auto src_col = [&](int e, int c) {
+        const int src = s_src[e][c * 16 + cl];
+        if constexpr (IL) {
+            return (src >= 0 ? in + a.in.off(src) * (int64_t)a.nbatch : zc) + (int64_t)g * a.nbatch + bt[c];
+        } else {
+            return (src >= 0 ? in + a.in.off(src) + (int64_t)bt[c] * a.in.bstride : zc) + g;
+        }
+    };
     const int e0 = a.tile_ptr[tile], nt = a.tile_ptr[tile + 1] - e0;
     for (int c0 = 0; c0 < nt; c0 += 64) {
         const int nc = min(64, nt - c0);
@@ -529,35 +554,50 @@ __global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double 
             s_src[oi][c] = cc < a.ncols ? a.slots[(int64_t)a.cols_box[cc / a.nbatch] * a.nops + s_ops[oi]] : -1;
         }
         __syncthreads();
+        double bv[CT][S];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const double *ip = src_col(0, c);
+#pragma unroll
+            for (int s = 0; s < S; ++s) bv[c][s] = ip[s * kst];
+        }
+        // ring of operator fragments: k-step j of the stream sits in slot j % NBUF
+        double af[NBUF][RB];
+        {
+            const double *A0 = A + (int64_t)s_ops[0] * AE + lane;
+#pragma unroll
+            for (int p = 0; p < PF; ++p)
+#pragma unroll
+                for (int r = 0; r < RB; ++r) af[p][r] = A0[(r * S + p) * 64];
+        }
         for (int e = 0; e < nc; ++e) {
-            double bv[CT][S];
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const int src = s_src[e][c * 16 + cl];
-                const double *ip = (src >= 0 ? in + a.in.off(src) + (int64_t)bt[c] * a.in.bstride : zc) + g;
-#pragma unroll
-                for (int s = 0; s < S; ++s) bv[c][s] = ip[4 * s];
-            }
+            const bool more = e + 1 < nc;
             const double *Ao = A + (int64_t)s_ops[e] * AE + lane;
-            // operator fragments one 16-row block at a time, the next block's
-            // loads in flight while this one is on the matrix cores
-            double ah[2][S];
+            // the next operator (this one again after the last: loaded, never used)
+            const double *An = more ? A + (int64_t)s_ops[e + 1] * AE + lane : Ao;
+            const double *nx[CT];
 #pragma unroll
-            for (int s = 0; s < S; ++s) ah[0][s] = Ao[s * 64];
+            for (int c = 0; c < CT; ++c) nx[c] = more ? src_col(e + 1, c) : zc;
+            double bn[CT][S];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const int h = r & 1;
-                if (r + 1 < RB) {
+            for (int s = 0; s < S; ++s) {
+                const int sp = s + PF;
 #pragma unroll
-                    for (int s = 0; s < S; ++s) ah[h ^ 1][s] = Ao[((r + 1) * S + s) * 64];
-                }
+                for (int r = 0; r < RB; ++r)
+                    af[sp % NBUF][r] = sp < S ? Ao[(r * S + sp) * 64] : An[(r * S + sp - S) * 64];
+#pragma unroll
+                for (int c = 0; c < CT; ++c) bn[c][s] = nx[c][s * kst];
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int s = 0; s < S; ++s)
+                for (int r = 0; r < RB; ++r)
 #pragma unroll
-                    for (int c = 0; c < CT; ++c) acc[c][r] = M::op(ah[h][s], bv[c][s], acc[c][r]);
+                    for (int c = 0; c < CT; ++c) acc[c][r] = M::op(af[s % NBUF][r], bv[c][s], acc[c][r]);
                 __builtin_amdgcn_sched_barrier(0);
             }
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int s = 0; s < S; ++s) bv[c][s] = bn[c][s];
         }
     }
 #pragma unroll

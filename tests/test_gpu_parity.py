@@ -663,10 +663,11 @@ def test_tables_match_pairwise_with_x_lists():
 @pytest.mark.parametrize("case", ["c0_1", "c0_3", "c0_251_leaves", "star_window"])
 def test_one_wave_tables(c0, case):
     """The one-wave near-table kernel (one operator load for two 16-column
-    tiles) against the four-wave kernel and the oracle: one and three
-    densities (tiles straddling leaves), 251 table leaves (five leaves moved
-    off the node pattern: the last 32-column group is ragged), and an
-    adaptive window whose table leaves sit on several levels."""
+    tiles) against the four-wave kernel and the oracle, forward and adjoint:
+    one density (charges one density per row) and three (density-fastest
+    charges, tiles straddling leaves), 251 table leaves with two densities
+    (five leaves moved off the node pattern: the last 32-column group is
+    ragged), and an adaptive window whose table leaves sit on several levels."""
     vp = _vp()
     if case == "c0_251_leaves":
         x, y = c0.x.copy(), c0.y.copy()
@@ -675,7 +676,8 @@ def test_one_wave_tables(c0, case):
             sl = slice(64 * b, 64 * b + 64)
             x[sl] += 4e-13 * (2.0 / 16) * rng.choice([-1.0, 1.0], 64)
             y[sl] += 4e-13 * (2.0 / 16) * rng.choice([-1.0, 1.0], 64)
-        w, f = c0.w, c0.f
+        w = c0.w
+        f = np.stack([gen.gaussian_sum_density(x, y, s)[0] for s in (60, 61)])
         rowptr, col, val, root = c0.rowptr, c0.col, c0.val, c0.root
     elif case == "star_window":
         wl = gen.config1()
@@ -688,7 +690,8 @@ def test_one_wave_tables(c0, case):
         x, y, w = c0.x, c0.y, c0.w
         f = np.stack([gen.gaussian_sum_density(x, y, s)[0] for s in range(50, 50 + nb)])
         rowptr, col, val, root = c0.rowptr, c0.col, c0.val, c0.root
-    out = {}
+    out, adj = {}, {}
+    g = np.random.default_rng(79).standard_normal(f.shape)
     for tw in (4, 1):
         plan = vp.Plan(x, y, w, rowptr=rowptr, col=col, val=val, order=30, nbatch=f.shape[0], root=root,
                        table_waves=tw)
@@ -697,13 +700,15 @@ def test_one_wave_tables(c0, case):
         if case == "c0_251_leaves":
             assert info["table_leaves"] == 251
         out[tw] = _host(plan.eval(_dev(f)))
+        adj[tw] = _host(plan.eval_adjoint(_dev(g)))
         plan.close()
     ref = direct.evaluate(x, y, w, f, rowptr, col, val) if rowptr is not None else direct.smooth(x, y, w, f)
     err = relinf(out[1], ref)
     d = relinf(out[1], out[4])
-    print(f"one-wave tables {case}: rel_inf={err:.3e}, vs four waves {d:.2e}")
+    da = relinf(adj[1], adj[4])
+    print(f"one-wave tables {case}: rel_inf={err:.3e}, vs four waves {d:.2e} (adjoint {da:.2e})")
     assert err <= TOL64
-    assert d <= 1e-14
+    assert d <= 1e-14 and da <= 1e-14
 
 
 @pytest.mark.parametrize("band", ["inside", "outside"])

@@ -39,14 +39,14 @@ def relinf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def _grid(nside, seeds, csr_seed, precision="fp64", order=30):
+def _grid(nside, seeds, csr_seed, precision="fp64", order=30, table_waves=0):
     vp = _vp()
     x, y, w = gen.uniform_grid(nside)
     f = np.stack([gen.gaussian_sum_density(x, y, s)[0] for s in seeds])
     cell_ptr = np.arange(0, x.shape[0] + 1, 64, dtype=np.int64)
     rowptr, col, val = gen.own_cell_csr(cell_ptr, csr_seed)
     plan = vp.Plan(x, y, w, rowptr=rowptr, col=col, val=val, order=order, nbatch=len(seeds),
-                   precision=precision, root=(-1.0, -1.0, 2.0))
+                   precision=precision, root=(-1.0, -1.0, 2.0), table_waves=table_waves)
     return plan, f
 
 
@@ -73,6 +73,15 @@ def test_noalloc_matches_eval_two_calls():
     _compare(big, f_big, "first plan again")
     big.close()
     small.close()
+
+
+def test_noalloc_one_wave_tables():
+    """The one-wave near-table kernel with several densities reads a
+    density-fastest copy of the charges, which the static array also holds."""
+    plan, f = _grid(8, [11, 12, 13], 14, table_waves=1)
+    assert plan.info()["table_waves"] == 1
+    _compare(plan, f, "one-wave tables, three densities, 8x8 boxes")
+    plan.close()
 
 
 def test_noalloc_fp32_bulk_form():
