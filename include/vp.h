@@ -125,7 +125,9 @@ typedef struct {
     void *stream;      /* hipStream_t for plan-time copies and evaluations;
                           NULL = the null stream */
     int32_t kernel;    /* VP_KERNEL_*; default VP_KERNEL_LAPLACE */
-    int32_t m2l_waves; /* waves per 16-column tile of the M2L kernels: 2 or 4;
+    int32_t m2l_waves; /* waves per 16-column tile of the M2L kernels: 2 or 4,
+                          or 1 = one wave per tile, four tiles per workgroup
+                          (scaled forms; the per-offset forms take 4);
                           0 = 4, or the autotuner's choice */
     double lambda;     /* VP_KERNEL_YUKAWA: lambda > 0 (Section 5 uses lambda^2 = 100) */
     int32_t table_waves; /* waves per 16-column tile of the near-table kernel:

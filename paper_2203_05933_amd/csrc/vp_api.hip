@@ -247,7 +247,8 @@ static void validate_plan_args(const double *x, const double *y, const double *w
     if (o.max_level < 0 || o.max_level > vp::LBITS) bad("max_level must be in 0..30");
     if (o.flags & ~(VP_FLAG_AUTOTUNE | VP_FLAG_ONE_STREAM | VP_FLAG_AUTOTUNE_LEAF)) bad("unknown flags");
     if (o.kernel != VP_KERNEL_LAPLACE && o.kernel != VP_KERNEL_YUKAWA) bad("unknown kernel");
-    if (o.m2l_waves != 0 && o.m2l_waves != 2 && o.m2l_waves != 4) bad("m2l_waves must be 0, 2 or 4");
+    if (o.m2l_waves != 0 && o.m2l_waves != 1 && o.m2l_waves != 2 && o.m2l_waves != 4)
+        bad("m2l_waves must be 0, 1, 2 or 4");
     if (o.table_waves != 0 && o.table_waves != 1 && o.table_waves != 2 && o.table_waves != 4)
         bad("table_waves must be 0, 1, 2 or 4");
     if (o.kernel == VP_KERNEL_YUKAWA && !(std::isfinite(o.lambda) && o.lambda > 0))

@@ -1458,7 +1458,7 @@ std::vector<P2MJob> p2m_job_descs(vp_plan_s *P, const std::vector<int32_t> &code
     return out;
 }
 
-std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr) {
+std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr, int group) {
     const int nt = (int)tile_ptr.size() - 1;
     std::vector<int32_t> ord(std::max(nt, 0));
     for (int t = 0; t < nt; ++t) ord[t] = t;
@@ -1469,21 +1469,24 @@ std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr) {
     // Dealt one by one, consecutive tiles (neighbouring boxes, which share
     // most of their source columns) land on eight different L2s and every
     // source column is fetched past L2 once per target.  Instead each XCD
-    // takes runs of XCD_RUN consecutive tiles of the order above: round r
-    // covers positions [8 r XCD_RUN, 8 (r+1) XCD_RUN), XCD x its x-th run,
-    // so the order's heaviest-first progress is kept round by round.  The
-    // last, incomplete round keeps the plain order.
+    // takes runs of XCD_RUN consecutive workgroups' tiles (a workgroup takes
+    // `group` consecutive tiles of the order above): round r covers
+    // workgroups [8 r XCD_RUN, 8 (r+1) XCD_RUN), XCD x its x-th run, so the
+    // order's heaviest-first progress is kept round by round.  The last,
+    // incomplete round (and a last, partial workgroup) keep the plain order.
     constexpr int XCDS = 8, XCD_RUN = 256;
-    const int full = nt / (XCDS * XCD_RUN) * (XCDS * XCD_RUN);
+    const int nu = (nt + group - 1) / group;         // workgroups
+    const int nfull = nt / group;                    // workgroups with `group` tiles
+    const int full = nfull / (XCDS * XCD_RUN) * (XCDS * XCD_RUN);
     std::vector<int32_t> launch(ord.size());
-    for (int p = 0; p < nt; ++p) {
+    for (int p = 0; p < nu; ++p) {
         int b = p;
         if (p < full) {
             const int run = p / XCD_RUN, x = run % XCDS, round = run / XCDS;
             const int j = round * XCD_RUN + p % XCD_RUN;  // position in XCD x's sequence
             b = j * XCDS + x;
         }
-        launch[b] = ord[p];
+        for (int w = 0; w < group && p * group + w < nt; ++w) launch[(size_t)b * group + w] = ord[(size_t)p * group + w];
     }
     return launch;
 }
@@ -1680,7 +1683,7 @@ void build_schedules(vp_plan_s *P) {
                 }
             tptr.push_back((int32_t)tops.size());
         }
-        const std::vector<int32_t> order = tile_order_by_work(tptr);
+        const std::vector<int32_t> order = tile_order_by_work(tptr), order4 = tile_order_by_work(tptr, 4);
         S.nboxes = (int)m2l.size();
         S.tile_ops = (int64_t)tops.size();
         S.translations = 0;
@@ -1690,6 +1693,7 @@ void build_schedules(vp_plan_s *P) {
         S.tops = up(tops);
         S.tsrc = up(tsrc);
         S.torder = up(order);
+        S.torder4 = up(order4);
         P->m2l_translations += S.translations;
         P->m2l_tile_ops += S.tile_ops;
         VP_HIP(hipStreamSynchronize(s));  // the host vectors leave scope
@@ -1760,7 +1764,10 @@ static void translate_m2l(hipStream_t s, int nw, int PD, const TranslateArgs &a,
 template <class TI, class TO, class TM, int RB>
 static void launch_m2l_scaled(hipStream_t s, int nw, unsigned blocks, const M2LScaledArgs &a, const TM *Q,
                               const TM *tin, const double *logt, const TI *in, TO *out) {
-    if (nw == 2)
+    if (nw == 1)
+        hipLaunchKernelGGL((k_m2l_wave<TI, TO, TM, RB>), dim3((blocks + 3) / 4), dim3(256), 0, s, a, Q, tin, logt,
+                           in, out);
+    else if (nw == 2)
         hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, RB, 2>), dim3(blocks), dim3(128), 0, s, a, Q, tin, logt, in, out);
     else
         hipLaunchKernelGGL((k_m2l_scaled<TI, TO, TM, RB, 4>), dim3(blocks), dim3(256), 0, s, a, Q, tin, logt, in, out);
@@ -1930,7 +1937,7 @@ static void launch_m2l(vp_plan_s *P, int part) {
         sa.tile_ptr = S.tptr;
         sa.tile_ops = S.tops;
         sa.tile_src = S.tsrc;
-        sa.tile_order = S.torder;
+        sa.tile_order = P->m2l_nw == 1 ? S.torder4 : S.torder;
         sa.P = Pn;
         sa.box_stride = (int64_t)nb * PD;
         sa.bt_stride = PD;
@@ -2769,8 +2776,9 @@ float time_forward(vp_plan_s *P, const double *f, double *u, int reps) {
 //   M2L form       FP64: scaled, per-offset products;  FP32-bulk: scaled FP32,
 //                  per-offset FP32, split hi/lo FP32, scaled FP64 (every one
 //                  meets the precision's accuracy target)
-//   M2L waves per 16-column tile (4, 2), near-table waves per tile (4, 2, or
-//   one wave over two tiles), streams (three, one).
+//   M2L waves per 16-column tile (4, 2, or one wave per tile in the scaled
+//   forms), near-table waves per tile (4, 2, or one wave over two tiles),
+//   streams (three, one).
 // Returns the best time (ms).
 float autotune(vp_plan_s *P) {
     TempArena tmp;
@@ -2794,7 +2802,10 @@ float autotune(vp_plan_s *P) {
     };
     if (P->fp32) knob(P->m2l_mode, {VP_M2L_FP32_SCALED, VP_M2L_FP32_MFMA, VP_M2L_FP32_SPLIT, VP_M2L_FP64_SCALED});
     else knob(P->m2l_mode, {VP_M2L_FP64_SCALED, VP_M2L_FP64_MFMA});
-    if (P->opt.m2l_waves == 0) knob(P->m2l_nw, {4, 2});
+    if (P->opt.m2l_waves == 0) {
+        const bool scaled = P->m2l_mode == VP_M2L_FP64_SCALED || P->m2l_mode == VP_M2L_FP32_SCALED;
+        knob(P->m2l_nw, scaled ? std::vector<int>{4, 2, 1} : std::vector<int>{4, 2});
+    }
     if (P->opt.table_waves == 0 && P->near.active) knob(P->table_nw, {4, 2, 1});
     int one = P->one_stream ? 1 : 0;
     if (!(P->opt.flags & VP_FLAG_ONE_STREAM)) {

@@ -191,6 +191,7 @@ struct M2LSched {
     int32_t *tops = nullptr;
     int32_t *tsrc = nullptr;    // [tile offset][16] source box per column, or -1
     int32_t *torder = nullptr;  // tiles by decreasing offset count
+    int32_t *torder4 = nullptr; // the same, dealt to the XCDs in groups of four tiles (one wave per tile)
     int64_t translations = 0, tile_ops = 0;
 };
 
@@ -288,7 +289,7 @@ struct vp_plan_s {
     bool self = false;
     bool fp32 = false;
     int m2l_mode = VP_M2L_FP64_MFMA;
-    int m2l_nw = 4;           // waves per 16-column tile of the M2L kernels (4 or 2; the autotuner may pick 2)
+    int m2l_nw = 4;           // waves per 16-column tile of the M2L kernels (4, 2, or 1: one wave per tile)
     int table_nw = 4;         // waves per tile of the near-table launch (1: one wave over two tiles)
     int tuned = 0;            // 0: defaults; 1: chosen by timing at plan time; 2: from the tuning cache
     double tune_ms = 0.0;     // plan time spent tuning
@@ -436,8 +437,9 @@ bool pattern_op_supported(int npat, int PD);
 void build_p2p_gather(vp_plan_s *P, const std::vector<int32_t> &leaves, const std::vector<int32_t> &uptr,
                       const std::vector<int32_t> &uidx, const std::vector<int32_t> &sb, const std::vector<int32_t> &se,
                       const double *sx, const double *sy, P2PGather &g);
-// launch order of tiles with tile_ptr[t+1] - tile_ptr[t] operators: most operators first
-std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr);
+// launch order of tiles with tile_ptr[t+1] - tile_ptr[t] operators: most operators
+// first, dealt to the XCDs in runs of workgroups of `group` consecutive tiles
+std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr, int group = 1);
 // one evaluation after prepare_charges; with u: the correction C f (adjoint C^T f) runs
 // beside the FMM and u = FMM sums (un-permuted; adjoint: times w) + correction
 void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f = nullptr, double *u = nullptr);

@@ -38,7 +38,7 @@ struct M2LScaledArgs {
     const int32_t *tile_ptr;  // offsets present in 16-column tile t: tile_ops[tile_ptr[t] .. tile_ptr[t+1])
     const int32_t *tile_ops;
     const int32_t *tile_src;  // [tile op][16]: source box of each column of the tile, or -1
-    const int32_t *tile_order;  // launch order of the tiles (most offsets first)
+    const int32_t *tile_order;  // launch order of the tiles (most offsets first; k_m2l_wave: in groups of four)
     int P;                    // complex coefficients per expansion
     int64_t box_stride;       // elements between the columns of consecutive boxes
     int64_t bt_stride;        // elements between the densities of one box
@@ -225,6 +225,144 @@ __global__ void __launch_bounds__(64 * NW, 12 / NW) k_m2l_scaled(M2LScaledArgs a
         a0r += red[v][NR - 2][lane];
         a0i += red[v][NR - 1][lane];
     }
+    if (g == 0) {
+        const double ls = a.logside[a.level[box]];
+        br[0][M::item_of(0)] += a0r * ls;
+        bi[0][M::item_of(0)] += a0i * ls;
+    }
+    TO *op = out + (int64_t)box * a.box_stride + (int64_t)bt * a.bt_stride;
+    const bool add = a.xinit[box] != 0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int l = r * 16 + M::row(i, g);
+            if (l < P) {
+                op[l] = (TO)(add ? (double)op[l] + br[r][i] : br[r][i]);
+                op[P + l] = (TO)(add ? (double)op[P + l] + bi[r][i] : bi[r][i]);
+            }
+        }
+    for (int row = 2 * P + g; row < a.PD; row += 4) op[row] = (TO)0;
+}
+
+// One tile per wave: the workgroup's four waves take four tiles of the launch
+// order (consecutive, so neighbouring boxes that share source columns run
+// together) and each runs ALL of its tile's offsets.  No partial sums cross
+// waves (no reduction through LDS, no barrier after the prologue, no wave
+// idling on a short share of the offsets), and the scaling tables are staged
+// once per four tiles.  The loop body is that of k_m2l_scaled.
+template <class TI, class TO, class TM, int RB>
+__global__ void __launch_bounds__(256, 3) k_m2l_wave(M2LScaledArgs a, const TM *__restrict__ Qf,
+                                                     const TM *__restrict__ tin, const double *__restrict__ logt,
+                                                     const TI *__restrict__ in, TO *__restrict__ out) {
+    typedef Mfma<TM> M;
+    constexpr int S = RB * 4;
+    constexpr int PQ = RB * 16;
+    constexpr int TAB = NOFF * PQ * 2;
+    __shared__ __align__(16) TM s_tin[TAB];
+    __shared__ double s_logt[2 * NOFF];
+    __shared__ int32_t s_ops[4][NOFF];
+    __shared__ int32_t s_src[4][NOFF][16];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cl = lane & 15, g = lane >> 4;
+    {
+        constexpr int CH = TAB * (int)sizeof(TM) / 16;
+        const uint4 *gi = reinterpret_cast<const uint4 *>(tin);
+        uint4 *si = reinterpret_cast<uint4 *>(s_tin);
+        for (int i = tid; i < CH; i += 256) si[i] = gi[i];
+        if (tid < 2 * NOFF) s_logt[tid] = logt[tid];
+    }
+    __syncthreads();
+    const int ntiles = (a.ncols + 15) / 16;
+    const int ti = blockIdx.x * 4 + wave;
+    if (ti >= ntiles) return;
+    const int tile = a.tile_order[ti];
+    const int col = tile * 16 + cl;
+    const bool valid = col < a.ncols;
+    const int box = valid ? a.cols_box[col / a.nbatch] : 0;
+    const int bt = valid ? col % a.nbatch : 0;
+    const int P = a.P;
+
+    // this wave's offsets and each column's source per offset (written and
+    // read by this wave only: a wave-level barrier orders the LDS accesses)
+    const int e0 = a.tile_ptr[tile], nt = a.tile_ptr[tile + 1] - e0;
+    for (int i = lane; i < nt; i += 64) s_ops[wave][i] = a.tile_ops[e0 + i];
+    for (int i = lane; i < nt * 16; i += 64) s_src[wave][i >> 4][i & 15] = a.tile_src[(int64_t)e0 * 16 + i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    TM q[RB][S];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int k = g * S + s;
+            q[r][s] = Qf[(r * S + (k >> 2)) * 64 + (k & 3) * 16 + cl];
+        }
+    double br[RB][4], bi[RB][4];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) br[r][i] = bi[r][i] = 0.0;
+    double a0r = 0.0, a0i = 0.0;
+    const int64_t bt_off = (int64_t)bt * a.bt_stride;
+    const TI *zc = static_cast<const TI *>(a.zero_col);
+    TM xr[S], xi[S];
+    {
+        const int src = nt > 0 ? s_src[wave][0][cl] : -1;
+        m2l_load_col<TI, TM, S>(src >= 0 ? in + (int64_t)src * a.box_stride + bt_off : zc, g, P, xr, xi);
+    }
+    const double m0 = g == 0 ? 1.0 : 0.0;
+    for (int e = 0; e < nt; ++e) {
+        const int o = s_ops[wave][e];
+        const TM *ti_ = s_tin + o * PQ * 2;
+        {
+            const double x0r = (double)xr[0] * m0, x0i = (double)xi[0] * m0;
+            const double lr = s_logt[2 * o], li = s_logt[2 * o + 1];
+            br[0][M::item_of(0)] += x0r * lr - x0i * li;
+            bi[0][M::item_of(0)] += x0r * li + x0i * lr;
+            a0r += x0r;
+            a0i += x0i;
+        }
+        const int en = e + 1;
+        const int srcn = en < nt ? s_src[wave][en][cl] : -1;
+        const TI *ipn = srcn >= 0 ? in + (int64_t)srcn * a.box_stride + bt_off : zc;
+        const TI *pnr = ipn + g * S, *pni = ipn + P + g * S;
+        typename M::acc_t zr[RB], zi[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            zr[r] = M::zero();
+            zi[r] = M::zero();
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int k = g * S + s;
+            const TM wr = ti_[2 * k], wi = ti_[2 * k + 1];
+            const TM yr = xr[s] * wr - xi[s] * wi;
+            const TM yi = xr[s] * wi + xi[s] * wr;
+            xr[s] = (TM)pnr[s];
+            xi[s] = (TM)pni[s];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const TM qv = q[r][s];
+                zr[r] = M::op(qv, yr, zr[r]);
+                zi[r] = M::op(qv, yi, zi[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int l = r * 16 + M::row(i, g);
+                const double vr = (double)ti_[2 * l], vi = (double)ti_[2 * l + 1];
+                const double zre = (double)zr[r][i], zim = (double)zi[r][i];
+                br[r][i] += zre * vr - zim * vi;
+                bi[r][i] += zre * vi + zim * vr;
+            }
+    }
+    if (!valid) return;
     if (g == 0) {
         const double ls = a.logside[a.level[box]];
         br[0][M::item_of(0)] += a0r * ls;

@@ -258,17 +258,17 @@ def test_every_order_matches_truncated_fmm_oracle(c0, order):
     vp = _vp()
     ref_p = FT.evaluate_uniform(c0.x, c0.y, c0.w, c0.f, c0.root, 64, order)
     res = []
-    for mode in ("fp64", "fp64_scaled"):
-        plan = vp.Plan(c0.x, c0.y, c0.w, order=order, m2l_mode=mode, root=c0.root)
+    for mode, waves in (("fp64", 0), ("fp64_scaled", 0), ("fp64_scaled", 1)):
+        plan = vp.Plan(c0.x, c0.y, c0.w, order=order, m2l_mode=mode, root=c0.root, m2l_waves=waves)
         u = _host(plan.eval(_dev(c0.f)))
         res.append((plan.get_array("local"), u))
         err = relinf(u, ref_p)
-        print(f"order {order} m2l={mode}: vs order-p FMM oracle {err:.2e}")
+        print(f"order {order} m2l={mode} waves={waves or 4}: vs order-p FMM oracle {err:.2e}")
         assert err <= 1e-13
         plan.close()
-    (l1, u1), (l2, u2) = res
-    assert relinf(l2, l1) <= 1e-13
-    assert relinf(u2, u1) <= 1e-13
+    (l1, u1), (l2, u2), (l3, u3) = res
+    assert relinf(l2, l1) <= 1e-13 and relinf(l3, l1) <= 1e-13
+    assert relinf(u2, u1) <= 1e-13 and relinf(u3, u1) <= 1e-13
     if order >= 30:
         ref = direct.smooth(c0.x, c0.y, c0.w, c0.f)
         assert relinf(u2, ref) <= TOL64
@@ -289,7 +289,7 @@ def test_autotuned_m2l(c0, precision, order, tol):
         info = plan.info()
         infos.append(info)
         assert info["m2l_mode"] in ((4, 1) if precision == "fp64" else (5, 2, 3, 4)), info["m2l_mode"]
-        assert info["m2l_waves"] in (2, 4) and info["table_waves"] in (1, 2, 4) and info["one_stream"] in (0, 1)
+        assert info["m2l_waves"] in (1, 2, 4) and info["table_waves"] in (1, 2, 4) and info["one_stream"] in (0, 1)
         u = _host(plan.eval(_dev(c0.f)))
         err = relinf(u, ref)
         print(f"autotuned {precision}: m2l mode {info['m2l_mode']}, waves {info['m2l_waves']}/"
@@ -304,12 +304,14 @@ def test_autotuned_m2l(c0, precision, order, tol):
 
 @pytest.mark.parametrize("precision,order,tol", [("fp64", 30, TOL64), ("fp32", 14, TOL32)])
 def test_two_waves_per_tile(c0, precision, order, tol):
-    """The two-wave variants of the M2L and near-table kernels (one of the
-    autotuner's choices) against the oracle and the four-wave default."""
+    """The two-wave and one-wave variants of the M2L and near-table kernels
+    (the autotuner's other choices: two waves sharing a tile; one wave per
+    M2L tile, four tiles per workgroup; one near-table wave over two tiles)
+    against the oracle and the four-wave default."""
     vp = _vp()
     ref = direct.evaluate(c0.x, c0.y, c0.w, c0.f, c0.rowptr, c0.col, c0.val)
     out = {}
-    for waves in (4, 2):
+    for waves in (4, 2, 1):
         for mode in (("fp64_scaled", "fp64") if precision == "fp64" else ("fp32_scaled", "split")):
             plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=order,
                            precision=precision, m2l_mode=mode, m2l_waves=waves, table_waves=waves, root=c0.root)
@@ -320,7 +322,8 @@ def test_two_waves_per_tile(c0, precision, order, tol):
             assert err <= tol
             plan.close()
     for mode in {m for _, m in out}:
-        assert relinf(out[(2, mode)], out[(4, mode)]) <= (1e-14 if precision == "fp64" else 1e-7)
+        for waves in (2, 1):
+            assert relinf(out[(waves, mode)], out[(4, mode)]) <= (1e-14 if precision == "fp64" else 1e-7)
 
 
 def test_autotuned_leaf_size(c0):
