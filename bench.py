@@ -236,8 +236,10 @@ def stage_roofline(info, tim, stage, workload_name=None):
     elif stage == "tables":
         # near-field tables: one multiply-add per (target, source) pair and density, FP64 matrix cores
         flops = info["table_pairs"] * nb * 2
+        one_wave = info["table_waves"] == 1 and info["table_pattern"] <= 64
         rec = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-               "kernel": "k_translate_split (near-field tables)",
+               "kernel": "k_tables_ct (near-field tables, one wave over two tiles)" if one_wave
+               else "k_translate_split (near-field tables)",
                "work": f"{info['table_pairs']} table pairs x {nb} densities x 2 flops"}
     elif stage == "m2l":
         # the "m2l" stage times the launch over the levels from split_level on;
@@ -257,7 +259,8 @@ def stage_roofline(info, tim, stage, workload_name=None):
         PDm = (max(2 * P + 1, P + PQ) + 15) // 16 * 16  # rows per expansion column
         issued = tile_ops * (64 * PQ * PQ if scaled else 32 * PDm * PDm)
         rec = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
-               "kernel": "k_m2l_scaled" if scaled else "k_translate_split", "issued_tflops": issued / avg_s / 1e12,
+               "kernel": ("k_m2l_wave" if info["m2l_waves"] == 1 else "k_m2l_scaled") if scaled
+               else "k_translate_split", "issued_tflops": issued / avg_s / 1e12,
                "work": f"{nv} translations (V lists and X-list virtual children, levels >= {info['split_level']}) "
                        f"x {nb} densities x {per} flops ({form}, P={P}); {tile_ops} tile products issued"}
     elif stage == "corr":
@@ -269,7 +272,9 @@ def stage_roofline(info, tim, stage, workload_name=None):
             bytes_ = nval * 8 + cells * (4 + 4 + 8 + 16) + m * 8 * nb + n_ * 8 * nb
             kern, what = "k_corr_cells", (f"{nval} distinct values of {nnz} x 8 B ({shared} of {cells} cells "
                                           f"share an identical block) + {cells} cell records")
-            if info["corr_groups"] > 0:
+            if info["corr_one_block"]:
+                kern = "k_fixed_apply (one shared 64 x 64 block over every (cell, density) column)"
+            elif info["corr_groups"] > 0:
                 kern = "k_corr_group + k_corr_cells"
                 what += f", {info['corr_groups']} groups of up to 16 cells"
         else:

@@ -128,12 +128,12 @@ typedef struct {
     int32_t m2l_waves; /* waves per 16-column tile of the M2L kernels: 2 or 4,
                           or 1 = one wave per tile, four tiles per workgroup
                           (scaled forms; the per-offset forms take 4);
-                          0 = 4, or the autotuner's choice */
+                          0 = 1, or the autotuner's choice */
     double lambda;     /* VP_KERNEL_YUKAWA: lambda > 0 (Section 5 uses lambda^2 = 100) */
     int32_t table_waves; /* waves per 16-column tile of the near-table kernel:
                             2 or 4, or 1 = one wave over two tiles (each
                             operator fragment loaded once for both; patterns
-                            of more than 64 points take 2 instead); 0 = 4, or
+                            of more than 64 points take 2 instead); 0 = 1, or
                             the autotuner's choice */
     int32_t reserved;
 } vp_options;
@@ -283,7 +283,8 @@ typedef struct {
                                   values of the shared cells */
     int32_t corr_groups;       /* one density: groups of up to 16 64-column cells reading one
                                   block, applied together on the matrix cores (0: none) */
-    int32_t reserved0;
+    int32_t corr_one_block;    /* 1: every cell is a 64 x 64 block reading one shared block, and C is
+                                  applied as that one fixed operator on the matrix cores */
     double root[3];
     int64_t table_pairs;       /* (target, source) pairs per density served by the near-field
                                   tables (near_pairs holds the pairwise kernel's) */
@@ -291,7 +292,7 @@ typedef struct {
     int64_t n_in;              /* density values per density (n unless oversampled) */
     int32_t os_p, os_q;        /* oversampled plan: nodes per box side (0, 0: none) */
     int32_t kernel;            /* VP_KERNEL_* */
-    int32_t reserved2;
+    int32_t table_pattern;     /* points per pattern leaf of the near-field tables (0: no tables) */
     double lambda;
     int32_t tuned;             /* 0: defaults; 1: tuned by timing in this call; 2: from the cache */
     int32_t m2l_waves;         /* waves per 16-column tile of the M2L kernels */

@@ -296,7 +296,7 @@ static void free_plan(vp_plan_s *P) {
 // life of the process
 // ---------------------------------------------------------------------------
 struct TuneChoice {
-    int m2l_mode = 0, m2l_nw = 4, table_nw = 4, one_stream = 0, max_leaf = 0;
+    int m2l_mode = 0, m2l_nw = 1, table_nw = 1, one_stream = 0, max_leaf = 0;
     float ms = 0.f;
 };
 static std::mutex g_tune_mu;
@@ -811,7 +811,8 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->corr_cells = P->ncell;
     info->corr_shared_cells = P->ncell_shared;
     info->corr_groups = P->nbatch == 1 ? P->ngrp : 0;
-    info->reserved0 = 0;
+    info->corr_one_block = P->corr_op != nullptr ? 1 : 0;
+    info->table_pattern = P->near.active ? P->near.npat : 0;
     info->corr_values_read = P->ncell > 0 ? P->corr_values_read : P->nnz;
     info->table_tile_ops = P->near.table_tile_ops;
     for (int k = 0; k < 3; ++k) info->root[k] = P->opt.root[k];

@@ -2804,9 +2804,9 @@ float autotune(vp_plan_s *P) {
     else knob(P->m2l_mode, {VP_M2L_FP64_SCALED, VP_M2L_FP64_MFMA});
     if (P->opt.m2l_waves == 0) {
         const bool scaled = P->m2l_mode == VP_M2L_FP64_SCALED || P->m2l_mode == VP_M2L_FP32_SCALED;
-        knob(P->m2l_nw, scaled ? std::vector<int>{4, 2, 1} : std::vector<int>{4, 2});
+        knob(P->m2l_nw, scaled ? std::vector<int>{1, 4, 2} : std::vector<int>{1, 2});
     }
-    if (P->opt.table_waves == 0 && P->near.active) knob(P->table_nw, {4, 2, 1});
+    if (P->opt.table_waves == 0 && P->near.active) knob(P->table_nw, {1, 4, 2});
     int one = P->one_stream ? 1 : 0;
     if (!(P->opt.flags & VP_FLAG_ONE_STREAM)) {
         bool &fld = P->one_stream;

@@ -289,8 +289,8 @@ struct vp_plan_s {
     bool self = false;
     bool fp32 = false;
     int m2l_mode = VP_M2L_FP64_MFMA;
-    int m2l_nw = 4;           // waves per 16-column tile of the M2L kernels (4, 2, or 1: one wave per tile)
-    int table_nw = 4;         // waves per tile of the near-table launch (1: one wave over two tiles)
+    int m2l_nw = 1;           // waves per 16-column tile of the M2L kernels (4, 2, or 1: one wave per tile)
+    int table_nw = 1;         // waves per tile of the near-table launch (1: one wave over two tiles)
     int tuned = 0;            // 0: defaults; 1: chosen by timing at plan time; 2: from the tuning cache
     double tune_ms = 0.0;     // plan time spent tuning
     bool one_stream = false;  // no second stream: every kernel on the plan's stream

@@ -72,11 +72,11 @@ class PlanInfo(ctypes.Structure):
                 ("m2l_coarse_translations", ctypes.c_int64), ("m2l_coarse_tile_ops", ctypes.c_int64),
                 ("split_level", ctypes.c_int32), ("corr_cells", ctypes.c_int32),
                 ("corr_shared_cells", ctypes.c_int32), ("corr_values_read", ctypes.c_int64),
-                ("corr_groups", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("corr_groups", ctypes.c_int32), ("corr_one_block", ctypes.c_int32),
                 ("root", ctypes.c_double * 3), ("table_pairs", ctypes.c_int64),
                 ("noalloc_bytes", ctypes.c_int64), ("n_in", ctypes.c_int64),
                 ("os_p", ctypes.c_int32), ("os_q", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32), ("lam", ctypes.c_double), ("tuned", ctypes.c_int32),
+                ("table_pattern", ctypes.c_int32), ("lam", ctypes.c_double), ("tuned", ctypes.c_int32),
                 ("m2l_waves", ctypes.c_int32), ("table_waves", ctypes.c_int32), ("one_stream", ctypes.c_int32),
                 ("tune_ms", ctypes.c_double)]
 
