@@ -59,13 +59,17 @@ C3_NAME = "uniform256x256_gl8_b16"
 # headers, and the named functions of the .hip files), and a change there
 # turns that stage's traffic into null.
 TRAFFIC_WORKLOAD = C3_NAME
-TRAFFIC = {}  # stage -> (read bytes, written bytes, digest) per launch, FP64 p = 30, 16 densities
+TRAFFIC = {  # stage -> (read bytes, written bytes, digest) per launch, FP64 p = 30, 16 densities
+    "m2l": (1278489139, 671406259, "4265be054807a3a4615cfa16b32a912a67aae83a34ad1b9c7a57a3eebc608e1d"),
+    "tables": (1282043023, 536849121, "bcc359c1c4a0d1f12926542ca4b3cf2048508424b80a2c8cf1083fb60413702f"),
+}
 CSRC = os.path.join(ROOT, "paper_2203_05933_amd", "csrc")
 STAGE_SOURCES = {
     "m2l": (["vp_m2l_scaled.hpp", "vp_translate.hpp", "vp_internal.hpp"],
-            {"vp_fmm.hip": ["build_schedules", "launch_m2l", "m2l_scaled", "launch_m2l_scaled"]}),
+            {"vp_fmm.hip": ["build_schedules", "tile_order_by_work", "launch_m2l", "m2l_scaled",
+                            "launch_m2l_scaled"]}),
     "tables": (["vp_translate.hpp", "vp_internal.hpp", "vp_near.hip"],
-               {"vp_fmm.hip": ["launch_tables", "run_tables"]}),
+               {"vp_fmm.hip": ["launch_tables", "run_tables", "tile_order_by_work", "prepare_charges"]}),
     "corr": (["vp_translate.hpp", "vp_internal.hpp"],
              {"vp_fmm.hip": ["correction_apply", "launch_fixed_apply", "build_cells"]}),
 }
