@@ -15,4 +15,8 @@ share come from the seeded generators in vp_workloads.
                          oversampled smooth sum with its adjoint
   yukawa.py            : the modified Helmholtz (Yukawa) smooth sum with
                          G = (lambda^2 / 2 pi) K_0(lambda r), and its transpose
+  corrections.py       : own-cell singular correction blocks of boxes and
+                         straight triangles (exact integrals of G against the
+                         cell's Lagrange basis, less the smooth rule), by polar
+                         coordinates about the target
 """
