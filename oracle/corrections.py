@@ -124,12 +124,15 @@ def _ray_integrals(shape, p, ref, Ainv, o, target, theta, edge_pt, edge_n):
 
 
 def s_row(shape, p, ref, o, A, i, tol=1e-15):
-    """S_i. = integral of G(r, r_i) l_j(r) over the cell, for target node i
-    (absolute tolerance of the angular quadrature: tol times the cell's area
-    times 1 + |log| of its size)."""
+    """S_i. = integral of G(r, r_i) l_j(r) over the cell r = o + A zeta, for
+    target node i (it does not depend on o); absolute tolerance of the angular
+    quadrature: tol times the cell's area times 1 + |log| of its size."""
     ref = np.asarray(ref, dtype=np.float64)
-    o = np.asarray(o, dtype=np.float64)
     A = np.asarray(A, dtype=np.float64)
+    # G depends on r - r_i only (Section 4.2, eq. Vkhat_box): the integral is
+    # that over the cell translated to o = 0, where no coordinate carries the
+    # cell's offset (which would cancel in r - o and lose digits)
+    o = np.zeros(2)
     Ainv = np.linalg.inv(A)
     J = abs(np.linalg.det(A))
     epsabs = tol * J * (1.0 + abs(0.5 * np.log(J)))
@@ -157,10 +160,9 @@ def block(shape, p, ref, wref, o, A, rows=None):
     """Correction block C [N, N] (rows: only those target rows, others zero)."""
     ref = np.asarray(ref, dtype=np.float64)
     wref = np.asarray(wref, dtype=np.float64)
-    o = np.asarray(o, dtype=np.float64)
     A = np.asarray(A, dtype=np.float64)
     N = len(ref)
-    r = o[None, :] + ref @ A.T
+    r = ref @ A.T  # relative to the cell origin (only differences enter)
     J = abs(np.linalg.det(A))
     C = np.zeros((N, N))
     for i in (range(N) if rows is None else rows):
@@ -198,5 +200,27 @@ def polygon_log_integral(verts, t):
         pa, pb = float(e @ (va - foot)), float(e @ (vb - foot))
         H = lambda s: 0.5 * d * d * (np.tan(np.arctan2(s, d)) * (np.log(d) - np.log(np.cos(np.arctan2(s, d))) - 1.5)
                                      + np.arctan2(s, d))
+        total += H(pb) - H(pa)
+    return total
+
+
+def polygon_log_integral_many(verts, t):
+    """polygon_log_integral for many (polygon, target) pairs at once:
+    verts [M, nv, 2] (counter-clockwise), t [M, 2] -> [M]."""
+    verts = np.asarray(verts, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    total = np.zeros(len(t))
+    nv = verts.shape[1]
+    for k in range(nv):
+        va, vb = verts[:, k], verts[:, (k + 1) % nv]
+        e = vb - va
+        e = e / np.linalg.norm(e, axis=1)[:, None]
+        foot = va + e * np.sum(e * (t - va), axis=1)[:, None]
+        d = np.linalg.norm(foot - t, axis=1)
+        pa, pb = np.sum(e * (va - foot), axis=1), np.sum(e * (vb - foot), axis=1)
+
+        def H(s):
+            psi = np.arctan2(s, d)
+            return 0.5 * d * d * (np.tan(psi) * (np.log(d) - np.log(np.cos(psi)) - 1.5) + psi)
         total += H(pb) - H(pa)
     return total
