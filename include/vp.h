@@ -354,6 +354,60 @@ enum {
 vp_status vp_set_timing(vp_plan_t plan, int32_t enable);
 vp_status vp_get_timing(vp_plan_t plan, double *ms, int64_t *nevals);
 
+/*
+ * vp_correction_blocks -- own-cell singular corrections generated on the
+ * device (Section 4.1, eqs. maptri_singular_quad and singcorr_inner_prod;
+ * Section 4.2, eqs. mapbox_singular_quad and Vkhat_box).
+ *
+ * Cells are affine images r = o_k + A_k zeta of one reference cell carrying
+ * one node pattern zeta_j: VP_CELL_BOX ([-1,1]^2, interpolation by
+ * polynomials of degree < p in each variable, N = p^2 nodes) or
+ * VP_CELL_TRIANGLE (the simplex xi, eta >= 0, xi + eta <= 1, total degree
+ * < p, N = p(p+1)/2 nodes).  For cell k, with nodes r_j = o_k + A_k zeta_j and
+ * smooth weights w_j = |det A_k| wref_j, entry (i, j) of block k is
+ *
+ *     C_ij = int_cell G(r, r_i) l_j(r) dA(r)  -  [j != i] G(r_j, r_i) w_j,
+ *
+ * l_j the Lagrange basis of the interpolation space on the pattern: the
+ * correction that turns the smooth rule's sum over the cell into the exact
+ * integral of G against the interpolant of f (the paper writes the same map
+ * through the interpolant's coefficients, V a = f, and the singular integrals
+ * of the basis).  Row i of a block is the own-cell row of target r_i in the
+ * correction matrix C of vp_plan.
+ *
+ * The singular integrals: the reference cell is split at the target into
+ * triangles with the target as apex; on each, log|A (zeta - zeta_i)| = log u +
+ * log|A d(v)| for zeta = zeta_i + u d(v), the u integral is exact (16
+ * Gauss-Legendre points with weights for u and for u log u; polynomials of
+ * degree < 16 along a ray) and the v integral is composite 12-point
+ * Gauss-Legendre graded toward the point of the edge nearest the target in
+ * physical space.  Agreement with direct high-precision integration is near
+ * 1e-14 of the largest entry of a block.
+ *
+ * shape, p      VP_CELL_BOX with 1 <= p <= 8, or VP_CELL_TRIANGLE with
+ *               1 <= p <= 10 (VP_EUNSUPPORTED above).
+ * ref_x, ref_y  HOST [N]: the pattern in reference coordinates, every node at
+ *               least 1e-9 inside the reference cell, unisolvent for the space.
+ * wref          HOST [N]: smooth weights in reference coordinates.
+ * ncell         number of cells, >= 0 (ncell * N below 2^31).
+ * maps          DEVICE [ncell][6]: o_x, o_y, A_00, A_01, A_10, A_11 per cell
+ *               (r = o + A zeta, A row-major), det A != 0; read, not modified.
+ * out           DEVICE [ncell][N][N]: block k, row i, column j; overwritten.
+ * stream        hipStream_t for the copies and the kernel (NULL: the null
+ *               stream).  The call builds the rule tables on the host, copies
+ *               them and the maps' check to and from the device, runs the
+ *               kernel and synchronises the stream before returning (it
+ *               allocates and frees one small device table: a set-up call).
+ * Errors: VP_EINVAL (message from vp_last_error(NULL)) for a NULL pointer, a
+ * node outside the cell, a pattern that is not unisolvent, a non-finite or
+ * singular map; VP_EUNSUPPORTED for an order outside the ranges above;
+ * VP_EDEVICE for a HIP error.  Nothing is written on VP_EINVAL.
+ */
+enum { VP_CELL_BOX = 0, VP_CELL_TRIANGLE = 1 };
+vp_status vp_correction_blocks(int32_t shape, int32_t p, const double *ref_x, const double *ref_y,
+                               const double *wref, int64_t ncell, const double *maps, double *out,
+                               void *stream);
+
 #ifdef __cplusplus
 }
 #endif

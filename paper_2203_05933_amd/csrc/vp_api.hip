@@ -739,6 +739,14 @@ extern "C" vp_status vp_eval_grad_targets(vp_plan_t P, const double *f, double *
     });
 }
 
+extern "C" vp_status vp_correction_blocks(int32_t shape, int32_t p, const double *ref_x, const double *ref_y,
+                                          const double *wref, int64_t ncell, const double *maps, double *out,
+                                          void *stream) {
+    return guarded(nullptr, [&] {
+        vp::correction_blocks(shape, p, ref_x, ref_y, wref, ncell, maps, out, static_cast<hipStream_t>(stream));
+    });
+}
+
 extern "C" vp_status vp_set_stream(vp_plan_t P, void *stream) {
     if (!P) return set_err(nullptr, VP_EINVAL, "plan is NULL");
     P->stream = static_cast<hipStream_t>(stream);

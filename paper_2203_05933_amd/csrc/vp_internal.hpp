@@ -437,6 +437,9 @@ bool pattern_op_supported(int npat, int PD);
 void build_p2p_gather(vp_plan_s *P, const std::vector<int32_t> &leaves, const std::vector<int32_t> &uptr,
                       const std::vector<int32_t> &uidx, const std::vector<int32_t> &sb, const std::vector<int32_t> &se,
                       const double *sx, const double *sy, P2PGather &g);
+// own-cell singular correction blocks of affine cells (vp_correction_blocks)
+void correction_blocks(int shape, int p, const double *ref_x, const double *ref_y, const double *wref,
+                       int64_t ncell, const double *maps, double *out, hipStream_t stream);
 // launch order of tiles with tile_ptr[t+1] - tile_ptr[t] operators: most operators
 // first, dealt to the XCDs in runs of workgroups of `group` consecutive tiles
 std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr, int group = 1);

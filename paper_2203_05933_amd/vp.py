@@ -37,7 +37,7 @@ _ARR_DTYPE = {0: np.int32, 1: np.int32, 2: np.int32, 3: np.int32, 4: np.int32, 5
 # Every entry point declared in include/vp.h.
 EXPORTS = ("vp_default_options", "vp_plan", "vp_plan_oversampled", "vp_eval", "vp_eval_adjoint", "vp_eval_grad_targets",
            "vp_eval_noalloc", "vp_set_stream", "vp_destroy", "vp_last_error", "vp_get_info", "vp_get_array",
-           "vp_set_timing", "vp_get_timing")
+           "vp_set_timing", "vp_get_timing", "vp_correction_blocks")
 STAGES = ("charge", "p2m", "m2m", "m2l", "p2l", "l2l", "p2p", "far", "finish", "tables", "corr", "coarse", "p2m_pat", "m2p")
 
 
@@ -127,6 +127,9 @@ def load_library(path: str = LIB_PATH):
     lib.vp_set_timing.restype = ctypes.c_int
     lib.vp_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.vp_get_timing.restype = ctypes.c_int
+    lib.vp_correction_blocks.argtypes = [ctypes.c_int32, ctypes.c_int32, dp, dp, dp, ctypes.c_int64, dp, dp,
+                                         ctypes.c_void_p]
+    lib.vp_correction_blocks.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -357,6 +360,34 @@ class TargetPotential(torch.autograd.Function):
             gt = (grad * g.unsqueeze(1)).sum(0)
         gf = plan.eval_adjoint(g.contiguous()) if ctx.needs_input_grad[1] else None
         return gt, gf, None
+
+
+CELL_SHAPES = {"box": 0, "triangle": 1}
+
+
+def correction_blocks(shape: str, p: int, ref_x, ref_y, wref, maps: torch.Tensor,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Own-cell singular correction blocks on the device (vp_correction_blocks).
+
+    shape: "box" (N = p^2 nodes) or "triangle" (N = p(p+1)/2); ref_x, ref_y,
+    wref: the node pattern and its smooth weights in reference coordinates
+    (host arrays); maps: float64 device tensor [ncell, 6] of (o_x, o_y, A_00,
+    A_01, A_10, A_11).  Returns the float64 device tensor [ncell, N, N]."""
+    lib = load_library()
+    rx, ry, rw = _host(ref_x, np.float64), _host(ref_y, np.float64), _host(wref, np.float64)
+    N = rx.shape[0]
+    if maps.dtype != torch.float64 or not maps.is_cuda or maps.dim() != 2 or maps.shape[1] != 6:
+        raise ValueError("maps must be a float64 device tensor [ncell, 6]")
+    maps = maps.contiguous()
+    ncell = maps.shape[0]
+    if out is None:
+        out = torch.empty((ncell, N, N), dtype=torch.float64, device=maps.device)
+    st = lib.vp_correction_blocks(CELL_SHAPES[shape], p, _ptr(rx), _ptr(ry), _ptr(rw), ncell,
+                                  ctypes.c_void_p(maps.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  _current_stream())
+    if st != VP_OK:
+        raise VPError(st, lib.vp_last_error(None).decode())
+    return out
 
 
 def volume_potential(f: torch.Tensor, plan: Plan) -> torch.Tensor:

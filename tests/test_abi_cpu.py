@@ -177,3 +177,47 @@ def test_yukawa_unsupported_forms(case):
     st, h, msg = _plan(lib, vp, x, y, w, 8, **kw)
     assert st == vp.VP_EUNSUPPORTED, (st, msg)
     assert h.value is None
+
+
+@pytest.mark.parametrize("case", ["shape", "order0", "order_big", "null_ref", "outside_box", "outside_tri",
+                                  "duplicate", "ncell_neg", "null_maps", "ok_box", "ok_tri"])
+def test_correction_blocks_host_checks(case):
+    """vp_correction_blocks checks the pattern (and, with no cells, returns
+    before any device call)."""
+    from vp_workloads import generators as gen
+    vp, lib = _lib()
+    xb, yb, wb = gen.gauss_legendre_box_nodes(4)
+    xt, yt, wt = gen.triangle_lattice_pattern(5)
+    shape, p, x, y, w, ncell, maps = 0, 4, xb, yb, wb, 0, None
+    expect = vp.VP_EINVAL
+    if case == "shape":
+        shape = 2
+    elif case == "order0":
+        p = 0
+    elif case == "order_big":
+        p, expect = 9, vp.VP_EUNSUPPORTED
+        x = y = w = np.zeros(81)
+    elif case == "null_ref":
+        x = None
+    elif case == "outside_box":
+        x = xb.copy()
+        x[3] = 1.0
+    elif case == "outside_tri":
+        shape, p, x, y, w = 1, 5, xt.copy(), yt, wt
+        x[0] = -1e-12
+    elif case == "duplicate":
+        shape, p, x, y, w = 1, 5, xt.copy(), yt.copy(), wt
+        x[1], y[1] = x[0], y[0]
+    elif case == "ncell_neg":
+        ncell = -1
+    elif case == "null_maps":
+        ncell = 3
+    elif case == "ok_box":
+        expect = vp.VP_OK
+    elif case == "ok_tri":
+        shape, p, x, y, w, expect = 1, 5, xt, yt, wt, vp.VP_OK
+    p_ = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(ctypes.c_void_p)
+    st = lib.vp_correction_blocks(shape, p, p_(x), p_(y), p_(w), ncell, maps, None, None)
+    assert st == expect, (st, lib.vp_last_error(None))
+    if expect != vp.VP_OK:
+        assert len(lib.vp_last_error(None)) > 0

@@ -429,6 +429,51 @@ def _interleave(ix: int, iy: int) -> int:
     return k
 
 
+def star_band_triangles(n_sectors: int = 2048):
+    """The boundary band of the star domain: n_sectors angular sectors between
+    rho = r - 0.01 and r, each split into two triangles; [2 n_sectors, 3, 2]
+    vertex coordinates (counter-clockwise)."""
+    th = 2.0 * np.pi * np.arange(n_sectors + 1) / n_sectors
+    rout = star_radius(th)
+    rin = rout - 0.01
+    P_in = np.stack([rin * np.cos(th), rin * np.sin(th)], axis=1)
+    P_out = np.stack([rout * np.cos(th), rout * np.sin(th)], axis=1)
+    tris = []
+    for k in range(n_sectors):
+        tris.append((P_in[k], P_out[k], P_out[k + 1]))
+        tris.append((P_in[k], P_out[k + 1], P_in[k + 1]))
+    return np.array(tris)
+
+
+def triangle_lattice_pattern(p: int = 9, shrink: float = 0.9):
+    """A node pattern on the reference simplex for interpolation of total
+    degree < p: the principal lattice (i, j) / (p - 1), i + j < p, contracted
+    by `shrink` toward the centroid so every node is interior; p (p + 1) / 2
+    nodes, with equal reference weights (summing to the area 1/2).  Returns
+    (xi, eta, wref)."""
+    if p == 1:  # one node: the centroid
+        return np.array([1.0 / 3.0]), np.array([1.0 / 3.0]), np.array([0.5])
+    lat = np.array([(i / (p - 1), j / (p - 1)) for i in range(p) for j in range(p - i)])
+    ref = 1.0 / 3.0 + shrink * (lat - 1.0 / 3.0)
+    n = ref.shape[0]
+    return ref[:, 0].copy(), ref[:, 1].copy(), np.full(n, 0.5 / n)
+
+
+def cell_maps(origins, A):
+    """[ncell, 6] rows (o_x, o_y, A_00, A_01, A_10, A_11) of affine cell maps
+    r = o + A zeta (origins [ncell, 2], A [ncell, 2, 2])."""
+    origins = np.asarray(origins, dtype=np.float64)
+    A = np.asarray(A, dtype=np.float64)
+    return np.concatenate([origins, A.reshape(-1, 4)], axis=1)
+
+
+def triangle_maps(tris):
+    """Cell maps of triangles [ntri, 3, 2]: o = v0, A = [v1 - v0, v2 - v0] (columns)."""
+    tris = np.asarray(tris, dtype=np.float64)
+    A = np.stack([tris[:, 1] - tris[:, 0], tris[:, 2] - tris[:, 0]], axis=2)
+    return cell_maps(tris[:, 0], A)
+
+
 def config1(n_sectors: int = 2048, tri_nodes: int = 45):
     """Star-shaped domain r = 1 + 0.3 cos 5 theta, about 1.5M nodes.
 
@@ -456,15 +501,7 @@ def config1(n_sectors: int = 2048, tri_nodes: int = 45):
 
     # --- triangle band
     rng_t = np.random.default_rng(11)
-    th = 2.0 * np.pi * np.arange(n_sectors + 1) / n_sectors
-    rout = star_radius(th)
-    rin = rout - 0.01
-    P_in = np.stack([rin * np.cos(th), rin * np.sin(th)], axis=1)
-    P_out = np.stack([rout * np.cos(th), rout * np.sin(th)], axis=1)
-    tris = []
-    for k in range(n_sectors):
-        tris.append((P_in[k], P_out[k], P_out[k + 1]))
-        tris.append((P_in[k], P_out[k + 1], P_in[k + 1]))
+    tris = star_band_triangles(n_sectors)
     tx_list, ty_list, tw_list = [], [], []
     for (a, b, c) in tris:
         lam = rng_t.dirichlet(np.ones(3), tri_nodes)
