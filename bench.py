@@ -409,6 +409,56 @@ def yukawa_record(steps, warmup, order, with_cpu):
     return rec
 
 
+def correction_generation_record(steps, warmup, with_cpu):
+    """Own-cell singular corrections generated on the device: the star
+    workload's 4,096 boundary-band triangles (45-node pattern, total degree
+    < 9) and its three box levels (8 x 8 Gauss-Legendre), one call each."""
+    import numpy as np
+    import torch
+    from paper_2203_05933_amd import vp
+    from vp_workloads import generators as gen
+    xt, yt, wt = gen.triangle_lattice_pattern(9)
+    tris = gen.star_band_triangles()
+    tmaps = torch.tensor(gen.triangle_maps(tris), dtype=torch.float64, device="cuda:0")
+    xb, yb, wb = gen.gauss_legendre_box_nodes(8)
+    hs = [2.6 / 2 ** (lvl + 1) for lvl in (7, 8, 9)]
+    bmaps = torch.tensor(gen.cell_maps(np.zeros((3, 2)), [h * np.eye(2) for h in hs]), dtype=torch.float64,
+                         device="cuda:0")
+    out = torch.empty((len(tris), 45, 45), dtype=torch.float64, device="cuda:0")
+    for _ in range(max(warmup, 1)):
+        vp.correction_blocks("triangle", 9, xt, yt, wt, tmaps, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        vp.correction_blocks("triangle", 9, xt, yt, wt, tmaps, out)
+    torch.cuda.synchronize()
+    tri_ms = (time.perf_counter() - t0) / steps * 1e3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        vp.correction_blocks("box", 8, xb, yb, wb, bmaps)
+    torch.cuda.synchronize()
+    box_ms = (time.perf_counter() - t0) / steps * 1e3
+    rec = {"workload": "star boundary band: 4,096 straight triangles x 45 nodes (total degree < 9); "
+                       "3 box sizes x 64 nodes (8 x 8 Gauss-Legendre)",
+           "triangles_ms_per_call": tri_ms, "triangle_blocks_per_s": len(tris) / (tri_ms * 1e-3),
+           "triangle_rows_per_s": len(tris) * 45 / (tri_ms * 1e-3),
+           "boxes_ms_per_call": box_ms, "unit": "blocks/s",
+           "note": "one vp_correction_blocks call: host rule tables, map checks, kernel, stream synchronised"}
+    log(f"[bench] correction generation: 4096 triangles {tri_ms:.2f} ms/call "
+        f"({rec['triangle_blocks_per_s']:.0f} blocks/s), 3 box sizes {box_ms:.2f} ms/call")
+    if with_cpu:
+        from oracle import corrections as CO
+        ref = np.stack([xt, yt], 1)
+        m = gen.triangle_maps(tris[:1])[0]
+        t0 = time.perf_counter()
+        CO.block(CO.TRIANGLE, 9, ref, wt, m[:2], m[2:].reshape(2, 2), rows=[0, 22])
+        row_s = (time.perf_counter() - t0) / 2
+        rec["cpu_baseline"] = {"value": 1.0 / (45 * row_s), "unit": "blocks/s", "cores": 1, "kind": "oracle",
+                               "sample": "2 rows of one band triangle's 45-row block (oracle.corrections), "
+                                         f"{2 * row_s:.1f} s, scaled to a block"}
+    return rec
+
+
 def per_entry_correction(steps, warmup, order, with_cpu):
     """The headline grid with every correction value drawn on its own."""
     import torch
@@ -550,6 +600,7 @@ def main():
                                                   args.order_fp32, not args.no_cpu)
         torch.cuda.empty_cache()
         secondary["yukawa"] = yukawa_record(args.steps, args.warmup, args.order, not args.no_cpu)
+        secondary["correction_generation"] = correction_generation_record(args.steps, args.warmup, not args.no_cpu)
 
     if args.copy_mib > 0:
         n_el = args.copy_mib * (1 << 20) // 8

@@ -2,10 +2,10 @@
 Section 4.1 eq. singcorr_inner_prod, Section 4.2 eq. mapbox_singular_quad)
 against the CPU oracle (oracle.corrections), through the C ABI.
 
-Tolerance: rows of a block agree with the oracle to 1e-12 of the row's
+Tolerance: rows of a block agree with the oracle to 2e-13 of the row's
 largest entry (the two integrate the same singular integrals by different
 rules: Duffy rays with exact u moments and graded v panels, against polar
-coordinates with tanh-sinh radii and adaptive angles).  At the full size of
+coordinates with tanh-sinh radii and adaptive angles; measured up to 9e-14).  At the full size of
 the star workload's 4,096 boundary triangles, every row is checked against a
 property that holds at any size: its entries plus the smooth weights sum to
 the closed-form integral of G over the cell (the Lagrange basis sums to one).
@@ -60,7 +60,7 @@ def test_box_blocks_match_oracle():
         for i in (0, 27, 63):
             err = np.max(np.abs(C[k, i] - Co[i])) / np.max(np.abs(Co[i]))
             print(f"box h={h} row {i}: rel {err:.2e}")
-            assert err <= 1e-12
+            assert err <= 2e-13
 
 
 @pytest.mark.parametrize("which", ["band0", "band_last", "skinny", "clockwise"])
@@ -80,7 +80,7 @@ def test_triangle_blocks_match_oracle(which):
     for i in rows:
         err = np.max(np.abs(C[i] - Co[i])) / np.max(np.abs(Co[i]))
         print(f"triangle {which} row {i}: rel {err:.2e}")
-        assert err <= 1e-12
+        assert err <= 2e-13
 
 
 def test_star_band_triangles_full_size_row_sums():
@@ -110,7 +110,7 @@ def test_star_band_triangles_full_size_row_sums():
     exact = G_SCALE * CO.polygon_log_integral_many(np.repeat(ccw, 45, axis=0), targets.reshape(-1, 2))
     err = np.abs(S_sum.ravel() - exact) / (J.repeat(45) * (1.0 + np.abs(np.log(np.sqrt(J.repeat(45))))))
     print(f"4096 band triangles: max row-sum error {err.max():.2e} (units of area x log size)")
-    assert err.max() <= 1e-12
+    assert err.max() <= 1e-13
 
 
 def test_box_levels_full_blocks_row_sums_and_repeatability():
@@ -131,7 +131,7 @@ def test_box_levels_full_blocks_row_sums_and_repeatability():
         exact = np.array([G_SCALE * CO.box_log_integral(-h, h, -h, h, h * ref[i]) for i in range(64)])
         err = np.max(np.abs(S_sum - exact)) / (h * h * (1 + abs(np.log(h))))
         print(f"box h={h}: max row-sum error {err:.2e}")
-        assert err <= 1e-12
+        assert err <= 1e-13
 
 
 def test_edge_cases():
