@@ -238,7 +238,7 @@ template <class E, int PR>
 __global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, const int4 *__restrict__ cslot,
                                             int nbatch, int P, int PD, const E *__restrict__ QT,
                                             const E *__restrict__ tin, const E *__restrict__ tout,
-                                            E *__restrict__ X) {
+                                            E *__restrict__ X, int chunk) {
     constexpr int H = 64 / PR;       // row groups in the wave
     __shared__ E ys[4][PR][2];       // scaled child columns (re, im interleaved)
     __shared__ E red[H][PR][2];      // per-group partial rows
@@ -250,7 +250,8 @@ __global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, c
     const int b = boxes[blockIdx.x];
     const int4 cs = cslot[blockIdx.x];
     auto child = [&](int c) { return c == 0 ? cs.x : (c == 1 ? cs.y : (c == 2 ? cs.z : cs.w)); };
-    for (int bt = 0; bt < nbatch; ++bt) {
+    const int bt_end = min(nbatch, (int)(blockIdx.y + 1) * chunk);
+    for (int bt = blockIdx.y * chunk; bt < bt_end; ++bt) {
 #pragma unroll
         for (int j = 0; j < 4 / H; ++j) {
             const int c = gi + H * j, ch = child(c);
@@ -314,7 +315,7 @@ template <class E, int PR>
 __global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, const int32_t *__restrict__ pcls,
                                             int nboxes, int nbatch, int P, int PD, const E *__restrict__ QT,
                                             const E *__restrict__ tin, const E *__restrict__ tout,
-                                            E *__restrict__ X) {
+                                            E *__restrict__ X, int chunk) {
     constexpr int H = 64 / PR;
     __shared__ E ys[H][PR][2];
     const int lane = threadIdx.x;
@@ -335,7 +336,8 @@ __global__ void __launch_bounds__(64) k_l2l(const int32_t *__restrict__ boxes, c
         vr = tout[(cls * P + l) * 2];
         vi = tout[(cls * P + l) * 2 + 1];
     }
-    for (int bt = 0; bt < nbatch; ++bt) {
+    const int bt_end = min(nbatch, (int)(blockIdx.y + 1) * chunk);
+    for (int bt = blockIdx.y * chunk; bt < bt_end; ++bt) {
         E yr = (E)0, yi = (E)0, or_ = (E)0, oi = (E)0;
         E *o = X + ((int64_t)b * nbatch + bt) * PD;
         if (row) {
@@ -613,38 +615,39 @@ __device__ inline double vp_log(double x) {
 
 // Table-driven base-2 logarithm for the pairwise near field (the
 // table-lookup scheme of P. T. P. Tang, ACM TOMS 16, 1990, with our own
-// table and series): x = 2^e m, m in [1/2, 1); the top 7 fraction bits i of
-// m select inv_c = fl(1/c_i), c_i the centre of m's interval of width 2^-8,
-// and L_i = -log2(inv_c) (both from the host, LOG_TABLE entries);
-// u = m inv_c - 1 (one rounding, |u| <= 2^-8) and
-// log2 x = e + L_i + u p(u), with p(u) = log2(1 + u)/u by its Taylor series
-// through u^5 (truncation below 2^-60).  The pair loop sums base-2
-// logarithms and each target's sum is multiplied by log 2 once, so the
-// exponent enters as one add instead of a two-part product.
+// table and series): x = 2^e m, m in [1/2, 1); the top LOG_BITS fraction
+// bits i of m select inv_c = fl(1/c_i), c_i the centre of m's interval of
+// width 2^-(LOG_BITS+1), and L_i = -log2(inv_c) (both from the host,
+// LOG_TABLE entries); u = m inv_c - 1 (one rounding, |u| <= 2^-(LOG_BITS+1))
+// and log2 x = e + L_i + u p(u), with p(u) = log2(1 + u)/u by its Taylor
+// series through u^LOG_DEG (truncation of u p(u) below 2^-56).  The pair loop
+// sums base-2 logarithms and each target's sum is multiplied by log 2 once,
+// so the exponent enters as one add instead of a two-part product.
 //
 // Table layout in LDS: the entry of fraction bits i sits at LOG_BASE + i,
-// found from bits 13..21 of m's high word (the 7 fraction bits and the two
-// lowest exponent bits, 01 for every m in [1/2, 1)).  x = 0 has m = 0 and
-// e = 0 and so selects entry 0, which holds (0, p(-1)): u = -1 and the sum
-// -p(-1) + p(-1) is exactly zero.  A zero distance (the self pair) thus
-// contributes exactly nothing without a compare or select in the pair loop.
-// Entries 1 .. LOG_BASE-1 are never read; the kernel keeps its source tiles
-// there.
-constexpr int LOG_BASE = 256;
+// found from the LOG_BITS fraction bits and the two lowest exponent bits of
+// m's high word (10 for every m in [1/2, 1): LOG_BASE = 2^(LOG_BITS+1)).
+// x = 0 has m = 0 and e = 0 and so selects entry 0, which holds (0, p(-1)):
+// u = -1 and the sum -p(-1) + p(-1) is exactly zero.  A zero distance (the
+// self pair) thus contributes exactly nothing without a compare or select in
+// the pair loop.  Entries 1 .. LOG_BASE-1 are never read; the kernel keeps
+// its source tiles there when they fit.
+constexpr int LOG_BASE = 2 << LOG_BITS;
+constexpr int LOG_DEG = (56 + LOG_BITS) / (LOG_BITS + 1) - 2;  // smallest D with 2^-(B+1)(D+2) <= 2^-56
 
 __device__ inline double log2p1_over_u(double u) {
     constexpr double IL2 = 1.44269504088896340736;  // 1 / log 2
-    double p = fma(u, -IL2 / 6.0, IL2 / 5.0);
-    p = fma(u, p, -IL2 / 4.0);
-    p = fma(u, p, IL2 / 3.0);
-    p = fma(u, p, -IL2 / 2.0);
-    return fma(u, p, IL2);
+    // IL2 sum_{k <= LOG_DEG} (-u)^k / (k + 1), by Horner
+    double p = ((LOG_DEG & 1) ? -IL2 : IL2) / (LOG_DEG + 1);
+#pragma unroll
+    for (int k = LOG_DEG - 1; k >= 0; --k) p = fma(u, p, ((k & 1) ? -IL2 : IL2) / (k + 1));
+    return p;
 }
 
 __device__ inline double vp_log2_tab(double x, const double2 *__restrict__ tab) {
     const int e = __builtin_amdgcn_frexp_exp(x);
     const double m = __builtin_amdgcn_frexp_mant(x);
-    const unsigned i = ((unsigned)__double2hiint(m) >> 13) & 511u;
+    const unsigned i = ((unsigned)__double2hiint(m) >> (20 - LOG_BITS)) & ((4u << LOG_BITS) - 1u);
     const double2 t = tab[i];
     const double u = fma(m, t.x, -1.0);
     return (double)e + fma(u, log2p1_over_u(u), t.y);
@@ -1937,7 +1940,10 @@ static void launch_m2l(vp_plan_s *P, int part) {
         sa.tile_ptr = S.tptr;
         sa.tile_ops = S.tops;
         sa.tile_src = S.tsrc;
-        sa.tile_order = P->m2l_nw == 1 ? S.torder4 : S.torder;
+        // the launch below the split level has few tiles on small trees: give
+        // each tile the most waves there (its latency sets the coarse chain)
+        const int nw = part == 1 && (a.ncols + 15) / 16 < 1024 ? 4 : P->m2l_nw;
+        sa.tile_order = nw == 1 ? S.torder4 : S.torder;
         sa.P = Pn;
         sa.box_stride = (int64_t)nb * PD;
         sa.bt_stride = PD;
@@ -1946,7 +1952,6 @@ static void launch_m2l(vp_plan_s *P, int part) {
         sa.xinit = P->x_init;
         sa.level = T.level;
         sa.logside = T.d_logside;
-        const int nw = P->m2l_nw;
         if (!f32)
             m2l_scaled<double, double, double>(s, nw, O.PQ, sa, O.m2l_q64, O.m2l_tin64, O.m2l_logt,
                                                (const double *)M, (double *)L);
@@ -1988,6 +1993,15 @@ static void run_p2m(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool tab
     VP_LAUNCH_CHECK();
 }
 
+// Densities per workgroup of a per-level M2M / L2L launch: all of them when
+// the level has enough boxes to fill the chip, else fewer, with the
+// densities spread over blockIdx.y (a wave otherwise walks every density of
+// its boxes in turn, and the coarse levels' few waves set the launch time)
+static int density_chunk(int nblocks, int nbatch) {
+    const int want = std::max(1, std::min(nbatch, 2048 / std::max(nblocks, 1)));
+    return (nbatch + want - 1) / want;
+}
+
 // M2M for the parents on levels l_hi down to l_lo (one launch per level)
 template <class E>
 static void run_m2m(vp_plan_s *P, const BoxGeo &G, int l_hi, int l_lo) {
@@ -2002,11 +2016,13 @@ static void run_m2m(vp_plan_s *P, const BoxGeo &G, int l_hi, int l_lo) {
     for (int l = l_hi; l >= l_lo; --l) {
         const int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
         if (c1 <= c0) continue;
+        const int chunk = density_chunk(c1 - c0, nb);
+        const dim3 grid((unsigned)(c1 - c0), (unsigned)((nb + chunk - 1) / chunk));
         switch (O.PR) {
 #define VP_M2M(PR)                                                                                                 \
     case PR:                                                                                                       \
-        hipLaunchKernelGGL((k_m2m<E, PR>), dim3(c1 - c0), dim3(64), 0, s, P->m2m_parents + c0,                   \
-                           reinterpret_cast<const int4 *>(P->m2m_cslot) + c0, nb, Pn, PD, shq, shi, sho, M);       \
+        hipLaunchKernelGGL((k_m2m<E, PR>), grid, dim3(64), 0, s, P->m2m_parents + c0,                            \
+                           reinterpret_cast<const int4 *>(P->m2m_cslot) + c0, nb, Pn, PD, shq, shi, sho, M, chunk); \
         break;
             VP_M2M(16) VP_M2M(32) VP_M2M(64)
 #undef VP_M2M
@@ -2031,11 +2047,13 @@ static void run_l2l(vp_plan_s *P, const BoxGeo &G, int l_lo, int l_hi) {
         const int c0 = P->lvl_box_begin[l], c1 = P->lvl_box_begin[l + 1];
         if (c1 <= c0) continue;
         const unsigned nblk = (unsigned)((c1 - c0 + 64 / O.PR - 1) / (64 / O.PR));
+        const int chunk = density_chunk((int)nblk, nb);
+        const dim3 grid(nblk, (unsigned)((nb + chunk - 1) / chunk));
         switch (O.PR) {
 #define VP_L2L(PR)                                                                                               \
     case PR:                                                                                                     \
-        hipLaunchKernelGGL((k_l2l<E, PR>), dim3(nblk), dim3(64), 0, s, P->lvl_boxes + c0, P->lvl_pcls + c0,      \
-                           c1 - c0, nb, Pn, PD, shq, shi, sho, L);                                               \
+        hipLaunchKernelGGL((k_l2l<E, PR>), grid, dim3(64), 0, s, P->lvl_boxes + c0, P->lvl_pcls + c0,           \
+                           c1 - c0, nb, Pn, PD, shq, shi, sho, L, chunk);                                        \
         break;
             VP_L2L(16) VP_L2L(32) VP_L2L(64)
 #undef VP_L2L

@@ -159,8 +159,10 @@ struct Operators {
 
 // near-field table slots per target level: 9 same level, 16 coarser, 16 finer
 constexpr int NTOPS = 41;
-// entries of the logarithm table of the pairwise near field (top fraction bits of the mantissa)
-constexpr int LOG_TABLE = 128;
+// logarithm table of the pairwise near field: LOG_BITS top fraction bits of
+// the mantissa select one of LOG_TABLE entries
+constexpr int LOG_BITS = 7;
+constexpr int LOG_TABLE = 1 << LOG_BITS;
 
 // Pairwise near-field sources of a list of target leaves, gathered once at
 // plan time (static geometry): for leaf k of the list, entries

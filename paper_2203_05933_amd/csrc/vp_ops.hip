@@ -186,7 +186,8 @@ void build_operators(vp_plan_s *P) {
         logt[2 * code + 1] = lg.imag();
     }
     // logarithm table of the pairwise near field: m in [1/2, 1) with top fraction
-    // bits i lies in [1/2 + i/256, 1/2 + (i+1)/256); c_i is that interval's centre
+    // bits i lies in [1/2 + i/(2 LOG_TABLE), 1/2 + (i+1)/(2 LOG_TABLE)); c_i is
+    // that interval's centre
     std::vector<double> ltab(2 * LOG_TABLE);
     for (int i = 0; i < LOG_TABLE; ++i) {
         const double c = 0.5 + (i + 0.5) / (2.0 * LOG_TABLE);
