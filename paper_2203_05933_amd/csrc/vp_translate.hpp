@@ -248,6 +248,7 @@ struct FinishArgs {
     const int32_t *perm = nullptr; // sorted target -> user index
     int64_t m = 0;                 // output row length
     double *u = nullptr;
+    int one_box = 0;               // nbatch % 16 == 0: the 16 columns of a tile are one box's densities
 };
 
 // ALDS: the operator sits in LDS, copied once per workgroup, instead of in
@@ -308,6 +309,32 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
             if constexpr (ALDS) __builtin_amdgcn_sched_barrier(0);
         }
         // element i of a lane: output row r * 16 + cl of tile column M::row(i, g)
+        if (FIN && fin.one_box) {
+            // one box per tile: its target rows and their permutation once for
+            // all sixteen densities (the general path below reloads them per column)
+            const int box = cols_box[t * 16 / nbatch];
+            const int64_t t0 = oa.off(box);
+            int pr[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int row = r * 16 + cl;
+                pr[r] = row < nrows_out ? fin.perm[t0 + row] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int bt = (t * 16 + M::row(i, g)) % nbatch;
+                const double *nr = fin.near + (int64_t)bt * oa.bstride + t0;
+                double *ub = fin.u + (int64_t)bt * fin.m;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const int row = r * 16 + cl;
+                    if (row < nrows_out) {
+                        double *o = ub + pr[r];
+                        *o = (nr[row] + (double)accs[r][i]) + *o;
+                    }
+                }
+            }
+        } else
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int col = t * 16 + M::row(i, g);
