@@ -299,6 +299,10 @@ typedef struct {
     int32_t table_waves;       /* waves per tile of the near-table kernel */
     int32_t one_stream;        /* 1: every kernel of an evaluation on the plan's stream */
     double tune_ms;            /* plan time spent timing candidates */
+    int32_t l2p_from_parents;  /* 1: forward evaluations evaluate the deepest level's pattern leaves
+                                  from their parents' local expansions (L2L into that level folded
+                                  into the L2P matrices; uniform grids, densities a multiple of 16) */
+    int32_t reserved3;
 } vp_plan_info_t;
 
 vp_status vp_get_info(vp_plan_t plan, vp_plan_info_t *info);

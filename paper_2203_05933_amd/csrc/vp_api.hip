@@ -835,6 +835,7 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->table_waves = P->table_nw;
     info->one_stream = P->one_stream ? 1 : 0;
     info->tune_ms = P->tune_ms;
+    info->l2p_from_parents = P->near.par_l2p ? 1 : 0;
     if (P->yk.active) {
         info->m2l_translations = P->yk.m2l_translations;
         info->m2l_tile_ops = P->yk.m2l_tile_ops;

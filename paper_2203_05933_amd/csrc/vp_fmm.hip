@@ -2486,7 +2486,8 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
     if (fmm) {
         if (coarse && !one) VP_HIP(hipStreamWaitEvent(ms, P->ev_coarse, 0));
         P->stage_begin(VP_STAGE_L2L);
-        run_l2l<E>(P, G, L0, Lmax);
+        // with the parents' L2P, the deepest level takes no L2L (forward only)
+        run_l2l<E>(P, G, L0, fused && N.par_l2p ? N.par_level - 1 : Lmax);
         P->stage_end(VP_STAGE_L2L);
     }
     P->stage_begin(VP_STAGE_FAR);
@@ -2507,6 +2508,10 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
             fin.m = P->m;
             fin.u = u;
             fin.one_box = P->nbatch % 16 == 0 ? 1 : 0;
+            if (N.par_l2p) {
+                fin.par_op = N.l2p_par_op;
+                fin.pc = N.l2p_pc;
+            }
             run_far<E, false>(P, R, G, P->acc_far, tables, 1, fin);
         } else if (fmm) {
             run_far<E, false>(P, R, G, P->acc_far, tables, 1);

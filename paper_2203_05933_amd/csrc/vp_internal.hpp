@@ -243,6 +243,13 @@ struct NearTables {
     int n_zero_near = 0, n_zero_far = 0;
     int32_t *far_add = nullptr;       // [nbox] 1: the pattern L2P adds (W lists wrote first); null: none
     bool fused_finish = false;        // forward: the pattern L2P writes the output (see vp_near.hip)
+    // forward with the fused finish: the pattern leaves fill the deepest level
+    // par_level, whose L2P starts from the parents' local expansions (the L2L
+    // into that level folded into l2p_par_op, one matrix per child class)
+    bool par_l2p = false;
+    int par_level = 0;
+    double *l2p_par_op = nullptr;     // [4][A-fragment order of npat x PD]
+    int32_t *l2p_pc = nullptr;        // [nbox] parent * 4 + child class of the pattern leaves
     std::vector<double> pat_rx, pat_ry;  // the node pattern, box-relative in units of the side
     // [5][PD x npat] A-fragment order: the leaf P2M, then the four quadrant
     // P2M matrices (about the quadrant centre at the children's scale, zero

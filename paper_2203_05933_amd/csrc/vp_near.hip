@@ -469,6 +469,64 @@ void build_near_tables(vp_plan_s *P) {
             }
         }
         vp_to_frag(B.data(), np, PD, PD, Bf.data());
+        // The pattern leaves fill the tree's deepest level and no other box sits
+        // there (uniform grids), with the fused finish: their L2P can start from
+        // the parents' local expansions, the L2L into that level folded into
+        // one matrix per child class q, B_q = L2P x L2L_q, and forward
+        // evaluations skip that L2L launch.  L2L_q as in the scaled form of
+        // the translations (t = child offset / parent side = (+-1/4, +-1/4)):
+        // B'_l = 2^-l t^-l sum_{k >= l} C(k, l) t^k B_k.
+        N.par_l2p = false;
+        if (!P->fp32 && N.fused_finish && P->nbatch % 16 == 0 && !l2p_pat.empty()) {
+            const int Lf = lev[l2p_pat[0]];
+            bool ok = Lf >= 3 && Lf == T.nlevels - 1;
+            for (int b : l2p_pat) ok = ok && lev[b] == Lf;
+            int at_lf = 0;
+            for (int b = 0; b < nbox; ++b) at_lf += lev[b] == Lf ? 1 : 0;
+            ok = ok && at_lf == (int)l2p_pat.size();
+            if (ok) {
+                std::vector<int32_t> par(nbox);
+                VP_HIP(hipMemcpyAsync(par.data(), T.parent, 4 * nbox, hipMemcpyDeviceToHost, s));
+                VP_HIP(hipStreamSynchronize(s));
+                std::vector<std::vector<long double>> Cb(Pn, std::vector<long double>(Pn, 0.0L));
+                for (int k = 0; k < Pn; ++k) {
+                    Cb[k][0] = 1.0L;
+                    for (int l = 1; l <= k; ++l) Cb[k][l] = Cb[k - 1][l - 1] + (l < k ? Cb[k - 1][l] : 0.0L);
+                }
+                std::vector<double> Tq((size_t)PD * PD), Bq((size_t)np * PD), Bqf((size_t)4 * np * PD);
+                for (int q = 0; q < 4; ++q) {
+                    const std::complex<long double> t(0.25L * ((q & 1) ? 1 : -1), 0.25L * ((q >> 1) ? 1 : -1));
+                    std::fill(Tq.begin(), Tq.end(), 0.0);
+                    for (int j = 0; j < 2 * Pn; ++j) {
+                        // input column j: B_k = 1 (j = k) or i (j = Pn + k)
+                        const int k = j < Pn ? j : j - Pn;
+                        const std::complex<long double> bk = j < Pn ? std::complex<long double>(1, 0)
+                                                                    : std::complex<long double>(0, 1);
+                        const std::complex<long double> tk = std::pow(t, k);
+                        for (int l = 0; l <= k; ++l) {
+                            const std::complex<long double> v =
+                                std::pow(0.5L, l) * std::pow(t, -l) * Cb[k][l] * tk * bk;
+                            Tq[(size_t)l * PD + j] = (double)v.real();
+                            Tq[(size_t)(Pn + l) * PD + j] = (double)v.imag();
+                        }
+                    }
+                    for (int i = 0; i < np; ++i)
+                        for (int j = 0; j < PD; ++j) {
+                            long double acc = 0.0L;
+                            for (int r = 0; r < PD; ++r) acc += (long double)B[(size_t)i * PD + r] * Tq[(size_t)r * PD + j];
+                            Bq[(size_t)i * PD + j] = (double)acc;
+                        }
+                    vp_to_frag(Bq.data(), np, PD, PD, Bqf.data() + (size_t)q * np * PD);
+                }
+                std::vector<int32_t> pc(nbox, 0);
+                for (int b : l2p_pat) pc[b] = par[b] * 4 + ((ix[b] & 1) | ((iy[b] & 1) << 1));
+                N.l2p_par_op = upload(P, Bqf);
+                N.l2p_pc = upload(P, pc);
+                N.par_l2p = true;
+                N.par_level = Lf;
+                VP_HIP(hipStreamSynchronize(s));  // Bqf, pc leave scope
+            }
+        }
         if (P->fp32) {
             std::vector<float> af(Af.begin(), Af.end()), bf(Bf.begin(), Bf.end());
             N.p2m_op_f32 = upload(P, af);

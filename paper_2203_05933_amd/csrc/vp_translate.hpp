@@ -249,6 +249,10 @@ struct FinishArgs {
     int64_t m = 0;                 // output row length
     double *u = nullptr;
     int one_box = 0;               // nbatch % 16 == 0: the 16 columns of a tile are one box's densities
+    // with one_box: the L2P starts from the parent's column too, through the
+    // class's matrix (par_op[4][A-fragments], pc[box] = parent * 4 + class)
+    const void *par_op = nullptr;
+    const int32_t *pc = nullptr;
 };
 
 // ALDS: the operator sits in LDS, copied once per workgroup, instead of in
@@ -314,6 +318,24 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
             // all sixteen densities (the general path below reloads them per column)
             const int box = cols_box[t * 16 / nbatch];
             const int64_t t0 = oa.off(box);
+            if (fin.par_op) {
+                // the parent's local expansion through the class's L2P x L2L matrix
+                const int pcv = fin.pc[box];
+                const int bt = (t * 16 + cl) % nbatch;
+                const TI *pp = in + ia.off(pcv >> 2) + (int64_t)bt * ia.bstride + g;
+                const TM *Bq = static_cast<const TM *>(fin.par_op) + (int64_t)(pcv & 3) * AE + lane;
+                TM bp[S];
+#pragma unroll
+                for (int s = 0; s < S; ++s) bp[s] = (TM)pp[4 * s];
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    TM a_s[RB];
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) a_s[r] = Bq[(r * S + s) * 64];
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) accs[r] = M::op(bp[s], a_s[r], accs[r]);
+                }
+            }
             int pr[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {

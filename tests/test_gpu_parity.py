@@ -714,6 +714,33 @@ def test_one_wave_tables(c0, case):
     assert d <= 1e-14 and da <= 1e-14
 
 
+@pytest.mark.parametrize("nbatch", [16, 32])
+def test_l2p_from_parents(c0, nbatch):
+    """With 16k densities on a uniform grid the deepest level's pattern leaves
+    take their far field from the parents' local expansions (the L2L into
+    that level folded into the L2P matrices): forward against the oracle,
+    and the adjoint (which keeps the plain L2L) on the same plan."""
+    vp = _vp()
+    fs = np.stack([gen.gaussian_sum_density(c0.x, c0.y, s)[0] for s in range(70, 70 + nbatch)])
+    plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=30, nbatch=nbatch,
+                   root=c0.root)
+    assert plan.info()["l2p_from_parents"] == 1
+    u = _host(plan.eval(_dev(fs)))
+    ref = direct.evaluate(c0.x, c0.y, c0.w, fs, c0.rowptr, c0.col, c0.val)
+    errs = [relinf(u[b], ref[b]) for b in range(nbatch)]
+    print(f"l2p from parents, {nbatch} densities: max rel_inf {max(errs):.3e}")
+    assert max(errs) <= TOL64
+    g = np.random.default_rng(71).standard_normal((nbatch, c0.n))
+    d = _host(plan.eval_adjoint(_dev(g)))
+    dref = direct.evaluate_adjoint(c0.x, c0.y, c0.w, g, c0.rowptr, c0.col, c0.val)
+    assert max(relinf(d[b], dref[b]) for b in range(nbatch)) <= TOL64
+    plan.close()
+    # one density: the plain path
+    p1 = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=30, root=c0.root)
+    assert p1.info()["l2p_from_parents"] == 0
+    p1.close()
+
+
 @pytest.mark.parametrize("band", ["inside", "outside"])
 def test_tables_with_nodes_off_pattern(c0, band):
     """Leaves whose nodes deviate from the node pattern.  The near-field
