@@ -99,7 +99,7 @@ static size_t carve_workspace(vp_plan_s *P, unsigned char *base, double **q, dou
     const int64_t len = std::max(P->n, P->m);
     const size_t esz = P->fp32 ? 4 : 8;
     const size_t ecount = (size_t)P->tree.nbox * P->nbatch * P->PD;
-    const size_t mcount = (size_t)(P->tree.nbox + 4 * (size_t)P->n_vleaf) * P->nbatch * P->PD;
+    const size_t mcount = (size_t)P->mexp_boxes() * P->nbatch * P->PD;
     const size_t sizes[6] = {8 * (size_t)P->nbatch * len, 8 * (size_t)P->nbatch * len,
                              8 * (size_t)P->nbatch * len, mcount * esz,
                              ecount * esz,                 P->qi ? 8 * (size_t)P->nbatch * len : 0};
@@ -500,7 +500,7 @@ static vp_status plan_build(const double *x, const double *y, const double *w, i
         const size_t esz = P->fp32 ? 4 : 8;
         // multipoles also for the virtual children of X-list sources
         const size_t ecount = (size_t)P->tree.nbox * P->nbatch * P->PD;
-        const size_t mcount = (size_t)(P->tree.nbox + 4 * (size_t)P->n_vleaf) * P->nbatch * P->PD;
+        const size_t mcount = (size_t)P->mexp_boxes() * P->nbatch * P->PD;
         P->Mexp = P->mem.alloc<unsigned char>(mcount * esz);
         P->Lexp = P->mem.alloc<unsigned char>(ecount * esz);
         // zeros read in place of an absent source column (M2L, near tables)
@@ -689,7 +689,7 @@ extern "C" vp_status vp_eval_noalloc(vp_plan_t P, const double *f, double *u) {
         // the expansions' padding rows must be zero (the plan zeroes its own
         // arrays once; the static array holds whatever the last call left)
         const int64_t ecount = (int64_t)P->tree.nbox * P->nbatch * P->PD;
-        const int64_t mcount = (int64_t)(P->tree.nbox + 4 * (int64_t)P->n_vleaf) * P->nbatch * P->PD;
+        const int64_t mcount = P->mexp_boxes() * P->nbatch * P->PD;
         if (P->fp32) {
             vp::fill_f32(static_cast<float *>(P->Mexp), 0.f, mcount, P->stream);
             vp::fill_f32(static_cast<float *>(P->Lexp), 0.f, ecount, P->stream);

@@ -1941,8 +1941,13 @@ static void launch_m2l(vp_plan_s *P, int part) {
         sa.tile_ops = S.tops;
         sa.tile_src = S.tsrc;
         // the launch below the split level has few tiles on small trees: give
-        // each tile the most waves there (its latency sets the coarse chain)
-        const int nw = part == 1 && (a.ncols + 15) / 16 < 1024 ? 4 : P->m2l_nw;
+        // each tile the most waves there (its latency sets the coarse chain);
+        // the one-wave form addresses the multipoles by 32-bit offsets
+        const int64_t mbytes = P->mexp_boxes() * nb * PD * (int64_t)sizeof(E);
+        const bool wave_fits = mbytes < ((int64_t)1 << 32) && P->zero_box() < (1 << 24);
+        int nw = part == 1 && (a.ncols + 15) / 16 < 1024 ? 4 : P->m2l_nw;
+        if (nw == 1 && !wave_fits) nw = 2;
+        sa.zero_box = (int)P->zero_box();
         sa.tile_order = nw == 1 ? S.torder4 : S.torder;
         sa.P = Pn;
         sa.box_stride = (int64_t)nb * PD;

@@ -368,7 +368,7 @@ struct vp_plan_s {
     double *acc_far = nullptr;  // [nbatch][max(n,m)] far-field potentials, sorted order
     double *qi = nullptr;    // [max(n,m)][nbatch] the charges again, density fastest (near tables, nbatch > 1)
     bool qi_valid = false;   // qi holds this evaluation's charges
-    void *Mexp = nullptr;    // [nbox + 4 n_vleaf][nbatch][PD] (double or float)
+    void *Mexp = nullptr;    // [mexp_boxes()][nbatch][PD] (double or float)
     void *Lexp = nullptr;
     void *zero_col = nullptr;  // max(PD, 128 nbatch) zero doubles (an absent source column, either element
                                // type and either charge layout)
@@ -398,6 +398,10 @@ struct vp_plan_s {
     // quadrant boundaries [5] of their sorted sources and targets
     int n_vleaf = 0;
     int32_t *vleaf = nullptr;
+    // multipole blocks: the boxes, the virtual children, and one block that
+    // stays zero (index zero_box(): the M2L's absent source)
+    int64_t zero_box() const { return (int64_t)tree.nbox + 4 * (int64_t)n_vleaf; }
+    int64_t mexp_boxes() const { return zero_box() + 1; }
     int32_t *vsplit_s = nullptr, *vsplit_t = nullptr;
     int32_t *w_leaves = nullptr;     // leaves with non-empty W list
     int n_w_leaves = 0;
