@@ -102,7 +102,7 @@ static size_t carve_workspace(vp_plan_s *P, unsigned char *base, double **q, dou
     const size_t mcount = (size_t)P->mexp_boxes() * P->nbatch * P->PD;
     const size_t sizes[6] = {8 * (size_t)P->nbatch * len, 8 * (size_t)P->nbatch * len,
                              8 * (size_t)P->nbatch * len, mcount * esz,
-                             ecount * esz,                 P->qi ? 8 * (size_t)P->nbatch * len : 0};
+                             ecount * esz,                 P->qi ? 8 * (size_t)P->nbatch * (len + QI_ZERO_PTS) : 0};
     void *parts[6];
     size_t off = 0;
     for (int k = 0; k < 6; ++k) {
@@ -518,7 +518,11 @@ static vp_status plan_build(const double *x, const double *y, const double *w, i
         vp::build_near_tables(P);
         // the near tables read their source columns from a density-fastest copy
         // of the charges (one box's columns are one contiguous block)
-        if (P->near.active && P->nbatch > 1) P->qi = P->mem.alloc<double>((size_t)P->nbatch * len);
+        if (P->near.active && P->nbatch > 1) {
+            P->qi = P->mem.alloc<double>((size_t)P->nbatch * (len + vp::QI_ZERO_PTS));
+            P->qi_zero = len;
+            vp::fill_f64(P->qi + len * P->nbatch, 0.0, (int64_t)vp::QI_ZERO_PTS * P->nbatch, P->stream);
+        }
         if (o.kernel == VP_KERNEL_YUKAWA) vp::build_yukawa(P);
         if (o.p2p_mode == VP_P2P_TABLES && !P->near.active)
             throw Error(VP_EUNSUPPORTED, "p2p_mode TABLES needs targets = nodes and congruent leaves");
@@ -697,6 +701,7 @@ extern "C" vp_status vp_eval_noalloc(vp_plan_t P, const double *f, double *u) {
             vp::fill_f64(static_cast<double *>(P->Mexp), 0.0, mcount, P->stream);
             vp::fill_f64(static_cast<double *>(P->Lexp), 0.0, ecount, P->stream);
         }
+        if (P->qi) vp::fill_f64(P->qi + P->qi_zero * P->nbatch, 0.0, (int64_t)vp::QI_ZERO_PTS * P->nbatch, P->stream);
         P->timing_eval_begin();
         vp::prepare_charges(P, f, false);
         vp::run_fmm(P, false, false, f, u);

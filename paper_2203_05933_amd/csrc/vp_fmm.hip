@@ -1896,7 +1896,10 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
     }
     P->stage_begin(VP_STAGE_CHARGE);
     // the density-fastest copy only for the one-wave near-table kernel, its one reader
-    P->qi_valid = P->qi != nullptr && P->table_nw == 1;
+    // (the table kernel addresses it by 32-bit byte offsets and 24-bit point indices)
+    P->qi_valid = P->qi != nullptr && P->table_nw == 1 &&
+                  (P->qi_zero + QI_ZERO_PTS) * P->nbatch * 8 < ((int64_t)1 << 32) &&
+                  P->qi_zero + QI_ZERO_PTS < (1 << 24);
     if (P->qi_valid)
         hipLaunchKernelGGL(k_charge_il, dim3((unsigned)((len + 63) / 64)), dim3(64),
                            64 * (P->nbatch + 1) * sizeof(double), P->stream, f, perm, w, P->q, len, P->nbatch, P->qi);
@@ -2155,7 +2158,11 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
             a.tile_ops = N.tile2_ops;
             a.tile_order = N.tile2_order;
             const dim3 grid((unsigned)((a.ncols + 31) / 32));
-            if (P->qi_valid)
+            a.in_zero = (int)P->qi_zero;
+            if (P->qi_valid && P->nbatch == 16)
+                hipLaunchKernelGGL((k_tables_ct<RB, S, 2, true, 16>), grid, dim3(64), 0, P->stream, a, N.K, P->qi,
+                                   P->acc);
+            else if (P->qi_valid)
                 hipLaunchKernelGGL((k_tables_ct<RB, S, 2, true>), grid, dim3(64), 0, P->stream, a, N.K, P->qi,
                                    P->acc);
             else

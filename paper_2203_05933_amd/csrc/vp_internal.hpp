@@ -36,6 +36,7 @@ struct Error : std::runtime_error {
 // Constants
 // ----------------------------------------------------------------------------
 constexpr int LBITS = 30;              // quantisation bits per coordinate
+constexpr int QI_ZERO_PTS = 128;         // zero points after the density-fastest charges
 constexpr int NOFF = 40;               // M2L offsets: [-3,3]^2 minus [-1,1]^2
 constexpr int MAX_BATCH = 64;
 constexpr double INV_2PI = 0.15915494309189533576888376337251436;
@@ -366,7 +367,9 @@ struct vp_plan_s {
     double *q = nullptr;     // [nbatch][max(n,m)] charges, sorted order
     double *acc = nullptr;   // [nbatch][max(n,m)] potentials, sorted order (near field; gradients x 2)
     double *acc_far = nullptr;  // [nbatch][max(n,m)] far-field potentials, sorted order
-    double *qi = nullptr;    // [max(n,m)][nbatch] the charges again, density fastest (near tables, nbatch > 1)
+    double *qi = nullptr;    // [max(n,m) + QI_ZERO_PTS][nbatch] the charges again, density fastest (near
+                             // tables, nbatch > 1); the last QI_ZERO_PTS points stay zero (an absent source)
+    int64_t qi_zero = 0;     // point index of that zero block (max(n, m))
     bool qi_valid = false;   // qi holds this evaluation's charges
     void *Mexp = nullptr;    // [mexp_boxes()][nbatch][PD] (double or float)
     void *Lexp = nullptr;

@@ -50,11 +50,6 @@ struct M2LScaledArgs {
     int zero_box;             // k_m2l_wave: box index of an all-zero block of the input array
 };
 
-// a load the scalar unit serves: the address is uniform across the wave and
-// the array is read-only while the kernel runs
-__device__ inline int ld_uniform(const int32_t *p, int i) {
-    return ((const __attribute__((address_space(4))) int32_t *)p)[i];
-}
 
 // Column of one source for the k-steps of lane group g (k = g*S + s).  An
 // absent source reads a column of zeros.  Rows k >= P of the real part (the

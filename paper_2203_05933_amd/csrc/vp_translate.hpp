@@ -82,7 +82,14 @@ struct TranslateArgs {
     const int32_t *tile_order = nullptr;  // optional launch order of the tiles (most operators first)
     const void *zero_col = nullptr;       // zeros of the input type, at least 4 S long (absent sources)
     const int32_t *xinit = nullptr;       // optional [box] nonzero: add to the output column (k_translate_split)
+    int in_zero = 0;                      // k_tables_ct with density-fastest charges: point index of a zero block
 };
+
+// a load the scalar unit serves: the address is uniform across the wave and
+// the array is read-only while the kernel runs
+__device__ inline int ld_uniform(const int32_t *p, int i) {
+    return ((const __attribute__((address_space(4))) int32_t *)p)[i];
+}
 
 // TI/TO: element types of input/output columns; TM: matrix-core type;
 // RB: 16-row blocks of the output; S: 4-row steps of the input;
@@ -554,7 +561,16 @@ __global__ void __launch_bounds__(64 * NW) k_translate_split(TranslateArgs a, co
 // and the next operator's source columns load one step at a time beside
 // them (loads complete in issue order, so spreading them keeps every wait
 // short).
-template <int RB, int S, int CT, bool IL>
+//
+// Addressing is kept off the VALU, which shares the SIMD with the FP64
+// products: the operator code comes through the scalar unit, so an
+// operator's fragments are one uniform base plus fixed per-lane offsets; the
+// entries are unrolled by two over two column buffers (no copies between
+// them).  IL: each column's source is staged as a point offset into the
+// charge copy (an absent source as the block of zeros at point a.in_zero),
+// so a column address is one 24-bit multiply-add into a 32-bit byte offset;
+// NB > 0 fixes nbatch (the k-step stride then folds into the load offsets).
+template <int RB, int S, int CT, bool IL, int NB = 0>
 __global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double *__restrict__ A,
                                                   const double *__restrict__ in, double *__restrict__ out) {
     typedef Mfma<double> M;
@@ -563,17 +579,18 @@ __global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double 
     constexpr int PF = 3, NBUF = PF + 1;  // operator prefetch distance (k-steps), ring slots
     static_assert(S % NBUF == 0, "the ring wraps at operator boundaries");
     __shared__ int32_t s_ops[64];
-    __shared__ int32_t s_src[64][W];
+    __shared__ int32_t s_src[64 + 1][W];  // one more entry: the look-ahead past the last operator
     const int lane = threadIdx.x, cl = lane & 15, g = lane >> 4;
-    const int tile = a.tile_order[blockIdx.x];
+    const int tile = ld_uniform(a.tile_order, blockIdx.x);
+    const int nbatch = NB > 0 ? NB : a.nbatch;
     int box[CT], bt[CT];
     bool valid[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
         const int col = tile * W + c * 16 + cl;
         valid[c] = col < a.ncols;
-        box[c] = valid[c] ? a.cols_box[col / a.nbatch] : 0;
-        bt[c] = valid[c] ? col % a.nbatch : 0;
+        box[c] = valid[c] ? a.cols_box[col / nbatch] : 0;
+        bt[c] = valid[c] ? col % nbatch : 0;
     }
     typename M::acc_t acc[CT][RB];
 #pragma unroll
@@ -581,61 +598,82 @@ __global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double 
 #pragma unroll
         for (int r = 0; r < RB; ++r) acc[c][r] = M::zero();
     const double *zc = static_cast<const double *>(a.zero_col);
-    // element k = 4 s + g of a source column is at src_col(e, c)[s * kst]
-    const int64_t kst = IL ? 4 * (int64_t)a.nbatch : 4;
-    // source column of tile c for operator entry e (absent: the zero column)
+    // IL: element k = 4 s + g of column c of entry e is at byte
+    // col_off(e, c) + s * kstb of the charge copy
+    const char *inb = reinterpret_cast<const char *>(in);
+    const unsigned nb8 = (unsigned)nbatch * 8u, kstb = 32u * (unsigned)nbatch;
+    unsigned lc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) lc[c] = (unsigned)(g * nbatch + bt[c]) * 8u;
+    // non-IL: element k = 4 s + g of a source column is at src_col(e, c)[4 s]
     auto src_col = [&](int e, int c) {
         const int src = s_src[e][c * 16 + cl];
-        if constexpr (IL) {
-            return (src >= 0 ? in + a.in.off(src) * (int64_t)a.nbatch : zc) + (int64_t)g * a.nbatch + bt[c];
-        } else {
-            return (src >= 0 ? in + a.in.off(src) + (int64_t)bt[c] * a.in.bstride : zc) + g;
+        return (src >= 0 ? in + a.in.off(src) + (int64_t)bt[c] * a.in.bstride : zc) + g;
+    };
+    auto ld_col = [&](int e, double(&b)[CT][S], int s, const unsigned(&off)[CT], const double *const(&ip)[CT]) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            if constexpr (IL) b[c][s] = *reinterpret_cast<const double *>(inb + (size_t)off[c] + (size_t)s * kstb);
+            else b[c][s] = ip[c][4 * s];
         }
     };
-    const int e0 = a.tile_ptr[tile], nt = a.tile_ptr[tile + 1] - e0;
+    auto col_addr = [&](int e, unsigned(&off)[CT], const double *(&ip)[CT]) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            if constexpr (IL) off[c] = __umul24((unsigned)s_src[e][c * 16 + cl], nb8) + lc[c];
+            else ip[c] = src_col(e, c);
+        }
+    };
+    // operator fragment (row block r, k-step s) of the operator at byte base ab
+    const unsigned lane8 = (unsigned)lane * 8u;
+    auto ld_op = [&](const char *ab, int r, int s) {
+        return *reinterpret_cast<const double *>(ab + (size_t)lane8 + (size_t)((r * S + s) * 64 * 8));
+    };
+    auto op_base = [&](int op) { return reinterpret_cast<const char *>(A + (int64_t)op * AE); };
+    const int e0 = ld_uniform(a.tile_ptr, tile), nt = ld_uniform(a.tile_ptr, tile + 1) - e0;
     for (int c0 = 0; c0 < nt; c0 += 64) {
         const int nc = min(64, nt - c0);
         __syncthreads();
         for (int i = lane; i < nc; i += 64) s_ops[i] = a.tile_ops[e0 + c0 + i];
         __syncthreads();
-        for (int i = lane; i < nc * W; i += 64) {
+        for (int i = lane; i < (nc + 1) * W; i += 64) {
             const int oi = i / W, c = i % W, cc = tile * W + c;
-            s_src[oi][c] = cc < a.ncols ? a.slots[(int64_t)a.cols_box[cc / a.nbatch] * a.nops + s_ops[oi]] : -1;
+            const int src = cc < a.ncols && oi < nc ? a.slots[(int64_t)a.cols_box[cc / nbatch] * a.nops + s_ops[oi]]
+                                                    : -1;
+            if constexpr (IL) s_src[oi][c] = src >= 0 ? (int)a.in.off(src) : a.in_zero;
+            else s_src[oi][c] = src;
         }
         __syncthreads();
-        double bv[CT][S];
+        double bA[CT][S], bB[CT][S];
+        {
+            unsigned off[CT];
+            const double *ip[CT];
+            col_addr(0, off, ip);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            const double *ip = src_col(0, c);
-#pragma unroll
-            for (int s = 0; s < S; ++s) bv[c][s] = ip[s * kst];
+            for (int s = 0; s < S; ++s) ld_col(0, bA, s, off, ip);
         }
         // ring of operator fragments: k-step j of the stream sits in slot j % NBUF
         double af[NBUF][RB];
         {
-            const double *A0 = A + (int64_t)s_ops[0] * AE + lane;
+            const char *A0 = op_base(ld_uniform(a.tile_ops, e0 + c0));
 #pragma unroll
             for (int p = 0; p < PF; ++p)
 #pragma unroll
-                for (int r = 0; r < RB; ++r) af[p][r] = A0[(r * S + p) * 64];
+                for (int r = 0; r < RB; ++r) af[p][r] = ld_op(A0, r, p);
         }
-        for (int e = 0; e < nc; ++e) {
-            const bool more = e + 1 < nc;
-            const double *Ao = A + (int64_t)s_ops[e] * AE + lane;
-            // the next operator (this one again after the last: loaded, never used)
-            const double *An = more ? A + (int64_t)s_ops[e + 1] * AE + lane : Ao;
-            const double *nx[CT];
-#pragma unroll
-            for (int c = 0; c < CT; ++c) nx[c] = more ? src_col(e + 1, c) : zc;
-            double bn[CT][S];
+        auto body = [&](int e, double(&bv)[CT][S], double(&bn)[CT][S]) {
+            // this operator and the next (this one again after the last: loaded, never used)
+            const char *Ao = op_base(ld_uniform(a.tile_ops, e0 + c0 + e));
+            const char *An = op_base(ld_uniform(a.tile_ops, e0 + c0 + (e + 1 < nc ? e + 1 : e)));
+            unsigned off[CT];
+            const double *ip[CT];
+            col_addr(e + 1, off, ip);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int sp = s + PF;
 #pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    af[sp % NBUF][r] = sp < S ? Ao[(r * S + sp) * 64] : An[(r * S + sp - S) * 64];
-#pragma unroll
-                for (int c = 0; c < CT; ++c) bn[c][s] = nx[c][s * kst];
+                for (int r = 0; r < RB; ++r) af[sp % NBUF][r] = sp < S ? ld_op(Ao, r, sp) : ld_op(An, r, sp - S);
+                ld_col(e + 1, bn, s, off, ip);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
@@ -643,11 +681,13 @@ __global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double 
                     for (int c = 0; c < CT; ++c) acc[c][r] = M::op(af[s % NBUF][r], bv[c][s], acc[c][r]);
                 __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-#pragma unroll
-                for (int s = 0; s < S; ++s) bv[c][s] = bn[c][s];
+        };
+        int e = 0;
+        for (; e + 1 < nc; e += 2) {
+            body(e, bA, bB);
+            body(e + 1, bB, bA);
         }
+        if (e < nc) body(e, bA, bB);
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
