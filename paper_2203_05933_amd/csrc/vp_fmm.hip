@@ -2280,6 +2280,32 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, doub
         a.nrows_out = N.npat;
         if (a.ncols <= 0) return;
         const E *op = f32 ? (const E *)N.l2p_op_f32 : (const E *)N.l2p_op;
+        if constexpr (sizeof(E) == 8) {
+            if (fin.u && N.par_l2p) {
+                // the deepest level from the leaves' and their parents' local expansions
+                L2PFinArgs fa;
+                fa.rec = N.l2p_rec;
+                int maxq = 0;
+                for (int q = 0; q < 5; ++q) fa.qbeg[q] = N.l2p_qbeg[q];
+                for (int q = 0; q < 4; ++q) maxq = std::max(maxq, N.l2p_qbeg[q + 1] - N.l2p_qbeg[q]);
+                fa.box_stride = (int64_t)P->nbatch * P->PD;
+                fa.PD = P->PD;
+                fa.tb = R.tb;
+                fa.near = fin.near;
+                fa.ntgt = R.ntgt;
+                fa.perm = fin.perm;
+                fa.u = fin.u;
+                fa.m = fin.m;
+                // two workgroups per compute unit (64 KB of operators each), a
+                // quarter of them per class
+                const unsigned grid = 4u * (unsigned)std::max(1, std::min(128, (maxq + 15) / 16));
+                if (N.npat != RBP * 16) throw Error(VP_EINTERNAL, "pattern size off its row blocks");
+                hipLaunchKernelGGL((k_l2p_fin<RBP, RBE * 4>), dim3(grid), dim3(256), 0, P->stream, fa, N.l2p_km,
+                                   N.par_km, static_cast<const double *>(P->Lexp));
+                VP_LAUNCH_CHECK();
+                return;
+            }
+        }
         if (fin.u)
             launch_fixed_apply<E, double, E, RBP, RBE * 4, false, true>(
                 P, a.cols_box, a.ncols, a.in, a.out, a.nrows_out, op, static_cast<const E *>(P->Lexp), acc,
@@ -2520,10 +2546,6 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
             fin.m = P->m;
             fin.u = u;
             fin.one_box = P->nbatch % 16 == 0 ? 1 : 0;
-            if (N.par_l2p) {
-                fin.par_op = N.l2p_par_op;
-                fin.pc = N.l2p_pc;
-            }
             run_far<E, false>(P, R, G, P->acc_far, tables, 1, fin);
         } else if (fmm) {
             run_far<E, false>(P, R, G, P->acc_far, tables, 1);

@@ -246,11 +246,13 @@ struct NearTables {
     bool fused_finish = false;        // forward: the pattern L2P writes the output (see vp_near.hip)
     // forward with the fused finish: the pattern leaves fill the deepest level
     // par_level, whose L2P starts from the parents' local expansions (the L2L
-    // into that level folded into l2p_par_op, one matrix per child class)
+    // into that level folded into par_km, one matrix per child class)
     bool par_l2p = false;
     int par_level = 0;
-    double *l2p_par_op = nullptr;     // [4][A-fragment order of npat x PD]
-    int32_t *l2p_pc = nullptr;        // [nbox] parent * 4 + child class of the pattern leaves
+    double *l2p_km = nullptr;         // L2P (npat x PD), k-major fragments
+    double *par_km = nullptr;         // [4] B_q = L2P x L2L_q, k-major fragments
+    int32_t *l2p_rec = nullptr;       // [tile][4] {box, parent * 4 + class, first density, 0}, by class
+    int l2p_qbeg[5] = {0, 0, 0, 0, 0};  // class q's tiles: [l2p_qbeg[q], l2p_qbeg[q + 1])
     std::vector<double> pat_rx, pat_ry;  // the node pattern, box-relative in units of the side
     // [5][PD x npat] A-fragment order: the leaf P2M, then the four quadrant
     // P2M matrices (about the quadrant centre at the children's scale, zero
@@ -426,6 +428,7 @@ struct vp_plan_s {
 };
 
 void vp_to_frag(const double *R, int rows, int cols, int ld, double *F);
+void vp_to_frag_kmajor(const double *R, int rows, int cols, int ld, double *F);
 
 namespace vp {
 // vp_tree.hip

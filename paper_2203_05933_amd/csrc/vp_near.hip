@@ -477,7 +477,9 @@ void build_near_tables(vp_plan_s *P) {
         // the translations (t = child offset / parent side = (+-1/4, +-1/4)):
         // B'_l = 2^-l t^-l sum_{k >= l} C(k, l) t^k B_k.
         N.par_l2p = false;
-        if (!P->fp32 && N.fused_finish && P->nbatch % 16 == 0 && !l2p_pat.empty()) {
+        // (the fused launch addresses the near sums and the output by 32-bit offsets)
+        if (!P->fp32 && N.fused_finish && P->nbatch % 16 == 0 && !l2p_pat.empty() &&
+            32 * (int64_t)std::max(P->n, P->m) < ((int64_t)1 << 32)) {
             const int Lf = lev[l2p_pat[0]];
             bool ok = Lf >= 3 && Lf == T.nlevels - 1;
             for (int b : l2p_pat) ok = ok && lev[b] == Lf;
@@ -493,7 +495,9 @@ void build_near_tables(vp_plan_s *P) {
                     Cb[k][0] = 1.0L;
                     for (int l = 1; l <= k; ++l) Cb[k][l] = Cb[k - 1][l - 1] + (l < k ? Cb[k - 1][l] : 0.0L);
                 }
-                std::vector<double> Tq((size_t)PD * PD), Bq((size_t)np * PD), Bqf((size_t)4 * np * PD);
+                std::vector<double> Tq((size_t)PD * PD), Bq((size_t)np * PD), Bqf((size_t)4 * np * PD),
+                    Bk((size_t)np * PD);
+                vp_to_frag_kmajor(B.data(), np, PD, PD, Bk.data());
                 for (int q = 0; q < 4; ++q) {
                     const std::complex<long double> t(0.25L * ((q & 1) ? 1 : -1), 0.25L * ((q >> 1) ? 1 : -1));
                     std::fill(Tq.begin(), Tq.end(), 0.0);
@@ -516,15 +520,26 @@ void build_near_tables(vp_plan_s *P) {
                             for (int r = 0; r < PD; ++r) acc += (long double)B[(size_t)i * PD + r] * Tq[(size_t)r * PD + j];
                             Bq[(size_t)i * PD + j] = (double)acc;
                         }
-                    vp_to_frag(Bq.data(), np, PD, PD, Bqf.data() + (size_t)q * np * PD);
+                    vp_to_frag_kmajor(Bq.data(), np, PD, PD, Bqf.data() + (size_t)q * np * PD);
                 }
-                std::vector<int32_t> pc(nbox, 0);
-                for (int b : l2p_pat) pc[b] = par[b] * 4 + ((ix[b] & 1) | ((iy[b] & 1) << 1));
-                N.l2p_par_op = upload(P, Bqf);
-                N.l2p_pc = upload(P, pc);
+                // the tiles (box, 16 densities) grouped by child class: a
+                // workgroup of the fused launch serves one class
+                std::vector<int32_t> rec;
+                for (int q = 0; q < 4; ++q) {
+                    N.l2p_qbeg[q] = (int)(rec.size() / 4);
+                    for (int b : l2p_pat) {
+                        const int cq = (ix[b] & 1) | ((iy[b] & 1) << 1);
+                        if (cq != q) continue;
+                        for (int d = 0; d < P->nbatch; d += 16) rec.insert(rec.end(), {b, par[b] * 4 + cq, d, 0});
+                    }
+                }
+                N.l2p_qbeg[4] = (int)(rec.size() / 4);
+                N.l2p_km = upload(P, Bk);
+                N.par_km = upload(P, Bqf);
+                N.l2p_rec = upload(P, rec);
                 N.par_l2p = true;
                 N.par_level = Lf;
-                VP_HIP(hipStreamSynchronize(s));  // Bqf, pc leave scope
+                VP_HIP(hipStreamSynchronize(s));  // Bk, Bqf, rec leave scope
             }
         }
         if (P->fp32) {

@@ -94,6 +94,17 @@ void vp_to_frag(const double *R, int rows, int cols, int ld, double *F) {
                 F[((size_t)rb * S + s) * 64 + lane] = R[(size_t)(rb * 16 + lane % 16) * ld + 4 * s + lane / 16];
 }
 
+// The same fragments with the k index split the other way: lane group g takes
+// the S consecutive columns S g .. S g + S - 1 over the S steps (a lane's
+// input elements are then contiguous: k_l2p_fin loads them 16 bytes at a time)
+void vp_to_frag_kmajor(const double *R, int rows, int cols, int ld, double *F) {
+    int RB = rows / 16, S = cols / 4;
+    for (int rb = 0; rb < RB; ++rb)
+        for (int s = 0; s < S; ++s)
+            for (int lane = 0; lane < 64; ++lane)
+                F[((size_t)rb * S + s) * 64 + lane] = R[(size_t)(rb * 16 + lane % 16) * ld + S * (lane / 16) + s];
+}
+
 namespace vp {
 
 static void to_frag(const double *R, int PD, double *F) { vp_to_frag(R, PD, PD, PD, F); }

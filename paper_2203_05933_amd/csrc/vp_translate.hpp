@@ -256,10 +256,6 @@ struct FinishArgs {
     int64_t m = 0;                 // output row length
     double *u = nullptr;
     int one_box = 0;               // nbatch % 16 == 0: the 16 columns of a tile are one box's densities
-    // with one_box: the L2P starts from the parent's column too, through the
-    // class's matrix (par_op[4][A-fragments], pc[box] = parent * 4 + class)
-    const void *par_op = nullptr;
-    const int32_t *pc = nullptr;
 };
 
 // ALDS: the operator sits in LDS, copied once per workgroup, instead of in
@@ -325,24 +321,6 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
             // all sixteen densities (the general path below reloads them per column)
             const int box = cols_box[t * 16 / nbatch];
             const int64_t t0 = oa.off(box);
-            if (fin.par_op) {
-                // the parent's local expansion through the class's L2P x L2L matrix
-                const int pcv = fin.pc[box];
-                const int bt = (t * 16 + cl) % nbatch;
-                const TI *pp = in + ia.off(pcv >> 2) + (int64_t)bt * ia.bstride + g;
-                const TM *Bq = static_cast<const TM *>(fin.par_op) + (int64_t)(pcv & 3) * AE + lane;
-                TM bp[S];
-#pragma unroll
-                for (int s = 0; s < S; ++s) bp[s] = (TM)pp[4 * s];
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    TM a_s[RB];
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) a_s[r] = Bq[(r * S + s) * 64];
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) accs[r] = M::op(bp[s], a_s[r], accs[r]);
-                }
-            }
             int pr[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -395,6 +373,140 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) bcur[s] = bnext[s];
+    }
+}
+
+// Pattern L2P of a uniform tree's deepest level, each leaf's local expansion
+// taken together with its parent's through the class matrix B_q = L2P x L2L_q
+// (so the L2L into that level never runs), and the finish of a forward
+// evaluation: u[b][perm[t]] = (near[b][t] + v) + u[b][perm[t]] for the leaf's
+// targets t.  A tile is one box's 16 densities from a.rec (grouped by child
+// class); each workgroup serves one class, with the L2P and that class's B_q
+// in LDS, and walks its class's tiles with a grid stride, one per wave.  The
+// operators are in k-major fragments (lane group g takes the S consecutive
+// expansion rows S g ..), so a lane's column elements are contiguous and load
+// 16 bytes at a time.  The next tile's columns load while this tile's products
+// run; this tile's parent columns and permutation load at its start, its near
+// sums and output rows after the first product, all before they are needed.
+// Every leaf has RB * 16 targets (the patterns are 16, 32 or 64 points).
+struct L2PFinArgs {
+    const int32_t *rec;    // [tile][4] {box, parent * 4 + class, first density, 0}
+    int qbeg[5];           // class q's tiles: [qbeg[q], qbeg[q + 1])
+    int64_t box_stride;    // local-expansion elements between boxes (nbatch PD)
+    int PD;                // between the densities of a box
+    const int32_t *tb;     // [box] first sorted target
+    const double *near;    // [nbatch][ntgt], sorted order
+    int64_t ntgt;
+    const int32_t *perm;   // sorted target -> user index
+    double *u;             // [nbatch][m], user order
+    int64_t m;
+};
+
+template <int RB, int S>
+__global__ void __launch_bounds__(256, 2) k_l2p_fin(L2PFinArgs a, const double *__restrict__ A,
+                                                    const double *__restrict__ Bq4, const double *__restrict__ L) {
+    typedef Mfma<double> M;
+    constexpr int AE = RB * S * 64;
+    static_assert(S % 2 == 0, "column elements load in pairs");
+    __shared__ __align__(16) double sA[AE];
+    __shared__ __align__(16) double sB[AE];
+    const int q = blockIdx.x & 3;
+    const int lane = threadIdx.x & 63, cl = lane & 15, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int e = threadIdx.x; e < AE; e += 256) {
+        sA[e] = A[e];
+        sB[e] = Bq4[(int64_t)q * AE + e];
+    }
+    __syncthreads();
+    const int jq = a.qbeg[q], nq = a.qbeg[q + 1] - jq;
+    const int stride = (int)((gridDim.x + 3 - q) / 4) * 4;  // waves of this class
+    int j = (int)(blockIdx.x >> 2) * 4 + wave;
+    if (j >= nq) return;
+    const int32_t *rec = a.rec + (int64_t)jq * 4;
+    // Addresses: a uniform base (scalar registers) plus a 32-bit lane offset,
+    // most of them fixed for the launch (the host checks that the offsets fit).
+    // Elements S g .. S g + S - 1 of density column d + cl of box b:
+    const unsigned col_off = (unsigned)(cl * a.PD + S * g) * 8u;
+    auto ld_cols = [&](int b, int d, double(&x)[S]) {
+        const char *base = reinterpret_cast<const char *>(L + (int64_t)b * a.box_stride + (int64_t)d * a.PD);
+#pragma unroll
+        for (int s = 0; s < S; s += 2) {
+            const double2 v = *reinterpret_cast<const double2 *>(base + (size_t)col_off + (size_t)(s * 8));
+            x[s] = v.x;
+            x[s + 1] = v.y;
+        }
+    };
+    // near sums and output rows of result element (r, i): density d0 + 4 i + g
+    // (M::row(i, g)), target row r * 16 + cl
+    const unsigned near_off0 = (unsigned)(g * a.ntgt + cl) * 8u;
+    // (a scheduling barrier per k-step keeps the compiler from reading the
+    // whole operator into registers ahead of the products)
+    auto product = [&](const double(&x)[S], const double *op, typename M::acc_t(&acc)[RB], unsigned oaddr) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                acc[r] = M::op(x[s], *reinterpret_cast<const double *>(reinterpret_cast<const char *>(op) + oaddr +
+                                                                      (r * S + s) * 64 * 8),
+                               acc[r]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    unsigned oaddr = (unsigned)lane * 8u;
+    int box = ld_uniform(rec, 4 * j), pcv = ld_uniform(rec, 4 * j + 1), d0 = ld_uniform(rec, 4 * j + 2);
+    double xa[S];
+    ld_cols(box, d0, xa);
+    for (; j < nq; j += stride) {
+        const int jn = j + stride < nq ? j + stride : j;
+        const int boxn = ld_uniform(rec, 4 * jn), pcn = ld_uniform(rec, 4 * jn + 1), dn = ld_uniform(rec, 4 * jn + 2);
+        const int t0 = ld_uniform(a.tb, box);
+        // issue order (loads complete in order): this tile's parent columns and
+        // permutation, then the next tile's own columns
+        double xp[S], xn[S];
+        ld_cols(pcv >> 2, d0, xp);
+        unsigned uoff[RB];
+        {
+            const char *pb = reinterpret_cast<const char *>(a.perm + t0);
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                uoff[r] = (unsigned)(g * a.m + *reinterpret_cast<const int32_t *>(pb + (size_t)((r * 16 + cl) * 4))) * 8u;
+        }
+        ld_cols(boxn, dn, xn);
+        __builtin_amdgcn_sched_barrier(0);
+        typename M::acc_t acc[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r] = M::zero();
+        product(xa, sA, acc, oaddr);
+        __builtin_amdgcn_sched_barrier(0);
+        double nv[RB][4], uv[RB][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const char *nb = reinterpret_cast<const char *>(a.near + (int64_t)(d0 + 4 * i) * a.ntgt + t0);
+            const char *ub = reinterpret_cast<const char *>(a.u + (int64_t)(d0 + 4 * i) * a.m);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                nv[r][i] = *reinterpret_cast<const double *>(nb + (size_t)near_off0 + (size_t)(r * 16 * 8));
+                uv[r][i] = *reinterpret_cast<const double *>(ub + (size_t)uoff[r]);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        product(xp, sB, acc, oaddr);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            char *ub = reinterpret_cast<char *>(a.u + (int64_t)(d0 + 4 * i) * a.m);
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                *reinterpret_cast<double *>(ub + (size_t)uoff[r]) = (nv[r][i] + acc[r][i]) + uv[r][i];
+        }
+        // the operator fragments are read from LDS per tile (hoisted out of
+        // the loop they would need every register)
+        asm volatile("" : "+v"(oaddr));
+#pragma unroll
+        for (int s = 0; s < S; ++s) xa[s] = xn[s];
+        box = boxn;
+        pcv = pcn;
+        d0 = dn;
     }
 }
 
