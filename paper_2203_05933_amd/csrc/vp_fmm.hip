@@ -2545,7 +2545,6 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
             fin.perm = P->tperm;
             fin.m = P->m;
             fin.u = u;
-            fin.one_box = P->nbatch % 16 == 0 ? 1 : 0;
             run_far<E, false>(P, R, G, P->acc_far, tables, 1, fin);
         } else if (fmm) {
             run_far<E, false>(P, R, G, P->acc_far, tables, 1);

@@ -28,11 +28,21 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // Column addressing: element r of the column (box a, density b) is at
 // base + off(a) + b * bstride + r, with off(a) = box_mult * a (expansion
 // arrays) or start[a] (point arrays in sorted order).
+// a load the scalar unit serves: the address is uniform across the wave and
+// the array is read-only while the kernel runs
+__device__ inline int ld_uniform(const int32_t *p, int i) {
+    return ((const __attribute__((address_space(4))) int32_t *)p)[i];
+}
+
 struct ColAddr {
     int64_t bstride;
     int64_t box_mult;
     const int32_t *start;
     __device__ inline int64_t off(int a) const { return start ? (int64_t)start[a] : box_mult * (int64_t)a; }
+    // the same for a box index that is uniform across the wave
+    __device__ inline int64_t off_u(int a) const {
+        return start ? (int64_t)ld_uniform(start, a) : box_mult * (int64_t)a;
+    }
 };
 
 template <class TM>
@@ -85,11 +95,6 @@ struct TranslateArgs {
     int in_zero = 0;                      // k_tables_ct with density-fastest charges: point index of a zero block
 };
 
-// a load the scalar unit serves: the address is uniform across the wave and
-// the array is read-only while the kernel runs
-__device__ inline int ld_uniform(const int32_t *p, int i) {
-    return ((const __attribute__((address_space(4))) int32_t *)p)[i];
-}
 
 // TI/TO: element types of input/output columns; TM: matrix-core type;
 // RB: 16-row blocks of the output; S: 4-row steps of the input;
@@ -255,7 +260,6 @@ struct FinishArgs {
     const int32_t *perm = nullptr; // sorted target -> user index
     int64_t m = 0;                 // output row length
     double *u = nullptr;
-    int one_box = 0;               // nbatch % 16 == 0: the 16 columns of a tile are one box's densities
 };
 
 // ALDS: the operator sits in LDS, copied once per workgroup, instead of in
@@ -285,14 +289,24 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
     }
     const int ntiles = (ncols + 15) / 16;
     const int tstride = gridDim.x * (blockDim.x >> 6);
+    // with nbatch a multiple of 16 a tile is one box's 16 densities: its box
+    // and column start come through the scalar unit (no dependent vector
+    // loads ahead of the column loads)
+    const bool one_box = nbatch % 16 == 0;
     auto load = [&](int t, TM *bv) {
-        const int col = min(t * 16 + cl, ncols - 1);
-        const int box = cols_box[col / nbatch], bt = col % nbatch;
-        const TI *ip = in + ia.off(box) + (int64_t)bt * ia.bstride + g;
+        const TI *ip;
+        if (one_box) {
+            const int box = ld_uniform(cols_box, t * 16 / nbatch);
+            ip = in + ia.off_u(box) + (int64_t)(t * 16 % nbatch + cl) * ia.bstride + g;
+        } else {
+            const int col = min(t * 16 + cl, ncols - 1);
+            const int box = cols_box[col / nbatch], bt = col % nbatch;
+            ip = in + ia.off(box) + (int64_t)bt * ia.bstride + g;
+        }
 #pragma unroll
         for (int s = 0; s < S; ++s) bv[s] = (TM)ip[4 * s];
     };
-    int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    int t = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     TM bcur[S], bnext[S];
     load(min(t, ntiles - 1), bcur);
     for (; t < ntiles; t += tstride) {
@@ -316,11 +330,11 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
             if constexpr (ALDS) __builtin_amdgcn_sched_barrier(0);
         }
         // element i of a lane: output row r * 16 + cl of tile column M::row(i, g)
-        if (FIN && fin.one_box) {
+        if (FIN && one_box) {
             // one box per tile: its target rows and their permutation once for
             // all sixteen densities (the general path below reloads them per column)
-            const int box = cols_box[t * 16 / nbatch];
-            const int64_t t0 = oa.off(box);
+            const int box = ld_uniform(cols_box, t * 16 / nbatch);
+            const int64_t t0 = oa.off_u(box);
             int pr[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
@@ -338,6 +352,22 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
                     if (row < nrows_out) {
                         double *o = ub + pr[r];
                         *o = (nr[row] + (double)accs[r][i]) + *o;
+                    }
+                }
+            }
+        } else if (!FIN && one_box) {
+            const int box = ld_uniform(cols_box, t * 16 / nbatch);
+            const int64_t t0 = oa.off_u(box);
+            const bool add = ACCUM || (addflag && ld_uniform(addflag, box));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                TO *op = out + t0 + (int64_t)(t * 16 % nbatch + M::row(i, g)) * oa.bstride;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const int row = r * 16 + cl;
+                    if (row < nrows_out) {
+                        if (add) op[row] += (TO)accs[r][i];
+                        else op[row] = (TO)accs[r][i];
                     }
                 }
             }
