@@ -306,6 +306,119 @@ __global__ void __launch_bounds__(64) k_m2m(const int32_t *__restrict__ boxes, c
     }
 }
 
+// The same M2M on the matrix cores when a 16-column tile is one parent's
+// sixteen densities (nbatch a multiple of 16, FP64): one tile per wave, the
+// children's columns scaled on the VALU, multiplied by Q as in k_m2l_wave
+// (Q's fragments and the scaling tables in LDS, Q staged from its transposed
+// copy) and the scaled results summed over the four children.  A child's
+// columns load while the previous child's products run; an absent child
+// reads the multipole array's zero block (zero_box).
+template <int RB>
+__global__ void __launch_bounds__(256) k_m2m_wave(const int32_t *__restrict__ parents,
+                                                  const int4 *__restrict__ cslot, int nparents, int nbatch, int P,
+                                                  int PD, int PR, int zero_box, const double *__restrict__ QT,
+                                                  const double *__restrict__ tin, const double *__restrict__ tout,
+                                                  double *__restrict__ X) {
+    typedef Mfma<double> M;
+    constexpr int S = RB * 4, PQ = RB * 16;
+    __shared__ __align__(16) double s_q[RB * S * 64];  // [s][r][lane]
+    __shared__ __align__(16) double s_in[4][PQ][2], s_out[4][PQ][2];
+    const int tid = threadIdx.x, lane = tid & 63, cl = lane & 15, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int i = tid; i < RB * S * 64; i += 256) {
+        const int st = i / (RB * 64), r = (i / 64) % RB, l = i & 63;
+        const int k = (l >> 4) * S + st, row = r * 16 + (l & 15);
+        s_q[i] = k < P && row < P ? QT[k * PR + row] : 0.0;
+    }
+    for (int i = tid; i < 4 * PQ; i += 256) {
+        const int c = i / PQ, k = i % PQ;
+        const bool in = k < P;
+        s_in[c][k][0] = in ? tin[(c * P + k) * 2] : 0.0;
+        s_in[c][k][1] = in ? tin[(c * P + k) * 2 + 1] : 0.0;
+        s_out[c][k][0] = in ? tout[(c * P + k) * 2] : 0.0;
+        s_out[c][k][1] = in ? tout[(c * P + k) * 2 + 1] : 0.0;
+    }
+    __syncthreads();
+    const int tpp = nbatch / 16;  // tiles per parent
+    const int t = blockIdx.x * 4 + wave;
+    if (t >= nparents * tpp) return;
+    const int pi = t / tpp, d0 = (t - pi * tpp) * 16;
+    const int pb = ld_uniform(parents, pi);
+    const int32_t *cs = reinterpret_cast<const int32_t *>(cslot) + 4 * pi;
+    const int64_t lane_off = (int64_t)(d0 + cl) * PD + g * S;
+    // an absent child reads the zero block
+    auto load = [&](int c, double(&xr)[S], double(&xi)[S]) {
+        const int chc = ld_uniform(cs, c);
+        const double *x = X + (int64_t)(chc >= 0 ? chc : zero_box) * nbatch * PD + lane_off;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            xr[s] = x[s];
+            xi[s] = x[P + s];
+        }
+    };
+    double br[RB][4], bi[RB][4];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) br[r][i] = bi[r][i] = 0.0;
+    unsigned qaddr = (unsigned)lane * 8u;
+    auto child = [&](int c, const double(&xr)[S], const double(&xi)[S]) {
+        typename M::acc_t zr[RB], zi[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) zr[r] = zi[r] = M::zero();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int k = g * S + s;
+            const double wr = s_in[c][k][0], wi = s_in[c][k][1];
+            const double yr = xr[s] * wr - xi[s] * wi, yi = xr[s] * wi + xi[s] * wr;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const double q = *reinterpret_cast<const double *>(reinterpret_cast<const char *>(s_q) + qaddr +
+                                                                   (s * RB + r) * 64 * 8);
+                zr[r] = M::op(q, yr, zr[r]);
+                zi[r] = M::op(q, yi, zi[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int l = r * 16 + M::row(i, g);
+                const double vr = s_out[c][l][0], vi = s_out[c][l][1];
+                br[r][i] = fma(-zi[r][i], vi, fma(zr[r][i], vr, br[r][i]));
+                bi[r][i] = fma(zi[r][i], vr, fma(zr[r][i], vi, bi[r][i]));
+            }
+    };
+    // each child's columns load during the previous child's products; Q's
+    // fragments are read from LDS per child (kept in registers across the
+    // children they would cost a wave per SIMD)
+    double ar[S], ai[S], nr[S], ni[S];
+    load(0, ar, ai);
+#pragma unroll 1
+    for (int c = 0; c < 4; ++c) {
+        load(c < 3 ? c + 1 : 3, nr, ni);  // (the last child again after the last: loaded, unused)
+        child(c, ar, ai);
+        asm volatile("" : "+v"(qaddr));
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            ar[s] = nr[s];
+            ai[s] = ni[s];
+        }
+    }
+    double *o = X + ((int64_t)pb * nbatch + d0 + cl) * PD;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int l = r * 16 + M::row(i, g);
+            if (l < P) {
+                o[l] = br[r][i];
+                o[P + l] = bi[r][i];
+            }
+        }
+    for (int row = 2 * P + g; row < PD; row += 4) o[row] = 0.0;
+}
+
 // L2L in the same scaled form (Q upper triangular), one target box per row
 // group: a wave serves 64 / PR boxes of a level, each row group staging its
 // own parent column.  The launch list carries parent * 4 + class beside each
@@ -2024,6 +2137,22 @@ static void run_m2m(vp_plan_s *P, const BoxGeo &G, int l_hi, int l_lo) {
     for (int l = l_hi; l >= l_lo; --l) {
         const int c0 = P->m2m_begin[l], c1 = P->m2m_begin[l + 1];
         if (c1 <= c0) continue;
+        if (!f32 && nb % 16 == 0 && (O.PR == 16 || O.PR == 32)) {
+            // one parent's sixteen densities per wave on the matrix cores
+            const int ntile = (c1 - c0) * (nb / 16);
+            const dim3 grid((unsigned)((ntile + 3) / 4));
+            const int4 *cs = reinterpret_cast<const int4 *>(P->m2m_cslot) + c0;
+            if (O.PR == 16)
+                hipLaunchKernelGGL((k_m2m_wave<1>), grid, dim3(256), 0, s, P->m2m_parents + c0, cs, c1 - c0, nb, Pn,
+                                   PD, O.PR, (int)P->zero_box(), (const double *)shq, (const double *)shi, (const double *)sho,
+                                   (double *)M);
+            else
+                hipLaunchKernelGGL((k_m2m_wave<2>), grid, dim3(256), 0, s, P->m2m_parents + c0, cs, c1 - c0, nb, Pn,
+                                   PD, O.PR, (int)P->zero_box(), (const double *)shq, (const double *)shi, (const double *)sho,
+                                   (double *)M);
+            VP_LAUNCH_CHECK();
+            continue;
+        }
         const int chunk = density_chunk(c1 - c0, nb);
         const dim3 grid((unsigned)(c1 - c0), (unsigned)((nb + chunk - 1) / chunk));
         switch (O.PR) {
