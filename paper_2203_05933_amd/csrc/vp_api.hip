@@ -516,6 +516,11 @@ static vp_status plan_build(const double *x, const double *y, const double *w, i
         }
         VP_HIP(hipStreamSynchronize(P->stream));
         vp::build_near_tables(P);
+        {
+            const vp::NearTables &N = P->near;
+            P->q_pattern_only = N.active && o.kernel != VP_KERNEL_YUKAWA && N.n_p2m_jobs_rest == 0 &&
+                                N.n_p2m_cols == N.n_p2m_leaf_cols && P->n_x_boxes == 0 && N.n_rest_leaves == 0;
+        }
         // the near tables read their source columns from a density-fastest copy
         // of the charges (one box's columns are one contiguous block)
         if (P->near.active && P->nbatch > 1) {
@@ -738,7 +743,7 @@ extern "C" vp_status vp_eval_grad_targets(vp_plan_t P, const double *f, double *
         return set_err(P, VP_EINVAL, "f and grad overlap");
     return guarded(P, [&] {
         P->timing_eval_begin();
-        vp::prepare_charges(P, f, false);
+        vp::prepare_charges(P, f, false, true);
         vp::run_fmm(P, false, true);
         vp::finish_grad(P, grad);
     });

@@ -76,7 +76,7 @@ __global__ void k_charge(const double *__restrict__ f, const int32_t *__restrict
 
 // The same, and qi[i][b] (density fastest) through an LDS transpose of the
 // workgroup's 64 points x nbatch densities, so that both stores write whole
-// contiguous rows.  Dynamic LDS: 64 (nbatch + 1) doubles.
+// contiguous rows (q == nullptr: only qi).  Dynamic LDS: 64 (nbatch + 1) doubles.
 __global__ void __launch_bounds__(64) k_charge_il(const double *__restrict__ f, const int32_t *__restrict__ perm,
                                                   const double *__restrict__ w, double *__restrict__ q,
                                                   int64_t len, int nbatch, double *__restrict__ qi) {
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(64) k_charge_il(const double *__restrict__ f, 
         const double wi = w ? w[i] : 1.0;
         for (int b = 0; b < nbatch; ++b) {
             const double v = wi * f[(int64_t)b * len + j];
-            q[(int64_t)b * len + i] = v;
+            if (q) q[(int64_t)b * len + i] = v;
             tile[li * ld + b] = v;
         }
     }
@@ -1993,10 +1993,11 @@ __global__ void k_interp_adjoint(const int64_t *__restrict__ in_start, const int
     }
 }
 
-void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
+void prepare_charges(vp_plan_s *P, const double *f, bool adjoint, bool grad) {
     int64_t len = adjoint ? P->m : P->n;
     const int32_t *perm = adjoint ? P->tperm : P->sperm;
     const double *w = adjoint ? nullptr : P->sw;
+    P->q_valid = true;
     if (!adjoint && P->os_p > 0) {
         P->qi_valid = false;
         P->stage_begin(VP_STAGE_CHARGE);
@@ -2013,9 +2014,11 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint) {
     P->qi_valid = P->qi != nullptr && P->table_nw == 1 &&
                   (P->qi_zero + QI_ZERO_PTS) * P->nbatch * 8 < ((int64_t)1 << 32) &&
                   P->qi_zero + QI_ZERO_PTS < (1 << 24);
+    P->q_valid = !(P->qi_valid && P->q_pattern_only && !adjoint && !grad);
     if (P->qi_valid)
         hipLaunchKernelGGL(k_charge_il, dim3((unsigned)((len + 63) / 64)), dim3(64),
-                           64 * (P->nbatch + 1) * sizeof(double), P->stream, f, perm, w, P->q, len, P->nbatch, P->qi);
+                           64 * (P->nbatch + 1) * sizeof(double), P->stream, f, perm, w,
+                           P->q_valid ? P->q : nullptr, len, P->nbatch, P->qi);
     else
         hipLaunchKernelGGL(k_charge, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, P->stream, f, perm, w,
                            P->q, len, P->nbatch);
@@ -2388,9 +2391,15 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, doub
         const E *op = f32 ? (const E *)N.p2m_op_f32 : (const E *)N.p2m_op;
         // the leading pattern-leaf columns all use operator 0: one fixed operator
         const int n0 = N.n_p2m_leaf_cols;
-        if (n0 > 0)
+        if (n0 > 0 && P->q_valid)
             launch_fixed_apply<double, E, E, RB, S, false>(P, N.p2m_cols, n0 * P->nbatch, a.in, a.out, a.nrows_out,
                                                            op, P->q, static_cast<E *>(P->Mexp));
+        else if (n0 > 0) {
+            // from the density-fastest copy: point k of column (box, d) at (start + k) nbatch + d
+            const ColAddr il{1, 0, R.sb, P->nbatch, P->nbatch};
+            launch_fixed_apply<double, E, E, RB, S, false>(P, N.p2m_cols, n0 * P->nbatch, il, a.out, a.nrows_out,
+                                                           op, P->qi, static_cast<E *>(P->Mexp));
+        }
         // the quadrant columns of X-list sources (operators 1..4)
         a.cols_box = N.p2m_cols + n0;
         a.ncols = (N.n_p2m_cols - n0) * P->nbatch;

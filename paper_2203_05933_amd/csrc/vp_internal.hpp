@@ -372,6 +372,12 @@ struct vp_plan_s {
     double *qi = nullptr;    // [max(n,m) + QI_ZERO_PTS][nbatch] the charges again, density fastest (near
                              // tables, nbatch > 1); the last QI_ZERO_PTS points stay zero (an absent source)
     int64_t qi_zero = 0;     // point index of that zero block (max(n, m))
+    // forward evaluations with the near tables whose only other reader of the
+    // charges is the pattern P2M of the leaves (no VALU P2M, quadrant P2M, P2L
+    // or leftover pairwise work): the pattern P2M then reads qi and q is not
+    // written (q_valid false)
+    bool q_pattern_only = false;
+    bool q_valid = true;
     bool qi_valid = false;   // qi holds this evaluation's charges
     void *Mexp = nullptr;    // [mexp_boxes()][nbatch][PD] (double or float)
     void *Lexp = nullptr;
@@ -465,7 +471,8 @@ std::vector<int32_t> tile_order_by_work(const std::vector<int32_t> &tile_ptr, in
 // one evaluation after prepare_charges; with u: the correction C f (adjoint C^T f) runs
 // beside the FMM and u = FMM sums (un-permuted; adjoint: times w) + correction
 void run_fmm(vp_plan_s *P, bool adjoint, bool grad, const double *f = nullptr, double *u = nullptr);
-void prepare_charges(vp_plan_s *P, const double *f, bool adjoint);
+// grad: the evaluation forms target gradients (its near field reads q)
+void prepare_charges(vp_plan_s *P, const double *f, bool adjoint, bool grad = false);
 void finish_grad(vp_plan_s *P, double *grad);
 void detect_runs(vp_plan_s *P);
 // vp_csr.hip

@@ -34,14 +34,19 @@ __device__ inline int ld_uniform(const int32_t *p, int i) {
     return ((const __attribute__((address_space(4))) int32_t *)p)[i];
 }
 
+// Column (box a, density d) of an array starts at off(a) + d bstride, its
+// element k kstride further on (kstride > 1 only for k_fixed_apply inputs:
+// the density-fastest charges, with start[] scaled by smult)
 struct ColAddr {
     int64_t bstride;
     int64_t box_mult;
     const int32_t *start;
-    __device__ inline int64_t off(int a) const { return start ? (int64_t)start[a] : box_mult * (int64_t)a; }
+    int64_t smult = 1;
+    int64_t kstride = 1;
+    __device__ inline int64_t off(int a) const { return start ? (int64_t)start[a] * smult : box_mult * (int64_t)a; }
     // the same for a box index that is uniform across the wave
     __device__ inline int64_t off_u(int a) const {
-        return start ? (int64_t)ld_uniform(start, a) : box_mult * (int64_t)a;
+        return start ? (int64_t)ld_uniform(start, a) * smult : box_mult * (int64_t)a;
     }
 };
 
@@ -297,14 +302,14 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
         const TI *ip;
         if (one_box) {
             const int box = ld_uniform(cols_box, t * 16 / nbatch);
-            ip = in + ia.off_u(box) + (int64_t)(t * 16 % nbatch + cl) * ia.bstride + g;
+            ip = in + ia.off_u(box) + (int64_t)(t * 16 % nbatch + cl) * ia.bstride + g * ia.kstride;
         } else {
             const int col = min(t * 16 + cl, ncols - 1);
             const int box = cols_box[col / nbatch], bt = col % nbatch;
-            ip = in + ia.off(box) + (int64_t)bt * ia.bstride + g;
+            ip = in + ia.off(box) + (int64_t)bt * ia.bstride + g * ia.kstride;
         }
 #pragma unroll
-        for (int s = 0; s < S; ++s) bv[s] = (TM)ip[4 * s];
+        for (int s = 0; s < S; ++s) bv[s] = (TM)ip[4 * s * ia.kstride];
     };
     int t = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     TM bcur[S], bnext[S];
