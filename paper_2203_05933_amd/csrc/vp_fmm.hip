@@ -2435,8 +2435,9 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, doub
                 fa.u = fin.u;
                 fa.m = fin.m;
                 // two workgroups per compute unit (64 KB of operators each), a
-                // quarter of them per class
-                const unsigned grid = 4u * (unsigned)std::max(1, std::min(128, (maxq + 15) / 16));
+                // quarter of them per class, in groups of 32 (the kernel's
+                // class-to-XCD mapping)
+                const unsigned grid = 32u * (unsigned)std::max(1, std::min(16, (maxq + 127) / 128));
                 if (N.npat != RBP * 16) throw Error(VP_EINTERNAL, "pattern size off its row blocks");
                 hipLaunchKernelGGL((k_l2p_fin<RBP, RBE * 4>), dim3(grid), dim3(256), 0, P->stream, fa, N.l2p_km,
                                    N.par_km, static_cast<const double *>(P->Lexp));

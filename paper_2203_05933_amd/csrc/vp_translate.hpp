@@ -416,8 +416,9 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
 // (so the L2L into that level never runs), and the finish of a forward
 // evaluation: u[b][perm[t]] = (near[b][t] + v) + u[b][perm[t]] for the leaf's
 // targets t.  A tile is one box's 16 densities from a.rec (grouped by child
-// class); each workgroup serves one class, with the L2P and that class's B_q
-// in LDS, and walks its class's tiles with a grid stride, one per wave.  The
+// class, in tree order within a class); each workgroup serves one class, with
+// the L2P and that class's B_q in LDS, and walks its class's tiles with a grid
+// stride, one per wave.  The
 // operators are in k-major fragments (lane group g takes the S consecutive
 // expansion rows S g ..), so a lane's column elements are contiguous and load
 // 16 bytes at a time.  The next tile's columns load while this tile's products
@@ -445,7 +446,12 @@ __global__ void __launch_bounds__(256, 2) k_l2p_fin(L2PFinArgs a, const double *
     static_assert(S % 2 == 0, "column elements load in pairs");
     __shared__ __align__(16) double sA[AE];
     __shared__ __align__(16) double sB[AE];
-    const int q = blockIdx.x & 3;
+    // workgroup b runs on XCD b % 8: the four classes of one position are
+    // workgroups b, b + 8, b + 16, b + 24, one XCD, so a parent's columns
+    // (read by its four children, one per class) come from that XCD's L2
+    // after the first read (the grid is a multiple of 32)
+    const int q = (blockIdx.x >> 3) & 3;
+    const int pos = (blockIdx.x & 7) | ((blockIdx.x >> 5) << 3);
     const int lane = threadIdx.x & 63, cl = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int e = threadIdx.x; e < AE; e += 256) {
@@ -454,8 +460,8 @@ __global__ void __launch_bounds__(256, 2) k_l2p_fin(L2PFinArgs a, const double *
     }
     __syncthreads();
     const int jq = a.qbeg[q], nq = a.qbeg[q + 1] - jq;
-    const int stride = (int)((gridDim.x + 3 - q) / 4) * 4;  // waves of this class
-    int j = (int)(blockIdx.x >> 2) * 4 + wave;
+    const int stride = (int)gridDim.x;  // waves of this class: a quarter of the workgroups, four waves each
+    int j = pos * 4 + wave;
     if (j >= nq) return;
     const int32_t *rec = a.rec + (int64_t)jq * 4;
     // Addresses: a uniform base (scalar registers) plus a 32-bit lane offset,
