@@ -734,6 +734,16 @@ def test_l2p_from_parents(c0, nbatch):
     d = _host(plan.eval_adjoint(_dev(g)))
     dref = direct.evaluate_adjoint(c0.x, c0.y, c0.w, g, c0.rowptr, c0.col, c0.val)
     assert max(relinf(d[b], dref[b]) for b in range(nbatch)) <= TOL64
+    # forward evaluations write only the density-fastest charges here; the
+    # target gradients (pairwise near field) need the other copy, and the next
+    # forward evaluation goes back to one copy
+    idx = gen.sample_indices(c0.n, 512, 72)
+    gr = _host(plan.eval_grad_targets(_dev(fs)))
+    gref = direct.smooth_grad(c0.x, c0.y, c0.w, fs, tidx=idx)
+    gerr = relinf(gr[:, :, idx], gref)
+    print(f"target gradients after a one-copy forward evaluation: rel_inf {gerr:.3e}")
+    assert gerr <= TOL64
+    assert np.array_equal(_host(plan.eval(_dev(fs))), u)
     plan.close()
     # one density: the plain path
     p1 = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=30, root=c0.root)
