@@ -708,18 +708,15 @@ __global__ void __launch_bounds__(64 * NW) k_translate_split(TranslateArgs a, co
 // sixteen densities of a box lie a whole charge array apart).
 //
 // Schedule: k-steps outermost, so each step issues RB * CT independent
-// products (no product waits on the one before it).  Operator fragments
-// stream PF k-steps ahead of the products, across operator boundaries (the
-// first steps of the next operator load during the last steps of this one),
-// and the next operator's source columns load one step at a time beside
-// them (loads complete in issue order, so spreading them keeps every wait
-// short).
+// products (no product waits on the one before it).  Operator fragments and
+// source charges stream PF k-steps ahead of the products through two small
+// register rings, across operator boundaries (the first steps of the next
+// operator and of its source columns load during the last steps of this
+// one); the rings leave room for three waves per SIMD.
 //
 // Addressing is kept off the VALU, which shares the SIMD with the FP64
 // products: the operator code comes through the scalar unit, so an
-// operator's fragments are one uniform base plus fixed per-lane offsets; the
-// entries are unrolled by two over two column buffers (no copies between
-// them).  IL: each column's source is staged as a point offset into the
+// operator's fragments are one uniform base plus fixed per-lane offsets.  IL: each column's source is staged as a point offset into the
 // charge copy (an absent source as the block of zeros at point a.in_zero),
 // so a column address is one 24-bit multiply-add into a 32-bit byte offset;
 // NB > 0 fixes nbatch (the k-step stride then folds into the load offsets).
@@ -763,13 +760,6 @@ __global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double 
         const int src = s_src[e][c * 16 + cl];
         return (src >= 0 ? in + a.in.off(src) + (int64_t)bt[c] * a.in.bstride : zc) + g;
     };
-    auto ld_col = [&](int e, double(&b)[CT][S], int s, const unsigned(&off)[CT], const double *const(&ip)[CT]) {
-#pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            if constexpr (IL) b[c][s] = *reinterpret_cast<const double *>(inb + (size_t)off[c] + (size_t)s * kstb);
-            else b[c][s] = ip[c][4 * s];
-        }
-    };
     auto col_addr = [&](int e, unsigned(&off)[CT], const double *(&ip)[CT]) {
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
@@ -797,50 +787,53 @@ __global__ void __launch_bounds__(64) k_tables_ct(TranslateArgs a, const double 
             else s_src[oi][c] = src;
         }
         __syncthreads();
-        double bA[CT][S], bB[CT][S];
-        {
-            unsigned off[CT];
-            const double *ip[CT];
-            col_addr(0, off, ip);
+        // rings: k-step j of the stream (operator fragments and source
+        // charges alike) sits in slot j % NBUF, loaded PF steps ahead
+        double af[NBUF][RB], cv[NBUF][CT];
+        unsigned offc[CT], offn[CT];
+        const double *ipc[CT], *ipn[CT];
+        col_addr(0, offc, ipc);
+        auto ld_ch = [&](int s, double(&dst)[CT], const unsigned(&off)[CT], const double *const(&ip)[CT]) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) ld_col(0, bA, s, off, ip);
-        }
-        // ring of operator fragments: k-step j of the stream sits in slot j % NBUF
-        double af[NBUF][RB];
+            for (int c = 0; c < CT; ++c) {
+                if constexpr (IL) dst[c] = *reinterpret_cast<const double *>(inb + (size_t)off[c] + (size_t)s * kstb);
+                else dst[c] = ip[c][4 * s];
+            }
+        };
         {
             const char *A0 = op_base(ld_uniform(a.tile_ops, e0 + c0));
 #pragma unroll
-            for (int p = 0; p < PF; ++p)
+            for (int p = 0; p < PF; ++p) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r) af[p][r] = ld_op(A0, r, p);
+                ld_ch(p, cv[p], offc, ipc);
+            }
         }
-        auto body = [&](int e, double(&bv)[CT][S], double(&bn)[CT][S]) {
+        for (int e = 0; e < nc; ++e) {
             // this operator and the next (this one again after the last: loaded, never used)
             const char *Ao = op_base(ld_uniform(a.tile_ops, e0 + c0 + e));
             const char *An = op_base(ld_uniform(a.tile_ops, e0 + c0 + (e + 1 < nc ? e + 1 : e)));
-            unsigned off[CT];
-            const double *ip[CT];
-            col_addr(e + 1, off, ip);
+            col_addr(e + 1, offn, ipn);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int sp = s + PF;
 #pragma unroll
                 for (int r = 0; r < RB; ++r) af[sp % NBUF][r] = sp < S ? ld_op(Ao, r, sp) : ld_op(An, r, sp - S);
-                ld_col(e + 1, bn, s, off, ip);
+                if (sp < S) ld_ch(sp, cv[sp % NBUF], offc, ipc);
+                else ld_ch(sp - S, cv[sp % NBUF], offn, ipn);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
 #pragma unroll
-                    for (int c = 0; c < CT; ++c) acc[c][r] = M::op(af[s % NBUF][r], bv[c][s], acc[c][r]);
+                    for (int c = 0; c < CT; ++c) acc[c][r] = M::op(af[s % NBUF][r], cv[s % NBUF][c], acc[c][r]);
                 __builtin_amdgcn_sched_barrier(0);
             }
-        };
-        int e = 0;
-        for (; e + 1 < nc; e += 2) {
-            body(e, bA, bB);
-            body(e + 1, bB, bA);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                offc[c] = offn[c];
+                ipc[c] = ipn[c];
+            }
         }
-        if (e < nc) body(e, bA, bB);
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
