@@ -170,6 +170,31 @@ def test_eval_adaptive_tree(targets):
     plan.close()
 
 
+def test_adaptive_tree_sixteen_densities():
+    """An adaptive tree with 16 densities: the matrix-core M2M takes one
+    parent's 16 densities per wave, and parents with fewer than four
+    children read the multipole array's zero block for the absent ones;
+    the M2L's absent sources read the same block.  Forward and adjoint
+    against the oracle, every density."""
+    vp = _vp()
+    x, y, w, _, rng = _clustered(11)
+    f = rng.standard_normal((16, x.shape[0]))
+    plan = vp.Plan(x, y, w, order=30, max_leaf=32, nbatch=16, root=(-1.0, -1.0, 2.0))
+    info = plan.info()
+    assert info["list_len"][2] > 0 and info["list_len"][3] > 0  # W and X lists in use
+    u = _host(plan.eval(_dev(f)))
+    ref = direct.smooth(x, y, w, f)
+    err = max(relinf(u[b], ref[b]) for b in range(16))
+    g = rng.standard_normal((16, x.shape[0]))
+    d = _host(plan.eval_adjoint(_dev(g)))
+    dref = direct.smooth_adjoint(x, y, w, g)
+    aerr = max(relinf(d[b], dref[b]) for b in range(16))
+    print(f"adaptive tree, 16 densities: rel_inf {err:.3e}, adjoint {aerr:.3e}")
+    assert err <= TOL64
+    assert aerr <= TOL64
+    plan.close()
+
+
 def test_adjoint_config0(c0):
     vp = _vp()
     plan = vp.Plan(c0.x, c0.y, c0.w, rowptr=c0.rowptr, col=c0.col, val=c0.val, order=30, root=c0.root)
