@@ -562,10 +562,23 @@ def main():
             r32["m2l"] = desc
             r32["speedup_vs_fp64"] = r32["value"] / value
             st32, roof32, _ = rooflines(inf32, tim32, wl.name)
+            plan32.close()
+            if key == "fp32_scaled" and not r32["choices"]["one_stream"] and not args.no_one_stream:
+                # the roofline from a serialized pass, as for FP64 (with three streams the
+                # stage times include the other streams' kernels)
+                ch = r32["choices"]
+                p1 = make_plan(wl, args.order_fp32, "fp32", m2l_mode=ch["m2l_mode"], one_stream=True,
+                               max_leaf=ch["max_leaf"], m2l_waves=ch["m2l_waves"], table_waves=ch["table_waves"])
+                u1 = torch.empty_like(u32)
+                _, tim1 = time_evals(p1, f, u1, args.steps, args.warmup)
+                r32["roofline_overlapped"] = roof32
+                st32, roof32, _ = rooflines(p1.info(), tim1, wl.name)
+                r32["roofline_source"] = "serialized pass (one stream, the same kernels)"
+                p1.close()
+                del u1
             r32["dominant_stage"] = st32
             r32["roofline"] = roof32
             forms32[key] = (r32, u32)
-            plan32.close()
 
     cpu = None
     rel64 = None
