@@ -358,6 +358,24 @@ def cpu_baseline(wl, count):
 # ----------------------------------------------------------------------------
 # secondary records
 # ----------------------------------------------------------------------------
+def serialized_roofline(wl, f, order, precision, rec, roof, steps, warmup):
+    """The roofline of a three-stream plan's dominant stage from a one-stream
+    pass of the same kernels (with three streams the stage times include the
+    other streams' kernels); returns (stage, roofline) and keeps the overlapped
+    record in rec["roofline_overlapped"]."""
+    import torch
+    ch = rec["choices"]
+    p1 = make_plan(wl, order, precision, m2l_mode=ch["m2l_mode"], one_stream=True, max_leaf=ch["max_leaf"],
+                   m2l_waves=ch["m2l_waves"], table_waves=ch["table_waves"])
+    u1 = torch.empty((wl.nbatch, wl.m), dtype=torch.float64, device="cuda:0")
+    _, tim1 = time_evals(p1, f, u1, steps, warmup)
+    rec["roofline_overlapped"] = roof
+    stage, roof1, _ = rooflines(p1.info(), tim1, wl.name)
+    rec["roofline_source"] = "serialized pass (one stream, the same kernels)"
+    p1.close()
+    return stage, roof1
+
+
 def precision_pair(name, steps, warmup, order, order32, with_cpu):
     """FP64 beside the FP32-bulk form (scaled and split hi/lo M2L) on one workload."""
     import torch
@@ -376,6 +394,9 @@ def precision_pair(name, steps, warmup, order, order32, with_cpu):
     for key, p, prec, mode in forms:
         rec, u, info, tim, plan = run_form(wl, f, p, prec, steps, warmup, mode, label=wl.name)
         stage, roof, _ = rooflines(info, tim, wl.name)
+        plan.close()
+        if not rec["choices"]["one_stream"]:
+            stage, roof = serialized_roofline(wl, f, p, prec, rec, roof, steps, warmup)
         rec["dominant_stage"] = stage
         rec["roofline"] = roof
         if ref is not None:
@@ -386,7 +407,6 @@ def precision_pair(name, steps, warmup, order, order32, with_cpu):
         else:
             rec["speedup_vs_fp64"] = rec["value"] / base
         out[key] = rec
-        plan.close()
         del u
     return out
 
@@ -564,18 +584,9 @@ def main():
             st32, roof32, _ = rooflines(inf32, tim32, wl.name)
             plan32.close()
             if key == "fp32_scaled" and not r32["choices"]["one_stream"] and not args.no_one_stream:
-                # the roofline from a serialized pass, as for FP64 (with three streams the
-                # stage times include the other streams' kernels)
-                ch = r32["choices"]
-                p1 = make_plan(wl, args.order_fp32, "fp32", m2l_mode=ch["m2l_mode"], one_stream=True,
-                               max_leaf=ch["max_leaf"], m2l_waves=ch["m2l_waves"], table_waves=ch["table_waves"])
-                u1 = torch.empty_like(u32)
-                _, tim1 = time_evals(p1, f, u1, args.steps, args.warmup)
-                r32["roofline_overlapped"] = roof32
-                st32, roof32, _ = rooflines(p1.info(), tim1, wl.name)
-                r32["roofline_source"] = "serialized pass (one stream, the same kernels)"
-                p1.close()
-                del u1
+                # the roofline from a serialized pass, as for FP64
+                st32, roof32 = serialized_roofline(wl, f, args.order_fp32, "fp32", r32, roof32, args.steps,
+                                                   args.warmup)
             r32["dominant_stage"] = st32
             r32["roofline"] = roof32
             forms32[key] = (r32, u32)

@@ -264,7 +264,8 @@ typedef struct {
     int32_t nbox, nleaf, nlevels, self_targets;
     int64_t list_len[4];       /* total entries of the U, V, W, X lists */
     int64_t table_leaves;      /* leaves served by near-field tables */
-    int64_t near_pairs;        /* pairwise near-field interactions per density */
+    int64_t near_pairs;        /* (target, source) pairs the pairwise near-field kernel evaluates
+                                  per density in the forward sum */
     int64_t workspace_bytes;   /* device memory held by the plan */
     int64_t m2l_translations;  /* M2L translations per density, V lists plus the
                                   virtual children of X-list sources */

@@ -255,19 +255,20 @@ void build_near_tables(vp_plan_s *P) {
         // no tables: the full U lists, with nodes as sources (evaluation) and,
         // for separate targets, targets as sources (adjoint)
         build_p2p_gather(P, leaves, uptr, uidx, sb, se, P->sx, P->sy, P->g_fwd);
-        if (!P->self) {
-            std::vector<int32_t> tb(nbox), te(nbox);
-            VP_HIP(hipMemcpyAsync(tb.data(), T.tb, 4 * nbox, hipMemcpyDeviceToHost, s));
-            VP_HIP(hipMemcpyAsync(te.data(), T.te, 4 * nbox, hipMemcpyDeviceToHost, s));
-            VP_HIP(hipStreamSynchronize(s));
-            build_p2p_gather(P, leaves, uptr, uidx, tb, te, P->tx, P->ty, P->g_adj);
-        }
+    }
+    // target ranges: the nodes themselves, or a separate target set
+    std::vector<int32_t> tb = sb, te = se;
+    if (!P->self) {
+        VP_HIP(hipMemcpyAsync(tb.data(), T.tb, 4 * nbox, hipMemcpyDeviceToHost, s));
+        VP_HIP(hipMemcpyAsync(te.data(), T.te, 4 * nbox, hipMemcpyDeviceToHost, s));
+        VP_HIP(hipStreamSynchronize(s));
+        if (!N.active) build_p2p_gather(P, leaves, uptr, uidx, tb, te, P->tx, P->ty, P->g_adj);
     }
 
-    // near-field pair count served by the pairwise kernel
+    // (target, source) pairs the pairwise kernel evaluates in the forward sum
     int64_t pairs = 0;
     for (int b = 0; b < nbox; ++b)
-        for (int e = rptr[b]; e < rptr[b + 1]; ++e) pairs += (int64_t)(se[b] - sb[b]) * (se[ridx[e]] - sb[ridx[e]]);
+        for (int e = rptr[b]; e < rptr[b + 1]; ++e) pairs += (int64_t)(te[b] - tb[b]) * (se[ridx[e]] - sb[ridx[e]]);
     P->near_pairs = pairs;
     // (target, source) pairs the near-field tables serve, per density
     int64_t tpairs = 0;

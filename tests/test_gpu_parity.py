@@ -91,6 +91,14 @@ def test_tree_and_lists_match_oracle(case, c0):
     plan = vp.Plan(x, y, w, tx, ty, max_leaf=ml, root=root)
     tr = OT.build_tree(x, y, tx, ty, root=root, max_leaf=ml)
     _compare_tree(plan, tr, tx is None)
+    if tx is not None:
+        # separate targets: the pairwise kernel serves every U-list pair, and its
+        # work count is targets of the leaf times sources of the neighbour
+        p, v = OT.all_lists(tr)["U"]
+        nt = tr.tgt_end - tr.tgt_begin
+        ns = tr.src_end - tr.src_begin
+        pairs = sum(int(nt[b]) * int(ns[v[p[b]:p[b + 1]]].sum()) for b in range(tr.nbox))
+        assert plan.info()["near_pairs"] == pairs
     plan.close()
 
 
