@@ -303,7 +303,10 @@ typedef struct {
     int32_t l2p_from_parents;  /* 1: forward evaluations evaluate the deepest level's pattern leaves
                                   from their parents' local expansions (L2L into that level folded
                                   into the L2P matrices; uniform grids, densities a multiple of 16) */
-    int32_t reserved3;
+    int32_t corr_folded;       /* 1: forward evaluations apply the own-cell corrections inside the
+                                  near-field tables (one shared block on congruent leaves: the self
+                                  slot's matrix becomes the leaf's own-cell quadrature, Section 4);
+                                  the correction pass is skipped */
 } vp_plan_info_t;
 
 vp_status vp_get_info(vp_plan_t plan, vp_plan_info_t *info);

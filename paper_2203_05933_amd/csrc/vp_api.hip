@@ -830,6 +830,7 @@ extern "C" vp_status vp_get_info(vp_plan_t P, vp_plan_info_t *info) {
     info->corr_shared_cells = P->ncell_shared;
     info->corr_groups = P->nbatch == 1 ? P->ngrp : 0;
     info->corr_one_block = P->corr_op != nullptr ? 1 : 0;
+    info->corr_folded = P->near.corr_folded ? 1 : 0;
     info->table_pattern = P->near.active ? P->near.npat : 0;
     info->corr_values_read = P->ncell > 0 ? P->corr_values_read : P->nnz;
     info->table_tile_ops = P->near.table_tile_ops;

@@ -1461,6 +1461,11 @@ void build_cells(vp_plan_s *P, bool transposed) {
             VP_HIP(hipMemcpyAsync(A.data(), vv + vbh[0], 8 * A.size(), hipMemcpyDeviceToHost, s));
             VP_HIP(hipStreamSynchronize(s));
             vp_to_frag(A.data(), 64, 64, 64, F.data());  // rows = cell rows, cols = the cell's column run
+            if (!transposed) {
+                P->corr_block = A;
+                P->corr_cell_row = row0;
+                P->corr_cell_col = col0;
+            }
             op = P->mem.alloc<double>(F.size());
             VP_HIP(hipMemcpyAsync(op, F.data(), 8 * F.size(), hipMemcpyHostToDevice, s));
             if (!P->cell_iota || (int)P->n_cell_iota < nc) {
@@ -2260,7 +2265,7 @@ static void run_p2p(vp_plan_s *P, const PointRoles &R, const int32_t *leaves, in
 // Near-field tables of congruent leaves: acc[:, leaf] += sum_o K_{l,o} q[:, nbr_o(leaf)],
 // all table levels in one launch (operator index = level block * NTOPS + slot).
 template <int RB>
-static void launch_tables(vp_plan_s *P, const PointRoles &R) {
+static void launch_tables(vp_plan_s *P, const PointRoles &R, const double *K) {
     NearTables &N = P->near;
     constexpr int S = RB * 4;
     TranslateArgs a;
@@ -2292,13 +2297,13 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
             const dim3 grid((unsigned)((a.ncols + 31) / 32));
             a.in_zero = (int)P->qi_zero;
             if (P->qi_valid && P->nbatch == 16)
-                hipLaunchKernelGGL((k_tables_ct<RB, S, 2, true, 16>), grid, dim3(64), 0, P->stream, a, N.K, P->qi,
+                hipLaunchKernelGGL((k_tables_ct<RB, S, 2, true, 16>), grid, dim3(64), 0, P->stream, a, K, P->qi,
                                    P->acc);
             else if (P->qi_valid)
-                hipLaunchKernelGGL((k_tables_ct<RB, S, 2, true>), grid, dim3(64), 0, P->stream, a, N.K, P->qi,
+                hipLaunchKernelGGL((k_tables_ct<RB, S, 2, true>), grid, dim3(64), 0, P->stream, a, K, P->qi,
                                    P->acc);
             else
-                hipLaunchKernelGGL((k_tables_ct<RB, S, 2, false>), grid, dim3(64), 0, P->stream, a, N.K, P->q,
+                hipLaunchKernelGGL((k_tables_ct<RB, S, 2, false>), grid, dim3(64), 0, P->stream, a, K, P->q,
                                    P->acc);
             done = true;
         }
@@ -2306,23 +2311,23 @@ static void launch_tables(vp_plan_s *P, const PointRoles &R) {
     if (done) {
     } else if (P->table_nw <= 2)
         hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, false, 2>), dim3(blocks),
-                           dim3(128), 0, P->stream, a, N.K, (const double *)nullptr, P->q, P->acc);
+                           dim3(128), 0, P->stream, a, K, (const double *)nullptr, P->q, P->acc);
     else
         hipLaunchKernelGGL((k_translate_split<double, double, double, RB, S, false, false, 4>), dim3(blocks),
-                           dim3(256), 0, P->stream, a, N.K, (const double *)nullptr, P->q, P->acc);
+                           dim3(256), 0, P->stream, a, K, (const double *)nullptr, P->q, P->acc);
     VP_LAUNCH_CHECK();
 }
 
-static void run_tables(vp_plan_s *P, const PointRoles &R) {
+static void run_tables(vp_plan_s *P, const PointRoles &R, const double *K) {
     switch (P->near.npat) {
-        case 16: launch_tables<1>(P, R); break;
-        case 32: launch_tables<2>(P, R); break;
-        case 48: launch_tables<3>(P, R); break;
-        case 64: launch_tables<4>(P, R); break;
-        case 80: launch_tables<5>(P, R); break;
-        case 96: launch_tables<6>(P, R); break;
-        case 112: launch_tables<7>(P, R); break;
-        case 128: launch_tables<8>(P, R); break;
+        case 16: launch_tables<1>(P, R, K); break;
+        case 32: launch_tables<2>(P, R, K); break;
+        case 48: launch_tables<3>(P, R, K); break;
+        case 64: launch_tables<4>(P, R, K); break;
+        case 80: launch_tables<5>(P, R, K); break;
+        case 96: launch_tables<6>(P, R, K); break;
+        case 112: launch_tables<7>(P, R, K); break;
+        case 128: launch_tables<8>(P, R, K); break;
         default: throw Error(VP_EINTERNAL, "unsupported pattern size");
     }
 }
@@ -2439,8 +2444,12 @@ static void launch_pattern_ops(vp_plan_s *P, const PointRoles &R, int kind, doub
                 // class-to-XCD mapping)
                 const unsigned grid = 32u * (unsigned)std::max(1, std::min(16, (maxq + 127) / 128));
                 if (N.npat != RBP * 16) throw Error(VP_EINTERNAL, "pattern size off its row blocks");
-                hipLaunchKernelGGL((k_l2p_fin<RBP, RBE * 4>), dim3(grid), dim3(256), 0, P->stream, fa, N.l2p_km,
-                                   N.par_km, static_cast<const double *>(P->Lexp));
+                if (fin.add_u)
+                    hipLaunchKernelGGL((k_l2p_fin<RBP, RBE * 4, true>), dim3(grid), dim3(256), 0, P->stream, fa,
+                                       N.l2p_km, N.par_km, static_cast<const double *>(P->Lexp));
+                else
+                    hipLaunchKernelGGL((k_l2p_fin<RBP, RBE * 4, false>), dim3(grid), dim3(256), 0, P->stream, fa,
+                                       N.l2p_km, N.par_km, static_cast<const double *>(P->Lexp));
                 VP_LAUNCH_CHECK();
                 return;
             }
@@ -2538,6 +2547,8 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
     const bool coarse = fmm && L0 > 2;
     // forward evaluation on an all-pattern grid: the L2P launch writes the output
     const bool fused = tables && fmm && N.fused_finish && !adjoint && u != nullptr;
+    // and with the own-cell corrections folded into the near tables' self slot
+    const bool folded = fused && N.corr_folded;
     hipStream_t ms = P->stream;
     hipStream_t s2 = one ? ms : P->aux, s3 = one ? ms : P->aux2;
     struct Restore {
@@ -2571,12 +2582,12 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
     // second stream: correction (HBM bound) and the near field
     P->stream = s2;
     auto corr = [&] {
-        if (u) correction_apply(P, f, u, adjoint);
+        if (u && !folded) correction_apply(P, f, u, adjoint);
     };
     auto tab = [&] {
         if (tables) {
             P->stage_begin(VP_STAGE_TABLES);
-            run_tables(P, R);
+            run_tables(P, R, folded ? N.Kf : N.K);
             P->stage_end(VP_STAGE_TABLES);
         }
     };
@@ -2684,6 +2695,7 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
             fin.perm = P->tperm;
             fin.m = P->m;
             fin.u = u;
+            fin.add_u = !folded;
             run_far<E, false>(P, R, G, P->acc_far, tables, 1, fin);
         } else if (fmm) {
             run_far<E, false>(P, R, G, P->acc_far, tables, 1);
@@ -2724,7 +2736,7 @@ static void run_yukawa(vp_plan_s *P, const PointRoles &R, bool adjoint, const do
     double *M = static_cast<double *>(P->Mexp), *Lx = static_cast<double *>(P->Lexp);
     if (u) correction_apply(P, f, u, adjoint);
     P->stage_begin(VP_STAGE_TABLES);
-    run_tables(P, R);
+    run_tables(P, R, N.K);
     P->stage_end(VP_STAGE_TABLES);
     const bool fmm = L >= 2;
     if (!fmm) {

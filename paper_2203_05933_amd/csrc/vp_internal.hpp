@@ -216,6 +216,10 @@ struct NearTables {
     int32_t *tile2_order = nullptr;
     int64_t table_tile_ops = 0;
     double *K = nullptr;              // [tab level][41] near matrices, A-fragment order
+    // forward evaluations with the own-cell corrections folded into the self
+    // slot (K_self + C W^-1 on the charges W f): K with that slot replaced
+    double *Kf = nullptr;
+    bool corr_folded = false;
     int32_t *pair_uptr = nullptr;     // U lists minus the table-served entries
     int32_t *pair_uidx = nullptr;
     int64_t rest_len = 0;
@@ -355,6 +359,10 @@ struct vp_plan_s {
     int64_t corr_values_read = 0;   // values the forward apply reads from memory
     // every cell one shared 64 x 64 block: that block in A-fragment order (else null)
     double *corr_op = nullptr, *corr_opT = nullptr;
+    // the same forward block row-major on the host, with the cells' first
+    // rows ([ncell + 1]) and first columns (for folding C into the near tables)
+    std::vector<double> corr_block;
+    std::vector<int32_t> corr_cell_row, corr_cell_col;
     int32_t *cell_iota = nullptr;   // 0, 1, 2, ... (the cells as the fixed-operator kernel's columns)
     int n_cell_iota = 0;
 

@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstring>
 #include <map>
 #include <vector>
 
@@ -541,6 +542,81 @@ void build_near_tables(vp_plan_s *P) {
                 N.par_l2p = true;
                 N.par_level = Lf;
                 VP_HIP(hipStreamSynchronize(s));  // Bk, Bqf, rec leave scope
+            }
+        }
+        // Own-cell corrections folded into the near tables (forward).  On a
+        // grid of congruent boxes whose corrections are one shared block A
+        // (Section 4: the correction depends on the box shape only), every
+        // leaf is one cell, and a leaf's sorted node i is row sigma(i) and
+        // column tau(i) of its cell with the same sigma, tau and weights w in
+        // every leaf, the correction C f of the leaf equals (A' W^-1)(W f)
+        // with A'_ij = A_sigma(i),tau(j): the self slot's operator becomes
+        // K_self + A' W^-1 and the correction pass is dropped.  K_self W + A'
+        // is the leaf's exact own-cell quadrature matrix (the correction is
+        // its difference from the smooth rule, Section 4.1).
+        N.corr_folded = false;
+        std::vector<int32_t> self_leaves;  // leaves whose own box is a table slot
+        for (int b : leaves)
+            if (tslot[(size_t)b * NTOPS + 4] == b) self_leaves.push_back(b);
+        if (N.fused_finish && P->self && !P->corr_block.empty() && P->opt.kernel != VP_KERNEL_YUKAWA &&
+            N.tab_levels.size() == 1 && np == 64 && P->corr_cell_col.size() == self_leaves.size() &&
+            P->m == P->n) {
+            const std::vector<int32_t> &crow = P->corr_cell_row, &ccol = P->corr_cell_col;
+            const int nc = (int)ccol.size();
+            std::vector<int32_t> perm(P->n);
+            std::vector<double> wu(P->n);
+            VP_HIP(hipMemcpyAsync(perm.data(), P->sperm, 4 * (size_t)P->n, hipMemcpyDeviceToHost, s));
+            VP_HIP(hipMemcpyAsync(wu.data(), P->w_user, 8 * (size_t)P->n, hipMemcpyDeviceToHost, s));
+            VP_HIP(hipStreamSynchronize(s));
+            std::vector<int32_t> cell_of(P->m, -1), used(nc, 0);
+            bool ok = (int64_t)crow.back() == P->m;
+            for (int k = 0; ok && k < nc; ++k) {
+                ok = crow[k + 1] - crow[k] == 64 && ccol[k] >= 0 && (int64_t)ccol[k] + 64 <= P->n;
+                for (int r = crow[k]; ok && r < crow[k + 1]; ++r) cell_of[r] = k;
+            }
+            std::vector<int32_t> sig(64), tau(64);
+            std::vector<double> wref(64);
+            bool first = true;
+            for (size_t li = 0; ok && li < self_leaves.size(); ++li) {
+                const int b = self_leaves[li];
+                ok = se[b] - sb[b] == 64 && lev[b] == N.tab_levels[0];
+                const int k = ok ? cell_of[perm[sb[b]]] : -1;
+                ok = ok && k >= 0 && !used[k];
+                if (!ok) break;
+                used[k] = 1;
+                for (int i = 0; ok && i < 64; ++i) {
+                    const int32_t uu = perm[sb[b] + i];
+                    const int32_t si = uu - crow[k], ti = uu - ccol[k];
+                    ok = cell_of[uu] == k && ti >= 0 && ti < 64;
+                    if (!ok) break;
+                    if (first) {
+                        sig[i] = si;
+                        tau[i] = ti;
+                        wref[i] = wu[uu];
+                        ok = std::isfinite(wref[i]) && wref[i] != 0.0;
+                    } else {
+                        ok = sig[i] == si && tau[i] == ti &&
+                             std::memcmp(&wref[i], &wu[uu], sizeof(double)) == 0;
+                    }
+                }
+                first = false;
+            }
+            if (ok) {
+                const double h = T.side[N.tab_levels[0]];
+                const double two_log_h = 2.0 * std::log(h);
+                std::vector<double> Rs((size_t)np * np), Kf(K);
+                const std::vector<double> &A = P->corr_block;
+                for (int i = 0; i < np; ++i)
+                    for (int j = 0; j < np; ++j) {
+                        const double ex = rx[j] - rx[i], ey = ry[j] - ry[i];
+                        const double r2 = ex * ex + ey * ey;
+                        const double g = (r2 == 0.0) ? 0.0 : -INV_4PI * (std::log(r2) + two_log_h);
+                        Rs[(size_t)i * np + j] = g + A[(size_t)sig[i] * 64 + tau[j]] / wref[j];
+                    }
+                vp_to_frag(Rs.data(), np, np, np, Kf.data() + (size_t)4 * np * np);
+                N.Kf = upload(P, Kf);
+                N.corr_folded = true;
+                VP_HIP(hipStreamSynchronize(s));  // Kf leaves scope
             }
         }
         if (P->fp32) {

@@ -259,12 +259,14 @@ __global__ void __launch_bounds__(256) k_pattern_op(TranslateArgs a, const TM *_
 // without ACCUM.  FIN (pattern L2P of a forward evaluation whose far field
 // has no other writer): the column's value v at sorted target t goes to the
 // output in user order, u[b][perm[t]] = (near[b][t] + v) + u[b][perm[t]]
-// (u holds the correction row), the sum k_add_acc forms otherwise.
+// (u holds the correction row; without fin.add_u, u = near + v), the sum
+// k_add_acc forms otherwise.
 struct FinishArgs {
     const double *near = nullptr;  // [nbatch][ntgt] near-field sums, sorted order
     const int32_t *perm = nullptr; // sorted target -> user index
     int64_t m = 0;                 // output row length
     double *u = nullptr;
+    bool add_u = true;             // add the correction rows already in u (false: u is only written)
 };
 
 // ALDS: the operator sits in LDS, copied once per workgroup, instead of in
@@ -356,7 +358,7 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
                     const int row = r * 16 + cl;
                     if (row < nrows_out) {
                         double *o = ub + pr[r];
-                        *o = (nr[row] + (double)accs[r][i]) + *o;
+                        *o = fin.add_u ? (nr[row] + (double)accs[r][i]) + *o : nr[row] + (double)accs[r][i];
                     }
                 }
             }
@@ -390,7 +392,8 @@ __global__ void __launch_bounds__(256, ALDS ? 3 : 1) k_fixed_apply(const int32_t
                     const int row = r * 16 + cl;
                     if (row < nrows_out) {
                         double *o = ub + fin.perm[t0 + row];
-                        *o = (fin.near[nb0 + t0 + row] + (double)accs[r][i]) + *o;
+                        const double v = fin.near[nb0 + t0 + row] + (double)accs[r][i];
+                        *o = fin.add_u ? v + *o : v;
                     }
                 }
             } else {
@@ -438,7 +441,8 @@ struct L2PFinArgs {
     int64_t m;
 };
 
-template <int RB, int S>
+// ADDU: add the correction rows already in u (else u is only written)
+template <int RB, int S, bool ADDU>
 __global__ void __launch_bounds__(256, 2) k_l2p_fin(L2PFinArgs a, const double *__restrict__ A,
                                                     const double *__restrict__ Bq4, const double *__restrict__ L) {
     typedef Mfma<double> M;
@@ -527,7 +531,7 @@ __global__ void __launch_bounds__(256, 2) k_l2p_fin(L2PFinArgs a, const double *
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 nv[r][i] = *reinterpret_cast<const double *>(nb + (size_t)near_off0 + (size_t)(r * 16 * 8));
-                uv[r][i] = *reinterpret_cast<const double *>(ub + (size_t)uoff[r]);
+                uv[r][i] = ADDU ? *reinterpret_cast<const double *>(ub + (size_t)uoff[r]) : 0.0;
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -538,7 +542,8 @@ __global__ void __launch_bounds__(256, 2) k_l2p_fin(L2PFinArgs a, const double *
             char *ub = reinterpret_cast<char *>(a.u + (int64_t)(d0 + 4 * i) * a.m);
 #pragma unroll
             for (int r = 0; r < RB; ++r)
-                *reinterpret_cast<double *>(ub + (size_t)uoff[r]) = (nv[r][i] + acc[r][i]) + uv[r][i];
+                *reinterpret_cast<double *>(ub + (size_t)uoff[r]) =
+                    ADDU ? (nv[r][i] + acc[r][i]) + uv[r][i] : nv[r][i] + acc[r][i];
         }
         // the operator fragments are read from LDS per tile (hoisted out of
         // the loop they would need every register)

@@ -78,7 +78,7 @@ class PlanInfo(ctypes.Structure):
                 ("os_p", ctypes.c_int32), ("os_q", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("table_pattern", ctypes.c_int32), ("lam", ctypes.c_double), ("tuned", ctypes.c_int32),
                 ("m2l_waves", ctypes.c_int32), ("table_waves", ctypes.c_int32), ("one_stream", ctypes.c_int32),
-                ("tune_ms", ctypes.c_double), ("l2p_from_parents", ctypes.c_int32), ("reserved3", ctypes.c_int32)]
+                ("tune_ms", ctypes.c_double), ("l2p_from_parents", ctypes.c_int32), ("corr_folded", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -784,6 +784,47 @@ def test_l2p_from_parents(c0, nbatch):
     p1.close()
 
 
+@pytest.mark.parametrize("case", ["shared", "shared_3_densities", "shared_fp32", "reordered_box", "per_entry"])
+def test_corrections_folded_into_tables(c0, case):
+    """Own-cell corrections that are one shared block on congruent leaves
+    (Section 4: the correction depends on the box shape only) are folded into
+    the near tables' self slot for forward evaluations.  The fold is declined
+    when one box lists its nodes in another order (its rows and columns of the
+    shared block meet the nodes in another order) or when the values differ
+    per cell.  Forward and adjoint against the oracle either way."""
+    vp = _vp()
+    nb = 3 if case == "shared_3_densities" else 16
+    fp32 = case == "shared_fp32"
+    x, y, w, val = c0.x.copy(), c0.y.copy(), c0.w.copy(), c0.val
+    if case == "reordered_box":
+        sl = slice(64 * 37, 64 * 38)
+        p = np.random.default_rng(81).permutation(64)
+        x[sl], y[sl], w[sl] = x[sl][p], y[sl][p], w[sl][p]
+    elif case == "per_entry":
+        val = c0.val + 1e-3 * np.random.default_rng(82).standard_normal(c0.val.shape)
+    fs = np.stack([gen.gaussian_sum_density(x, y, s)[0] for s in range(90, 90 + nb)])
+    plan = vp.Plan(x, y, w, rowptr=c0.rowptr, col=c0.col, val=val, order=14 if fp32 else 30, nbatch=nb,
+                   precision="fp32" if fp32 else "fp64", root=c0.root)
+    info = plan.info()
+    # (the finish from the parents' expansions: FP64 with a multiple of 16 densities)
+    assert info["l2p_from_parents"] == (1 if nb == 16 and not fp32 else 0)
+    assert info["corr_one_block"] == (0 if case == "per_entry" else 1)
+    assert info["corr_folded"] == (1 if case.startswith("shared") else 0)
+    u = _host(plan.eval(_dev(fs)))
+    ref = direct.evaluate(x, y, w, fs, c0.rowptr, c0.col, val)
+    err = max(relinf(u[b], ref[b]) for b in range(nb))
+    g = np.random.default_rng(83).standard_normal((nb, c0.n))
+    d = _host(plan.eval_adjoint(_dev(g)))
+    dref = direct.evaluate_adjoint(x, y, w, g, c0.rowptr, c0.col, val)
+    derr = max(relinf(d[b], dref[b]) for b in range(nb))
+    print(f"corrections {case}: folded={info['corr_folded']} forward rel_inf {err:.3e}, adjoint {derr:.3e}")
+    tol = TOL32 if fp32 else TOL64
+    assert err <= tol and derr <= tol
+    # repeated forward evaluations agree bit for bit (u is written, not accumulated)
+    assert np.array_equal(_host(plan.eval(_dev(fs))), u)
+    plan.close()
+
+
 @pytest.mark.parametrize("band", ["inside", "outside"])
 def test_tables_with_nodes_off_pattern(c0, band):
     """Leaves whose nodes deviate from the node pattern.  The near-field
