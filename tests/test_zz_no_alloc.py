@@ -39,12 +39,13 @@ def relinf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def _grid(nside, seeds, csr_seed, precision="fp64", order=30, table_waves=0):
+def _grid(nside, seeds, csr_seed, precision="fp64", order=30, table_waves=0, shared=False):
     vp = _vp()
     x, y, w = gen.uniform_grid(nside)
     f = np.stack([gen.gaussian_sum_density(x, y, s)[0] for s in seeds])
     cell_ptr = np.arange(0, x.shape[0] + 1, 64, dtype=np.int64)
-    rowptr, col, val = gen.own_cell_csr(cell_ptr, csr_seed)
+    cls = np.zeros(nside * nside, dtype=np.int64) if shared else None
+    rowptr, col, val = gen.own_cell_csr(cell_ptr, csr_seed, cell_class=cls)
     plan = vp.Plan(x, y, w, rowptr=rowptr, col=col, val=val, order=order, nbatch=len(seeds),
                    precision=precision, root=(-1.0, -1.0, 2.0), table_waves=table_waves)
     return plan, f
@@ -87,6 +88,17 @@ def test_noalloc_one_wave_tables():
 def test_noalloc_fp32_bulk_form():
     plan, f = _grid(8, [7], 8, precision="fp32", order=14)
     _compare(plan, f, "fp32-bulk 8x8 boxes")
+    plan.close()
+
+
+@pytest.mark.parametrize("nb", [3, 16])
+def test_noalloc_folded_corrections(nb):
+    """One shared correction block on congruent boxes: forward evaluations
+    apply it inside the near tables and write the output without reading it
+    (the output buffer starts as NaN here)."""
+    plan, f = _grid(8, list(range(20, 20 + nb)), 21, shared=True)
+    assert plan.info()["corr_folded"] == 1
+    _compare(plan, f, f"folded corrections, {nb} densities, 8x8 boxes")
     plan.close()
 
 
