@@ -111,6 +111,74 @@ __global__ void __launch_bounds__(64) k_charge_il(const double *__restrict__ f, 
     }
 }
 
+// Charges and the leaf P2M in one pass, for forward evaluations whose only
+// charge readers are the near tables (density-fastest copy) and the P2M of
+// pattern leaves, with 16 densities: a wave takes one leaf's 16 densities,
+// forms the charges w_k f_d[perm k] of its sorted nodes k = 4 s + g, stores
+// them density-fastest and multiplies them by the P2M matrix (A: RB x S
+// fragments, the product order of k_fixed_apply, so the multipoles are the
+// same to the bit).  Multipoles of box b, density d, row r at
+// Mx[b * 16 PD + d PD + r].
+template <int RB, int S>
+__global__ void __launch_bounds__(256) k_p2m_charge(const int32_t *__restrict__ leaves, int nleaf,
+                                                    const int32_t *__restrict__ sb, const int32_t *__restrict__ perm,
+                                                    const double *__restrict__ w, const double *__restrict__ f,
+                                                    int64_t flen, const double *__restrict__ A,
+                                                    double *__restrict__ qi, double *__restrict__ Mx, int PD) {
+    typedef Mfma<double> M;
+    constexpr int AE = RB * S * 64;
+    __shared__ double sA[AE];
+    for (int e = threadIdx.x; e < AE; e += blockDim.x) sA[e] = A[e];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, cl = lane & 15, g = lane >> 4;
+    const int stride = (int)gridDim.x * 4;
+    int j = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (j >= nleaf) return;
+    const double *fd = f + (int64_t)cl * flen;
+    // sorted node indices and charges of leaf jj (element k = 4 s + g of density cl)
+    auto ld_idx = [&](int jj, int (&ix)[S], double (&wv)[S]) {
+        const int s0 = ld_uniform(sb, ld_uniform(leaves, jj)) + g;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            ix[s] = perm[s0 + 4 * s];
+            wv[s] = w[s0 + 4 * s];
+        }
+    };
+    int ix[S];
+    double wv[S], x[S];
+    ld_idx(j, ix, wv);
+#pragma unroll
+    for (int s = 0; s < S; ++s) x[s] = wv[s] * fd[ix[s]];
+    for (; j < nleaf; j += stride) {
+        const int box = ld_uniform(leaves, j);
+        const int s0 = ld_uniform(sb, box);
+        double *qo = qi + ((int64_t)s0 + g) * 16 + cl;
+#pragma unroll
+        for (int s = 0; s < S; ++s) qo[64 * s] = x[s];
+        const int jn = j + stride < nleaf ? j + stride : j;
+        ld_idx(jn, ix, wv);
+        typename M::acc_t acc[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r] = M::zero();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            double a_s[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) a_s[r] = sA[(r * S + s) * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) acc[r] = M::op(x[s], a_s[r], acc[r]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) x[s] = wv[s] * fd[ix[s]];
+        double *mo = Mx + (int64_t)box * 16 * PD + cl;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < RB; ++r) mo[M::row(i, g) * PD + r * 16] = acc[r][i];
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Power tables for P2M / P2L.  Sources come in chunks of 16; lane
 // (j = l % 16, g = l / 16) fills entries k in [g*KP, (g+1)*KP) of row j,
@@ -2020,7 +2088,27 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint, bool grad) {
                   (P->qi_zero + QI_ZERO_PTS) * P->nbatch * 8 < ((int64_t)1 << 32) &&
                   P->qi_zero + QI_ZERO_PTS < (1 << 24);
     P->q_valid = !(P->qi_valid && P->q_pattern_only && !adjoint && !grad);
-    if (P->qi_valid)
+    // the leaf P2M fused into the charge pass: every leaf a pattern leaf of 64
+    // nodes whose multipoles the fixed-matrix P2M forms (FP64, 16 densities)
+    const NearTables &N = P->near;
+    const int rb = P->PD / 16;
+    P->p2m_in_charges = !P->q_valid && !P->fp32 && P->nbatch == 16 && P->tree.nlevels >= 3 && N.active &&
+                        N.npat == 64 && P->PD % 16 == 0 && rb >= 1 && rb <= 4 &&
+                        N.n_p2m_leaf_cols == P->tree.nleaf && N.p2m_op != nullptr;
+    if (P->p2m_in_charges) {
+        const int nl = N.n_p2m_leaf_cols;
+        const unsigned grid = (unsigned)std::min((nl + 3) / 4, 1280);
+        double *Mx = static_cast<double *>(P->Mexp);
+        switch (rb) {
+#define VP_P2MQ(RB)                                                                                              \
+    case RB:                                                                                                     \
+        hipLaunchKernelGGL((k_p2m_charge<RB, 16>), dim3(grid), dim3(256), 0, P->stream, N.p2m_cols, nl,          \
+                           P->tree.sb, perm, w, f, len, N.p2m_op, P->qi, Mx, P->PD);                             \
+        break;
+            VP_P2MQ(1) VP_P2MQ(2) VP_P2MQ(3) VP_P2MQ(4)
+#undef VP_P2MQ
+        }
+    } else if (P->qi_valid)
         hipLaunchKernelGGL(k_charge_il, dim3((unsigned)((len + 63) / 64)), dim3(64),
                            64 * (P->nbatch + 1) * sizeof(double), P->stream, f, perm, w,
                            P->q_valid ? P->q : nullptr, len, P->nbatch, P->qi);
@@ -2613,7 +2701,7 @@ static void run_passes(vp_plan_s *P, const PointRoles &R, const BoxGeo &G, bool 
     // plan's stream: leaf multipoles and the upward pass down to the split level
     P->stream = ms;
     if (fmm) {
-        if (tables) {
+        if (tables && !P->p2m_in_charges) {
             P->stage_begin(VP_STAGE_P2M_PAT);
             run_pattern_op<E>(P, R, PAT_P2M);
             P->stage_end(VP_STAGE_P2M_PAT);

@@ -387,6 +387,7 @@ struct vp_plan_s {
     bool q_pattern_only = false;
     bool q_valid = true;
     bool qi_valid = false;   // qi holds this evaluation's charges
+    bool p2m_in_charges = false;  // this evaluation's charge pass also formed the leaf multipoles
     void *Mexp = nullptr;    // [mexp_boxes()][nbatch][PD] (double or float)
     void *Lexp = nullptr;
     void *zero_col = nullptr;  // max(PD, 128 nbatch) zero doubles (an absent source column, either element
