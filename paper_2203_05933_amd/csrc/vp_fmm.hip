@@ -135,28 +135,43 @@ __global__ void __launch_bounds__(256) k_p2m_charge(const int32_t *__restrict__ 
     int j = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (j >= nleaf) return;
     const double *fd = f + (int64_t)cl * flen;
-    // sorted node indices and charges of leaf jj (element k = 4 s + g of density cl)
-    auto ld_idx = [&](int jj, int (&ix)[S], double (&wv)[S]) {
-        const int s0 = ld_uniform(sb, ld_uniform(leaves, jj)) + g;
+    // sorted node indices and weights of leaf jj (element k = 4 s + g)
+    auto first = [&](int jj) { return ld_uniform(sb, ld_uniform(leaves, jj)) + g; };
+    auto ld_perm = [&](int jj, int (&ix)[S]) {
+        const int s0 = first(jj);
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            ix[s] = perm[s0 + 4 * s];
-            wv[s] = w[s0 + 4 * s];
-        }
+        for (int s = 0; s < S; ++s) ix[s] = perm[s0 + 4 * s];
     };
+    auto ld_w = [&](int jj, double (&wv)[S]) {
+        const int s0 = first(jj);
+#pragma unroll
+        for (int s = 0; s < S; ++s) wv[s] = w[s0 + 4 * s];
+    };
+    auto next = [&](int jj) { return jj + stride < nleaf ? jj + stride : jj; };
+    // pipeline: this leaf's charges x and the next leaf's node indices and
+    // weights; per leaf the next leaf's density values are requested, then
+    // the indices of the one after, before this leaf's products, and the
+    // weights of the one after once the next leaf's charges are formed
     int ix[S];
     double wv[S], x[S];
-    ld_idx(j, ix, wv);
+    ld_perm(j, ix);
+    ld_w(j, wv);
 #pragma unroll
     for (int s = 0; s < S; ++s) x[s] = wv[s] * fd[ix[s]];
+    int jn = next(j);
+    ld_perm(jn, ix);
+    ld_w(jn, wv);
     for (; j < nleaf; j += stride) {
         const int box = ld_uniform(leaves, j);
         const int s0 = ld_uniform(sb, box);
         double *qo = qi + ((int64_t)s0 + g) * 16 + cl;
 #pragma unroll
         for (int s = 0; s < S; ++s) qo[64 * s] = x[s];
-        const int jn = j + stride < nleaf ? j + stride : j;
-        ld_idx(jn, ix, wv);
+        double fv[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) fv[s] = fd[ix[s]];
+        const int jn2 = next(jn);
+        ld_perm(jn2, ix);
         typename M::acc_t acc[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) acc[r] = M::zero();
@@ -169,13 +184,15 @@ __global__ void __launch_bounds__(256) k_p2m_charge(const int32_t *__restrict__ 
             for (int r = 0; r < RB; ++r) acc[r] = M::op(x[s], a_s[r], acc[r]);
             __builtin_amdgcn_sched_barrier(0);
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s) x[s] = wv[s] * fd[ix[s]];
         double *mo = Mx + (int64_t)box * 16 * PD + cl;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int r = 0; r < RB; ++r) mo[M::row(i, g) * PD + r * 16] = acc[r][i];
+#pragma unroll
+        for (int s = 0; s < S; ++s) x[s] = wv[s] * fv[s];
+        ld_w(jn2, wv);
+        jn = jn2;
     }
 }
 
