@@ -117,17 +117,18 @@ __global__ void __launch_bounds__(64) k_charge_il(const double *__restrict__ f, 
 // forms the charges w_k f_d[perm k] of its sorted nodes k = 4 s + g, stores
 // them density-fastest and multiplies them by the P2M matrix (A: RB x S
 // fragments, the product order of k_fixed_apply, so the multipoles are the
-// same to the bit).  Multipoles of box b, density d, row r at
+// same to the bit; TM float: the FP32-bulk form, charges rounded to FP32 for
+// the product as there).  Multipoles of box b, density d, row r at
 // Mx[b * 16 PD + d PD + r].
-template <int RB, int S>
+template <class TM, int RB, int S>
 __global__ void __launch_bounds__(256) k_p2m_charge(const int32_t *__restrict__ leaves, int nleaf,
                                                     const int32_t *__restrict__ sb, const int32_t *__restrict__ perm,
                                                     const double *__restrict__ w, const double *__restrict__ f,
-                                                    int64_t flen, const double *__restrict__ A,
-                                                    double *__restrict__ qi, double *__restrict__ Mx, int PD) {
-    typedef Mfma<double> M;
+                                                    int64_t flen, const TM *__restrict__ A,
+                                                    double *__restrict__ qi, TM *__restrict__ Mx, int PD) {
+    typedef Mfma<TM> M;
     constexpr int AE = RB * S * 64;
-    __shared__ double sA[AE];
+    __shared__ TM sA[AE];
     for (int e = threadIdx.x; e < AE; e += blockDim.x) sA[e] = A[e];
     __syncthreads();
     const int lane = threadIdx.x & 63, cl = lane & 15, g = lane >> 4;
@@ -177,14 +178,14 @@ __global__ void __launch_bounds__(256) k_p2m_charge(const int32_t *__restrict__ 
         for (int r = 0; r < RB; ++r) acc[r] = M::zero();
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            double a_s[RB];
+            TM a_s[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) a_s[r] = sA[(r * S + s) * 64 + lane];
 #pragma unroll
-            for (int r = 0; r < RB; ++r) acc[r] = M::op(x[s], a_s[r], acc[r]);
+            for (int r = 0; r < RB; ++r) acc[r] = M::op((TM)x[s], a_s[r], acc[r]);
             __builtin_amdgcn_sched_barrier(0);
         }
-        double *mo = Mx + (int64_t)box * 16 * PD + cl;
+        TM *mo = Mx + (int64_t)box * 16 * PD + cl;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -2106,21 +2107,25 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint, bool grad) {
                   P->qi_zero + QI_ZERO_PTS < (1 << 24);
     P->q_valid = !(P->qi_valid && P->q_pattern_only && !adjoint && !grad);
     // the leaf P2M fused into the charge pass: every leaf a pattern leaf of 64
-    // nodes whose multipoles the fixed-matrix P2M forms (FP64, 16 densities)
+    // nodes whose multipoles the fixed-matrix P2M forms (16 densities)
     const NearTables &N = P->near;
     const int rb = P->PD / 16;
-    P->p2m_in_charges = !P->q_valid && !P->fp32 && P->nbatch == 16 && P->tree.nlevels >= 3 && N.active &&
-                        N.npat == 64 && P->PD % 16 == 0 && rb >= 1 && rb <= 4 &&
-                        N.n_p2m_leaf_cols == P->tree.nleaf && N.p2m_op != nullptr;
+    P->p2m_in_charges = !P->q_valid && P->nbatch == 16 && P->tree.nlevels >= 3 && N.active && N.npat == 64 &&
+                        P->PD % 16 == 0 && rb >= 1 && rb <= 4 && N.n_p2m_leaf_cols == P->tree.nleaf &&
+                        (P->fp32 ? N.p2m_op_f32 != nullptr : N.p2m_op != nullptr);
     if (P->p2m_in_charges) {
         const int nl = N.n_p2m_leaf_cols;
         const unsigned grid = (unsigned)std::min((nl + 3) / 4, 1280);
-        double *Mx = static_cast<double *>(P->Mexp);
-        switch (rb) {
+        switch (rb * 2 + (P->fp32 ? 1 : 0)) {
 #define VP_P2MQ(RB)                                                                                              \
-    case RB:                                                                                                     \
-        hipLaunchKernelGGL((k_p2m_charge<RB, 16>), dim3(grid), dim3(256), 0, P->stream, N.p2m_cols, nl,          \
-                           P->tree.sb, perm, w, f, len, N.p2m_op, P->qi, Mx, P->PD);                             \
+    case RB * 2:                                                                                                 \
+        hipLaunchKernelGGL((k_p2m_charge<double, RB, 16>), dim3(grid), dim3(256), 0, P->stream, N.p2m_cols, nl,  \
+                           P->tree.sb, perm, w, f, len, N.p2m_op, P->qi, static_cast<double *>(P->Mexp), P->PD); \
+        break;                                                                                                   \
+    case RB * 2 + 1:                                                                                             \
+        hipLaunchKernelGGL((k_p2m_charge<float, RB, 16>), dim3(grid), dim3(256), 0, P->stream, N.p2m_cols, nl,   \
+                           P->tree.sb, perm, w, f, len, N.p2m_op_f32, P->qi, static_cast<float *>(P->Mexp),      \
+                           P->PD);                                                                               \
         break;
             VP_P2MQ(1) VP_P2MQ(2) VP_P2MQ(3) VP_P2MQ(4)
 #undef VP_P2MQ
