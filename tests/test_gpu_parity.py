@@ -803,14 +803,22 @@ def test_corrections_folded_into_tables(c0, case):
     elif case == "per_entry":
         val = c0.val + 1e-3 * np.random.default_rng(82).standard_normal(c0.val.shape)
     fs = np.stack([gen.gaussian_sum_density(x, y, s)[0] for s in range(90, 90 + nb)])
+    # (one-wave tables: the density-fastest charge copy, which with 16 densities the
+    # charge pass writes together with the leaf multipoles)
     plan = vp.Plan(x, y, w, rowptr=c0.rowptr, col=c0.col, val=val, order=14 if fp32 else 30, nbatch=nb,
-                   precision="fp32" if fp32 else "fp64", root=c0.root)
+                   precision="fp32" if fp32 else "fp64", root=c0.root, table_waves=1)
     info = plan.info()
     # (the finish from the parents' expansions: FP64 with a multiple of 16 densities)
     assert info["l2p_from_parents"] == (1 if nb == 16 and not fp32 else 0)
     assert info["corr_one_block"] == (0 if case == "per_entry" else 1)
     assert info["corr_folded"] == (1 if case.startswith("shared") else 0)
+    plan.set_timing(True)
     u = _host(plan.eval(_dev(fs)))
+    tim = plan.timing()["ms"]
+    plan.set_timing(False)
+    assert tim["corr"] == 0.0 if info["corr_folded"] else tim["corr"] > 0.0
+    # leaf multipoles formed in the charge pass with 16 densities
+    assert (tim["p2m_pat"] == 0.0) == (nb == 16) and tim["charge"] > 0.0
     ref = direct.evaluate(x, y, w, fs, c0.rowptr, c0.col, val)
     err = max(relinf(u[b], ref[b]) for b in range(nb))
     g = np.random.default_rng(83).standard_normal((nb, c0.n))
