@@ -192,7 +192,9 @@ def tuned_choices(info):
     return {"m2l_mode": names.get(info["m2l_mode"], info["m2l_mode"]), "m2l_waves": info["m2l_waves"],
             "table_waves": info["table_waves"], "one_stream": bool(info["one_stream"]), "max_leaf": info["max_leaf"],
             "tuned": {0: "defaults", 1: "timed at plan time", 2: "from the tuning cache"}[info["tuned"]],
-            "tune_ms": info["tune_ms"]}
+            "tune_ms": info["tune_ms"],
+            # own-cell corrections applied inside the near tables' self slot (no correction pass)
+            "corrections_folded": bool(info["corr_folded"])}
 
 
 def run_form(wl, f, order, precision, steps, warmup, m2l_mode="auto", one_stream=False, label="", tune=True,
