@@ -2115,7 +2115,8 @@ void prepare_charges(vp_plan_s *P, const double *f, bool adjoint, bool grad) {
                         (P->fp32 ? N.p2m_op_f32 != nullptr : N.p2m_op != nullptr);
     if (P->p2m_in_charges) {
         const int nl = N.n_p2m_leaf_cols;
-        const unsigned grid = (unsigned)std::min((nl + 3) / 4, 1280);
+        // two workgroups per compute unit (the register budget), each looping over leaves
+        const unsigned grid = (unsigned)std::min((nl + 3) / 4, 512);
         switch (rb * 2 + (P->fp32 ? 1 : 0)) {
 #define VP_P2MQ(RB)                                                                                              \
     case RB * 2:                                                                                                 \
